@@ -1,0 +1,240 @@
+/*
+ * tpc.h -- C ABI of the MI355X TPC track-reconstruction library (libtpcreco).
+ *
+ * The paper (section "Hardware and data flow") names full online TPC track
+ * reconstruction on the EPN GPUs as the most compute-intensive part of
+ * synchronous processing, fed with zero-suppressed data of complete
+ * collisions.  This library implements that path on gfx950 in five calls:
+ *
+ *   tpc_cluster            zero-suppressed ADC samples -> clusters
+ *   tpc_find_neighbours    clusters -> cellular-automaton links
+ *   tpc_build_tracklets    links -> cleaned links + tracklets
+ *   tpc_fit_tracks         tracklets -> followed, resolved, refitted tracks
+ *   tpc_process_timeframe  all four in one launch sequence
+ *
+ * Conventions
+ *   - Every array pointer inside the structs below is a DEVICE pointer,
+ *     allocated and owned by the caller.  The library never frees caller
+ *     memory and keeps no reference to it after tpc_sync returns.
+ *   - The library owns only its context: parameters, a status word and the
+ *     scratch buffers sized by tpc_create from a tpc_sizes bound.
+ *   - Every call validates its host-side arguments (TPC_ERR_ARG, returned
+ *     synchronously), then only enqueues kernels on the context's stream.
+ *     Errors found on the device (capacity overflow, malformed input when
+ *     params.validate is set, numeric failure) latch into the status word;
+ *     a later stage that sees a latched error exits without writing, and
+ *     tpc_sync returns the first latched error together with the counts.
+ *   - No exception crosses the ABI; every function returns a tpc_status.
+ *   - One context per stream; distinct contexts are independent and may be
+ *     used from different threads.
+ *
+ * Units: lengths in cm; fixed-point positions in 2^-16 cm; local x of row r
+ * is X_fx[r] * 2^-16 with X_fx[r] = round((85 + 160 r / 151) * 2^16); the
+ * drift coordinate of time bin tau is z = tau / 2 cm.  A "unit" is one sector
+ * of one time frame; sector geometry is identical for every unit, so many
+ * frames are batched by concatenating their units.
+ */
+#ifndef TPC_H
+#define TPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPC_NROW 152
+#define TPC_NPAD_MAX 138
+
+typedef enum {
+  TPC_OK = 0,
+  TPC_ERR_ARG = -1,      /* bad host-side argument (returned synchronously) */
+  TPC_ERR_CAPACITY = -2, /* an output or scratch capacity was too small */
+  TPC_ERR_INPUT = -3,    /* input not sorted or out of range (validate mode) */
+  TPC_ERR_HIP = -4,      /* a HIP runtime call failed */
+  TPC_ERR_NUMERIC = -5,  /* a refit stayed non-positive-definite in FP64 */
+  TPC_ERR_STATE = -6     /* context misuse */
+} tpc_status;
+
+/* Reconstruction constants.  The paper specifies none of them; the values
+ * of tpc_params_default are the readings stated with the method. */
+typedef struct {
+  int32_t qmax_min;       /* peak threshold on the peak ADC (5; 10 at noise 2) */
+  int32_t min_tracklet;   /* minimum tracklet length (5) */
+  int32_t max_miss;       /* consecutive empty rows that stop following (6) */
+  int32_t min_track_hits; /* minimum hits of a kept track (15) */
+  int64_t win_y, win_z;   /* neighbour search windows, 2^-16 cm (2.5 cm) */
+  int64_t s_max;          /* neighbour score cut (2^32 = 0.5 cm midpoint) */
+  double chi2_max;        /* hit acceptance in following (16) */
+  double snp_max;         /* |sin phi| that stops propagation (0.95) */
+  double bz_b;            /* curvature per unit q/pT: 0.3e-3 * Bz[kG] */
+  double c0_snp, c0_tgl, c0_qpt; /* seed covariance sigmas (0.1, 0.1, 10) */
+  double qpt_clamp;       /* |q/pT| clamp of the seed (20 c/GeV) */
+  double edge_margin;     /* cm beyond the pad plane that stops following */
+  double lowpt_qpt;       /* |q/pT| at or above which FP64 fallback applies (5) */
+  double c0r_y, c0r_z;    /* refit prior sigmas of y, z (5 cm: broad) */
+  double c0r_snp, c0r_tgl, c0r_qpt; /* refit prior sigmas (0.5, 0.5, 10) */
+  double refit_snp_max;   /* |sin phi| a refit step may not reach (0.999) */
+  double sigma_y[TPC_NROW], sigma_z[TPC_NROW]; /* measurement errors [cm] */
+  int32_t validate;       /* 1: check input order and ranges on the device */
+  int32_t force_fallback; /* 1: redo every refit in FP64 (test hook) */
+} tpc_params;
+
+/* Upper bounds used to size the context's scratch. */
+typedef struct {
+  uint32_t max_units;     /* units per call (36 per time frame) */
+  uint32_t max_time_bins; /* time bins per unit (< 65536) */
+  uint32_t max_clusters;  /* clusters per call */
+  uint32_t max_tracklets; /* tracklets per call */
+} tpc_sizes;
+
+/* Zero-suppressed input: samples sorted by (unit, row, time, pad). */
+typedef struct {
+  const uint16_t* pad;        /* [n_samples] pad index, < pads of the row */
+  const uint16_t* time;       /* [n_samples] time bin, < n_time_bins */
+  const uint16_t* adc;        /* [n_samples] ADC value (10 bit) */
+  const uint32_t* row_start;  /* [n_units*152 + 1] first sample of each (unit,row) */
+  uint32_t n_samples;
+  uint32_t n_units;
+  uint32_t n_time_bins;
+} tpc_zs_input;
+
+/* Clusters in canonical order (unit, row, peak time, peak pad). */
+typedef struct {
+  uint32_t capacity;          /* entries available in each per-cluster array */
+  uint32_t n_units;           /* set by the caller (same as the input's) */
+  uint32_t n_time_bins;       /* set by the caller (same as the input's) */
+  uint32_t* n_clusters;       /* [1] device count, written by tpc_cluster */
+  uint32_t* crow_start;       /* [n_units*152 + 1] first cluster of each (unit,row) */
+  int32_t* y_fx;              /* local y of the centroid, 2^-16 cm */
+  int32_t* z_fx;              /* drift z of the centroid, 2^-16 cm */
+  float *dpad, *dtime;        /* centroid minus peak, in pads / time bins */
+  float *s2pad, *s2time;      /* second central moments */
+  uint16_t *qtot, *qmax;      /* total and peak charge (ADC) */
+  uint16_t *ppad, *ptime;     /* peak position */
+  uint8_t* flags;             /* 1 = peak on an edge pad, 2 = saturated sample */
+  /* optional (NULL to skip): integer moments and the sample -> cluster map */
+  int32_t *sp, *st, *spp, *stt;
+  uint16_t* nsamp;
+  int32_t* sample_label;      /* [n_samples] cluster id or -1 */
+} tpc_clusters;
+
+/* Cellular-automaton links, one entry per cluster (-1 = none). */
+typedef struct {
+  uint32_t capacity;
+  int32_t *down, *up;         /* raw best pair in rows r-1 / r+1 */
+  int32_t *downc, *upc;       /* reciprocal (cleaned) links */
+} tpc_links;
+
+/* Tracklets: a start cluster plus its chain of cleaned up-links. */
+typedef struct {
+  uint32_t capacity;
+  uint32_t* n_tracklets;      /* [1] device count */
+  uint32_t* start;            /* start cluster, ascending */
+  uint16_t* len;              /* clusters in the chain (>= min_tracklet) */
+} tpc_tracklets;
+
+/* Fitted tracks in ascending tracklet order. */
+typedef struct {
+  uint32_t capacity;          /* tracks */
+  uint32_t hit_capacity;      /* entries of hits[] */
+  uint32_t* n_tracks;         /* [1] device count */
+  uint32_t* n_hits;           /* [1] device count */
+  uint32_t* tracklet;         /* source tracklet id */
+  float* par;                 /* [cap*5] y, z - z_anchor, sin phi, tan lambda, q/pT */
+  float* cov;                 /* [cap*15] packed upper triangle, row-major */
+  float* chi2;
+  uint16_t* ndf;              /* 2 n_hits - 5 */
+  uint8_t* row;               /* row of the parameters (innermost kept hit) */
+  uint8_t* flags;             /* 1 not PD (high pT), 4 refit redone in FP64 */
+  int32_t* z_anchor;          /* drift z of the tracklet start, 2^-16 cm */
+  uint32_t* hit_start;        /* [cap+1] offsets into hits[] */
+  uint32_t* hits;             /* cluster ids, ascending row */
+  int32_t* cluster_track;     /* [clusters] track index or -1 */
+  /* optional (NULL to skip): per-tracklet following result before
+     resolution, cluster per row or -1 */
+  int32_t* follow_hits;       /* [tracklet capacity * 152] */
+} tpc_tracks;
+
+typedef struct {
+  int32_t status;             /* first latched error (tpc_status) */
+  uint32_t required;          /* capacity that an overflow needed */
+  uint32_t n_samples, n_clusters, n_tracklets, n_tracks, n_hits;
+  uint32_t n_fallback;        /* refits redone in FP64 */
+  uint32_t n_fallback_fail;   /* FP64 refits still not PD (dropped) */
+  uint32_t n_not_pd;          /* high-pT tracks flagged not PD */
+  uint32_t n_refit_fail;      /* tracks dropped by a failed refit step */
+} tpc_counts;
+
+typedef struct tpc_ctx tpc_ctx;
+
+/* Fill p with the default constants for a given electronic-noise sigma
+ * (the peak threshold is round(5 * noise_sigma)). */
+int tpc_params_default(tpc_params* p, double noise_sigma);
+
+/* Library-side geometry: pads per row and fixed-point row radius / pitch. */
+int tpc_geometry(int32_t* npads, int32_t* x_fx, int32_t* pitch_fx);
+
+/* Bytes of device scratch a context with these bounds allocates. */
+int tpc_workspace_size(const tpc_sizes* max, size_t* bytes);
+
+/* Create a context on the current device bound to hip_stream (a
+ * hipStream_t; NULL = the null stream).  Allocates the scratch. */
+int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* hip_stream);
+int tpc_destroy(tpc_ctx* ctx);
+
+/* Clusterizer: peaks are samples whose (adc, time, pad) key exceeds that of
+ * every present 8-neighbour and whose ADC reaches qmax_min; each sample joins
+ * the peak it reaches in at most two uphill steps.  Writes n_clusters,
+ * crow_start and every non-NULL per-cluster array. */
+int tpc_cluster(tpc_ctx* ctx, const tpc_zs_input* in, tpc_clusters* out);
+
+/* For each cluster in rows 1..150: the pair (j in row r-1, k in row r+1)
+ * inside the windows minimising (2y_i-y_j-y_k)^2 + (2z_i-z_j-z_k)^2 <= s_max,
+ * ties to the smaller (j, k).  Writes down/up. */
+int tpc_find_neighbours(tpc_ctx* ctx, const tpc_clusters* cl, tpc_links* links);
+
+/* Keeps reciprocal links (downc/upc) and emits chains of at least
+ * min_tracklet clusters that start at a cluster without a cleaned down-link. */
+int tpc_build_tracklets(tpc_ctx* ctx, const tpc_clusters* cl, tpc_links* links,
+                        tpc_tracklets* out);
+
+/* Kalman following (outward pass A, inward pass B), conflict resolution
+ * (each cluster kept by the track with the most hits, then the lower
+ * tracklet id) and the inward FP32 refit with FP64 fallback for low-pT
+ * tracks whose covariance loses positive definiteness. */
+int tpc_fit_tracks(tpc_ctx* ctx, const tpc_clusters* cl, const tpc_links* links,
+                   const tpc_tracklets* tl, tpc_tracks* out);
+
+/* The four stages in one launch sequence on the context's stream. */
+int tpc_process_timeframe(tpc_ctx* ctx, const tpc_zs_input* in, tpc_clusters* cl,
+                          tpc_links* links, tpc_tracklets* tl, tpc_tracks* tr);
+
+/* Wait for the stream, then report the first latched error and the counts.
+ * Clears the status word for the next call. */
+int tpc_sync(tpc_ctx* ctx, tpc_counts* counts);
+
+/* The stream the context launches on (a hipStream_t). */
+void* tpc_stream(tpc_ctx* ctx);
+
+/* Stage timing for measurement (not part of the reconstruction).  When on,
+ * every later call records a pair of HIP events on the context's stream
+ * around each of the TPC_PROF_STAGES stages below; tpc_profile_read waits
+ * for the stream, writes the summed milliseconds and the number of timed
+ * launches per stage, and clears them.  Leave it off while a launch sequence
+ * is captured into a HIP graph.  Stages: 0 sample index, 1 cluster count,
+ * 2 window scan, 3 cluster emit, 4 cluster grid, 5 neighbours, 6 tracklets,
+ * 7 following, 8 resolution, 9 refit FP32, 10 refit FP64, 11 track output. */
+#define TPC_PROF_STAGES 12
+int tpc_profile_enable(tpc_ctx* ctx, int on);
+int tpc_profile_read(tpc_ctx* ctx, double* ms, uint32_t* launches);
+const char* tpc_profile_stage_name(int stage);
+
+const char* tpc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPC_H */

@@ -46,6 +46,9 @@ class OParams(ctypes.Structure):
         ("c0_snp", ctypes.c_double), ("c0_tgl", ctypes.c_double), ("c0_qpt", ctypes.c_double),
         ("qpt_clamp", ctypes.c_double), ("edge_margin", ctypes.c_double),
         ("lowpt_qpt", ctypes.c_double),
+        ("c0r_y", ctypes.c_double), ("c0r_z", ctypes.c_double), ("c0r_snp", ctypes.c_double),
+        ("c0r_tgl", ctypes.c_double), ("c0r_qpt", ctypes.c_double),
+        ("refit_snp_max", ctypes.c_double),
         ("sigma_y", ctypes.c_double * NROW), ("sigma_z", ctypes.c_double * NROW),
         ("brute_force", ctypes.c_int32), ("n_threads", ctypes.c_int32),
     ]
@@ -73,6 +76,7 @@ def default_params(noise_sigma: float = 1.0) -> dict:
         win_y=163840, win_z=163840, s_max=1 << 32,
         chi2_max=16.0, snp_max=0.95, bz_b=0.299792458e-3 * 5.0,
         c0_snp=0.1, c0_tgl=0.1, c0_qpt=10.0, qpt_clamp=20.0, edge_margin=1.0, lowpt_qpt=5.0,
+        c0r_y=5.0, c0r_z=5.0, c0r_snp=0.5, c0r_tgl=0.5, c0r_qpt=10.0, refit_snp_max=0.999,
         sigma_y=[0.06] * NROW, sigma_z=[0.05] * NROW,
     )
 

@@ -47,6 +47,8 @@ typedef struct {
   double qpt_clamp;        /* |q/pT| clamp of the seed */
   double edge_margin;      /* cm beyond the pad plane that stops following */
   double lowpt_qpt;        /* |q/pT| above which a track counts as low-pT */
+  double c0r_y, c0r_z, c0r_snp, c0r_tgl, c0r_qpt; /* refit prior sigmas (broad) */
+  double refit_snp_max;    /* |sin phi| a refit step may not reach */
   double sigma_y[NROW], sigma_z[NROW]; /* per-row measurement errors [cm] */
   int32_t brute_force;     /* 1: scan whole rows instead of time windows */
   int32_t n_threads;
@@ -853,6 +855,11 @@ static void resolve_unit(void* ctx, int unit) {
 /* ------------------------------------------------------------ refit */
 enum { TFLAG_NOT_PD = 1, TFLAG_REFIT_FAIL = 2 };
 
+/* Refit of a track over its kept hits.  The start is the circle through the
+   innermost, middle and outermost kept clusters, evaluated at the outermost
+   one, with a broad covariance, so that the result depends on the kept hits
+   alone; the Kalman filter then runs inward through every kept hit.  A step
+   fails only if the helix cannot reach the next hit's row. */
 static void refit_track(fit_job* J, int64_t t) {
   const oparams* par = J->par;
   const int32_t* H = J->hits + t * NROW;
@@ -860,32 +867,51 @@ static void refit_track(fit_job* J, int64_t t) {
   for (int r = NROW - 1; r >= 0; --r)
     if (H[r] >= 0 && J->cluster_owner[H[r]] == t) rows[n++] = r;
   const int64_t anchor = J->z[J->tl_start[t]];
-  const double* pb = J->pb_state + t * 6;
-  kstate k;
-  for (int i = 0; i < 5; ++i) k.p[i] = pb[i];
-  k.x = G_X[(int)pb[5]];
   J->out_flags[t] = 0;
   ktrace tr = {0, 0};
-  /* start at the outermost kept hit with a reset covariance */
-  if (helix_propagate(par, k.p, k.x, G_X[rows[0]], NULL, &tr)) {
-    J->out_flags[t] |= TFLAG_REFIT_FAIL;
-    J->kept[t] = 0;
-    return;
-  }
-  k.x = G_X[rows[0]];
-  c0_reset(par, &k, rows[0]);
+  /* circle through A (innermost), M (middle), E (outermost) kept clusters */
+  const int rA = rows[n - 1], rM = rows[n - 1 - ((n + 1) / 2 - 1)], rE = rows[0];
+  const int64_t cA = H[rA], cM = H[rM], cE = H[rE];
+  const double mx = G_X[rM] - G_X[rA], my = (J->y[cM] - J->y[cA]) / 65536.0;
+  const double ex = G_X[rE] - G_X[rA], ey = (J->y[cE] - J->y[cA]) / 65536.0;
+  const double dMA = hypot(mx, my), dEA = hypot(ex, ey), dEM = hypot(G_X[rE] - G_X[rM], ey - my);
+  double C = 2.0 * (mx * ey - my * ex) / (dMA * dEM * dEA);
+  double qpt = -C / par->bz_b;
+  if (qpt > par->qpt_clamp) qpt = par->qpt_clamp;
+  if (qpt < -par->qpt_clamp) qpt = -par->qpt_clamp;
+  C = -par->bz_b * qpt;
+  double sarg = dEA * C / 2.0;
+  if (sarg > 1.0) sarg = 1.0;
+  if (sarg < -1.0) sarg = -1.0;
+  const double h = dEA * fabs(C) / 2.0;
+  const double arc = h > 0 ? dEA * asin(h > 1.0 ? 1.0 : h) / h : dEA;
+  kstate k;
+  k.x = G_X[rE];
+  k.p[0] = J->y[cE] / 65536.0;
+  k.p[1] = (J->z[cE] - anchor) / 65536.0;
+  k.p[2] = sin(atan2(ey, ex) + asin(sarg)); /* tangent at the far end of the chord */
+  k.p[3] = (double)(J->z[cE] - J->z[cA]) / 65536.0 / arc;
+  k.p[4] = qpt;
+  memset(k.C, 0, sizeof k.C);
+  k.C[0][0] = par->c0r_y * par->c0r_y;
+  k.C[1][1] = par->c0r_z * par->c0r_z;
+  k.C[2][2] = par->c0r_snp * par->c0r_snp;
+  k.C[3][3] = par->c0r_tgl * par->c0r_tgl;
+  k.C[4][4] = par->c0r_qpt * par->c0r_qpt;
+  oparams rp = *par;
+  rp.snp_max = par->refit_snp_max;
   double chi2sum = 0;
   int pd_ok = 1;
   for (int i = 0; i < n; ++i) {
     const int r = rows[i];
-    if (i > 0 && kstate_propagate(par, &k, G_X[r], &tr)) {
+    if (i > 0 && kstate_propagate(&rp, &k, G_X[r], &tr)) {
       J->out_flags[t] |= TFLAG_REFIT_FAIL;
       J->kept[t] = 0;
       return;
     }
-    double my, mz, chi2;
-    meas(J, H[r], anchor, &my, &mz);
-    if (kstate_update(&k, my, mz, par->sigma_y[r] * par->sigma_y[r],
+    double mmy, mmz, chi2;
+    meas(J, H[r], anchor, &mmy, &mmz);
+    if (kstate_update(&k, mmy, mmz, par->sigma_y[r] * par->sigma_y[r],
                       par->sigma_z[r] * par->sigma_z[r], &chi2, &tr)) {
       J->out_flags[t] |= TFLAG_REFIT_FAIL;
       J->kept[t] = 0;

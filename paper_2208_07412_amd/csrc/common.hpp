@@ -1,0 +1,198 @@
+// Device-side building blocks shared by the kernels of libtpcreco:
+// parameter block, status word, wave64 / workgroup scans and the
+// three-phase device-wide scan used for every order-preserving compaction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tpc.h"
+
+#define NROW TPC_NROW
+#define SCAN_BLOCK 256
+#define SCAN_ITEMS 8
+#define SCAN_TILE (SCAN_BLOCK * SCAN_ITEMS)
+
+// Parameters and row tables, resident in device memory for one context.
+struct DevParams {
+  int32_t np[NROW];   // pads per row
+  int32_t xfx[NROW];  // row radius, 2^-16 cm
+  int32_t pfx[NROW];  // pad pitch, 2^-16 cm
+  float x[NROW], hw[NROW], vy[NROW], vz[NROW];
+  double xd[NROW], hwd[NROW], vyd[NROW], vzd[NROW];
+  int32_t qmax_min, min_tracklet, max_miss, min_track_hits;
+  int64_t win_y, win_z, s_max;
+  float chi2_max, snp_max, bz_b, c0_snp2, c0_tgl2, c0_qpt2, qpt_clamp, edge_margin, lowpt_qpt;
+  double chi2_max_d, snp_max_d, bz_b_d, c0_snp2_d, c0_tgl2_d, c0_qpt2_d, qpt_clamp_d,
+      edge_margin_d;
+  float c0r2[5], refit_snp_max;  // refit prior variances (y, z, snp, tgl, q/pT)
+  double c0r2_d[5], refit_snp_max_d;
+  int32_t validate, force_fallback;
+};
+
+// Status word and device-side counts of one context.
+struct DevStatus {
+  int32_t status;
+  uint32_t required;
+  uint32_t n_clusters, n_tracklets, n_tracks, n_hits;
+  uint32_t n_fallback, n_fallback_fail, n_not_pd, n_refit_fail;
+  uint32_t n_fb_list;
+  uint32_t pad_[5];
+};
+
+__device__ __forceinline__ void latch(DevStatus* st, int code, uint32_t required = 0) {
+  atomicCAS(&st->status, 0, code);
+  if (required) atomicMax(&st->required, required);
+}
+
+__device__ __forceinline__ bool failed(const DevStatus* st) {
+  return __atomic_load_n(&st->status, __ATOMIC_RELAXED) != 0;
+}
+
+__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {  // b > 0
+  int64_t q = a / b;
+  if ((a % b != 0) && (a < 0)) --q;
+  return q;
+}
+
+// Bijective remap of a 1-D grid so that consecutive logical blocks land on
+// the same XCD (blocks are dispatched round-robin over 8 XCDs), which keeps
+// neighbouring tiles in one L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
+  const uint32_t full = nb & ~7u;
+  if (bid >= full) return bid;
+  const uint32_t per = full >> 3;
+  return (bid & 7u) * per + (bid >> 3);
+}
+
+// ------------------------------------------------------------ wave64 scans
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T o = __shfl_up(v, d, 64);
+    if ((int)lane_id() >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan over a workgroup of BLOCK threads; returns the prefix and
+// the block total.  lds needs BLOCK/64 + 1 entries.
+template <typename T, int BLOCK>
+__device__ __forceinline__ T block_excl_scan(T v, T* lds, T& total) {
+  const int w = threadIdx.x >> 6;
+  const T inc = wave_incl_scan(v);
+  if (lane_id() == 63) lds[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T acc = 0;
+    for (int i = 0; i < BLOCK / 64; ++i) {
+      const T t = lds[i];
+      lds[i] = acc;
+      acc += t;
+    }
+    lds[BLOCK / 64] = acc;
+  }
+  __syncthreads();
+  const T res = lds[w] + inc - v;
+  total = lds[BLOCK / 64];
+  __syncthreads();
+  return res;
+}
+
+// ------------------------------------------------- device-wide scan (3 phases)
+// Get:  T operator()(uint32_t i) const -- value of element i (i < n)
+// Emit: void operator()(uint32_t i, T prefix, T value) const
+// The element count is min(*n_dev, n_cap) when n_dev is given, else n_cap.
+__device__ __forceinline__ uint32_t scan_count(const uint32_t* n_dev, uint32_t n_cap) {
+  if (!n_dev) return n_cap;
+  const uint32_t n = *n_dev;
+  return n < n_cap ? n : n_cap;
+}
+
+template <typename T, class Get>
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(Get get, const uint32_t* n_dev,
+                                                            uint32_t n_cap, T* bsum,
+                                                            const DevStatus* st) {
+  __shared__ T lds[SCAN_BLOCK / 64 + 1];
+  if (failed(st)) return;
+  const uint32_t n = scan_count(n_dev, n_cap);
+  const uint32_t base = blockIdx.x * SCAN_TILE;
+  T acc = 0;
+  if (base < n) {
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const uint32_t i = base + k * SCAN_BLOCK + threadIdx.x;
+      if (i < n) acc += get(i);
+    }
+  }
+  T total;
+  block_excl_scan<T, SCAN_BLOCK>(acc, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block sums in place, by one workgroup of 1024.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_blocks(T* bsum, uint32_t nb, T* total_out,
+                                                      uint32_t* total32_out, const DevStatus* st) {
+  __shared__ T lds[1024 / 64 + 1];
+  if (failed(st)) return;
+  T carry = 0;
+  for (uint32_t off = 0; off < nb; off += 1024) {
+    const uint32_t i = off + threadIdx.x;
+    const T v = i < nb ? bsum[i] : T(0);
+    T tot;
+    const T ex = block_excl_scan<T, 1024>(v, lds, tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (total_out) *total_out = carry;
+    if (total32_out) *total32_out = (uint32_t)carry;
+  }
+}
+
+template <typename T, class Get, class Emit>
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(Get get, Emit emit, const uint32_t* n_dev,
+                                                          uint32_t n_cap, const T* bsum,
+                                                          const DevStatus* st) {
+  __shared__ T lds[SCAN_BLOCK / 64 + 1];
+  if (failed(st)) return;
+  const uint32_t n = scan_count(n_dev, n_cap);
+  const uint32_t base = blockIdx.x * SCAN_TILE;
+  if (base >= n) return;  // uniform per block
+  // each thread owns SCAN_ITEMS consecutive elements for an ordered scan
+  const uint32_t first = base + threadIdx.x * SCAN_ITEMS;
+  T vals[SCAN_ITEMS];
+  T acc = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const uint32_t i = first + k;
+    vals[k] = i < n ? get(i) : T(0);
+    acc += vals[k];
+  }
+  T total;
+  T pre = block_excl_scan<T, SCAN_BLOCK>(acc, lds, total) + bsum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const uint32_t i = first + k;
+    if (i < n) emit(i, pre, vals[k]);
+    pre += vals[k];
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T v, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// fill the first min(*n_dev, n_cap) entries
+template <typename T>
+__global__ void k_fill_dev(T* p, T v, const uint32_t* n_dev, uint32_t n_cap) {
+  const uint32_t n = scan_count(n_dev, n_cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = v;
+}

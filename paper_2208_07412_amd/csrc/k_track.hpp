@@ -1,0 +1,859 @@
+// Kalman track following, conflict resolution, refit and output.
+//
+// One tracklet per lane.  The state is (y, z - z_anchor, sin phi, tan lambda,
+// q/pT) at the local x of a pad row; z is kept relative to the tracklet's
+// first cluster so that FP32 keeps full precision in long time frames.  The
+// covariance is a packed 5x5 upper triangle in registers.  Propagation is
+// the exact helix in a uniform Bz field (no material, no process noise).
+#pragma once
+
+#include "common.hpp"
+#include "k_cluster.hpp"
+#include "k_links.hpp"
+
+#define FX_SCALE 1.52587890625e-05  // 2^-16
+
+enum { TF_NOT_PD = 1, TF_REFIT_FAIL = 2, TF_FP64 = 4, TF_FP64_FAIL = 8 };
+
+template <typename T>
+struct Trk {
+  T p[5];
+  T c[15];
+};
+
+__device__ __forceinline__ constexpr int PI(int i, int j) {  // i <= j
+  return i * 5 - i * (i - 1) / 2 + (j - i);
+}
+
+template <typename T>
+__device__ __forceinline__ T cov(const T* c, int i, int j) {
+  return i <= j ? c[PI(i, j)] : c[PI(j, i)];
+}
+
+// per-precision views of the parameter block
+template <typename T>
+struct PV;
+template <>
+struct PV<float> {
+  const DevParams* P;
+  __device__ float x(int r) const { return P->x[r]; }
+  __device__ float hw(int r) const { return P->hw[r]; }
+  __device__ float vy(int r) const { return P->vy[r]; }
+  __device__ float vz(int r) const { return P->vz[r]; }
+  __device__ float chi2_max() const { return P->chi2_max; }
+  __device__ float snp_max() const { return P->snp_max; }
+  __device__ float b() const { return P->bz_b; }
+  __device__ float c0_snp2() const { return P->c0_snp2; }
+  __device__ float c0_tgl2() const { return P->c0_tgl2; }
+  __device__ float c0_qpt2() const { return P->c0_qpt2; }
+  __device__ float qpt_clamp() const { return P->qpt_clamp; }
+  __device__ float edge_margin() const { return P->edge_margin; }
+  __device__ float refit_snp_max() const { return P->refit_snp_max; }
+  __device__ float c0r(int i) const { return P->c0r2[i]; }
+};
+template <>
+struct PV<double> {
+  const DevParams* P;
+  __device__ double x(int r) const { return P->xd[r]; }
+  __device__ double hw(int r) const { return P->hwd[r]; }
+  __device__ double vy(int r) const { return P->vyd[r]; }
+  __device__ double vz(int r) const { return P->vzd[r]; }
+  __device__ double chi2_max() const { return P->chi2_max_d; }
+  __device__ double snp_max() const { return P->snp_max_d; }
+  __device__ double b() const { return P->bz_b_d; }
+  __device__ double c0_snp2() const { return P->c0_snp2_d; }
+  __device__ double c0_tgl2() const { return P->c0_tgl2_d; }
+  __device__ double c0_qpt2() const { return P->c0_qpt2_d; }
+  __device__ double qpt_clamp() const { return P->qpt_clamp_d; }
+  __device__ double edge_margin() const { return P->edge_margin_d; }
+  __device__ double refit_snp_max() const { return P->refit_snp_max_d; }
+  __device__ double c0r(int i) const { return P->c0r2_d[i]; }
+};
+
+// exact row-to-row distance from the integer radii
+template <typename T>
+__device__ __forceinline__ T row_dx(const DevParams* P, int r1, int r2) {
+  return (T)(P->xfx[r2] - P->xfx[r1]) * (T)FX_SCALE;
+}
+
+// d(signed arc)/dC at fixed dx: integral over u in [0, dx] of
+// u * s / (1 - s^2)^(3/2), s = s1 + C u, by 8-point Gauss-Legendre.
+template <typename T>
+__device__ __forceinline__ T darc_dc(T s1, T C, T dx) {
+  const T X[8] = {(T)0.01985507175123188, (T)0.10166676129318664, (T)0.2372337950418355,
+                  (T)0.4082826787521751,  (T)0.5917173212478249,  (T)0.7627662049581645,
+                  (T)0.8983332387068134,  (T)0.9801449282487681};
+  const T Wt[8] = {(T)0.05061426814518813, (T)0.11119051722668724, (T)0.15685332293894363,
+                   (T)0.18134189168918100, (T)0.18134189168918100, (T)0.15685332293894363,
+                   (T)0.11119051722668724, (T)0.05061426814518813};
+  T acc = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const T s = s1 + C * dx * X[i];
+    const T w = (T)1 - s * s;
+    acc += Wt[i] * X[i] * s / (w * sqrt(w));
+  }
+  return acc * dx * dx;
+}
+
+// Helix propagation over dx; with_cov also transports the covariance with
+// the analytic Jacobian.  Returns false (state untouched) if |sin phi| would
+// reach snp_max.
+template <typename T>
+__device__ __forceinline__ bool propagate(Trk<T>& k, T dx, const PV<T>& pv, bool with_cov,
+                                          T snp_lim) {
+  const T b = pv.b();
+  const T C = -b * k.p[4];
+  const T s1 = k.p[2], s2 = s1 + C * dx;
+  if (!(fabs(s2) < snp_lim)) return false;
+  const T c1 = sqrt((T)1 - s1 * s1), c2 = sqrt((T)1 - s2 * s2);
+  const T D = c1 + c2, N = s1 + s2, f = N / D;
+  const T chord = fabs(dx) * sqrt((T)1 + f * f);
+  T h = chord * fabs(C) * (T)0.5;
+  if (h > (T)1) h = (T)1;
+  const T L = h > (T)0 ? chord * asin(h) / h : chord;
+  const T A = dx >= (T)0 ? L : -L;
+  if (with_cov) {
+    const T D2 = D * D;
+    const T j02 = dx * ((T)2 * D + N * (s1 / c1 + s2 / c2)) / D2;
+    const T j04 = -b * dx * dx * (D + N * s2 / c2) / D2;
+    const T j12 = k.p[3] * dx * N / (c1 * c2 * D);
+    const T j13 = A;
+    const T j14 = -b * k.p[3] * darc_dc(s1, C, dx);
+    const T j24 = -b * dx;
+    T m[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) m[i][j] = cov(k.c, i, j);
+    T t[5][5];  // J * M
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      t[0][j] = m[0][j] + j02 * m[2][j] + j04 * m[4][j];
+      t[1][j] = m[1][j] + j12 * m[2][j] + j13 * m[3][j] + j14 * m[4][j];
+      t[2][j] = m[2][j] + j24 * m[4][j];
+      t[3][j] = m[3][j];
+      t[4][j] = m[4][j];
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {  // (J M) J^T, upper triangle
+      const T col[5] = {t[i][0] + j02 * t[i][2] + j04 * t[i][4],
+                        t[i][1] + j12 * t[i][2] + j13 * t[i][3] + j14 * t[i][4],
+                        t[i][2] + j24 * t[i][4], t[i][3], t[i][4]};
+#pragma unroll
+      for (int j = i; j < 5; ++j) k.c[PI(i, j)] = col[j];
+    }
+  }
+  k.p[0] += dx * f;
+  k.p[1] += k.p[3] * A;
+  k.p[2] = s2;
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ T chi2_of(const Trk<T>& k, T my, T mz, T vy, T vz) {
+  const T r0 = my - k.p[0], r1 = mz - k.p[1];
+  const T S00 = k.c[0] + vy, S01 = k.c[1], S11 = k.c[5] + vz;
+  const T det = S00 * S11 - S01 * S01;
+  return (r0 * r0 * S11 - (T)2 * r0 * r1 * S01 + r1 * r1 * S00) / det;
+}
+
+// Kalman update with a (y, z) measurement.  Returns false (state untouched)
+// if |sin phi| >= 1 afterwards.
+template <typename T>
+__device__ __forceinline__ bool update(Trk<T>& k, T my, T mz, T vy, T vz, T* chi2) {
+  const T r0 = my - k.p[0], r1 = mz - k.p[1];
+  const T S00 = k.c[0] + vy, S01 = k.c[1], S11 = k.c[5] + vz;
+  const T det = S00 * S11 - S01 * S01;
+  const T I00 = S11 / det, I01 = -S01 / det, I11 = S00 / det;
+  if (chi2) *chi2 = r0 * r0 * I00 + (T)2 * r0 * r1 * I01 + r1 * r1 * I11;
+  T K0[5], K1[5], c0[5], c1v[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    c0[i] = cov(k.c, 0, i);
+    c1v[i] = cov(k.c, 1, i);
+    K0[i] = c0[i] * I00 + c1v[i] * I01;
+    K1[i] = c0[i] * I01 + c1v[i] * I11;
+  }
+  const T np2 = k.p[2] + K0[2] * r0 + K1[2] * r1;
+  if (!(fabs(np2) < (T)1)) return false;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) k.p[i] += K0[i] * r0 + K1[i] * r1;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) k.c[PI(i, j)] -= K0[i] * c0[j] + K1[i] * c1v[j];
+  return true;
+}
+
+// The same update with the covariance in Joseph form,
+// C' = (I - K H) C (I - K H)^T + K V K^T, which equals C - K H C in exact
+// arithmetic but keeps FP32 precision while the prior variance collapses by
+// many orders of magnitude over the first hits (used by the refit).
+template <typename T>
+__device__ __forceinline__ bool update_joseph(Trk<T>& k, T my, T mz, T vy, T vz, T* chi2) {
+  const T r0 = my - k.p[0], r1 = mz - k.p[1];
+  const T S00 = k.c[0] + vy, S01 = k.c[1], S11 = k.c[5] + vz;
+  const T det = S00 * S11 - S01 * S01;
+  const T I00 = S11 / det, I01 = -S01 / det, I11 = S00 / det;
+  if (chi2) *chi2 = r0 * r0 * I00 + (T)2 * r0 * r1 * I01 + r1 * r1 * I11;
+  T K0[5], K1[5], c0[5], c1v[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    c0[i] = cov(k.c, 0, i);
+    c1v[i] = cov(k.c, 1, i);
+    K0[i] = c0[i] * I00 + c1v[i] * I01;
+    K1[i] = c0[i] * I01 + c1v[i] * I11;
+  }
+  const T np2 = k.p[2] + K0[2] * r0 + K1[2] * r1;
+  if (!(fabs(np2) < (T)1)) return false;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) k.p[i] += K0[i] * r0 + K1[i] * r1;
+  // columns 0 and 1 of M = (I - K H) C
+  T m0[5], m1[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    m0[i] = c0[i] - K0[i] * c0[0] - K1[i] * c1v[0];
+    m1[i] = c1v[i] - K0[i] * c0[1] - K1[i] * c1v[1];
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      const T mij = k.c[PI(i, j)] - K0[i] * c0[j] - K1[i] * c1v[j];
+      k.c[PI(i, j)] = mij - m0[i] * K0[j] - m1[i] * K1[j] + vy * K0[i] * K0[j] + vz * K1[i] * K1[j];
+    }
+  return true;
+}
+
+// positive definiteness by LDL^T: all pivots > 0
+template <typename T>
+__device__ __forceinline__ bool is_pd(const T* c) {
+  T L[5][5];
+  T D[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    T d = c[PI(j, j)];
+#pragma unroll
+    for (int m = 0; m < j; ++m) d -= L[j][m] * L[j][m] * D[m];
+    if (!(d > (T)0)) return false;
+    D[j] = d;
+#pragma unroll
+    for (int i = j + 1; i < 5; ++i) {
+      T a = c[PI(j, i)];
+#pragma unroll
+      for (int m = 0; m < j; ++m) a -= L[i][m] * L[j][m] * D[m];
+      L[i][j] = a / d;
+    }
+  }
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ void c0_reset(Trk<T>& k, const PV<T>& pv, int r) {
+#pragma unroll
+  for (int i = 0; i < 15; ++i) k.c[i] = 0;
+  k.c[PI(0, 0)] = pv.vy(r);
+  k.c[PI(1, 1)] = pv.vz(r);
+  k.c[PI(2, 2)] = pv.c0_snp2();
+  k.c[PI(3, 3)] = pv.c0_tgl2();
+  k.c[PI(4, 4)] = pv.c0_qpt2();
+}
+
+// unit-row of a cluster: the last ur with crow[ur] <= c
+__device__ __forceinline__ uint32_t cluster_ur(const uint32_t* crow, uint32_t n_ur, uint32_t c) {
+  uint32_t a = 0, b = n_ur;
+  while (b - a > 1) {
+    const uint32_t m = (a + b) >> 1;
+    if (crow[m] <= c) a = m;
+    else b = m;
+  }
+  return a;
+}
+
+struct FollowOut {
+  int32_t* hits;      // [cap*152], rows [lo, hi] written
+  float* state;       // [cap*6]: pass-B state + its row
+  uint16_t* nhits;    // [cap]
+  uint16_t* range;    // [cap]: lo | hi << 8
+  uint8_t* ok;        // [cap]
+};
+
+// best candidate of row r: smallest (chi2, id) with chi2 <= chi2_max
+__device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint32_t* cblk,
+                                              uint32_t nblk, uint32_t ur, const Trk<float>& k,
+                                              int32_t anchor, float vy, float vz, float chi2max) {
+  const float w = sqrtf(chi2max * (k.c[5] + vz));
+  const float zabs = k.p[1] + (float)anchor * (float)FX_SCALE;
+  const float flo = floorf(2.0f * (zabs - w)) - 3.0f, fhi = ceilf(2.0f * (zabs + w)) + 3.0f;
+  // NaN or out-of-range windows collapse to an empty or clamped block range
+  int32_t blo = flo > 0.0f ? (flo < 1.0e6f ? ((int32_t)flo >> 3) : (int32_t)nblk) : 0;
+  int32_t bhi = fhi >= 0.0f ? (fhi < 1.0e6f ? ((int32_t)fhi >> 3) : (int32_t)nblk - 1) : -1;
+  if (!(fhi >= 0.0f) || !(flo == flo)) bhi = -1;
+  if (blo > (int32_t)nblk - 1) blo = nblk - 1;
+  if (bhi > (int32_t)nblk - 1) bhi = nblk - 1;
+  uint32_t a, b;
+  row_range(cblk + (size_t)ur * (nblk + 1), nblk, blo, bhi + 1, cl.row_start(ur),
+            cl.row_start(ur + 1), a, b);
+  int32_t best = -1;
+  float bchi = 0.0f;
+  for (uint32_t c = a; c < b; ++c) {
+    const float my = (float)cl.y_fx[c] * (float)FX_SCALE;
+    const float mz = (float)(cl.z_fx[c] - anchor) * (float)FX_SCALE;
+    const float x2 = chi2_of(k, my, mz, vy, vz);
+    if (x2 <= chi2max && (best < 0 || x2 < bchi)) {
+      best = (int32_t)c;
+      bchi = x2;
+    }
+  }
+  return best;
+}
+
+__global__ __launch_bounds__(64) void k_follow(ClusterView cl, const uint32_t* __restrict__ cblk,
+                                               uint32_t nblk, uint32_t n_ur,
+                                               const int32_t* __restrict__ upc,
+                                               const uint32_t* __restrict__ tl_start,
+                                               const uint16_t* __restrict__ tl_len,
+                                               const uint32_t* n_tl_dev, uint32_t tl_cap,
+                                               FollowOut fo, const DevParams* __restrict__ P,
+                                               const DevStatus* st) {
+  if (failed(st)) return;
+  const PV<float> pv{P};
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  const uint32_t n_cl = scan_count(cl.n_clusters, cl.capacity);
+  const float chi2max = pv.chi2_max();
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+    fo.ok[t] = 0;
+    fo.nhits[t] = 0;
+    fo.range[t] = 0;
+    const uint32_t A = tl_start[t];
+    const int L = tl_len[t];
+    if (A >= n_cl || L < 3) continue;
+    const uint32_t urA = cluster_ur(cl.crow, n_ur, A);
+    const int r1 = urA % NROW;
+    const uint32_t ubase = urA - r1;
+    if (r1 + L > NROW) continue;
+    int32_t* H = fo.hits + (size_t)t * NROW;
+    // middle and end of the tracklet
+    uint32_t M = A, E = A, c = A;
+    const int im = (L + 1) / 2 - 1;
+    bool bad = false;
+    for (int i = 1; i < L; ++i) {
+      const int32_t nx = upc[c];
+      if (nx < 0 || (uint32_t)nx >= n_cl) {
+        bad = true;
+        break;
+      }
+      c = (uint32_t)nx;
+      if (i == im) M = c;
+      E = c;
+    }
+    if (bad) continue;
+    const int rM = r1 + im, rE = r1 + L - 1;
+    const int32_t anchor = cl.z_fx[A];
+    // ---- seed: circle through A, M, E; differences are exact integers
+    const int64_t dxm = P->xfx[rM] - P->xfx[r1], dym = (int64_t)cl.y_fx[M] - cl.y_fx[A];
+    const int64_t dxe = P->xfx[rE] - P->xfx[r1], dye = (int64_t)cl.y_fx[E] - cl.y_fx[A];
+    const int64_t dxx = P->xfx[rE] - P->xfx[rM], dyy = (int64_t)cl.y_fx[E] - cl.y_fx[M];
+    const float cross = (float)(dxm * dye - dym * dxe) * (float)(FX_SCALE * FX_SCALE);
+    const float fma_ = hypotf((float)dxm, (float)dym) * (float)FX_SCALE;
+    const float fea = hypotf((float)dxe, (float)dye) * (float)FX_SCALE;
+    const float fem = hypotf((float)dxx, (float)dyy) * (float)FX_SCALE;
+    const float b = pv.b();
+    float C = 2.0f * cross / (fma_ * fem * fea);
+    float qpt = -C / b;
+    qpt = fminf(fmaxf(qpt, -pv.qpt_clamp()), pv.qpt_clamp());
+    C = -b * qpt;
+    const float sarg = fminf(fmaxf(fea * C * 0.5f, -1.0f), 1.0f);
+    const float phiA = atan2f((float)dye, (float)dxe) - asinf(sarg);
+    const float h = fea * fabsf(C) * 0.5f;
+    const float arc = h > 0.0f ? fea * asinf(fminf(h, 1.0f)) / h : fea;
+    Trk<float> k;
+    k.p[0] = (float)cl.y_fx[A] * (float)FX_SCALE;
+    k.p[1] = 0.0f;
+    k.p[2] = sinf(phiA);
+    k.p[3] = (float)(cl.z_fx[E] - anchor) * (float)FX_SCALE / arc;
+    k.p[4] = qpt;
+    if (!(fabsf(k.p[2]) < pv.snp_max())) continue;
+    c0_reset(k, pv, r1);
+    // ---- pass A: outward
+    float my = k.p[0], mz = 0.0f;
+    if (!update(k, my, mz, pv.vy(r1), pv.vz(r1), (float*)nullptr)) continue;
+    H[r1] = (int32_t)A;
+    int nh = 1;
+    Trk<float> last = k;
+    int r_out = r1, nmiss = 0, hi = r1;
+    int32_t ctl = (int32_t)A;  // walks the tracklet chain
+    for (int r = r1 + 1; r < NROW; ++r) {
+      if (!propagate(k, row_dx<float>(P, r - 1, r), pv, true, pv.snp_max())) break;
+      int32_t cand;
+      if (r < r1 + L) {
+        ctl = upc[ctl];
+        cand = ctl;
+      } else {
+        if (fabsf(k.p[0]) > pv.hw(r) + pv.edge_margin()) break;
+        cand = search_row(cl, cblk, nblk, ubase + r, k, anchor, pv.vy(r), pv.vz(r), chi2max);
+      }
+      hi = r;
+      H[r] = -1;
+      if (cand < 0) {
+        if (++nmiss >= P->max_miss) break;
+        continue;
+      }
+      my = (float)cl.y_fx[cand] * (float)FX_SCALE;
+      mz = (float)(cl.z_fx[cand] - anchor) * (float)FX_SCALE;
+      if (!update(k, my, mz, pv.vy(r), pv.vz(r), (float*)nullptr)) break;
+      H[r] = cand;
+      ++nh;
+      last = k;
+      r_out = r;
+      nmiss = 0;
+    }
+    // ---- pass B: inward from the outermost hit with a reset covariance
+    k = last;
+    c0_reset(k, pv, r_out);
+    Trk<float> inner = last;
+    int r_in = r_out, lo = r1;
+    {
+      const int32_t co = H[r_out];
+      my = (float)cl.y_fx[co] * (float)FX_SCALE;
+      mz = (float)(cl.z_fx[co] - anchor) * (float)FX_SCALE;
+    }
+    if (update(k, my, mz, pv.vy(r_out), pv.vz(r_out), (float*)nullptr)) {
+      inner = k;
+      nmiss = 0;
+      for (int r = r_out - 1; r >= 0; --r) {
+        if (!propagate(k, row_dx<float>(P, r + 1, r), pv, true, pv.snp_max())) break;
+        int32_t cand = r >= r1 ? H[r] : -1;
+        bool fresh = false;
+        if (cand < 0) {
+          if (fabsf(k.p[0]) > pv.hw(r) + pv.edge_margin()) break;
+          cand = search_row(cl, cblk, nblk, ubase + r, k, anchor, pv.vy(r), pv.vz(r), chi2max);
+          if (r < lo) {
+            lo = r;
+            H[r] = -1;
+          }
+          if (cand < 0) {
+            if (r < r1 && ++nmiss >= P->max_miss) break;
+            continue;
+          }
+          fresh = true;
+        }
+        my = (float)cl.y_fx[cand] * (float)FX_SCALE;
+        mz = (float)(cl.z_fx[cand] - anchor) * (float)FX_SCALE;
+        if (!update(k, my, mz, pv.vy(r), pv.vz(r), (float*)nullptr)) break;
+        if (fresh) {
+          H[r] = cand;
+          ++nh;
+        }
+        inner = k;
+        r_in = r;
+        nmiss = 0;
+      }
+    }
+    float* S = fo.state + (size_t)t * 6;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) S[i] = inner.p[i];
+    S[5] = (float)r_in;
+    fo.nhits[t] = (uint16_t)nh;
+    fo.range[t] = (uint16_t)(lo | (hi << 8));
+    fo.ok[t] = 1;
+  }
+}
+
+__device__ __forceinline__ uint64_t track_key(uint32_t nh, uint32_t t) {
+  return ((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - t);
+}
+
+// Every followed tracklet with enough hits bids for its clusters.
+__global__ void k_claim(FollowOut fo, const uint32_t* n_tl_dev, uint32_t tl_cap,
+                        unsigned long long* __restrict__ owner, uint32_t n_cl_cap,
+                        const DevParams* __restrict__ P, const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+    if (!fo.ok[t] || (int)fo.nhits[t] < P->min_track_hits) continue;
+    const unsigned long long key = track_key(fo.nhits[t], t);
+    const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
+    const int32_t* H = fo.hits + (size_t)t * NROW;
+    for (int r = lo; r <= hi; ++r) {
+      const int32_t c = H[r];
+      if (c >= 0 && (uint32_t)c < n_cl_cap) atomicMax(&owner[c], key);
+    }
+  }
+}
+
+// Hits each track keeps after the claims; < min_track_hits drops the track.
+__global__ void k_keep(FollowOut fo, const uint32_t* n_tl_dev, uint32_t tl_cap,
+                       const unsigned long long* __restrict__ owner, uint32_t n_cl_cap,
+                       uint16_t* __restrict__ nkept, const DevParams* __restrict__ P,
+                       const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+    uint32_t n = 0;
+    if (fo.ok[t] && (int)fo.nhits[t] >= P->min_track_hits) {
+      const unsigned long long key = track_key(fo.nhits[t], t);
+      const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
+      const int32_t* H = fo.hits + (size_t)t * NROW;
+      for (int r = lo; r <= hi; ++r) {
+        const int32_t c = H[r];
+        n += (c >= 0 && (uint32_t)c < n_cl_cap && owner[c] == key) ? 1u : 0u;
+      }
+      if ((int)n < P->min_track_hits) n = 0;
+    }
+    nkept[t] = (uint16_t)n;
+  }
+}
+
+struct RefitOut {
+  float* par;      // [cap*5]
+  float* cov;      // [cap*15]
+  float* chi2;     // [cap]
+  uint8_t* row;    // [cap]
+  uint8_t* flags;  // [cap]
+};
+
+__device__ __forceinline__ int32_t tl_anchor(const ClusterView& cl, const uint32_t* tl_start,
+                                             uint32_t t) {
+  return cl.z_fx[tl_start[t]];
+}
+
+// Kept hits of the first refit updates, done in FP64: while the prior
+// variance collapses by orders of magnitude, FP32 cancellation in the
+// covariance update would bias the result; afterwards FP32 keeps up.
+#define REFIT_HEAD 5
+
+// Kalman steps of the refit: from row r downwards, through at most
+// max_hits kept hits; the state k sits at row r_state.  On return r is the
+// next row to examine.  Returns 1 if the helix cannot reach a hit's row or an
+// update fails; pd turns false if an update left the covariance not PD.
+template <typename T>
+__device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, const FollowOut& fo,
+                         const unsigned long long* owner, const DevParams* P, Trk<T>& k,
+                         T& chi2s, int& r_state, int& r, int max_hits, bool& pd) {
+  const PV<T> pv{P};
+  const unsigned long long key = track_key(fo.nhits[t], t);
+  const int lo = fo.range[t] & 255;
+  const int32_t* H = fo.hits + (size_t)t * NROW;
+  int done = 0;
+  for (; r >= lo && done < max_hits; --r) {
+    const int32_t c = H[r];
+    if (c < 0 || owner[c] != key) continue;
+    if (r != r_state && !propagate(k, row_dx<T>(P, r_state, r), pv, true, pv.refit_snp_max()))
+      return 1;
+    const T my = (T)cl.y_fx[c] * (T)FX_SCALE;
+    const T mz = (T)(cl.z_fx[c] - anchor) * (T)FX_SCALE;
+    T x2;
+    if (!update_joseph(k, my, mz, pv.vy(r), pv.vz(r), &x2)) return 1;
+    chi2s += x2;
+    if (!is_pd(k.c)) pd = false;
+    r_state = r;
+    ++done;
+  }
+  return 0;
+}
+
+// Start of the refit: the circle through the innermost, middle and outermost
+// kept clusters, evaluated at the outermost one, with the broad refit prior.
+// Fixed-point differences are exact integers.  Returns the outermost kept
+// row, or -1 if the track has fewer than 3 kept hits.
+template <typename T>
+__device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, const FollowOut& fo,
+                          const unsigned long long* owner, const DevParams* P, Trk<T>& k) {
+  const PV<T> pv{P};
+  const unsigned long long key = track_key(fo.nhits[t], t);
+  const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
+  const int32_t* H = fo.hits + (size_t)t * NROW;
+  int n = 0, rA = -1, rE = -1;
+  for (int r = hi; r >= lo; --r) {
+    const int32_t c = H[r];
+    if (c < 0 || owner[c] != key) continue;
+    if (rE < 0) rE = r;
+    rA = r;
+    ++n;
+  }
+  if (n < 3) return -1;
+  const int im = (n + 1) / 2 - 1;  // middle, counted from the innermost
+  int rM = -1, j = 0;
+  for (int r = lo; r <= hi; ++r) {
+    const int32_t c = H[r];
+    if (c < 0 || owner[c] != key) continue;
+    if (j++ == im) {
+      rM = r;
+      break;
+    }
+  }
+  const int32_t cA = H[rA], cM = H[rM], cE = H[rE];
+  const int64_t dxm = P->xfx[rM] - P->xfx[rA], dym = (int64_t)cl.y_fx[cM] - cl.y_fx[cA];
+  const int64_t dxe = P->xfx[rE] - P->xfx[rA], dye = (int64_t)cl.y_fx[cE] - cl.y_fx[cA];
+  const int64_t dxx = P->xfx[rE] - P->xfx[rM], dyy = (int64_t)cl.y_fx[cE] - cl.y_fx[cM];
+  const T S = (T)FX_SCALE;
+  const T cross = (T)(dxm * dye - dym * dxe) * S * S;
+  const T dma = hypot((T)dxm, (T)dym) * S, dea = hypot((T)dxe, (T)dye) * S;
+  const T dem = hypot((T)dxx, (T)dyy) * S;
+  const T b = pv.b();
+  T C = (T)2 * cross / (dma * dem * dea);
+  T qpt = -C / b;
+  qpt = fmin(fmax(qpt, -pv.qpt_clamp()), pv.qpt_clamp());
+  C = -b * qpt;
+  const T sarg = fmin(fmax(dea * C * (T)0.5, (T)-1), (T)1);
+  const T h = dea * fabs(C) * (T)0.5;
+  const T arc = h > (T)0 ? dea * asin(fmin(h, (T)1)) / h : dea;
+  k.p[0] = (T)cl.y_fx[cE] * S;
+  k.p[1] = (T)(cl.z_fx[cE] - anchor) * S;
+  k.p[2] = sin(atan2((T)dye, (T)dxe) + asin(sarg));  // tangent at the far end of the chord
+  k.p[3] = (T)(cl.z_fx[cE] - cl.z_fx[cA]) * S / arc;
+  k.p[4] = qpt;
+#pragma unroll
+  for (int i = 0; i < 15; ++i) k.c[i] = 0;
+  k.c[PI(0, 0)] = pv.c0r(0);
+  k.c[PI(1, 1)] = pv.c0r(1);
+  k.c[PI(2, 2)] = pv.c0r(2);
+  k.c[PI(3, 3)] = pv.c0r(3);
+  k.c[PI(4, 4)] = pv.c0r(4);
+  return rE;
+}
+
+struct RefitHead {
+  double* state;   // [cap*20]: p[5], packed covariance[15]
+  double* chi2;    // [cap]
+  int16_t* r;      // [cap] next row to examine
+  int16_t* rprev;  // [cap] row of the state
+  uint8_t* flags;  // [cap] 1 failed, 2 not PD, 4 low pT
+};
+
+__global__ __launch_bounds__(64) void k_refit_head(ClusterView cl,
+                                                   const uint32_t* __restrict__ tl_start,
+                                                   FollowOut fo, const uint32_t* n_tl_dev,
+                                                   uint32_t tl_cap,
+                                                   const unsigned long long* __restrict__ owner,
+                                                   const uint16_t* __restrict__ nkept,
+                                                   RefitHead hd, const DevParams* __restrict__ P,
+                                                   const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+    if (nkept[t] == 0) continue;
+    Trk<double> k;
+    double chi2s = 0;
+    const int32_t anchor = tl_anchor(cl, tl_start, t);
+    int rs = refit_seed<double>(t, cl, anchor, fo, owner, P, k);
+    int r = rs;
+    bool pd = true;
+    const bool lowpt = fabs(k.p[4]) >= (double)P->lowpt_qpt;
+    const int rc = rs < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, owner, P, k, chi2s, rs, r,
+                                                  REFIT_HEAD, pd);
+    double* S = hd.state + (size_t)t * 20;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) S[i] = k.p[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) S[5 + i] = k.c[i];
+    hd.chi2[t] = chi2s;
+    hd.r[t] = (int16_t)r;
+    hd.rprev[t] = (int16_t)rs;
+    hd.flags[t] = (uint8_t)((rc ? 1 : 0) | (pd ? 0 : 2) | (lowpt ? 4 : 0));
+  }
+}
+
+__global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* __restrict__ tl_start,
+                                                FollowOut fo, const uint32_t* n_tl_dev,
+                                                uint32_t tl_cap,
+                                                const unsigned long long* __restrict__ owner,
+                                                const uint16_t* __restrict__ nkept, RefitHead hd,
+                                                RefitOut ro, uint32_t* __restrict__ fb_list,
+                                                const DevParams* __restrict__ P, DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+    ro.flags[t] = 0;
+    if (nkept[t] == 0) continue;
+    if (hd.flags[t] & 1) {
+      ro.flags[t] = TF_REFIT_FAIL;
+      atomicAdd(&st->n_refit_fail, 1u);
+      continue;
+    }
+    Trk<float> k;
+    const double* S = hd.state + (size_t)t * 20;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) k.p[i] = (float)S[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) k.c[i] = (float)S[5 + i];
+    float chi2s = (float)hd.chi2[t];
+    int rprev = hd.rprev[t], r = hd.r[t];
+    bool pd = (hd.flags[t] & 2) == 0;
+    const int rc = refit_run<float>(t, cl, tl_anchor(cl, tl_start, t), fo, owner, P, k, chi2s,
+                                    rprev, r, NROW, pd);
+    if (rc) {
+      ro.flags[t] = TF_REFIT_FAIL;
+      atomicAdd(&st->n_refit_fail, 1u);
+      continue;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) ro.par[(size_t)t * 5 + i] = k.p[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) ro.cov[(size_t)t * 15 + i] = k.c[i];
+    ro.chi2[t] = chi2s;
+    ro.row[t] = (uint8_t)rprev;
+    const bool lowpt = (hd.flags[t] & 4) != 0;
+    if (P->force_fallback || (!pd && lowpt)) {
+      const uint32_t i = atomicAdd(&st->n_fb_list, 1u);
+      if (i < tl_cap) fb_list[i] = t;
+    } else if (!pd) {
+      ro.flags[t] = TF_NOT_PD;
+      atomicAdd(&st->n_not_pd, 1u);
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_refit64(ClusterView cl, const uint32_t* __restrict__ tl_start,
+                                                FollowOut fo, uint32_t tl_cap,
+                                                const unsigned long long* __restrict__ owner,
+                                                RefitOut ro, const uint32_t* __restrict__ fb_list,
+                                                const DevParams* __restrict__ P, DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n = scan_count(&st->n_fb_list, tl_cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t t = fb_list[i];
+    Trk<double> k;
+    double chi2s = 0;
+    const int32_t anchor = tl_anchor(cl, tl_start, t);
+    int rprev = refit_seed<double>(t, cl, anchor, fo, owner, P, k);
+    int r = rprev;
+    bool pd = true;
+    const int rc = rprev < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, owner, P, k, chi2s, rprev,
+                                                     r, NROW, pd);
+    atomicAdd(&st->n_fallback, 1u);
+    if (rc || rprev < 0 || !pd) {
+      const bool fail = rc || rprev < 0;
+      ro.flags[t] = fail ? TF_REFIT_FAIL : TF_FP64_FAIL;
+      atomicAdd(fail ? &st->n_refit_fail : &st->n_fallback_fail, 1u);
+      continue;
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) ro.par[(size_t)t * 5 + j] = (float)k.p[j];
+#pragma unroll
+    for (int j = 0; j < 15; ++j) ro.cov[(size_t)t * 15 + j] = (float)k.c[j];
+    ro.chi2[t] = (float)chi2s;
+    ro.row[t] = (uint8_t)rprev;
+    ro.flags[t] = TF_FP64;
+  }
+}
+
+// final keep flag of a tracklet slot
+__device__ __forceinline__ bool final_kept(const uint16_t* nkept, const RefitOut& ro, uint32_t t) {
+  return nkept[t] != 0 && (ro.flags[t] & (TF_REFIT_FAIL | TF_FP64_FAIL)) == 0;
+}
+
+struct GetTrackPair {
+  const uint16_t* nkept;
+  RefitOut ro;
+  __device__ unsigned long long operator()(uint32_t t) const {
+    return final_kept(nkept, ro, t) ? ((1ull << 32) | nkept[t]) : 0ull;
+  }
+};
+
+struct EmitTrackPair {
+  uint32_t* trk_index;  // [cap] track index or 0xFFFFFFFF
+  uint32_t* hit_off;    // [cap]
+  __device__ void operator()(uint32_t t, unsigned long long pre, unsigned long long v) const {
+    trk_index[t] = v ? (uint32_t)(pre >> 32) : 0xFFFFFFFFu;
+    hit_off[t] = (uint32_t)pre;
+  }
+};
+
+struct TrackOut {
+  uint32_t capacity, hit_capacity;
+  uint32_t* tracklet;
+  float *par, *cov, *chi2;
+  uint16_t* ndf;
+  uint8_t *row, *flags;
+  int32_t* z_anchor;
+  uint32_t* hit_start;
+  uint32_t* hits;
+  int32_t* cluster_track;
+};
+
+__global__ void k_track_totals(const unsigned long long* total, TrackOut to, uint32_t* n_tracks,
+                               uint32_t* n_hits, DevStatus* st) {
+  const unsigned long long v = *total;
+  const uint32_t nt = (uint32_t)(v >> 32), nh = (uint32_t)v;
+  st->n_tracks = nt;
+  st->n_hits = nh;
+  if (n_tracks) *n_tracks = nt;
+  if (n_hits) *n_hits = nh;
+  if (nt > to.capacity) latch(st, TPC_ERR_CAPACITY, nt);
+  if (nh > to.hit_capacity) latch(st, TPC_ERR_CAPACITY, nh);
+  if (nt <= to.capacity) to.hit_start[nt] = nh;
+}
+
+__global__ void k_track_emit(ClusterView cl, const uint32_t* __restrict__ tl_start, FollowOut fo,
+                             const uint32_t* n_tl_dev, uint32_t tl_cap,
+                             const unsigned long long* __restrict__ owner,
+                             const uint16_t* __restrict__ nkept, RefitOut ro,
+                             const uint32_t* __restrict__ trk_index,
+                             const uint32_t* __restrict__ hit_off, TrackOut to,
+                             const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+    const uint32_t j = trk_index[t];
+    if (j == 0xFFFFFFFFu || j >= to.capacity) continue;
+    to.tracklet[j] = t;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) to.par[(size_t)j * 5 + i] = ro.par[(size_t)t * 5 + i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) to.cov[(size_t)j * 15 + i] = ro.cov[(size_t)t * 15 + i];
+    to.chi2[j] = ro.chi2[t];
+    to.ndf[j] = (uint16_t)(2 * nkept[t] - 5);
+    to.row[j] = ro.row[t];
+    to.flags[j] = ro.flags[t];
+    to.z_anchor[j] = cl.z_fx[tl_start[t]];
+    uint32_t o = hit_off[t];
+    to.hit_start[j] = o;
+    const unsigned long long key = track_key(fo.nhits[t], t);
+    const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
+    const int32_t* H = fo.hits + (size_t)t * NROW;
+    for (int r = lo; r <= hi; ++r) {
+      const int32_t c = H[r];
+      if (c >= 0 && owner[c] == key) {
+        if (o < to.hit_capacity) to.hits[o] = (uint32_t)c;
+        ++o;
+      }
+    }
+  }
+}
+
+__global__ void k_cluster_track(const unsigned long long* __restrict__ owner,
+                                const uint32_t* __restrict__ trk_index, const uint32_t* n_cl_dev,
+                                uint32_t n_cl_cap, uint32_t tl_cap, int32_t* __restrict__ out,
+                                const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n = scan_count(n_cl_dev, n_cl_cap);
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const unsigned long long key = owner[c];
+    int32_t v = -1;
+    if (key) {
+      const uint32_t t = 0xFFFFFFFFu - (uint32_t)key;
+      if (t < tl_cap) {
+        const uint32_t j = trk_index[t];
+        if (j != 0xFFFFFFFFu) v = (int32_t)j;
+      }
+    }
+    out[c] = v;
+  }
+}
+
+// Per-tracklet following result as full rows (debug output).
+__global__ void k_follow_export(FollowOut fo, const uint32_t* n_tl_dev, uint32_t tl_cap,
+                                int32_t* __restrict__ out, const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tl * NROW;
+       i += gridDim.x * blockDim.x) {
+    const uint32_t t = i / NROW;
+    const int r = i % NROW;
+    const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
+    out[i] = (fo.ok[t] && r >= lo && r <= hi) ? fo.hits[i] : -1;
+  }
+}

@@ -1,0 +1,720 @@
+// libtpcreco: host side of the C ABI declared in include/tpc.h.
+//
+// A context owns the parameter block, the status word and the scratch; each
+// tpc_* call checks its host arguments and enqueues kernels on the context's
+// stream.  No call synchronises except tpc_sync, and nothing inside a launch
+// sequence allocates or uses hipMemset, so a sequence can be captured into a
+// HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+#include "k_cluster.hpp"
+#include "k_links.hpp"
+#include "k_track.hpp"
+
+#ifndef TPC_CL_WINDOW
+#define TPC_CL_WINDOW 48
+#endif
+
+namespace {
+
+constexpr uint32_t kWin = TPC_CL_WINDOW;
+
+struct Geometry {
+  int32_t np[NROW], xfx[NROW], pfx[NROW];
+};
+
+// Row r at x = 85 + 160 r / 151 cm with round(66 + 72 r / 151) pads of pitch
+// 2 x tan(10 deg) / n; fixed-point values in 2^-16 cm.
+Geometry make_geometry() {
+  Geometry g;
+  for (int r = 0; r < NROW; ++r) {
+    g.np[r] = (int32_t)((2 * (66 * 151 + 72 * r) + 151) / (2 * 151));
+    const int64_t num = (int64_t)(85 * 151 + 160 * r) * 65536;
+    g.xfx[r] = (int32_t)((2 * num + 151) / (2 * 151));
+    const double x = 85.0 + r * 160.0 / 151.0;
+    g.pfx[r] = (int32_t)std::floor(2.0 * x * std::tan(M_PI / 18.0) / g.np[r] * 65536.0 + 0.5);
+  }
+  return g;
+}
+
+uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+}  // namespace
+
+struct tpc_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  tpc_params par;
+  tpc_sizes max;
+  DevParams* d_par = nullptr;
+  DevStatus* d_st = nullptr;
+  // scratch
+  uint32_t* zblk = nullptr;   // sample block index
+  uint32_t* cblk = nullptr;   // cluster block index (hit grid)
+  uint32_t* win = nullptr;    // clusterizer window counts / offsets
+  void* bsum = nullptr;       // scan block sums (u64)
+  unsigned long long* tot64 = nullptr;
+  uint32_t* tot32 = nullptr;
+  uint16_t* chain_len = nullptr;
+  int32_t* f_hits = nullptr;
+  float* f_state = nullptr;
+  uint16_t* f_nhits = nullptr;
+  uint16_t* f_range = nullptr;
+  uint8_t* f_ok = nullptr;
+  unsigned long long* owner = nullptr;
+  uint16_t* nkept = nullptr;
+  float *r_par = nullptr, *r_cov = nullptr, *r_chi2 = nullptr;
+  uint8_t *r_row = nullptr, *r_flags = nullptr;
+  uint32_t* fb_list = nullptr;
+  double* h_state = nullptr;
+  double* h_chi2 = nullptr;
+  int16_t *h_r = nullptr, *h_rprev = nullptr;
+  uint8_t* h_flags = nullptr;
+  uint32_t* trk_index = nullptr;
+  uint32_t* hit_off = nullptr;
+  size_t bsum_cap = 0;
+  uint32_t nblk_max = 0, nwin_max = 0;
+  // stage timing (measurement only)
+  static constexpr int kProfCap = 64;
+  bool prof_on = false;
+  bool prof_events = false;
+  hipEvent_t prof_ev[TPC_PROF_STAGES][2][kProfCap];
+  uint32_t prof_n[TPC_PROF_STAGES] = {};
+};
+
+namespace {
+
+struct Layout {
+  size_t off = 0;
+  template <typename T>
+  size_t add(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    const size_t o = off;
+    off += n * sizeof(T);
+    return o;
+  }
+};
+
+struct Plan {
+  size_t zblk, cblk, win, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok,
+      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
+      h_flags, trk_index, hit_off, par, st, total;
+  size_t bsum_cap;
+  uint32_t nblk, nwin;
+};
+
+Plan plan_for(const tpc_sizes& m) {
+  Plan p;
+  Layout L;
+  const uint64_t nur = (uint64_t)m.max_units * NROW;
+  p.nblk = ceil_div(m.max_time_bins, 8);
+  p.nwin = ceil_div(m.max_time_bins, kWin);
+  uint64_t nscan = nur * p.nwin;
+  if (m.max_clusters > nscan) nscan = m.max_clusters;
+  if (m.max_tracklets > nscan) nscan = m.max_tracklets;
+  p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
+  const uint64_t mc = m.max_clusters > 0 ? m.max_clusters : 1;
+  const uint64_t mt = m.max_tracklets > 0 ? m.max_tracklets : 1;
+  p.zblk = L.add<uint32_t>(nur * (p.nblk + 1));
+  p.cblk = L.add<uint32_t>(nur * (p.nblk + 1));
+  p.win = L.add<uint32_t>(nur * p.nwin);
+  p.bsum = L.add<unsigned long long>(p.bsum_cap);
+  p.tot64 = L.add<unsigned long long>(1);
+  p.tot32 = L.add<uint32_t>(1);
+  p.chain_len = L.add<uint16_t>(mc);
+  p.f_hits = L.add<int32_t>(mt * NROW);
+  p.f_state = L.add<float>(mt * 6);
+  p.f_nhits = L.add<uint16_t>(mt);
+  p.f_range = L.add<uint16_t>(mt);
+  p.f_ok = L.add<uint8_t>(mt);
+  p.owner = L.add<unsigned long long>(mc);
+  p.nkept = L.add<uint16_t>(mt);
+  p.r_par = L.add<float>(mt * 5);
+  p.r_cov = L.add<float>(mt * 15);
+  p.r_chi2 = L.add<float>(mt);
+  p.r_row = L.add<uint8_t>(mt);
+  p.r_flags = L.add<uint8_t>(mt);
+  p.fb_list = L.add<uint32_t>(mt);
+  p.h_state = L.add<double>(mt * 20);
+  p.h_chi2 = L.add<double>(mt);
+  p.h_r = L.add<int16_t>(mt);
+  p.h_rprev = L.add<int16_t>(mt);
+  p.h_flags = L.add<uint8_t>(mt);
+  p.trk_index = L.add<uint32_t>(mt);
+  p.hit_off = L.add<uint32_t>(mt);
+  p.par = L.add<DevParams>(1);
+  p.st = L.add<DevStatus>(1);
+  p.total = (L.off + 255) & ~(size_t)255;
+  return p;
+}
+
+DevParams make_dev_params(const tpc_params& p) {
+  DevParams d;
+  std::memset(&d, 0, sizeof d);
+  const Geometry g = make_geometry();
+  for (int r = 0; r < NROW; ++r) {
+    d.np[r] = g.np[r];
+    d.xfx[r] = g.xfx[r];
+    d.pfx[r] = g.pfx[r];
+    d.xd[r] = g.xfx[r] / 65536.0;
+    d.hwd[r] = (double)((int64_t)g.np[r] * g.pfx[r]) / 131072.0;
+    d.vyd[r] = p.sigma_y[r] * p.sigma_y[r];
+    d.vzd[r] = p.sigma_z[r] * p.sigma_z[r];
+    d.x[r] = (float)d.xd[r];
+    d.hw[r] = (float)d.hwd[r];
+    d.vy[r] = (float)d.vyd[r];
+    d.vz[r] = (float)d.vzd[r];
+  }
+  d.qmax_min = p.qmax_min;
+  d.min_tracklet = p.min_tracklet;
+  d.max_miss = p.max_miss;
+  d.min_track_hits = p.min_track_hits;
+  d.win_y = p.win_y;
+  d.win_z = p.win_z;
+  d.s_max = p.s_max;
+  d.chi2_max_d = p.chi2_max;
+  d.snp_max_d = p.snp_max;
+  d.bz_b_d = p.bz_b;
+  d.c0_snp2_d = p.c0_snp * p.c0_snp;
+  d.c0_tgl2_d = p.c0_tgl * p.c0_tgl;
+  d.c0_qpt2_d = p.c0_qpt * p.c0_qpt;
+  d.qpt_clamp_d = p.qpt_clamp;
+  d.edge_margin_d = p.edge_margin;
+  d.chi2_max = (float)p.chi2_max;
+  d.snp_max = (float)p.snp_max;
+  d.bz_b = (float)p.bz_b;
+  d.c0_snp2 = (float)d.c0_snp2_d;
+  d.c0_tgl2 = (float)d.c0_tgl2_d;
+  d.c0_qpt2 = (float)d.c0_qpt2_d;
+  d.qpt_clamp = (float)p.qpt_clamp;
+  d.edge_margin = (float)p.edge_margin;
+  d.lowpt_qpt = (float)p.lowpt_qpt;
+  const double c0r[5] = {p.c0r_y, p.c0r_z, p.c0r_snp, p.c0r_tgl, p.c0r_qpt};
+  for (int i = 0; i < 5; ++i) {
+    d.c0r2_d[i] = c0r[i] * c0r[i];
+    d.c0r2[i] = (float)d.c0r2_d[i];
+  }
+  d.refit_snp_max_d = p.refit_snp_max;
+  d.refit_snp_max = (float)p.refit_snp_max;
+  d.validate = p.validate;
+  d.force_fallback = p.force_fallback;
+  return d;
+}
+
+#define HIP_OK(x)                        \
+  do {                                   \
+    if ((x) != hipSuccess) return TPC_ERR_HIP; \
+  } while (0)
+
+int launch_ok() { return hipGetLastError() == hipSuccess ? TPC_OK : TPC_ERR_HIP; }
+
+uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 1u << 20) {
+  uint64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+// Records a pair of events around one stage when stage timing is on.
+struct StageTimer {
+  tpc_ctx* c;
+  int id;
+  bool on;
+  StageTimer(tpc_ctx* ctx, int stage) : c(ctx), id(stage) {
+    on = c->prof_on && c->prof_n[id] < tpc_ctx::kProfCap;
+    if (on) (void)hipEventRecord(c->prof_ev[id][0][c->prof_n[id]], c->stream);
+  }
+  ~StageTimer() {
+    if (on) {
+      (void)hipEventRecord(c->prof_ev[id][1][c->prof_n[id]], c->stream);
+      ++c->prof_n[id];
+    }
+  }
+};
+
+template <typename T, class Get, class Emit>
+void run_scan(tpc_ctx* c, Get get, Emit emit, const uint32_t* n_dev, uint32_t n_cap, T* total,
+              uint32_t* total32) {
+  uint32_t nb = ceil_div(n_cap, SCAN_TILE);
+  if (nb < 1) nb = 1;
+  T* bs = reinterpret_cast<T*>(c->bsum);
+  k_scan_reduce<T, Get><<<nb, SCAN_BLOCK, 0, c->stream>>>(get, n_dev, n_cap, bs, c->d_st);
+  k_scan_blocks<T><<<1, 1024, 0, c->stream>>>(bs, nb, total, total32, c->d_st);
+  k_scan_down<T, Get, Emit><<<nb, SCAN_BLOCK, 0, c->stream>>>(get, emit, n_dev, n_cap, bs, c->d_st);
+}
+
+struct GetU32 {
+  const uint32_t* a;
+  __device__ uint32_t operator()(uint32_t i) const { return a[i]; }
+};
+struct EmitU32 {
+  uint32_t* out;
+  __device__ void operator()(uint32_t i, uint32_t pre, uint32_t) const { out[i] = pre; }
+};
+
+ZsArgs zs_args(const tpc_zs_input* in) {
+  return ZsArgs{in->pad, in->time, in->adc, in->row_start, in->n_samples, in->n_units,
+                in->n_time_bins};
+}
+
+ClusterView cluster_view(const tpc_clusters* cl) {
+  return ClusterView{cl->y_fx, cl->z_fx, cl->ptime, cl->crow_start, cl->n_clusters, cl->capacity};
+}
+
+FollowOut follow_out(tpc_ctx* c) {
+  return FollowOut{c->f_hits, c->f_state, c->f_nhits, c->f_range, c->f_ok};
+}
+
+RefitOut refit_out(tpc_ctx* c) {
+  return RefitOut{c->r_par, c->r_cov, c->r_chi2, c->r_row, c->r_flags};
+}
+
+// ------------------------------------------------------------- validation
+int check_units(tpc_ctx* c, uint32_t n_units, uint32_t n_time_bins) {
+  if (n_units == 0 || n_units > c->max.max_units) return TPC_ERR_ARG;
+  if (n_time_bins == 0 || n_time_bins > c->max.max_time_bins) return TPC_ERR_ARG;
+  return TPC_OK;
+}
+
+int check_input(tpc_ctx* c, const tpc_zs_input* in) {
+  if (!in) return TPC_ERR_ARG;
+  if (check_units(c, in->n_units, in->n_time_bins)) return TPC_ERR_ARG;
+  if (!in->row_start) return TPC_ERR_ARG;
+  if (in->n_samples && (!in->pad || !in->time || !in->adc)) return TPC_ERR_ARG;
+  return TPC_OK;
+}
+
+int check_clusters(tpc_ctx* c, const tpc_clusters* cl, bool full) {
+  if (!cl) return TPC_ERR_ARG;
+  if (check_units(c, cl->n_units, cl->n_time_bins)) return TPC_ERR_ARG;
+  if (!cl->n_clusters || !cl->crow_start || !cl->y_fx || !cl->z_fx || !cl->ptime)
+    return TPC_ERR_ARG;
+  if (cl->capacity > c->max.max_clusters) return TPC_ERR_ARG;
+  if (full && (!cl->dpad || !cl->dtime || !cl->s2pad || !cl->s2time || !cl->qtot || !cl->qmax ||
+               !cl->ppad || !cl->flags))
+    return TPC_ERR_ARG;
+  const bool any_m = cl->sp || cl->st || cl->spp || cl->stt || cl->nsamp;
+  const bool all_m = cl->sp && cl->st && cl->spp && cl->stt && cl->nsamp;
+  if (any_m && !all_m) return TPC_ERR_ARG;
+  return TPC_OK;
+}
+
+int check_links(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, bool clean) {
+  if (!l || !l->down || !l->up) return TPC_ERR_ARG;
+  if (clean && (!l->downc || !l->upc)) return TPC_ERR_ARG;
+  if (l->capacity < cl->capacity) return TPC_ERR_ARG;
+  (void)c;
+  return TPC_OK;
+}
+
+int check_tracklets(tpc_ctx* c, const tpc_tracklets* t) {
+  if (!t || !t->n_tracklets || !t->start || !t->len) return TPC_ERR_ARG;
+  if (t->capacity > c->max.max_tracklets) return TPC_ERR_ARG;
+  return TPC_OK;
+}
+
+int check_tracks(const tpc_tracks* t) {
+  if (!t || !t->n_tracks || !t->n_hits || !t->tracklet || !t->par || !t->cov || !t->chi2 ||
+      !t->ndf || !t->row || !t->flags || !t->z_anchor || !t->hit_start || !t->hits ||
+      !t->cluster_track)
+    return TPC_ERR_ARG;
+  return TPC_OK;
+}
+
+// ------------------------------------------------------------- stages
+int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
+  const uint32_t n_ur = in->n_units * NROW;
+  const uint32_t nblk = ceil_div(in->n_time_bins, 8);
+  const uint32_t nwin = ceil_div(in->n_time_bins, kWin);
+  hipStream_t s = c->stream;
+  {
+    StageTimer tm(c, 0);
+    k_block_index<<<n_ur, 256, 0, s>>>(in->time, in->pad, in->row_start, n_ur, nblk,
+                                       in->n_time_bins, in->n_samples, c->zblk, c->d_par, c->d_st, 1);
+  }
+  ClusterOut co{out->capacity, out->y_fx, out->z_fx, out->dpad, out->dtime, out->s2pad, out->s2time,
+                out->qtot, out->qmax, out->ppad, out->ptime, out->flags, out->sp, out->st,
+                out->spp, out->stt, out->nsamp, out->sample_label};
+  const ZsArgs za = zs_args(in);
+  const uint32_t nwt = n_ur * nwin;
+  {
+    StageTimer tm(c, 1);
+    k_cluster<kWin, false><<<nwt, 256, 0, s>>>(za, c->zblk, nblk, nwin, n_ur, c->win, nullptr, co,
+                                               c->d_par, c->d_st);
+  }
+  {
+    StageTimer tm(c, 2);
+    run_scan<uint32_t>(c, GetU32{c->win}, EmitU32{c->win}, nullptr, nwt, (uint32_t*)nullptr,
+                       out->n_clusters);
+    k_crow_start<<<grid_for(n_ur + 1, 256), 256, 0, s>>>(c->win, nwin, n_ur, out->n_clusters,
+                                                         out->capacity, out->crow_start, c->d_st);
+  }
+  {
+    StageTimer tm(c, 3);
+    k_cluster<kWin, true><<<nwt, 256, 0, s>>>(za, c->zblk, nblk, nwin, n_ur, nullptr, c->win, co,
+                                              c->d_par, c->d_st);
+  }
+  if (out->sample_label)
+    k_sample_label<<<n_ur, 256, 0, s>>>(za, out->crow_start, out->ppad, out->ptime, n_ur,
+                                        out->sample_label, c->d_st);
+  return launch_ok();
+}
+
+int stage_grid(tpc_ctx* c, const tpc_clusters* cl) {
+  const uint32_t n_ur = cl->n_units * NROW;
+  const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
+  StageTimer tm(c, 4);
+  k_block_index<<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk,
+                                             cl->n_time_bins, cl->capacity, c->cblk, c->d_par,
+                                             c->d_st, 0);
+  return launch_ok();
+}
+
+int stage_neighbours(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l) {
+  const uint32_t n_ur = cl->n_units * NROW;
+  const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
+  StageTimer tm(c, 5);
+  k_neighbours<<<n_ur, 256, 0, c->stream>>>(cluster_view(cl), c->cblk, nblk, n_ur, l->down, l->up,
+                                            c->d_par, c->d_st);
+  return launch_ok();
+}
+
+int stage_tracklets(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l, tpc_tracklets* t) {
+  hipStream_t s = c->stream;
+  const uint32_t cap = cl->capacity;
+  const uint32_t g = grid_for(cap, 256);
+  StageTimer tm(c, 6);
+  k_ca_clean<<<g, 256, 0, s>>>(l->down, l->up, l->downc, l->upc, cl->n_clusters, cap, c->d_st);
+  k_chain_len<<<g, 256, 0, s>>>(l->downc, l->upc, c->chain_len, cl->n_clusters, cap, c->d_par,
+                                c->d_st);
+  run_scan<uint32_t>(c, GetKeepLen{c->chain_len},
+                     EmitTracklet{c->chain_len, t->start, t->len, t->capacity}, cl->n_clusters, cap,
+                     (uint32_t*)nullptr, c->tot32);
+  k_tracklet_count<<<1, 1, 0, s>>>(c->tot32, t->capacity, t->n_tracklets, c->d_st);
+  return launch_ok();
+}
+
+int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_tracklets* t,
+              tpc_tracks* tr) {
+  hipStream_t s = c->stream;
+  const uint32_t n_ur = cl->n_units * NROW;
+  const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
+  const uint32_t tcap = t->capacity;
+  const uint32_t ccap = cl->capacity;
+  const ClusterView cv = cluster_view(cl);
+  const FollowOut fo = follow_out(c);
+  const RefitOut ro = refit_out(c);
+  const uint32_t g64 = grid_for(tcap, 64);
+  const uint32_t g256 = grid_for(tcap, 256);
+  // per-call counters of the fit stage
+  k_fill<uint32_t><<<1, 64, 0, s>>>(&c->d_st->n_fallback, 0u, 5);
+  {
+    StageTimer tm(c, 7);
+    k_follow<<<g64, 64, 0, s>>>(cv, c->cblk, nblk, n_ur, l->upc, t->start, t->len,
+                                t->n_tracklets, tcap, fo, c->d_par, c->d_st);
+  }
+  {
+    StageTimer tm(c, 8);
+    k_fill_dev<unsigned long long><<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, 0ull,
+                                                                        cl->n_clusters, ccap);
+    k_claim<<<g256, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->d_par, c->d_st);
+    k_keep<<<g256, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->nkept, c->d_par,
+                                c->d_st);
+  }
+  {
+    StageTimer tm(c, 9);
+    const RefitHead hd{c->h_state, c->h_chi2, c->h_r, c->h_rprev, c->h_flags};
+    k_refit_head<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept, hd,
+                                    c->d_par, c->d_st);
+    k_refit32<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept, hd,
+                                 ro, c->fb_list, c->d_par, c->d_st);
+  }
+  {
+    StageTimer tm(c, 10);
+    k_refit64<<<g64, 64, 0, s>>>(cv, t->start, fo, tcap, c->owner, ro, c->fb_list, c->d_par,
+                                 c->d_st);
+  }
+  StageTimer tm(c, 11);
+  run_scan<unsigned long long>(c, GetTrackPair{c->nkept, ro}, EmitTrackPair{c->trk_index, c->hit_off},
+                               t->n_tracklets, tcap, c->tot64, (uint32_t*)nullptr);
+  TrackOut to{tr->capacity, tr->hit_capacity, tr->tracklet, tr->par, tr->cov, tr->chi2, tr->ndf,
+              tr->row, tr->flags, tr->z_anchor, tr->hit_start, tr->hits, tr->cluster_track};
+  k_track_totals<<<1, 1, 0, s>>>(c->tot64, to, tr->n_tracks, tr->n_hits, c->d_st);
+  k_track_emit<<<g256, 256, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept, ro,
+                                    c->trk_index, c->hit_off, to, c->d_st);
+  k_cluster_track<<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, c->trk_index, cl->n_clusters, ccap,
+                                                      tcap, tr->cluster_track, c->d_st);
+  if (tr->follow_hits)
+    k_follow_export<<<grid_for((uint64_t)tcap * NROW, 256), 256, 0, s>>>(fo, t->n_tracklets, tcap,
+                                                                          tr->follow_hits, c->d_st);
+  return launch_ok();
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+int tpc_params_default(tpc_params* p, double noise_sigma) {
+  if (!p || !(noise_sigma > 0)) return TPC_ERR_ARG;
+  std::memset(p, 0, sizeof *p);
+  p->qmax_min = (int32_t)std::floor(5.0 * noise_sigma + 0.5);
+  p->min_tracklet = 5;
+  p->max_miss = 6;
+  p->min_track_hits = 15;
+  p->win_y = 163840;
+  p->win_z = 163840;
+  p->s_max = (int64_t)1 << 32;
+  p->chi2_max = 16.0;
+  p->snp_max = 0.95;
+  p->bz_b = 0.299792458e-3 * 5.0;
+  p->c0_snp = 0.1;
+  p->c0_tgl = 0.1;
+  p->c0_qpt = 10.0;
+  p->qpt_clamp = 20.0;
+  p->edge_margin = 1.0;
+  p->lowpt_qpt = 5.0;
+  p->c0r_y = 5.0;
+  p->c0r_z = 5.0;
+  p->c0r_snp = 0.5;
+  p->c0r_tgl = 0.5;
+  p->c0r_qpt = 10.0;
+  p->refit_snp_max = 0.999;
+  for (int r = 0; r < NROW; ++r) {
+    p->sigma_y[r] = 0.06;
+    p->sigma_z[r] = 0.05;
+  }
+  return TPC_OK;
+}
+
+int tpc_geometry(int32_t* npads, int32_t* x_fx, int32_t* pitch_fx) {
+  const Geometry g = make_geometry();
+  for (int r = 0; r < NROW; ++r) {
+    if (npads) npads[r] = g.np[r];
+    if (x_fx) x_fx[r] = g.xfx[r];
+    if (pitch_fx) pitch_fx[r] = g.pfx[r];
+  }
+  return TPC_OK;
+}
+
+int tpc_workspace_size(const tpc_sizes* max, size_t* bytes) {
+  if (!max || !bytes) return TPC_ERR_ARG;
+  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65535)
+    return TPC_ERR_ARG;
+  *bytes = plan_for(*max).total;
+  return TPC_OK;
+}
+
+int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* hip_stream) {
+  if (!out || !p || !max) return TPC_ERR_ARG;
+  *out = nullptr;
+  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65535)
+    return TPC_ERR_ARG;
+  if (p->min_tracklet < 3 || p->min_tracklet > NROW || p->min_track_hits < 3 || p->max_miss < 1 ||
+      p->qmax_min < 1 || !(p->chi2_max > 0) || !(p->snp_max > 0 && p->snp_max < 1) ||
+      p->win_y < 0 || p->win_z < 0 || p->s_max < 0)
+    return TPC_ERR_ARG;
+  for (int r = 0; r < NROW; ++r)
+    if (!(p->sigma_y[r] > 0) || !(p->sigma_z[r] > 0)) return TPC_ERR_ARG;
+  tpc_ctx* c = new (std::nothrow) tpc_ctx();
+  if (!c) return TPC_ERR_STATE;
+  c->stream = (hipStream_t)hip_stream;
+  c->par = *p;
+  c->max = *max;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return TPC_ERR_HIP;
+  }
+  const Plan pl = plan_for(*max);
+  char* base = nullptr;
+  if (hipMalloc(&base, pl.total) != hipSuccess) {
+    delete c;
+    return TPC_ERR_HIP;
+  }
+  c->zblk = (uint32_t*)(base + pl.zblk);
+  c->cblk = (uint32_t*)(base + pl.cblk);
+  c->win = (uint32_t*)(base + pl.win);
+  c->bsum = base + pl.bsum;
+  c->tot64 = (unsigned long long*)(base + pl.tot64);
+  c->tot32 = (uint32_t*)(base + pl.tot32);
+  c->chain_len = (uint16_t*)(base + pl.chain_len);
+  c->f_hits = (int32_t*)(base + pl.f_hits);
+  c->f_state = (float*)(base + pl.f_state);
+  c->f_nhits = (uint16_t*)(base + pl.f_nhits);
+  c->f_range = (uint16_t*)(base + pl.f_range);
+  c->f_ok = (uint8_t*)(base + pl.f_ok);
+  c->owner = (unsigned long long*)(base + pl.owner);
+  c->nkept = (uint16_t*)(base + pl.nkept);
+  c->r_par = (float*)(base + pl.r_par);
+  c->r_cov = (float*)(base + pl.r_cov);
+  c->r_chi2 = (float*)(base + pl.r_chi2);
+  c->r_row = (uint8_t*)(base + pl.r_row);
+  c->r_flags = (uint8_t*)(base + pl.r_flags);
+  c->fb_list = (uint32_t*)(base + pl.fb_list);
+  c->h_state = (double*)(base + pl.h_state);
+  c->h_chi2 = (double*)(base + pl.h_chi2);
+  c->h_r = (int16_t*)(base + pl.h_r);
+  c->h_rprev = (int16_t*)(base + pl.h_rprev);
+  c->h_flags = (uint8_t*)(base + pl.h_flags);
+  c->trk_index = (uint32_t*)(base + pl.trk_index);
+  c->hit_off = (uint32_t*)(base + pl.hit_off);
+  c->d_par = (DevParams*)(base + pl.par);
+  c->d_st = (DevStatus*)(base + pl.st);
+  c->bsum_cap = pl.bsum_cap;
+  c->nblk_max = pl.nblk;
+  c->nwin_max = pl.nwin;
+  const DevParams dp = make_dev_params(*p);
+  DevStatus ds;
+  std::memset(&ds, 0, sizeof ds);
+  if (hipMemcpy(c->d_par, &dp, sizeof dp, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_st, &ds, sizeof ds, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(base);
+    delete c;
+    return TPC_ERR_HIP;
+  }
+  *out = c;
+  return TPC_OK;
+}
+
+int tpc_destroy(tpc_ctx* c) {
+  if (!c) return TPC_ERR_ARG;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->prof_events)
+    for (int i = 0; i < TPC_PROF_STAGES; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int k = 0; k < tpc_ctx::kProfCap; ++k) (void)hipEventDestroy(c->prof_ev[i][j][k]);
+  // zblk is the base of the single scratch allocation
+  (void)hipFree(c->zblk);
+  delete c;
+  return TPC_OK;
+}
+
+int tpc_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
+  if (!c || check_input(c, in) || check_clusters(c, out, true)) return TPC_ERR_ARG;
+  if (out->n_units != in->n_units || out->n_time_bins != in->n_time_bins) return TPC_ERR_ARG;
+  return stage_cluster(c, in, out);
+}
+
+int tpc_find_neighbours(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l) {
+  if (!c || check_clusters(c, cl, false) || check_links(c, cl, l, false)) return TPC_ERR_ARG;
+  int rc = stage_grid(c, cl);
+  if (rc) return rc;
+  return stage_neighbours(c, cl, l);
+}
+
+int tpc_build_tracklets(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l, tpc_tracklets* t) {
+  if (!c || check_clusters(c, cl, false) || check_links(c, cl, l, true) || check_tracklets(c, t))
+    return TPC_ERR_ARG;
+  return stage_tracklets(c, cl, l, t);
+}
+
+int tpc_fit_tracks(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_tracklets* t,
+                   tpc_tracks* tr) {
+  if (!c || check_clusters(c, cl, false) || check_links(c, cl, l, true) || check_tracklets(c, t) ||
+      check_tracks(tr))
+    return TPC_ERR_ARG;
+  int rc = stage_grid(c, cl);
+  if (rc) return rc;
+  return stage_fit(c, cl, l, t, tr);
+}
+
+int tpc_process_timeframe(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* cl, tpc_links* l,
+                          tpc_tracklets* t, tpc_tracks* tr) {
+  if (!c || check_input(c, in) || check_clusters(c, cl, true) || check_links(c, cl, l, true) ||
+      check_tracklets(c, t) || check_tracks(tr))
+    return TPC_ERR_ARG;
+  if (cl->n_units != in->n_units || cl->n_time_bins != in->n_time_bins) return TPC_ERR_ARG;
+  int rc = stage_cluster(c, in, cl);
+  if (!rc) rc = stage_grid(c, cl);
+  if (!rc) rc = stage_neighbours(c, cl, l);
+  if (!rc) rc = stage_tracklets(c, cl, l, t);
+  if (!rc) rc = stage_fit(c, cl, l, t, tr);
+  return rc;
+}
+
+int tpc_sync(tpc_ctx* c, tpc_counts* counts) {
+  if (!c) return TPC_ERR_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return TPC_ERR_HIP;
+  DevStatus ds;
+  if (hipMemcpy(&ds, c->d_st, sizeof ds, hipMemcpyDeviceToHost) != hipSuccess) return TPC_ERR_HIP;
+  if (counts) {
+    std::memset(counts, 0, sizeof *counts);
+    counts->status = ds.status;
+    counts->required = ds.required;
+    counts->n_clusters = ds.n_clusters;
+    counts->n_tracklets = ds.n_tracklets;
+    counts->n_tracks = ds.n_tracks;
+    counts->n_hits = ds.n_hits;
+    counts->n_fallback = ds.n_fallback;
+    counts->n_fallback_fail = ds.n_fallback_fail;
+    counts->n_not_pd = ds.n_not_pd;
+    counts->n_refit_fail = ds.n_refit_fail;
+  }
+  DevStatus zero;
+  std::memset(&zero, 0, sizeof zero);
+  if (hipMemcpy(c->d_st, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
+    return TPC_ERR_HIP;
+  return ds.status;
+}
+
+void* tpc_stream(tpc_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+int tpc_profile_enable(tpc_ctx* c, int on) {
+  if (!c) return TPC_ERR_ARG;
+  if (on && !c->prof_events) {
+    for (int i = 0; i < TPC_PROF_STAGES; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int k = 0; k < tpc_ctx::kProfCap; ++k)
+          if (hipEventCreate(&c->prof_ev[i][j][k]) != hipSuccess) return TPC_ERR_HIP;
+    c->prof_events = true;
+  }
+  c->prof_on = on != 0;
+  return TPC_OK;
+}
+
+int tpc_profile_read(tpc_ctx* c, double* ms, uint32_t* launches) {
+  if (!c || !ms || !launches) return TPC_ERR_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return TPC_ERR_HIP;
+  for (int i = 0; i < TPC_PROF_STAGES; ++i) {
+    double acc = 0;
+    for (uint32_t k = 0; k < c->prof_n[i]; ++k) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, c->prof_ev[i][0][k], c->prof_ev[i][1][k]) != hipSuccess)
+        return TPC_ERR_HIP;
+      acc += t;
+    }
+    ms[i] = acc;
+    launches[i] = c->prof_n[i];
+    c->prof_n[i] = 0;
+  }
+  return TPC_OK;
+}
+
+const char* tpc_profile_stage_name(int i) {
+  static const char* names[TPC_PROF_STAGES] = {
+      "sample_index", "cluster_count", "window_scan", "cluster_emit", "cluster_grid",
+      "neighbours", "tracklets", "following", "resolution", "refit_fp32", "refit_fp64",
+      "track_output"};
+  return (i >= 0 && i < TPC_PROF_STAGES) ? names[i] : "unknown";
+}
+
+const char* tpc_status_string(int s) {
+  switch (s) {
+    case TPC_OK: return "ok";
+    case TPC_ERR_ARG: return "invalid argument";
+    case TPC_ERR_CAPACITY: return "capacity exceeded";
+    case TPC_ERR_INPUT: return "malformed input";
+    case TPC_ERR_HIP: return "HIP runtime error";
+    case TPC_ERR_NUMERIC: return "numeric failure";
+    case TPC_ERR_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,396 @@
+"""Python binding of libtpcreco (include/tpc.h): argument marshalling only.
+
+Device memory comes from torch tensors on the GPU, the stream is torch's
+current stream; every step of the reconstruction runs in the library's HIP
+kernels.  There is no CPU fallback: if the library is missing, loading it
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+NROW = 152
+_here = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+P = ctypes.c_void_p
+U32 = ctypes.c_uint32
+I32 = ctypes.c_int32
+
+
+class TpcParams(ctypes.Structure):
+    _fields_ = [
+        ("qmax_min", I32), ("min_tracklet", I32), ("max_miss", I32), ("min_track_hits", I32),
+        ("win_y", ctypes.c_int64), ("win_z", ctypes.c_int64), ("s_max", ctypes.c_int64),
+        ("chi2_max", ctypes.c_double), ("snp_max", ctypes.c_double), ("bz_b", ctypes.c_double),
+        ("c0_snp", ctypes.c_double), ("c0_tgl", ctypes.c_double), ("c0_qpt", ctypes.c_double),
+        ("qpt_clamp", ctypes.c_double), ("edge_margin", ctypes.c_double),
+        ("lowpt_qpt", ctypes.c_double),
+        ("c0r_y", ctypes.c_double), ("c0r_z", ctypes.c_double), ("c0r_snp", ctypes.c_double),
+        ("c0r_tgl", ctypes.c_double), ("c0r_qpt", ctypes.c_double),
+        ("refit_snp_max", ctypes.c_double),
+        ("sigma_y", ctypes.c_double * NROW), ("sigma_z", ctypes.c_double * NROW),
+        ("validate", I32), ("force_fallback", I32),
+    ]
+
+
+class TpcSizes(ctypes.Structure):
+    _fields_ = [("max_units", U32), ("max_time_bins", U32), ("max_clusters", U32),
+                ("max_tracklets", U32)]
+
+
+class TpcZsInput(ctypes.Structure):
+    _fields_ = [("pad", P), ("time", P), ("adc", P), ("row_start", P), ("n_samples", U32),
+                ("n_units", U32), ("n_time_bins", U32)]
+
+
+class TpcClusters(ctypes.Structure):
+    _fields_ = [("capacity", U32), ("n_units", U32), ("n_time_bins", U32), ("n_clusters", P),
+                ("crow_start", P), ("y_fx", P), ("z_fx", P), ("dpad", P), ("dtime", P),
+                ("s2pad", P), ("s2time", P), ("qtot", P), ("qmax", P), ("ppad", P), ("ptime", P),
+                ("flags", P), ("sp", P), ("st", P), ("spp", P), ("stt", P), ("nsamp", P),
+                ("sample_label", P)]
+
+
+class TpcLinks(ctypes.Structure):
+    _fields_ = [("capacity", U32), ("down", P), ("up", P), ("downc", P), ("upc", P)]
+
+
+class TpcTracklets(ctypes.Structure):
+    _fields_ = [("capacity", U32), ("n_tracklets", P), ("start", P), ("len", P)]
+
+
+class TpcTracks(ctypes.Structure):
+    _fields_ = [("capacity", U32), ("hit_capacity", U32), ("n_tracks", P), ("n_hits", P),
+                ("tracklet", P), ("par", P), ("cov", P), ("chi2", P), ("ndf", P), ("row", P),
+                ("flags", P), ("z_anchor", P), ("hit_start", P), ("hits", P),
+                ("cluster_track", P), ("follow_hits", P)]
+
+
+class TpcCounts(ctypes.Structure):
+    _fields_ = [("status", I32), ("required", U32), ("n_samples", U32), ("n_clusters", U32),
+                ("n_tracklets", U32), ("n_tracks", U32), ("n_hits", U32), ("n_fallback", U32),
+                ("n_fallback_fail", U32), ("n_not_pd", U32), ("n_refit_fail", U32)]
+
+
+EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_create",
+           "tpc_destroy", "tpc_cluster", "tpc_find_neighbours", "tpc_build_tracklets",
+           "tpc_fit_tracks", "tpc_process_timeframe", "tpc_sync", "tpc_stream",
+           "tpc_status_string", "tpc_profile_enable", "tpc_profile_read",
+           "tpc_profile_stage_name"]
+PROF_STAGES = 12
+
+
+def library_path() -> str:
+    return os.path.join(_here, "libtpcreco.so")
+
+
+def load():
+    """Load libtpcreco.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not built: run __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    lib.tpc_params_default.argtypes = [P, ctypes.c_double]
+    lib.tpc_geometry.argtypes = [P, P, P]
+    lib.tpc_workspace_size.argtypes = [P, P]
+    lib.tpc_create.argtypes = [P, P, P, P]
+    lib.tpc_destroy.argtypes = [P]
+    lib.tpc_cluster.argtypes = [P, P, P]
+    lib.tpc_find_neighbours.argtypes = [P, P, P]
+    lib.tpc_build_tracklets.argtypes = [P, P, P, P]
+    lib.tpc_fit_tracks.argtypes = [P, P, P, P, P]
+    lib.tpc_process_timeframe.argtypes = [P, P, P, P, P, P]
+    lib.tpc_sync.argtypes = [P, P]
+    lib.tpc_stream.argtypes = [P]
+    lib.tpc_stream.restype = P
+    lib.tpc_status_string.argtypes = [ctypes.c_int]
+    lib.tpc_status_string.restype = ctypes.c_char_p
+    lib.tpc_profile_enable.argtypes = [P, ctypes.c_int]
+    lib.tpc_profile_read.argtypes = [P, P, P]
+    lib.tpc_profile_stage_name.argtypes = [ctypes.c_int]
+    lib.tpc_profile_stage_name.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class TpcError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = load().tpc_status_string(code).decode()
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+        self.code = code
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise TpcError(rc, what)
+
+
+def params(overrides: Optional[dict] = None, noise_sigma: float = 1.0) -> TpcParams:
+    """Library defaults, optionally overridden by a dict of field values."""
+    p = TpcParams()
+    _check(load().tpc_params_default(ctypes.byref(p), noise_sigma), "tpc_params_default")
+    for k, v in (overrides or {}).items():
+        if k in ("sigma_y", "sigma_z"):
+            arr = getattr(p, k)
+            for i in range(NROW):
+                arr[i] = float(v[i])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def geometry():
+    npads = np.zeros(NROW, np.int32)
+    xfx = np.zeros(NROW, np.int32)
+    pfx = np.zeros(NROW, np.int32)
+    load().tpc_geometry(npads.ctypes.data, xfx.ctypes.data, pfx.ctypes.data)
+    return npads, xfx, pfx
+
+
+def workspace_size(max_units: int, max_time_bins: int, max_clusters: int, max_tracklets: int) -> int:
+    s = TpcSizes(max_units, max_time_bins, max_clusters, max_tracklets)
+    out = ctypes.c_size_t(0)
+    _check(load().tpc_workspace_size(ctypes.byref(s), ctypes.byref(out)), "tpc_workspace_size")
+    return out.value
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def to_device_zs(pad, time, adc, row_start, n_units: int, n_time_bins: int, device="cuda") -> dict:
+    """Copy a host ZS input (numpy) to device tensors (unsigned as signed views)."""
+    torch = _torch()
+    t = lambda a, dt, vt: torch.from_numpy(np.ascontiguousarray(a, dt).view(vt)).to(device)
+    return dict(pad=t(pad, np.uint16, np.int16), time=t(time, np.uint16, np.int16),
+                adc=t(adc, np.uint16, np.int16), row_start=t(row_start, np.uint32, np.int32),
+                n_samples=int(len(pad)), n_units=int(n_units), n_time_bins=int(n_time_bins))
+
+
+def zs_struct(zs: dict) -> TpcZsInput:
+    return TpcZsInput(_dptr(zs["pad"]), _dptr(zs["time"]), _dptr(zs["adc"]), _dptr(zs["row_start"]),
+                      zs["n_samples"], zs["n_units"], zs["n_time_bins"])
+
+
+class Buffers:
+    """Device tensors of one stage's outputs plus the matching C struct."""
+
+    def __init__(self, tensors: Dict[str, object], struct):
+        self.t = tensors
+        self.s = struct
+
+    def __getitem__(self, k):
+        return self.t[k]
+
+
+class Reco:
+    """One library context bound to a torch stream on one GPU."""
+
+    def __init__(self, max_units: int, max_time_bins: int, max_clusters: int,
+                 max_tracklets: int, param_overrides: Optional[dict] = None,
+                 noise_sigma: float = 1.0, device: str = "cuda", stream=None):
+        torch = _torch()
+        self.lib = load()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params = params(param_overrides, noise_sigma)
+        self.sizes = TpcSizes(max_units, max_time_bins, max_clusters, max_tracklets)
+        self.ctx = P()
+        with torch.cuda.device(self.device):
+            _check(self.lib.tpc_create(ctypes.byref(self.ctx), ctypes.byref(self.params),
+                                       ctypes.byref(self.sizes), self.stream.cuda_stream),
+                   "tpc_create")
+
+    def close(self):
+        if self.ctx:
+            self.lib.tpc_destroy(self.ctx)
+            self.ctx = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ buffers
+    def alloc_clusters(self, n_units: int, n_time_bins: int, capacity: int, n_samples: int = 0,
+                       moments: bool = False, labels: bool = False) -> Buffers:
+        torch = _torch()
+        d = self.device
+        e = lambda n, dt: torch.empty(max(n, 1), dtype=dt, device=d)
+        cap = int(capacity)
+        t = dict(n_clusters=torch.zeros(1, dtype=torch.int32, device=d),
+                 crow_start=e(n_units * NROW + 1, torch.int32),
+                 y_fx=e(cap, torch.int32), z_fx=e(cap, torch.int32),
+                 dpad=e(cap, torch.float32), dtime=e(cap, torch.float32),
+                 s2pad=e(cap, torch.float32), s2time=e(cap, torch.float32),
+                 qtot=e(cap, torch.int16), qmax=e(cap, torch.int16),
+                 ppad=e(cap, torch.int16), ptime=e(cap, torch.int16), flags=e(cap, torch.uint8))
+        if moments:
+            for k in ("sp", "st", "spp", "stt"):
+                t[k] = e(cap, torch.int32)
+            t["nsamp"] = e(cap, torch.int16)
+        if labels:
+            t["sample_label"] = e(n_samples, torch.int32)
+        s = TpcClusters(cap, n_units, n_time_bins, *[_dptr(t.get(k)) for k in (
+            "n_clusters", "crow_start", "y_fx", "z_fx", "dpad", "dtime", "s2pad", "s2time", "qtot",
+            "qmax", "ppad", "ptime", "flags", "sp", "st", "spp", "stt", "nsamp", "sample_label")])
+        return Buffers(t, s)
+
+    def clusters_from_host(self, cl: dict, n_units: int, n_time_bins: int) -> Buffers:
+        """Device copy of a host cluster set (positions, peaks, row table)."""
+        torch = _torch()
+        n = len(cl["y_fx"])
+        b = self.alloc_clusters(n_units, n_time_bins, max(n, 1))
+        dev = lambda a, dt, vt: torch.from_numpy(np.ascontiguousarray(a, dt).view(vt)).to(self.device)
+        b.t["n_clusters"].copy_(torch.tensor([n], dtype=torch.int32))
+        b.t["crow_start"].copy_(dev(cl["crow_start"], np.uint32, np.int32))
+        if n:
+            b.t["y_fx"][:n].copy_(dev(cl["y_fx"], np.int32, np.int32))
+            b.t["z_fx"][:n].copy_(dev(cl["z_fx"], np.int32, np.int32))
+            b.t["ptime"][:n].copy_(dev(cl["ptime"], np.uint16, np.int16))
+            b.t["ppad"][:n].copy_(dev(cl["ppad"], np.uint16, np.int16))
+        return b
+
+    def alloc_links(self, capacity: int) -> Buffers:
+        torch = _torch()
+        cap = max(int(capacity), 1)
+        t = {k: torch.empty(cap, dtype=torch.int32, device=self.device)
+             for k in ("down", "up", "downc", "upc")}
+        return Buffers(t, TpcLinks(cap, *[_dptr(t[k]) for k in ("down", "up", "downc", "upc")]))
+
+    def alloc_tracklets(self, capacity: int) -> Buffers:
+        torch = _torch()
+        cap = max(int(capacity), 1)
+        t = dict(n_tracklets=torch.zeros(1, dtype=torch.int32, device=self.device),
+                 start=torch.empty(cap, dtype=torch.int32, device=self.device),
+                 len=torch.empty(cap, dtype=torch.int16, device=self.device))
+        return Buffers(t, TpcTracklets(cap, _dptr(t["n_tracklets"]), _dptr(t["start"]),
+                                       _dptr(t["len"])))
+
+    def alloc_tracks(self, capacity: int, hit_capacity: int, cluster_capacity: int,
+                     follow_capacity: int = 0) -> Buffers:
+        torch = _torch()
+        d = self.device
+        cap = max(int(capacity), 1)
+        e = lambda n, dt: torch.empty(max(int(n), 1), dtype=dt, device=d)
+        t = dict(n_tracks=torch.zeros(1, dtype=torch.int32, device=d),
+                 n_hits=torch.zeros(1, dtype=torch.int32, device=d),
+                 tracklet=e(cap, torch.int32), par=e(cap * 5, torch.float32),
+                 cov=e(cap * 15, torch.float32), chi2=e(cap, torch.float32),
+                 ndf=e(cap, torch.int16), row=e(cap, torch.uint8), flags=e(cap, torch.uint8),
+                 z_anchor=e(cap, torch.int32), hit_start=e(cap + 1, torch.int32),
+                 hits=e(hit_capacity, torch.int32), cluster_track=e(cluster_capacity, torch.int32))
+        if follow_capacity:
+            t["follow_hits"] = e(follow_capacity * NROW, torch.int32)
+        s = TpcTracks(cap, max(int(hit_capacity), 1), *[_dptr(t.get(k)) for k in (
+            "n_tracks", "n_hits", "tracklet", "par", "cov", "chi2", "ndf", "row", "flags",
+            "z_anchor", "hit_start", "hits", "cluster_track", "follow_hits")])
+        return Buffers(t, s)
+
+    # ------------------------------------------------------------ calls
+    def cluster(self, zs: dict, out: Buffers):
+        _check(self.lib.tpc_cluster(self.ctx, ctypes.byref(zs_struct(zs)), ctypes.byref(out.s)),
+               "tpc_cluster")
+
+    def find_neighbours(self, cl: Buffers, links: Buffers):
+        _check(self.lib.tpc_find_neighbours(self.ctx, ctypes.byref(cl.s), ctypes.byref(links.s)),
+               "tpc_find_neighbours")
+
+    def build_tracklets(self, cl: Buffers, links: Buffers, tl: Buffers):
+        _check(self.lib.tpc_build_tracklets(self.ctx, ctypes.byref(cl.s), ctypes.byref(links.s),
+                                            ctypes.byref(tl.s)), "tpc_build_tracklets")
+
+    def fit_tracks(self, cl: Buffers, links: Buffers, tl: Buffers, tr: Buffers):
+        _check(self.lib.tpc_fit_tracks(self.ctx, ctypes.byref(cl.s), ctypes.byref(links.s),
+                                       ctypes.byref(tl.s), ctypes.byref(tr.s)), "tpc_fit_tracks")
+
+    def process(self, zs: dict, cl: Buffers, links: Buffers, tl: Buffers, tr: Buffers,
+                zs_s: Optional[TpcZsInput] = None):
+        s = zs_s if zs_s is not None else zs_struct(zs)
+        _check(self.lib.tpc_process_timeframe(self.ctx, ctypes.byref(s), ctypes.byref(cl.s),
+                                              ctypes.byref(links.s), ctypes.byref(tl.s),
+                                              ctypes.byref(tr.s)), "tpc_process_timeframe")
+
+    def profile(self, on: bool = True):
+        _check(self.lib.tpc_profile_enable(self.ctx, 1 if on else 0), "tpc_profile_enable")
+
+    def profile_read(self) -> dict:
+        """Summed milliseconds and launch counts per stage since the last read."""
+        ms = np.zeros(PROF_STAGES, np.float64)
+        n = np.zeros(PROF_STAGES, np.uint32)
+        _check(self.lib.tpc_profile_read(self.ctx, ms.ctypes.data, n.ctypes.data),
+               "tpc_profile_read")
+        return {self.lib.tpc_profile_stage_name(i).decode(): (float(ms[i]), int(n[i]))
+                for i in range(PROF_STAGES)}
+
+    def sync(self, raise_on_error: bool = True) -> dict:
+        c = TpcCounts()
+        rc = self.lib.tpc_sync(self.ctx, ctypes.byref(c))
+        out = {k: getattr(c, k) for k, _ in TpcCounts._fields_}
+        if raise_on_error and rc != 0:
+            raise TpcError(rc, f"tpc_sync (required {c.required})")
+        return out
+
+
+# ---------------------------------------------------------------- host views
+def _u(t, n, dt):
+    a = t[:n].cpu().numpy()
+    return a.view(dt) if a.dtype.itemsize == np.dtype(dt).itemsize else a.astype(dt)
+
+
+def clusters_to_host(b: Buffers, n_units: int) -> dict:
+    n = int(b["n_clusters"].item())
+    out = dict(crow_start=b["crow_start"][: n_units * NROW + 1].cpu().numpy().view(np.uint32),
+               n_units=n_units)
+    for k, dt in (("y_fx", np.int32), ("z_fx", np.int32), ("dpad", np.float32),
+                  ("dtime", np.float32), ("s2pad", np.float32), ("s2time", np.float32),
+                  ("qtot", np.uint16), ("qmax", np.uint16), ("ppad", np.uint16),
+                  ("ptime", np.uint16), ("flags", np.uint8), ("sp", np.int32), ("st", np.int32),
+                  ("spp", np.int32), ("stt", np.int32), ("nsamp", np.uint16)):
+        if k in b.t:
+            out[k] = _u(b[k], n, dt)
+    if "sample_label" in b.t:
+        out["sample_label"] = b["sample_label"].cpu().numpy()
+    return out
+
+
+def links_to_host(b: Buffers, n: int) -> dict:
+    return {k: b[k][:n].cpu().numpy() for k in ("down", "up", "downc", "upc")}
+
+
+def tracklets_to_host(b: Buffers) -> dict:
+    n = int(b["n_tracklets"].item())
+    return dict(tl_start=_u(b["start"], n, np.uint32), tl_len=_u(b["len"], n, np.uint16))
+
+
+def tracks_to_host(b: Buffers, n_clusters: int, n_tracklets: int = 0) -> dict:
+    n = int(b["n_tracks"].item())
+    nh = int(b["n_hits"].item())
+    out = dict(tracklet=_u(b["tracklet"], n, np.uint32),
+               par=b["par"][: n * 5].cpu().numpy().reshape(n, 5),
+               cov=b["cov"][: n * 15].cpu().numpy().reshape(n, 15),
+               chi2=b["chi2"][:n].cpu().numpy(), ndf=_u(b["ndf"], n, np.uint16),
+               row=b["row"][:n].cpu().numpy(), flags=b["flags"][:n].cpu().numpy(),
+               z_anchor=b["z_anchor"][:n].cpu().numpy(),
+               hit_start=_u(b["hit_start"], n + 1, np.uint32), hits=_u(b["hits"], nh, np.uint32),
+               cluster_track=b["cluster_track"][:n_clusters].cpu().numpy())
+    if "follow_hits" in b.t and n_tracklets:
+        out["follow_hits"] = b["follow_hits"][: n_tracklets * NROW].cpu().numpy().reshape(
+            n_tracklets, NROW)
+    return out
