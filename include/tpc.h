@@ -76,6 +76,9 @@ typedef struct {
   double c0r_y, c0r_z;    /* refit prior sigmas of y, z (5 cm: broad) */
   double c0r_snp, c0r_tgl, c0r_qpt; /* refit prior sigmas (0.5, 0.5, 10) */
   double refit_snp_max;   /* |sin phi| a refit step may not reach (0.999) */
+  double fp32_guard;      /* an FP32 refit update that leaves less than this
+                             fraction of a variance sends the track to the
+                             FP64 refit (0.1; 0 disables) */
   double sigma_y[TPC_NROW], sigma_z[TPC_NROW]; /* measurement errors [cm] */
   int32_t validate;       /* 1: check input order and ranges on the device */
   int32_t force_fallback; /* 1: redo every refit in FP64 (test hook) */
@@ -161,7 +164,7 @@ typedef struct {
   int32_t status;             /* first latched error (tpc_status) */
   uint32_t required;          /* capacity that an overflow needed */
   uint32_t n_samples, n_clusters, n_tracklets, n_tracks, n_hits;
-  uint32_t n_fallback;        /* refits redone in FP64 */
+  uint32_t n_fallback;        /* refits redone in FP64 (PD check or cancellation guard) */
   uint32_t n_fallback_fail;   /* FP64 refits still not PD (dropped) */
   uint32_t n_not_pd;          /* high-pT tracks flagged not PD */
   uint32_t n_refit_fail;      /* tracks dropped by a failed refit step */

@@ -26,6 +26,7 @@ struct DevParams {
   double chi2_max_d, snp_max_d, bz_b_d, c0_snp2_d, c0_tgl2_d, c0_qpt2_d, qpt_clamp_d,
       edge_margin_d;
   float c0r2[5], refit_snp_max;  // refit prior variances (y, z, snp, tgl, q/pT)
+  float fp32_guard;
   double c0r2_d[5], refit_snp_max_d;
   int32_t validate, force_fallback;
 };

@@ -531,7 +531,8 @@ __device__ __forceinline__ int32_t tl_anchor(const ClusterView& cl, const uint32
 template <typename T>
 __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, const FollowOut& fo,
                          const unsigned long long* owner, const DevParams* P, Trk<T>& k,
-                         T& chi2s, int& r_state, int& r, int max_hits, bool& pd) {
+                         T& chi2s, int& r_state, int& r, int max_hits, bool& pd,
+                         bool* guard = nullptr) {
   const PV<T> pv{P};
   const unsigned long long key = track_key(fo.nhits[t], t);
   const int lo = fo.range[t] & 255;
@@ -545,7 +546,17 @@ __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, cons
     const T my = (T)cl.y_fx[c] * (T)FX_SCALE;
     const T mz = (T)(cl.z_fx[c] - anchor) * (T)FX_SCALE;
     T x2;
+    T d0[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) d0[i] = k.c[PI(i, i)];
     if (!update_joseph(k, my, mz, pv.vy(r), pv.vz(r), &x2)) return 1;
+    // cancellation guard: an update that removes more than (1 - fp32_guard)
+    // of a variance in one step loses FP32 precision in the covariance
+    if (guard) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+        if (k.c[PI(i, i)] < (T)P->fp32_guard * d0[i]) *guard = true;
+    }
     chi2s += x2;
     if (!is_pd(k.c)) pd = false;
     r_state = r;
@@ -682,8 +693,9 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
     float chi2s = (float)hd.chi2[t];
     int rprev = hd.rprev[t], r = hd.r[t];
     bool pd = (hd.flags[t] & 2) == 0;
+    bool guard = false;
     const int rc = refit_run<float>(t, cl, tl_anchor(cl, tl_start, t), fo, owner, P, k, chi2s,
-                                    rprev, r, NROW, pd);
+                                    rprev, r, NROW, pd, &guard);
     if (rc) {
       ro.flags[t] = TF_REFIT_FAIL;
       atomicAdd(&st->n_refit_fail, 1u);
@@ -696,7 +708,7 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
     ro.chi2[t] = chi2s;
     ro.row[t] = (uint8_t)rprev;
     const bool lowpt = (hd.flags[t] & 4) != 0;
-    if (P->force_fallback || (!pd && lowpt)) {
+    if (P->force_fallback || guard || (!pd && lowpt)) {
       const uint32_t i = atomicAdd(&st->n_fb_list, 1u);
       if (i < tl_cap) fb_list[i] = t;
     } else if (!pd) {

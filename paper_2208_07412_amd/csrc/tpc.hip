@@ -202,6 +202,7 @@ DevParams make_dev_params(const tpc_params& p) {
   }
   d.refit_snp_max_d = p.refit_snp_max;
   d.refit_snp_max = (float)p.refit_snp_max;
+  d.fp32_guard = (float)p.fp32_guard;
   d.validate = p.validate;
   d.force_fallback = p.force_fallback;
   return d;
@@ -486,6 +487,7 @@ int tpc_params_default(tpc_params* p, double noise_sigma) {
   p->c0r_tgl = 0.5;
   p->c0r_qpt = 10.0;
   p->refit_snp_max = 0.999;
+  p->fp32_guard = 0.1;
   for (int r = 0; r < NROW; ++r) {
     p->sigma_y[r] = 0.06;
     p->sigma_z[r] = 0.05;

@@ -32,7 +32,7 @@ class TpcParams(ctypes.Structure):
         ("lowpt_qpt", ctypes.c_double),
         ("c0r_y", ctypes.c_double), ("c0r_z", ctypes.c_double), ("c0r_snp", ctypes.c_double),
         ("c0r_tgl", ctypes.c_double), ("c0r_qpt", ctypes.c_double),
-        ("refit_snp_max", ctypes.c_double),
+        ("refit_snp_max", ctypes.c_double), ("fp32_guard", ctypes.c_double),
         ("sigma_y", ctypes.c_double * NROW), ("sigma_z", ctypes.c_double * NROW),
         ("validate", I32), ("force_fallback", I32),
     ]

@@ -41,6 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_defaults_agree_with_oracle_readings():
     p = tpc.params()
     d = oracle.default_params()
+    assert p.fp32_guard == 0.1
     for k, v in d.items():
         if k in ("sigma_y", "sigma_z"):
             assert list(getattr(p, k)) == v
@@ -95,6 +96,6 @@ def test_status_strings():
 def test_struct_layouts_match_header():
     # field counts of the binding against the header's struct members
     src = open(os.path.join(ROOT, "include", "tpc.h")).read()
-    assert ctypes.sizeof(tpc.TpcParams) == 4 * 4 + 3 * 8 + 15 * 8 + 2 * 152 * 8 + 2 * 4
+    assert ctypes.sizeof(tpc.TpcParams) == 4 * 4 + 3 * 8 + 16 * 8 + 2 * 152 * 8 + 2 * 4
     assert ctypes.sizeof(tpc.TpcCounts) == 11 * 4
     assert "uint32_t capacity;" in src
