@@ -18,12 +18,16 @@
 #include "k_track.hpp"
 
 #ifndef TPC_CL_WINDOW
-#define TPC_CL_WINDOW 48
+#define TPC_CL_WINDOW 32
+#endif
+#ifndef TPC_CL_CHUNK
+#define TPC_CL_CHUNK 8
 #endif
 
 namespace {
 
 constexpr uint32_t kWin = TPC_CL_WINDOW;
+constexpr uint32_t kChunk = TPC_CL_CHUNK;
 
 struct Geometry {
   int32_t np[NROW], xfx[NROW], pfx[NROW];
@@ -344,10 +348,12 @@ int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
                 out->spp, out->stt, out->nsamp, out->sample_label};
   const ZsArgs za = zs_args(in);
   const uint32_t nwt = n_ur * nwin;
+  const uint32_t nchunk = ceil_div(nwin, kChunk);
+  const uint32_t ngrid = n_ur * nchunk;
   {
     StageTimer tm(c, 1);
-    k_cluster<kWin, false><<<nwt, 256, 0, s>>>(za, c->zblk, nblk, nwin, n_ur, c->win, nullptr, co,
-                                               c->d_par, c->d_st);
+    k_cluster_count<kWin, kChunk><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk, nwin, nchunk, n_ur,
+                                                        c->win, c->d_par, c->d_st);
   }
   {
     StageTimer tm(c, 2);
@@ -358,8 +364,8 @@ int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
   }
   {
     StageTimer tm(c, 3);
-    k_cluster<kWin, true><<<nwt, 256, 0, s>>>(za, c->zblk, nblk, nwin, n_ur, nullptr, c->win, co,
-                                              c->d_par, c->d_st);
+    k_cluster_emit<kWin, kChunk><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk, nwin, nchunk, n_ur,
+                                                       c->win, co, c->d_par, c->d_st);
   }
   if (out->sample_label)
     k_sample_label<<<n_ur, 256, 0, s>>>(za, out->crow_start, out->ppad, out->ptime, n_ur,
