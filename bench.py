@@ -7,9 +7,13 @@ seed 303, reconstructed in one graph-captured launch sequence (the batched
 form).  Inputs are resident in HBM before the timed region starts.
 
 Beside it: the plain form (one central collision per synchronous call, seed
-202) with its per-call latency, per-stage timing of the library's kernels
-(HIP events on the library's stream) for the roofline, and the CPU oracle
-timed on a bounded sample of the same workload.
+202, default launch shapes, no graph) with its per-call latency; the serving
+form (a Poisson stream of chunks of 10-200 collisions, seed 404, at 80% of
+the measured capacity, admitted continuously over several streams) with its
+p50/p99 chunk latency; per-stage timing of the library's kernels (HIP events
+on the library's stream) for the roofline; and the CPU oracle timed on a
+bounded sample of the same workload.  Launch shapes of the batched and
+serving forms are picked by the autotuner on the workload itself.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is not supported: the path
 runs on one GPU.
@@ -37,15 +41,37 @@ def log(*a):
 # Algorithmic bytes each stage must move, per unit of work:
 # samples are (pad, time, adc) u16; a cluster record is y_fx, z_fx (i32),
 # pad, time, s2pad, s2time (f32), qtot, qmax, ppad, ptime (u16), flags (u8).
-def stage_bytes(ns, nc, n_ur, nblk):
+def stage_bytes(ns, nc, n_ur, T):
     rec = 4 * 2 + 4 * 4 + 2 * 4 + 1
+    nblk_s = (T + 3) // 4   # sample index: one entry per 4 time bins
+    nblk_c = (T + 7) // 8   # cluster grid: one entry per 8 time bins
     return {
-        "sample_index": 2 * ns + 4 * n_ur * (nblk + 1),
+        "sample_index": 2 * ns + 4 * n_ur * (nblk_s + 1),
         "cluster_count": 6 * ns,
         "cluster_emit": 6 * ns + rec * nc,
-        "cluster_grid": 2 * nc + 4 * n_ur * (nblk + 1),
+        "cluster_grid": 2 * nc + 4 * n_ur * (nblk_c + 1),
         "neighbours": 8 * nc + 8 * nc,
     }
+
+
+def pmc_traffic(kernel_file, stage):
+    """HBM bytes per launch of a stage's kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known
+    size), or None when the kernel source changed since the counters were
+    taken or no summary exists."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"pmc_{stage}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic_json: "):
+            rec = json.loads(line[len("traffic_json: "):])
+    if rec is None:
+        return None
+    h = hashlib.sha256(open(os.path.join(ROOT, kernel_file), "rb").read()).hexdigest()
+    return rec["bytes_per_launch"] if rec.get("source_sha256") == h else None
 
 
 def make_reco(tpc, ev, stream, max_clusters, max_tracklets, noise):
@@ -84,6 +110,94 @@ def cpu_baseline(ev, target_s=12.0):
                        f"{total_c} clusters in {total_t:.1f} s")
 
 
+def serve_leg(args, torch, tpcsynth, tuning):
+    """Poisson stream of chunks (10-200 collisions each) admitted continuously
+    on several streams; capacity first (every pool chunk arrives at once),
+    then arrivals at 80% of it."""
+    from paper_2208_07412_amd import serve
+
+    t = time.perf_counter()
+    pool = []
+    for i in range(args.serve_pool):
+        ev = tpcsynth.generate(tpcsynth.config_chunk(404, i), 404 + i)
+        pool.append(serve.make_job(i, ev))
+        del ev
+    T = max(j.n_time_bins for j in pool)
+    max_cl = max(j.cl_cap for j in pool)
+    max_tl = max(j.tl_cap for j in pool)
+    log(f"[bench] serving pool: {[j.n_time_bins // 100 - 5 for j in pool]} collisions, "
+        f"{sum(j.n_samples for j in pool)} samples, made in {time.perf_counter() - t:.1f}s")
+    ex = serve.GpuExecutor(args.serve_slots, 36, T, max_cl, max_tl, tuning=tuning)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.8)
+
+    def copies(idx):
+        return [serve.Job(k, pool[i].zs, pool[i].n_units, pool[i].n_time_bins, pool[i].n_samples,
+                          cl_cap=pool[i].cl_cap, tl_cap=pool[i].tl_cap) for k, i in enumerate(idx)]
+
+    def run(jobs, arrivals):
+        sched = serve.Scheduler(ex, args.serve_slots, budget)
+        t0 = time.perf_counter()
+        done = serve.run_stream(sched, jobs, arrivals)
+        span = time.perf_counter() - t0
+        bad = [j.error for j in done if j.error]
+        if bad:
+            raise RuntimeError(f"serving errors: {bad[:3]}")
+        return done, span, sched
+
+    idx = list(range(len(pool)))
+    run(copies(idx), np.zeros(len(idx)))  # warm-up: allocator, first launches
+    done, span, _ = run(copies(idx + idx), np.zeros(2 * len(idx)))
+    cap_chunks = len(done) / span
+    cap_clusters = sum(j.counts["n_clusters"] for j in done) / span
+    rate = 0.8 * cap_chunks
+    n = args.serve_chunks
+    rng = np.random.default_rng(404)
+    sel = [int(x) for x in rng.integers(0, len(pool), n)]
+    arr = serve.poisson_arrivals(n, rate, seed=405)
+    done, span, sched = run(copies(sel), arr)
+    ncl = sum(j.counts["n_clusters"] for j in done)
+    st = serve.latency_stats(done)
+    ex.close()
+    return dict(workload="Poisson stream of time-frame chunks, 10-200 minimum-bias collisions "
+                         "each (100 n + 500 bins), seed 404", pool=len(pool), chunks=n,
+                slots=args.serve_slots, capacity_chunks_per_s=cap_chunks,
+                capacity_clusters_per_s=cap_clusters, rate_hz=rate, clusters_per_s=ncl / span,
+                p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], mean_ms=st["mean_ms"],
+                max_concurrent=sched.max_concurrent,
+                reruns=sum(j.retries for j in done))
+
+
+def stress_leg(torch, tpcsynth, tpc, stream, n_coll=20):
+    """Precision-stress chunk (30% loopers at 0.05-0.2 GeV/c, noise 2 ADC,
+    10% dead pads): how often the FP32 refit hands a track to the FP64 one,
+    and the time of the two refit stages."""
+    ev = tpcsynth.generate(tpcsynth.config_chunk(505, 0, stress=True, n_coll=n_coll), 505)
+    mc = max(ev.n_samples // 6, 1 << 16)
+    mt = max(mc // 8, 1 << 14)
+    reco = tpc.Reco(ev.n_units, ev.n_time_bins, mc, mt, noise_sigma=2.0, stream=stream)
+    zs = tpc.to_device_zs(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins)
+    b = buffers(reco, ev, mc, mt)
+    with torch.cuda.stream(stream):
+        reco.process(zs, *b)
+    c = reco.sync()
+    reco.profile(True)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            reco.process(zs, *b)
+    prof = reco.profile_read()
+    reco.profile(False)
+    reco.sync()
+    reco.close()
+    ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+    return dict(workload=f"precision-stress chunk, {n_coll} collisions, seed 505",
+                samples=ev.n_samples, clusters=c["n_clusters"], tracks=c["n_tracks"],
+                fp64_refits=c["n_fallback"], fp64_rate=c["n_fallback"] / max(c["n_tracks"], 1),
+                fp64_not_pd=c["n_fallback_fail"], flagged_not_pd=c["n_not_pd"],
+                refit_fp32_ms=ms["refit_fp32"], refit_fp64_ms=ms["refit_fp64"],
+                total_ms=sum(ms.values()))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,7 +206,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form leg")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-form leg")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-stress", action="store_true", help="skip the precision-stress leg")
     ap.add_argument("--collisions", type=int, default=100)
+    ap.add_argument("--serve-pool", type=int, default=6, help="distinct chunks resident in HBM")
+    ap.add_argument("--serve-chunks", type=int, default=36, help="chunks in the Poisson stream")
+    ap.add_argument("--serve-slots", type=int, default=3, help="concurrent chunks (streams)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} not supported; the reconstruction path runs on one "
@@ -106,6 +228,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calib_copy:
+        # known traffic: 2^30 bytes read and 2^30 bytes written per launch
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(calib_copy_bytes=1 << 30, launches=5)), flush=True)
+        return
     t0 = time.perf_counter()
     cfg = tpcsynth.config_c3(303, args.collisions)
     ev = tpcsynth.generate(cfg, 303)
@@ -129,6 +260,18 @@ def main():
     nc = counts["n_clusters"]
     log(f"[bench] clusters {nc} tracklets {counts['n_tracklets']} tracks {counts['n_tracks']} "
         f"fallback {counts['n_fallback']}")
+
+    tuning = None
+    if not args.no_tune:
+        from paper_2208_07412_amd.autotune import autotune
+
+        def run_once():
+            with torch.cuda.stream(stream):
+                reco.process(zs, cl, links, tl, tr, zs_s)
+
+        t = time.perf_counter()
+        tuning = autotune(reco, run_once)
+        log(f"[bench] autotune in {time.perf_counter() - t:.1f}s: {tuning}")
 
     # per-stage timing (eager launches, events on the library's stream)
     reco.profile(True)
@@ -174,13 +317,14 @@ def main():
 
     # roofline of the dominant HBM-bound stage
     n_ur = ev.n_units * 152
-    nblk = (ev.n_time_bins + 7) // 8
-    sb = stage_bytes(ns, nc, n_ur, nblk)
+    sb = stage_bytes(ns, nc, n_ur, ev.n_time_bins)
     dom = max(stages, key=lambda k: stages[k])
     hbm_dom = max(sb, key=lambda k: stages.get(k, 0.0))
     ach = sb[hbm_dom] / (stages[hbm_dom] / 1e3) / 1e9
+    traffic = pmc_traffic("paper_2208_07412_amd/csrc/k_cluster.hpp", hbm_dom) \
+        if hbm_dom.startswith("cluster_") else None
     roofline = dict(bound="hbm", kernel=hbm_dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=None, bytes_per_launch=sb[hbm_dom],
+                    frac=ach / HBM_PEAK_GBS, traffic=traffic, bytes_per_launch=sb[hbm_dom],
                     ms_per_launch=stages[hbm_dom], dominant_stage=dom,
                     dominant_stage_ms=stages[dom])
 
@@ -192,6 +336,8 @@ def main():
                            form="batched (graph replay)" if graph is not None else "eager",
                            samples=ns, clusters=nc, tracks=counts["n_tracks"]),
                roofline=roofline, stages_ms=stages)
+    if tuning is not None:
+        out["tuning"] = tuning["chosen"]
     del graph
 
     # plain form: one central collision per synchronous call
@@ -221,6 +367,16 @@ def main():
         reco2.close()
         log(f"[bench] plain: {out['plain']}")
     reco.close()
+    del cl, links, tl, tr, zs
+    torch.cuda.empty_cache()
+
+    if not args.no_serve:
+        out["serving"] = serve_leg(args, torch, tpcsynth, tuning["chosen"] if tuning else None)
+        log(f"[bench] serving: {out['serving']}")
+
+    if not args.no_stress:
+        out["precision_stress"] = stress_leg(torch, tpcsynth, tpc, stream)
+        log(f"[bench] precision stress: {out['precision_stress']}")
 
     if not args.no_cpu:
         t = time.perf_counter()

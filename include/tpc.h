@@ -227,7 +227,7 @@ void* tpc_stream(tpc_ctx* ctx);
  * for the stream, writes the summed milliseconds and the number of timed
  * launches per stage, and clears them.  Leave it off while a launch sequence
  * is captured into a HIP graph.  Stages: 0 sample index, 1 cluster count,
- * 2 window scan, 3 cluster emit, 4 cluster grid, 5 neighbours, 6 tracklets,
+ * 2 cluster scan, 3 cluster emit, 4 cluster grid, 5 neighbours, 6 tracklets,
  * 7 following, 8 resolution, 9 refit FP32, 10 refit FP64, 11 track output. */
 #define TPC_PROF_STAGES 12
 int tpc_profile_enable(tpc_ctx* ctx, int on);
@@ -235,6 +235,22 @@ int tpc_profile_read(tpc_ctx* ctx, double* ms, uint32_t* launches);
 const char* tpc_profile_stage_name(int stage);
 
 const char* tpc_status_string(int status);
+
+/* Launch shapes (performance only: every choice gives the same results).
+ * cl_window: clusterizer window in time bins, 16 or 32; cl_chunk: windows
+ * walked by one workgroup, 4, 8 or 16; follow_block: threads per workgroup
+ * of the following kernel, 64, 128 or 256.  tpc_set_tuning rejects other
+ * values with TPC_ERR_ARG and leaves the context unchanged; it takes effect
+ * at the next call (a captured graph keeps the shapes it was captured with). */
+typedef struct {
+  int32_t cl_window;
+  int32_t cl_chunk;
+  int32_t follow_block;
+  int32_t reserved;
+} tpc_tuning;
+int tpc_tuning_default(tpc_tuning* t);
+int tpc_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);
+int tpc_get_tuning(tpc_ctx* ctx, tpc_tuning* t);
 
 #ifdef __cplusplus
 }

@@ -114,7 +114,8 @@ def _p(a: Optional[np.ndarray]):
 
 def make_params(params: Optional[dict] = None, brute_force: bool = False,
                 n_threads: int = 1) -> OParams:
-    d = default_params() if params is None else params
+    d = default_params()
+    d.update(params or {})  # a partial dict overrides the defaults
     op = OParams()
     for k, v in d.items():
         if k in ("sigma_y", "sigma_z"):

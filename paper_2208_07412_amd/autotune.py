@@ -1,0 +1,58 @@
+"""Launch-shape autotuner.
+
+Every launch shape the library offers (clusterizer window and windows per
+workgroup; workgroup size of the following kernel) gives identical results, so
+the choice is made by timing alone: each candidate runs the full launch
+sequence on the caller's resident workload, the library's stage timers (HIP
+events on its stream) give the time of the stages the shape affects, and the
+fastest candidate of each group is kept on the context.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Tuple
+
+CLUSTER_SHAPES: List[Tuple[int, int]] = [(16, 4), (16, 8), (16, 16), (32, 4), (32, 8), (32, 16)]
+FOLLOW_BLOCKS: List[int] = [64, 128, 256]
+CLUSTER_STAGES = ("sample_index", "cluster_count", "cluster_scan", "cluster_emit")
+FOLLOW_STAGES = ("following",)
+
+
+def _stage_ms(prof: Dict[str, tuple], names) -> float:
+    tot = 0.0
+    for n in names:
+        ms, k = prof[n]
+        tot += ms / max(k, 1)
+    return tot
+
+
+def _time(reco, run, names, reps: int) -> float:
+    run()  # untimed: first use of a shape
+    reco.sync()
+    reco.profile(True)
+    for _ in range(reps):
+        run()
+    prof = reco.profile_read()
+    reco.profile(False)
+    reco.sync()
+    return _stage_ms(prof, names)
+
+
+def autotune(reco, run, reps: int = 3) -> dict:
+    """run() enqueues one full reconstruction on reco's stream.  Leaves the
+    fastest shapes set on reco and returns them with every timing (ms)."""
+    start = reco.tuning()
+    res = {"cluster": {}, "follow": {}}
+    for w, k in CLUSTER_SHAPES:
+        reco.set_tuning(cl_window=w, cl_chunk=k)
+        res["cluster"][f"{w}x{k}"] = _time(reco, run, CLUSTER_STAGES, reps)
+    best_c = min(res["cluster"], key=res["cluster"].get)
+    w, k = (int(x) for x in best_c.split("x"))
+    reco.set_tuning(cl_window=w, cl_chunk=k)
+    for fb in FOLLOW_BLOCKS:
+        reco.set_tuning(follow_block=fb)
+        res["follow"][str(fb)] = _time(reco, run, FOLLOW_STAGES, reps)
+    best_f = int(min(res["follow"], key=res["follow"].get))
+    reco.set_tuning(follow_block=best_f)
+    res["chosen"] = reco.tuning()
+    res["start"] = start
+    return res

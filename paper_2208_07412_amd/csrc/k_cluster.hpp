@@ -1,20 +1,22 @@
 // Clusterizer kernels.
 //
 // Work unit: one (unit,row) x one window of W time bins.  The samples of the
-// window plus an 8-bin halo on each side are scattered into an LDS tile
+// window plus a 4-bin halo on each side are scattered into an LDS tile
 // (ADC per (time, pad)); every sample then finds its uphill neighbour
 // ("up code", the argmax of the (adc, time, pad) key over the 3x3
-// neighbourhood, index (dt+1)*3 + (dp+1), 4 = itself) and every peak gathers
-// the samples of its 5x5 window that reach it in at most two uphill steps.
-// Clusters are written in the order of their peaks (time, then pad); windows
-// find their output offsets by a decoupled look-back in ticket order, so the
-// canonical order needs no second pass and no atomics on the outputs.
+// neighbourhood, index (dt+1)*3 + (dp+1), 4 = itself) and every peak
+// accumulates the samples of its 5x5 window that reach it in at most two
+// uphill steps.  Clusters are written in the order of their peaks (time, then
+// pad): a count pass gives every chunk of K windows its number of peaks, a
+// device-wide scan turns the counts into output offsets, and the emit pass
+// writes each cluster at its final index with no atomics on the outputs.
 #pragma once
 
 #include "common.hpp"
 
-#define CL_HALO 8
-#define CL_TP 142  // tile row stride: pad p is stored in column p + 2
+#define CL_HALO 4    // time bins loaded on each side of a window
+#define CL_BSHIFT 2  // the sample index has one entry per 4 time bins
+#define CL_TP 142    // tile row stride: pad p is stored in column p + 2
 
 struct ZsArgs {
   const uint16_t* pad;
@@ -35,14 +37,16 @@ struct ClusterOut {
   int32_t* sample_label;
 };
 
-// Offsets of the samples (or clusters) of each (unit,row) per block of 8 time
-// bins: blk[ur*(nblk+1) + b] = first index with key time >= 8b; the entry at
-// nblk is the row end.  One workgroup per (unit,row); rows are time-sorted.
+// Offsets of the samples (or clusters) of each (unit,row) per block of
+// 2^bshift time bins: blk[ur*(nblk+1) + b] = first index with key time >=
+// b << bshift; the entry at nblk is the row end.  One workgroup per
+// (unit,row); rows are time-sorted.
 __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict__ tkey,
                                                      const uint16_t* __restrict__ pkey,
                                                      const uint32_t* __restrict__ rstart,
-                                                     uint32_t n_ur, uint32_t nblk, uint32_t T,
-                                                     uint32_t n_total, uint32_t* __restrict__ blk,
+                                                     uint32_t n_ur, uint32_t nblk, uint32_t bshift,
+                                                     uint32_t T, uint32_t n_total,
+                                                     uint32_t* __restrict__ blk,
                                                      const DevParams* __restrict__ P,
                                                      DevStatus* st, int check_input) {
   if (failed(st)) return;
@@ -62,12 +66,12 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
         latch(st, TPC_ERR_INPUT);
         t = T - 1;
       }
-      const uint32_t cur = t >> 3;
+      const uint32_t cur = t >> bshift;
       int32_t prev = -1;
       if (s > s0) {
         uint32_t tp = tkey[s - 1];
         if (tp >= T) tp = T - 1;
-        prev = (int32_t)(tp >> 3);
+        prev = (int32_t)(tp >> bshift);
       }
       for (int32_t k = prev + 1; k <= (int32_t)cur; ++k) b[k] = s;
       if (s == s1 - 1)
@@ -108,42 +112,60 @@ __device__ __forceinline__ int code_offset(int code) {
   return (code / 3 - 1) * CL_TP + (code % 3 - 1);
 }
 
+// ------------------------------------------------------------ tile cells
+// A 16-bit tile cell holds the ADC in bits 0-9.  The emit pass adds, in place:
+//   non-peak: the up code in bits 10-13;
+//   peak:     bit 14, and the peak's slot in the current moment batch in
+//             bits 10-13 (low four bits) and 15 (fifth bit); slot 31 = none.
+// A cell's ADC bits never change, so neighbours reading them concurrently are
+// unaffected.
+#define CL_PEAK 0x4000
+#define CL_SLOTS 31  // peaks whose moments are accumulated per batch
+#define CL_NOSLOT 0xBC00
+
+__device__ __forceinline__ int slot_bits(int k) { return ((k & 15) << 10) | ((k & 16) << 11); }
+__device__ __forceinline__ int slot_of(int cell) {
+  return ((cell >> 10) & 15) | ((cell >> 11) & 16);
+}
+// up code of a cell for the owner chase; a peak points at itself
+__device__ __forceinline__ int chase_code(int cell) {
+  return (cell & CL_PEAK) ? 4 : ((cell >> 10) & 15);
+}
+
 // ------------------------------------------------------------ window loop
 // A workgroup is one wave (64 lanes); it walks K consecutive windows of one
-// (unit,row).  The samples of the next window (core plus an 8-bin halo on
-// each side) are loaded into registers while the current window is worked on
-// from LDS, and the tile is cleared by writing zero back into exactly the
-// cells that were filled.  Tile cells hold the ADC in bits 0-9; the emit pass
-// adds the up code (bits 10-13) and the peak flag (bit 14) in place -- a
-// cell's ADC bits never change, so neighbours reading them concurrently are
-// unaffected.  Compaction is a ballot plus a population count per 64 samples.
-
-#define CL_PRE 4     // samples per lane held in registers for the next window
-#define CL_SLOTS 64  // peaks whose moments are accumulated per batch
+// (unit,row).  The samples of the next window (core plus halo) are loaded
+// into registers while the current window is worked on from LDS, and the tile
+// is cleared by writing zero back into exactly the cells that were filled.
+// Compaction is a ballot plus a population count per 64 samples.
 
 struct WinRange {
   uint32_t s_lo, s_hi;  // window plus halo
   uint32_t c_lo, c_hi;  // core
 };
 
-__device__ __forceinline__ WinRange window_range(const uint32_t* zb, uint32_t nblk, int w, int W,
+template <int W>
+__device__ __forceinline__ WinRange window_range(const uint32_t* zb, uint32_t nblk, int w,
                                                  uint32_t rs0, uint32_t rs1) {
+  constexpr int BW = W >> CL_BSHIFT, BH = CL_HALO >> CL_BSHIFT;
   WinRange R;
-  const int b0 = (w * W) >> 3;
-  row_range(zb, nblk, b0 - 1, b0 + W / 8 + 1, rs0, rs1, R.s_lo, R.s_hi);
-  row_range(zb, nblk, b0, b0 + W / 8, rs0, rs1, R.c_lo, R.c_hi);
+  const int b0 = w * BW;
+  row_range(zb, nblk, b0 - BH, b0 + BW + BH, rs0, rs1, R.s_lo, R.s_hi);
+  row_range(zb, nblk, b0, b0 + BW, rs0, rs1, R.c_lo, R.c_hi);
   return R;
 }
 
 // sample packed as time << 16 | pad (0xFFFFFFFF: none), plus its ADC
+template <int PRE>
 struct SampleRegs {
-  uint32_t tp[CL_PRE];
-  uint16_t a[CL_PRE];
+  uint32_t tp[PRE];
+  uint16_t a[PRE];
 };
 
-__device__ __forceinline__ void prefetch(const ZsArgs& in, const WinRange& R, SampleRegs& S) {
+template <int PRE>
+__device__ __forceinline__ void prefetch(const ZsArgs& in, const WinRange& R, SampleRegs<PRE>& S) {
 #pragma unroll
-  for (int j = 0; j < CL_PRE; ++j) {
+  for (int j = 0; j < PRE; ++j) {
     const uint32_t s = R.s_lo + threadIdx.x + j * 64;
     if (s < R.s_hi) {
       S.tp[j] = ((uint32_t)in.time[s] << 16) | in.pad[s];
@@ -156,13 +178,14 @@ __device__ __forceinline__ void prefetch(const ZsArgs& in, const WinRange& R, Sa
 }
 
 // packed sample j of this lane's share of [s_lo, s_hi): registers first
-__device__ __forceinline__ uint32_t sample_tp(const ZsArgs& in, const SampleRegs& S, uint32_t j,
-                                              uint32_t s) {
+template <int PRE>
+__device__ __forceinline__ uint32_t sample_tp(const ZsArgs& in, const SampleRegs<PRE>& S,
+                                              uint32_t j, uint32_t s) {
   uint32_t tp = 0xFFFFFFFFu;
 #pragma unroll
-  for (int jj = 0; jj < CL_PRE; ++jj)
+  for (int jj = 0; jj < PRE; ++jj)
     if (j == (uint32_t)jj) tp = S.tp[jj];
-  if (j >= CL_PRE) tp = ((uint32_t)in.time[s] << 16) | in.pad[s];
+  if (j >= PRE) tp = ((uint32_t)in.time[s] << 16) | in.pad[s];
   return tp;
 }
 
@@ -176,15 +199,15 @@ __device__ __forceinline__ int cell_of(uint32_t tp, int tile_t0, int np) {
 }
 
 // place (place = true) or clear the window's samples in the tile
-template <int ROWS>
+template <int ROWS, int PRE>
 __device__ __forceinline__ void scatter(uint16_t* tile, const ZsArgs& in, const WinRange& R,
-                                        const SampleRegs& S, int tile_t0, int np, bool place) {
+                                        const SampleRegs<PRE>& S, int tile_t0, int np, bool place) {
 #pragma unroll
-  for (int j = 0; j < CL_PRE; ++j) {
+  for (int j = 0; j < PRE; ++j) {
     const int c = cell_of<ROWS>(S.tp[j], tile_t0, np);
     if (c >= 0) tile[c] = place ? (uint16_t)(S.a[j] & 0x3FF) : 0;
   }
-  for (uint32_t s = R.s_lo + CL_PRE * 64 + threadIdx.x; s < R.s_hi; s += 64) {
+  for (uint32_t s = R.s_lo + PRE * 64 + threadIdx.x; s < R.s_hi; s += 64) {
     const uint32_t tp = ((uint32_t)in.time[s] << 16) | in.pad[s];
     const int c = cell_of<ROWS>(tp, tile_t0, np);
     if (c >= 0) tile[c] = place ? (uint16_t)(in.adc[s] & 0x3FF) : 0;
@@ -211,20 +234,40 @@ __device__ __forceinline__ int up_code_of(const uint16_t* tile, int c, int qmin)
   return code | ((code == 4 && a >= qmin) ? 16 : 0);
 }
 
+// The peak test alone: the sample's key beats its 8 neighbours (earlier
+// neighbours may tie on ADC, later ones may not) and its ADC reaches qmin.
+__device__ __forceinline__ bool is_peak(const uint16_t* tile, int c, int qmin) {
+  const int a = tile[c] & 0x3FF;
+  const int e = max(max(tile[c - CL_TP - 1] & 0x3FF, tile[c - CL_TP] & 0x3FF),
+                    max(tile[c - CL_TP + 1] & 0x3FF, tile[c - 1] & 0x3FF));
+  const int l = max(max(tile[c + 1] & 0x3FF, tile[c + CL_TP - 1] & 0x3FF),
+                    max(tile[c + CL_TP] & 0x3FF, tile[c + CL_TP + 1] & 0x3FF));
+  return a >= qmin && e <= a && l < a;
+}
+
 __device__ __forceinline__ uint32_t lanes_below() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
-template <int W, int K>
+template <int ROWS>
+__device__ __forceinline__ void clear_tile(uint16_t* tile) {
+  constexpr int TILE = ROWS * CL_TP;
+  uint4* t4 = reinterpret_cast<uint4*>(tile);
+  constexpr int N4 = TILE * 2 / 16;
+  for (int i = threadIdx.x; i < N4; i += 64) t4[i] = make_uint4(0, 0, 0, 0);
+  for (int i = N4 * 8 + threadIdx.x; i < TILE; i += 64) tile[i] = 0;
+}
+
+// Number of peaks of every chunk of K windows.
+template <int W, int K, int PRE>
 __global__ __launch_bounds__(64) void k_cluster_count(ZsArgs in, const uint32_t* __restrict__ zblk,
                                                       uint32_t nblk, uint32_t nwin,
                                                       uint32_t nchunk, uint32_t n_ur,
-                                                      uint32_t* __restrict__ win_cnt,
+                                                      uint32_t* __restrict__ chunk_cnt,
                                                       const DevParams* __restrict__ P,
                                                       const DevStatus* st) {
   constexpr int ROWS = W + 2 * CL_HALO;
-  constexpr int TILE = ROWS * CL_TP;
-  __shared__ __attribute__((aligned(16))) uint16_t tile[TILE];
+  __shared__ __attribute__((aligned(16))) uint16_t tile[ROWS * CL_TP];
   if (failed(st)) return;
   const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
@@ -236,58 +279,56 @@ __global__ __launch_bounds__(64) void k_cluster_count(ZsArgs in, const uint32_t*
   if (rs0 > rs1) rs0 = rs1;
   const int w0 = chunk * K;
   const int w1 = min((int)nwin, w0 + K);
-  {
-    uint4* t4 = reinterpret_cast<uint4*>(tile);
-    constexpr int N4 = TILE * 2 / 16;
-    for (int i = threadIdx.x; i < N4; i += 64) t4[i] = make_uint4(0, 0, 0, 0);
-    for (int i = N4 * 8 + threadIdx.x; i < TILE; i += 64) tile[i] = 0;
-  }
-  WinRange R = window_range(zb, nblk, w0, W, rs0, rs1);
-  SampleRegs cur, nxt;
+  clear_tile<ROWS>(tile);
+  WinRange R = window_range<W>(zb, nblk, w0, rs0, rs1);
+  SampleRegs<PRE> cur, nxt;
   prefetch(in, R, cur);
   __syncthreads();
+  uint32_t cnt = 0;
   for (int w = w0; w < w1; ++w) {
     const int tile_t0 = w * W - CL_HALO;
     scatter<ROWS>(tile, in, R, cur, tile_t0, np, true);
     WinRange Rn = R;
     if (w + 1 < w1) {
-      Rn = window_range(zb, nblk, w + 1, W, rs0, rs1);
+      Rn = window_range<W>(zb, nblk, w + 1, rs0, rs1);
       prefetch(in, Rn, nxt);
     }
     __syncthreads();
-    uint32_t cnt = 0;
     for (uint32_t s0 = R.s_lo; s0 < R.c_hi; s0 += 64) {
       const uint32_t s = s0 + threadIdx.x;
       bool pk = false;
       if (s >= R.c_lo && s < R.c_hi) {
         const int c = cell_of<ROWS>(sample_tp(in, cur, (s0 - R.s_lo) >> 6, s), tile_t0, np);
-        pk = c >= 0 && (up_code_of(tile, c, qmin) & 16);
+        pk = c >= 0 && is_peak(tile, c, qmin);
       }
       cnt += __popcll(__ballot(pk));
     }
-    if (threadIdx.x == 0) win_cnt[(size_t)ur * nwin + w] = cnt;
     __syncthreads();
     scatter<ROWS>(tile, in, R, cur, tile_t0, np, false);
     __syncthreads();
     R = Rn;
     cur = nxt;
   }
+  if (threadIdx.x == 0) chunk_cnt[(size_t)ur * nchunk + chunk] = cnt;
 }
 
-template <int W, int K>
+template <int W, int K, int PRE>
 __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* __restrict__ zblk,
                                                      uint32_t nblk, uint32_t nwin, uint32_t nchunk,
                                                      uint32_t n_ur,
-                                                     const uint32_t* __restrict__ win_off,
+                                                     const uint32_t* __restrict__ chunk_off,
                                                      ClusterOut out,
                                                      const DevParams* __restrict__ P,
                                                      const DevStatus* st) {
   constexpr int ROWS = W + 2 * CL_HALO;
-  constexpr int TILE = ROWS * CL_TP;
-  __shared__ __attribute__((aligned(16))) uint16_t tile[TILE];
-  __shared__ uint16_t pk_cell[CL_SLOTS];
-  // per peak of the batch: q, sp, st, spp, stt, n, sat
-  __shared__ int32_t acc[7][CL_SLOTS];
+  __shared__ __attribute__((aligned(16))) uint16_t tile[ROWS * CL_TP];
+  __shared__ uint16_t pk_cell[CL_SLOTS + 1];
+  // per peak of the batch, packed sums (every field stays below its width:
+  // at most 25 samples of ADC <= 1023 per peak)
+  //   acc0: q (15 bits) | n (5 bits) << 15 | n_sat (5 bits) << 20 |
+  //         sum a(dp+2) (17 bits) << 25 | sum a dp^2 (17 bits) << 42
+  //   acc1: sum a(dt+2) (17 bits) | sum a dt^2 (17 bits) << 32
+  __shared__ unsigned long long acc0[CL_SLOTS + 1], acc1[CL_SLOTS + 1];
   if (failed(st)) return;
   const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
@@ -301,59 +342,60 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
   if (rs0 > rs1) rs0 = rs1;
   const int w0 = chunk * K;
   const int w1 = min((int)nwin, w0 + K);
-  {
-    uint4* t4 = reinterpret_cast<uint4*>(tile);
-    constexpr int N4 = TILE * 2 / 16;
-    for (int i = threadIdx.x; i < N4; i += 64) t4[i] = make_uint4(0, 0, 0, 0);
-    for (int i = N4 * 8 + threadIdx.x; i < TILE; i += 64) tile[i] = 0;
-  }
-  WinRange R = window_range(zb, nblk, w0, W, rs0, rs1);
-  SampleRegs cur, nxt;
+  clear_tile<ROWS>(tile);
+  WinRange R = window_range<W>(zb, nblk, w0, rs0, rs1);
+  SampleRegs<PRE> cur, nxt;
   prefetch(in, R, cur);
+  uint32_t base = chunk_off[(size_t)ur * nchunk + chunk];
   __syncthreads();
   for (int w = w0; w < w1; ++w) {
     const int tile_t0 = w * W - CL_HALO;
     scatter<ROWS>(tile, in, R, cur, tile_t0, np, true);
     WinRange Rn = R;
     if (w + 1 < w1) {
-      Rn = window_range(zb, nblk, w + 1, W, rs0, rs1);
+      Rn = window_range<W>(zb, nblk, w + 1, rs0, rs1);
       prefetch(in, Rn, nxt);
     }
-    const uint32_t base = win_off[(size_t)ur * nwin + w];
     __syncthreads();
-    // up codes of the samples within 4 bins of the core, written in place
+    // Up codes of the samples within 3 bins of the core, written in place;
+    // core peaks are ranked in sample order and the first CL_SLOTS get slots.
+    uint32_t total = 0;
     for (uint32_t s0 = R.s_lo; s0 < R.s_hi; s0 += 64) {
       const uint32_t s = s0 + threadIdx.x;
-      if (s >= R.s_hi) continue;
-      const uint32_t tp = sample_tp(in, cur, (s0 - R.s_lo) >> 6, s);
-      const int c = cell_of<ROWS>(tp, tile_t0, np);
-      const int lt = (int)(tp >> 16) - tile_t0;
-      if (c < 0 || lt < CL_HALO - 4 || lt >= CL_HALO + W + 4) continue;
-      const int code = up_code_of(tile, c, qmin);
-      tile[c] = (uint16_t)((tile[c] & 0x3FF) | (code << 10));
-    }
-    __syncthreads();
-    // peaks of the core in sample order, in batches of CL_SLOTS
-    uint32_t done = 0;  // peaks handled in earlier batches
-    for (;;) {
-      uint32_t rank = 0, nb = 0;
-      for (uint32_t s0 = R.s_lo; s0 < R.c_hi; s0 += 64) {
-        const uint32_t s = s0 + threadIdx.x;
-        int c = -1;
-        if (s >= R.c_lo && s < R.c_hi)
-          c = cell_of<ROWS>(sample_tp(in, cur, (s0 - R.s_lo) >> 6, s), tile_t0, np);
-        const bool pk = c >= 0 && (tile[c] & 0x4000) != 0;
-        const uint64_t m = __ballot(pk);
-        const uint32_t k = rank + (uint32_t)__popcll(m & ((1ull << threadIdx.x) - 1ull));
-        if (pk && k >= done && k < done + CL_SLOTS) pk_cell[k - done] = (uint16_t)c;
-        rank += (uint32_t)__popcll(m);
+      int c = -1, lt = -1;
+      if (s < R.s_hi) {
+        const uint32_t tp = sample_tp(in, cur, (s0 - R.s_lo) >> 6, s);
+        c = cell_of<ROWS>(tp, tile_t0, np);
+        lt = (int)(tp >> 16) - tile_t0;
       }
-      nb = min(rank - done, (uint32_t)CL_SLOTS);
-      if (nb == 0) break;
-#pragma unroll
-      for (int m = 0; m < 7; ++m) acc[m][threadIdx.x] = 0;
+      const bool live = c >= 0 && lt >= CL_HALO - 3 && lt < CL_HALO + W + 3;
+      const int code = live ? up_code_of(tile, c, qmin) : 0;
+      const bool pk = live && (code & 16) && lt >= CL_HALO && lt < CL_HALO + W;
+      const uint64_t m = __ballot(pk);
+      const uint32_t k = total + (uint32_t)__popcll(m & ((1ull << threadIdx.x) - 1ull));
+      if (live) {
+        const int a = tile[c] & 0x3FF;
+        int v;
+        if (!(code & 16)) {
+          v = a | (code << 10);
+        } else if (pk && k < CL_SLOTS) {
+          v = a | CL_PEAK | slot_bits(k);
+          pk_cell[k] = (uint16_t)c;
+        } else {
+          v = a | CL_PEAK | CL_NOSLOT;
+        }
+        tile[c] = (uint16_t)v;
+      }
+      total += (uint32_t)__popcll(m);
+    }
+    uint32_t done = 0;  // peaks handled in earlier batches
+    uint32_t nb = min(total, (uint32_t)CL_SLOTS);
+    while (nb > 0) {
+      if (threadIdx.x < CL_SLOTS + 1) {
+        acc0[threadIdx.x] = 0;
+        acc1[threadIdx.x] = 0;
+      }
       __syncthreads();
-      const int c_first = pk_cell[0], c_last = pk_cell[nb - 1];
       // every sample within two bins of the core adds itself to its peak
       for (uint32_t s0 = R.s_lo; s0 < R.s_hi; s0 += 64) {
         const uint32_t s = s0 + threadIdx.x;
@@ -363,46 +405,36 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
         const int lt = (int)(tp >> 16) - tile_t0;
         if (x < 0 || lt < CL_HALO - 2 || lt >= CL_HALO + W + 2) continue;
         const int tx = tile[x];
-        int own = -1;
-        if (tx & 0x4000) {
-          own = x;
-        } else {
-          const int y = x + code_offset((tx >> 10) & 15);
-          const int ty = tile[y];
-          if (ty & 0x4000) {
-            own = y;
-          } else {
-            const int z = y + code_offset((ty >> 10) & 15);
-            if (tile[z] & 0x4000) own = z;
-          }
-        }
-        if (own < c_first || own > c_last) continue;
-        // slot of the owner peak: binary search of the batch (ascending cells)
-        int lo = 0, hi = (int)nb - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if ((int)pk_cell[mid] < own) lo = mid + 1;
-          else hi = mid;
-        }
-        if ((int)pk_cell[lo] != own) continue;
-        const int a = tx & 0x3FF;
-        const int d = x - own;
+        const int y = x + code_offset(chase_code(tx));
+        const int ty = tile[y];
+        const int z = y + code_offset(chase_code(ty));
+        const int tz = tile[z];
+        const int slot = slot_of(tz);
+        if (!(tz & CL_PEAK) || slot == CL_SLOTS) continue;
+        const uint32_t a = tx & 0x3FF;
+        const int d = x - z;
         const int dt = (d + 2 * CL_TP + 2) / CL_TP - 2;
         const int dp = d - dt * CL_TP;
-        atomicAdd(&acc[0][lo], a);
-        atomicAdd(&acc[1][lo], a * dp);
-        atomicAdd(&acc[2][lo], a * dt);
-        atomicAdd(&acc[3][lo], a * dp * dp);
-        atomicAdd(&acc[4][lo], a * dt * dt);
-        atomicAdd(&acc[5][lo], 1);
-        if (a >= 1023) atomicOr(&acc[6][lo], 1);
+        const uint64_t v0 = (uint64_t)a | (1ull << 15) | ((uint64_t)(a >= 1023) << 20) |
+                            ((uint64_t)(a * (uint32_t)(dp + 2)) << 25) |
+                            ((uint64_t)(a * (uint32_t)(dp * dp)) << 42);
+        const uint64_t v1 = (uint64_t)(a * (uint32_t)(dt + 2)) |
+                            ((uint64_t)(a * (uint32_t)(dt * dt)) << 32);
+        atomicAdd(&acc0[slot], (unsigned long long)v0);
+        atomicAdd(&acc1[slot], (unsigned long long)v1);
       }
       __syncthreads();
       const uint32_t i = threadIdx.x;
       if (i < nb) {
         const int c = pk_cell[i];
-        const int q = acc[0][i], sp = acc[1][i], st_ = acc[2][i], spp = acc[3][i],
-                  stt = acc[4][i], ns = acc[5][i], sat = acc[6][i];
+        const uint64_t v0 = acc0[i], v1 = acc1[i];
+        const int q = (int)(v0 & 0x7FFF);
+        const int ns = (int)((v0 >> 15) & 31);
+        const int sat = (int)((v0 >> 20) & 31);
+        const int sp = (int)((v0 >> 25) & 0x1FFFF) - 2 * q;
+        const int spp = (int)((v0 >> 42) & 0x1FFFF);
+        const int st_ = (int)(v1 & 0x1FFFF) - 2 * q;
+        const int stt = (int)((v1 >> 32) & 0x1FFFF);
         const uint32_t k = base + done + i;
         if (k < out.capacity) {
           const int lt = c / CL_TP;
@@ -432,25 +464,42 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
             out.nsamp[k] = (uint16_t)ns;
           }
         }
+        // the peak leaves the batch
+        tile[c] = (uint16_t)((tile[c] & 0x43FF) | CL_NOSLOT);
       }
       done += nb;
+      nb = min(total - done, (uint32_t)CL_SLOTS);
+      if (nb == 0) break;
       __syncthreads();
-      if (done >= rank) break;
+      // slots for the next batch of core peaks, in sample order
+      uint32_t rank = 0;
+      for (uint32_t s0 = R.s_lo; s0 < R.c_hi; s0 += 64) {
+        const uint32_t s = s0 + threadIdx.x;
+        int c = -1;
+        if (s >= R.c_lo && s < R.c_hi)
+          c = cell_of<ROWS>(sample_tp(in, cur, (s0 - R.s_lo) >> 6, s), tile_t0, np);
+        const bool pk = c >= 0 && (tile[c] & CL_PEAK) != 0;
+        const uint64_t m = __ballot(pk);
+        const uint32_t k = rank + (uint32_t)__popcll(m & ((1ull << threadIdx.x) - 1ull));
+        if (pk && k >= done && k < done + nb) {
+          tile[c] = (uint16_t)((tile[c] & 0x43FF) | slot_bits(k - done));
+          pk_cell[k - done] = (uint16_t)c;
+        }
+        rank += (uint32_t)__popcll(m);
+      }
     }
+    base += total;
     if (out.sample_label) {
+      __syncthreads();
       for (uint32_t s = R.c_lo + threadIdx.x; s < R.c_hi; s += 64) {
         const uint32_t tp = ((uint32_t)in.time[s] << 16) | in.pad[s];
         const int lt = (int)(tp >> 16) - tile_t0;
-        const int c = cell_of<ROWS>(tp, tile_t0, np);
+        const int x = cell_of<ROWS>(tp, tile_t0, np);
         int32_t lab = -1;
-        if (c >= 0 && lt >= CL_HALO && lt < CL_HALO + W) {
-          const int cx = tile[c];
-          const int y = c + code_offset((cx >> 10) & 15);
-          const int cy = tile[y];
-          const int z = y + code_offset((cy >> 10) & 15);
-          const int cz = tile[z];
-          const int pk = (cx & 0x4000) ? c : ((cy & 0x4000) ? y : ((cz & 0x4000) ? z : -1));
-          if (pk >= 0) lab = ((pk / CL_TP + tile_t0) << 8) | (pk % CL_TP - 2);
+        if (x >= 0 && lt >= CL_HALO && lt < CL_HALO + W) {
+          const int y = x + code_offset(chase_code(tile[x]));
+          const int z = y + code_offset(chase_code(tile[y]));
+          if (tile[z] & CL_PEAK) lab = ((z / CL_TP + tile_t0) << 8) | (z % CL_TP - 2);
         }
         out.sample_label[s] = lab;
       }
@@ -463,14 +512,14 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
   }
 }
 
-// crow_start[ur] = first cluster of (unit,row), from the scanned window counts.
-__global__ void k_crow_start(const uint32_t* __restrict__ win_off, uint32_t nwin, uint32_t n_ur,
-                             const uint32_t* __restrict__ n_clusters, uint32_t capacity,
-                             uint32_t* __restrict__ crow, DevStatus* st) {
+// crow_start[ur] = first cluster of (unit,row), from the scanned chunk counts.
+__global__ void k_crow_start(const uint32_t* __restrict__ chunk_off, uint32_t nchunk,
+                             uint32_t n_ur, const uint32_t* __restrict__ n_clusters,
+                             uint32_t capacity, uint32_t* __restrict__ crow, DevStatus* st) {
   const uint32_t n = *n_clusters;
   for (uint32_t ur = blockIdx.x * blockDim.x + threadIdx.x; ur <= n_ur;
        ur += gridDim.x * blockDim.x)
-    crow[ur] = ur < n_ur ? win_off[(size_t)ur * nwin] : n;
+    crow[ur] = ur < n_ur ? chunk_off[(size_t)ur * nchunk] : n;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->n_clusters = n;
     if (n > capacity) latch(st, TPC_ERR_CAPACITY, n);

@@ -39,47 +39,152 @@ __device__ __forceinline__ void nb_candidates(const ClusterView& cl, const uint3
             cl.row_start(ur + 1), a, b);
 }
 
+// Best (j, k) pair for cluster i among the candidates [ja, jb) x [ka, kb),
+// positions read through the accessors J (row r-1) and K (row r+1), which
+// return (y, z) from LDS-staged rows or global memory.  The k candidates inside the window are listed once in registers
+// (up to NB_KLIST; beyond that the whole range is scanned per j).
+#define NB_KLIST 8
+template <class PJ, class PK>
+__device__ __forceinline__ void nb_best(PJ J, PK K, int64_t yi, int64_t zi, int64_t wy,
+                                        int64_t wz, int64_t smax, uint32_t ja, uint32_t jb,
+                                        uint32_t ka, uint32_t kb, int32_t& bd, int32_t& bu) {
+  uint32_t kl[NB_KLIST];
+  int nk = 0;
+  bool over = false;
+  for (uint32_t k = ka; k < kb; ++k) {
+    const int2 pk = K(k);
+    const int64_t yk = pk.x, zk = pk.y;
+    if (yk - yi > wy || yi - yk > wy || zk - zi > wz || zi - zk > wz) continue;
+    if (nk < NB_KLIST) {
+#pragma unroll
+      for (int m = 0; m < NB_KLIST; ++m)
+        if (m == nk) kl[m] = k;
+      ++nk;
+    } else {
+      over = true;
+    }
+  }
+  if (nk == 0) return;
+  int64_t best = -1;
+  for (uint32_t j = ja; j < jb; ++j) {
+    const int2 pj = J(j);
+    const int64_t yj = pj.x, zj = pj.y;
+    if (yj - yi > wy || yi - yj > wy || zj - zi > wz || zi - zj > wz) continue;
+    const int64_t ay = 2 * yi - yj, az = 2 * zi - zj;
+    if (!over) {
+#pragma unroll
+      for (int m = 0; m < NB_KLIST; ++m) {
+        if (m >= nk) break;
+        const uint32_t k = kl[m];
+        const int2 pk = K(k);
+        const int64_t dy = ay - pk.x, dz = az - pk.y;
+        const int64_t s = dy * dy + dz * dz;
+        // j and k ascend, so a strict "<" keeps the smallest (j, k) on ties
+        if (s <= smax && (best < 0 || s < best)) {
+          best = s;
+          bd = (int32_t)j;
+          bu = (int32_t)k;
+        }
+      }
+    } else {
+      for (uint32_t k = ka; k < kb; ++k) {
+        const int2 pk = K(k);
+        const int64_t yk = pk.x, zk = pk.y;
+        if (yk - yi > wy || yi - yk > wy || zk - zi > wz || zi - zk > wz) continue;
+        const int64_t dy = ay - yk, dz = az - zk;
+        const int64_t s = dy * dy + dz * dz;
+        if (s <= smax && (best < 0 || s < best)) {
+          best = s;
+          bd = (int32_t)j;
+          bu = (int32_t)k;
+        }
+      }
+    }
+  }
+}
+
+// One workgroup per (unit,row) walks the row's clusters in batches of 256
+// (time order).  The candidate clusters of the two neighbouring rows for the
+// whole batch -- a contiguous range in each, since rows are time-sorted --
+// are staged in LDS when they fit, so every candidate is read from HBM once.
+#define NB_STAGE 1024
 __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32_t* __restrict__ cblk,
                                                     uint32_t nblk, uint32_t n_ur,
                                                     int32_t* __restrict__ down,
                                                     int32_t* __restrict__ up,
                                                     const DevParams* __restrict__ P,
                                                     const DevStatus* st) {
+  __shared__ int2 sp[2][NB_STAGE];
+  __shared__ uint32_t rng[4];
   if (failed(st)) return;
   const int64_t wy = P->win_y, wz = P->win_z, smax = P->s_max;
-  const uint32_t nb = gridDim.x;
-  for (uint32_t bid = blockIdx.x; bid < n_ur; bid += nb) {
-    const uint32_t ur = bid;
+  for (uint32_t b = blockIdx.x; b < n_ur; b += gridDim.x) {
+    // consecutive rows of a sector share an XCD (and its L2) when the grid
+    // covers every row
+    const uint32_t ur = gridDim.x == n_ur ? xcd_remap(b, n_ur) : b;
     const int r = ur % NROW;
     const uint32_t c0 = cl.row_start(ur), c1 = cl.row_start(ur + 1);
-    for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-      int32_t bd = -1, bu = -1;
-      if (r >= 1 && r <= NROW - 2) {
-        const int64_t yi = cl.y_fx[i], zi = cl.z_fx[i];
-        uint32_t ja, jb, ka, kb;
+    if (r < 1 || r > NROW - 2) {
+      for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+        down[i] = -1;
+        up[i] = -1;
+      }
+      continue;
+    }
+    for (uint32_t base = c0; base < c1; base += blockDim.x) {
+      const uint32_t i = base + threadIdx.x;
+      const bool valid = i < c1;
+      int64_t yi = 0, zi = 0;
+      uint32_t ja = 0, jb = 0, ka = 0, kb = 0;
+      if (valid) {
+        yi = cl.y_fx[i];
+        zi = cl.z_fx[i];
         nb_candidates(cl, cblk, nblk, ur - 1, zi, wz, ja, jb);
         nb_candidates(cl, cblk, nblk, ur + 1, zi, wz, ka, kb);
-        int64_t best = -1;
-        for (uint32_t j = ja; j < jb; ++j) {
-          const int64_t yj = cl.y_fx[j], zj = cl.z_fx[j];
-          if (yj - yi > wy || yi - yj > wy || zj - zi > wz || zi - zj > wz) continue;
-          const int64_t ay = 2 * yi - yj, az = 2 * zi - zj;
-          for (uint32_t k = ka; k < kb; ++k) {
-            const int64_t yk = cl.y_fx[k], zk = cl.z_fx[k];
-            if (yk - yi > wy || yi - yk > wy || zk - zi > wz || zi - zk > wz) continue;
-            const int64_t dy = ay - yk, dz = az - zk;
-            const int64_t s = dy * dy + dz * dz;
-            // j and k ascend, so a strict "<" keeps the smallest (j, k) on ties
-            if (s <= smax && (best < 0 || s < best)) {
-              best = s;
-              bd = (int32_t)j;
-              bu = (int32_t)k;
-            }
-          }
-        }
       }
-      down[i] = bd;
-      up[i] = bu;
+      if (threadIdx.x == 0) {
+        rng[0] = 0xFFFFFFFFu;
+        rng[1] = 0;
+        rng[2] = 0xFFFFFFFFu;
+        rng[3] = 0;
+      }
+      __syncthreads();
+      if (valid && jb > ja) {
+        atomicMin(&rng[0], ja);
+        atomicMax(&rng[1], jb);
+      }
+      if (valid && kb > ka) {
+        atomicMin(&rng[2], ka);
+        atomicMax(&rng[3], kb);
+      }
+      __syncthreads();
+      const uint32_t JA = rng[0], JB = rng[1], KA = rng[2], KB = rng[3];
+      const bool stage_j = JB > JA && JB - JA <= NB_STAGE;
+      const bool stage_k = KB > KA && KB - KA <= NB_STAGE;
+      if (stage_j)
+        for (uint32_t t = threadIdx.x; t < JB - JA; t += blockDim.x) {
+          sp[0][t] = make_int2(cl.y_fx[JA + t], cl.z_fx[JA + t]);
+        }
+      if (stage_k)
+        for (uint32_t t = threadIdx.x; t < KB - KA; t += blockDim.x) {
+          sp[1][t] = make_int2(cl.y_fx[KA + t], cl.z_fx[KA + t]);
+        }
+      __syncthreads();
+      int32_t bd = -1, bu = -1;
+      if (valid && jb > ja && kb > ka) {
+        auto Jl = [&](uint32_t c) { return sp[0][c - JA]; };
+        auto Kl = [&](uint32_t c) { return sp[1][c - KA]; };
+        auto G = [&](uint32_t c) { return make_int2(cl.y_fx[c], cl.z_fx[c]); };
+        if (stage_j && stage_k) nb_best(Jl, Kl, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);
+        else if (stage_j) nb_best(Jl, G, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);
+        else if (stage_k) nb_best(G, Kl, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);
+        else nb_best(G, G, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);
+      }
+      if (valid) {
+        down[i] = bd;
+        up[i] = bu;
+      }
+      __syncthreads();
     }
   }
 }

@@ -70,6 +70,26 @@ struct PV<double> {
   __device__ double c0r(int i) const { return P->c0r2_d[i]; }
 };
 
+// Low-order parts of y and sin phi carried beside an FP32 state.  Over many
+// rows a stiff track adds almost the same increment C dx to sin phi at every
+// step, so FP32 rounding errs the same way each time and the sum drifts like
+// a curvature offset of about ulp(sin phi) / dx; adding each increment with
+// an error-free two-sum and keeping the rounding error removes the drift.
+template <typename T>
+struct LoParts {
+  T y, s;
+};
+
+// a + b = hi + lo exactly (two-sum); lo accumulates into *acc
+template <typename T>
+__device__ __forceinline__ T two_sum_acc(T a, T b, T* acc) {
+  const T b2 = b + *acc;
+  const T hi = a + b2;
+  const T bb = hi - a;
+  *acc = (a - (hi - bb)) + (b2 - bb);
+  return hi;
+}
+
 // exact row-to-row distance from the integer radii
 template <typename T>
 __device__ __forceinline__ T row_dx(const DevParams* P, int r1, int r2) {
@@ -96,15 +116,38 @@ __device__ __forceinline__ T darc_dc(T s1, T C, T dx) {
   return acc * dx * dx;
 }
 
+// FP32: the same quadrature with w^(-3/2) from the hardware reciprocal square
+// root (a Jacobian element: a few ulp are far below what the fit resolves).
+template <>
+__device__ __forceinline__ float darc_dc<float>(float s1, float C, float dx) {
+  const float X[8] = {0.01985507175123188f, 0.10166676129318664f, 0.2372337950418355f,
+                      0.4082826787521751f,  0.5917173212478249f,  0.7627662049581645f,
+                      0.8983332387068134f,  0.9801449282487681f};
+  const float Wt[8] = {0.05061426814518813f, 0.11119051722668724f, 0.15685332293894363f,
+                       0.18134189168918100f, 0.18134189168918100f, 0.15685332293894363f,
+                       0.11119051722668724f, 0.05061426814518813f};
+  const float Cdx = C * dx;
+  float acc = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float s = s1 + Cdx * X[i];
+    const float r = __builtin_amdgcn_rsqf(1.0f - s * s);
+    acc += (Wt[i] * X[i]) * s * (r * r * r);
+  }
+  return acc * dx * dx;
+}
+
 // Helix propagation over dx; with_cov also transports the covariance with
 // the analytic Jacobian.  Returns false (state untouched) if |sin phi| would
 // reach snp_max.
 template <typename T>
 __device__ __forceinline__ bool propagate(Trk<T>& k, T dx, const PV<T>& pv, bool with_cov,
-                                          T snp_lim) {
+                                          T snp_lim, LoParts<T>* lo = nullptr) {
   const T b = pv.b();
   const T C = -b * k.p[4];
-  const T s1 = k.p[2], s2 = s1 + C * dx;
+  const T s1 = k.p[2];
+  T slo = lo ? lo->s : (T)0;
+  const T s2 = lo ? two_sum_acc(s1, C * dx, &slo) : s1 + C * dx;
   if (!(fabs(s2) < snp_lim)) return false;
   const T c1 = sqrt((T)1 - s1 * s1), c2 = sqrt((T)1 - s2 * s2);
   const T D = c1 + c2, N = s1 + s2, f = N / D;
@@ -144,18 +187,33 @@ __device__ __forceinline__ bool propagate(Trk<T>& k, T dx, const PV<T>& pv, bool
       for (int j = i; j < 5; ++j) k.c[PI(i, j)] = col[j];
     }
   }
-  k.p[0] += dx * f;
+  if (lo) {
+    k.p[0] = two_sum_acc(k.p[0], dx * f, &lo->y);
+    lo->s = slo;
+  } else {
+    k.p[0] += dx * f;
+  }
   k.p[1] += k.p[3] * A;
   k.p[2] = s2;
   return true;
 }
 
+// inverse of the residual covariance S = C_yz + V, once per row
 template <typename T>
-__device__ __forceinline__ T chi2_of(const Trk<T>& k, T my, T mz, T vy, T vz) {
-  const T r0 = my - k.p[0], r1 = mz - k.p[1];
+struct SInv {
+  T i00, i01, i11;
+};
+template <typename T>
+__device__ __forceinline__ SInv<T> s_inverse(const Trk<T>& k, T vy, T vz) {
   const T S00 = k.c[0] + vy, S01 = k.c[1], S11 = k.c[5] + vz;
-  const T det = S00 * S11 - S01 * S01;
-  return (r0 * r0 * S11 - (T)2 * r0 * r1 * S01 + r1 * r1 * S00) / det;
+  const T rd = (T)1 / (S00 * S11 - S01 * S01);
+  return SInv<T>{S11 * rd, -S01 * rd, S00 * rd};
+}
+
+template <typename T>
+__device__ __forceinline__ T chi2_of(const Trk<T>& k, T my, T mz, const SInv<T>& si) {
+  const T r0 = my - k.p[0], r1 = mz - k.p[1];
+  return r0 * r0 * si.i00 + (T)2 * r0 * r1 * si.i01 + r1 * r1 * si.i11;
 }
 
 // Kalman update with a (y, z) measurement.  Returns false (state untouched)
@@ -163,9 +221,8 @@ __device__ __forceinline__ T chi2_of(const Trk<T>& k, T my, T mz, T vy, T vz) {
 template <typename T>
 __device__ __forceinline__ bool update(Trk<T>& k, T my, T mz, T vy, T vz, T* chi2) {
   const T r0 = my - k.p[0], r1 = mz - k.p[1];
-  const T S00 = k.c[0] + vy, S01 = k.c[1], S11 = k.c[5] + vz;
-  const T det = S00 * S11 - S01 * S01;
-  const T I00 = S11 / det, I01 = -S01 / det, I11 = S00 / det;
+  const SInv<T> si = s_inverse(k, vy, vz);
+  const T I00 = si.i00, I01 = si.i01, I11 = si.i11;
   if (chi2) *chi2 = r0 * r0 * I00 + (T)2 * r0 * r1 * I01 + r1 * r1 * I11;
   T K0[5], K1[5], c0[5], c1v[5];
 #pragma unroll
@@ -191,11 +248,11 @@ __device__ __forceinline__ bool update(Trk<T>& k, T my, T mz, T vy, T vz, T* chi
 // arithmetic but keeps FP32 precision while the prior variance collapses by
 // many orders of magnitude over the first hits (used by the refit).
 template <typename T>
-__device__ __forceinline__ bool update_joseph(Trk<T>& k, T my, T mz, T vy, T vz, T* chi2) {
+__device__ __forceinline__ bool update_joseph(Trk<T>& k, T my, T mz, T vy, T vz, T* chi2,
+                                              LoParts<T>* lo = nullptr) {
   const T r0 = my - k.p[0], r1 = mz - k.p[1];
-  const T S00 = k.c[0] + vy, S01 = k.c[1], S11 = k.c[5] + vz;
-  const T det = S00 * S11 - S01 * S01;
-  const T I00 = S11 / det, I01 = -S01 / det, I11 = S00 / det;
+  const SInv<T> si = s_inverse(k, vy, vz);
+  const T I00 = si.i00, I01 = si.i01, I11 = si.i11;
   if (chi2) *chi2 = r0 * r0 * I00 + (T)2 * r0 * r1 * I01 + r1 * r1 * I11;
   T K0[5], K1[5], c0[5], c1v[5];
 #pragma unroll
@@ -207,8 +264,16 @@ __device__ __forceinline__ bool update_joseph(Trk<T>& k, T my, T mz, T vy, T vz,
   }
   const T np2 = k.p[2] + K0[2] * r0 + K1[2] * r1;
   if (!(fabs(np2) < (T)1)) return false;
+  if (lo) {
+    k.p[0] = two_sum_acc(k.p[0], K0[0] * r0 + K1[0] * r1, &lo->y);
+    k.p[2] = two_sum_acc(k.p[2], K0[2] * r0 + K1[2] * r1, &lo->s);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) k.p[i] += K0[i] * r0 + K1[i] * r1;
+    for (int i = 0; i < 5; ++i)
+      if (i != 0 && i != 2) k.p[i] += K0[i] * r0 + K1[i] * r1;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) k.p[i] += K0[i] * r0 + K1[i] * r1;
+  }
   // columns 0 and 1 of M = (I - K H) C
   T m0[5], m1[5];
 #pragma unroll
@@ -297,10 +362,11 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
             cl.row_start(ur + 1), a, b);
   int32_t best = -1;
   float bchi = 0.0f;
+  const SInv<float> si = s_inverse(k, vy, vz);
   for (uint32_t c = a; c < b; ++c) {
     const float my = (float)cl.y_fx[c] * (float)FX_SCALE;
     const float mz = (float)(cl.z_fx[c] - anchor) * (float)FX_SCALE;
-    const float x2 = chi2_of(k, my, mz, vy, vz);
+    const float x2 = chi2_of(k, my, mz, si);
     if (x2 <= chi2max && (best < 0 || x2 < bchi)) {
       best = (int32_t)c;
       bchi = x2;
@@ -309,7 +375,8 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
   return best;
 }
 
-__global__ __launch_bounds__(64) void k_follow(ClusterView cl, const uint32_t* __restrict__ cblk,
+template <int B>
+__global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __restrict__ cblk,
                                                uint32_t nblk, uint32_t n_ur,
                                                const int32_t* __restrict__ upc,
                                                const uint32_t* __restrict__ tl_start,
@@ -532,7 +599,7 @@ template <typename T>
 __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, const FollowOut& fo,
                          const unsigned long long* owner, const DevParams* P, Trk<T>& k,
                          T& chi2s, int& r_state, int& r, int max_hits, bool& pd,
-                         bool* guard = nullptr) {
+                         bool* guard = nullptr, LoParts<T>* lp = nullptr) {
   const PV<T> pv{P};
   const unsigned long long key = track_key(fo.nhits[t], t);
   const int lo = fo.range[t] & 255;
@@ -541,7 +608,8 @@ __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, cons
   for (; r >= lo && done < max_hits; --r) {
     const int32_t c = H[r];
     if (c < 0 || owner[c] != key) continue;
-    if (r != r_state && !propagate(k, row_dx<T>(P, r_state, r), pv, true, pv.refit_snp_max()))
+    if (r != r_state &&
+        !propagate(k, row_dx<T>(P, r_state, r), pv, true, pv.refit_snp_max(), lp))
       return 1;
     const T my = (T)cl.y_fx[c] * (T)FX_SCALE;
     const T mz = (T)(cl.z_fx[c] - anchor) * (T)FX_SCALE;
@@ -549,7 +617,7 @@ __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, cons
     T d0[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) d0[i] = k.c[PI(i, i)];
-    if (!update_joseph(k, my, mz, pv.vy(r), pv.vz(r), &x2)) return 1;
+    if (!update_joseph(k, my, mz, pv.vy(r), pv.vz(r), &x2, lp)) return 1;
     // cancellation guard: an update that removes more than (1 - fp32_guard)
     // of a variance in one step loses FP32 precision in the covariance
     if (guard) {
@@ -688,6 +756,8 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
     const double* S = hd.state + (size_t)t * 20;
 #pragma unroll
     for (int i = 0; i < 5; ++i) k.p[i] = (float)S[i];
+    // the FP64 head hands over y and sin phi to twice FP32 precision
+    LoParts<float> lo{(float)(S[0] - (double)k.p[0]), (float)(S[2] - (double)k.p[2])};
 #pragma unroll
     for (int i = 0; i < 15; ++i) k.c[i] = (float)S[5 + i];
     float chi2s = (float)hd.chi2[t];
@@ -695,7 +765,9 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
     bool pd = (hd.flags[t] & 2) == 0;
     bool guard = false;
     const int rc = refit_run<float>(t, cl, tl_anchor(cl, tl_start, t), fo, owner, P, k, chi2s,
-                                    rprev, r, NROW, pd, &guard);
+                                    rprev, r, NROW, pd, &guard, &lo);
+    k.p[0] += lo.y;
+    k.p[2] += lo.s;
     if (rc) {
       ro.flags[t] = TF_REFIT_FAIL;
       atomicAdd(&st->n_refit_fail, 1u);

@@ -11,23 +11,18 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "common.hpp"
 #include "k_cluster.hpp"
 #include "k_links.hpp"
 #include "k_track.hpp"
 
-#ifndef TPC_CL_WINDOW
-#define TPC_CL_WINDOW 32
-#endif
-#ifndef TPC_CL_CHUNK
-#define TPC_CL_CHUNK 8
-#endif
-
 namespace {
 
-constexpr uint32_t kWin = TPC_CL_WINDOW;
-constexpr uint32_t kChunk = TPC_CL_CHUNK;
+// Clusterizer tile shapes compiled into the library (window in time bins,
+// windows per workgroup); the smallest product sizes the chunk-count scratch.
+constexpr uint32_t kMinWinChunk = 16 * 4;
 
 struct Geometry {
   int32_t np[NROW], xfx[NROW], pfx[NROW];
@@ -61,7 +56,7 @@ struct tpc_ctx {
   // scratch
   uint32_t* zblk = nullptr;   // sample block index
   uint32_t* cblk = nullptr;   // cluster block index (hit grid)
-  uint32_t* win = nullptr;    // clusterizer window counts / offsets
+  uint32_t* win = nullptr;    // clusterizer chunk counts / offsets
   void* bsum = nullptr;       // scan block sums (u64)
   unsigned long long* tot64 = nullptr;
   uint32_t* tot32 = nullptr;
@@ -83,7 +78,7 @@ struct tpc_ctx {
   uint32_t* trk_index = nullptr;
   uint32_t* hit_off = nullptr;
   size_t bsum_cap = 0;
-  uint32_t nblk_max = 0, nwin_max = 0;
+  tpc_tuning tune;
   // stage timing (measurement only)
   static constexpr int kProfCap = 64;
   bool prof_on = false;
@@ -110,7 +105,7 @@ struct Plan {
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
       h_flags, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
-  uint32_t nblk, nwin;
+  uint32_t nblk, nblk_s, nchunk;
 };
 
 Plan plan_for(const tpc_sizes& m) {
@@ -118,16 +113,17 @@ Plan plan_for(const tpc_sizes& m) {
   Layout L;
   const uint64_t nur = (uint64_t)m.max_units * NROW;
   p.nblk = ceil_div(m.max_time_bins, 8);
-  p.nwin = ceil_div(m.max_time_bins, kWin);
-  uint64_t nscan = nur * p.nwin;
+  p.nblk_s = ceil_div(m.max_time_bins, 1u << CL_BSHIFT);
+  p.nchunk = ceil_div(m.max_time_bins, kMinWinChunk) + 1;
+  uint64_t nscan = nur * p.nchunk;
   if (m.max_clusters > nscan) nscan = m.max_clusters;
   if (m.max_tracklets > nscan) nscan = m.max_tracklets;
   p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
   const uint64_t mc = m.max_clusters > 0 ? m.max_clusters : 1;
   const uint64_t mt = m.max_tracklets > 0 ? m.max_tracklets : 1;
-  p.zblk = L.add<uint32_t>(nur * (p.nblk + 1));
+  p.zblk = L.add<uint32_t>(nur * (p.nblk_s + 1));
   p.cblk = L.add<uint32_t>(nur * (p.nblk + 1));
-  p.win = L.add<uint32_t>(nur * p.nwin);
+  p.win = L.add<uint32_t>(nur * p.nchunk);
   p.bsum = L.add<unsigned long long>(p.bsum_cap);
   p.tot64 = L.add<unsigned long long>(1);
   p.tot32 = L.add<uint32_t>(1);
@@ -333,40 +329,64 @@ int check_tracks(const tpc_tracks* t) {
 }
 
 // ------------------------------------------------------------- stages
+template <int W, int K>
+void launch_cluster(tpc_ctx* c, const ZsArgs& za, uint32_t nblk_s, uint32_t n_ur,
+                    const ClusterOut& co, uint32_t* n_clusters, uint32_t capacity,
+                    uint32_t* crow_start) {
+  constexpr int PRE = W == 16 ? 2 : 3;
+  hipStream_t s = c->stream;
+  const uint32_t nwin = ceil_div(za.n_time_bins, W);
+  const uint32_t nchunk = ceil_div(nwin, K);
+  const uint32_t ngrid = n_ur * nchunk;
+  {
+    StageTimer tm(c, 1);
+    k_cluster_count<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur,
+                                                     c->win, c->d_par, c->d_st);
+  }
+  {
+    StageTimer tm(c, 2);
+    run_scan<uint32_t>(c, GetU32{c->win}, EmitU32{c->win}, nullptr, ngrid, (uint32_t*)nullptr,
+                       n_clusters);
+    k_crow_start<<<grid_for(n_ur + 1, 256), 256, 0, s>>>(c->win, nchunk, n_ur, n_clusters,
+                                                         capacity, crow_start, c->d_st);
+  }
+  {
+    StageTimer tm(c, 3);
+    k_cluster_emit<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur, c->win,
+                                                    co, c->d_par, c->d_st);
+  }
+}
+
 int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
   const uint32_t n_ur = in->n_units * NROW;
-  const uint32_t nblk = ceil_div(in->n_time_bins, 8);
-  const uint32_t nwin = ceil_div(in->n_time_bins, kWin);
+  const uint32_t nblk_s = ceil_div(in->n_time_bins, 1u << CL_BSHIFT);
   hipStream_t s = c->stream;
   {
     StageTimer tm(c, 0);
-    k_block_index<<<n_ur, 256, 0, s>>>(in->time, in->pad, in->row_start, n_ur, nblk,
-                                       in->n_time_bins, in->n_samples, c->zblk, c->d_par, c->d_st, 1);
+    k_block_index<<<n_ur, 256, 0, s>>>(in->time, in->pad, in->row_start, n_ur, nblk_s, CL_BSHIFT,
+                                       in->n_time_bins, in->n_samples, c->zblk, c->d_par, c->d_st,
+                                       1);
   }
   ClusterOut co{out->capacity, out->y_fx, out->z_fx, out->dpad, out->dtime, out->s2pad, out->s2time,
                 out->qtot, out->qmax, out->ppad, out->ptime, out->flags, out->sp, out->st,
                 out->spp, out->stt, out->nsamp, out->sample_label};
   const ZsArgs za = zs_args(in);
-  const uint32_t nwt = n_ur * nwin;
-  const uint32_t nchunk = ceil_div(nwin, kChunk);
-  const uint32_t ngrid = n_ur * nchunk;
-  {
-    StageTimer tm(c, 1);
-    k_cluster_count<kWin, kChunk><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk, nwin, nchunk, n_ur,
-                                                        c->win, c->d_par, c->d_st);
-  }
-  {
-    StageTimer tm(c, 2);
-    run_scan<uint32_t>(c, GetU32{c->win}, EmitU32{c->win}, nullptr, nwt, (uint32_t*)nullptr,
-                       out->n_clusters);
-    k_crow_start<<<grid_for(n_ur + 1, 256), 256, 0, s>>>(c->win, nwin, n_ur, out->n_clusters,
-                                                         out->capacity, out->crow_start, c->d_st);
-  }
-  {
-    StageTimer tm(c, 3);
-    k_cluster_emit<kWin, kChunk><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk, nwin, nchunk, n_ur,
-                                                       c->win, co, c->d_par, c->d_st);
-  }
+  const int w = c->tune.cl_window, k = c->tune.cl_chunk;
+  auto run = [&](auto W, auto K) {
+    launch_cluster<decltype(W)::value, decltype(K)::value>(c, za, nblk_s, n_ur, co, out->n_clusters,
+                                                           out->capacity, out->crow_start);
+  };
+  using I16 = std::integral_constant<int, 16>;
+  using I32 = std::integral_constant<int, 32>;
+  using I4 = std::integral_constant<int, 4>;
+  using I8 = std::integral_constant<int, 8>;
+  using I16k = std::integral_constant<int, 16>;
+  if (w == 16 && k == 4) run(I16{}, I4{});
+  else if (w == 16 && k == 8) run(I16{}, I8{});
+  else if (w == 16 && k == 16) run(I16{}, I16k{});
+  else if (w == 32 && k == 4) run(I32{}, I4{});
+  else if (w == 32 && k == 8) run(I32{}, I8{});
+  else run(I32{}, I16k{});
   if (out->sample_label)
     k_sample_label<<<n_ur, 256, 0, s>>>(za, out->crow_start, out->ppad, out->ptime, n_ur,
                                         out->sample_label, c->d_st);
@@ -377,7 +397,7 @@ int stage_grid(tpc_ctx* c, const tpc_clusters* cl) {
   const uint32_t n_ur = cl->n_units * NROW;
   const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
   StageTimer tm(c, 4);
-  k_block_index<<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk,
+  k_block_index<<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk, 3,
                                              cl->n_time_bins, cl->capacity, c->cblk, c->d_par,
                                              c->d_st, 0);
   return launch_ok();
@@ -423,8 +443,17 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   k_fill<uint32_t><<<1, 64, 0, s>>>(&c->d_st->n_fallback, 0u, 5);
   {
     StageTimer tm(c, 7);
-    k_follow<<<g64, 64, 0, s>>>(cv, c->cblk, nblk, n_ur, l->upc, t->start, t->len,
-                                t->n_tracklets, tcap, fo, c->d_par, c->d_st);
+    const int fb = c->tune.follow_block;
+    const uint32_t gf = grid_for(tcap, fb);
+    if (fb == 256)
+      k_follow<256><<<gf, 256, 0, s>>>(cv, c->cblk, nblk, n_ur, l->upc, t->start, t->len,
+                                       t->n_tracklets, tcap, fo, c->d_par, c->d_st);
+    else if (fb == 128)
+      k_follow<128><<<gf, 128, 0, s>>>(cv, c->cblk, nblk, n_ur, l->upc, t->start, t->len,
+                                       t->n_tracklets, tcap, fo, c->d_par, c->d_st);
+    else
+      k_follow<64><<<gf, 64, 0, s>>>(cv, c->cblk, nblk, n_ur, l->upc, t->start, t->len,
+                                     t->n_tracklets, tcap, fo, c->d_par, c->d_st);
   }
   {
     StageTimer tm(c, 8);
@@ -575,8 +604,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->d_par = (DevParams*)(base + pl.par);
   c->d_st = (DevStatus*)(base + pl.st);
   c->bsum_cap = pl.bsum_cap;
-  c->nblk_max = pl.nblk;
-  c->nwin_max = pl.nwin;
+  tpc_tuning_default(&c->tune);
   const DevParams dp = make_dev_params(*p);
   DevStatus ds;
   std::memset(&ds, 0, sizeof ds);
@@ -706,10 +734,34 @@ int tpc_profile_read(tpc_ctx* c, double* ms, uint32_t* launches) {
 
 const char* tpc_profile_stage_name(int i) {
   static const char* names[TPC_PROF_STAGES] = {
-      "sample_index", "cluster_count", "window_scan", "cluster_emit", "cluster_grid",
+      "sample_index", "cluster_count", "cluster_scan", "cluster_emit", "cluster_grid",
       "neighbours", "tracklets", "following", "resolution", "refit_fp32", "refit_fp64",
       "track_output"};
   return (i >= 0 && i < TPC_PROF_STAGES) ? names[i] : "unknown";
+}
+
+int tpc_tuning_default(tpc_tuning* t) {
+  if (!t) return TPC_ERR_ARG;
+  t->cl_window = 16;
+  t->cl_chunk = 8;
+  t->follow_block = 64;
+  t->reserved = 0;
+  return TPC_OK;
+}
+
+int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
+  if (!c || !t) return TPC_ERR_ARG;
+  if (t->cl_window != 16 && t->cl_window != 32) return TPC_ERR_ARG;
+  if (t->cl_chunk != 4 && t->cl_chunk != 8 && t->cl_chunk != 16) return TPC_ERR_ARG;
+  if (t->follow_block != 64 && t->follow_block != 128 && t->follow_block != 256) return TPC_ERR_ARG;
+  c->tune = *t;
+  return TPC_OK;
+}
+
+int tpc_get_tuning(tpc_ctx* c, tpc_tuning* t) {
+  if (!c || !t) return TPC_ERR_ARG;
+  *t = c->tune;
+  return TPC_OK;
 }
 
 const char* tpc_status_string(int s) {

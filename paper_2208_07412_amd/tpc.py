@@ -77,11 +77,15 @@ class TpcCounts(ctypes.Structure):
                 ("n_fallback_fail", U32), ("n_not_pd", U32), ("n_refit_fail", U32)]
 
 
+class TpcTuning(ctypes.Structure):
+    _fields_ = [("cl_window", I32), ("cl_chunk", I32), ("follow_block", I32), ("reserved", I32)]
+
+
 EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_create",
            "tpc_destroy", "tpc_cluster", "tpc_find_neighbours", "tpc_build_tracklets",
            "tpc_fit_tracks", "tpc_process_timeframe", "tpc_sync", "tpc_stream",
            "tpc_status_string", "tpc_profile_enable", "tpc_profile_read",
-           "tpc_profile_stage_name"]
+           "tpc_profile_stage_name", "tpc_tuning_default", "tpc_set_tuning", "tpc_get_tuning"]
 PROF_STAGES = 12
 
 
@@ -118,6 +122,9 @@ def load():
     lib.tpc_profile_read.argtypes = [P, P, P]
     lib.tpc_profile_stage_name.argtypes = [ctypes.c_int]
     lib.tpc_profile_stage_name.restype = ctypes.c_char_p
+    lib.tpc_tuning_default.argtypes = [P]
+    lib.tpc_set_tuning.argtypes = [P, P]
+    lib.tpc_get_tuning.argtypes = [P, P]
     _lib = lib
     return lib
 
@@ -326,6 +333,21 @@ class Reco:
         _check(self.lib.tpc_process_timeframe(self.ctx, ctypes.byref(s), ctypes.byref(cl.s),
                                               ctypes.byref(links.s), ctypes.byref(tl.s),
                                               ctypes.byref(tr.s)), "tpc_process_timeframe")
+
+    def tuning(self) -> dict:
+        t = TpcTuning()
+        _check(self.lib.tpc_get_tuning(self.ctx, ctypes.byref(t)), "tpc_get_tuning")
+        return {k: getattr(t, k) for k, _ in TpcTuning._fields_ if k != "reserved"}
+
+    def set_tuning(self, **kw):
+        """Change launch shapes (cl_window, cl_chunk, follow_block)."""
+        t = TpcTuning()
+        _check(self.lib.tpc_get_tuning(self.ctx, ctypes.byref(t)), "tpc_get_tuning")
+        for k, v in kw.items():
+            if k not in ("cl_window", "cl_chunk", "follow_block"):
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(self.lib.tpc_set_tuning(self.ctx, ctypes.byref(t)), "tpc_set_tuning")
 
     def profile(self, on: bool = True):
         _check(self.lib.tpc_profile_enable(self.ctx, 1 if on else 0), "tpc_profile_enable")

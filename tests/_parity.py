@@ -24,12 +24,14 @@ PAR_RTOL = 1e-4
 
 
 def run_gpu(ev, params=None, max_tracklets=None, labels=False, moments=True, follow=True,
-            reco=None):
+            reco=None, tuning=None):
     ns = max(ev.n_samples, 1)
     mt = max_tracklets or max(ns // 8, 1024)
     own = reco is None
     if own:
         reco = tpc.Reco(ev.n_units, ev.n_time_bins, ns, mt, param_overrides=params)
+    if tuning:
+        reco.set_tuning(**tuning)
     zs = tpc.to_device_zs(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins)
     cl = reco.alloc_clusters(ev.n_units, ev.n_time_bins, ns, n_samples=ns, moments=moments,
                              labels=labels)

@@ -99,3 +99,14 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(tpc.TpcParams) == 4 * 4 + 3 * 8 + 16 * 8 + 2 * 152 * 8 + 2 * 4
     assert ctypes.sizeof(tpc.TpcCounts) == 11 * 4
     assert "uint32_t capacity;" in src
+
+
+def test_tuning_defaults_and_validation():
+    lib = tpc.load()
+    t = tpc.TpcTuning()
+    assert lib.tpc_tuning_default(ctypes.byref(t)) == 0
+    assert (t.cl_window, t.cl_chunk, t.follow_block) == (16, 8, 64)
+    assert lib.tpc_set_tuning(None, ctypes.byref(t)) == -1
+    assert lib.tpc_get_tuning(None, ctypes.byref(t)) == -1
+    assert lib.tpc_tuning_default(None) == -1
+    assert ctypes.sizeof(tpc.TpcTuning) == 16

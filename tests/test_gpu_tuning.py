@@ -1,0 +1,79 @@
+"""Every launch shape the library offers gives the oracle's results.
+
+Launch shapes (clusterizer window and windows per workgroup, workgroup size
+of the following kernel) only change how work is spread over the GPU, so each
+one is held to the same parity rules as the default: clusters, links,
+tracklets and hit sets bit-exact, parameters within tolerance.  The
+dense-lattice frame gives windows with hundreds of peaks, more than one
+moment batch.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tpcsynth
+
+from _parity import compare_clusters, compare_fit, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+NPADS, _, _ = oracle.geometry()
+SHAPES = [(16, 4, 64), (16, 8, 128), (16, 16, 256), (32, 4, 256), (32, 8, 64), (32, 16, 128)]
+
+
+@pytest.fixture(scope="module")
+def frame():
+    cfg = tpcsynth.EventConfig("pileup", 1000, [tpcsynth.Collision(t, 400, 80) for t in
+                                                (0.0, 150.0, 420.0, 500.0)])
+    ev = tpcsynth.generate(cfg, 61)
+    return ev, run_oracle(ev, labels=True)
+
+
+@pytest.mark.parametrize("w,k,fb", SHAPES)
+def test_shape_parity(frame, w, k, fb):
+    ev, o = frame
+    g = run_gpu(ev, labels=True, tuning=dict(cl_window=w, cl_chunk=k, follow_block=fb))
+    compare_clusters(g["clusters"], o["clusters"], labels=True)
+    assert np.array_equal(g["links"]["down"], o["down"])
+    assert np.array_equal(g["links"]["up"], o["up"])
+    assert np.array_equal(g["tracklets"]["tl_start"], o["tracklets"]["tl_start"])
+    compare_fit(g, o)
+
+
+def _lattice_event(T, step_t, step_p, adc):
+    pad, time, a = [], [], []
+    rows = (0, 40, 151)
+    rs = np.zeros(153, np.uint32)
+    for r in rows:
+        n = 0
+        for t in range(0, T, step_t):
+            for p in range(0, int(NPADS[r]), step_p):
+                time.append(t)
+                pad.append(p)
+                a.append(adc(t, p))
+                n += 1
+        rs[r + 1] = n
+    rs = np.cumsum(rs).astype(np.uint32)
+    cfg = tpcsynth.config_small(0, n_time_bins=T)
+    return tpcsynth.Event(cfg, np.array(pad, np.uint16), np.array(time, np.uint16),
+                          np.array(a, np.uint16), rs, 1, T, {}, {}, None)
+
+
+@pytest.mark.parametrize("w,k", [(16, 8), (32, 4)])
+def test_most_peaks_per_window(w, k):
+    # isolated samples on every other pad and bin: each one is a peak, so a
+    # window holds far more peaks than one moment batch
+    ev = _lattice_event(100, 2, 2, lambda t, p: 5 + (t * 7 + p * 3) % 900)
+    g = run_gpu(ev, labels=True, max_tracklets=64, tuning=dict(cl_window=w, cl_chunk=k))
+    o = run_oracle(ev, labels=True)
+    assert len(o["clusters"]["y_fx"]) == ev.n_samples
+    compare_clusters(g["clusters"], o["clusters"], labels=True)
+
+
+@pytest.mark.parametrize("w,k", [(16, 8), (32, 16)])
+def test_fully_occupied_rows(w, k):
+    # every (time, pad) present: the densest input a row can have
+    ev = _lattice_event(120, 1, 1, lambda t, p: 3 + ((t * 131 + p * 71) * 2654435761 % 2**32) % 400)
+    g = run_gpu(ev, labels=True, max_tracklets=64, tuning=dict(cl_window=w, cl_chunk=k))
+    o = run_oracle(ev, labels=True)
+    compare_clusters(g["clusters"], o["clusters"], labels=True)

@@ -1,0 +1,123 @@
+"""Host logic of the serving loop, driven by a simulated device: admission in
+arrival order by free slot and HBM budget, continuous admission (a waiting
+chunk starts as soon as a slot and memory free up, not when a batch ends),
+reruns after a reported capacity overflow, and latency bookkeeping."""
+import numpy as np
+import pytest
+
+from paper_2208_07412_amd import serve
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+class FakeDevice:
+    """Each chunk takes `dur[id]` seconds; chunks in `overflow` report a
+    capacity overflow on their first run."""
+
+    def __init__(self, clock, dur, overflow=()):
+        self.clock = clock
+        self.dur = dur
+        self.overflow = set(overflow)
+        self.end = {}
+        self.log = []
+
+    def launch(self, slot, job):
+        self.end[slot] = self.clock() + self.dur[job.id]
+        self.log.append(("start", job.id, slot, self.clock()))
+
+    def done(self, slot):
+        return self.clock() >= self.end[slot]
+
+    def finish(self, slot, job):
+        self.log.append(("end", job.id, slot, self.clock()))
+        if job.id in self.overflow and job.retries == 0:
+            job.cl_cap *= 2
+            return True
+        return False
+
+
+def _jobs(n, cl=1000, tl=100):
+    return [serve.Job(i, None, 1, 500, 0, cl_cap=cl, tl_cap=tl) for i in range(n)]
+
+
+def test_fifo_slots_and_latency():
+    clk = Clock()
+    n = 40
+    rng = np.random.default_rng(1)
+    dev = FakeDevice(clk, {i: float(rng.uniform(0.01, 0.05)) for i in range(n)})
+    sch = serve.Scheduler(dev, n_slots=3, budget_bytes=10**12)
+    arr = serve.poisson_arrivals(n, 80.0, seed=2)
+    jobs = _jobs(n)
+    done = serve.run_stream(sch, jobs, arr, clock=clk, poll_s=1e-4, sleep=clk.sleep)
+    assert len(done) == n and sch.idle
+    assert sch.max_concurrent <= 3
+    starts = [e[1] for e in dev.log if e[0] == "start"]
+    assert starts == sorted(starts)  # admitted in arrival order
+    for j in jobs:
+        assert j.start >= j.arrival - 1e-12
+        assert j.latency >= dev.dur[j.id] - 1e-9
+    st = serve.latency_stats(jobs)
+    assert st["p50_ms"] <= st["p99_ms"]
+
+
+def test_continuous_admission_fills_freed_slots():
+    # two slots, chunk 0 long and chunk 1 short: chunk 2 (waiting) must start
+    # when chunk 1 ends, while chunk 0 is still running
+    clk = Clock()
+    dev = FakeDevice(clk, {0: 1.0, 1: 0.1, 2: 0.1, 3: 0.1})
+    sch = serve.Scheduler(dev, n_slots=2, budget_bytes=10**12)
+    jobs = _jobs(4)
+    serve.run_stream(sch, jobs, np.zeros(4), clock=clk, poll_s=1e-3, sleep=clk.sleep)
+    assert jobs[2].start == pytest.approx(0.1, abs=2e-3)
+    assert jobs[3].start == pytest.approx(0.2, abs=3e-3)
+    assert jobs[0].done == pytest.approx(1.0, abs=2e-3)
+
+
+def test_memory_budget_limits_admission():
+    clk = Clock()
+    dev = FakeDevice(clk, {i: 0.05 for i in range(6)})
+    per = serve.job_bytes(_jobs(1)[0])
+    sch = serve.Scheduler(dev, n_slots=4, budget_bytes=2 * per + 1)
+    jobs = _jobs(6)
+    serve.run_stream(sch, jobs, np.zeros(6), clock=clk, poll_s=1e-3, sleep=clk.sleep)
+    assert sch.peak_in_use <= sch.budget
+    assert sch.max_concurrent == 2  # memory, not slots, was the limit
+
+
+def test_oversized_chunk_is_rejected_not_hung():
+    clk = Clock()
+    dev = FakeDevice(clk, {0: 0.01, 1: 0.01})
+    jobs = _jobs(2)
+    jobs[1].cl_cap = 10**9
+    sch = serve.Scheduler(dev, n_slots=2, budget_bytes=serve.job_bytes(jobs[0]) * 2)
+    done = serve.run_stream(sch, jobs, np.zeros(2), clock=clk, poll_s=1e-3, sleep=clk.sleep)
+    assert len(done) == 2
+    assert jobs[1].error is not None and jobs[0].error is None
+
+
+def test_capacity_overflow_reruns_first():
+    clk = Clock()
+    dev = FakeDevice(clk, {i: 0.02 for i in range(5)}, overflow={1})
+    sch = serve.Scheduler(dev, n_slots=1, budget_bytes=10**12)
+    jobs = _jobs(5)
+    serve.run_stream(sch, jobs, np.zeros(5), clock=clk, poll_s=1e-3, sleep=clk.sleep)
+    assert jobs[1].retries == 1 and jobs[1].cl_cap == 2000
+    starts = [e[1] for e in dev.log if e[0] == "start"]
+    assert starts == [0, 1, 1, 2, 3, 4]  # the rerun goes ahead of later arrivals
+
+
+def test_estimates_and_arrivals():
+    cl, tl = serve.estimate_caps(10**6)
+    assert cl >= 10**6 // 6 and tl >= cl // 12
+    a = serve.poisson_arrivals(20000, 50.0, seed=3)
+    gaps = np.diff(np.concatenate([[0.0], a]))
+    assert abs(gaps.mean() - 0.02) < 0.001 and np.all(gaps > 0)
