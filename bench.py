@@ -54,21 +54,21 @@ def stage_bytes(ns, nc, n_ur, T):
     }
 
 
-def pmc_traffic(kernel_file, stage):
+def pmc_traffic(kernel_file, stage, kernel_name):
     """HBM bytes per launch of a stage's kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known
     size), or None when the kernel source changed since the counters were
-    taken or no summary exists."""
+    taken, the summary is for another launch shape, or none exists."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"pmc_{stage}.md")
+    path = os.path.join(ROOT, "profiles", f"pmc_{stage}_c3_slice.md")
     if not os.path.exists(path):
         return None
     rec = None
     for line in open(path):
         if line.startswith("traffic_json: "):
             rec = json.loads(line[len("traffic_json: "):])
-    if rec is None:
+    if rec is None or not rec.get("kernel", "").startswith(kernel_name):
         return None
     h = hashlib.sha256(open(os.path.join(ROOT, kernel_file), "rb").read()).hexdigest()
     return rec["bytes_per_launch"] if rec.get("source_sha256") == h else None
@@ -321,7 +321,9 @@ def main():
     dom = max(stages, key=lambda k: stages[k])
     hbm_dom = max(sb, key=lambda k: stages.get(k, 0.0))
     ach = sb[hbm_dom] / (stages[hbm_dom] / 1e3) / 1e9
-    traffic = pmc_traffic("paper_2208_07412_amd/csrc/k_cluster.hpp", hbm_dom) \
+    tn = tuning["chosen"] if tuning else {"cl_window": 16, "cl_chunk": 8}
+    kname = f"void k_{hbm_dom}<{tn['cl_window']}, {tn['cl_chunk']},"
+    traffic = pmc_traffic("paper_2208_07412_amd/csrc/k_cluster.hpp", hbm_dom, kname) \
         if hbm_dom.startswith("cluster_") else None
     roofline = dict(bound="hbm", kernel=hbm_dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS, traffic=traffic, bytes_per_launch=sb[hbm_dom],

@@ -37,7 +37,16 @@ def _time(reco, run, names, reps: int) -> float:
     return _stage_ms(prof, names)
 
 
-def autotune(reco, run, reps: int = 3) -> dict:
+def _pick(times: Dict[str, float], keep: str, margin: float) -> str:
+    """Fastest candidate, but the current one stays unless beaten by more
+    than `margin` (timings within noise should not flip the choice)."""
+    best = min(times, key=times.get)
+    if keep in times and times[best] > (1.0 - margin) * times[keep]:
+        return keep
+    return best
+
+
+def autotune(reco, run, reps: int = 3, margin: float = 0.02) -> dict:
     """run() enqueues one full reconstruction on reco's stream.  Leaves the
     fastest shapes set on reco and returns them with every timing (ms)."""
     start = reco.tuning()
@@ -45,13 +54,13 @@ def autotune(reco, run, reps: int = 3) -> dict:
     for w, k in CLUSTER_SHAPES:
         reco.set_tuning(cl_window=w, cl_chunk=k)
         res["cluster"][f"{w}x{k}"] = _time(reco, run, CLUSTER_STAGES, reps)
-    best_c = min(res["cluster"], key=res["cluster"].get)
+    best_c = _pick(res["cluster"], f"{start['cl_window']}x{start['cl_chunk']}", margin)
     w, k = (int(x) for x in best_c.split("x"))
     reco.set_tuning(cl_window=w, cl_chunk=k)
     for fb in FOLLOW_BLOCKS:
         reco.set_tuning(follow_block=fb)
         res["follow"][str(fb)] = _time(reco, run, FOLLOW_STAGES, reps)
-    best_f = int(min(res["follow"], key=res["follow"].get))
+    best_f = int(_pick(res["follow"], str(start["follow_block"]), margin))
     reco.set_tuning(follow_block=best_f)
     res["chosen"] = reco.tuning()
     res["start"] = start

@@ -40,7 +40,21 @@ struct ClusterOut {
 // Offsets of the samples (or clusters) of each (unit,row) per block of
 // 2^bshift time bins: blk[ur*(nblk+1) + b] = first index with key time >=
 // b << bshift; the entry at nblk is the row end.  One workgroup per
-// (unit,row); rows are time-sorted.
+// (unit,row); rows are time-sorted.  Each thread takes 8 consecutive keys
+// per step (one 16-byte load when the key array is 16-byte aligned; the
+// aligned block never crosses a page, and keys outside the row are masked).
+__device__ __forceinline__ void bi_sample(uint32_t s, uint32_t t, int32_t prev, uint32_t s1,
+                                          uint32_t nblk, uint32_t bshift, uint32_t* b,
+                                          DevStatus* st) {
+  const int32_t cur = (int32_t)(t >> bshift);
+  for (int32_t k = prev + 1; k <= cur; ++k) b[k] = s;
+  if (s == s1 - 1)
+    for (uint32_t k = cur + 1; k <= nblk; ++k) b[k] = s1;
+  // a time-unsorted row leaves some entries stale; readers clamp every
+  // range to the row, so this is reported but never read out of bounds
+  if (cur < prev) latch(st, TPC_ERR_INPUT);
+}
+
 __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict__ tkey,
                                                      const uint16_t* __restrict__ pkey,
                                                      const uint32_t* __restrict__ rstart,
@@ -50,6 +64,7 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
                                                      const DevParams* __restrict__ P,
                                                      DevStatus* st, int check_input) {
   if (failed(st)) return;
+  const bool vec = ((uintptr_t)tkey & 15) == 0 && (!check_input || ((uintptr_t)pkey & 15) == 0);
   for (uint32_t ur = blockIdx.x; ur < n_ur; ur += gridDim.x) {
     uint32_t s0 = rstart[ur], s1 = rstart[ur + 1];
     if (s1 > n_total) s1 = n_total;
@@ -60,34 +75,54 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
       continue;
     }
     const int np = P->np[ur % NROW];
-    for (uint32_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-      uint32_t t = tkey[s];
-      if (t >= T) {
-        latch(st, TPC_ERR_INPUT);
-        t = T - 1;
-      }
-      const uint32_t cur = t >> bshift;
-      int32_t prev = -1;
-      if (s > s0) {
-        uint32_t tp = tkey[s - 1];
-        if (tp >= T) tp = T - 1;
-        prev = (int32_t)(tp >> bshift);
-      }
-      for (int32_t k = prev + 1; k <= (int32_t)cur; ++k) b[k] = s;
-      if (s == s1 - 1)
-        for (uint32_t k = cur + 1; k <= nblk; ++k) b[k] = s1;
-      if (check_input) {
-        const uint32_t p = pkey[s];
-        if ((int)p >= np) latch(st, TPC_ERR_INPUT);
-        if (P->validate && s > s0) {
-          const uint32_t k0 = ((uint32_t)tkey[s - 1] << 8) | pkey[s - 1];
-          const uint32_t k1 = (t << 8) | p;
-          if (k1 <= k0) latch(st, TPC_ERR_INPUT);
+    const bool validate = check_input && P->validate;
+    for (uint32_t g = (s0 >> 3) + threadIdx.x; g < ((s1 + 7) >> 3); g += blockDim.x) {
+      const uint32_t base = g << 3;
+      uint16_t tv[8], pv[8];
+      if (vec) {
+        const uint4 tq = *reinterpret_cast<const uint4*>(tkey + base);
+        const uint32_t tw[4] = {tq.x, tq.y, tq.z, tq.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tv[e] = (uint16_t)(tw[e >> 1] >> ((e & 1) * 16));
+        if (check_input) {
+          const uint4 pq = *reinterpret_cast<const uint4*>(pkey + base);
+          const uint32_t pw[4] = {pq.x, pq.y, pq.z, pq.w};
+#pragma unroll
+          for (int e = 0; e < 8; ++e) pv[e] = (uint16_t)(pw[e >> 1] >> ((e & 1) * 16));
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t s = base + e;
+          tv[e] = (s >= s0 && s < s1) ? tkey[s] : 0;
+          pv[e] = (check_input && s >= s0 && s < s1) ? pkey[s] : 0;
         }
       }
-      // a time-unsorted row leaves some entries stale; readers clamp every
-      // range to the row, so this is reported but never read out of bounds
-      if ((int32_t)cur < prev) latch(st, TPC_ERR_INPUT);
+      // key before this group (inside the row)
+      uint32_t tp = (base > s0) ? (uint32_t)tkey[base - 1] : 0;
+      uint32_t pp = (validate && base > s0) ? (uint32_t)pkey[base - 1] : 0;
+      if (tp >= T) tp = T - 1;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t s = base + e;
+        uint32_t t = tv[e];
+        const uint32_t p = pv[e];
+        if (s >= s0 && s < s1) {
+          const uint32_t traw = t;
+          if (t >= T) {
+            latch(st, TPC_ERR_INPUT);
+            t = T - 1;
+          }
+          bi_sample(s, t, s > s0 ? (int32_t)(tp >> bshift) : -1, s1, nblk, bshift, b, st);
+          if (check_input) {
+            if ((int)p >= np) latch(st, TPC_ERR_INPUT);
+            if (validate && s > s0 && ((traw << 8) | p) <= ((tp << 8) | pp))
+              latch(st, TPC_ERR_INPUT);
+          }
+          tp = t;
+          pp = p;
+        }
+      }
     }
   }
 }
@@ -214,34 +249,43 @@ __device__ __forceinline__ void scatter(uint16_t* tile, const ZsArgs& in, const 
   }
 }
 
+// ADC of the cells c-1, c, c+1 of one tile row (bits 0-9 of three 16-bit
+// fields): two aligned 32-bit LDS reads cover them whatever the parity of c.
+struct Row3 {
+  int l, m, r;
+};
+__device__ __forceinline__ Row3 row3(const uint16_t* tile, int c) {
+  const uint32_t* t32 = reinterpret_cast<const uint32_t*>(tile);
+  const int w = (c - 1) >> 1;
+  const uint64_t v = ((uint64_t)t32[w + 1] << 32 | t32[w]) >> (((c - 1) & 1) * 16);
+  return Row3{(int)(v & 0x3FF), (int)((v >> 16) & 0x3FF), (int)((v >> 32) & 0x3FF)};
+}
+
 // up code (bits 0-3) and peak flag (bit 4) of the sample in cell c
 __device__ __forceinline__ int up_code_of(const uint16_t* tile, int c, int qmin) {
-  const int a = tile[c] & 0x3FF;
+  const Row3 u = row3(tile, c - CL_TP), m = row3(tile, c), d = row3(tile, c + CL_TP);
+  const int a = m.m;
+  const int an[9] = {u.l, u.m, u.r, m.l, 0, m.r, d.l, d.m, d.r};
   int best = a * 16 + 4, code = 4;
 #pragma unroll
-  for (int dt = -1; dt <= 1; ++dt)
-#pragma unroll
-    for (int dp = -1; dp <= 1; ++dp) {
-      if (dt == 0 && dp == 0) continue;
-      const int an = tile[c + dt * CL_TP + dp] & 0x3FF;
-      const int idx = (dt + 1) * 3 + (dp + 1);
-      const int k = an * 16 + idx;
-      if (an != 0 && k > best) {
-        best = k;
-        code = idx;
-      }
+  for (int idx = 0; idx < 9; ++idx) {
+    if (idx == 4) continue;
+    const int k = an[idx] * 16 + idx;
+    if (an[idx] != 0 && k > best) {
+      best = k;
+      code = idx;
     }
+  }
   return code | ((code == 4 && a >= qmin) ? 16 : 0);
 }
 
 // The peak test alone: the sample's key beats its 8 neighbours (earlier
 // neighbours may tie on ADC, later ones may not) and its ADC reaches qmin.
 __device__ __forceinline__ bool is_peak(const uint16_t* tile, int c, int qmin) {
-  const int a = tile[c] & 0x3FF;
-  const int e = max(max(tile[c - CL_TP - 1] & 0x3FF, tile[c - CL_TP] & 0x3FF),
-                    max(tile[c - CL_TP + 1] & 0x3FF, tile[c - 1] & 0x3FF));
-  const int l = max(max(tile[c + 1] & 0x3FF, tile[c + CL_TP - 1] & 0x3FF),
-                    max(tile[c + CL_TP] & 0x3FF, tile[c + CL_TP + 1] & 0x3FF));
+  const Row3 u = row3(tile, c - CL_TP), m = row3(tile, c), d = row3(tile, c + CL_TP);
+  const int a = m.m;
+  const int e = max(max(u.l, u.m), max(u.r, m.l));
+  const int l = max(max(m.r, d.l), max(d.m, d.r));
   return a >= qmin && e <= a && l < a;
 }
 

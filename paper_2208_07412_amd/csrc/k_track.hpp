@@ -7,6 +7,8 @@
 // the exact helix in a uniform Bz field (no material, no process noise).
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "k_cluster.hpp"
 #include "k_links.hpp"
@@ -149,18 +151,48 @@ __device__ __forceinline__ bool propagate(Trk<T>& k, T dx, const PV<T>& pv, bool
   T slo = lo ? lo->s : (T)0;
   const T s2 = lo ? two_sum_acc(s1, C * dx, &slo) : s1 + C * dx;
   if (!(fabs(s2) < snp_lim)) return false;
-  const T c1 = sqrt((T)1 - s1 * s1), c2 = sqrt((T)1 - s2 * s2);
-  const T D = c1 + c2, N = s1 + s2, f = N / D;
-  const T chord = fabs(dx) * sqrt((T)1 + f * f);
-  T h = chord * fabs(C) * (T)0.5;
-  if (h > (T)1) h = (T)1;
-  const T L = h > (T)0 ? chord * asin(h) / h : chord;
+  T c1, c2, ic1, ic2, iD, f, chord, L;
+  const T N = s1 + s2;
+  if constexpr (std::is_same<T, float>::value) {
+    // FP32: hardware reciprocal and reciprocal square root (about 1 ulp)
+    // instead of correctly rounded division and square root, and the series
+    // of asin(h)/h for the small turning angles of one row step
+    ic1 = __builtin_amdgcn_rsqf(1.0f - s1 * s1);
+    ic2 = __builtin_amdgcn_rsqf(1.0f - s2 * s2);
+    c1 = (1.0f - s1 * s1) * ic1;
+    c2 = (1.0f - s2 * s2) * ic2;
+    iD = __builtin_amdgcn_rcpf(c1 + c2);
+    f = N * iD;
+    const float q = 1.0f + f * f;
+    chord = fabsf(dx) * (q * __builtin_amdgcn_rsqf(q));
+    float h = chord * fabsf(C) * 0.5f;
+    if (h > 1.0f) h = 1.0f;
+    if (h < 0.1f) {
+      const float h2 = h * h;
+      L = chord * (1.0f + h2 * (1.0f / 6.0f + h2 * (3.0f / 40.0f + h2 * (5.0f / 112.0f +
+                                                                         h2 * (35.0f / 1152.0f)))));
+    } else {
+      L = chord * asinf(h) / h;
+    }
+  } else {
+    c1 = sqrt((T)1 - s1 * s1);
+    c2 = sqrt((T)1 - s2 * s2);
+    ic1 = (T)1 / c1;
+    ic2 = (T)1 / c2;
+    iD = (T)1 / (c1 + c2);
+    f = N * iD;
+    chord = fabs(dx) * sqrt((T)1 + f * f);
+    T h = chord * fabs(C) * (T)0.5;
+    if (h > (T)1) h = (T)1;
+    L = h > (T)0 ? chord * asin(h) / h : chord;
+  }
+  const T D = c1 + c2;
   const T A = dx >= (T)0 ? L : -L;
   if (with_cov) {
-    const T D2 = D * D;
-    const T j02 = dx * ((T)2 * D + N * (s1 / c1 + s2 / c2)) / D2;
-    const T j04 = -b * dx * dx * (D + N * s2 / c2) / D2;
-    const T j12 = k.p[3] * dx * N / (c1 * c2 * D);
+    const T iD2 = iD * iD;
+    const T j02 = dx * ((T)2 * D + N * (s1 * ic1 + s2 * ic2)) * iD2;
+    const T j04 = -b * dx * dx * (D + N * s2 * ic2) * iD2;
+    const T j12 = k.p[3] * dx * N * (ic1 * ic2 * iD);
     const T j13 = A;
     const T j14 = -b * k.p[3] * darc_dc(s1, C, dx);
     const T j24 = -b * dx;
@@ -303,12 +335,13 @@ __device__ __forceinline__ bool is_pd(const T* c) {
     for (int m = 0; m < j; ++m) d -= L[j][m] * L[j][m] * D[m];
     if (!(d > (T)0)) return false;
     D[j] = d;
+    const T id = (T)1 / d;
 #pragma unroll
     for (int i = j + 1; i < 5; ++i) {
       T a = c[PI(j, i)];
 #pragma unroll
       for (int m = 0; m < j; ++m) a -= L[i][m] * L[j][m] * D[m];
-      L[i][j] = a / d;
+      L[i][j] = a * id;
     }
   }
   return true;
@@ -375,156 +408,230 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
   return best;
 }
 
+// Middle and end cluster of every tracklet (walk of its cleaned up-links) and
+// the unit-row of its start; 0xFFFFFFFF marks a tracklet that cannot be
+// followed (broken chain or rows beyond the last).
+__global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_t n_ur,
+                                                         const int32_t* __restrict__ upc,
+                                                         const uint32_t* __restrict__ tl_start,
+                                                         const uint16_t* __restrict__ tl_len,
+                                                         const uint32_t* n_tl_dev, uint32_t tl_cap,
+                                                         uint32_t* __restrict__ pts,
+                                                         const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  const uint32_t n_cl = scan_count(cl.n_clusters, cl.capacity);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+    const uint32_t A = tl_start[t];
+    const int L = tl_len[t];
+    uint32_t M = 0xFFFFFFFFu, E = 0xFFFFFFFFu, urA = 0;
+    if (A < n_cl && L >= 3) {
+      urA = cluster_ur(cl.crow, n_ur, A);
+      if ((int)(urA % NROW) + L <= NROW) {
+        const int im = (L + 1) / 2 - 1;
+        uint32_t c = A, m = A;
+        bool bad = false;
+        for (int i = 1; i < L; ++i) {
+          const int32_t nx = upc[c];
+          if (nx < 0 || (uint32_t)nx >= n_cl) {
+            bad = true;
+            break;
+          }
+          c = (uint32_t)nx;
+          if (i == im) m = c;
+        }
+        if (!bad) {
+          M = m;
+          E = c;
+        }
+      }
+    }
+    pts[(size_t)t * 3 + 0] = M;
+    pts[(size_t)t * 3 + 1] = E;
+    pts[(size_t)t * 3 + 2] = urA;
+  }
+}
+
+// Following of one tracklet per lane: seed and first update, pass A outward
+// row by row, pass B inward from the outermost pass-A hit, result.
+enum { FS_A = 1, FS_B = 2 };
+
+struct FollowLane {
+  Trk<float> k;   // state at row r
+  float sp[5];    // state after the last update (pass A, then pass B)
+  uint32_t t;
+  int32_t anchor, ctl;
+  uint32_t ubase;
+  int r, r1, L, nmiss, nh, hi, lo, rs, phase;  // rs: row of sp
+};
+
+// Seed and first update of tracklet t; false if it cannot be followed.
+__device__ __forceinline__ bool follow_init(FollowLane& f, uint32_t t, const ClusterView& cl,
+                                            const uint32_t* tl_start, const uint16_t* tl_len,
+                                            const uint32_t* pts, FollowOut& fo,
+                                            const DevParams* P, const PV<float>& pv) {
+  fo.ok[t] = 0;
+  fo.nhits[t] = 0;
+  fo.range[t] = 0;
+  const uint32_t M = pts[(size_t)t * 3 + 0], E = pts[(size_t)t * 3 + 1];
+  if (M == 0xFFFFFFFFu) return false;
+  const uint32_t urA = pts[(size_t)t * 3 + 2];
+  const uint32_t A = tl_start[t];
+  const int L = tl_len[t];
+  const int r1 = urA % NROW;
+  f.t = t;
+  f.L = L;
+  f.r1 = r1;
+  f.ubase = urA - r1;
+  const int im = (L + 1) / 2 - 1;
+  const int rM = r1 + im, rE = r1 + L - 1;
+  const int32_t anchor = cl.z_fx[A];
+  f.anchor = anchor;
+  // ---- seed: circle through A, M, E; differences are exact integers
+  const int64_t dxm = P->xfx[rM] - P->xfx[r1], dym = (int64_t)cl.y_fx[M] - cl.y_fx[A];
+  const int64_t dxe = P->xfx[rE] - P->xfx[r1], dye = (int64_t)cl.y_fx[E] - cl.y_fx[A];
+  const int64_t dxx = P->xfx[rE] - P->xfx[rM], dyy = (int64_t)cl.y_fx[E] - cl.y_fx[M];
+  const float cross = (float)(dxm * dye - dym * dxe) * (float)(FX_SCALE * FX_SCALE);
+  const float fma_ = hypotf((float)dxm, (float)dym) * (float)FX_SCALE;
+  const float fea = hypotf((float)dxe, (float)dye) * (float)FX_SCALE;
+  const float fem = hypotf((float)dxx, (float)dyy) * (float)FX_SCALE;
+  const float b = pv.b();
+  float C = 2.0f * cross / (fma_ * fem * fea);
+  float qpt = -C / b;
+  qpt = fminf(fmaxf(qpt, -pv.qpt_clamp()), pv.qpt_clamp());
+  C = -b * qpt;
+  const float sarg = fminf(fmaxf(fea * C * 0.5f, -1.0f), 1.0f);
+  const float phiA = atan2f((float)dye, (float)dxe) - asinf(sarg);
+  const float h = fea * fabsf(C) * 0.5f;
+  const float arc = h > 0.0f ? fea * asinf(fminf(h, 1.0f)) / h : fea;
+  Trk<float>& k = f.k;
+  k.p[0] = (float)cl.y_fx[A] * (float)FX_SCALE;
+  k.p[1] = 0.0f;
+  k.p[2] = sinf(phiA);
+  k.p[3] = (float)(cl.z_fx[E] - anchor) * (float)FX_SCALE / arc;
+  k.p[4] = qpt;
+  if (!(fabsf(k.p[2]) < pv.snp_max())) return false;
+  c0_reset(k, pv, r1);
+  if (!update(k, k.p[0], 0.0f, pv.vy(r1), pv.vz(r1), (float*)nullptr)) return false;
+  fo.hits[(size_t)t * NROW + r1] = (int32_t)A;
+  f.nh = 1;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) f.sp[i] = k.p[i];
+  f.rs = r1;
+  f.nmiss = 0;
+  f.hi = r1;
+  f.ctl = (int32_t)A;
+  f.r = r1;
+  return true;
+}
+
+// Pass B start: the outermost pass-A hit (row rs) with a reset covariance;
+// false if its update fails (the tracklet then ends with the pass-A state).
+__device__ __forceinline__ bool follow_start_b(FollowLane& f, const ClusterView& cl,
+                                               const FollowOut& fo, const PV<float>& pv) {
+  Trk<float>& k = f.k;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) k.p[i] = f.sp[i];
+  c0_reset(k, pv, f.rs);
+  f.lo = f.r1;
+  const int32_t co = fo.hits[(size_t)f.t * NROW + f.rs];
+  const float my = (float)cl.y_fx[co] * (float)FX_SCALE;
+  const float mz = (float)(cl.z_fx[co] - f.anchor) * (float)FX_SCALE;
+  if (!update(k, my, mz, pv.vy(f.rs), pv.vz(f.rs), (float*)nullptr)) return false;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) f.sp[i] = k.p[i];
+  f.nmiss = 0;
+  f.r = f.rs;
+  return true;
+}
+
+__device__ __forceinline__ void follow_finish(const FollowLane& f, FollowOut& fo) {
+  float* S = fo.state + (size_t)f.t * 6;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) S[i] = f.sp[i];
+  S[5] = (float)f.rs;
+  fo.nhits[f.t] = (uint16_t)f.nh;
+  fo.range[f.t] = (uint16_t)(f.lo | (f.hi << 8));
+  fo.ok[f.t] = 1;
+}
+
+// One row of pass A (outward) or pass B (inward) for a lane in FS_A / FS_B.
+// Returns true when the pass has ended.
+__device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl,
+                                            const uint32_t* cblk, uint32_t nblk,
+                                            const int32_t* upc, FollowOut& fo, const DevParams* P,
+                                            const PV<float>& pv, float chi2max) {
+  const bool pa = f.phase == FS_A;
+  const int rn = f.r + (pa ? 1 : -1);
+  if (rn >= NROW || rn < 0) return true;
+  Trk<float>& k = f.k;
+  if (!propagate(k, row_dx<float>(P, f.r, rn), pv, true, pv.snp_max())) return true;
+  int32_t* H = fo.hits + (size_t)f.t * NROW;
+  int32_t cand = -1;
+  bool fresh = false;
+  if (pa && rn < f.r1 + f.L) {
+    f.ctl = upc[f.ctl];
+    cand = f.ctl;
+  } else {
+    if (!pa && rn >= f.r1) cand = H[rn];
+    if (cand < 0) {
+      if (fabsf(k.p[0]) > pv.hw(rn) + pv.edge_margin()) return true;
+      cand = search_row(cl, cblk, nblk, f.ubase + rn, k, f.anchor, pv.vy(rn), pv.vz(rn), chi2max);
+      fresh = true;
+    }
+  }
+  f.r = rn;
+  if (pa) {
+    f.hi = rn;
+    H[rn] = -1;
+  } else if (fresh && rn < f.lo) {
+    f.lo = rn;
+    H[rn] = -1;
+  }
+  if (cand < 0) {
+    if ((pa || rn < f.r1) && ++f.nmiss >= P->max_miss) return true;
+    return false;
+  }
+  const float my = (float)cl.y_fx[cand] * (float)FX_SCALE;
+  const float mz = (float)(cl.z_fx[cand] - f.anchor) * (float)FX_SCALE;
+  if (!update(k, my, mz, pv.vy(rn), pv.vz(rn), (float*)nullptr)) return true;
+  if (pa || fresh) {
+    H[rn] = cand;
+    ++f.nh;
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) f.sp[i] = k.p[i];
+  f.rs = rn;
+  f.nmiss = 0;
+  return false;
+}
+
 template <int B>
 __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __restrict__ cblk,
-                                               uint32_t nblk, uint32_t n_ur,
-                                               const int32_t* __restrict__ upc,
+                                               uint32_t nblk, const int32_t* __restrict__ upc,
                                                const uint32_t* __restrict__ tl_start,
                                                const uint16_t* __restrict__ tl_len,
+                                               const uint32_t* __restrict__ pts,
                                                const uint32_t* n_tl_dev, uint32_t tl_cap,
                                                FollowOut fo, const DevParams* __restrict__ P,
-                                               const DevStatus* st) {
+                                               DevStatus* st) {
   if (failed(st)) return;
   const PV<float> pv{P};
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  const uint32_t n_cl = scan_count(cl.n_clusters, cl.capacity);
   const float chi2max = pv.chi2_max();
+  // consecutive tracklets (same start row, nearby times) share a wave
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
-    fo.ok[t] = 0;
-    fo.nhits[t] = 0;
-    fo.range[t] = 0;
-    const uint32_t A = tl_start[t];
-    const int L = tl_len[t];
-    if (A >= n_cl || L < 3) continue;
-    const uint32_t urA = cluster_ur(cl.crow, n_ur, A);
-    const int r1 = urA % NROW;
-    const uint32_t ubase = urA - r1;
-    if (r1 + L > NROW) continue;
-    int32_t* H = fo.hits + (size_t)t * NROW;
-    // middle and end of the tracklet
-    uint32_t M = A, E = A, c = A;
-    const int im = (L + 1) / 2 - 1;
-    bool bad = false;
-    for (int i = 1; i < L; ++i) {
-      const int32_t nx = upc[c];
-      if (nx < 0 || (uint32_t)nx >= n_cl) {
-        bad = true;
-        break;
-      }
-      c = (uint32_t)nx;
-      if (i == im) M = c;
-      E = c;
+    FollowLane f;
+    if (!follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) continue;
+    f.phase = FS_A;
+    while (!follow_step(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
     }
-    if (bad) continue;
-    const int rM = r1 + im, rE = r1 + L - 1;
-    const int32_t anchor = cl.z_fx[A];
-    // ---- seed: circle through A, M, E; differences are exact integers
-    const int64_t dxm = P->xfx[rM] - P->xfx[r1], dym = (int64_t)cl.y_fx[M] - cl.y_fx[A];
-    const int64_t dxe = P->xfx[rE] - P->xfx[r1], dye = (int64_t)cl.y_fx[E] - cl.y_fx[A];
-    const int64_t dxx = P->xfx[rE] - P->xfx[rM], dyy = (int64_t)cl.y_fx[E] - cl.y_fx[M];
-    const float cross = (float)(dxm * dye - dym * dxe) * (float)(FX_SCALE * FX_SCALE);
-    const float fma_ = hypotf((float)dxm, (float)dym) * (float)FX_SCALE;
-    const float fea = hypotf((float)dxe, (float)dye) * (float)FX_SCALE;
-    const float fem = hypotf((float)dxx, (float)dyy) * (float)FX_SCALE;
-    const float b = pv.b();
-    float C = 2.0f * cross / (fma_ * fem * fea);
-    float qpt = -C / b;
-    qpt = fminf(fmaxf(qpt, -pv.qpt_clamp()), pv.qpt_clamp());
-    C = -b * qpt;
-    const float sarg = fminf(fmaxf(fea * C * 0.5f, -1.0f), 1.0f);
-    const float phiA = atan2f((float)dye, (float)dxe) - asinf(sarg);
-    const float h = fea * fabsf(C) * 0.5f;
-    const float arc = h > 0.0f ? fea * asinf(fminf(h, 1.0f)) / h : fea;
-    Trk<float> k;
-    k.p[0] = (float)cl.y_fx[A] * (float)FX_SCALE;
-    k.p[1] = 0.0f;
-    k.p[2] = sinf(phiA);
-    k.p[3] = (float)(cl.z_fx[E] - anchor) * (float)FX_SCALE / arc;
-    k.p[4] = qpt;
-    if (!(fabsf(k.p[2]) < pv.snp_max())) continue;
-    c0_reset(k, pv, r1);
-    // ---- pass A: outward
-    float my = k.p[0], mz = 0.0f;
-    if (!update(k, my, mz, pv.vy(r1), pv.vz(r1), (float*)nullptr)) continue;
-    H[r1] = (int32_t)A;
-    int nh = 1;
-    Trk<float> last = k;
-    int r_out = r1, nmiss = 0, hi = r1;
-    int32_t ctl = (int32_t)A;  // walks the tracklet chain
-    for (int r = r1 + 1; r < NROW; ++r) {
-      if (!propagate(k, row_dx<float>(P, r - 1, r), pv, true, pv.snp_max())) break;
-      int32_t cand;
-      if (r < r1 + L) {
-        ctl = upc[ctl];
-        cand = ctl;
-      } else {
-        if (fabsf(k.p[0]) > pv.hw(r) + pv.edge_margin()) break;
-        cand = search_row(cl, cblk, nblk, ubase + r, k, anchor, pv.vy(r), pv.vz(r), chi2max);
-      }
-      hi = r;
-      H[r] = -1;
-      if (cand < 0) {
-        if (++nmiss >= P->max_miss) break;
-        continue;
-      }
-      my = (float)cl.y_fx[cand] * (float)FX_SCALE;
-      mz = (float)(cl.z_fx[cand] - anchor) * (float)FX_SCALE;
-      if (!update(k, my, mz, pv.vy(r), pv.vz(r), (float*)nullptr)) break;
-      H[r] = cand;
-      ++nh;
-      last = k;
-      r_out = r;
-      nmiss = 0;
-    }
-    // ---- pass B: inward from the outermost hit with a reset covariance
-    k = last;
-    c0_reset(k, pv, r_out);
-    Trk<float> inner = last;
-    int r_in = r_out, lo = r1;
-    {
-      const int32_t co = H[r_out];
-      my = (float)cl.y_fx[co] * (float)FX_SCALE;
-      mz = (float)(cl.z_fx[co] - anchor) * (float)FX_SCALE;
-    }
-    if (update(k, my, mz, pv.vy(r_out), pv.vz(r_out), (float*)nullptr)) {
-      inner = k;
-      nmiss = 0;
-      for (int r = r_out - 1; r >= 0; --r) {
-        if (!propagate(k, row_dx<float>(P, r + 1, r), pv, true, pv.snp_max())) break;
-        int32_t cand = r >= r1 ? H[r] : -1;
-        bool fresh = false;
-        if (cand < 0) {
-          if (fabsf(k.p[0]) > pv.hw(r) + pv.edge_margin()) break;
-          cand = search_row(cl, cblk, nblk, ubase + r, k, anchor, pv.vy(r), pv.vz(r), chi2max);
-          if (r < lo) {
-            lo = r;
-            H[r] = -1;
-          }
-          if (cand < 0) {
-            if (r < r1 && ++nmiss >= P->max_miss) break;
-            continue;
-          }
-          fresh = true;
-        }
-        my = (float)cl.y_fx[cand] * (float)FX_SCALE;
-        mz = (float)(cl.z_fx[cand] - anchor) * (float)FX_SCALE;
-        if (!update(k, my, mz, pv.vy(r), pv.vz(r), (float*)nullptr)) break;
-        if (fresh) {
-          H[r] = cand;
-          ++nh;
-        }
-        inner = k;
-        r_in = r;
-        nmiss = 0;
+    if (follow_start_b(f, cl, fo, pv)) {
+      f.phase = FS_B;
+      while (!follow_step(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
       }
     }
-    float* S = fo.state + (size_t)t * 6;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) S[i] = inner.p[i];
-    S[5] = (float)r_in;
-    fo.nhits[t] = (uint16_t)nh;
-    fo.range[t] = (uint16_t)(lo | (hi << 8));
-    fo.ok[t] = 1;
+    follow_finish(f, fo);
   }
 }
 
@@ -532,18 +639,30 @@ __device__ __forceinline__ uint64_t track_key(uint32_t nh, uint32_t t) {
   return ((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - t);
 }
 
+// Conflict resolution runs one wave per tracklet: the lanes take the rows
+// of the tracklet's hit table (contiguous), so every table read is coalesced.
+// The tracklet index is made wave-uniform so its scalars load once.
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
 // Every followed tracklet with enough hits bids for its clusters.
-__global__ void k_claim(FollowOut fo, const uint32_t* n_tl_dev, uint32_t tl_cap,
-                        unsigned long long* __restrict__ owner, uint32_t n_cl_cap,
-                        const DevParams* __restrict__ P, const DevStatus* st) {
+__global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_tl_dev,
+                                               uint32_t tl_cap,
+                                               unsigned long long* __restrict__ owner,
+                                               uint32_t n_cl_cap, const DevParams* __restrict__ P,
+                                               const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t t = wave_uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
+       t += nw) {
     if (!fo.ok[t] || (int)fo.nhits[t] < P->min_track_hits) continue;
     const unsigned long long key = track_key(fo.nhits[t], t);
     const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
     const int32_t* H = fo.hits + (size_t)t * NROW;
-    for (int r = lo; r <= hi; ++r) {
+    for (int r = lo + (int)lane; r <= hi; r += 64) {
       const int32_t c = H[r];
       if (c >= 0 && (uint32_t)c < n_cl_cap) atomicMax(&owner[c], key);
     }
@@ -551,25 +670,35 @@ __global__ void k_claim(FollowOut fo, const uint32_t* n_tl_dev, uint32_t tl_cap,
 }
 
 // Hits each track keeps after the claims; < min_track_hits drops the track.
-__global__ void k_keep(FollowOut fo, const uint32_t* n_tl_dev, uint32_t tl_cap,
-                       const unsigned long long* __restrict__ owner, uint32_t n_cl_cap,
-                       uint16_t* __restrict__ nkept, const DevParams* __restrict__ P,
-                       const DevStatus* st) {
+__global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl_dev,
+                                              uint32_t tl_cap,
+                                              const unsigned long long* __restrict__ owner,
+                                              uint32_t n_cl_cap, uint16_t* __restrict__ nkept,
+                                              const DevParams* __restrict__ P,
+                                              const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t t = wave_uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
+       t += nw) {
     uint32_t n = 0;
     if (fo.ok[t] && (int)fo.nhits[t] >= P->min_track_hits) {
       const unsigned long long key = track_key(fo.nhits[t], t);
       const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
       const int32_t* H = fo.hits + (size_t)t * NROW;
-      for (int r = lo; r <= hi; ++r) {
-        const int32_t c = H[r];
-        n += (c >= 0 && (uint32_t)c < n_cl_cap && owner[c] == key) ? 1u : 0u;
+      for (int r0 = lo; r0 <= hi; r0 += 64) {
+        const int r = r0 + (int)lane;
+        bool kept = false;
+        if (r <= hi) {
+          const int32_t c = H[r];
+          kept = c >= 0 && (uint32_t)c < n_cl_cap && owner[c] == key;
+        }
+        n += (uint32_t)__popcll(__ballot(kept));
       }
       if ((int)n < P->min_track_hits) n = 0;
     }
-    nkept[t] = (uint16_t)n;
+    if (lane == 0) nkept[t] = (uint16_t)n;
   }
 }
 
@@ -871,39 +1000,47 @@ __global__ void k_track_totals(const unsigned long long* total, TrackOut to, uin
   if (nt <= to.capacity) to.hit_start[nt] = nh;
 }
 
-__global__ void k_track_emit(ClusterView cl, const uint32_t* __restrict__ tl_start, FollowOut fo,
-                             const uint32_t* n_tl_dev, uint32_t tl_cap,
-                             const unsigned long long* __restrict__ owner,
-                             const uint16_t* __restrict__ nkept, RefitOut ro,
-                             const uint32_t* __restrict__ trk_index,
-                             const uint32_t* __restrict__ hit_off, TrackOut to,
-                             const DevStatus* st) {
+__global__ __launch_bounds__(256) void k_track_emit(
+    ClusterView cl, const uint32_t* __restrict__ tl_start, FollowOut fo, const uint32_t* n_tl_dev,
+    uint32_t tl_cap, const unsigned long long* __restrict__ owner,
+    const uint16_t* __restrict__ nkept, RefitOut ro, const uint32_t* __restrict__ trk_index,
+    const uint32_t* __restrict__ hit_off, TrackOut to, const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t t = wave_uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
+       t += nw) {
     const uint32_t j = trk_index[t];
     if (j == 0xFFFFFFFFu || j >= to.capacity) continue;
-    to.tracklet[j] = t;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) to.par[(size_t)j * 5 + i] = ro.par[(size_t)t * 5 + i];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) to.cov[(size_t)j * 15 + i] = ro.cov[(size_t)t * 15 + i];
-    to.chi2[j] = ro.chi2[t];
-    to.ndf[j] = (uint16_t)(2 * nkept[t] - 5);
-    to.row[j] = ro.row[t];
-    to.flags[j] = ro.flags[t];
-    to.z_anchor[j] = cl.z_fx[tl_start[t]];
+    if (lane < 5) to.par[(size_t)j * 5 + lane] = ro.par[(size_t)t * 5 + lane];
+    if (lane < 15) to.cov[(size_t)j * 15 + lane] = ro.cov[(size_t)t * 15 + lane];
     uint32_t o = hit_off[t];
-    to.hit_start[j] = o;
+    if (lane == 0) {
+      to.tracklet[j] = t;
+      to.chi2[j] = ro.chi2[t];
+      to.ndf[j] = (uint16_t)(2 * nkept[t] - 5);
+      to.row[j] = ro.row[t];
+      to.flags[j] = ro.flags[t];
+      to.z_anchor[j] = cl.z_fx[tl_start[t]];
+      to.hit_start[j] = o;
+    }
+    // kept hits in ascending row order
     const unsigned long long key = track_key(fo.nhits[t], t);
     const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
     const int32_t* H = fo.hits + (size_t)t * NROW;
-    for (int r = lo; r <= hi; ++r) {
-      const int32_t c = H[r];
-      if (c >= 0 && owner[c] == key) {
-        if (o < to.hit_capacity) to.hits[o] = (uint32_t)c;
-        ++o;
+    for (int r0 = lo; r0 <= hi; r0 += 64) {
+      const int r = r0 + (int)lane;
+      int32_t c = -1;
+      bool kept = false;
+      if (r <= hi) {
+        c = H[r];
+        kept = c >= 0 && owner[c] == key;
       }
+      const uint64_t m = __ballot(kept);
+      const uint32_t k = o + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (kept && k < to.hit_capacity) to.hits[k] = (uint32_t)c;
+      o += (uint32_t)__popcll(m);
     }
   }
 }

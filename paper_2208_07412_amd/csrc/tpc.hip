@@ -66,6 +66,7 @@ struct tpc_ctx {
   uint16_t* f_nhits = nullptr;
   uint16_t* f_range = nullptr;
   uint8_t* f_ok = nullptr;
+  uint32_t* f_pts = nullptr;  // per tracklet: middle and end cluster, unit-row of the start
   unsigned long long* owner = nullptr;
   uint16_t* nkept = nullptr;
   float *r_par = nullptr, *r_cov = nullptr, *r_chi2 = nullptr;
@@ -101,7 +102,7 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok,
+  size_t zblk, cblk, win, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
       h_flags, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
@@ -133,6 +134,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.f_nhits = L.add<uint16_t>(mt);
   p.f_range = L.add<uint16_t>(mt);
   p.f_ok = L.add<uint8_t>(mt);
+  p.f_pts = L.add<uint32_t>(mt * 3);
   p.owner = L.add<unsigned long long>(mc);
   p.nkept = L.add<uint16_t>(mt);
   p.r_par = L.add<float>(mt * 5);
@@ -438,29 +440,33 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   const FollowOut fo = follow_out(c);
   const RefitOut ro = refit_out(c);
   const uint32_t g64 = grid_for(tcap, 64);
-  const uint32_t g256 = grid_for(tcap, 256);
+  const uint32_t gw = grid_for(tcap, 32);
   // per-call counters of the fit stage
   k_fill<uint32_t><<<1, 64, 0, s>>>(&c->d_st->n_fallback, 0u, 5);
   {
     StageTimer tm(c, 7);
+    k_tracklet_points<<<grid_for(tcap, 256), 256, 0, s>>>(cv, n_ur, l->upc, t->start, t->len,
+                                                           t->n_tracklets, tcap, c->f_pts,
+                                                           c->d_st);
     const int fb = c->tune.follow_block;
     const uint32_t gf = grid_for(tcap, fb);
     if (fb == 256)
-      k_follow<256><<<gf, 256, 0, s>>>(cv, c->cblk, nblk, n_ur, l->upc, t->start, t->len,
+      k_follow<256><<<gf, 256, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len, c->f_pts,
                                        t->n_tracklets, tcap, fo, c->d_par, c->d_st);
     else if (fb == 128)
-      k_follow<128><<<gf, 128, 0, s>>>(cv, c->cblk, nblk, n_ur, l->upc, t->start, t->len,
+      k_follow<128><<<gf, 128, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len, c->f_pts,
                                        t->n_tracklets, tcap, fo, c->d_par, c->d_st);
     else
-      k_follow<64><<<gf, 64, 0, s>>>(cv, c->cblk, nblk, n_ur, l->upc, t->start, t->len,
+      k_follow<64><<<gf, 64, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len, c->f_pts,
                                      t->n_tracklets, tcap, fo, c->d_par, c->d_st);
   }
   {
     StageTimer tm(c, 8);
     k_fill_dev<unsigned long long><<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, 0ull,
                                                                         cl->n_clusters, ccap);
-    k_claim<<<g256, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->d_par, c->d_st);
-    k_keep<<<g256, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->nkept, c->d_par,
+    // one wave per tracklet, about 8 tracklets per wave
+    k_claim<<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->d_par, c->d_st);
+    k_keep<<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->nkept, c->d_par,
                                 c->d_st);
   }
   {
@@ -482,7 +488,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   TrackOut to{tr->capacity, tr->hit_capacity, tr->tracklet, tr->par, tr->cov, tr->chi2, tr->ndf,
               tr->row, tr->flags, tr->z_anchor, tr->hit_start, tr->hits, tr->cluster_track};
   k_track_totals<<<1, 1, 0, s>>>(c->tot64, to, tr->n_tracks, tr->n_hits, c->d_st);
-  k_track_emit<<<g256, 256, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept, ro,
+  k_track_emit<<<gw, 256, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept, ro,
                                     c->trk_index, c->hit_off, to, c->d_st);
   k_cluster_track<<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, c->trk_index, cl->n_clusters, ccap,
                                                       tcap, tr->cluster_track, c->d_st);
@@ -586,6 +592,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->f_nhits = (uint16_t*)(base + pl.f_nhits);
   c->f_range = (uint16_t*)(base + pl.f_range);
   c->f_ok = (uint8_t*)(base + pl.f_ok);
+  c->f_pts = (uint32_t*)(base + pl.f_pts);
   c->owner = (unsigned long long*)(base + pl.owner);
   c->nkept = (uint16_t*)(base + pl.nkept);
   c->r_par = (float*)(base + pl.r_par);

@@ -121,3 +121,11 @@ def test_estimates_and_arrivals():
     a = serve.poisson_arrivals(20000, 50.0, seed=3)
     gaps = np.diff(np.concatenate([[0.0], a]))
     assert abs(gaps.mean() - 0.02) < 0.001 and np.all(gaps > 0)
+
+
+def test_autotune_pick_keeps_current_within_margin():
+    from paper_2208_07412_amd.autotune import _pick
+
+    assert _pick({"a": 1.00, "b": 0.99}, "a", 0.02) == "a"
+    assert _pick({"a": 1.00, "b": 0.95}, "a", 0.02) == "b"
+    assert _pick({"a": 1.00, "b": 0.99}, "c", 0.02) == "b"
