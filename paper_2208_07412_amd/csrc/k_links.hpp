@@ -13,6 +13,7 @@
 struct ClusterView {
   const int32_t* y_fx;
   const int32_t* z_fx;
+  const int2* pos;           // (y_fx, z_fx) packed, one load per cluster
   const uint16_t* ptime;
   const uint32_t* crow;      // [n_ur+1]
   const uint32_t* n_clusters;
@@ -23,6 +24,16 @@ struct ClusterView {
     return v < capacity ? v : capacity;
   }
 };
+
+// Packed copy of the fixed-point positions for the search kernels.
+__global__ void k_pack_pos(const int32_t* __restrict__ y, const int32_t* __restrict__ z,
+                           const uint32_t* n_dev, uint32_t n_cap, int2* __restrict__ pos,
+                           const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n = scan_count(n_dev, n_cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    pos[i] = make_int2(y[i], z[i]);
+}
 
 // Candidate cluster range of row ur for a drift position z (fixed point):
 // |z_c - z| <= win_z and the centroid lies within 2 bins of the peak time.
@@ -137,8 +148,9 @@ __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32
       int64_t yi = 0, zi = 0;
       uint32_t ja = 0, jb = 0, ka = 0, kb = 0;
       if (valid) {
-        yi = cl.y_fx[i];
-        zi = cl.z_fx[i];
+        const int2 pi = cl.pos[i];
+        yi = pi.x;
+        zi = pi.y;
         nb_candidates(cl, cblk, nblk, ur - 1, zi, wz, ja, jb);
         nb_candidates(cl, cblk, nblk, ur + 1, zi, wz, ka, kb);
       }
@@ -163,18 +175,18 @@ __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32
       const bool stage_k = KB > KA && KB - KA <= NB_STAGE;
       if (stage_j)
         for (uint32_t t = threadIdx.x; t < JB - JA; t += blockDim.x) {
-          sp[0][t] = make_int2(cl.y_fx[JA + t], cl.z_fx[JA + t]);
+          sp[0][t] = cl.pos[JA + t];
         }
       if (stage_k)
         for (uint32_t t = threadIdx.x; t < KB - KA; t += blockDim.x) {
-          sp[1][t] = make_int2(cl.y_fx[KA + t], cl.z_fx[KA + t]);
+          sp[1][t] = cl.pos[KA + t];
         }
       __syncthreads();
       int32_t bd = -1, bu = -1;
       if (valid && jb > ja && kb > ka) {
         auto Jl = [&](uint32_t c) { return sp[0][c - JA]; };
         auto Kl = [&](uint32_t c) { return sp[1][c - KA]; };
-        auto G = [&](uint32_t c) { return make_int2(cl.y_fx[c], cl.z_fx[c]); };
+        auto G = [&](uint32_t c) { return cl.pos[c]; };
         if (stage_j && stage_k) nb_best(Jl, Kl, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);
         else if (stage_j) nb_best(Jl, G, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);
         else if (stage_k) nb_best(G, Kl, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);

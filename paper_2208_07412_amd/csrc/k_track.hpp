@@ -375,6 +375,7 @@ struct FollowOut {
   uint16_t* nhits;    // [cap]
   uint16_t* range;    // [cap]: lo | hi << 8
   uint8_t* ok;        // [cap]
+  uint8_t* krow;      // [cap*152]: rows of the kept hits, ascending (after resolution)
 };
 
 // best candidate of row r: smallest (chi2, id) with chi2 <= chi2_max
@@ -397,8 +398,9 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
   float bchi = 0.0f;
   const SInv<float> si = s_inverse(k, vy, vz);
   for (uint32_t c = a; c < b; ++c) {
-    const float my = (float)cl.y_fx[c] * (float)FX_SCALE;
-    const float mz = (float)(cl.z_fx[c] - anchor) * (float)FX_SCALE;
+    const int2 q = cl.pos[c];
+    const float my = (float)q.x * (float)FX_SCALE;
+    const float mz = (float)(q.y - anchor) * (float)FX_SCALE;
     const float x2 = chi2_of(k, my, mz, si);
     if (x2 <= chi2max && (best < 0 || x2 < bchi)) {
       best = (int32_t)c;
@@ -485,12 +487,13 @@ __device__ __forceinline__ bool follow_init(FollowLane& f, uint32_t t, const Clu
   f.ubase = urA - r1;
   const int im = (L + 1) / 2 - 1;
   const int rM = r1 + im, rE = r1 + L - 1;
-  const int32_t anchor = cl.z_fx[A];
+  const int2 qA = cl.pos[A], qM = cl.pos[M], qE = cl.pos[E];
+  const int32_t anchor = qA.y;
   f.anchor = anchor;
   // ---- seed: circle through A, M, E; differences are exact integers
-  const int64_t dxm = P->xfx[rM] - P->xfx[r1], dym = (int64_t)cl.y_fx[M] - cl.y_fx[A];
-  const int64_t dxe = P->xfx[rE] - P->xfx[r1], dye = (int64_t)cl.y_fx[E] - cl.y_fx[A];
-  const int64_t dxx = P->xfx[rE] - P->xfx[rM], dyy = (int64_t)cl.y_fx[E] - cl.y_fx[M];
+  const int64_t dxm = P->xfx[rM] - P->xfx[r1], dym = (int64_t)qM.x - qA.x;
+  const int64_t dxe = P->xfx[rE] - P->xfx[r1], dye = (int64_t)qE.x - qA.x;
+  const int64_t dxx = P->xfx[rE] - P->xfx[rM], dyy = (int64_t)qE.x - qM.x;
   const float cross = (float)(dxm * dye - dym * dxe) * (float)(FX_SCALE * FX_SCALE);
   const float fma_ = hypotf((float)dxm, (float)dym) * (float)FX_SCALE;
   const float fea = hypotf((float)dxe, (float)dye) * (float)FX_SCALE;
@@ -505,10 +508,10 @@ __device__ __forceinline__ bool follow_init(FollowLane& f, uint32_t t, const Clu
   const float h = fea * fabsf(C) * 0.5f;
   const float arc = h > 0.0f ? fea * asinf(fminf(h, 1.0f)) / h : fea;
   Trk<float>& k = f.k;
-  k.p[0] = (float)cl.y_fx[A] * (float)FX_SCALE;
+  k.p[0] = (float)qA.x * (float)FX_SCALE;
   k.p[1] = 0.0f;
   k.p[2] = sinf(phiA);
-  k.p[3] = (float)(cl.z_fx[E] - anchor) * (float)FX_SCALE / arc;
+  k.p[3] = (float)(qE.y - anchor) * (float)FX_SCALE / arc;
   k.p[4] = qpt;
   if (!(fabsf(k.p[2]) < pv.snp_max())) return false;
   c0_reset(k, pv, r1);
@@ -535,8 +538,9 @@ __device__ __forceinline__ bool follow_start_b(FollowLane& f, const ClusterView&
   c0_reset(k, pv, f.rs);
   f.lo = f.r1;
   const int32_t co = fo.hits[(size_t)f.t * NROW + f.rs];
-  const float my = (float)cl.y_fx[co] * (float)FX_SCALE;
-  const float mz = (float)(cl.z_fx[co] - f.anchor) * (float)FX_SCALE;
+  const int2 q = cl.pos[co];
+  const float my = (float)q.x * (float)FX_SCALE;
+  const float mz = (float)(q.y - f.anchor) * (float)FX_SCALE;
   if (!update(k, my, mz, pv.vy(f.rs), pv.vz(f.rs), (float*)nullptr)) return false;
 #pragma unroll
   for (int i = 0; i < 5; ++i) f.sp[i] = k.p[i];
@@ -592,8 +596,9 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
     if ((pa || rn < f.r1) && ++f.nmiss >= P->max_miss) return true;
     return false;
   }
-  const float my = (float)cl.y_fx[cand] * (float)FX_SCALE;
-  const float mz = (float)(cl.z_fx[cand] - f.anchor) * (float)FX_SCALE;
+  const int2 q = cl.pos[cand];
+  const float my = (float)q.x * (float)FX_SCALE;
+  const float mz = (float)(q.y - f.anchor) * (float)FX_SCALE;
   if (!update(k, my, mz, pv.vy(rn), pv.vz(rn), (float*)nullptr)) return true;
   if (pa || fresh) {
     H[rn] = cand;
@@ -687,6 +692,7 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
       const unsigned long long key = track_key(fo.nhits[t], t);
       const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
       const int32_t* H = fo.hits + (size_t)t * NROW;
+      uint8_t* KR = fo.krow + (size_t)t * NROW;
       for (int r0 = lo; r0 <= hi; r0 += 64) {
         const int r = r0 + (int)lane;
         bool kept = false;
@@ -694,7 +700,9 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
           const int32_t c = H[r];
           kept = c >= 0 && (uint32_t)c < n_cl_cap && owner[c] == key;
         }
-        n += (uint32_t)__popcll(__ballot(kept));
+        const uint64_t m = __ballot(kept);
+        if (kept) KR[n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)r;
+        n += (uint32_t)__popcll(m);
       }
       if ((int)n < P->min_track_hits) n = 0;
     }
@@ -720,28 +728,28 @@ __device__ __forceinline__ int32_t tl_anchor(const ClusterView& cl, const uint32
 // covariance update would bias the result; afterwards FP32 keeps up.
 #define REFIT_HEAD 5
 
-// Kalman steps of the refit: from row r downwards, through at most
-// max_hits kept hits; the state k sits at row r_state.  On return r is the
-// next row to examine.  Returns 1 if the helix cannot reach a hit's row or an
+// Kalman steps of the refit: kept hits i, i-1, ... (rows descending), at
+// most max_hits of them; the state k sits at row r_state.  On return i is the
+// next kept hit to use.  Returns 1 if the helix cannot reach a hit's row or an
 // update fails; pd turns false if an update left the covariance not PD.
 template <typename T>
 __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, const FollowOut& fo,
-                         const unsigned long long* owner, const DevParams* P, Trk<T>& k,
-                         T& chi2s, int& r_state, int& r, int max_hits, bool& pd,
-                         bool* guard = nullptr, LoParts<T>* lp = nullptr) {
+                         const DevParams* P, Trk<T>& k, T& chi2s, int& r_state, int& i,
+                         int max_hits, bool& pd, bool* guard = nullptr,
+                         LoParts<T>* lp = nullptr) {
   const PV<T> pv{P};
-  const unsigned long long key = track_key(fo.nhits[t], t);
-  const int lo = fo.range[t] & 255;
   const int32_t* H = fo.hits + (size_t)t * NROW;
+  const uint8_t* KR = fo.krow + (size_t)t * NROW;
   int done = 0;
-  for (; r >= lo && done < max_hits; --r) {
+  for (; i >= 0 && done < max_hits; --i) {
+    const int r = KR[i];
     const int32_t c = H[r];
-    if (c < 0 || owner[c] != key) continue;
     if (r != r_state &&
         !propagate(k, row_dx<T>(P, r_state, r), pv, true, pv.refit_snp_max(), lp))
       return 1;
-    const T my = (T)cl.y_fx[c] * (T)FX_SCALE;
-    const T mz = (T)(cl.z_fx[c] - anchor) * (T)FX_SCALE;
+    const int2 q = cl.pos[c];
+    const T my = (T)q.x * (T)FX_SCALE;
+    const T mz = (T)(q.y - anchor) * (T)FX_SCALE;
     T x2;
     T d0[5];
 #pragma unroll
@@ -768,34 +776,18 @@ __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, cons
 // row, or -1 if the track has fewer than 3 kept hits.
 template <typename T>
 __device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, const FollowOut& fo,
-                          const unsigned long long* owner, const DevParams* P, Trk<T>& k) {
+                          int n, const DevParams* P, Trk<T>& k) {
   const PV<T> pv{P};
-  const unsigned long long key = track_key(fo.nhits[t], t);
-  const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
-  const int32_t* H = fo.hits + (size_t)t * NROW;
-  int n = 0, rA = -1, rE = -1;
-  for (int r = hi; r >= lo; --r) {
-    const int32_t c = H[r];
-    if (c < 0 || owner[c] != key) continue;
-    if (rE < 0) rE = r;
-    rA = r;
-    ++n;
-  }
   if (n < 3) return -1;
+  const int32_t* H = fo.hits + (size_t)t * NROW;
+  const uint8_t* KR = fo.krow + (size_t)t * NROW;
   const int im = (n + 1) / 2 - 1;  // middle, counted from the innermost
-  int rM = -1, j = 0;
-  for (int r = lo; r <= hi; ++r) {
-    const int32_t c = H[r];
-    if (c < 0 || owner[c] != key) continue;
-    if (j++ == im) {
-      rM = r;
-      break;
-    }
-  }
+  const int rA = KR[0], rM = KR[im], rE = KR[n - 1];
   const int32_t cA = H[rA], cM = H[rM], cE = H[rE];
-  const int64_t dxm = P->xfx[rM] - P->xfx[rA], dym = (int64_t)cl.y_fx[cM] - cl.y_fx[cA];
-  const int64_t dxe = P->xfx[rE] - P->xfx[rA], dye = (int64_t)cl.y_fx[cE] - cl.y_fx[cA];
-  const int64_t dxx = P->xfx[rE] - P->xfx[rM], dyy = (int64_t)cl.y_fx[cE] - cl.y_fx[cM];
+  const int2 qA = cl.pos[cA], qM = cl.pos[cM], qE = cl.pos[cE];
+  const int64_t dxm = P->xfx[rM] - P->xfx[rA], dym = (int64_t)qM.x - qA.x;
+  const int64_t dxe = P->xfx[rE] - P->xfx[rA], dye = (int64_t)qE.x - qA.x;
+  const int64_t dxx = P->xfx[rE] - P->xfx[rM], dyy = (int64_t)qE.x - qM.x;
   const T S = (T)FX_SCALE;
   const T cross = (T)(dxm * dye - dym * dxe) * S * S;
   const T dma = hypot((T)dxm, (T)dym) * S, dea = hypot((T)dxe, (T)dye) * S;
@@ -808,10 +800,10 @@ __device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, con
   const T sarg = fmin(fmax(dea * C * (T)0.5, (T)-1), (T)1);
   const T h = dea * fabs(C) * (T)0.5;
   const T arc = h > (T)0 ? dea * asin(fmin(h, (T)1)) / h : dea;
-  k.p[0] = (T)cl.y_fx[cE] * S;
-  k.p[1] = (T)(cl.z_fx[cE] - anchor) * S;
+  k.p[0] = (T)qE.x * S;
+  k.p[1] = (T)(qE.y - anchor) * S;
   k.p[2] = sin(atan2((T)dye, (T)dxe) + asin(sarg));  // tangent at the far end of the chord
-  k.p[3] = (T)(cl.z_fx[cE] - cl.z_fx[cA]) * S / arc;
+  k.p[3] = (T)(qE.y - qA.y) * S / arc;
   k.p[4] = qpt;
 #pragma unroll
   for (int i = 0; i < 15; ++i) k.c[i] = 0;
@@ -826,7 +818,7 @@ __device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, con
 struct RefitHead {
   double* state;   // [cap*20]: p[5], packed covariance[15]
   double* chi2;    // [cap]
-  int16_t* r;      // [cap] next row to examine
+  int16_t* r;      // [cap] next kept hit to use (index into the kept rows)
   int16_t* rprev;  // [cap] row of the state
   uint8_t* flags;  // [cap] 1 failed, 2 not PD, 4 low pT
 };
@@ -842,15 +834,16 @@ __global__ __launch_bounds__(64) void k_refit_head(ClusterView cl,
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
-    if (nkept[t] == 0) continue;
+    const int n = nkept[t];
+    if (n == 0) continue;
     Trk<double> k;
     double chi2s = 0;
     const int32_t anchor = tl_anchor(cl, tl_start, t);
-    int rs = refit_seed<double>(t, cl, anchor, fo, owner, P, k);
-    int r = rs;
+    int rs = refit_seed<double>(t, cl, anchor, fo, n, P, k);
+    int r = n - 1;
     bool pd = true;
     const bool lowpt = fabs(k.p[4]) >= (double)P->lowpt_qpt;
-    const int rc = rs < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, owner, P, k, chi2s, rs, r,
+    const int rc = rs < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, P, k, chi2s, rs, r,
                                                   REFIT_HEAD, pd);
     double* S = hd.state + (size_t)t * 20;
 #pragma unroll
@@ -893,8 +886,8 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
     int rprev = hd.rprev[t], r = hd.r[t];
     bool pd = (hd.flags[t] & 2) == 0;
     bool guard = false;
-    const int rc = refit_run<float>(t, cl, tl_anchor(cl, tl_start, t), fo, owner, P, k, chi2s,
-                                    rprev, r, NROW, pd, &guard, &lo);
+    const int rc = refit_run<float>(t, cl, tl_anchor(cl, tl_start, t), fo, P, k, chi2s, rprev, r,
+                                    NROW, pd, &guard, &lo);
     k.p[0] += lo.y;
     k.p[2] += lo.s;
     if (rc) {
@@ -921,7 +914,7 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
 
 __global__ __launch_bounds__(64) void k_refit64(ClusterView cl, const uint32_t* __restrict__ tl_start,
                                                 FollowOut fo, uint32_t tl_cap,
-                                                const unsigned long long* __restrict__ owner,
+                                                const uint16_t* __restrict__ nkept,
                                                 RefitOut ro, const uint32_t* __restrict__ fb_list,
                                                 const DevParams* __restrict__ P, DevStatus* st) {
   if (failed(st)) return;
@@ -931,11 +924,12 @@ __global__ __launch_bounds__(64) void k_refit64(ClusterView cl, const uint32_t* 
     Trk<double> k;
     double chi2s = 0;
     const int32_t anchor = tl_anchor(cl, tl_start, t);
-    int rprev = refit_seed<double>(t, cl, anchor, fo, owner, P, k);
-    int r = rprev;
+    const int n = nkept[t];
+    int rprev = refit_seed<double>(t, cl, anchor, fo, n, P, k);
+    int r = n - 1;
     bool pd = true;
-    const int rc = rprev < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, owner, P, k, chi2s, rprev,
-                                                     r, NROW, pd);
+    const int rc = rprev < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, P, k, chi2s, rprev, r, NROW,
+                                                     pd);
     atomicAdd(&st->n_fallback, 1u);
     if (rc || rprev < 0 || !pd) {
       const bool fail = rc || rprev < 0;
@@ -1026,22 +1020,11 @@ __global__ __launch_bounds__(256) void k_track_emit(
       to.hit_start[j] = o;
     }
     // kept hits in ascending row order
-    const unsigned long long key = track_key(fo.nhits[t], t);
-    const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
     const int32_t* H = fo.hits + (size_t)t * NROW;
-    for (int r0 = lo; r0 <= hi; r0 += 64) {
-      const int r = r0 + (int)lane;
-      int32_t c = -1;
-      bool kept = false;
-      if (r <= hi) {
-        c = H[r];
-        kept = c >= 0 && owner[c] == key;
-      }
-      const uint64_t m = __ballot(kept);
-      const uint32_t k = o + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      if (kept && k < to.hit_capacity) to.hits[k] = (uint32_t)c;
-      o += (uint32_t)__popcll(m);
-    }
+    const uint8_t* KR = fo.krow + (size_t)t * NROW;
+    const uint32_t n = nkept[t];
+    for (uint32_t i = lane; i < n; i += 64)
+      if (o + i < to.hit_capacity) to.hits[o + i] = (uint32_t)H[KR[i]];
   }
 }
 

@@ -66,7 +66,9 @@ struct tpc_ctx {
   uint16_t* f_nhits = nullptr;
   uint16_t* f_range = nullptr;
   uint8_t* f_ok = nullptr;
-  uint32_t* f_pts = nullptr;  // per tracklet: middle and end cluster, unit-row of the start
+  uint32_t* f_pts = nullptr;
+  uint8_t* f_krow = nullptr;
+  int2* pos = nullptr;  // packed cluster positions  // per tracklet: middle and end cluster, unit-row of the start
   unsigned long long* owner = nullptr;
   uint16_t* nkept = nullptr;
   float *r_par = nullptr, *r_cov = nullptr, *r_chi2 = nullptr;
@@ -102,7 +104,7 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts,
+  size_t zblk, cblk, win, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_krow, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
       h_flags, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
@@ -135,6 +137,8 @@ Plan plan_for(const tpc_sizes& m) {
   p.f_range = L.add<uint16_t>(mt);
   p.f_ok = L.add<uint8_t>(mt);
   p.f_pts = L.add<uint32_t>(mt * 3);
+  p.f_krow = L.add<uint8_t>(mt * NROW);
+  p.pos = L.add<int2>(mc);
   p.owner = L.add<unsigned long long>(mc);
   p.nkept = L.add<uint16_t>(mt);
   p.r_par = L.add<float>(mt * 5);
@@ -266,12 +270,13 @@ ZsArgs zs_args(const tpc_zs_input* in) {
                 in->n_time_bins};
 }
 
-ClusterView cluster_view(const tpc_clusters* cl) {
-  return ClusterView{cl->y_fx, cl->z_fx, cl->ptime, cl->crow_start, cl->n_clusters, cl->capacity};
+ClusterView cluster_view(tpc_ctx* c, const tpc_clusters* cl) {
+  return ClusterView{cl->y_fx,        cl->z_fx,        c->pos,       cl->ptime,
+                     cl->crow_start, cl->n_clusters, cl->capacity};
 }
 
 FollowOut follow_out(tpc_ctx* c) {
-  return FollowOut{c->f_hits, c->f_state, c->f_nhits, c->f_range, c->f_ok};
+  return FollowOut{c->f_hits, c->f_state, c->f_nhits, c->f_range, c->f_ok, c->f_krow};
 }
 
 RefitOut refit_out(tpc_ctx* c) {
@@ -402,6 +407,8 @@ int stage_grid(tpc_ctx* c, const tpc_clusters* cl) {
   k_block_index<<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk, 3,
                                              cl->n_time_bins, cl->capacity, c->cblk, c->d_par,
                                              c->d_st, 0);
+  k_pack_pos<<<grid_for(cl->capacity, 256), 256, 0, c->stream>>>(cl->y_fx, cl->z_fx, cl->n_clusters,
+                                                                 cl->capacity, c->pos, c->d_st);
   return launch_ok();
 }
 
@@ -409,7 +416,7 @@ int stage_neighbours(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l) {
   const uint32_t n_ur = cl->n_units * NROW;
   const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
   StageTimer tm(c, 5);
-  k_neighbours<<<n_ur, 256, 0, c->stream>>>(cluster_view(cl), c->cblk, nblk, n_ur, l->down, l->up,
+  k_neighbours<<<n_ur, 256, 0, c->stream>>>(cluster_view(c, cl), c->cblk, nblk, n_ur, l->down, l->up,
                                             c->d_par, c->d_st);
   return launch_ok();
 }
@@ -436,7 +443,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
   const uint32_t tcap = t->capacity;
   const uint32_t ccap = cl->capacity;
-  const ClusterView cv = cluster_view(cl);
+  const ClusterView cv = cluster_view(c, cl);
   const FollowOut fo = follow_out(c);
   const RefitOut ro = refit_out(c);
   const uint32_t g64 = grid_for(tcap, 64);
@@ -479,7 +486,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 10);
-    k_refit64<<<g64, 64, 0, s>>>(cv, t->start, fo, tcap, c->owner, ro, c->fb_list, c->d_par,
+    k_refit64<<<g64, 64, 0, s>>>(cv, t->start, fo, tcap, c->nkept, ro, c->fb_list, c->d_par,
                                  c->d_st);
   }
   StageTimer tm(c, 11);
@@ -593,6 +600,8 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->f_range = (uint16_t*)(base + pl.f_range);
   c->f_ok = (uint8_t*)(base + pl.f_ok);
   c->f_pts = (uint32_t*)(base + pl.f_pts);
+  c->f_krow = (uint8_t*)(base + pl.f_krow);
+  c->pos = (int2*)(base + pl.pos);
   c->owner = (unsigned long long*)(base + pl.owner);
   c->nkept = (uint16_t*)(base + pl.nkept);
   c->r_par = (float*)(base + pl.r_par);
