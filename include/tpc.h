@@ -89,7 +89,7 @@ typedef struct {
   uint32_t max_units;     /* units per call (36 per time frame) */
   uint32_t max_time_bins; /* time bins per unit (< 65536) */
   uint32_t max_clusters;  /* clusters per call */
-  uint32_t max_tracklets; /* tracklets per call */
+  uint32_t max_tracklets; /* tracklets per call, at most 2^24 */
 } tpc_sizes;
 
 /* Zero-suppressed input: samples sorted by (unit, row, time, pad). */

@@ -66,6 +66,13 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
   return (bid & 7u) * per + (bid >> 3);
 }
 
+// A value the whole wave holds alike, moved to a scalar register so that
+// the loop control and address arithmetic built on it stay scalar.
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // ------------------------------------------------------------ wave64 scans
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 

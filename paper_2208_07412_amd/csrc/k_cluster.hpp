@@ -4,7 +4,7 @@
 // window plus a 4-bin halo on each side are scattered into an LDS tile
 // (ADC per (time, pad)); every sample then finds its uphill neighbour
 // ("up code", the argmax of the (adc, time, pad) key over the 3x3
-// neighbourhood, index (dt+1)*3 + (dp+1), 4 = itself) and every peak
+// neighbourhood, encoded (dt+1)*4 + (dp+1), 5 = itself) and every peak
 // accumulates the samples of its 5x5 window that reach it in at most two
 // uphill steps.  Clusters are written in the order of their peaks (time, then
 // pad): a count pass gives every chunk of K windows its number of peaks, a
@@ -143,8 +143,9 @@ __device__ __forceinline__ void row_range(const uint32_t* blk_row, uint32_t nblk
   if (b > s1) b = s1;
 }
 
+// tile offset of the neighbour an up code points at
 __device__ __forceinline__ int code_offset(int code) {
-  return (code / 3 - 1) * CL_TP + (code % 3 - 1);
+  return ((code >> 2) - 1) * CL_TP + ((code & 3) - 1);
 }
 
 // ------------------------------------------------------------ tile cells
@@ -164,7 +165,7 @@ __device__ __forceinline__ int slot_of(int cell) {
 }
 // up code of a cell for the owner chase; a peak points at itself
 __device__ __forceinline__ int chase_code(int cell) {
-  return (cell & CL_PEAK) ? 4 : ((cell >> 10) & 15);
+  return (cell & CL_PEAK) ? 5 : ((cell >> 10) & 15);
 }
 
 // ------------------------------------------------------------ window loop
@@ -187,6 +188,10 @@ __device__ __forceinline__ WinRange window_range(const uint32_t* zb, uint32_t nb
   const int b0 = w * BW;
   row_range(zb, nblk, b0 - BH, b0 + BW + BH, rs0, rs1, R.s_lo, R.s_hi);
   row_range(zb, nblk, b0, b0 + BW, rs0, rs1, R.c_lo, R.c_hi);
+  R.s_lo = uni(R.s_lo);
+  R.s_hi = uni(R.s_hi);
+  R.c_lo = uni(R.c_lo);
+  R.c_hi = uni(R.c_hi);
   return R;
 }
 
@@ -261,22 +266,24 @@ __device__ __forceinline__ Row3 row3(const uint16_t* tile, int c) {
   return Row3{(int)(v & 0x3FF), (int)((v >> 16) & 0x3FF), (int)((v >> 32) & 0x3FF)};
 }
 
-// up code (bits 0-3) and peak flag (bit 4) of the sample in cell c
+// up code (bits 0-3) and peak flag (bit 4) of the sample in cell c: the
+// argmax of the key (adc, time, pad) over the cell and its present neighbours
 __device__ __forceinline__ int up_code_of(const uint16_t* tile, int c, int qmin) {
   const Row3 u = row3(tile, c - CL_TP), m = row3(tile, c), d = row3(tile, c + CL_TP);
   const int a = m.m;
-  const int an[9] = {u.l, u.m, u.r, m.l, 0, m.r, d.l, d.m, d.r};
-  int best = a * 16 + 4, code = 4;
+  // neighbours in (dt, dp) order with their codes; ties go to the later one
+  const int an[8] = {u.l, u.m, u.r, m.l, m.r, d.l, d.m, d.r};
+  const int cd[8] = {0, 1, 2, 4, 6, 8, 9, 10};
+  int best = a * 16 + 5, code = 5;
 #pragma unroll
-  for (int idx = 0; idx < 9; ++idx) {
-    if (idx == 4) continue;
-    const int k = an[idx] * 16 + idx;
-    if (an[idx] != 0 && k > best) {
+  for (int n = 0; n < 8; ++n) {
+    const int k = an[n] * 16 + cd[n];
+    if (an[n] != 0 && k > best) {
       best = k;
-      code = idx;
+      code = cd[n];
     }
   }
-  return code | ((code == 4 && a >= qmin) ? 16 : 0);
+  return code | ((code == 5 && a >= qmin) ? 16 : 0);
 }
 
 // The peak test alone: the sample's key beats its 8 neighbours (earlier
@@ -316,9 +323,9 @@ __global__ __launch_bounds__(64) void k_cluster_count(ZsArgs in, const uint32_t*
   const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
   if (ur >= n_ur) return;
-  const int np = P->np[ur % NROW], qmin = P->qmax_min;
+  const int np = uni(P->np[ur % NROW]), qmin = uni(P->qmax_min);
   const uint32_t* zb = zblk + (size_t)ur * (nblk + 1);
-  uint32_t rs0 = zb[0], rs1 = zb[nblk];
+  uint32_t rs0 = uni(zb[0]), rs1 = uni(zb[nblk]);
   if (rs1 > in.n_samples) rs1 = in.n_samples;
   if (rs0 > rs1) rs0 = rs1;
   const int w0 = chunk * K;
@@ -356,6 +363,55 @@ __global__ __launch_bounds__(64) void k_cluster_count(ZsArgs in, const uint32_t*
   if (threadIdx.x == 0) chunk_cnt[(size_t)ur * nchunk + chunk] = cnt;
 }
 
+// Output of the staged peaks [0, n): one lane per cluster.
+__device__ __forceinline__ void emit_staged(const unsigned long long* acc0,
+                                            const unsigned long long* acc1,
+                                            const uint32_t* st_pt, const uint16_t* st_q,
+                                            uint32_t n, uint32_t obase, int np, int64_t pfx,
+                                            const ClusterOut& out) {
+  const uint32_t i = threadIdx.x;
+  if (i >= n) return;
+  const uint64_t v0 = acc0[i], v1 = acc1[i];
+  const int q = (int)(v0 & 0x7FFF);
+  const int ns = (int)((v0 >> 15) & 31);
+  const int sat = (int)((v0 >> 20) & 31);
+  const int sp = (int)((v0 >> 25) & 0x1FFFF) - 2 * q;
+  const int spp = (int)((v0 >> 42) & 0x1FFFF);
+  const int st_ = (int)(v1 & 0x1FFFF) - 2 * q;
+  const int stt = (int)((v1 >> 32) & 0x1FFFF);
+  const uint32_t k = obase + i;
+  if (k >= out.capacity) return;
+  const int ppad = (int)(st_pt[i] & 0xFF);
+  const int ptime = (int)(st_pt[i] >> 8);
+  // exact: numerators below 2^53, quotients far from the rounding gap
+  const double Q = q;
+  const double u = 2.0 * ((double)ppad * Q + sp) - (double)(np - 1) * Q;
+  out.y_fx[k] = (int32_t)floor((u * (double)pfx + Q) / (2.0 * Q));
+  out.z_fx[k] = (int32_t)floor((65536.0 * ((double)ptime * Q + st_) + Q) / (2.0 * Q));
+  const float fq = (float)q;
+  const float mp = (float)sp / fq, mt = (float)st_ / fq;
+  out.dpad[k] = mp;
+  out.dtime[k] = mt;
+  out.s2pad[k] = (float)spp / fq - mp * mp;
+  out.s2time[k] = (float)stt / fq - mt * mt;
+  out.qtot[k] = (uint16_t)q;
+  out.qmax[k] = st_q[i];
+  out.ppad[k] = (uint16_t)ppad;
+  out.ptime[k] = (uint16_t)ptime;
+  out.flags[k] = (uint8_t)(((ppad <= 1 || ppad >= np - 2) ? 1 : 0) | (sat ? 2 : 0));
+  if (out.sp) {
+    out.sp[k] = sp;
+    out.st[k] = st_;
+    out.spp[k] = spp;
+    out.stt[k] = stt;
+    out.nsamp[k] = (uint16_t)ns;
+  }
+}
+
+// Emit pass.  Moments of a batch of peaks accumulate in the staging slots
+// [ns, ns + 31); finished peaks stay staged (across windows of the chunk)
+// until more than 33 are waiting, then all lanes write clusters together.
+#define CL_STAGE 64
 template <int W, int K, int PRE>
 __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* __restrict__ zblk,
                                                      uint32_t nblk, uint32_t nwin, uint32_t nchunk,
@@ -367,21 +423,23 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
   constexpr int ROWS = W + 2 * CL_HALO;
   __shared__ __attribute__((aligned(16))) uint16_t tile[ROWS * CL_TP];
   __shared__ uint16_t pk_cell[CL_SLOTS + 1];
-  // per peak of the batch, packed sums (every field stays below its width:
-  // at most 25 samples of ADC <= 1023 per peak)
+  // per staged peak, packed sums (every field stays below its width: at
+  // most 25 samples of ADC <= 1023 per peak)
   //   acc0: q (15 bits) | n (5 bits) << 15 | n_sat (5 bits) << 20 |
   //         sum a(dp+2) (17 bits) << 25 | sum a dp^2 (17 bits) << 42
   //   acc1: sum a(dt+2) (17 bits) | sum a dt^2 (17 bits) << 32
-  __shared__ unsigned long long acc0[CL_SLOTS + 1], acc1[CL_SLOTS + 1];
+  __shared__ unsigned long long acc0[CL_STAGE], acc1[CL_STAGE];
+  __shared__ uint32_t st_pt[CL_STAGE];  // ptime << 8 | ppad
+  __shared__ uint16_t st_q[CL_STAGE];   // qmax
   if (failed(st)) return;
   const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
   if (ur >= n_ur) return;
   const int r = ur % NROW;
-  const int np = P->np[r], qmin = P->qmax_min;
-  const int64_t pfx = P->pfx[r];
+  const int np = uni(P->np[r]), qmin = uni(P->qmax_min);
+  const int64_t pfx = uni(P->pfx[r]);
   const uint32_t* zb = zblk + (size_t)ur * (nblk + 1);
-  uint32_t rs0 = zb[0], rs1 = zb[nblk];
+  uint32_t rs0 = uni(zb[0]), rs1 = uni(zb[nblk]);
   if (rs1 > in.n_samples) rs1 = in.n_samples;
   if (rs0 > rs1) rs0 = rs1;
   const int w0 = chunk * K;
@@ -390,7 +448,8 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
   WinRange R = window_range<W>(zb, nblk, w0, rs0, rs1);
   SampleRegs<PRE> cur, nxt;
   prefetch(in, R, cur);
-  uint32_t base = chunk_off[(size_t)ur * nchunk + chunk];
+  uint32_t obase = uni(chunk_off[(size_t)ur * nchunk + chunk]);  // output index of staged peak 0
+  uint32_t ns = 0;                                         // staged peaks
   __syncthreads();
   for (int w = w0; w < w1; ++w) {
     const int tile_t0 = w * W - CL_HALO;
@@ -435,12 +494,13 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
     uint32_t done = 0;  // peaks handled in earlier batches
     uint32_t nb = min(total, (uint32_t)CL_SLOTS);
     while (nb > 0) {
-      if (threadIdx.x < CL_SLOTS + 1) {
-        acc0[threadIdx.x] = 0;
-        acc1[threadIdx.x] = 0;
+      if (threadIdx.x < CL_SLOTS) {
+        acc0[ns + threadIdx.x] = 0;
+        acc1[ns + threadIdx.x] = 0;
       }
       __syncthreads();
-      // every sample within two bins of the core adds itself to its peak
+      // every sample within two bins of the core adds itself to its peak;
+      // the offset to the peak is the sum of the two chase steps
       for (uint32_t s0 = R.s_lo; s0 < R.s_hi; s0 += 64) {
         const uint32_t s = s0 + threadIdx.x;
         if (s >= R.s_hi) continue;
@@ -449,72 +509,44 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
         const int lt = (int)(tp >> 16) - tile_t0;
         if (x < 0 || lt < CL_HALO - 2 || lt >= CL_HALO + W + 2) continue;
         const int tx = tile[x];
-        const int y = x + code_offset(chase_code(tx));
+        const int cx = chase_code(tx);
+        const int y = x + code_offset(cx);
         const int ty = tile[y];
-        const int z = y + code_offset(chase_code(ty));
-        const int tz = tile[z];
+        const int cy = chase_code(ty);
+        const int tz = tile[y + code_offset(cy)];
         const int slot = slot_of(tz);
         if (!(tz & CL_PEAK) || slot == CL_SLOTS) continue;
         const uint32_t a = tx & 0x3FF;
-        const int d = x - z;
-        const int dt = (d + 2 * CL_TP + 2) / CL_TP - 2;
-        const int dp = d - dt * CL_TP;
+        const uint32_t dt2 = 4 - (cx >> 2) - (cy >> 2);  // dt + 2, dt = sample - peak
+        const uint32_t dp2 = 4 - (cx & 3) - (cy & 3);
+        const uint32_t dt = dt2 - 2, dp = dp2 - 2;
         const uint64_t v0 = (uint64_t)a | (1ull << 15) | ((uint64_t)(a >= 1023) << 20) |
-                            ((uint64_t)(a * (uint32_t)(dp + 2)) << 25) |
-                            ((uint64_t)(a * (uint32_t)(dp * dp)) << 42);
-        const uint64_t v1 = (uint64_t)(a * (uint32_t)(dt + 2)) |
-                            ((uint64_t)(a * (uint32_t)(dt * dt)) << 32);
-        atomicAdd(&acc0[slot], (unsigned long long)v0);
-        atomicAdd(&acc1[slot], (unsigned long long)v1);
+                            ((uint64_t)(a * dp2) << 25) | ((uint64_t)(a * (dp * dp)) << 42);
+        const uint64_t v1 = (uint64_t)(a * dt2) | ((uint64_t)(a * (dt * dt)) << 32);
+        atomicAdd(&acc0[ns + slot], (unsigned long long)v0);
+        atomicAdd(&acc1[ns + slot], (unsigned long long)v1);
       }
       __syncthreads();
-      const uint32_t i = threadIdx.x;
-      if (i < nb) {
-        const int c = pk_cell[i];
-        const uint64_t v0 = acc0[i], v1 = acc1[i];
-        const int q = (int)(v0 & 0x7FFF);
-        const int ns = (int)((v0 >> 15) & 31);
-        const int sat = (int)((v0 >> 20) & 31);
-        const int sp = (int)((v0 >> 25) & 0x1FFFF) - 2 * q;
-        const int spp = (int)((v0 >> 42) & 0x1FFFF);
-        const int st_ = (int)(v1 & 0x1FFFF) - 2 * q;
-        const int stt = (int)((v1 >> 32) & 0x1FFFF);
-        const uint32_t k = base + done + i;
-        if (k < out.capacity) {
-          const int lt = c / CL_TP;
-          const int ppad = c - lt * CL_TP - 2;
-          const int ptime = lt + tile_t0;
-          // exact: numerators below 2^53, quotients far from the rounding gap
-          const double Q = q;
-          const double u = 2.0 * ((double)ppad * Q + sp) - (double)(np - 1) * Q;
-          out.y_fx[k] = (int32_t)floor((u * (double)pfx + Q) / (2.0 * Q));
-          out.z_fx[k] = (int32_t)floor((65536.0 * ((double)ptime * Q + st_) + Q) / (2.0 * Q));
-          const float fq = (float)q;
-          const float mp = (float)sp / fq, mt = (float)st_ / fq;
-          out.dpad[k] = mp;
-          out.dtime[k] = mt;
-          out.s2pad[k] = (float)spp / fq - mp * mp;
-          out.s2time[k] = (float)stt / fq - mt * mt;
-          out.qtot[k] = (uint16_t)q;
-          out.qmax[k] = (uint16_t)(tile[c] & 0x3FF);
-          out.ppad[k] = (uint16_t)ppad;
-          out.ptime[k] = (uint16_t)ptime;
-          out.flags[k] = (uint8_t)(((ppad <= 1 || ppad >= np - 2) ? 1 : 0) | (sat ? 2 : 0));
-          if (out.sp) {
-            out.sp[k] = sp;
-            out.st[k] = st_;
-            out.spp[k] = spp;
-            out.stt[k] = stt;
-            out.nsamp[k] = (uint16_t)ns;
-          }
-        }
-        // the peak leaves the batch
-        tile[c] = (uint16_t)((tile[c] & 0x43FF) | CL_NOSLOT);
+      if (threadIdx.x < nb) {
+        // stage the batch's peaks; the peak leaves the batch
+        const int c = pk_cell[threadIdx.x];
+        const int cell = tile[c];
+        const int lt = c / CL_TP;
+        st_pt[ns + threadIdx.x] = ((uint32_t)(lt + tile_t0) << 8) | (uint32_t)(c - lt * CL_TP - 2);
+        st_q[ns + threadIdx.x] = (uint16_t)(cell & 0x3FF);
+        tile[c] = (uint16_t)((cell & 0x43FF) | CL_NOSLOT);
       }
+      ns += nb;
       done += nb;
       nb = min(total - done, (uint32_t)CL_SLOTS);
-      if (nb == 0) break;
       __syncthreads();
+      if (ns + CL_SLOTS > CL_STAGE) {
+        emit_staged(acc0, acc1, st_pt, st_q, ns, obase, np, pfx, out);
+        obase += ns;
+        ns = 0;
+        __syncthreads();
+      }
+      if (nb == 0) break;
       // slots for the next batch of core peaks, in sample order
       uint32_t rank = 0;
       for (uint32_t s0 = R.s_lo; s0 < R.c_hi; s0 += 64) {
@@ -532,7 +564,6 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
         rank += (uint32_t)__popcll(m);
       }
     }
-    base += total;
     if (out.sample_label) {
       __syncthreads();
       for (uint32_t s = R.c_lo + threadIdx.x; s < R.c_hi; s += 64) {
@@ -554,6 +585,7 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
     R = Rn;
     cur = nxt;
   }
+  emit_staged(acc0, acc1, st_pt, st_q, ns, obase, np, pfx, out);
 }
 
 // crow_start[ur] = first cluster of (unit,row), from the scanned chunk counts.

@@ -640,31 +640,30 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
   }
 }
 
-__device__ __forceinline__ uint64_t track_key(uint32_t nh, uint32_t t) {
-  return ((uint64_t)nh << 32) | (uint64_t)(0xFFFFFFFFu - t);
+// Claim priority of a track: more hits first, then the lower tracklet id
+// (tracklet ids stay below 2^24, hit counts below 2^8).
+__device__ __forceinline__ uint32_t track_key(uint32_t nh, uint32_t t) {
+  return (nh << 24) | (0xFFFFFFu - t);
 }
 
 // Conflict resolution runs one wave per tracklet: the lanes take the rows
 // of the tracklet's hit table (contiguous), so every table read is coalesced.
 // The tracklet index is made wave-uniform so its scalars load once.
-__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
 
 // Every followed tracklet with enough hits bids for its clusters.
 __global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_tl_dev,
                                                uint32_t tl_cap,
-                                               unsigned long long* __restrict__ owner,
+                                               uint32_t* __restrict__ owner,
                                                uint32_t n_cl_cap, const DevParams* __restrict__ P,
                                                const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t t = wave_uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
+  for (uint32_t t = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
        t += nw) {
     if (!fo.ok[t] || (int)fo.nhits[t] < P->min_track_hits) continue;
-    const unsigned long long key = track_key(fo.nhits[t], t);
+    const uint32_t key = track_key(fo.nhits[t], t);
     const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
     const int32_t* H = fo.hits + (size_t)t * NROW;
     for (int r = lo + (int)lane; r <= hi; r += 64) {
@@ -677,7 +676,7 @@ __global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_t
 // Hits each track keeps after the claims; < min_track_hits drops the track.
 __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl_dev,
                                               uint32_t tl_cap,
-                                              const unsigned long long* __restrict__ owner,
+                                              const uint32_t* __restrict__ owner,
                                               uint32_t n_cl_cap, uint16_t* __restrict__ nkept,
                                               const DevParams* __restrict__ P,
                                               const DevStatus* st) {
@@ -685,11 +684,11 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t t = wave_uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
+  for (uint32_t t = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
        t += nw) {
     uint32_t n = 0;
     if (fo.ok[t] && (int)fo.nhits[t] >= P->min_track_hits) {
-      const unsigned long long key = track_key(fo.nhits[t], t);
+      const uint32_t key = track_key(fo.nhits[t], t);
       const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
       const int32_t* H = fo.hits + (size_t)t * NROW;
       uint8_t* KR = fo.krow + (size_t)t * NROW;
@@ -827,7 +826,7 @@ __global__ __launch_bounds__(64) void k_refit_head(ClusterView cl,
                                                    const uint32_t* __restrict__ tl_start,
                                                    FollowOut fo, const uint32_t* n_tl_dev,
                                                    uint32_t tl_cap,
-                                                   const unsigned long long* __restrict__ owner,
+                                                   const uint32_t* __restrict__ owner,
                                                    const uint16_t* __restrict__ nkept,
                                                    RefitHead hd, const DevParams* __restrict__ P,
                                                    const DevStatus* st) {
@@ -860,7 +859,7 @@ __global__ __launch_bounds__(64) void k_refit_head(ClusterView cl,
 __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* __restrict__ tl_start,
                                                 FollowOut fo, const uint32_t* n_tl_dev,
                                                 uint32_t tl_cap,
-                                                const unsigned long long* __restrict__ owner,
+                                                const uint32_t* __restrict__ owner,
                                                 const uint16_t* __restrict__ nkept, RefitHead hd,
                                                 RefitOut ro, uint32_t* __restrict__ fb_list,
                                                 const DevParams* __restrict__ P, DevStatus* st) {
@@ -996,14 +995,14 @@ __global__ void k_track_totals(const unsigned long long* total, TrackOut to, uin
 
 __global__ __launch_bounds__(256) void k_track_emit(
     ClusterView cl, const uint32_t* __restrict__ tl_start, FollowOut fo, const uint32_t* n_tl_dev,
-    uint32_t tl_cap, const unsigned long long* __restrict__ owner,
+    uint32_t tl_cap, const uint32_t* __restrict__ owner,
     const uint16_t* __restrict__ nkept, RefitOut ro, const uint32_t* __restrict__ trk_index,
     const uint32_t* __restrict__ hit_off, TrackOut to, const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t t = wave_uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
+  for (uint32_t t = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
        t += nw) {
     const uint32_t j = trk_index[t];
     if (j == 0xFFFFFFFFu || j >= to.capacity) continue;
@@ -1028,17 +1027,17 @@ __global__ __launch_bounds__(256) void k_track_emit(
   }
 }
 
-__global__ void k_cluster_track(const unsigned long long* __restrict__ owner,
+__global__ void k_cluster_track(const uint32_t* __restrict__ owner,
                                 const uint32_t* __restrict__ trk_index, const uint32_t* n_cl_dev,
                                 uint32_t n_cl_cap, uint32_t tl_cap, int32_t* __restrict__ out,
                                 const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n = scan_count(n_cl_dev, n_cl_cap);
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-    const unsigned long long key = owner[c];
+    const uint32_t key = owner[c];
     int32_t v = -1;
     if (key) {
-      const uint32_t t = 0xFFFFFFFFu - (uint32_t)key;
+      const uint32_t t = 0xFFFFFFu - (key & 0xFFFFFFu);
       if (t < tl_cap) {
         const uint32_t j = trk_index[t];
         if (j != 0xFFFFFFFFu) v = (int32_t)j;

@@ -69,7 +69,7 @@ struct tpc_ctx {
   uint32_t* f_pts = nullptr;
   uint8_t* f_krow = nullptr;
   int2* pos = nullptr;  // packed cluster positions  // per tracklet: middle and end cluster, unit-row of the start
-  unsigned long long* owner = nullptr;
+  uint32_t* owner = nullptr;
   uint16_t* nkept = nullptr;
   float *r_par = nullptr, *r_cov = nullptr, *r_chi2 = nullptr;
   uint8_t *r_row = nullptr, *r_flags = nullptr;
@@ -139,7 +139,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.f_pts = L.add<uint32_t>(mt * 3);
   p.f_krow = L.add<uint8_t>(mt * NROW);
   p.pos = L.add<int2>(mc);
-  p.owner = L.add<unsigned long long>(mc);
+  p.owner = L.add<uint32_t>(mc);
   p.nkept = L.add<uint16_t>(mt);
   p.r_par = L.add<float>(mt * 5);
   p.r_cov = L.add<float>(mt * 15);
@@ -469,7 +469,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 8);
-    k_fill_dev<unsigned long long><<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, 0ull,
+    k_fill_dev<uint32_t><<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, 0u,
                                                                         cl->n_clusters, ccap);
     // one wave per tracklet, about 8 tracklets per wave
     k_claim<<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->d_par, c->d_st);
@@ -555,7 +555,8 @@ int tpc_geometry(int32_t* npads, int32_t* x_fx, int32_t* pitch_fx) {
 
 int tpc_workspace_size(const tpc_sizes* max, size_t* bytes) {
   if (!max || !bytes) return TPC_ERR_ARG;
-  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65535)
+  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65535 ||
+      max->max_tracklets > (1u << 24))
     return TPC_ERR_ARG;
   *bytes = plan_for(*max).total;
   return TPC_OK;
@@ -564,7 +565,8 @@ int tpc_workspace_size(const tpc_sizes* max, size_t* bytes) {
 int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* hip_stream) {
   if (!out || !p || !max) return TPC_ERR_ARG;
   *out = nullptr;
-  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65535)
+  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65535 ||
+      max->max_tracklets > (1u << 24))
     return TPC_ERR_ARG;
   if (p->min_tracklet < 3 || p->min_tracklet > NROW || p->min_track_hits < 3 || p->max_miss < 1 ||
       p->qmax_min < 1 || !(p->chi2_max > 0) || !(p->snp_max > 0 && p->snp_max < 1) ||
@@ -602,7 +604,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->f_pts = (uint32_t*)(base + pl.f_pts);
   c->f_krow = (uint8_t*)(base + pl.f_krow);
   c->pos = (int2*)(base + pl.pos);
-  c->owner = (unsigned long long*)(base + pl.owner);
+  c->owner = (uint32_t*)(base + pl.owner);
   c->nkept = (uint16_t*)(base + pl.nkept);
   c->r_par = (float*)(base + pl.r_par);
   c->r_cov = (float*)(base + pl.r_cov);

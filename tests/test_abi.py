@@ -67,6 +67,8 @@ def test_workspace_size():
         tpc.workspace_size(0, 500, 10, 10)
     with pytest.raises(tpc.TpcError):
         tpc.workspace_size(1, 70_000, 10, 10)
+    with pytest.raises(tpc.TpcError):  # tracklet ids must fit the 24-bit claim key
+        tpc.workspace_size(1, 500, 10, (1 << 24) + 1)
 
 
 def test_create_rejects_bad_arguments_before_touching_the_device():
