@@ -41,14 +41,16 @@ def log(*a):
 # Algorithmic bytes each stage must move, per unit of work:
 # samples are (pad, time, adc) u16; a cluster record is y_fx, z_fx (i32),
 # pad, time, s2pad, s2time (f32), qtot, qmax, ppad, ptime (u16), flags (u8).
-def stage_bytes(ns, nc, n_ur, T):
+def stage_bytes(ns, nc, n_ur, T, W=16):
     rec = 4 * 2 + 4 * 4 + 2 * 4 + 1
+    raw = 24                 # raw record per cluster between the two clusterizer passes
     nblk_s = (T + 3) // 4   # sample index: one entry per 4 time bins
     nblk_c = (T + 7) // 8   # cluster grid: one entry per 8 time bins
+    nwin = n_ur * ((T + W - 1) // W)
     return {
         "sample_index": 2 * ns + 4 * n_ur * (nblk_s + 1),
-        "cluster_count": 6 * ns,
-        "cluster_emit": 6 * ns + rec * nc,
+        "cluster_peaks": 6 * ns + raw * nc + 4 * nwin,
+        "cluster_output": raw * nc + rec * nc + 4 * nwin,
         "cluster_grid": 2 * nc + 4 * n_ur * (nblk_c + 1),
         "neighbours": 8 * nc + 8 * nc,
     }
@@ -76,7 +78,7 @@ def pmc_traffic(kernel_file, stage, kernel_name):
 
 def make_reco(tpc, ev, stream, max_clusters, max_tracklets, noise):
     return tpc.Reco(ev.n_units, ev.n_time_bins, max_clusters, max_tracklets,
-                    noise_sigma=noise, stream=stream)
+                    noise_sigma=noise, stream=stream, max_samples=max(ev.n_samples, 1))
 
 
 def buffers(reco, ev, max_clusters, max_tracklets):
@@ -127,7 +129,8 @@ def serve_leg(args, torch, tpcsynth, tuning):
     max_tl = max(j.tl_cap for j in pool)
     log(f"[bench] serving pool: {[j.n_time_bins // 100 - 5 for j in pool]} collisions, "
         f"{sum(j.n_samples for j in pool)} samples, made in {time.perf_counter() - t:.1f}s")
-    ex = serve.GpuExecutor(args.serve_slots, 36, T, max_cl, max_tl, tuning=tuning)
+    ex = serve.GpuExecutor(args.serve_slots, 36, T, max_cl, max_tl, tuning=tuning,
+                           max_samples=max(j.n_samples for j in pool))
     free, _ = torch.cuda.mem_get_info()
     budget = int(free * 0.8)
 
@@ -175,7 +178,8 @@ def stress_leg(torch, tpcsynth, tpc, stream, n_coll=20):
     ev = tpcsynth.generate(tpcsynth.config_chunk(505, 0, stress=True, n_coll=n_coll), 505)
     mc = max(ev.n_samples // 6, 1 << 16)
     mt = max(mc // 8, 1 << 14)
-    reco = tpc.Reco(ev.n_units, ev.n_time_bins, mc, mt, noise_sigma=2.0, stream=stream)
+    reco = tpc.Reco(ev.n_units, ev.n_time_bins, mc, mt, noise_sigma=2.0, stream=stream,
+                    max_samples=ev.n_samples)
     zs = tpc.to_device_zs(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins)
     b = buffers(reco, ev, mc, mt)
     with torch.cuda.stream(stream):
@@ -317,12 +321,14 @@ def main():
 
     # roofline of the dominant HBM-bound stage
     n_ur = ev.n_units * 152
-    sb = stage_bytes(ns, nc, n_ur, ev.n_time_bins)
+    sb = stage_bytes(ns, nc, n_ur, ev.n_time_bins,
+                     tuning["chosen"]["cl_window"] if tuning else 16)
     dom = max(stages, key=lambda k: stages[k])
     hbm_dom = max(sb, key=lambda k: stages.get(k, 0.0))
     ach = sb[hbm_dom] / (stages[hbm_dom] / 1e3) / 1e9
     tn = tuning["chosen"] if tuning else {"cl_window": 16, "cl_chunk": 8}
-    kname = f"void k_{hbm_dom}<{tn['cl_window']}, {tn['cl_chunk']},"
+    kname = (f"void k_cluster_peaks<{tn['cl_window']}, {tn['cl_chunk']},"
+             if hbm_dom == "cluster_peaks" else f"void k_{hbm_dom}<{tn['cl_window']}>")
     traffic = pmc_traffic("paper_2208_07412_amd/csrc/k_cluster.hpp", hbm_dom, kname) \
         if hbm_dom.startswith("cluster_") else None
     roofline = dict(bound="hbm", kernel=hbm_dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",

@@ -90,6 +90,7 @@ typedef struct {
   uint32_t max_time_bins; /* time bins per unit (< 65536) */
   uint32_t max_clusters;  /* clusters per call */
   uint32_t max_tracklets; /* tracklets per call, at most 2^24 */
+  uint32_t max_samples;   /* zero-suppressed samples per call (24 bytes of scratch each) */
 } tpc_sizes;
 
 /* Zero-suppressed input: samples sorted by (unit, row, time, pad). */
@@ -190,7 +191,8 @@ int tpc_destroy(tpc_ctx* ctx);
 /* Clusterizer: peaks are samples whose (adc, time, pad) key exceeds that of
  * every present 8-neighbour and whose ADC reaches qmax_min; each sample joins
  * the peak it reaches in at most two uphill steps.  Writes n_clusters,
- * crow_start and every non-NULL per-cluster array. */
+ * crow_start and every non-NULL per-cluster array.  in->n_samples must not
+ * exceed the context's max_samples (TPC_ERR_ARG). */
 int tpc_cluster(tpc_ctx* ctx, const tpc_zs_input* in, tpc_clusters* out);
 
 /* For each cluster in rows 1..150: the pair (j in row r-1, k in row r+1)
@@ -226,9 +228,10 @@ void* tpc_stream(tpc_ctx* ctx);
  * around each of the TPC_PROF_STAGES stages below; tpc_profile_read waits
  * for the stream, writes the summed milliseconds and the number of timed
  * launches per stage, and clears them.  Leave it off while a launch sequence
- * is captured into a HIP graph.  Stages: 0 sample index, 1 cluster count,
- * 2 cluster scan, 3 cluster emit, 4 cluster grid, 5 neighbours, 6 tracklets,
- * 7 following, 8 resolution, 9 refit FP32, 10 refit FP64, 11 track output. */
+ * is captured into a HIP graph.  Stages: 0 sample index, 1 cluster peaks
+ * (peak finding and moments, one pass over the samples), 2 cluster scan,
+ * 3 cluster output, 4 cluster grid, 5 neighbours, 6 tracklets, 7 following,
+ * 8 resolution, 9 refit FP32, 10 refit FP64, 11 track output. */
 #define TPC_PROF_STAGES 12
 int tpc_profile_enable(tpc_ctx* ctx, int on);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, uint32_t* launches);

@@ -13,7 +13,7 @@ from typing import Dict, List, Tuple
 
 CLUSTER_SHAPES: List[Tuple[int, int]] = [(16, 4), (16, 8), (16, 16), (32, 4), (32, 8), (32, 16)]
 FOLLOW_BLOCKS: List[int] = [64, 128, 256]
-CLUSTER_STAGES = ("sample_index", "cluster_count", "cluster_scan", "cluster_emit")
+CLUSTER_STAGES = ("sample_index", "cluster_peaks", "cluster_scan", "cluster_output")
 FOLLOW_STAGES = ("following",)
 
 

@@ -6,10 +6,11 @@
 // ("up code", the argmax of the (adc, time, pad) key over the 3x3
 // neighbourhood, encoded (dt+1)*4 + (dp+1), 5 = itself) and every peak
 // accumulates the samples of its 5x5 window that reach it in at most two
-// uphill steps.  Clusters are written in the order of their peaks (time, then
-// pad): a count pass gives every chunk of K windows its number of peaks, a
-// device-wide scan turns the counts into output offsets, and the emit pass
-// writes each cluster at its final index with no atomics on the outputs.
+// uphill steps.  Clusters come out in the order of their peaks (time, then
+// pad): the peak pass writes one raw record per peak beside the window's
+// samples and each window's peak count, a device-wide scan turns the counts
+// into output offsets, and the output pass writes each cluster at its final
+// index, with no atomics on the outputs.
 #pragma once
 
 #include "common.hpp"
@@ -309,16 +310,36 @@ __device__ __forceinline__ void clear_tile(uint16_t* tile) {
   for (int i = N4 * 8 + threadIdx.x; i < TILE; i += 64) tile[i] = 0;
 }
 
-// Number of peaks of every chunk of K windows.
+// Raw record of one cluster, written by the peak pass at the sample index of
+// the window's first core sample plus the peak's rank in the window (a
+// window has no more peaks than core samples, so windows never overlap):
+//   m0: q (15 bits) | n (5 bits) << 15 | n_sat (5 bits) << 20 |
+//       sum a(dp+2) (17 bits) << 25 | sum a dp^2 (17 bits) << 42
+//   m1: sum a(dt+2) (17 bits) | sum a dt^2 (17 bits) << 32
+//   m2: ppad | ptime << 8 | qmax << 32
+// Every field stays below its width: at most 25 samples of ADC <= 1023 per
+// peak.
+struct ClusterRec {
+  unsigned long long m0, m1, m2;
+};
+
+// Peak pass: one wave walks K windows of one (unit,row); per window it
+// finds the up codes and peaks, accumulates each peak's moments in LDS
+// (batches of CL_SLOTS peaks), writes one raw record per peak and the
+// window's peak count.
 template <int W, int K, int PRE>
-__global__ __launch_bounds__(64) void k_cluster_count(ZsArgs in, const uint32_t* __restrict__ zblk,
+__global__ __launch_bounds__(64) void k_cluster_peaks(ZsArgs in, const uint32_t* __restrict__ zblk,
                                                       uint32_t nblk, uint32_t nwin,
                                                       uint32_t nchunk, uint32_t n_ur,
-                                                      uint32_t* __restrict__ chunk_cnt,
+                                                      uint32_t* __restrict__ win_cnt,
+                                                      ClusterRec* __restrict__ rec,
+                                                      int32_t* __restrict__ sample_label,
                                                       const DevParams* __restrict__ P,
                                                       const DevStatus* st) {
   constexpr int ROWS = W + 2 * CL_HALO;
   __shared__ __attribute__((aligned(16))) uint16_t tile[ROWS * CL_TP];
+  __shared__ uint16_t pk_cell[CL_SLOTS + 1];
+  __shared__ unsigned long long acc0[CL_SLOTS + 1], acc1[CL_SLOTS + 1];
   if (failed(st)) return;
   const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
@@ -334,122 +355,6 @@ __global__ __launch_bounds__(64) void k_cluster_count(ZsArgs in, const uint32_t*
   WinRange R = window_range<W>(zb, nblk, w0, rs0, rs1);
   SampleRegs<PRE> cur, nxt;
   prefetch(in, R, cur);
-  __syncthreads();
-  uint32_t cnt = 0;
-  for (int w = w0; w < w1; ++w) {
-    const int tile_t0 = w * W - CL_HALO;
-    scatter<ROWS>(tile, in, R, cur, tile_t0, np, true);
-    WinRange Rn = R;
-    if (w + 1 < w1) {
-      Rn = window_range<W>(zb, nblk, w + 1, rs0, rs1);
-      prefetch(in, Rn, nxt);
-    }
-    __syncthreads();
-    for (uint32_t s0 = R.s_lo; s0 < R.c_hi; s0 += 64) {
-      const uint32_t s = s0 + threadIdx.x;
-      bool pk = false;
-      if (s >= R.c_lo && s < R.c_hi) {
-        const int c = cell_of<ROWS>(sample_tp(in, cur, (s0 - R.s_lo) >> 6, s), tile_t0, np);
-        pk = c >= 0 && is_peak(tile, c, qmin);
-      }
-      cnt += __popcll(__ballot(pk));
-    }
-    __syncthreads();
-    scatter<ROWS>(tile, in, R, cur, tile_t0, np, false);
-    __syncthreads();
-    R = Rn;
-    cur = nxt;
-  }
-  if (threadIdx.x == 0) chunk_cnt[(size_t)ur * nchunk + chunk] = cnt;
-}
-
-// Output of the staged peaks [0, n): one lane per cluster.
-__device__ __forceinline__ void emit_staged(const unsigned long long* acc0,
-                                            const unsigned long long* acc1,
-                                            const uint32_t* st_pt, const uint16_t* st_q,
-                                            uint32_t n, uint32_t obase, int np, int64_t pfx,
-                                            const ClusterOut& out) {
-  const uint32_t i = threadIdx.x;
-  if (i >= n) return;
-  const uint64_t v0 = acc0[i], v1 = acc1[i];
-  const int q = (int)(v0 & 0x7FFF);
-  const int ns = (int)((v0 >> 15) & 31);
-  const int sat = (int)((v0 >> 20) & 31);
-  const int sp = (int)((v0 >> 25) & 0x1FFFF) - 2 * q;
-  const int spp = (int)((v0 >> 42) & 0x1FFFF);
-  const int st_ = (int)(v1 & 0x1FFFF) - 2 * q;
-  const int stt = (int)((v1 >> 32) & 0x1FFFF);
-  const uint32_t k = obase + i;
-  if (k >= out.capacity) return;
-  const int ppad = (int)(st_pt[i] & 0xFF);
-  const int ptime = (int)(st_pt[i] >> 8);
-  // exact: numerators below 2^53, quotients far from the rounding gap
-  const double Q = q;
-  const double u = 2.0 * ((double)ppad * Q + sp) - (double)(np - 1) * Q;
-  out.y_fx[k] = (int32_t)floor((u * (double)pfx + Q) / (2.0 * Q));
-  out.z_fx[k] = (int32_t)floor((65536.0 * ((double)ptime * Q + st_) + Q) / (2.0 * Q));
-  const float fq = (float)q;
-  const float mp = (float)sp / fq, mt = (float)st_ / fq;
-  out.dpad[k] = mp;
-  out.dtime[k] = mt;
-  out.s2pad[k] = (float)spp / fq - mp * mp;
-  out.s2time[k] = (float)stt / fq - mt * mt;
-  out.qtot[k] = (uint16_t)q;
-  out.qmax[k] = st_q[i];
-  out.ppad[k] = (uint16_t)ppad;
-  out.ptime[k] = (uint16_t)ptime;
-  out.flags[k] = (uint8_t)(((ppad <= 1 || ppad >= np - 2) ? 1 : 0) | (sat ? 2 : 0));
-  if (out.sp) {
-    out.sp[k] = sp;
-    out.st[k] = st_;
-    out.spp[k] = spp;
-    out.stt[k] = stt;
-    out.nsamp[k] = (uint16_t)ns;
-  }
-}
-
-// Emit pass.  Moments of a batch of peaks accumulate in the staging slots
-// [ns, ns + 31); finished peaks stay staged (across windows of the chunk)
-// until more than 33 are waiting, then all lanes write clusters together.
-#define CL_STAGE 64
-template <int W, int K, int PRE>
-__global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* __restrict__ zblk,
-                                                     uint32_t nblk, uint32_t nwin, uint32_t nchunk,
-                                                     uint32_t n_ur,
-                                                     const uint32_t* __restrict__ chunk_off,
-                                                     ClusterOut out,
-                                                     const DevParams* __restrict__ P,
-                                                     const DevStatus* st) {
-  constexpr int ROWS = W + 2 * CL_HALO;
-  __shared__ __attribute__((aligned(16))) uint16_t tile[ROWS * CL_TP];
-  __shared__ uint16_t pk_cell[CL_SLOTS + 1];
-  // per staged peak, packed sums (every field stays below its width: at
-  // most 25 samples of ADC <= 1023 per peak)
-  //   acc0: q (15 bits) | n (5 bits) << 15 | n_sat (5 bits) << 20 |
-  //         sum a(dp+2) (17 bits) << 25 | sum a dp^2 (17 bits) << 42
-  //   acc1: sum a(dt+2) (17 bits) | sum a dt^2 (17 bits) << 32
-  __shared__ unsigned long long acc0[CL_STAGE], acc1[CL_STAGE];
-  __shared__ uint32_t st_pt[CL_STAGE];  // ptime << 8 | ppad
-  __shared__ uint16_t st_q[CL_STAGE];   // qmax
-  if (failed(st)) return;
-  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
-  if (ur >= n_ur) return;
-  const int r = ur % NROW;
-  const int np = uni(P->np[r]), qmin = uni(P->qmax_min);
-  const int64_t pfx = uni(P->pfx[r]);
-  const uint32_t* zb = zblk + (size_t)ur * (nblk + 1);
-  uint32_t rs0 = uni(zb[0]), rs1 = uni(zb[nblk]);
-  if (rs1 > in.n_samples) rs1 = in.n_samples;
-  if (rs0 > rs1) rs0 = rs1;
-  const int w0 = chunk * K;
-  const int w1 = min((int)nwin, w0 + K);
-  clear_tile<ROWS>(tile);
-  WinRange R = window_range<W>(zb, nblk, w0, rs0, rs1);
-  SampleRegs<PRE> cur, nxt;
-  prefetch(in, R, cur);
-  uint32_t obase = uni(chunk_off[(size_t)ur * nchunk + chunk]);  // output index of staged peak 0
-  uint32_t ns = 0;                                         // staged peaks
   __syncthreads();
   for (int w = w0; w < w1; ++w) {
     const int tile_t0 = w * W - CL_HALO;
@@ -491,12 +396,13 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
       }
       total += (uint32_t)__popcll(m);
     }
-    uint32_t done = 0;  // peaks handled in earlier batches
+    ClusterRec* wrec = rec + R.c_lo;  // this window's records
+    uint32_t done = 0;                // peaks handled in earlier batches
     uint32_t nb = min(total, (uint32_t)CL_SLOTS);
     while (nb > 0) {
       if (threadIdx.x < CL_SLOTS) {
-        acc0[ns + threadIdx.x] = 0;
-        acc1[ns + threadIdx.x] = 0;
+        acc0[threadIdx.x] = 0;
+        acc1[threadIdx.x] = 0;
       }
       __syncthreads();
       // every sample within two bins of the core adds itself to its peak;
@@ -523,30 +429,29 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
         const uint64_t v0 = (uint64_t)a | (1ull << 15) | ((uint64_t)(a >= 1023) << 20) |
                             ((uint64_t)(a * dp2) << 25) | ((uint64_t)(a * (dp * dp)) << 42);
         const uint64_t v1 = (uint64_t)(a * dt2) | ((uint64_t)(a * (dt * dt)) << 32);
-        atomicAdd(&acc0[ns + slot], (unsigned long long)v0);
-        atomicAdd(&acc1[ns + slot], (unsigned long long)v1);
+        atomicAdd(&acc0[slot], (unsigned long long)v0);
+        atomicAdd(&acc1[slot], (unsigned long long)v1);
       }
       __syncthreads();
       if (threadIdx.x < nb) {
-        // stage the batch's peaks; the peak leaves the batch
+        // the batch's records; the peak leaves the batch
         const int c = pk_cell[threadIdx.x];
         const int cell = tile[c];
         const int lt = c / CL_TP;
-        st_pt[ns + threadIdx.x] = ((uint32_t)(lt + tile_t0) << 8) | (uint32_t)(c - lt * CL_TP - 2);
-        st_q[ns + threadIdx.x] = (uint16_t)(cell & 0x3FF);
+        const uint64_t meta = (uint64_t)(uint32_t)(c - lt * CL_TP - 2) |
+                              ((uint64_t)(uint32_t)(lt + tile_t0) << 8) |
+                              ((uint64_t)(cell & 0x3FF) << 32);
+        ClusterRec rr;
+        rr.m0 = acc0[threadIdx.x];
+        rr.m1 = acc1[threadIdx.x];
+        rr.m2 = meta;
+        wrec[done + threadIdx.x] = rr;
         tile[c] = (uint16_t)((cell & 0x43FF) | CL_NOSLOT);
       }
-      ns += nb;
       done += nb;
       nb = min(total - done, (uint32_t)CL_SLOTS);
-      __syncthreads();
-      if (ns + CL_SLOTS > CL_STAGE) {
-        emit_staged(acc0, acc1, st_pt, st_q, ns, obase, np, pfx, out);
-        obase += ns;
-        ns = 0;
-        __syncthreads();
-      }
       if (nb == 0) break;
+      __syncthreads();
       // slots for the next batch of core peaks, in sample order
       uint32_t rank = 0;
       for (uint32_t s0 = R.s_lo; s0 < R.c_hi; s0 += 64) {
@@ -564,7 +469,8 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
         rank += (uint32_t)__popcll(m);
       }
     }
-    if (out.sample_label) {
+    if (threadIdx.x == 0) win_cnt[(size_t)ur * nwin + w] = total;
+    if (sample_label) {
       __syncthreads();
       for (uint32_t s = R.c_lo + threadIdx.x; s < R.c_hi; s += 64) {
         const uint32_t tp = ((uint32_t)in.time[s] << 16) | in.pad[s];
@@ -576,7 +482,7 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
           const int z = y + code_offset(chase_code(tile[y]));
           if (tile[z] & CL_PEAK) lab = ((z / CL_TP + tile_t0) << 8) | (z % CL_TP - 2);
         }
-        out.sample_label[s] = lab;
+        sample_label[s] = lab;
       }
     }
     __syncthreads();
@@ -585,17 +491,103 @@ __global__ __launch_bounds__(64) void k_cluster_emit(ZsArgs in, const uint32_t* 
     R = Rn;
     cur = nxt;
   }
-  emit_staged(acc0, acc1, st_pt, st_q, ns, obase, np, pfx, out);
 }
 
-// crow_start[ur] = first cluster of (unit,row), from the scanned chunk counts.
-__global__ void k_crow_start(const uint32_t* __restrict__ chunk_off, uint32_t nchunk,
+// Output pass: clusters from the raw records, one thread per cluster.  A
+// workgroup takes 256 consecutive windows (of all units and rows, in
+// canonical order): their scanned counts give each cluster its window and
+// rank, the window's first core sample gives the record.
+template <int W>
+__global__ __launch_bounds__(256) void k_cluster_output(const uint32_t* __restrict__ win_off,
+                                                     const uint32_t* __restrict__ n_clusters,
+                                                     uint32_t nwin, uint32_t n_ur,
+                                                     const uint32_t* __restrict__ zblk,
+                                                     uint32_t nblk, uint32_t n_samples,
+                                                     const ClusterRec* __restrict__ rec,
+                                                     ClusterOut out, const DevParams* __restrict__ P,
+                                                     const DevStatus* st) {
+  __shared__ uint32_t off[257], clo[256];
+  if (failed(st)) return;
+  const uint32_t nw_all = n_ur * nwin;
+  const uint32_t total = *n_clusters;
+  for (uint32_t wb = blockIdx.x * 256u; wb < nw_all; wb += gridDim.x * 256u) {
+    const uint32_t g = wb + threadIdx.x;
+    if (g < nw_all) {
+      off[threadIdx.x] = win_off[g];
+      const uint32_t ur = g / nwin, w = g % nwin;
+      const uint32_t* zb = zblk + (size_t)ur * (nblk + 1);
+      uint32_t rs0 = zb[0], rs1 = zb[nblk];
+      if (rs1 > n_samples) rs1 = n_samples;
+      if (rs0 > rs1) rs0 = rs1;
+      uint32_t a, b;
+      row_range(zb, nblk, (int32_t)(w * (W >> CL_BSHIFT)), (int32_t)((w + 1) * (W >> CL_BSHIFT)),
+                rs0, rs1, a, b);
+      clo[threadIdx.x] = a;
+    }
+    if (threadIdx.x == 0) off[min(256u, nw_all - wb)] = wb + 256 < nw_all ? win_off[wb + 256] : total;
+    __syncthreads();
+    const uint32_t nt = min(256u, nw_all - wb);
+    const uint32_t c0 = off[0], c1 = off[nt];
+    for (uint32_t k = c0 + threadIdx.x; k < c1; k += 256) {
+      // window of cluster k: last j with off[j] <= k
+      uint32_t lo = 0, hi = nt;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid;
+        else hi = mid;
+      }
+      if (k >= out.capacity) continue;
+      const uint32_t g = wb + lo;
+      const ClusterRec rr = rec[clo[lo] + (k - off[lo])];
+      const int np = P->np[(g / nwin) % NROW];
+      const int64_t pfx = P->pfx[(g / nwin) % NROW];
+      const uint64_t v0 = rr.m0, v1 = rr.m1, v2 = rr.m2;
+      const int q = (int)(v0 & 0x7FFF);
+      const int ns = (int)((v0 >> 15) & 31);
+      const int sat = (int)((v0 >> 20) & 31);
+      const int sp = (int)((v0 >> 25) & 0x1FFFF) - 2 * q;
+      const int spp = (int)((v0 >> 42) & 0x1FFFF);
+      const int st_ = (int)(v1 & 0x1FFFF) - 2 * q;
+      const int stt = (int)((v1 >> 32) & 0x1FFFF);
+      const int ppad = (int)(v2 & 0xFF);
+      const int ptime = (int)((v2 >> 8) & 0xFFFF);
+      // exact: numerators below 2^53, quotients far from the rounding gap
+      const double Q = q;
+      const double u = 2.0 * ((double)ppad * Q + sp) - (double)(np - 1) * Q;
+      out.y_fx[k] = (int32_t)floor((u * (double)pfx + Q) / (2.0 * Q));
+      out.z_fx[k] = (int32_t)floor((65536.0 * ((double)ptime * Q + st_) + Q) / (2.0 * Q));
+      const float fq = (float)q;
+      const float mp = (float)sp / fq, mt = (float)st_ / fq;
+      out.dpad[k] = mp;
+      out.dtime[k] = mt;
+      out.s2pad[k] = (float)spp / fq - mp * mp;
+      out.s2time[k] = (float)stt / fq - mt * mt;
+      out.qtot[k] = (uint16_t)q;
+      out.qmax[k] = (uint16_t)(v2 >> 32);
+      out.ppad[k] = (uint16_t)ppad;
+      out.ptime[k] = (uint16_t)ptime;
+      out.flags[k] = (uint8_t)(((ppad <= 1 || ppad >= np - 2) ? 1 : 0) | (sat ? 2 : 0));
+      if (out.sp) {
+        out.sp[k] = sp;
+        out.st[k] = st_;
+        out.spp[k] = spp;
+        out.stt[k] = stt;
+        out.nsamp[k] = (uint16_t)ns;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// crow_start[ur] = first cluster of (unit,row), from the scanned window
+// counts (nwin windows per unit-row).
+__global__ void k_crow_start(const uint32_t* __restrict__ win_off, uint32_t nwin,
                              uint32_t n_ur, const uint32_t* __restrict__ n_clusters,
                              uint32_t capacity, uint32_t* __restrict__ crow, DevStatus* st) {
   const uint32_t n = *n_clusters;
   for (uint32_t ur = blockIdx.x * blockDim.x + threadIdx.x; ur <= n_ur;
        ur += gridDim.x * blockDim.x)
-    crow[ur] = ur < n_ur ? chunk_off[(size_t)ur * nchunk] : n;
+    crow[ur] = ur < n_ur ? win_off[(size_t)ur * nwin] : n;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->n_clusters = n;
     if (n > capacity) latch(st, TPC_ERR_CAPACITY, n);

@@ -21,8 +21,8 @@
 namespace {
 
 // Clusterizer tile shapes compiled into the library (window in time bins,
-// windows per workgroup); the smallest product sizes the chunk-count scratch.
-constexpr uint32_t kMinWinChunk = 16 * 4;
+// windows per workgroup); the smallest window sizes the window-count scratch.
+constexpr uint32_t kMinWin = 16;
 
 struct Geometry {
   int32_t np[NROW], xfx[NROW], pfx[NROW];
@@ -56,7 +56,8 @@ struct tpc_ctx {
   // scratch
   uint32_t* zblk = nullptr;   // sample block index
   uint32_t* cblk = nullptr;   // cluster block index (hit grid)
-  uint32_t* win = nullptr;    // clusterizer chunk counts / offsets
+  uint32_t* win = nullptr;    // clusterizer window counts / offsets
+  ClusterRec* crec = nullptr;  // raw cluster records, indexed like the samples
   void* bsum = nullptr;       // scan block sums (u64)
   unsigned long long* tot64 = nullptr;
   uint32_t* tot32 = nullptr;
@@ -104,11 +105,11 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_krow, pos,
+  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_krow, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
       h_flags, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
-  uint32_t nblk, nblk_s, nchunk;
+  uint32_t nblk, nblk_s, nwin;
 };
 
 Plan plan_for(const tpc_sizes& m) {
@@ -117,8 +118,8 @@ Plan plan_for(const tpc_sizes& m) {
   const uint64_t nur = (uint64_t)m.max_units * NROW;
   p.nblk = ceil_div(m.max_time_bins, 8);
   p.nblk_s = ceil_div(m.max_time_bins, 1u << CL_BSHIFT);
-  p.nchunk = ceil_div(m.max_time_bins, kMinWinChunk) + 1;
-  uint64_t nscan = nur * p.nchunk;
+  p.nwin = ceil_div(m.max_time_bins, kMinWin);
+  uint64_t nscan = nur * p.nwin;
   if (m.max_clusters > nscan) nscan = m.max_clusters;
   if (m.max_tracklets > nscan) nscan = m.max_tracklets;
   p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
@@ -126,7 +127,8 @@ Plan plan_for(const tpc_sizes& m) {
   const uint64_t mt = m.max_tracklets > 0 ? m.max_tracklets : 1;
   p.zblk = L.add<uint32_t>(nur * (p.nblk_s + 1));
   p.cblk = L.add<uint32_t>(nur * (p.nblk + 1));
-  p.win = L.add<uint32_t>(nur * p.nchunk);
+  p.win = L.add<uint32_t>(nur * p.nwin);
+  p.crec = L.add<ClusterRec>(m.max_samples > 0 ? m.max_samples : 1);
   p.bsum = L.add<unsigned long long>(p.bsum_cap);
   p.tot64 = L.add<unsigned long long>(1);
   p.tot32 = L.add<uint32_t>(1);
@@ -292,6 +294,7 @@ int check_units(tpc_ctx* c, uint32_t n_units, uint32_t n_time_bins) {
 
 int check_input(tpc_ctx* c, const tpc_zs_input* in) {
   if (!in) return TPC_ERR_ARG;
+  if (in->n_samples > c->max.max_samples) return TPC_ERR_ARG;
   if (check_units(c, in->n_units, in->n_time_bins)) return TPC_ERR_ARG;
   if (!in->row_start) return TPC_ERR_ARG;
   if (in->n_samples && (!in->pad || !in->time || !in->adc)) return TPC_ERR_ARG;
@@ -345,22 +348,25 @@ void launch_cluster(tpc_ctx* c, const ZsArgs& za, uint32_t nblk_s, uint32_t n_ur
   const uint32_t nwin = ceil_div(za.n_time_bins, W);
   const uint32_t nchunk = ceil_div(nwin, K);
   const uint32_t ngrid = n_ur * nchunk;
+  const uint32_t nwt = n_ur * nwin;
   {
     StageTimer tm(c, 1);
-    k_cluster_count<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur,
-                                                     c->win, c->d_par, c->d_st);
+    k_cluster_peaks<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur,
+                                                     c->win, c->crec, co.sample_label, c->d_par,
+                                                     c->d_st);
   }
   {
     StageTimer tm(c, 2);
-    run_scan<uint32_t>(c, GetU32{c->win}, EmitU32{c->win}, nullptr, ngrid, (uint32_t*)nullptr,
+    run_scan<uint32_t>(c, GetU32{c->win}, EmitU32{c->win}, nullptr, nwt, (uint32_t*)nullptr,
                        n_clusters);
-    k_crow_start<<<grid_for(n_ur + 1, 256), 256, 0, s>>>(c->win, nchunk, n_ur, n_clusters,
-                                                         capacity, crow_start, c->d_st);
+    k_crow_start<<<grid_for(n_ur + 1, 256), 256, 0, s>>>(c->win, nwin, n_ur, n_clusters, capacity,
+                                                         crow_start, c->d_st);
   }
   {
     StageTimer tm(c, 3);
-    k_cluster_emit<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur, c->win,
-                                                    co, c->d_par, c->d_st);
+    k_cluster_output<W><<<grid_for(nwt, 256), 256, 0, s>>>(c->win, n_clusters, nwin, n_ur, c->zblk,
+                                                        nblk_s, za.n_samples, c->crec, co,
+                                                        c->d_par, c->d_st);
   }
 }
 
@@ -592,6 +598,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->zblk = (uint32_t*)(base + pl.zblk);
   c->cblk = (uint32_t*)(base + pl.cblk);
   c->win = (uint32_t*)(base + pl.win);
+  c->crec = (ClusterRec*)(base + pl.crec);
   c->bsum = base + pl.bsum;
   c->tot64 = (unsigned long long*)(base + pl.tot64);
   c->tot32 = (uint32_t*)(base + pl.tot32);
@@ -752,7 +759,7 @@ int tpc_profile_read(tpc_ctx* c, double* ms, uint32_t* launches) {
 
 const char* tpc_profile_stage_name(int i) {
   static const char* names[TPC_PROF_STAGES] = {
-      "sample_index", "cluster_count", "cluster_scan", "cluster_emit", "cluster_grid",
+      "sample_index", "cluster_peaks", "cluster_scan", "cluster_output", "cluster_grid",
       "neighbours", "tracklets", "following", "resolution", "refit_fp32", "refit_fp64",
       "track_output"};
   return (i >= 0 && i < TPC_PROF_STAGES) ? names[i] : "unknown";

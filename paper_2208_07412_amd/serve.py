@@ -176,7 +176,8 @@ class GpuExecutor:
 
     def __init__(self, n_slots: int, max_units: int, max_time_bins: int, max_clusters: int,
                  max_tracklets: int, param_overrides: Optional[dict] = None,
-                 noise_sigma: float = 1.0, keep_outputs: bool = False, tuning: Optional[dict] = None):
+                 noise_sigma: float = 1.0, keep_outputs: bool = False, tuning: Optional[dict] = None,
+                 max_samples: Optional[int] = None):
         import torch
 
         self.torch = torch
@@ -186,7 +187,7 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self.recos = [tpc.Reco(max_units, max_time_bins, max_clusters, max_tracklets,
                                param_overrides=param_overrides, noise_sigma=noise_sigma,
-                               stream=s) for s in self.streams]
+                               stream=s, max_samples=max_samples) for s in self.streams]
         if tuning:
             for r in self.recos:
                 r.set_tuning(**tuning)

@@ -40,7 +40,7 @@ class TpcParams(ctypes.Structure):
 
 class TpcSizes(ctypes.Structure):
     _fields_ = [("max_units", U32), ("max_time_bins", U32), ("max_clusters", U32),
-                ("max_tracklets", U32)]
+                ("max_tracklets", U32), ("max_samples", U32)]
 
 
 class TpcZsInput(ctypes.Structure):
@@ -163,8 +163,10 @@ def geometry():
     return npads, xfx, pfx
 
 
-def workspace_size(max_units: int, max_time_bins: int, max_clusters: int, max_tracklets: int) -> int:
-    s = TpcSizes(max_units, max_time_bins, max_clusters, max_tracklets)
+def workspace_size(max_units: int, max_time_bins: int, max_clusters: int, max_tracklets: int,
+                   max_samples: Optional[int] = None) -> int:
+    s = TpcSizes(max_units, max_time_bins, max_clusters, max_tracklets,
+                 max_clusters if max_samples is None else max_samples)
     out = ctypes.c_size_t(0)
     _check(load().tpc_workspace_size(ctypes.byref(s), ctypes.byref(out)), "tpc_workspace_size")
     return out.value
@@ -210,13 +212,16 @@ class Reco:
 
     def __init__(self, max_units: int, max_time_bins: int, max_clusters: int,
                  max_tracklets: int, param_overrides: Optional[dict] = None,
-                 noise_sigma: float = 1.0, device: str = "cuda", stream=None):
+                 noise_sigma: float = 1.0, device: str = "cuda", stream=None,
+                 max_samples: Optional[int] = None):
+        """max_samples bounds the samples of one call (default: max_clusters)."""
         torch = _torch()
         self.lib = load()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = params(param_overrides, noise_sigma)
-        self.sizes = TpcSizes(max_units, max_time_bins, max_clusters, max_tracklets)
+        self.sizes = TpcSizes(max_units, max_time_bins, max_clusters, max_tracklets,
+                              max_clusters if max_samples is None else max_samples)
         self.ctx = P()
         with torch.cuda.device(self.device):
             _check(self.lib.tpc_create(ctypes.byref(self.ctx), ctypes.byref(self.params),
