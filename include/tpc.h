@@ -87,7 +87,7 @@ typedef struct {
 /* Upper bounds used to size the context's scratch. */
 typedef struct {
   uint32_t max_units;     /* units per call (36 per time frame) */
-  uint32_t max_time_bins; /* time bins per unit (< 65536) */
+  uint32_t max_time_bins; /* time bins per unit, at most 65000 (z_fx stays below 2^31) */
   uint32_t max_clusters;  /* clusters per call */
   uint32_t max_tracklets; /* tracklets per call, at most 2^24 */
   uint32_t max_samples;   /* zero-suppressed samples per call (24 bytes of scratch each) */

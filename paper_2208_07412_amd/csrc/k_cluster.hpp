@@ -146,7 +146,8 @@ __device__ __forceinline__ void row_range(const uint32_t* blk_row, uint32_t nblk
 
 // tile offset of the neighbour an up code points at
 __device__ __forceinline__ int code_offset(int code) {
-  return ((code >> 2) - 1) * CL_TP + ((code & 3) - 1);
+  // (code >> 2) < 4: a 24-bit multiply
+  return (int)__umul24((uint32_t)(code >> 2) & 3u, CL_TP) - CL_TP + ((code & 3) - 1);
 }
 
 // ------------------------------------------------------------ tile cells
@@ -236,7 +237,10 @@ __device__ __forceinline__ int cell_of(uint32_t tp, int tile_t0, int np) {
   if (tp == 0xFFFFFFFFu) return -1;
   const int lt = (int)(tp >> 16) - tile_t0;
   const int p = (int)(tp & 0xFFFF);
-  return (lt >= 0 && lt < ROWS && p < np) ? lt * CL_TP + p + 2 : -1;
+  // lt < ROWS < 256 where used: a 24-bit multiply
+  return (lt >= 0 && lt < ROWS && p < np)
+             ? (int)__umul24(__builtin_amdgcn_ubfe((uint32_t)lt, 0, 8), CL_TP) + p + 2
+             : -1;
 }
 
 // place (place = true) or clear the window's samples in the tile
@@ -425,10 +429,15 @@ __global__ __launch_bounds__(64) void k_cluster_peaks(ZsArgs in, const uint32_t*
         const uint32_t a = tx & 0x3FF;
         const uint32_t dt2 = 4 - (cx >> 2) - (cy >> 2);  // dt + 2, dt = sample - peak
         const uint32_t dp2 = 4 - (cx & 3) - (cy & 3);
-        const uint32_t dt = dt2 - 2, dp = dp2 - 2;
-        const uint64_t v0 = (uint64_t)a | (1ull << 15) | ((uint64_t)(a >= 1023) << 20) |
-                            ((uint64_t)(a * dp2) << 25) | ((uint64_t)(a * (dp * dp)) << 42);
-        const uint64_t v1 = (uint64_t)(a * dt2) | ((uint64_t)(a * (dt * dt)) << 32);
+        // (dt)^2 = (dt2 - 2)^2 is 4, 1, 0, 1, 4 for dt2 = 0..4
+        const uint32_t dtt = (dt2 == 2) ? 0u : ((dt2 & 1) ? 1u : 4u);
+        const uint32_t dpp = (dp2 == 2) ? 0u : ((dp2 & 1) ? 1u : 4u);
+        const uint32_t ap = __umul24(a, dp2), at = __umul24(a, dt2);
+        // the packed fields assembled as two 32-bit halves
+        const uint32_t lo0 = a | (1u << 15) | ((uint32_t)(a >= 1023) << 20) | (ap << 25);
+        const uint32_t hi0 = (ap >> 7) | (__umul24(a, dpp) << 10);
+        const uint64_t v0 = ((uint64_t)hi0 << 32) | lo0;
+        const uint64_t v1 = ((uint64_t)__umul24(a, dtt) << 32) | at;
         atomicAdd(&acc0[slot], (unsigned long long)v0);
         atomicAdd(&acc1[slot], (unsigned long long)v1);
       }

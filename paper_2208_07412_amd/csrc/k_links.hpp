@@ -52,20 +52,27 @@ __device__ __forceinline__ void nb_candidates(const ClusterView& cl, const uint3
 
 // Best (j, k) pair for cluster i among the candidates [ja, jb) x [ka, kb),
 // positions read through the accessors J (row r-1) and K (row r+1), which
-// return (y, z) from LDS-staged rows or global memory.  The k candidates inside the window are listed once in registers
-// (up to NB_KLIST; beyond that the whole range is scanned per j).
+// return (y, z) from LDS-staged rows or global memory.  The k candidates
+// inside the window are listed once in registers (up to NB_KLIST; beyond
+// that the whole range is scanned per j).  Positions are below 2^30 in
+// magnitude and windows are capped at 2^30 (far beyond any row), so every
+// difference fits 32 bits and a score (sum of two squares) fits 64 bits
+// unsigned; the decision is the exact integer one.
 #define NB_KLIST 8
+__device__ __forceinline__ bool nb_in(int32_t a, int32_t b, int32_t w) {
+  const int32_t d = a - b;
+  return d <= w && d >= -w;
+}
 template <class PJ, class PK>
-__device__ __forceinline__ void nb_best(PJ J, PK K, int64_t yi, int64_t zi, int64_t wy,
-                                        int64_t wz, int64_t smax, uint32_t ja, uint32_t jb,
+__device__ __forceinline__ void nb_best(PJ J, PK K, int32_t yi, int32_t zi, int32_t wy,
+                                        int32_t wz, uint64_t smax, uint32_t ja, uint32_t jb,
                                         uint32_t ka, uint32_t kb, int32_t& bd, int32_t& bu) {
   uint32_t kl[NB_KLIST];
   int nk = 0;
   bool over = false;
   for (uint32_t k = ka; k < kb; ++k) {
     const int2 pk = K(k);
-    const int64_t yk = pk.x, zk = pk.y;
-    if (yk - yi > wy || yi - yk > wy || zk - zi > wz || zi - zk > wz) continue;
+    if (!nb_in(pk.x, yi, wy) || !nb_in(pk.y, zi, wz)) continue;
     if (nk < NB_KLIST) {
 #pragma unroll
       for (int m = 0; m < NB_KLIST; ++m)
@@ -76,39 +83,33 @@ __device__ __forceinline__ void nb_best(PJ J, PK K, int64_t yi, int64_t zi, int6
     }
   }
   if (nk == 0) return;
-  int64_t best = -1;
+  uint64_t best = ~0ull;
   for (uint32_t j = ja; j < jb; ++j) {
     const int2 pj = J(j);
-    const int64_t yj = pj.x, zj = pj.y;
-    if (yj - yi > wy || yi - yj > wy || zj - zi > wz || zi - zj > wz) continue;
-    const int64_t ay = 2 * yi - yj, az = 2 * zi - zj;
+    if (!nb_in(pj.x, yi, wy) || !nb_in(pj.y, zi, wz)) continue;
+    // 2 y_i - y_j - y_k = (y_i - y_j) + (y_i - y_k), each term inside its window
+    const int32_t ay = yi - pj.x, az = zi - pj.y;
+    auto consider = [&](uint32_t k, int2 pk) {
+      const int32_t dy = ay + (yi - pk.x), dz = az + (zi - pk.y);
+      const uint64_t sc = (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
+      // j and k ascend, so a strict "<" keeps the smallest (j, k) on ties
+      if (sc <= smax && sc < best) {
+        best = sc;
+        bd = (int32_t)j;
+        bu = (int32_t)k;
+      }
+    };
     if (!over) {
 #pragma unroll
       for (int m = 0; m < NB_KLIST; ++m) {
         if (m >= nk) break;
-        const uint32_t k = kl[m];
-        const int2 pk = K(k);
-        const int64_t dy = ay - pk.x, dz = az - pk.y;
-        const int64_t s = dy * dy + dz * dz;
-        // j and k ascend, so a strict "<" keeps the smallest (j, k) on ties
-        if (s <= smax && (best < 0 || s < best)) {
-          best = s;
-          bd = (int32_t)j;
-          bu = (int32_t)k;
-        }
+        consider(kl[m], K(kl[m]));
       }
     } else {
       for (uint32_t k = ka; k < kb; ++k) {
         const int2 pk = K(k);
-        const int64_t yk = pk.x, zk = pk.y;
-        if (yk - yi > wy || yi - yk > wy || zk - zi > wz || zi - zk > wz) continue;
-        const int64_t dy = ay - yk, dz = az - zk;
-        const int64_t s = dy * dy + dz * dz;
-        if (s <= smax && (best < 0 || s < best)) {
-          best = s;
-          bd = (int32_t)j;
-          bu = (int32_t)k;
-        }
+        if (!nb_in(pk.x, yi, wy) || !nb_in(pk.y, zi, wz)) continue;
+        consider(k, pk);
       }
     }
   }
@@ -128,7 +129,10 @@ __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32
   __shared__ int2 sp[2][NB_STAGE];
   __shared__ uint32_t rng[4];
   if (failed(st)) return;
-  const int64_t wy = P->win_y, wz = P->win_z, smax = P->s_max;
+  const int64_t wz64 = P->win_z;
+  const int32_t wy = (int32_t)min(P->win_y, (int64_t)1 << 30);
+  const int32_t wz = (int32_t)min(wz64, (int64_t)1 << 30);
+  const uint64_t smax = (uint64_t)P->s_max;
   for (uint32_t b = blockIdx.x; b < n_ur; b += gridDim.x) {
     // consecutive rows of a sector share an XCD (and its L2) when the grid
     // covers every row
@@ -145,14 +149,14 @@ __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32
     for (uint32_t base = c0; base < c1; base += blockDim.x) {
       const uint32_t i = base + threadIdx.x;
       const bool valid = i < c1;
-      int64_t yi = 0, zi = 0;
+      int32_t yi = 0, zi = 0;
       uint32_t ja = 0, jb = 0, ka = 0, kb = 0;
       if (valid) {
         const int2 pi = cl.pos[i];
         yi = pi.x;
         zi = pi.y;
-        nb_candidates(cl, cblk, nblk, ur - 1, zi, wz, ja, jb);
-        nb_candidates(cl, cblk, nblk, ur + 1, zi, wz, ka, kb);
+        nb_candidates(cl, cblk, nblk, ur - 1, zi, wz64, ja, jb);
+        nb_candidates(cl, cblk, nblk, ur + 1, zi, wz64, ka, kb);
       }
       if (threadIdx.x == 0) {
         rng[0] = 0xFFFFFFFFu;

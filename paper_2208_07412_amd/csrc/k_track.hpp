@@ -122,13 +122,13 @@ __device__ __forceinline__ T darc_dc(T s1, T C, T dx) {
 // root (a Jacobian element: a few ulp are far below what the fit resolves).
 template <>
 __device__ __forceinline__ float darc_dc<float>(float s1, float C, float dx) {
+  const float Cdx = C * dx;
   const float X[8] = {0.01985507175123188f, 0.10166676129318664f, 0.2372337950418355f,
                       0.4082826787521751f,  0.5917173212478249f,  0.7627662049581645f,
                       0.8983332387068134f,  0.9801449282487681f};
   const float Wt[8] = {0.05061426814518813f, 0.11119051722668724f, 0.15685332293894363f,
                        0.18134189168918100f, 0.18134189168918100f, 0.15685332293894363f,
                        0.11119051722668724f, 0.05061426814518813f};
-  const float Cdx = C * dx;
   float acc = 0.0f;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -456,7 +456,6 @@ __global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_
 
 // Following of one tracklet per lane: seed and first update, pass A outward
 // row by row, pass B inward from the outermost pass-A hit, result.
-enum { FS_A = 1, FS_B = 2 };
 
 struct FollowLane {
   Trk<float> k;   // state at row r
@@ -464,7 +463,7 @@ struct FollowLane {
   uint32_t t;
   int32_t anchor, ctl;
   uint32_t ubase;
-  int r, r1, L, nmiss, nh, hi, lo, rs, phase;  // rs: row of sp
+  int r, r1, L, nmiss, nh, hi, lo, rs;  // rs: row of sp
 };
 
 // Seed and first update of tracklet t; false if it cannot be followed.
@@ -559,13 +558,13 @@ __device__ __forceinline__ void follow_finish(const FollowLane& f, FollowOut& fo
   fo.ok[f.t] = 1;
 }
 
-// One row of pass A (outward) or pass B (inward) for a lane in FS_A / FS_B.
-// Returns true when the pass has ended.
+// One row of pass A (outward, pa) or pass B (inward).  Returns true when the
+// pass has ended.
+template <bool pa>
 __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl,
                                             const uint32_t* cblk, uint32_t nblk,
                                             const int32_t* upc, FollowOut& fo, const DevParams* P,
                                             const PV<float>& pv, float chi2max) {
-  const bool pa = f.phase == FS_A;
   const int rn = f.r + (pa ? 1 : -1);
   if (rn >= NROW || rn < 0) return true;
   Trk<float>& k = f.k;
@@ -628,12 +627,10 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
     FollowLane f;
     if (!follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) continue;
-    f.phase = FS_A;
-    while (!follow_step(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
+    while (!follow_step<true>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
     }
     if (follow_start_b(f, cl, fo, pv)) {
-      f.phase = FS_B;
-      while (!follow_step(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
+      while (!follow_step<false>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
       }
     }
     follow_finish(f, fo);

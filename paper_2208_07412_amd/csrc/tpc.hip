@@ -561,7 +561,7 @@ int tpc_geometry(int32_t* npads, int32_t* x_fx, int32_t* pitch_fx) {
 
 int tpc_workspace_size(const tpc_sizes* max, size_t* bytes) {
   if (!max || !bytes) return TPC_ERR_ARG;
-  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65535 ||
+  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65000 ||
       max->max_tracklets > (1u << 24))
     return TPC_ERR_ARG;
   *bytes = plan_for(*max).total;
@@ -571,7 +571,7 @@ int tpc_workspace_size(const tpc_sizes* max, size_t* bytes) {
 int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* hip_stream) {
   if (!out || !p || !max) return TPC_ERR_ARG;
   *out = nullptr;
-  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65535 ||
+  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65000 ||
       max->max_tracklets > (1u << 24))
     return TPC_ERR_ARG;
   if (p->min_tracklet < 3 || p->min_tracklet > NROW || p->min_track_hits < 3 || p->max_miss < 1 ||
