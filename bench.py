@@ -31,6 +31,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (published)
+# FP32 operations of one unit of following work (FMA = 2), from the formulas:
+# helix step with analytic Jacobian (8-point quadrature) and covariance
+# transport; chi2 of one candidate against the inverted residual covariance;
+# one Kalman update (gain, state, covariance).
+FLOPS_STEP, FLOPS_CAND, FLOPS_UPDATE = 220, 12, 122
 METRIC = "TPC clusters reconstructed/sec on 1 MI355X (batched vs plain); p50/p99 chunk latency"
 
 
@@ -45,7 +51,7 @@ def stage_bytes(ns, nc, n_ur, T, W=16):
     rec = 4 * 2 + 4 * 4 + 2 * 4 + 1
     raw = 24                 # raw record per cluster between the two clusterizer passes
     nblk_s = (T + 3) // 4   # sample index: one entry per 4 time bins
-    nblk_c = (T + 7) // 8   # cluster grid: one entry per 8 time bins
+    nblk_c = (T + 3) // 4   # cluster grid: one entry per 4 time bins
     nwin = n_ur * ((T + W - 1) // W)
     return {
         "sample_index": 2 * ns + 4 * n_ur * (nblk_s + 1),
@@ -277,6 +283,13 @@ def main():
         tuning = autotune(reco, run_once)
         log(f"[bench] autotune in {time.perf_counter() - t:.1f}s: {tuning}")
 
+    # work counters of the following (a counting variant of its kernel, run once)
+    reco.profile(False, count_work=True)
+    with torch.cuda.stream(stream):
+        reco.process(zs, cl, links, tl, tr, zs_s)
+    fcounts = reco.sync()
+    reco.profile(False)
+
     # per-stage timing (eager launches, events on the library's stream)
     reco.profile(True)
     with torch.cuda.stream(stream):
@@ -285,7 +298,7 @@ def main():
     prof = reco.profile_read()
     reco.profile(False)
     reco.sync()
-    stages = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+    stages = {k: v[0] / 3 for k, v in prof.items()}  # per reconstruction
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
 
     # timed region: the batched form, one graph replay per step
@@ -319,7 +332,8 @@ def main():
     log(f"[bench] batched: {ms_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} wall), "
         f"{value:.4g} clusters/s")
 
-    # roofline of the dominant HBM-bound stage
+    # roofline of the dominant kernel (the following: FP32 ALU) and of the
+    # dominant HBM-bound stage (the clusterizer's peak pass)
     n_ur = ev.n_units * 152
     sb = stage_bytes(ns, nc, n_ur, ev.n_time_bins,
                      tuning["chosen"]["cl_window"] if tuning else 16)
@@ -331,9 +345,19 @@ def main():
              if hbm_dom == "cluster_peaks" else f"void k_{hbm_dom}<{tn['cl_window']}>")
     traffic = pmc_traffic("paper_2208_07412_amd/csrc/k_cluster.hpp", hbm_dom, kname) \
         if hbm_dom.startswith("cluster_") else None
-    roofline = dict(bound="hbm", kernel=hbm_dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=traffic, bytes_per_launch=sb[hbm_dom],
-                    ms_per_launch=stages[hbm_dom], dominant_stage=dom,
+    roofline_hbm = dict(bound="hbm", kernel=hbm_dom, achieved=ach, peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=traffic,
+                        bytes_per_launch=sb[hbm_dom], ms_per_launch=stages[hbm_dom])
+    flops = (FLOPS_STEP * fcounts["follow_steps"] + FLOPS_CAND * fcounts["follow_candidates"] +
+             FLOPS_UPDATE * fcounts["follow_updates"])
+    ach_f = flops / (stages["following"] / 1e3) / 1e12
+    roofline = dict(bound="alu", kernel="following", achieved=ach_f, peak=FP32_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=ach_f / FP32_PEAK_TFLOPS,
+                    traffic=pmc_traffic("paper_2208_07412_amd/csrc/k_track.hpp", "following",
+                                        "void k_follow<"),
+                    flops_per_launch=flops, ms_per_launch=stages["following"],
+                    steps=fcounts["follow_steps"], candidates=fcounts["follow_candidates"],
+                    updates=fcounts["follow_updates"], dominant_stage=dom,
                     dominant_stage_ms=stages[dom])
 
     out = dict(metric=METRIC, value=value, unit="clusters/s", n_gpus=1, steps=args.steps,
@@ -343,7 +367,7 @@ def main():
                            "36 sectors x 152 rows, 10500 time bins, seed 303",
                            form="batched (graph replay)" if graph is not None else "eager",
                            samples=ns, clusters=nc, tracks=counts["n_tracks"]),
-               roofline=roofline, stages_ms=stages)
+               roofline=roofline, roofline_hbm=roofline_hbm, stages_ms=stages)
     if tuning is not None:
         out["tuning"] = tuning["chosen"]
     del graph

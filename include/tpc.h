@@ -169,6 +169,10 @@ typedef struct {
   uint32_t n_fallback_fail;   /* FP64 refits still not PD (dropped) */
   uint32_t n_not_pd;          /* high-pT tracks flagged not PD */
   uint32_t n_refit_fail;      /* tracks dropped by a failed refit step */
+  uint32_t reserved;
+  /* work of the last following stage (measurement): helix steps with
+     covariance transport, candidate chi2 evaluations, Kalman updates */
+  uint64_t follow_steps, follow_candidates, follow_updates;
 } tpc_counts;
 
 typedef struct tpc_ctx tpc_ctx;
@@ -228,9 +232,12 @@ void* tpc_stream(tpc_ctx* ctx);
  * around each of the TPC_PROF_STAGES stages below; tpc_profile_read waits
  * for the stream, writes the summed milliseconds and the number of timed
  * launches per stage, and clears them.  Leave it off while a launch sequence
- * is captured into a HIP graph.  Stages: 0 sample index, 1 cluster peaks
+ * is captured into a HIP graph.  on = 1: stage timers; on = 2: work counters
+ * of the following (tpc_counts.follow_*), from a slower counting variant of
+ * its kernel; 3: both.  Stages: 0 sample index, 1 cluster peaks
  * (peak finding and moments, one pass over the samples), 2 cluster scan,
- * 3 cluster output, 4 cluster grid, 5 neighbours, 6 tracklets, 7 following,
+ * 3 cluster output, 4 cluster grid, 5 neighbours, 6 tracklets (and their
+ * seed points, timed inside the fit call), 7 following (one kernel),
  * 8 resolution, 9 refit FP32, 10 refit FP64, 11 track output. */
 #define TPC_PROF_STAGES 12
 int tpc_profile_enable(tpc_ctx* ctx, int on);
@@ -242,14 +249,16 @@ const char* tpc_status_string(int status);
 /* Launch shapes (performance only: every choice gives the same results).
  * cl_window: clusterizer window in time bins, 16 or 32; cl_chunk: windows
  * walked by one workgroup, 4, 8 or 16; follow_block: threads per workgroup
- * of the following kernel, 64, 128 or 256.  tpc_set_tuning rejects other
+ * of the following kernel, 64, 128 or 256; follow_mode: 0 one tracklet per
+ * lane, 1 lanes refilled from a range of tracklets per wave (lanes then
+ * work on different passes at once).  tpc_set_tuning rejects other
  * values with TPC_ERR_ARG and leaves the context unchanged; it takes effect
  * at the next call (a captured graph keeps the shapes it was captured with). */
 typedef struct {
   int32_t cl_window;
   int32_t cl_chunk;
   int32_t follow_block;
-  int32_t reserved;
+  int32_t follow_mode;
 } tpc_tuning;
 int tpc_tuning_default(tpc_tuning* t);
 int tpc_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

@@ -12,17 +12,13 @@ from __future__ import annotations
 from typing import Dict, List, Tuple
 
 CLUSTER_SHAPES: List[Tuple[int, int]] = [(16, 4), (16, 8), (16, 16), (32, 4), (32, 8), (32, 16)]
-FOLLOW_BLOCKS: List[int] = [64, 128, 256]
+FOLLOW_SHAPES: List[Tuple[int, int]] = [(64, 0), (128, 0), (256, 0), (64, 1), (128, 1), (256, 1)]
 CLUSTER_STAGES = ("sample_index", "cluster_peaks", "cluster_scan", "cluster_output")
 FOLLOW_STAGES = ("following",)
 
 
-def _stage_ms(prof: Dict[str, tuple], names) -> float:
-    tot = 0.0
-    for n in names:
-        ms, k = prof[n]
-        tot += ms / max(k, 1)
-    return tot
+def _stage_ms(prof: Dict[str, tuple], names, runs: int) -> float:
+    return sum(prof[n][0] for n in names) / runs
 
 
 def _time(reco, run, names, reps: int) -> float:
@@ -34,7 +30,7 @@ def _time(reco, run, names, reps: int) -> float:
     prof = reco.profile_read()
     reco.profile(False)
     reco.sync()
-    return _stage_ms(prof, names)
+    return _stage_ms(prof, names, reps)
 
 
 def _pick(times: Dict[str, float], keep: str, margin: float) -> str:
@@ -57,11 +53,12 @@ def autotune(reco, run, reps: int = 3, margin: float = 0.02) -> dict:
     best_c = _pick(res["cluster"], f"{start['cl_window']}x{start['cl_chunk']}", margin)
     w, k = (int(x) for x in best_c.split("x"))
     reco.set_tuning(cl_window=w, cl_chunk=k)
-    for fb in FOLLOW_BLOCKS:
-        reco.set_tuning(follow_block=fb)
-        res["follow"][str(fb)] = _time(reco, run, FOLLOW_STAGES, reps)
-    best_f = int(_pick(res["follow"], str(start["follow_block"]), margin))
-    reco.set_tuning(follow_block=best_f)
+    for fb, fm in FOLLOW_SHAPES:
+        reco.set_tuning(follow_block=fb, follow_mode=fm)
+        res["follow"][f"{fb}x{fm}"] = _time(reco, run, FOLLOW_STAGES, reps)
+    best_f = _pick(res["follow"], f"{start['follow_block']}x{start['follow_mode']}", margin)
+    fb, fm = (int(x) for x in best_f.split("x"))
+    reco.set_tuning(follow_block=fb, follow_mode=fm)
     res["chosen"] = reco.tuning()
     res["start"] = start
     return res

@@ -39,6 +39,7 @@ struct DevStatus {
   uint32_t n_fallback, n_fallback_fail, n_not_pd, n_refit_fail;
   uint32_t n_fb_list;
   uint32_t pad_[5];
+  unsigned long long f_steps, f_cands, f_upds;  // following work (measurement)
 };
 
 __device__ __forceinline__ void latch(DevStatus* st, int code, uint32_t required = 0) {
@@ -84,6 +85,13 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     if ((int)lane_id() >= d) v += o;
   }
   return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(uint32_t v) {
+  unsigned long long x = v;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
 }
 
 // Exclusive scan over a workgroup of BLOCK threads; returns the prefix and

@@ -1,7 +1,7 @@
 // Cellular-automaton neighbour finding and tracklet building.
 //
 // Clusters of each (unit,row) are sorted by peak time, and the block index
-// (first cluster per 8 time bins) is the per-row hit grid: a drift-window
+// (first cluster per 4 time bins) is the per-row hit grid: a drift-window
 // lookup is two table reads, and the pad direction is filtered per candidate
 // (a row holds a handful of clusters per window).  All decisions are exact
 // integer arithmetic on the fixed-point positions.
@@ -35,6 +35,10 @@ __global__ void k_pack_pos(const int32_t* __restrict__ y, const int32_t* __restr
     pos[i] = make_int2(y[i], z[i]);
 }
 
+// The cluster grid (block index over peak times) has one entry per
+// 2^CG_BSHIFT time bins.
+#define CG_BSHIFT 2
+
 // Candidate cluster range of row ur for a drift position z (fixed point):
 // |z_c - z| <= win_z and the centroid lies within 2 bins of the peak time.
 __device__ __forceinline__ void nb_candidates(const ClusterView& cl, const uint32_t* cblk,
@@ -42,8 +46,8 @@ __device__ __forceinline__ void nb_candidates(const ClusterView& cl, const uint3
                                               uint32_t& a, uint32_t& b) {
   const int64_t lo = floor_div64(z - wz, 32768) - 3;
   const int64_t hi = floor_div64(z + wz, 32768) + 3;
-  int32_t blo = lo < 0 ? 0 : (int32_t)(lo >> 3);
-  int32_t bhi = hi < 0 ? -1 : (int32_t)(hi >> 3);
+  int32_t blo = lo < 0 ? 0 : (int32_t)(lo >> CG_BSHIFT);
+  int32_t bhi = hi < 0 ? -1 : (int32_t)(hi >> CG_BSHIFT);
   if (blo > (int32_t)nblk - 1) blo = nblk - 1;
   if (bhi > (int32_t)nblk - 1) bhi = nblk - 1;
   row_range(cblk + (size_t)ur * (nblk + 1), nblk, blo, bhi + 1, cl.row_start(ur),

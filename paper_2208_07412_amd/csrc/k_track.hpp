@@ -15,7 +15,7 @@
 
 #define FX_SCALE 1.52587890625e-05  // 2^-16
 
-enum { TF_NOT_PD = 1, TF_REFIT_FAIL = 2, TF_FP64 = 4, TF_FP64_FAIL = 8 };
+enum { TF_NOT_PD = 1, TF_REFIT_FAIL = 2, TF_FP64 = 4, TF_FP64_FAIL = 8, TF_TO_FP64 = 16 };
 
 template <typename T>
 struct Trk {
@@ -381,13 +381,14 @@ struct FollowOut {
 // best candidate of row r: smallest (chi2, id) with chi2 <= chi2_max
 __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint32_t* cblk,
                                               uint32_t nblk, uint32_t ur, const Trk<float>& k,
-                                              int32_t anchor, float vy, float vz, float chi2max) {
+                                              int32_t anchor, float vy, float vz, float chi2max,
+                                              uint32_t& n_cand) {
   const float w = sqrtf(chi2max * (k.c[5] + vz));
   const float zabs = k.p[1] + (float)anchor * (float)FX_SCALE;
   const float flo = floorf(2.0f * (zabs - w)) - 3.0f, fhi = ceilf(2.0f * (zabs + w)) + 3.0f;
   // NaN or out-of-range windows collapse to an empty or clamped block range
-  int32_t blo = flo > 0.0f ? (flo < 1.0e6f ? ((int32_t)flo >> 3) : (int32_t)nblk) : 0;
-  int32_t bhi = fhi >= 0.0f ? (fhi < 1.0e6f ? ((int32_t)fhi >> 3) : (int32_t)nblk - 1) : -1;
+  int32_t blo = flo > 0.0f ? (flo < 1.0e6f ? ((int32_t)flo >> CG_BSHIFT) : (int32_t)nblk) : 0;
+  int32_t bhi = fhi >= 0.0f ? (fhi < 1.0e6f ? ((int32_t)fhi >> CG_BSHIFT) : (int32_t)nblk - 1) : -1;
   if (!(fhi >= 0.0f) || !(flo == flo)) bhi = -1;
   if (blo > (int32_t)nblk - 1) blo = nblk - 1;
   if (bhi > (int32_t)nblk - 1) bhi = nblk - 1;
@@ -397,6 +398,7 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
   int32_t best = -1;
   float bchi = 0.0f;
   const SInv<float> si = s_inverse(k, vy, vz);
+  n_cand += b - a;
   for (uint32_t c = a; c < b; ++c) {
     const int2 q = cl.pos[c];
     const float my = (float)q.x * (float)FX_SCALE;
@@ -464,6 +466,7 @@ struct FollowLane {
   int32_t anchor, ctl;
   uint32_t ubase;
   int r, r1, L, nmiss, nh, hi, lo, rs;  // rs: row of sp
+  uint32_t n_steps, n_cands, n_upds;      // work done (measurement)
 };
 
 // Seed and first update of tracklet t; false if it cannot be followed.
@@ -514,6 +517,7 @@ __device__ __forceinline__ bool follow_init(FollowLane& f, uint32_t t, const Clu
   k.p[4] = qpt;
   if (!(fabsf(k.p[2]) < pv.snp_max())) return false;
   c0_reset(k, pv, r1);
+  f.n_upds += 1;
   if (!update(k, k.p[0], 0.0f, pv.vy(r1), pv.vz(r1), (float*)nullptr)) return false;
   fo.hits[(size_t)t * NROW + r1] = (int32_t)A;
   f.nh = 1;
@@ -540,6 +544,7 @@ __device__ __forceinline__ bool follow_start_b(FollowLane& f, const ClusterView&
   const int2 q = cl.pos[co];
   const float my = (float)q.x * (float)FX_SCALE;
   const float mz = (float)(q.y - f.anchor) * (float)FX_SCALE;
+  ++f.n_upds;
   if (!update(k, my, mz, pv.vy(f.rs), pv.vz(f.rs), (float*)nullptr)) return false;
 #pragma unroll
   for (int i = 0; i < 5; ++i) f.sp[i] = k.p[i];
@@ -558,17 +563,21 @@ __device__ __forceinline__ void follow_finish(const FollowLane& f, FollowOut& fo
   fo.ok[f.t] = 1;
 }
 
-// One row of pass A (outward, pa) or pass B (inward).  Returns true when the
-// pass has ended.
-template <bool pa>
+// One row of pass A (outward) or pass B (inward).  PA = 1: pass A, 0: pass
+// B, -1: the lane's own pass (rt_pa), when lanes of a wave are in different
+// passes.  Returns true when the pass has ended.
+template <int PA>
 __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl,
                                             const uint32_t* cblk, uint32_t nblk,
                                             const int32_t* upc, FollowOut& fo, const DevParams* P,
-                                            const PV<float>& pv, float chi2max) {
+                                            const PV<float>& pv, float chi2max,
+                                            bool rt_pa = false) {
+  const bool pa = PA < 0 ? rt_pa : PA == 1;
   const int rn = f.r + (pa ? 1 : -1);
   if (rn >= NROW || rn < 0) return true;
   Trk<float>& k = f.k;
   if (!propagate(k, row_dx<float>(P, f.r, rn), pv, true, pv.snp_max())) return true;
+  ++f.n_steps;
   int32_t* H = fo.hits + (size_t)f.t * NROW;
   int32_t cand = -1;
   bool fresh = false;
@@ -579,7 +588,8 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
     if (!pa && rn >= f.r1) cand = H[rn];
     if (cand < 0) {
       if (fabsf(k.p[0]) > pv.hw(rn) + pv.edge_margin()) return true;
-      cand = search_row(cl, cblk, nblk, f.ubase + rn, k, f.anchor, pv.vy(rn), pv.vz(rn), chi2max);
+      cand = search_row(cl, cblk, nblk, f.ubase + rn, k, f.anchor, pv.vy(rn), pv.vz(rn), chi2max,
+                        f.n_cands);
       fresh = true;
     }
   }
@@ -598,6 +608,7 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
   const int2 q = cl.pos[cand];
   const float my = (float)q.x * (float)FX_SCALE;
   const float mz = (float)(q.y - f.anchor) * (float)FX_SCALE;
+  ++f.n_upds;
   if (!update(k, my, mz, pv.vy(rn), pv.vz(rn), (float*)nullptr)) return true;
   if (pa || fresh) {
     H[rn] = cand;
@@ -610,30 +621,157 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
   return false;
 }
 
-template <int B>
+// COUNT: also count the work done (helix steps, candidates, updates) into
+// per-wave counters, for measurement only.
+template <int B, bool COUNT>
 __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __restrict__ cblk,
                                                uint32_t nblk, const int32_t* __restrict__ upc,
                                                const uint32_t* __restrict__ tl_start,
                                                const uint16_t* __restrict__ tl_len,
                                                const uint32_t* __restrict__ pts,
                                                const uint32_t* n_tl_dev, uint32_t tl_cap,
-                                               FollowOut fo, const DevParams* __restrict__ P,
-                                               DevStatus* st) {
-  if (failed(st)) return;
+                                               FollowOut fo, ulonglong4* __restrict__ work,
+                                               const DevParams* __restrict__ P, DevStatus* st) {
+  const uint32_t wave = blockIdx.x * (B / 64) + (threadIdx.x >> 6);
+  if (failed(st)) {
+    if (COUNT && (threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(0, 0, 0, 0);
+    return;
+  }
   const PV<float> pv{P};
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const float chi2max = pv.chi2_max();
   // consecutive tracklets (same start row, nearby times) share a wave
+  uint32_t w_steps = 0, w_cands = 0, w_upds = 0;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
     FollowLane f;
-    if (!follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) continue;
-    while (!follow_step<true>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
+    f.n_steps = f.n_cands = f.n_upds = 0;
+    if (!follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) {
+      if (COUNT) w_upds += f.n_upds;
+      continue;
+    }
+    while (!follow_step<1>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
     }
     if (follow_start_b(f, cl, fo, pv)) {
-      while (!follow_step<false>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
+      while (!follow_step<0>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
       }
     }
     follow_finish(f, fo);
+    if (COUNT) {
+      w_steps += f.n_steps;
+      w_cands += f.n_cands;
+      w_upds += f.n_upds;
+    }
+  }
+  if (!COUNT) return;
+  // work counters: one plain store per wave, summed by k_work_sum (atomics
+  // from every wave on one address would serialise at the end of the kernel)
+  const unsigned long long s0 = wave_sum_u64(w_steps), s1 = wave_sum_u64(w_cands),
+                           s2 = wave_sum_u64(w_upds);
+  if ((threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(s0, s1, s2, 0);
+}
+
+// Following with lane refill: each wave owns a range of FW_RANGE consecutive
+// tracklets and keeps its lanes busy, handing the next tracklets of its range
+// to idle lanes once at least FW_REFILL of them are idle (or all are).  Lanes
+// of a wave may then be in different passes; a lane's results are the same
+// as in k_follow, only the order of work differs.
+#define FW_RANGE 128
+#define FW_REFILL 16
+enum { FS_IDLE = 0, FS_A = 1, FS_B = 2 };
+template <int B, bool COUNT>
+__global__ __launch_bounds__(B) void k_follow_refill(
+    ClusterView cl, const uint32_t* __restrict__ cblk, uint32_t nblk,
+    const int32_t* __restrict__ upc, const uint32_t* __restrict__ tl_start,
+    const uint16_t* __restrict__ tl_len, const uint32_t* __restrict__ pts,
+    const uint32_t* n_tl_dev, uint32_t tl_cap, FollowOut fo, ulonglong4* __restrict__ work,
+    const DevParams* __restrict__ P, DevStatus* st) {
+  const uint32_t wave = blockIdx.x * (B / 64) + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  if (failed(st)) {
+    if (COUNT && lane == 0) work[wave] = make_ulonglong4(0, 0, 0, 0);
+    return;
+  }
+  const PV<float> pv{P};
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  const float chi2max = pv.chi2_max();
+  const uint32_t nw = gridDim.x * (B / 64);
+  uint32_t w_steps = 0, w_cands = 0, w_upds = 0;
+  for (uint32_t rb = uni(wave * FW_RANGE); rb < n_tl; rb += nw * FW_RANGE) {
+    const uint32_t re = min(rb + FW_RANGE, n_tl);
+    uint32_t next = rb;
+    FollowLane f;
+    int phase = FS_IDLE;
+    for (;;) {
+      const uint64_t idle = __ballot(phase == FS_IDLE);
+      const uint32_t n_idle = (uint32_t)__popcll(idle);
+      if (n_idle == 64 && next >= re) break;
+      if (next < re && (n_idle >= FW_REFILL || n_idle == 64)) {
+        if (phase == FS_IDLE) {
+          const uint32_t t = next + (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
+          if (t < re) {
+            f.n_steps = f.n_cands = f.n_upds = 0;
+            if (follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) {
+              phase = FS_A;
+            } else if (COUNT) {
+              w_upds += f.n_upds;
+            }
+          }
+        }
+        next = min(next + n_idle, re);
+        continue;
+      }
+      if (phase != FS_IDLE &&
+          follow_step<-1>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max, phase == FS_A)) {
+        if (phase == FS_A && follow_start_b(f, cl, fo, pv)) {
+          phase = FS_B;
+        } else {
+          follow_finish(f, fo);
+          if (COUNT) {
+            w_steps += f.n_steps;
+            w_cands += f.n_cands;
+            w_upds += f.n_upds;
+          }
+          phase = FS_IDLE;
+        }
+      }
+    }
+  }
+  if (!COUNT) return;
+  const unsigned long long s0 = wave_sum_u64(w_steps), s1 = wave_sum_u64(w_cands),
+                           s2 = wave_sum_u64(w_upds);
+  if (lane == 0) work[wave] = make_ulonglong4(s0, s1, s2, 0);
+}
+
+// Sum of the following's per-wave work counters into the status block.
+__global__ __launch_bounds__(1024) void k_work_sum(const ulonglong4* __restrict__ work,
+                                                   uint32_t n, DevStatus* st) {
+  __shared__ unsigned long long part[3][16];
+  unsigned long long a = 0, b = 0, c = 0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const ulonglong4 v = work[i];
+    a += v.x;
+    b += v.y;
+    c += v.z;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += __shfl_xor(a, d, 64);
+    b += __shfl_xor(b, d, 64);
+    c += __shfl_xor(c, d, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = a;
+    part[1][threadIdx.x >> 6] = b;
+    part[2][threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+      for (uint32_t w = 0; w < blockDim.x / 64; ++w) s[k] += part[k][w];
+    st->f_steps = s[0];
+    st->f_cands = s[1];
+    st->f_upds = s[2];
   }
 }
 
@@ -899,14 +1037,25 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
     ro.row[t] = (uint8_t)rprev;
     const bool lowpt = (hd.flags[t] & 4) != 0;
     if (P->force_fallback || guard || (!pd && lowpt)) {
-      const uint32_t i = atomicAdd(&st->n_fb_list, 1u);
-      if (i < tl_cap) fb_list[i] = t;
+      ro.flags[t] = TF_TO_FP64;  // listed for the FP64 refit by a scan
     } else if (!pd) {
       ro.flags[t] = TF_NOT_PD;
       atomicAdd(&st->n_not_pd, 1u);
     }
   }
 }
+
+// The tracks the FP32 refit hands to the FP64 one, in tracklet order.
+struct GetToFp64 {
+  const uint8_t* flags;
+  __device__ uint32_t operator()(uint32_t t) const { return (flags[t] & TF_TO_FP64) ? 1u : 0u; }
+};
+struct EmitFbList {
+  uint32_t* list;
+  __device__ void operator()(uint32_t t, uint32_t pos, uint32_t v) const {
+    if (v) list[pos] = t;
+  }
+};
 
 __global__ __launch_bounds__(64) void k_refit64(ClusterView cl, const uint32_t* __restrict__ tl_start,
                                                 FollowOut fo, uint32_t tl_cap,
@@ -915,6 +1064,7 @@ __global__ __launch_bounds__(64) void k_refit64(ClusterView cl, const uint32_t* 
                                                 const DevParams* __restrict__ P, DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n = scan_count(&st->n_fb_list, tl_cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_fallback = n;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t t = fb_list[i];
     Trk<double> k;
@@ -926,7 +1076,6 @@ __global__ __launch_bounds__(64) void k_refit64(ClusterView cl, const uint32_t* 
     bool pd = true;
     const int rc = rprev < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, P, k, chi2s, rprev, r, NROW,
                                                      pd);
-    atomicAdd(&st->n_fallback, 1u);
     if (rc || rprev < 0 || !pd) {
       const bool fail = rc || rprev < 0;
       ro.flags[t] = fail ? TF_REFIT_FAIL : TF_FP64_FAIL;

@@ -69,6 +69,7 @@ struct tpc_ctx {
   uint8_t* f_ok = nullptr;
   uint32_t* f_pts = nullptr;
   uint8_t* f_krow = nullptr;
+  ulonglong4* f_work = nullptr;  // per-wave work counters of the following
   int2* pos = nullptr;  // packed cluster positions  // per tracklet: middle and end cluster, unit-row of the start
   uint32_t* owner = nullptr;
   uint16_t* nkept = nullptr;
@@ -86,6 +87,7 @@ struct tpc_ctx {
   // stage timing (measurement only)
   static constexpr int kProfCap = 64;
   bool prof_on = false;
+  bool count_work = false;  // following work counters (measurement)
   bool prof_events = false;
   hipEvent_t prof_ev[TPC_PROF_STAGES][2][kProfCap];
   uint32_t prof_n[TPC_PROF_STAGES] = {};
@@ -105,7 +107,7 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_krow, pos,
+  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_krow, f_work, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
       h_flags, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
@@ -116,7 +118,7 @@ Plan plan_for(const tpc_sizes& m) {
   Plan p;
   Layout L;
   const uint64_t nur = (uint64_t)m.max_units * NROW;
-  p.nblk = ceil_div(m.max_time_bins, 8);
+  p.nblk = ceil_div(m.max_time_bins, 1u << CG_BSHIFT);
   p.nblk_s = ceil_div(m.max_time_bins, 1u << CL_BSHIFT);
   p.nwin = ceil_div(m.max_time_bins, kMinWin);
   uint64_t nscan = nur * p.nwin;
@@ -140,6 +142,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.f_ok = L.add<uint8_t>(mt);
   p.f_pts = L.add<uint32_t>(mt * 3);
   p.f_krow = L.add<uint8_t>(mt * NROW);
+  p.f_work = L.add<ulonglong4>(mt / 64 + 8);
   p.pos = L.add<int2>(mc);
   p.owner = L.add<uint32_t>(mc);
   p.nkept = L.add<uint16_t>(mt);
@@ -408,9 +411,10 @@ int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
 
 int stage_grid(tpc_ctx* c, const tpc_clusters* cl) {
   const uint32_t n_ur = cl->n_units * NROW;
-  const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
+  const uint32_t nblk = ceil_div(cl->n_time_bins, 1u << CG_BSHIFT);
   StageTimer tm(c, 4);
-  k_block_index<<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk, 3,
+  k_block_index<<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk,
+                                             CG_BSHIFT,
                                              cl->n_time_bins, cl->capacity, c->cblk, c->d_par,
                                              c->d_st, 0);
   k_pack_pos<<<grid_for(cl->capacity, 256), 256, 0, c->stream>>>(cl->y_fx, cl->z_fx, cl->n_clusters,
@@ -420,7 +424,7 @@ int stage_grid(tpc_ctx* c, const tpc_clusters* cl) {
 
 int stage_neighbours(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l) {
   const uint32_t n_ur = cl->n_units * NROW;
-  const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
+  const uint32_t nblk = ceil_div(cl->n_time_bins, 1u << CG_BSHIFT);
   StageTimer tm(c, 5);
   k_neighbours<<<n_ur, 256, 0, c->stream>>>(cluster_view(c, cl), c->cblk, nblk, n_ur, l->down, l->up,
                                             c->d_par, c->d_st);
@@ -446,7 +450,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
               tpc_tracks* tr) {
   hipStream_t s = c->stream;
   const uint32_t n_ur = cl->n_units * NROW;
-  const uint32_t nblk = ceil_div(cl->n_time_bins, 8);
+  const uint32_t nblk = ceil_div(cl->n_time_bins, 1u << CG_BSHIFT);
   const uint32_t tcap = t->capacity;
   const uint32_t ccap = cl->capacity;
   const ClusterView cv = cluster_view(c, cl);
@@ -457,21 +461,42 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   // per-call counters of the fit stage
   k_fill<uint32_t><<<1, 64, 0, s>>>(&c->d_st->n_fallback, 0u, 5);
   {
-    StageTimer tm(c, 7);
+    StageTimer tm(c, 6);  // the tracklets' seed points belong to tracklet building
     k_tracklet_points<<<grid_for(tcap, 256), 256, 0, s>>>(cv, n_ur, l->upc, t->start, t->len,
                                                            t->n_tracklets, tcap, c->f_pts,
                                                            c->d_st);
+  }
+  {
+    StageTimer tm(c, 7);
     const int fb = c->tune.follow_block;
     const uint32_t gf = grid_for(tcap, fb);
-    if (fb == 256)
-      k_follow<256><<<gf, 256, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len, c->f_pts,
-                                       t->n_tracklets, tcap, fo, c->d_par, c->d_st);
-    else if (fb == 128)
-      k_follow<128><<<gf, 128, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len, c->f_pts,
-                                       t->n_tracklets, tcap, fo, c->d_par, c->d_st);
-    else
-      k_follow<64><<<gf, 64, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len, c->f_pts,
-                                     t->n_tracklets, tcap, fo, c->d_par, c->d_st);
+    const bool refill = c->tune.follow_mode == 1;
+    // refill mode: one wave per range of FW_RANGE tracklets
+    const uint32_t gr = grid_for((uint64_t)ceil_div(tcap, FW_RANGE) * 64, fb);
+    auto launch = [&](auto Bc, auto Cc) {
+      constexpr int Bv = decltype(Bc)::value;
+      constexpr bool Cv = decltype(Cc)::value;
+      if (refill)
+        k_follow_refill<Bv, Cv><<<gr, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
+                                                  c->f_pts, t->n_tracklets, tcap, fo, c->f_work,
+                                                  c->d_par, c->d_st);
+      else
+        k_follow<Bv, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
+                                           c->f_pts, t->n_tracklets, tcap, fo, c->f_work,
+                                           c->d_par, c->d_st);
+    };
+    using B64 = std::integral_constant<int, 64>;
+    using B128 = std::integral_constant<int, 128>;
+    using B256 = std::integral_constant<int, 256>;
+    using Cnt = std::true_type;
+    using NoCnt = std::false_type;
+    const bool cnt = c->count_work;
+    if (fb == 256) cnt ? launch(B256{}, Cnt{}) : launch(B256{}, NoCnt{});
+    else if (fb == 128) cnt ? launch(B128{}, Cnt{}) : launch(B128{}, NoCnt{});
+    else cnt ? launch(B64{}, Cnt{}) : launch(B64{}, NoCnt{});
+    if (cnt)
+      k_work_sum<<<1, 1024, 0, s>>>(c->f_work, (refill ? gr : gf) * (uint32_t)(fb / 64),
+                                    c->d_st);
   }
   {
     StageTimer tm(c, 8);
@@ -492,6 +517,8 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 10);
+    run_scan<uint32_t>(c, GetToFp64{ro.flags}, EmitFbList{c->fb_list}, t->n_tracklets, tcap,
+                       (uint32_t*)nullptr, &c->d_st->n_fb_list);
     k_refit64<<<g64, 64, 0, s>>>(cv, t->start, fo, tcap, c->nkept, ro, c->fb_list, c->d_par,
                                  c->d_st);
   }
@@ -610,6 +637,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->f_ok = (uint8_t*)(base + pl.f_ok);
   c->f_pts = (uint32_t*)(base + pl.f_pts);
   c->f_krow = (uint8_t*)(base + pl.f_krow);
+  c->f_work = (ulonglong4*)(base + pl.f_work);
   c->pos = (int2*)(base + pl.pos);
   c->owner = (uint32_t*)(base + pl.owner);
   c->nkept = (uint16_t*)(base + pl.nkept);
@@ -716,6 +744,9 @@ int tpc_sync(tpc_ctx* c, tpc_counts* counts) {
     counts->n_fallback_fail = ds.n_fallback_fail;
     counts->n_not_pd = ds.n_not_pd;
     counts->n_refit_fail = ds.n_refit_fail;
+    counts->follow_steps = ds.f_steps;
+    counts->follow_candidates = ds.f_cands;
+    counts->follow_updates = ds.f_upds;
   }
   DevStatus zero;
   std::memset(&zero, 0, sizeof zero);
@@ -727,7 +758,9 @@ int tpc_sync(tpc_ctx* c, tpc_counts* counts) {
 void* tpc_stream(tpc_ctx* c) { return c ? (void*)c->stream : nullptr; }
 
 int tpc_profile_enable(tpc_ctx* c, int on) {
-  if (!c) return TPC_ERR_ARG;
+  if (!c || on < 0 || on > 3) return TPC_ERR_ARG;
+  c->count_work = (on & 2) != 0;
+  on &= 1;
   if (on && !c->prof_events) {
     for (int i = 0; i < TPC_PROF_STAGES; ++i)
       for (int j = 0; j < 2; ++j)
@@ -770,7 +803,7 @@ int tpc_tuning_default(tpc_tuning* t) {
   t->cl_window = 16;
   t->cl_chunk = 8;
   t->follow_block = 64;
-  t->reserved = 0;
+  t->follow_mode = 0;
   return TPC_OK;
 }
 
@@ -779,6 +812,7 @@ int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if (t->cl_window != 16 && t->cl_window != 32) return TPC_ERR_ARG;
   if (t->cl_chunk != 4 && t->cl_chunk != 8 && t->cl_chunk != 16) return TPC_ERR_ARG;
   if (t->follow_block != 64 && t->follow_block != 128 && t->follow_block != 256) return TPC_ERR_ARG;
+  if (t->follow_mode != 0 && t->follow_mode != 1) return TPC_ERR_ARG;
   c->tune = *t;
   return TPC_OK;
 }

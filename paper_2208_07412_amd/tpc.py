@@ -74,11 +74,13 @@ class TpcTracks(ctypes.Structure):
 class TpcCounts(ctypes.Structure):
     _fields_ = [("status", I32), ("required", U32), ("n_samples", U32), ("n_clusters", U32),
                 ("n_tracklets", U32), ("n_tracks", U32), ("n_hits", U32), ("n_fallback", U32),
-                ("n_fallback_fail", U32), ("n_not_pd", U32), ("n_refit_fail", U32)]
+                ("n_fallback_fail", U32), ("n_not_pd", U32), ("n_refit_fail", U32),
+                ("reserved", U32), ("follow_steps", ctypes.c_uint64),
+                ("follow_candidates", ctypes.c_uint64), ("follow_updates", ctypes.c_uint64)]
 
 
 class TpcTuning(ctypes.Structure):
-    _fields_ = [("cl_window", I32), ("cl_chunk", I32), ("follow_block", I32), ("reserved", I32)]
+    _fields_ = [("cl_window", I32), ("cl_chunk", I32), ("follow_block", I32), ("follow_mode", I32)]
 
 
 EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_create",
@@ -342,20 +344,22 @@ class Reco:
     def tuning(self) -> dict:
         t = TpcTuning()
         _check(self.lib.tpc_get_tuning(self.ctx, ctypes.byref(t)), "tpc_get_tuning")
-        return {k: getattr(t, k) for k, _ in TpcTuning._fields_ if k != "reserved"}
+        return {k: getattr(t, k) for k, _ in TpcTuning._fields_}
 
     def set_tuning(self, **kw):
-        """Change launch shapes (cl_window, cl_chunk, follow_block)."""
+        """Change launch shapes (cl_window, cl_chunk, follow_block, follow_mode)."""
         t = TpcTuning()
         _check(self.lib.tpc_get_tuning(self.ctx, ctypes.byref(t)), "tpc_get_tuning")
         for k, v in kw.items():
-            if k not in ("cl_window", "cl_chunk", "follow_block"):
+            if k not in ("cl_window", "cl_chunk", "follow_block", "follow_mode"):
                 raise KeyError(k)
             setattr(t, k, int(v))
         _check(self.lib.tpc_set_tuning(self.ctx, ctypes.byref(t)), "tpc_set_tuning")
 
-    def profile(self, on: bool = True):
-        _check(self.lib.tpc_profile_enable(self.ctx, 1 if on else 0), "tpc_profile_enable")
+    def profile(self, on: bool = True, count_work: bool = False):
+        """Stage timers on/off; count_work also counts the following's work."""
+        _check(self.lib.tpc_profile_enable(self.ctx, (1 if on else 0) | (2 if count_work else 0)),
+               "tpc_profile_enable")
 
     def profile_read(self) -> dict:
         """Summed milliseconds and launch counts per stage since the last read."""

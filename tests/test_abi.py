@@ -99,7 +99,7 @@ def test_struct_layouts_match_header():
     # field counts of the binding against the header's struct members
     src = open(os.path.join(ROOT, "include", "tpc.h")).read()
     assert ctypes.sizeof(tpc.TpcParams) == 4 * 4 + 3 * 8 + 16 * 8 + 2 * 152 * 8 + 2 * 4
-    assert ctypes.sizeof(tpc.TpcCounts) == 11 * 4
+    assert ctypes.sizeof(tpc.TpcCounts) == 12 * 4 + 3 * 8
     assert "uint32_t capacity;" in src
 
 
@@ -107,7 +107,7 @@ def test_tuning_defaults_and_validation():
     lib = tpc.load()
     t = tpc.TpcTuning()
     assert lib.tpc_tuning_default(ctypes.byref(t)) == 0
-    assert (t.cl_window, t.cl_chunk, t.follow_block) == (16, 8, 64)
+    assert (t.cl_window, t.cl_chunk, t.follow_block, t.follow_mode) == (16, 8, 64, 0)
     assert lib.tpc_set_tuning(None, ctypes.byref(t)) == -1
     assert lib.tpc_get_tuning(None, ctypes.byref(t)) == -1
     assert lib.tpc_tuning_default(None) == -1

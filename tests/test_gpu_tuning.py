@@ -1,7 +1,8 @@
 """Every launch shape the library offers gives the oracle's results.
 
 Launch shapes (clusterizer window and windows per workgroup, workgroup size
-of the following kernel) only change how work is spread over the GPU, so each
+and lane-refill mode of the following kernel) only change how work is spread
+over the GPU, so each
 one is held to the same parity rules as the default: clusters, links,
 tracklets and hit sets bit-exact, parameters within tolerance.  The
 dense-lattice frame gives windows with hundreds of peaks, more than one
@@ -18,7 +19,8 @@ from _parity import compare_clusters, compare_fit, run_gpu, run_oracle
 pytestmark = pytest.mark.gpu
 
 NPADS, _, _ = oracle.geometry()
-SHAPES = [(16, 4, 64), (16, 8, 128), (16, 16, 256), (32, 4, 256), (32, 8, 64), (32, 16, 128)]
+SHAPES = [(16, 4, 64, 0), (16, 8, 128, 1), (16, 16, 256, 0), (32, 4, 256, 1), (32, 8, 64, 1),
+          (32, 16, 128, 0)]
 
 
 @pytest.fixture(scope="module")
@@ -29,10 +31,11 @@ def frame():
     return ev, run_oracle(ev, labels=True)
 
 
-@pytest.mark.parametrize("w,k,fb", SHAPES)
-def test_shape_parity(frame, w, k, fb):
+@pytest.mark.parametrize("w,k,fb,fm", SHAPES)
+def test_shape_parity(frame, w, k, fb, fm):
     ev, o = frame
-    g = run_gpu(ev, labels=True, tuning=dict(cl_window=w, cl_chunk=k, follow_block=fb))
+    g = run_gpu(ev, labels=True, tuning=dict(cl_window=w, cl_chunk=k, follow_block=fb,
+                                              follow_mode=fm))
     compare_clusters(g["clusters"], o["clusters"], labels=True)
     assert np.array_equal(g["links"]["down"], o["down"])
     assert np.array_equal(g["links"]["up"], o["up"])
@@ -77,3 +80,24 @@ def test_fully_occupied_rows(w, k):
     g = run_gpu(ev, labels=True, max_tracklets=64, tuning=dict(cl_window=w, cl_chunk=k))
     o = run_oracle(ev, labels=True)
     compare_clusters(g["clusters"], o["clusters"], labels=True)
+
+
+def test_work_counting_variant_same_results(frame):
+    # the measurement variant of the following kernel counts its work and
+    # must leave every output unchanged
+    ev, o = frame
+    from paper_2208_07412_amd import tpc
+
+    ns = ev.n_samples
+    reco = tpc.Reco(ev.n_units, ev.n_time_bins, ns, ns // 8)
+    reco.profile(False, count_work=True)
+    g1 = run_gpu(ev, reco=reco, max_tracklets=ns // 8)
+    c = g1["counts"]
+    assert c["follow_steps"] > 0 and c["follow_updates"] > 0 and c["follow_candidates"] > 0
+    assert c["follow_updates"] <= c["follow_steps"] + 2 * c["n_tracklets"]
+    reco.profile(False)
+    g2 = run_gpu(ev, reco=reco, max_tracklets=ns // 8)
+    assert g2["counts"]["follow_steps"] == 0
+    for k in ("tracklet", "par", "cov", "hits", "cluster_track"):
+        assert np.array_equal(g1["tracks"][k], g2["tracks"][k])
+    reco.close()
