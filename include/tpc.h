@@ -247,7 +247,7 @@ const char* tpc_profile_stage_name(int stage);
 const char* tpc_status_string(int status);
 
 /* Launch shapes (performance only: every choice gives the same results).
- * cl_window: clusterizer window in time bins, 16 or 32; cl_chunk: windows
+ * cl_window: clusterizer window in time bins, 8, 16 or 32; cl_chunk: windows
  * walked by one workgroup, 4, 8 or 16; follow_block: threads per workgroup
  * of the following kernel, 64, 128 or 256; follow_mode: 0 one tracklet per
  * lane, 1 lanes refilled from a range of tracklets per wave (lanes then

@@ -11,7 +11,8 @@ from __future__ import annotations
 
 from typing import Dict, List, Tuple
 
-CLUSTER_SHAPES: List[Tuple[int, int]] = [(16, 4), (16, 8), (16, 16), (32, 4), (32, 8), (32, 16)]
+CLUSTER_SHAPES: List[Tuple[int, int]] = [(8, 4), (8, 8), (8, 16), (16, 4), (16, 8), (16, 16),
+                                         (32, 4), (32, 8), (32, 16)]
 FOLLOW_SHAPES: List[Tuple[int, int]] = [(64, 0), (128, 0), (256, 0), (64, 1), (128, 1), (256, 1)]
 CLUSTER_STAGES = ("sample_index", "cluster_peaks", "cluster_scan", "cluster_output")
 FOLLOW_STAGES = ("following",)

@@ -22,7 +22,7 @@ namespace {
 
 // Clusterizer tile shapes compiled into the library (window in time bins,
 // windows per workgroup); the smallest window sizes the window-count scratch.
-constexpr uint32_t kMinWin = 16;
+constexpr uint32_t kMinWin = 8;
 
 struct Geometry {
   int32_t np[NROW], xfx[NROW], pfx[NROW];
@@ -346,7 +346,7 @@ template <int W, int K>
 void launch_cluster(tpc_ctx* c, const ZsArgs& za, uint32_t nblk_s, uint32_t n_ur,
                     const ClusterOut& co, uint32_t* n_clusters, uint32_t capacity,
                     uint32_t* crow_start) {
-  constexpr int PRE = W == 16 ? 2 : 3;
+  constexpr int PRE = W == 8 ? 1 : (W == 16 ? 2 : 3);
   hipStream_t s = c->stream;
   const uint32_t nwin = ceil_div(za.n_time_bins, W);
   const uint32_t nchunk = ceil_div(nwin, K);
@@ -397,7 +397,11 @@ int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
   using I4 = std::integral_constant<int, 4>;
   using I8 = std::integral_constant<int, 8>;
   using I16k = std::integral_constant<int, 16>;
-  if (w == 16 && k == 4) run(I16{}, I4{});
+  using I8w = std::integral_constant<int, 8>;
+  if (w == 8 && k == 4) run(I8w{}, I4{});
+  else if (w == 8 && k == 8) run(I8w{}, I8{});
+  else if (w == 8 && k == 16) run(I8w{}, I16k{});
+  else if (w == 16 && k == 4) run(I16{}, I4{});
   else if (w == 16 && k == 8) run(I16{}, I8{});
   else if (w == 16 && k == 16) run(I16{}, I16k{});
   else if (w == 32 && k == 4) run(I32{}, I4{});
@@ -809,7 +813,7 @@ int tpc_tuning_default(tpc_tuning* t) {
 
 int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if (!c || !t) return TPC_ERR_ARG;
-  if (t->cl_window != 16 && t->cl_window != 32) return TPC_ERR_ARG;
+  if (t->cl_window != 8 && t->cl_window != 16 && t->cl_window != 32) return TPC_ERR_ARG;
   if (t->cl_chunk != 4 && t->cl_chunk != 8 && t->cl_chunk != 16) return TPC_ERR_ARG;
   if (t->follow_block != 64 && t->follow_block != 128 && t->follow_block != 256) return TPC_ERR_ARG;
   if (t->follow_mode != 0 && t->follow_mode != 1) return TPC_ERR_ARG;

@@ -19,8 +19,8 @@ from _parity import compare_clusters, compare_fit, run_gpu, run_oracle
 pytestmark = pytest.mark.gpu
 
 NPADS, _, _ = oracle.geometry()
-SHAPES = [(16, 4, 64, 0), (16, 8, 128, 1), (16, 16, 256, 0), (32, 4, 256, 1), (32, 8, 64, 1),
-          (32, 16, 128, 0)]
+SHAPES = [(8, 8, 64, 0), (8, 16, 128, 1), (16, 4, 64, 0), (16, 8, 128, 1), (16, 16, 256, 0),
+          (32, 4, 256, 1), (32, 8, 64, 1), (32, 16, 128, 0)]
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +62,7 @@ def _lattice_event(T, step_t, step_p, adc):
                           np.array(a, np.uint16), rs, 1, T, {}, {}, None)
 
 
-@pytest.mark.parametrize("w,k", [(16, 8), (32, 4)])
+@pytest.mark.parametrize("w,k", [(8, 4), (16, 8), (32, 4)])
 def test_most_peaks_per_window(w, k):
     # isolated samples on every other pad and bin: each one is a peak, so a
     # window holds far more peaks than one moment batch
@@ -73,7 +73,7 @@ def test_most_peaks_per_window(w, k):
     compare_clusters(g["clusters"], o["clusters"], labels=True)
 
 
-@pytest.mark.parametrize("w,k", [(16, 8), (32, 16)])
+@pytest.mark.parametrize("w,k", [(8, 16), (16, 8), (32, 16)])
 def test_fully_occupied_rows(w, k):
     # every (time, pad) present: the densest input a row can have
     ev = _lattice_event(120, 1, 1, lambda t, p: 3 + ((t * 131 + p * 71) * 2654435761 % 2**32) % 400)
