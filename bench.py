@@ -51,7 +51,7 @@ def stage_bytes(ns, nc, n_ur, T, W=16):
     rec = 4 * 2 + 4 * 4 + 2 * 4 + 1
     raw = 24                 # raw record per cluster between the two clusterizer passes
     nblk_s = (T + 3) // 4   # sample index: one entry per 4 time bins
-    nblk_c = (T + 3) // 4   # cluster grid: one entry per 4 time bins
+    nblk_c = (T + 1) // 2   # cluster grid: one entry per 2 time bins
     nwin = n_ur * ((T + W - 1) // W)
     return {
         "sample_index": 2 * ns + 4 * n_ur * (nblk_s + 1),

@@ -249,11 +249,13 @@ const char* tpc_status_string(int status);
 /* Launch shapes (performance only: every choice gives the same results).
  * cl_window: clusterizer window in time bins, 8, 16 or 32; cl_chunk: windows
  * walked by one workgroup, 4, 8 or 16; follow_block: threads per workgroup
- * of the following kernel, 64, 128 or 256; follow_mode: 0 one tracklet per
- * lane, 1 lanes refilled from a range of tracklets per wave (lanes then
- * work on different passes at once).  tpc_set_tuning rejects other
- * values with TPC_ERR_ARG and leaves the context unchanged; it takes effect
- * at the next call (a captured graph keeps the shapes it was captured with). */
+ * of the following kernel, 64, 128 or 256; follow_mode: 0 one launch per
+ * pass (outward, then inward), each over the tracklets sorted by the most
+ * rows the pass can take, longest first; 1 one launch that runs both passes
+ * of a tracklet per lane, in tracklet order.  One tracklet per lane in both
+ * modes.  tpc_set_tuning rejects other values with TPC_ERR_ARG and leaves
+ * the context unchanged; it takes effect at the next call (a captured graph
+ * keeps the shapes it was captured with). */
 typedef struct {
   int32_t cl_window;
   int32_t cl_chunk;

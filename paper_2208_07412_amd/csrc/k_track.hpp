@@ -415,12 +415,16 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
 // Middle and end cluster of every tracklet (walk of its cleaned up-links) and
 // the unit-row of its start; 0xFFFFFFFF marks a tracklet that cannot be
 // followed (broken chain or rows beyond the last).
+// Per tracklet: its middle and end clusters, its start unit-row, and the
+// sort key of the outward following pass: the rows above its start row (the
+// most rows that pass can take), 0 if it cannot be followed.
 __global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_t n_ur,
                                                          const int32_t* __restrict__ upc,
                                                          const uint32_t* __restrict__ tl_start,
                                                          const uint16_t* __restrict__ tl_len,
                                                          const uint32_t* n_tl_dev, uint32_t tl_cap,
                                                          uint32_t* __restrict__ pts,
+                                                         uint8_t* __restrict__ key,
                                                          const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
@@ -429,9 +433,11 @@ __global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_
     const uint32_t A = tl_start[t];
     const int L = tl_len[t];
     uint32_t M = 0xFFFFFFFFu, E = 0xFFFFFFFFu, urA = 0;
+    uint8_t rows = 0;
     if (A < n_cl && L >= 3) {
       urA = cluster_ur(cl.crow, n_ur, A);
-      if ((int)(urA % NROW) + L <= NROW) {
+      const int r1 = (int)(urA % NROW);
+      if (r1 + L <= NROW) {
         const int im = (L + 1) / 2 - 1;
         uint32_t c = A, m = A;
         bool bad = false;
@@ -447,12 +453,82 @@ __global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_
         if (!bad) {
           M = m;
           E = c;
+          rows = (uint8_t)(NROW - 1 - r1);
         }
       }
     }
     pts[(size_t)t * 3 + 0] = M;
     pts[(size_t)t * 3 + 1] = E;
     pts[(size_t)t * 3 + 2] = urA;
+    key[t] = rows;
+  }
+}
+
+// Stable counting sort of the tracklets by an 8-bit key, largest first.  The
+// key is the most rows a following pass can take (rows above the start row
+// outward; the row of the outermost pass-A hit inward): the passes that can
+// run longest start first, and the lanes of a wave start on one row and step
+// through the same rows, reading the same parts of the hit grid.  Three steps: k_sort_work<false> counts each
+// block of SORT_BLOCK tracklets per key into bins[key' * nblk + block]
+// (key' = 255 - key); an exclusive scan of bins in place gives every
+// (key', block) its first position; k_sort_work<true> writes perm, ranking
+// the elements of one key in index order.  Tracklets of equal estimate keep
+// their order (unit, row, time), so neighbouring tracks share a wave.  Wave w of
+// a workgroup takes the elements [256 w, 256 w + 256) of its block.
+#define SORT_BLOCK 1024
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_sort_work(const uint8_t* __restrict__ key,
+                                                   const uint32_t* n_tl_dev, uint32_t tl_cap,
+                                                   uint32_t nblk, uint32_t* __restrict__ bins,
+                                                   uint32_t* __restrict__ perm,
+                                                   const DevStatus* st) {
+  if (failed(st)) return;
+  __shared__ uint32_t h[4][256];  // per wave: count per key, then next position per key
+  const uint32_t n = scan_count(n_tl_dev, tl_cap);
+  const uint32_t b0 = blockIdx.x * SORT_BLOCK;
+  const uint32_t m = b0 < n ? min((uint32_t)SORT_BLOCK, n - b0) : 0u;
+  if (SCATTER && m == 0) return;  // uniform per workgroup
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) h[j][threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t bin[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t i = 256u * w + 64u * j + lane;
+    bin[j] = i < m ? 255u - key[b0 + i] : 0u;
+    if (i < m) atomicAdd(&h[w][bin[j]], 1u);
+  }
+  __syncthreads();
+  const uint32_t k = threadIdx.x;
+  const uint32_t c0 = h[0][k], c1 = h[1][k], c2 = h[2][k], c3 = h[3][k];
+  if (!SCATTER) {
+    bins[(size_t)k * nblk + blockIdx.x] = c0 + c1 + c2 + c3;
+    return;
+  }
+  const uint32_t base = bins[(size_t)k * nblk + blockIdx.x];
+  __syncthreads();
+  h[0][k] = base;
+  h[1][k] = base + c0;
+  h[2][k] = base + c0 + c1;
+  h[3][k] = base + c0 + c1 + c2;
+  __syncthreads();
+  const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t i = 256u * w + 64u * j + lane;
+    const bool v = i < m;
+    uint64_t eq = __ballot(v);  // valid lanes with the same key
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (bin[j] >> bit) & 1u;
+      const uint64_t bb = __ballot(on);
+      eq &= on ? bb : ~bb;
+    }
+    if (v) perm[h[w][bin[j]] + (uint32_t)__popcll(eq & below)] = b0 + i;
+    // the highest lane of each key advances the key's position; the reads
+    // above belong to an earlier instruction of this wave
+    if (v && (eq >> lane) == 1ull) h[w][bin[j]] += (uint32_t)__popcll(eq);
   }
 }
 
@@ -563,16 +639,14 @@ __device__ __forceinline__ void follow_finish(const FollowLane& f, FollowOut& fo
   fo.ok[f.t] = 1;
 }
 
-// One row of pass A (outward) or pass B (inward).  PA = 1: pass A, 0: pass
-// B, -1: the lane's own pass (rt_pa), when lanes of a wave are in different
-// passes.  Returns true when the pass has ended.
+// One row of pass A (outward, PA = 1) or pass B (inward, PA = 0).  Returns
+// true when the pass has ended.
 template <int PA>
 __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl,
                                             const uint32_t* cblk, uint32_t nblk,
                                             const int32_t* upc, FollowOut& fo, const DevParams* P,
-                                            const PV<float>& pv, float chi2max,
-                                            bool rt_pa = false) {
-  const bool pa = PA < 0 ? rt_pa : PA == 1;
+                                            const PV<float>& pv, float chi2max) {
+  constexpr bool pa = PA == 1;
   const int rn = f.r + (pa ? 1 : -1);
   if (rn >= NROW || rn < 0) return true;
   Trk<float>& k = f.k;
@@ -621,14 +695,44 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
   return false;
 }
 
+// Pass B start of tracklet t from what pass A left in the outputs: the
+// state at the outermost pass-A hit, its row, the hit count and row range.
+__device__ __forceinline__ void follow_resume(FollowLane& f, uint32_t t, const ClusterView& cl,
+                                              const uint32_t* tl_start, const uint16_t* tl_len,
+                                              const uint32_t* pts, const FollowOut& fo) {
+  const uint32_t urA = pts[(size_t)t * 3 + 2];
+  f.t = t;
+  f.r1 = (int)(urA % NROW);
+  f.ubase = urA - (uint32_t)f.r1;
+  f.L = tl_len[t];
+  f.anchor = cl.pos[tl_start[t]].y;
+  const float* S = fo.state + (size_t)t * 6;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) f.sp[i] = S[i];
+  f.rs = (int)S[5];
+  f.nh = fo.nhits[t];
+  f.hi = fo.range[t] >> 8;
+  f.ctl = -1;
+}
+
+enum { FP_A = 0, FP_B = 1, FP_AB = 2 };
+
+// Following, one tracklet per lane.  FP_A: seed and pass A of the tracklets
+// in the order perm gives, leaving the pass-A
+// result in the outputs and the sort key of pass B (the row of the outermost
+// pass-A hit) in key; FP_B: pass B of the tracklets that pass A
+// followed, in the order perm gives; FP_AB: both passes per lane, tracklets in
+// index order (perm unused).  Either way a tracklet's result is the same.
 // COUNT: also count the work done (helix steps, candidates, updates) into
 // per-wave counters, for measurement only.
-template <int B, bool COUNT>
+template <int B, int PASS, bool COUNT>
 __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __restrict__ cblk,
                                                uint32_t nblk, const int32_t* __restrict__ upc,
                                                const uint32_t* __restrict__ tl_start,
                                                const uint16_t* __restrict__ tl_len,
                                                const uint32_t* __restrict__ pts,
+                                               const uint32_t* __restrict__ perm,
+                                               uint8_t* __restrict__ key,
                                                const uint32_t* n_tl_dev, uint32_t tl_cap,
                                                FollowOut fo, ulonglong4* __restrict__ work,
                                                const DevParams* __restrict__ P, DevStatus* st) {
@@ -640,22 +744,34 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
   const PV<float> pv{P};
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const float chi2max = pv.chi2_max();
-  // consecutive tracklets (same start row, nearby times) share a wave
   uint32_t w_steps = 0, w_cands = 0, w_upds = 0;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tl; i += gridDim.x * blockDim.x) {
+    const uint32_t t = PASS == FP_AB ? i : perm[i];
     FollowLane f;
     f.n_steps = f.n_cands = f.n_upds = 0;
-    if (!follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) {
+    if (PASS == FP_B) {
+      if (!fo.ok[t]) continue;
+      follow_resume(f, t, cl, tl_start, tl_len, pts, fo);
+    } else if (!follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) {
+      if (PASS == FP_A) key[t] = 0;
       if (COUNT) w_upds += f.n_upds;
       continue;
     }
-    while (!follow_step<1>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
-    }
-    if (follow_start_b(f, cl, fo, pv)) {
-      while (!follow_step<0>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
+    if (PASS != FP_B) {
+      while (!follow_step<1>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
       }
     }
-    follow_finish(f, fo);
+    if (PASS == FP_A) {
+      f.lo = f.r1;
+      follow_finish(f, fo);
+      key[t] = (uint8_t)f.rs;
+    } else if (follow_start_b(f, cl, fo, pv)) {
+      while (!follow_step<0>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
+      }
+      follow_finish(f, fo);
+    } else if (PASS == FP_AB) {
+      follow_finish(f, fo);
+    }
     if (COUNT) {
       w_steps += f.n_steps;
       w_cands += f.n_cands;
@@ -668,78 +784,6 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
   const unsigned long long s0 = wave_sum_u64(w_steps), s1 = wave_sum_u64(w_cands),
                            s2 = wave_sum_u64(w_upds);
   if ((threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(s0, s1, s2, 0);
-}
-
-// Following with lane refill: each wave owns a range of FW_RANGE consecutive
-// tracklets and keeps its lanes busy, handing the next tracklets of its range
-// to idle lanes once at least FW_REFILL of them are idle (or all are).  Lanes
-// of a wave may then be in different passes; a lane's results are the same
-// as in k_follow, only the order of work differs.
-#define FW_RANGE 128
-#define FW_REFILL 16
-enum { FS_IDLE = 0, FS_A = 1, FS_B = 2 };
-template <int B, bool COUNT>
-__global__ __launch_bounds__(B) void k_follow_refill(
-    ClusterView cl, const uint32_t* __restrict__ cblk, uint32_t nblk,
-    const int32_t* __restrict__ upc, const uint32_t* __restrict__ tl_start,
-    const uint16_t* __restrict__ tl_len, const uint32_t* __restrict__ pts,
-    const uint32_t* n_tl_dev, uint32_t tl_cap, FollowOut fo, ulonglong4* __restrict__ work,
-    const DevParams* __restrict__ P, DevStatus* st) {
-  const uint32_t wave = blockIdx.x * (B / 64) + (threadIdx.x >> 6);
-  const uint32_t lane = threadIdx.x & 63;
-  if (failed(st)) {
-    if (COUNT && lane == 0) work[wave] = make_ulonglong4(0, 0, 0, 0);
-    return;
-  }
-  const PV<float> pv{P};
-  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  const float chi2max = pv.chi2_max();
-  const uint32_t nw = gridDim.x * (B / 64);
-  uint32_t w_steps = 0, w_cands = 0, w_upds = 0;
-  for (uint32_t rb = uni(wave * FW_RANGE); rb < n_tl; rb += nw * FW_RANGE) {
-    const uint32_t re = min(rb + FW_RANGE, n_tl);
-    uint32_t next = rb;
-    FollowLane f;
-    int phase = FS_IDLE;
-    for (;;) {
-      const uint64_t idle = __ballot(phase == FS_IDLE);
-      const uint32_t n_idle = (uint32_t)__popcll(idle);
-      if (n_idle == 64 && next >= re) break;
-      if (next < re && (n_idle >= FW_REFILL || n_idle == 64)) {
-        if (phase == FS_IDLE) {
-          const uint32_t t = next + (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
-          if (t < re) {
-            f.n_steps = f.n_cands = f.n_upds = 0;
-            if (follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) {
-              phase = FS_A;
-            } else if (COUNT) {
-              w_upds += f.n_upds;
-            }
-          }
-        }
-        next = min(next + n_idle, re);
-        continue;
-      }
-      if (phase != FS_IDLE &&
-          follow_step<-1>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max, phase == FS_A)) {
-        if (phase == FS_A && follow_start_b(f, cl, fo, pv)) {
-          phase = FS_B;
-        } else {
-          follow_finish(f, fo);
-          if (COUNT) {
-            w_steps += f.n_steps;
-            w_cands += f.n_cands;
-            w_upds += f.n_upds;
-          }
-          phase = FS_IDLE;
-        }
-      }
-    }
-  }
-  if (!COUNT) return;
-  const unsigned long long s0 = wave_sum_u64(w_steps), s1 = wave_sum_u64(w_cands),
-                           s2 = wave_sum_u64(w_upds);
-  if (lane == 0) work[wave] = make_ulonglong4(s0, s1, s2, 0);
 }
 
 // Sum of the following's per-wave work counters into the status block.

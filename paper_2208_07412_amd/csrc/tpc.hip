@@ -67,10 +67,13 @@ struct tpc_ctx {
   uint16_t* f_nhits = nullptr;
   uint16_t* f_range = nullptr;
   uint8_t* f_ok = nullptr;
-  uint32_t* f_pts = nullptr;
+  uint32_t* f_pts = nullptr;   // per tracklet: middle and end cluster, unit-row of the start
+  uint8_t* f_key = nullptr;    // per tracklet: estimated rows of the next following pass
+  uint32_t* f_perm = nullptr;  // tracklets in the order a following pass takes them
+  uint32_t* f_bins = nullptr;  // counts, then first positions, per (work estimate, block)
   uint8_t* f_krow = nullptr;
   ulonglong4* f_work = nullptr;  // per-wave work counters of the following
-  int2* pos = nullptr;  // packed cluster positions  // per tracklet: middle and end cluster, unit-row of the start
+  int2* pos = nullptr;           // packed cluster positions
   uint32_t* owner = nullptr;
   uint16_t* nkept = nullptr;
   float *r_par = nullptr, *r_cov = nullptr, *r_chi2 = nullptr;
@@ -107,7 +110,7 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_krow, f_work, pos,
+  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
       h_flags, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
@@ -124,6 +127,8 @@ Plan plan_for(const tpc_sizes& m) {
   uint64_t nscan = nur * p.nwin;
   if (m.max_clusters > nscan) nscan = m.max_clusters;
   if (m.max_tracklets > nscan) nscan = m.max_tracklets;
+  if (256ull * ceil_div(m.max_tracklets, SORT_BLOCK) > nscan)
+    nscan = 256ull * ceil_div(m.max_tracklets, SORT_BLOCK);
   p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
   const uint64_t mc = m.max_clusters > 0 ? m.max_clusters : 1;
   const uint64_t mt = m.max_tracklets > 0 ? m.max_tracklets : 1;
@@ -141,8 +146,11 @@ Plan plan_for(const tpc_sizes& m) {
   p.f_range = L.add<uint16_t>(mt);
   p.f_ok = L.add<uint8_t>(mt);
   p.f_pts = L.add<uint32_t>(mt * 3);
+  p.f_key = L.add<uint8_t>(mt);
+  p.f_perm = L.add<uint32_t>(mt);
+  p.f_bins = L.add<uint32_t>(256 * ceil_div(mt, SORT_BLOCK));
   p.f_krow = L.add<uint8_t>(mt * NROW);
-  p.f_work = L.add<ulonglong4>(mt / 64 + 8);
+  p.f_work = L.add<ulonglong4>(2 * (mt / 64 + 8));  // two passes
   p.pos = L.add<int2>(mc);
   p.owner = L.add<uint32_t>(mc);
   p.nkept = L.add<uint16_t>(mt);
@@ -468,26 +476,42 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
     StageTimer tm(c, 6);  // the tracklets' seed points belong to tracklet building
     k_tracklet_points<<<grid_for(tcap, 256), 256, 0, s>>>(cv, n_ur, l->upc, t->start, t->len,
                                                            t->n_tracklets, tcap, c->f_pts,
-                                                           c->d_st);
+                                                           c->f_key, c->d_st);
   }
   {
     StageTimer tm(c, 7);
     const int fb = c->tune.follow_block;
     const uint32_t gf = grid_for(tcap, fb);
-    const bool refill = c->tune.follow_mode == 1;
-    // refill mode: one wave per range of FW_RANGE tracklets
-    const uint32_t gr = grid_for((uint64_t)ceil_div(tcap, FW_RANGE) * 64, fb);
+    const uint32_t nwf = gf * (uint32_t)(fb / 64);  // waves per following launch
+    const bool split = c->tune.follow_mode == 0;
+    const uint32_t nsb = ceil_div(tcap, SORT_BLOCK);
     auto launch = [&](auto Bc, auto Cc) {
       constexpr int Bv = decltype(Bc)::value;
       constexpr bool Cv = decltype(Cc)::value;
-      if (refill)
-        k_follow_refill<Bv, Cv><<<gr, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
-                                                  c->f_pts, t->n_tracklets, tcap, fo, c->f_work,
-                                                  c->d_par, c->d_st);
-      else
-        k_follow<Bv, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
-                                           c->f_pts, t->n_tracklets, tcap, fo, c->f_work,
-                                           c->d_par, c->d_st);
+      if (split) {
+        // pass A, then pass B, each over the tracklets sorted by the most rows
+        // the pass can take (the key k_tracklet_points, then pass A, leaves)
+        for (int pass = 0; pass < 2; ++pass) {
+          k_sort_work<false><<<nsb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, nsb, c->f_bins,
+                                                 c->f_perm, c->d_st);
+          run_scan<uint32_t>(c, GetU32{c->f_bins}, EmitU32{c->f_bins}, (const uint32_t*)nullptr,
+                             256 * nsb, (uint32_t*)nullptr, (uint32_t*)nullptr);
+          k_sort_work<true><<<nsb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, nsb, c->f_bins,
+                                                c->f_perm, c->d_st);
+          if (pass == 0)
+            k_follow<Bv, FP_A, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
+                                                     c->f_pts, c->f_perm, c->f_key, t->n_tracklets,
+                                                     tcap, fo, c->f_work, c->d_par, c->d_st);
+          else
+            k_follow<Bv, FP_B, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
+                                                     c->f_pts, c->f_perm, c->f_key, t->n_tracklets,
+                                                     tcap, fo, c->f_work + nwf, c->d_par, c->d_st);
+        }
+      } else {
+        k_follow<Bv, FP_AB, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
+                                                  c->f_pts, nullptr, c->f_key, t->n_tracklets,
+                                                  tcap, fo, c->f_work, c->d_par, c->d_st);
+      }
     };
     using B64 = std::integral_constant<int, 64>;
     using B128 = std::integral_constant<int, 128>;
@@ -498,9 +522,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
     if (fb == 256) cnt ? launch(B256{}, Cnt{}) : launch(B256{}, NoCnt{});
     else if (fb == 128) cnt ? launch(B128{}, Cnt{}) : launch(B128{}, NoCnt{});
     else cnt ? launch(B64{}, Cnt{}) : launch(B64{}, NoCnt{});
-    if (cnt)
-      k_work_sum<<<1, 1024, 0, s>>>(c->f_work, (refill ? gr : gf) * (uint32_t)(fb / 64),
-                                    c->d_st);
+    if (cnt) k_work_sum<<<1, 1024, 0, s>>>(c->f_work, (split ? 2 : 1) * nwf, c->d_st);
   }
   {
     StageTimer tm(c, 8);
@@ -640,6 +662,9 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->f_range = (uint16_t*)(base + pl.f_range);
   c->f_ok = (uint8_t*)(base + pl.f_ok);
   c->f_pts = (uint32_t*)(base + pl.f_pts);
+  c->f_key = (uint8_t*)(base + pl.f_key);
+  c->f_perm = (uint32_t*)(base + pl.f_perm);
+  c->f_bins = (uint32_t*)(base + pl.f_bins);
   c->f_krow = (uint8_t*)(base + pl.f_krow);
   c->f_work = (ulonglong4*)(base + pl.f_work);
   c->pos = (int2*)(base + pl.pos);
