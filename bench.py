@@ -3,8 +3,10 @@
 
 Workload (headline): a 2 ms slice of 50 kHz minimum-bias Pb-Pb, 100
 collisions overlapping in 10,500 time bins, 36 sectors x 152 pad rows,
-seed 303, reconstructed in one graph-captured launch sequence (the batched
-form).  Inputs are resident in HBM before the timed region starts.
+seed 303, reconstructed as one graph replay per step (the batched form: one
+library context over the whole slice, or the units cut into slices on
+concurrent streams, whichever is faster).  Inputs are resident in HBM before
+the timed region starts.
 
 Beside it: the plain form (one central collision per synchronous call, seed
 202, default launch shapes, no graph) with its per-call latency; the serving
@@ -220,6 +222,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-stress", action="store_true", help="skip the precision-stress leg")
     ap.add_argument("--collisions", type=int, default=100)
+    ap.add_argument("--slices", type=int, nargs="*", default=[2, 3, 4],
+                    help="unit slices on concurrent streams tried for the batched form")
     ap.add_argument("--serve-pool", type=int, default=6, help="distinct chunks resident in HBM")
     ap.add_argument("--serve-chunks", type=int, default=36, help="chunks in the Poisson stream")
     ap.add_argument("--serve-slots", type=int, default=3, help="concurrent chunks (streams)")
@@ -235,6 +239,7 @@ def main():
 
     import tpcsynth
     from paper_2208_07412_amd import tpc
+    from paper_2208_07412_amd.pipeline import Pipeline
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -301,35 +306,61 @@ def main():
     stages = {k: v[0] / 3 for k, v in prof.items()}  # per reconstruction
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
 
-    # timed region: the batched form, one graph replay per step
-    graph = None
-    if not args.no_graph:
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=stream):
-            reco.process(zs, cl, links, tl, tr, zs_s)
-        torch.cuda.synchronize()
+    # the batched form: one context over the whole slice, or the slice's units
+    # cut into n slices on n streams (pipeline.Pipeline), each captured as one
+    # graph; the fastest form is the one timed
+    def capture(enqueue):
+        g = torch.cuda.CUDAGraph()
         with torch.cuda.stream(stream):
-            graph.replay()
-        reco.sync()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        e0.record(stream)
-        for _ in range(args.steps):
-            if graph is not None:
-                graph.replay()
-            else:
-                reco.process(zs, cl, links, tl, tr, zs_s)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_step = e0.elapsed_time(e1) / args.steps
-    c2 = reco.sync()
+            enqueue()  # first use of every launch outside the capture
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            enqueue()
+        torch.cuda.synchronize()
+        return g
+
+    def time_steps(run, steps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(steps):
+                run()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, (time.perf_counter() - w0) / steps * 1e3
+
+    forms = {}
+    one = lambda: reco.process(zs, cl, links, tl, tr, zs_s)
+    if args.no_graph:
+        forms[1] = (None, one, None)
+    else:
+        g1 = capture(one)
+        forms[1] = (g1, g1.replay, None)
+        for n in args.slices:
+            if n <= 1:
+                continue
+            pl = Pipeline(zs, n, tuning=tuning["chosen"] if tuning else None)
+            gn = capture(pl.enqueue)
+            forms[n] = (gn, gn.replay, pl)
+    form_ms = {n: time_steps(f[1], 5)[0] for n, f in forms.items()}
+    best = min(form_ms, key=form_ms.get)
+    log("[bench] batched forms (slices: ms/step): " +
+        ", ".join(f"{n}: {v:.3f}" for n, v in form_ms.items()))
+    for n, f in forms.items():
+        if n != best and f[2] is not None:
+            f[2].close()
+    graph, run_best, pl_best = forms[best]
+
+    # timed region: the chosen batched form, one graph replay per step
+    ms_step, wall_ms = time_steps(run_best, args.steps)
+    c2 = pl_best.sync() if pl_best is not None else reco.sync()
     assert c2["n_clusters"] == nc, "graph replay changed the result"
+    assert c2["n_tracks"] == counts["n_tracks"], "graph replay changed the result"
     value = nc / (ms_step / 1e3)
-    log(f"[bench] batched: {ms_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} wall), "
+    log(f"[bench] batched ({best} slice(s)): {ms_step:.3f} ms/step ({wall_ms:.3f} wall), "
         f"{value:.4g} clusters/s")
 
     # roofline of the dominant kernel (the following: FP32 ALU) and of the
@@ -365,12 +396,16 @@ def main():
                vs_baseline=None, dtype="f32+int", data="synthetic",
                config=dict(workload="2 ms Pb-Pb slice at 50 kHz: 100 minimum-bias collisions, "
                            "36 sectors x 152 rows, 10500 time bins, seed 303",
-                           form="batched (graph replay)" if graph is not None else "eager",
+                           form=(f"batched: {best} unit slice(s) on {best} stream(s), one "
+                                 "graph replay per step") if graph is not None else "eager",
+                           slices=best, slice_ms=form_ms,
                            samples=ns, clusters=nc, tracks=counts["n_tracks"]),
                roofline=roofline, roofline_hbm=roofline_hbm, stages_ms=stages)
     if tuning is not None:
         out["tuning"] = tuning["chosen"]
-    del graph
+    del graph, forms
+    if pl_best is not None:
+        pl_best.close()
 
     # plain form: one central collision per synchronous call
     if not args.no_plain:

@@ -31,6 +31,18 @@ struct DevParams {
   int32_t validate, force_fallback;
 };
 
+// The parameters and row tables copied into LDS by the whole workgroup (a
+// barrier follows): per-lane row lookups in long serial loops then cost an
+// LDS read instead of a round trip to the caches.
+__device__ __forceinline__ const DevParams* params_to_lds(const DevParams* P, DevParams* lds) {
+  static_assert(sizeof(DevParams) % 8 == 0, "copied in 8-byte words");
+  const uint2* src = reinterpret_cast<const uint2*>(P);
+  uint2* dst = reinterpret_cast<uint2*>(lds);
+  for (uint32_t i = threadIdx.x; i < sizeof(DevParams) / 8; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  return lds;
+}
+
 // Status word and device-side counts of one context.
 struct DevStatus {
   int32_t status;
@@ -76,6 +88,16 @@ __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_read
 
 // ------------------------------------------------------------ wave64 scans
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Issue priority of the calling wave from a wave-uniform amount of remaining
+// serial work (steps): waves with the longest serial chains set the length of
+// a launch whose total work is small, so they issue first on their SIMD.
+__device__ __forceinline__ void wave_prio(uint32_t steps) {
+  if (steps >= 96) __builtin_amdgcn_s_setprio(3);
+  else if (steps >= 64) __builtin_amdgcn_s_setprio(2);
+  else if (steps >= 32) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {

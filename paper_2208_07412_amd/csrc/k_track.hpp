@@ -735,12 +735,14 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
                                                uint8_t* __restrict__ key,
                                                const uint32_t* n_tl_dev, uint32_t tl_cap,
                                                FollowOut fo, ulonglong4* __restrict__ work,
-                                               const DevParams* __restrict__ P, DevStatus* st) {
+                                               const DevParams* __restrict__ Pg, DevStatus* st) {
   const uint32_t wave = blockIdx.x * (B / 64) + (threadIdx.x >> 6);
   if (failed(st)) {
     if (COUNT && (threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(0, 0, 0, 0);
     return;
   }
+  __shared__ DevParams Ps;
+  const DevParams* P = params_to_lds(Pg, &Ps);
   const PV<float> pv{P};
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const float chi2max = pv.chi2_max();
@@ -829,7 +831,15 @@ __device__ __forceinline__ uint32_t track_key(uint32_t nh, uint32_t t) {
 // of the tracklet's hit table (contiguous), so every table read is coalesced.
 // The tracklet index is made wave-uniform so its scalars load once.
 
-// Every followed tracklet with enough hits bids for its clusters.
+// Every followed tracklet with enough hits bids for its clusters: the owner
+// of a cluster is the largest key among its bidders.  Two launches instead of
+// one atomicMax per hit: FIX = false stores every bidder's key (one of them
+// lands); FIX = true reads the owner back and raises it with atomicMax only
+// where the bidder's key is larger.  Owners only grow in the second launch
+// and hold bidders' keys, so the largest bidder either reads its own key or
+// raises the owner to it: the result is the maximum.  Most clusters have one
+// bidder and cost a plain store and a load instead of a device-scope atomic.
+template <bool FIX>
 __global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_tl_dev,
                                                uint32_t tl_cap,
                                                uint32_t* __restrict__ owner,
@@ -847,16 +857,21 @@ __global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_t
     const int32_t* H = fo.hits + (size_t)t * NROW;
     for (int r = lo + (int)lane; r <= hi; r += 64) {
       const int32_t c = H[r];
-      if (c >= 0 && (uint32_t)c < n_cl_cap) atomicMax(&owner[c], key);
+      if (c < 0 || (uint32_t)c >= n_cl_cap) continue;
+      if (!FIX) owner[c] = key;
+      else if (owner[c] < key) atomicMax(&owner[c], key);
     }
   }
 }
 
 // Hits each track keeps after the claims; < min_track_hits drops the track.
+// The kept count is also the refit's sort key: the refit takes the tracks
+// sorted by it, so the lanes of a wave refit tracks of equal length.
 __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl_dev,
                                               uint32_t tl_cap,
                                               const uint32_t* __restrict__ owner,
                                               uint32_t n_cl_cap, uint16_t* __restrict__ nkept,
+                                              uint8_t* __restrict__ key,
                                               const DevParams* __restrict__ P,
                                               const DevStatus* st) {
   if (failed(st)) return;
@@ -884,7 +899,10 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
       }
       if ((int)n < P->min_track_hits) n = 0;
     }
-    if (lane == 0) nkept[t] = (uint16_t)n;
+    if (lane == 0) {
+      nkept[t] = (uint16_t)n;
+      key[t] = (uint8_t)n;  // sort key of the refit (n <= NROW)
+    }
   }
 }
 
@@ -919,13 +937,19 @@ __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, cons
   const int32_t* H = fo.hits + (size_t)t * NROW;
   const uint8_t* KR = fo.krow + (size_t)t * NROW;
   int done = 0;
+  if (i < 0 || max_hits <= 0) return 0;
+  // the row, cluster and position of the next hit are read a step ahead,
+  // each behind a part of this step's arithmetic, so that their dependent
+  // loads overlap it
+  int r = KR[i];
+  int2 q = cl.pos[H[r]];
   for (; i >= 0 && done < max_hits; --i) {
-    const int r = KR[i];
-    const int32_t c = H[r];
+    const bool more = i > 0 && done + 1 < max_hits;
+    const int r_n = more ? (int)KR[i - 1] : r;
     if (r != r_state &&
         !propagate(k, row_dx<T>(P, r_state, r), pv, true, pv.refit_snp_max(), lp))
       return 1;
-    const int2 q = cl.pos[c];
+    const int32_t c_n = more ? H[r_n] : 0;
     const T my = (T)q.x * (T)FX_SCALE;
     const T mz = (T)(q.y - anchor) * (T)FX_SCALE;
     T x2;
@@ -940,10 +964,13 @@ __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, cons
       for (int i = 0; i < 5; ++i)
         if (k.c[PI(i, i)] < (T)P->fp32_guard * d0[i]) *guard = true;
     }
+    const int2 q_n = more ? cl.pos[c_n] : q;
     chi2s += x2;
     if (!is_pd(k.c)) pd = false;
     r_state = r;
     ++done;
+    r = r_n;
+    q = q_n;
   }
   return 0;
 }
@@ -1007,11 +1034,15 @@ __global__ __launch_bounds__(64) void k_refit_head(ClusterView cl,
                                                    uint32_t tl_cap,
                                                    const uint32_t* __restrict__ owner,
                                                    const uint16_t* __restrict__ nkept,
-                                                   RefitHead hd, const DevParams* __restrict__ P,
+                                                   const uint32_t* __restrict__ perm,
+                                                   RefitHead hd, const DevParams* __restrict__ Pg,
                                                    const DevStatus* st) {
   if (failed(st)) return;
+  __shared__ DevParams Ps;
+  const DevParams* P = params_to_lds(Pg, &Ps);
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_tl; j += gridDim.x * blockDim.x) {
+    const uint32_t t = perm[j];
     const int n = nkept[t];
     if (n == 0) continue;
     Trk<double> k;
@@ -1039,12 +1070,17 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
                                                 FollowOut fo, const uint32_t* n_tl_dev,
                                                 uint32_t tl_cap,
                                                 const uint32_t* __restrict__ owner,
-                                                const uint16_t* __restrict__ nkept, RefitHead hd,
+                                                const uint16_t* __restrict__ nkept,
+                                                const uint32_t* __restrict__ perm, RefitHead hd,
                                                 RefitOut ro, uint32_t* __restrict__ fb_list,
-                                                const DevParams* __restrict__ P, DevStatus* st) {
+                                                const DevParams* __restrict__ Pg, DevStatus* st) {
   if (failed(st)) return;
+  __shared__ DevParams Ps;
+  const DevParams* P = params_to_lds(Pg, &Ps);
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_tl; j += gridDim.x * blockDim.x) {
+    const uint32_t t = perm[j];
+    wave_prio(uni((uint32_t)nkept[t]));  // sorted: lane 0 holds the wave's longest track
     ro.flags[t] = 0;
     if (nkept[t] == 0) continue;
     if (hd.flags[t] & 1) {
@@ -1105,8 +1141,10 @@ __global__ __launch_bounds__(64) void k_refit64(ClusterView cl, const uint32_t* 
                                                 FollowOut fo, uint32_t tl_cap,
                                                 const uint16_t* __restrict__ nkept,
                                                 RefitOut ro, const uint32_t* __restrict__ fb_list,
-                                                const DevParams* __restrict__ P, DevStatus* st) {
+                                                const DevParams* __restrict__ Pg, DevStatus* st) {
   if (failed(st)) return;
+  __shared__ DevParams Ps;
+  const DevParams* P = params_to_lds(Pg, &Ps);
   const uint32_t n = scan_count(&st->n_fb_list, tl_cap);
   if (blockIdx.x == 0 && threadIdx.x == 0) st->n_fallback = n;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {

@@ -470,6 +470,16 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   const RefitOut ro = refit_out(c);
   const uint32_t g64 = grid_for(tcap, 64);
   const uint32_t gw = grid_for(tcap, 32);
+  // f_perm = the tracklets sorted by f_key, largest first (stable)
+  const uint32_t nsb = ceil_div(tcap, SORT_BLOCK);
+  auto sort_by_key = [&]() {
+    k_sort_work<false><<<nsb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, nsb, c->f_bins,
+                                           c->f_perm, c->d_st);
+    run_scan<uint32_t>(c, GetU32{c->f_bins}, EmitU32{c->f_bins}, (const uint32_t*)nullptr,
+                       256 * nsb, (uint32_t*)nullptr, (uint32_t*)nullptr);
+    k_sort_work<true><<<nsb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, nsb, c->f_bins,
+                                          c->f_perm, c->d_st);
+  };
   // per-call counters of the fit stage
   k_fill<uint32_t><<<1, 64, 0, s>>>(&c->d_st->n_fallback, 0u, 5);
   {
@@ -484,7 +494,6 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
     const uint32_t gf = grid_for(tcap, fb);
     const uint32_t nwf = gf * (uint32_t)(fb / 64);  // waves per following launch
     const bool split = c->tune.follow_mode == 0;
-    const uint32_t nsb = ceil_div(tcap, SORT_BLOCK);
     auto launch = [&](auto Bc, auto Cc) {
       constexpr int Bv = decltype(Bc)::value;
       constexpr bool Cv = decltype(Cc)::value;
@@ -492,12 +501,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
         // pass A, then pass B, each over the tracklets sorted by the most rows
         // the pass can take (the key k_tracklet_points, then pass A, leaves)
         for (int pass = 0; pass < 2; ++pass) {
-          k_sort_work<false><<<nsb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, nsb, c->f_bins,
-                                                 c->f_perm, c->d_st);
-          run_scan<uint32_t>(c, GetU32{c->f_bins}, EmitU32{c->f_bins}, (const uint32_t*)nullptr,
-                             256 * nsb, (uint32_t*)nullptr, (uint32_t*)nullptr);
-          k_sort_work<true><<<nsb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, nsb, c->f_bins,
-                                                c->f_perm, c->d_st);
+          sort_by_key();
           if (pass == 0)
             k_follow<Bv, FP_A, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
                                                      c->f_pts, c->f_perm, c->f_key, t->n_tracklets,
@@ -529,17 +533,19 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
     k_fill_dev<uint32_t><<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, 0u,
                                                                         cl->n_clusters, ccap);
     // one wave per tracklet, about 8 tracklets per wave
-    k_claim<<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->d_par, c->d_st);
-    k_keep<<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->nkept, c->d_par,
-                                c->d_st);
+    k_claim<false><<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->d_par, c->d_st);
+    k_claim<true><<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->d_par, c->d_st);
+    k_keep<<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->nkept, c->f_key,
+                              c->d_par, c->d_st);
   }
   {
     StageTimer tm(c, 9);
     const RefitHead hd{c->h_state, c->h_chi2, c->h_r, c->h_rprev, c->h_flags};
-    k_refit_head<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept, hd,
-                                    c->d_par, c->d_st);
-    k_refit32<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept, hd,
-                                 ro, c->fb_list, c->d_par, c->d_st);
+    sort_by_key();  // tracks by kept hits: lanes of a wave refit equally long tracks
+    k_refit_head<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept,
+                                    c->f_perm, hd, c->d_par, c->d_st);
+    k_refit32<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept,
+                                 c->f_perm, hd, ro, c->fb_list, c->d_par, c->d_st);
   }
   {
     StageTimer tm(c, 10);

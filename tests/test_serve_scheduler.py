@@ -129,3 +129,19 @@ def test_autotune_pick_keeps_current_within_margin():
     assert _pick({"a": 1.00, "b": 0.99}, "a", 0.02) == "a"
     assert _pick({"a": 1.00, "b": 0.95}, "a", 0.02) == "b"
     assert _pick({"a": 1.00, "b": 0.99}, "c", 0.02) == "b"
+
+
+def test_split_units_balances_samples():
+    from paper_2208_07412_amd.pipeline import split_units
+
+    rng = np.random.default_rng(5)
+    per_row = rng.integers(0, 50, 36 * 152)
+    rs = np.concatenate([[0], np.cumsum(per_row)]).astype(np.uint32)
+    for n in (1, 2, 3, 4, 36, 50):
+        b = split_units(rs, 36, n)
+        assert b[0] == 0 and b[-1] == 36 and len(b) == min(n, 36) + 1
+        assert all(x < y for x, y in zip(b[:-1], b[1:]))
+    b = split_units(rs, 36, 4)
+    s = [int(rs[u * 152]) for u in b]
+    part = np.diff(s)
+    assert part.max() - part.min() <= 2 * per_row.reshape(36, 152).sum(1).max()
