@@ -64,13 +64,21 @@ def stage_bytes(ns, nc, n_ur, T, W=16):
     }
 
 
-def pmc_traffic(kernel_file, stage, kernel_name):
-    """HBM bytes per launch of a stage's kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known
-    size), or None when the kernel source changed since the counters were
-    taken, the summary is for another launch shape, or none exists."""
+def source_hash(files):
+    """sha256 over the given source files (repository-relative), in order."""
     import hashlib
 
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def pmc_traffic(files, stage, kernel_name):
+    """HBM bytes per launch of a stage's kernel(s) from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known
+    size), or None when the kernel sources changed since the counters were
+    taken, the summary is for another launch shape, or none exists."""
     path = os.path.join(ROOT, "profiles", f"pmc_{stage}_c3_slice.md")
     if not os.path.exists(path):
         return None
@@ -80,8 +88,14 @@ def pmc_traffic(kernel_file, stage, kernel_name):
             rec = json.loads(line[len("traffic_json: "):])
     if rec is None or not rec.get("kernel", "").startswith(kernel_name):
         return None
-    h = hashlib.sha256(open(os.path.join(ROOT, kernel_file), "rb").read()).hexdigest()
-    return rec["bytes_per_launch"] if rec.get("source_sha256") == h else None
+    return rec["bytes_per_launch"] if rec.get("source_sha256") == source_hash(files) else None
+
+
+KERNEL_SOURCES = {
+    "cluster_peaks": ("paper_2208_07412_amd/csrc/common.hpp", "paper_2208_07412_amd/csrc/k_cluster.hpp"),
+    "following": ("paper_2208_07412_amd/csrc/common.hpp", "paper_2208_07412_amd/csrc/k_cluster.hpp",
+                  "paper_2208_07412_amd/csrc/k_links.hpp", "paper_2208_07412_amd/csrc/k_track.hpp"),
+}
 
 
 def make_reco(tpc, ev, stream, max_clusters, max_tracklets, noise):
@@ -363,33 +377,37 @@ def main():
     log(f"[bench] batched ({best} slice(s)): {ms_step:.3f} ms/step ({wall_ms:.3f} wall), "
         f"{value:.4g} clusters/s")
 
-    # roofline of the dominant kernel (the following: FP32 ALU) and of the
-    # dominant HBM-bound stage (the clusterizer's peak pass)
+    # rooflines: the clusterizer's peak pass (one kernel, the longest single
+    # launch; HBM bytes) and the following stage (its two pass launches and
+    # their sorts; FP32 operations).  `roofline` is the one whose launch time
+    # is the larger, i.e. the dominant kernel.
     n_ur = ev.n_units * 152
-    sb = stage_bytes(ns, nc, n_ur, ev.n_time_bins,
-                     tuning["chosen"]["cl_window"] if tuning else 16)
-    dom = max(stages, key=lambda k: stages[k])
-    hbm_dom = max(sb, key=lambda k: stages.get(k, 0.0))
-    ach = sb[hbm_dom] / (stages[hbm_dom] / 1e3) / 1e9
     tn = tuning["chosen"] if tuning else {"cl_window": 16, "cl_chunk": 8}
-    kname = (f"void k_cluster_peaks<{tn['cl_window']}, {tn['cl_chunk']},"
-             if hbm_dom == "cluster_peaks" else f"void k_{hbm_dom}<{tn['cl_window']}>")
-    traffic = pmc_traffic("paper_2208_07412_amd/csrc/k_cluster.hpp", hbm_dom, kname) \
-        if hbm_dom.startswith("cluster_") else None
-    roofline_hbm = dict(bound="hbm", kernel=hbm_dom, achieved=ach, peak=HBM_PEAK_GBS,
-                        unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=traffic,
-                        bytes_per_launch=sb[hbm_dom], ms_per_launch=stages[hbm_dom])
+    sb = stage_bytes(ns, nc, n_ur, ev.n_time_bins, tn["cl_window"])
+    dom = max(stages, key=lambda k: stages[k])
+    ach = sb["cluster_peaks"] / (stages["cluster_peaks"] / 1e3) / 1e9
+    kname = f"void k_cluster_peaks<{tn['cl_window']}, {tn['cl_chunk']},"
+    roof_peaks = dict(bound="hbm", kernel="k_cluster_peaks", achieved=ach, peak=HBM_PEAK_GBS,
+                      unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                      traffic=pmc_traffic(KERNEL_SOURCES["cluster_peaks"], "cluster_peaks", kname),
+                      bytes_per_launch=sb["cluster_peaks"], ms_per_launch=stages["cluster_peaks"])
     flops = (FLOPS_STEP * fcounts["follow_steps"] + FLOPS_CAND * fcounts["follow_candidates"] +
              FLOPS_UPDATE * fcounts["follow_updates"])
     ach_f = flops / (stages["following"] / 1e3) / 1e12
-    roofline = dict(bound="alu", kernel="following", achieved=ach_f, peak=FP32_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=ach_f / FP32_PEAK_TFLOPS,
-                    traffic=pmc_traffic("paper_2208_07412_amd/csrc/k_track.hpp", "following",
-                                        "void k_follow<"),
-                    flops_per_launch=flops, ms_per_launch=stages["following"],
-                    steps=fcounts["follow_steps"], candidates=fcounts["follow_candidates"],
-                    updates=fcounts["follow_updates"], dominant_stage=dom,
-                    dominant_stage_ms=stages[dom])
+    roof_follow = dict(bound="alu", kernel="following (k_follow pass A + pass B, with their sorts)",
+                       achieved=ach_f, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                       frac=ach_f / FP32_PEAK_TFLOPS,
+                       traffic=pmc_traffic(KERNEL_SOURCES["following"], "following",
+                                           "void k_follow<"),
+                       flops_per_launch=flops, ms_per_launch=stages["following"],
+                       steps=fcounts["follow_steps"], candidates=fcounts["follow_candidates"],
+                       updates=fcounts["follow_updates"])
+    if stages["cluster_peaks"] >= stages["following"]:
+        roofline, roofline_2 = roof_peaks, roof_follow
+    else:
+        roofline, roofline_2 = roof_follow, roof_peaks
+    roofline["dominant_stage"] = dom
+    roofline["dominant_stage_ms"] = stages[dom]
 
     out = dict(metric=METRIC, value=value, unit="clusters/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
@@ -400,7 +418,7 @@ def main():
                                  "graph replay per step") if graph is not None else "eager",
                            slices=best, slice_ms=form_ms,
                            samples=ns, clusters=nc, tracks=counts["n_tracks"]),
-               roofline=roofline, roofline_hbm=roofline_hbm, stages_ms=stages)
+               roofline=roofline, roofline_2=roofline_2, stages_ms=stages)
     if tuning is not None:
         out["tuning"] = tuning["chosen"]
     del graph, forms

@@ -837,7 +837,7 @@ int tpc_tuning_default(tpc_tuning* t) {
   if (!t) return TPC_ERR_ARG;
   t->cl_window = 16;
   t->cl_chunk = 8;
-  t->follow_block = 64;
+  t->follow_block = 128;
   t->follow_mode = 0;
   return TPC_OK;
 }
