@@ -276,18 +276,17 @@ __device__ __forceinline__ Row3 row3(const uint16_t* tile, int c) {
 __device__ __forceinline__ int up_code_of(const uint16_t* tile, int c, int qmin) {
   const Row3 u = row3(tile, c - CL_TP), m = row3(tile, c), d = row3(tile, c + CL_TP);
   const int a = m.m;
-  // neighbours in (dt, dp) order with their codes; ties go to the later one
-  const int an[8] = {u.l, u.m, u.r, m.l, m.r, d.l, d.m, d.r};
-  const int cd[8] = {0, 1, 2, 4, 6, 8, 9, 10};
-  int best = a * 16 + 5, code = 5;
-#pragma unroll
-  for (int n = 0; n < 8; ++n) {
-    const int k = an[n] * 16 + cd[n];
-    if (an[n] != 0 && k > best) {
-      best = k;
-      code = cd[n];
-    }
-  }
+  // key = adc * 16 + code: the codes order the nine cells by (time, pad), so
+  // the largest key is the argmax of (adc, time, pad) and its low bits are the
+  // up code.  An empty cell (adc 0) has a key below 16 and never beats a
+  // present cell; if nothing present is left (an ADC-0 sample alone), the
+  // sample keeps its own code.
+  int best = (a << 4) | 5;
+  best = max(best, max(u.l << 4, (u.m << 4) | 1));
+  best = max(best, max((u.r << 4) | 2, (m.l << 4) | 4));
+  best = max(best, max((m.r << 4) | 6, (d.l << 4) | 8));
+  best = max(best, max((d.m << 4) | 9, (d.r << 4) | 10));
+  const int code = best >= 16 ? (best & 15) : 5;
   return code | ((code == 5 && a >= qmin) ? 16 : 0);
 }
 
