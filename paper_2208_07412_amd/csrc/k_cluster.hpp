@@ -428,9 +428,8 @@ __global__ __launch_bounds__(64) void k_cluster_peaks(ZsArgs in, const uint32_t*
         const uint32_t a = tx & 0x3FF;
         const uint32_t dt2 = 4 - (cx >> 2) - (cy >> 2);  // dt + 2, dt = sample - peak
         const uint32_t dp2 = 4 - (cx & 3) - (cy & 3);
-        // (dt)^2 = (dt2 - 2)^2 is 4, 1, 0, 1, 4 for dt2 = 0..4
-        const uint32_t dtt = (dt2 == 2) ? 0u : ((dt2 & 1) ? 1u : 4u);
-        const uint32_t dpp = (dp2 == 2) ? 0u : ((dp2 & 1) ? 1u : 4u);
+        const int dt = (int)dt2 - 2, dp = (int)dp2 - 2;
+        const uint32_t dtt = (uint32_t)__mul24(dt, dt), dpp = (uint32_t)__mul24(dp, dp);
         const uint32_t ap = __umul24(a, dp2), at = __umul24(a, dt2);
         // the packed fields assembled as two 32-bit halves
         const uint32_t lo0 = a | (1u << 15) | ((uint32_t)(a >= 1023) << 20) | (ap << 25);
