@@ -433,7 +433,11 @@ __global__ __launch_bounds__(64) void k_cluster_peaks(ZsArgs in, const uint32_t*
         const uint32_t ap = __umul24(a, dp2), at = __umul24(a, dt2);
         // the packed fields assembled as two 32-bit halves
         const uint32_t lo0 = a | (1u << 15) | ((uint32_t)(a >= 1023) << 20) | (ap << 25);
-        const uint32_t hi0 = (ap >> 7) | (__umul24(a, dpp) << 10);
+        // a * dp^2 as one 24-bit multiply (left to itself the compiler
+        // reassociates it with the shift into a quarter-rate 32-bit multiply)
+        uint32_t adpp;
+        asm("v_mul_u32_u24 %0, %1, %2" : "=v"(adpp) : "v"(a), "v"(dpp));
+        const uint32_t hi0 = (ap >> 7) | (adpp << 10);
         const uint64_t v0 = ((uint64_t)hi0 << 32) | lo0;
         const uint64_t v1 = ((uint64_t)__umul24(a, dtt) << 32) | at;
         atomicAdd(&acc0[slot], (unsigned long long)v0);
