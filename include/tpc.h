@@ -253,7 +253,11 @@ const char* tpc_status_string(int status);
  * pass (outward, then inward), each over the tracklets sorted by the most
  * rows the pass can take, longest first; 1 one launch that runs both passes
  * of a tracklet per lane, in tracklet order.  One tracklet per lane in both
- * modes.  tpc_set_tuning rejects other values with TPC_ERR_ARG and leaves
+ * modes.  refit_waves: most waves of the FP32 refit resident per compute
+ * unit, 0 (no limit), 4, 5, 6 or 8; the refit lasts as long as its longest
+ * tracks' serial chains, which run faster with fewer waves sharing a SIMD
+ * (the limit is a reservation of LDS per workgroup).  tpc_set_tuning rejects
+ * other values with TPC_ERR_ARG and leaves
  * the context unchanged; it takes effect at the next call (a captured graph
  * keeps the shapes it was captured with). */
 typedef struct {
@@ -261,6 +265,7 @@ typedef struct {
   int32_t cl_chunk;
   int32_t follow_block;
   int32_t follow_mode;
+  int32_t refit_waves;
 } tpc_tuning;
 int tpc_tuning_default(tpc_tuning* t);
 int tpc_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

@@ -1,7 +1,8 @@
 """Launch-shape autotuner.
 
 Every launch shape the library offers (clusterizer window and windows per
-workgroup; workgroup size of the following kernel) gives identical results, so
+workgroup; workgroup size and mode of the following; resident waves of the
+FP32 refit) gives identical results, so
 the choice is made by timing alone: each candidate runs the full launch
 sequence on the caller's resident workload, the library's stage timers (HIP
 events on its stream) give the time of the stages the shape affects, and the
@@ -16,6 +17,8 @@ CLUSTER_SHAPES: List[Tuple[int, int]] = [(8, 4), (8, 8), (8, 16), (16, 4), (16, 
 FOLLOW_SHAPES: List[Tuple[int, int]] = [(fb, fm) for fm in (0, 1) for fb in (64, 128, 256)]
 CLUSTER_STAGES = ("sample_index", "cluster_peaks", "cluster_scan", "cluster_output")
 FOLLOW_STAGES = ("following",)
+REFIT_WAVES: List[int] = [0, 4, 5, 6, 8]
+REFIT_STAGES = ("refit_fp32",)
 
 
 def _stage_ms(prof: Dict[str, tuple], names, runs: int) -> float:
@@ -60,6 +63,12 @@ def autotune(reco, run, reps: int = 3, margin: float = 0.02) -> dict:
     best_f = _pick(res["follow"], f"{start['follow_block']}x{start['follow_mode']}", margin)
     fb, fm = (int(x) for x in best_f.split("x"))
     reco.set_tuning(follow_block=fb, follow_mode=fm)
+    res["refit"] = {}
+    for rw in REFIT_WAVES:
+        reco.set_tuning(refit_waves=rw)
+        res["refit"][str(rw)] = _time(reco, run, REFIT_STAGES, reps)
+    best_r = _pick(res["refit"], str(start["refit_waves"]), margin)
+    reco.set_tuning(refit_waves=int(best_r))
     res["chosen"] = reco.tuning()
     res["start"] = start
     return res

@@ -544,7 +544,11 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
     sort_by_key();  // tracks by kept hits: lanes of a wave refit equally long tracks
     k_refit_head<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept,
                                     c->f_perm, hd, c->d_par, c->d_st);
-    k_refit32<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept,
+    // at most refit_waves one-wave workgroups per CU (160 KB of LDS shared):
+    // the rest of each workgroup's share is reserved, not used
+    const int rw = c->tune.refit_waves;
+    const size_t lds_pad = rw ? (size_t)(160 << 10) / rw - sizeof(DevParams) - 256 : 0;
+    k_refit32<<<g64, 64, lds_pad, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept,
                                  c->f_perm, hd, ro, c->fb_list, c->d_par, c->d_st);
   }
   {
@@ -839,6 +843,7 @@ int tpc_tuning_default(tpc_tuning* t) {
   t->cl_chunk = 8;
   t->follow_block = 128;
   t->follow_mode = 0;
+  t->refit_waves = 6;
   return TPC_OK;
 }
 
@@ -848,6 +853,9 @@ int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if (t->cl_chunk != 4 && t->cl_chunk != 8 && t->cl_chunk != 16) return TPC_ERR_ARG;
   if (t->follow_block != 64 && t->follow_block != 128 && t->follow_block != 256) return TPC_ERR_ARG;
   if (t->follow_mode != 0 && t->follow_mode != 1) return TPC_ERR_ARG;
+  if (t->refit_waves != 0 && t->refit_waves != 4 && t->refit_waves != 5 && t->refit_waves != 6 &&
+      t->refit_waves != 8)
+    return TPC_ERR_ARG;
   c->tune = *t;
   return TPC_OK;
 }

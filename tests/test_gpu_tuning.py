@@ -13,14 +13,15 @@ import pytest
 
 import oracle
 import tpcsynth
+from paper_2208_07412_amd import tpc
 
 from _parity import compare_clusters, compare_fit, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
 NPADS, _, _ = oracle.geometry()
-SHAPES = [(8, 8, 64, 0), (8, 16, 128, 1), (16, 4, 64, 0), (16, 8, 128, 1), (16, 16, 256, 0),
-          (32, 4, 256, 1), (32, 8, 64, 1), (32, 16, 128, 0)]
+SHAPES = [(8, 8, 64, 0, 0), (8, 16, 128, 1, 4), (16, 4, 64, 0, 5), (16, 8, 128, 1, 6),
+          (16, 16, 256, 0, 8), (32, 4, 256, 1, 0), (32, 8, 64, 1, 5), (32, 16, 128, 0, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -31,11 +32,11 @@ def frame():
     return ev, run_oracle(ev, labels=True)
 
 
-@pytest.mark.parametrize("w,k,fb,fm", SHAPES)
-def test_shape_parity(frame, w, k, fb, fm):
+@pytest.mark.parametrize("w,k,fb,fm,rw", SHAPES)
+def test_shape_parity(frame, w, k, fb, fm, rw):
     ev, o = frame
     g = run_gpu(ev, labels=True, tuning=dict(cl_window=w, cl_chunk=k, follow_block=fb,
-                                              follow_mode=fm))
+                                              follow_mode=fm, refit_waves=rw))
     compare_clusters(g["clusters"], o["clusters"], labels=True)
     assert np.array_equal(g["links"]["down"], o["down"])
     assert np.array_equal(g["links"]["up"], o["up"])
@@ -100,4 +101,17 @@ def test_work_counting_variant_same_results(frame):
     assert g2["counts"]["follow_steps"] == 0
     for k in ("tracklet", "par", "cov", "hits", "cluster_track"):
         assert np.array_equal(g1["tracks"][k], g2["tracks"][k])
+    reco.close()
+
+
+def test_set_tuning_rejects_unknown_shapes():
+    reco = tpc.Reco(1, 100, 1024, 64)
+    before = reco.tuning()
+    for bad in (dict(cl_window=12), dict(cl_chunk=3), dict(follow_block=96), dict(follow_mode=2),
+                dict(refit_waves=3)):
+        with pytest.raises(tpc.TpcError):
+            reco.set_tuning(**bad)
+        assert reco.tuning() == before
+    reco.set_tuning(refit_waves=0)
+    assert reco.tuning()["refit_waves"] == 0
     reco.close()
