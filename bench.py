@@ -356,17 +356,20 @@ def main():
         for n in args.slices:
             if n <= 1:
                 continue
-            pl = Pipeline(zs, n, tuning=tuning["chosen"] if tuning else None)
-            gn = capture(pl.enqueue)
-            forms[n] = (gn, gn.replay, pl)
+            for st in ("cluster", "none"):
+                pl = Pipeline(zs, n, tuning=tuning["chosen"] if tuning else None, stagger=st)
+                gn = capture(pl.enqueue)
+                forms[f"{n}/{st}"] = (gn, gn.replay, pl)
     form_ms = {n: time_steps(f[1], 5)[0] for n, f in forms.items()}
     best = min(form_ms, key=form_ms.get)
-    log("[bench] batched forms (slices: ms/step): " +
+    log("[bench] batched forms (slices/start: ms/step): " +
         ", ".join(f"{n}: {v:.3f}" for n, v in form_ms.items()))
     for n, f in forms.items():
         if n != best and f[2] is not None:
             f[2].close()
     graph, run_best, pl_best = forms[best]
+    n_slices = pl_best.n_parts if pl_best is not None else 1
+    start_pt = pl_best.stagger if pl_best is not None else None
 
     # timed region: the chosen batched form, one graph replay per step
     ms_step, wall_ms = time_steps(run_best, args.steps)
@@ -374,7 +377,8 @@ def main():
     assert c2["n_clusters"] == nc, "graph replay changed the result"
     assert c2["n_tracks"] == counts["n_tracks"], "graph replay changed the result"
     value = nc / (ms_step / 1e3)
-    log(f"[bench] batched ({best} slice(s)): {ms_step:.3f} ms/step ({wall_ms:.3f} wall), "
+    log(f"[bench] batched ({n_slices} slice(s), start {start_pt}): {ms_step:.3f} ms/step "
+        f"({wall_ms:.3f} wall), "
         f"{value:.4g} clusters/s")
 
     # rooflines: the clusterizer's peak pass (one kernel, the longest single
@@ -414,9 +418,10 @@ def main():
                vs_baseline=None, dtype="f32+int", data="synthetic",
                config=dict(workload="2 ms Pb-Pb slice at 50 kHz: 100 minimum-bias collisions, "
                            "36 sectors x 152 rows, 10500 time bins, seed 303",
-                           form=(f"batched: {best} unit slice(s) on {best} stream(s), one "
-                                 "graph replay per step") if graph is not None else "eager",
-                           slices=best, slice_ms=form_ms,
+                           form=(f"batched: {n_slices} unit slice(s) on {n_slices} stream(s) "
+                                 f"(slice start: {start_pt}), one graph replay per step")
+                           if graph is not None else "eager",
+                           slices=n_slices, slice_start=start_pt, slice_ms=form_ms,
                            samples=ns, clusters=nc, tracks=counts["n_tracks"]),
                roofline=roofline, roofline_2=roofline_2, stages_ms=stages)
     if tuning is not None:

@@ -2,12 +2,13 @@
 
 A unit (one sector of one frame) is reconstructed independently of every
 other unit, so a frame can be cut into slices of consecutive units and each
-slice reconstructed by its own library context on its own HIP stream.  Slice
-i starts when slice i-1 has finished clustering, so the slices run about one
-stage apart: the stages whose end is bound by latency (the longest tracks of
-the refit and of the FP64 refit, the longest chains of the tracklet building,
-the longest tracklets of the following) overlap with throughput-bound stages
-of the next slice.  Each slice writes its own outputs, equal to those of one
+slice reconstructed by its own library context on its own HIP stream.  By
+default slice i starts when slice i-1 has finished clustering (other start
+points are a choice), so the slices run about one stage apart: the stages
+whose end is bound by latency (the longest tracks of the refit and of the
+FP64 refit, the longest chains of the tracklet building, the longest
+tracklets of the following) overlap with throughput-bound stages of the next
+slice.  Each slice writes its own outputs, equal to those of one
 call over its units.  The launch sequence of all slices can be captured into
 one HIP graph (the slice streams fork from and join the capturing stream).
 """
@@ -67,21 +68,24 @@ class Slice:
         self.links = r.alloc_links(self.max_clusters)
         self.tl = r.alloc_tracklets(self.max_tracklets)
         self.tr = r.alloc_tracks(self.max_tracklets, self.max_clusters, self.max_clusters)
-        self.clustered = torch.cuda.Event()
+        self.mark = torch.cuda.Event()  # where the next slice may start
         self.done = torch.cuda.Event()
 
-    def enqueue(self, start, after):
+    def enqueue(self, start, after, stagger: str):
         """Enqueue the slice on its stream behind the events start and after
-        (the previous slice's end of clustering, or None)."""
+        (the previous slice's stagger point, or None)."""
         torch = tpc._torch()
         self.stream.wait_event(start)
         if after is not None:
             self.stream.wait_event(after)
         with torch.cuda.stream(self.stream):
             self.reco.cluster(self.zs, self.cl)
-            self.clustered.record(self.stream)
+            if stagger == "cluster":
+                self.mark.record(self.stream)
             self.reco.find_neighbours(self.cl, self.links)
             self.reco.build_tracklets(self.cl, self.links, self.tl)
+            if stagger == "tracklets":
+                self.mark.record(self.stream)
             self.reco.fit_tracks(self.cl, self.links, self.tl, self.tr)
             self.done.record(self.stream)
 
@@ -91,10 +95,18 @@ class Pipeline:
     previous one.  enqueue() forks the slices from the current stream and
     joins them back into it."""
 
+    STAGGERS = ("cluster", "tracklets", "none")
+
     def __init__(self, zs: dict, n_parts: int, device="cuda", cl_ratio: int = 8,
                  tl_ratio: int = 8, noise_sigma: float = 1.0,
-                 param_overrides: Optional[dict] = None, tuning: Optional[dict] = None):
+                 param_overrides: Optional[dict] = None, tuning: Optional[dict] = None,
+                 stagger: str = "cluster"):
+        """stagger: the point of slice i-1 after which slice i starts (the end
+        of its clustering, of its tracklet building, or no wait)."""
         torch = tpc._torch()
+        if stagger not in self.STAGGERS:
+            raise ValueError(f"stagger must be one of {self.STAGGERS}")
+        self.stagger = stagger
         self.device = torch.device(device)
         rs = zs["row_start"].cpu().numpy().view(np.uint32)
         self.bounds = split_units(rs, zs["n_units"], n_parts)
@@ -113,7 +125,8 @@ class Pipeline:
         self.start.record(main)
         prev = None
         for sl in self.slices:
-            sl.enqueue(self.start, prev.clustered if prev is not None else None)
+            after = prev.mark if prev is not None and self.stagger != "none" else None
+            sl.enqueue(self.start, after, self.stagger)
             prev = sl
         for sl in self.slices:
             main.wait_event(sl.done)

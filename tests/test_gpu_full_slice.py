@@ -1,7 +1,8 @@
 """Parity at the full size of the headline workload (the 2 ms slice: 100
-collisions, 36 sectors x 152 rows, 10,500 bins, seed 303), in the launch
+collisions, 36 sectors x 152 rows, 10,500 bins, seed 303), in a launch
 configuration the benchmark times (default launch shapes, the units in four
-slices on concurrent streams, one graph replay).  The oracle is run on sampled
+slices on concurrent streams, one graph replay; the other slicings give the
+same outputs, which the pipeline tests check).  The oracle is run on sampled
 units one by one (a unit is reconstructed independently of the others), and
 properties that hold at any size are checked over the whole slice."""
 import numpy as np

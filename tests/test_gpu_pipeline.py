@@ -71,11 +71,12 @@ def _check(p, full):
     assert c_off == len(fc["y_fx"]) and k_off == len(ftr["tracklet"])
 
 
-@pytest.mark.parametrize("parts", [1, 3])
-def test_slices_equal_one_call(frame, parts):
+@pytest.mark.parametrize("parts,stagger", [(1, "cluster"), (3, "cluster"), (4, "none"),
+                                           (2, "tracklets")])
+def test_slices_equal_one_call(frame, parts, stagger):
     ev, full = frame
     zs = tpc.to_device_zs(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins)
-    p = pipeline.Pipeline(zs, parts)
+    p = pipeline.Pipeline(zs, parts, stagger=stagger)
     assert p.n_parts == parts and p.bounds[0] == 0 and p.bounds[-1] == ev.n_units
     p.enqueue()
     torch.cuda.synchronize()
