@@ -109,6 +109,16 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
   return v;
 }
 
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+  return v;
+}
 __device__ __forceinline__ unsigned long long wave_sum_u64(uint32_t v) {
   unsigned long long x = v;
 #pragma unroll

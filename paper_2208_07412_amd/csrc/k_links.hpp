@@ -66,15 +66,15 @@ __device__ __forceinline__ bool nb_in(int32_t a, int32_t b, int32_t w) {
   const int32_t d = a - b;
   return d <= w && d >= -w;
 }
-__device__ __forceinline__ void nb_best(const int2* __restrict__ pos, int32_t yi, int32_t zi,
-                                        int32_t wy, int32_t wz, uint64_t smax, uint32_t ja,
-                                        uint32_t jb, uint32_t ka, uint32_t kb, int32_t& bd,
-                                        int32_t& bu) {
+template <class PJ, class PK>
+__device__ __forceinline__ void nb_best(PJ J, PK K, int32_t yi, int32_t zi, int32_t wy,
+                                        int32_t wz, uint64_t smax, uint32_t ja, uint32_t jb,
+                                        uint32_t ka, uint32_t kb, int32_t& bd, int32_t& bu) {
   uint32_t kl[NB_KLIST];
   int nk = 0;
   bool over = false;
   for (uint32_t k = ka; k < kb; ++k) {
-    const int2 pk = pos[k];
+    const int2 pk = K(k);
     if (!nb_in(pk.x, yi, wy) || !nb_in(pk.y, zi, wz)) continue;
     if (nk < NB_KLIST) {
 #pragma unroll
@@ -88,7 +88,7 @@ __device__ __forceinline__ void nb_best(const int2* __restrict__ pos, int32_t yi
   if (nk == 0) return;
   uint64_t best = ~0ull;
   for (uint32_t j = ja; j < jb; ++j) {
-    const int2 pj = pos[j];
+    const int2 pj = J(j);
     if (!nb_in(pj.x, yi, wy) || !nb_in(pj.y, zi, wz)) continue;
     // 2 y_i - y_j - y_k = (y_i - y_j) + (y_i - y_k), each term inside its window
     const int32_t ay = yi - pj.x, az = zi - pj.y;
@@ -106,11 +106,11 @@ __device__ __forceinline__ void nb_best(const int2* __restrict__ pos, int32_t yi
 #pragma unroll
       for (int m = 0; m < NB_KLIST; ++m) {
         if (m >= nk) break;
-        consider(kl[m], pos[kl[m]]);
+        consider(kl[m], K(kl[m]));
       }
     } else {
       for (uint32_t k = ka; k < kb; ++k) {
-        const int2 pk = pos[k];
+        const int2 pk = K(k);
         if (!nb_in(pk.x, yi, wy) || !nb_in(pk.y, zi, wz)) continue;
         consider(k, pk);
       }
@@ -119,23 +119,29 @@ __device__ __forceinline__ void nb_best(const int2* __restrict__ pos, int32_t yi
 }
 
 // One lane per cluster, one workgroup per (unit,row), the row's clusters in
-// batches of 256.  The candidates are read from the packed positions through
-// the caches (a row's positions are a few tens of KB): waves need no barrier,
-// so they run independently and hide each other's latency.  (Staging each
-// batch's candidate ranges in LDS read every candidate from HBM once, but the
-// barriers around it serialised each workgroup's batches: 1.40 ms against
-// 1.13 ms for the slice.)
+// batches of 64 per wave.  Each wave copies the union of its lanes'
+// candidate ranges in rows r-1 and r+1 (contiguous: rows are time-sorted)
+// into its own LDS slice when it fits and scores from there; no workgroup
+// barrier is involved (a wave reads back its own LDS writes in order), so
+// waves run independently and hide each other's latency.  (Staging per
+// workgroup batch of 256 behind barriers serialised each workgroup's batches:
+// 1.40 ms for the slice; reading every candidate through the caches: 1.13 ms.)
+#define NB_WSTAGE 256
 __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32_t* __restrict__ cblk,
                                                     uint32_t nblk, uint32_t n_ur,
                                                     int32_t* __restrict__ down,
                                                     int32_t* __restrict__ up,
                                                     const DevParams* __restrict__ P,
                                                     const DevStatus* st) {
+  __shared__ int2 sp[4][2][NB_WSTAGE];
   if (failed(st)) return;
   const int64_t wz64 = P->win_z;
   const int32_t wy = (int32_t)min(P->win_y, (int64_t)1 << 30);
   const int32_t wz = (int32_t)min(wz64, (int64_t)1 << 30);
   const uint64_t smax = (uint64_t)P->s_max;
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int2* sj = sp[w][0];
+  int2* sk = sp[w][1];
   for (uint32_t b = blockIdx.x; b < n_ur; b += gridDim.x) {
     // consecutive rows of a sector share an XCD (and its L2) when the grid
     // covers every row
@@ -149,15 +155,47 @@ __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32
       }
       continue;
     }
-    for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-      const int2 pi = cl.pos[i];
-      uint32_t ja, jb, ka, kb;
-      nb_candidates(cl, cblk, nblk, ur - 1, pi.y, wz64, ja, jb);
-      nb_candidates(cl, cblk, nblk, ur + 1, pi.y, wz64, ka, kb);
+    for (uint32_t base = c0 + w * 64; base < c1; base += blockDim.x) {  // uniform per wave
+      const uint32_t i = base + lane;
+      const bool valid = i < c1;
+      int32_t yi = 0, zi = 0;
+      uint32_t ja = 0, jb = 0, ka = 0, kb = 0;
+      if (valid) {
+        const int2 pi = cl.pos[i];
+        yi = pi.x;
+        zi = pi.y;
+        nb_candidates(cl, cblk, nblk, ur - 1, zi, wz64, ja, jb);
+        nb_candidates(cl, cblk, nblk, ur + 1, zi, wz64, ka, kb);
+      }
+      const bool act = valid && jb > ja && kb > ka;
+      // the wave's union ranges (inactive lanes contribute nothing)
+      const uint32_t JA = (uint32_t)wave_min_i32(act ? (int32_t)ja : INT32_MAX);
+      const uint32_t JB = (uint32_t)wave_max_i32(act ? (int32_t)jb : 0);
+      const uint32_t KA = (uint32_t)wave_min_i32(act ? (int32_t)ka : INT32_MAX);
+      const uint32_t KB = (uint32_t)wave_max_i32(act ? (int32_t)kb : 0);
+      const bool stage = JB > JA && KB > KA && JB - JA <= NB_WSTAGE && KB - KA <= NB_WSTAGE;
+      if (stage) {
+        for (uint32_t t = lane; t < JB - JA; t += 64) sj[t] = cl.pos[JA + t];
+        for (uint32_t t = lane; t < KB - KA; t += 64) sk[t] = cl.pos[KA + t];
+      }
+      // the wave's LDS writes before its reads (in order within a wave)
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
       int32_t bd = -1, bu = -1;
-      if (jb > ja && kb > ka) nb_best(cl.pos, pi.x, pi.y, wy, wz, smax, ja, jb, ka, kb, bd, bu);
-      down[i] = bd;
-      up[i] = bu;
+      if (act) {
+        if (stage) {
+          auto J = [&](uint32_t c) { return sj[c - JA]; };
+          auto K = [&](uint32_t c) { return sk[c - KA]; };
+          nb_best(J, K, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);
+        } else {
+          auto G = [&](uint32_t c) { return cl.pos[c]; };
+          nb_best(G, G, yi, zi, wy, wz, smax, ja, jb, ka, kb, bd, bu);
+        }
+      }
+      if (valid) {
+        down[i] = bd;
+        up[i] = bu;
+      }
     }
   }
 }
