@@ -668,14 +668,12 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
     }
   }
   f.r = rn;
-  if (pa) {
-    f.hi = rn;
-    H[rn] = -1;
-  } else if (fresh && rn < f.lo) {
-    f.lo = rn;
-    H[rn] = -1;
-  }
+  // a row this pass visits first gets exactly one store: its hit, or -1
+  const bool first = pa || (fresh && rn < f.lo);
+  if (pa) f.hi = rn;
+  else if (first) f.lo = rn;
   if (cand < 0) {
+    if (first) H[rn] = -1;
     if ((pa || rn < f.r1) && ++f.nmiss >= P->max_miss) return true;
     return false;
   }
@@ -683,7 +681,10 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
   const float my = (float)q.x * (float)FX_SCALE;
   const float mz = (float)(q.y - f.anchor) * (float)FX_SCALE;
   ++f.n_upds;
-  if (!update(k, my, mz, pv.vy(rn), pv.vz(rn), (float*)nullptr)) return true;
+  if (!update(k, my, mz, pv.vy(rn), pv.vz(rn), (float*)nullptr)) {
+    if (first) H[rn] = -1;
+    return true;
+  }
   if (pa || fresh) {
     H[rn] = cand;
     ++f.nh;
