@@ -272,10 +272,11 @@ __device__ __forceinline__ Row3 row3(const uint16_t* tile, int c) {
 }
 
 // up code (bits 0-3) and peak flag (bit 4) of the sample in cell c: the
-// argmax of the key (adc, time, pad) over the cell and its present neighbours
-__device__ __forceinline__ int up_code_of(const uint16_t* tile, int c, int qmin) {
+// argmax of the key (adc, time, pad) over the cell and its present neighbours;
+// a = the cell's ADC
+__device__ __forceinline__ int up_code_of(const uint16_t* tile, int c, int qmin, int& a) {
   const Row3 u = row3(tile, c - CL_TP), m = row3(tile, c), d = row3(tile, c + CL_TP);
-  const int a = m.m;
+  a = m.m;
   // key = adc * 16 + code: the codes order the nine cells by (time, pad), so
   // the largest key is the argmax of (adc, time, pad) and its low bits are the
   // up code.  An empty cell (adc 0) has a key below 16 and never beats a
@@ -380,23 +381,18 @@ __global__ __launch_bounds__(64) void k_cluster_peaks(ZsArgs in, const uint32_t*
         lt = (int)(tp >> 16) - tile_t0;
       }
       const bool live = c >= 0 && lt >= CL_HALO - 3 && lt < CL_HALO + W + 3;
-      const int code = live ? up_code_of(tile, c, qmin) : 0;
+      int a = 0;
+      const int code = live ? up_code_of(tile, c, qmin, a) : 0;
       const bool pk = live && (code & 16) && lt >= CL_HALO && lt < CL_HALO + W;
       const uint64_t m = __ballot(pk);
       const uint32_t k = total + (uint32_t)__popcll(m & ((1ull << threadIdx.x) - 1ull));
-      if (live) {
-        const int a = tile[c] & 0x3FF;
-        int v;
-        if (!(code & 16)) {
-          v = a | (code << 10);
-        } else if (pk && k < CL_SLOTS) {
-          v = a | CL_PEAK | slot_bits(k);
-          pk_cell[k] = (uint16_t)c;
-        } else {
-          v = a | CL_PEAK | CL_NOSLOT;
-        }
-        tile[c] = (uint16_t)v;
-      }
+      const bool pslot = pk && k < CL_SLOTS;
+      // non-peak: its up code; peak: the flag and its slot (or none); the
+      // cell's own lane is its only writer, so its ADC bits are a
+      const int v = (code & 16) ? (a | CL_PEAK | (pslot ? slot_bits((int)k) : CL_NOSLOT))
+                                : (a | (code << 10));
+      if (live) tile[c] = (uint16_t)v;
+      if (pslot) pk_cell[k] = (uint16_t)c;
       total += (uint32_t)__popcll(m);
     }
     ClusterRec* wrec = rec + R.c_lo;  // this window's records
