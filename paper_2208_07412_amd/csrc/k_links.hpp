@@ -213,43 +213,62 @@ __global__ void k_ca_clean(const int32_t* __restrict__ down, const int32_t* __re
   }
 }
 
-// Length of the chain starting at every start cluster (0 for non-starts and
-// chains shorter than min_tracklet).  Chains cross one row per link, so a
-// walk longer than 152 means corrupt links and is cut.
-__global__ void k_chain_len(const int32_t* __restrict__ downc, const int32_t* __restrict__ upc,
-                            uint16_t* __restrict__ len, const uint32_t* n_dev, uint32_t n_cap,
-                            const DevParams* __restrict__ P, const DevStatus* st) {
+// Start clusters of chains (no cleaned down-link, a cleaned up-link), listed
+// in ascending order by a scan so that the chain walks below run one lane
+// per start on dense waves.
+struct GetStart {
+  const int32_t* downc;
+  const int32_t* upc;
+  __device__ uint32_t operator()(uint32_t i) const {
+    return (downc[i] == -1 && upc[i] != -1) ? 1u : 0u;
+  }
+};
+struct EmitStart {
+  uint32_t* cand;
+  uint32_t capacity;
+  __device__ void operator()(uint32_t i, uint32_t pos, uint32_t v) const {
+    if (v && pos < capacity) cand[pos] = i;
+  }
+};
+
+// Length of the chain of every listed start (0 below min_tracklet).  Chains
+// cross one row per link, so a walk longer than 152 means corrupt links and
+// is cut.
+__global__ void k_chain_len(const uint32_t* __restrict__ cand, const uint32_t* n_cand_dev,
+                            uint32_t cand_cap, const int32_t* __restrict__ upc,
+                            const uint32_t* n_cl_dev, uint32_t n_cl_cap,
+                            uint16_t* __restrict__ len, const DevParams* __restrict__ P,
+                            const DevStatus* st) {
   if (failed(st)) return;
-  const uint32_t n = scan_count(n_dev, n_cap);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    uint32_t L = 0;
-    if (downc[i] == -1 && upc[i] != -1) {
-      L = 1;
-      int32_t c = upc[i];
-      while (c >= 0 && (uint32_t)c < n && L < NROW) {
-        ++L;
-        c = upc[c];
-      }
-      if ((int)L < P->min_tracklet) L = 0;
+  const uint32_t n = scan_count(n_cand_dev, cand_cap);
+  const uint32_t n_cl = scan_count(n_cl_dev, n_cl_cap);
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    uint32_t L = 1;
+    int32_t c = upc[cand[p]];
+    while (c >= 0 && (uint32_t)c < n_cl && L < NROW) {
+      ++L;
+      c = upc[c];
     }
-    len[i] = (uint16_t)L;
+    if ((int)L < P->min_tracklet) L = 0;
+    len[p] = (uint16_t)L;
   }
 }
 
 struct GetKeepLen {
   const uint16_t* len;
-  __device__ uint32_t operator()(uint32_t i) const { return len[i] != 0 ? 1u : 0u; }
+  __device__ uint32_t operator()(uint32_t p) const { return len[p] != 0 ? 1u : 0u; }
 };
 
 struct EmitTracklet {
+  const uint32_t* cand;
   const uint16_t* len;
   uint32_t* start;
   uint16_t* out_len;
   uint32_t capacity;
-  __device__ void operator()(uint32_t i, uint32_t pos, uint32_t v) const {
+  __device__ void operator()(uint32_t p, uint32_t pos, uint32_t v) const {
     if (v && pos < capacity) {
-      start[pos] = i;
-      out_len[pos] = len[i];
+      start[pos] = cand[p];
+      out_len[pos] = len[p];
     }
   }
 };

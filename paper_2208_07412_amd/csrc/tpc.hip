@@ -61,7 +61,8 @@ struct tpc_ctx {
   void* bsum = nullptr;       // scan block sums (u64)
   unsigned long long* tot64 = nullptr;
   uint32_t* tot32 = nullptr;
-  uint16_t* chain_len = nullptr;
+  uint16_t* chain_len = nullptr;  // per listed chain start
+  uint32_t* cand = nullptr;       // chain starts, ascending
   int32_t* f_hits = nullptr;
   float* f_state = nullptr;
   uint16_t* f_nhits = nullptr;
@@ -110,7 +111,7 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
+  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
       h_flags, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
@@ -138,8 +139,9 @@ Plan plan_for(const tpc_sizes& m) {
   p.crec = L.add<ClusterRec>(m.max_samples > 0 ? m.max_samples : 1);
   p.bsum = L.add<unsigned long long>(p.bsum_cap);
   p.tot64 = L.add<unsigned long long>(1);
-  p.tot32 = L.add<uint32_t>(1);
-  p.chain_len = L.add<uint16_t>(mc);
+  p.tot32 = L.add<uint32_t>(2);
+  p.chain_len = L.add<uint16_t>(mc / 2 + 1);
+  p.cand = L.add<uint32_t>(mc / 2 + 1);
   p.f_hits = L.add<int32_t>(mt * NROW);
   p.f_state = L.add<float>(mt * 6);
   p.f_nhits = L.add<uint16_t>(mt);
@@ -449,12 +451,17 @@ int stage_tracklets(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l, tpc_trackl
   const uint32_t g = grid_for(cap, 256);
   StageTimer tm(c, 6);
   k_ca_clean<<<g, 256, 0, s>>>(l->down, l->up, l->downc, l->upc, cl->n_clusters, cap, c->d_st);
-  k_chain_len<<<g, 256, 0, s>>>(l->downc, l->upc, c->chain_len, cl->n_clusters, cap, c->d_par,
-                                c->d_st);
-  run_scan<uint32_t>(c, GetKeepLen{c->chain_len},
-                     EmitTracklet{c->chain_len, t->start, t->len, t->capacity}, cl->n_clusters, cap,
+  // chain starts (at most one per two clusters: chains are disjoint and have
+  // at least two), their chain lengths, then the tracklets in start order
+  const uint32_t capc = cap / 2 + 1;
+  run_scan<uint32_t>(c, GetStart{l->downc, l->upc}, EmitStart{c->cand, capc}, cl->n_clusters, cap,
                      (uint32_t*)nullptr, c->tot32);
-  k_tracklet_count<<<1, 1, 0, s>>>(c->tot32, t->capacity, t->n_tracklets, c->d_st);
+  k_chain_len<<<grid_for(capc, 256), 256, 0, s>>>(c->cand, c->tot32, capc, l->upc, cl->n_clusters,
+                                                  cap, c->chain_len, c->d_par, c->d_st);
+  run_scan<uint32_t>(c, GetKeepLen{c->chain_len},
+                     EmitTracklet{c->cand, c->chain_len, t->start, t->len, t->capacity}, c->tot32,
+                     capc, (uint32_t*)nullptr, c->tot32 + 1);
+  k_tracklet_count<<<1, 1, 0, s>>>(c->tot32 + 1, t->capacity, t->n_tracklets, c->d_st);
   return launch_ok();
 }
 
@@ -666,6 +673,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->tot64 = (unsigned long long*)(base + pl.tot64);
   c->tot32 = (uint32_t*)(base + pl.tot32);
   c->chain_len = (uint16_t*)(base + pl.chain_len);
+  c->cand = (uint32_t*)(base + pl.cand);
   c->f_hits = (int32_t*)(base + pl.f_hits);
   c->f_state = (float*)(base + pl.f_state);
   c->f_nhits = (uint16_t*)(base + pl.f_nhits);
