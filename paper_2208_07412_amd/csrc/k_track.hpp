@@ -1196,9 +1196,13 @@ struct GetTrackPair {
 struct EmitTrackPair {
   uint32_t* trk_index;  // [cap] track index or 0xFFFFFFFF
   uint32_t* hit_off;    // [cap]
+  uint32_t* tlist;      // [cap] tracklet of each track
+  uint32_t cap;
   __device__ void operator()(uint32_t t, unsigned long long pre, unsigned long long v) const {
-    trk_index[t] = v ? (uint32_t)(pre >> 32) : 0xFFFFFFFFu;
+    const uint32_t j = (uint32_t)(pre >> 32);
+    trk_index[t] = v ? j : 0xFFFFFFFFu;
     hit_off[t] = (uint32_t)pre;
+    if (v && j < cap) tlist[j] = t;
   }
 };
 
@@ -1227,22 +1231,21 @@ __global__ void k_track_totals(const unsigned long long* total, TrackOut to, uin
   if (nt <= to.capacity) to.hit_start[nt] = nh;
 }
 
+// One wave per track (the tracklets that became tracks, listed in order).
 __global__ __launch_bounds__(256) void k_track_emit(
-    ClusterView cl, const uint32_t* __restrict__ tl_start, FollowOut fo, const uint32_t* n_tl_dev,
-    uint32_t tl_cap, const uint32_t* __restrict__ owner,
-    const uint16_t* __restrict__ nkept, RefitOut ro, const uint32_t* __restrict__ trk_index,
+    ClusterView cl, const uint32_t* __restrict__ tl_start, FollowOut fo,
+    const uint32_t* __restrict__ tlist, const uint16_t* __restrict__ nkept, RefitOut ro,
     const uint32_t* __restrict__ hit_off, TrackOut to, const DevStatus* st) {
   if (failed(st)) return;
-  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  const uint32_t n_trk = min(st->n_tracks, to.capacity);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t t = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
-       t += nw) {
-    const uint32_t j = trk_index[t];
-    if (j == 0xFFFFFFFFu || j >= to.capacity) continue;
+  for (uint32_t j = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); j < n_trk;
+       j += nw) {
+    const uint32_t t = uni(tlist[j]);
     if (lane < 5) to.par[(size_t)j * 5 + lane] = ro.par[(size_t)t * 5 + lane];
     if (lane < 15) to.cov[(size_t)j * 15 + lane] = ro.cov[(size_t)t * 15 + lane];
-    uint32_t o = hit_off[t];
+    const uint32_t o = hit_off[t];
     if (lane == 0) {
       to.tracklet[j] = t;
       to.chi2[j] = ro.chi2[t];

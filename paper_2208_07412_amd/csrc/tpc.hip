@@ -566,13 +566,14 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
                                  c->d_st);
   }
   StageTimer tm(c, 11);
-  run_scan<unsigned long long>(c, GetTrackPair{c->nkept, ro}, EmitTrackPair{c->trk_index, c->hit_off},
+  run_scan<unsigned long long>(c, GetTrackPair{c->nkept, ro}, EmitTrackPair{c->trk_index, c->hit_off, c->f_perm, tcap},
                                t->n_tracklets, tcap, c->tot64, (uint32_t*)nullptr);
   TrackOut to{tr->capacity, tr->hit_capacity, tr->tracklet, tr->par, tr->cov, tr->chi2, tr->ndf,
               tr->row, tr->flags, tr->z_anchor, tr->hit_start, tr->hits, tr->cluster_track};
   k_track_totals<<<1, 1, 0, s>>>(c->tot64, to, tr->n_tracks, tr->n_hits, c->d_st);
-  k_track_emit<<<gw, 256, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept, ro,
-                                    c->trk_index, c->hit_off, to, c->d_st);
+  // tracklets of the tracks listed in f_perm (free after the refit)
+  k_track_emit<<<gw, 256, 0, s>>>(cv, t->start, fo, c->f_perm, c->nkept, ro, c->hit_off, to,
+                                  c->d_st);
   k_cluster_track<<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, c->trk_index, cl->n_clusters, ccap,
                                                       tcap, tr->cluster_track, c->d_st);
   if (tr->follow_hits)
