@@ -89,16 +89,6 @@ __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_read
 // ------------------------------------------------------------ wave64 scans
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Issue priority of the calling wave from a wave-uniform amount of remaining
-// serial work (steps): waves with the longest serial chains set the length of
-// a launch whose total work is small, so they issue first on their SIMD.
-__device__ __forceinline__ void wave_prio(uint32_t steps) {
-  if (steps >= 96) __builtin_amdgcn_s_setprio(3);
-  else if (steps >= 64) __builtin_amdgcn_s_setprio(2);
-  else if (steps >= 32) __builtin_amdgcn_s_setprio(1);
-  else __builtin_amdgcn_s_setprio(0);
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
 #pragma unroll

@@ -1026,88 +1026,51 @@ __device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, con
   return rE;
 }
 
-struct RefitHead {
-  double* state;   // [cap*20]: p[5], packed covariance[15]
-  double* chi2;    // [cap]
-  int16_t* r;      // [cap] next kept hit to use (index into the kept rows)
-  int16_t* rprev;  // [cap] row of the state
-  uint8_t* flags;  // [cap] 1 failed, 2 not PD, 4 low pT
-};
-
-__global__ __launch_bounds__(64) void k_refit_head(ClusterView cl,
-                                                   const uint32_t* __restrict__ tl_start,
-                                                   FollowOut fo, const uint32_t* n_tl_dev,
-                                                   uint32_t tl_cap,
-                                                   const uint32_t* __restrict__ owner,
-                                                   const uint16_t* __restrict__ nkept,
-                                                   const uint32_t* __restrict__ perm,
-                                                   RefitHead hd, const DevParams* __restrict__ Pg,
-                                                   const DevStatus* st) {
+// The refit of each kept track, tracks taken in the order perm gives (sorted
+// by kept hits): the circle seed and the first REFIT_HEAD updates in FP64,
+// where the broad prior's variances collapse by orders of magnitude, then the
+// rest in FP32 (Joseph form, y and sin phi carried with their rounding
+// errors).  Tracks that need more (low pT with a covariance that is not
+// positive definite, or an update that cancels most of a variance) are
+// flagged for the FP64 refit.
+__global__ __launch_bounds__(64) void k_refit(ClusterView cl, const uint32_t* __restrict__ tl_start,
+                                              FollowOut fo, const uint32_t* n_tl_dev,
+                                              uint32_t tl_cap, const uint16_t* __restrict__ nkept,
+                                              const uint32_t* __restrict__ perm, RefitOut ro,
+                                              const DevParams* __restrict__ Pg, DevStatus* st) {
   if (failed(st)) return;
   __shared__ DevParams Ps;
   const DevParams* P = params_to_lds(Pg, &Ps);
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_tl; j += gridDim.x * blockDim.x) {
     const uint32_t t = perm[j];
+    ro.flags[t] = 0;
     const int n = nkept[t];
     if (n == 0) continue;
-    Trk<double> k;
-    double chi2s = 0;
     const int32_t anchor = tl_anchor(cl, tl_start, t);
-    int rs = refit_seed<double>(t, cl, anchor, fo, n, P, k);
+    // FP64 head
+    Trk<double> kd;
+    double chi2d = 0;
+    int rprev = refit_seed<double>(t, cl, anchor, fo, n, P, kd);
     int r = n - 1;
     bool pd = true;
-    const bool lowpt = fabs(k.p[4]) >= (double)P->lowpt_qpt;
-    const int rc = rs < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, P, k, chi2s, rs, r,
-                                                  REFIT_HEAD, pd);
-    double* S = hd.state + (size_t)t * 20;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) S[i] = k.p[i];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) S[5 + i] = k.c[i];
-    hd.chi2[t] = chi2s;
-    hd.r[t] = (int16_t)r;
-    hd.rprev[t] = (int16_t)rs;
-    hd.flags[t] = (uint8_t)((rc ? 1 : 0) | (pd ? 0 : 2) | (lowpt ? 4 : 0));
-  }
-}
-
-__global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* __restrict__ tl_start,
-                                                FollowOut fo, const uint32_t* n_tl_dev,
-                                                uint32_t tl_cap,
-                                                const uint32_t* __restrict__ owner,
-                                                const uint16_t* __restrict__ nkept,
-                                                const uint32_t* __restrict__ perm, RefitHead hd,
-                                                RefitOut ro, uint32_t* __restrict__ fb_list,
-                                                const DevParams* __restrict__ Pg, DevStatus* st) {
-  if (failed(st)) return;
-  __shared__ DevParams Ps;
-  const DevParams* P = params_to_lds(Pg, &Ps);
-  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_tl; j += gridDim.x * blockDim.x) {
-    const uint32_t t = perm[j];
-    wave_prio(uni((uint32_t)nkept[t]));  // sorted: lane 0 holds the wave's longest track
-    ro.flags[t] = 0;
-    if (nkept[t] == 0) continue;
-    if (hd.flags[t] & 1) {
+    const bool lowpt = rprev >= 0 && fabs(kd.p[4]) >= (double)P->lowpt_qpt;
+    if (rprev < 0 || refit_run<double>(t, cl, anchor, fo, P, kd, chi2d, rprev, r, REFIT_HEAD, pd)) {
       ro.flags[t] = TF_REFIT_FAIL;
       atomicAdd(&st->n_refit_fail, 1u);
       continue;
     }
+    // FP32 from the head's state; y and sin phi handed over to twice FP32
+    // precision
     Trk<float> k;
-    const double* S = hd.state + (size_t)t * 20;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) k.p[i] = (float)S[i];
-    // the FP64 head hands over y and sin phi to twice FP32 precision
-    LoParts<float> lo{(float)(S[0] - (double)k.p[0]), (float)(S[2] - (double)k.p[2])};
+    for (int i = 0; i < 5; ++i) k.p[i] = (float)kd.p[i];
+    LoParts<float> lo{(float)(kd.p[0] - (double)k.p[0]), (float)(kd.p[2] - (double)k.p[2])};
 #pragma unroll
-    for (int i = 0; i < 15; ++i) k.c[i] = (float)S[5 + i];
-    float chi2s = (float)hd.chi2[t];
-    int rprev = hd.rprev[t], r = hd.r[t];
-    bool pd = (hd.flags[t] & 2) == 0;
+    for (int i = 0; i < 15; ++i) k.c[i] = (float)kd.c[i];
+    float chi2s = (float)chi2d;
     bool guard = false;
-    const int rc = refit_run<float>(t, cl, tl_anchor(cl, tl_start, t), fo, P, k, chi2s, rprev, r,
-                                    NROW, pd, &guard, &lo);
+    const int rc = refit_run<float>(t, cl, anchor, fo, P, k, chi2s, rprev, r, NROW, pd, &guard, &lo);
     k.p[0] += lo.y;
     k.p[2] += lo.s;
     if (rc) {
@@ -1121,7 +1084,6 @@ __global__ __launch_bounds__(64) void k_refit32(ClusterView cl, const uint32_t* 
     for (int i = 0; i < 15; ++i) ro.cov[(size_t)t * 15 + i] = k.c[i];
     ro.chi2[t] = chi2s;
     ro.row[t] = (uint8_t)rprev;
-    const bool lowpt = (hd.flags[t] & 4) != 0;
     if (P->force_fallback || guard || (!pd && lowpt)) {
       ro.flags[t] = TF_TO_FP64;  // listed for the FP64 refit by a scan
     } else if (!pd) {

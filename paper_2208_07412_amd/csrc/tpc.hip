@@ -80,10 +80,6 @@ struct tpc_ctx {
   float *r_par = nullptr, *r_cov = nullptr, *r_chi2 = nullptr;
   uint8_t *r_row = nullptr, *r_flags = nullptr;
   uint32_t* fb_list = nullptr;
-  double* h_state = nullptr;
-  double* h_chi2 = nullptr;
-  int16_t *h_r = nullptr, *h_rprev = nullptr;
-  uint8_t* h_flags = nullptr;
   uint32_t* trk_index = nullptr;
   uint32_t* hit_off = nullptr;
   size_t bsum_cap = 0;
@@ -112,8 +108,7 @@ struct Layout {
 
 struct Plan {
   size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
-      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, h_state, h_chi2, h_r, h_rprev,
-      h_flags, trk_index, hit_off, par, st, total;
+      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
   uint32_t nblk, nblk_s, nwin;
 };
@@ -162,11 +157,6 @@ Plan plan_for(const tpc_sizes& m) {
   p.r_row = L.add<uint8_t>(mt);
   p.r_flags = L.add<uint8_t>(mt);
   p.fb_list = L.add<uint32_t>(mt);
-  p.h_state = L.add<double>(mt * 20);
-  p.h_chi2 = L.add<double>(mt);
-  p.h_r = L.add<int16_t>(mt);
-  p.h_rprev = L.add<int16_t>(mt);
-  p.h_flags = L.add<uint8_t>(mt);
   p.trk_index = L.add<uint32_t>(mt);
   p.hit_off = L.add<uint32_t>(mt);
   p.par = L.add<DevParams>(1);
@@ -547,16 +537,13 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 9);
-    const RefitHead hd{c->h_state, c->h_chi2, c->h_r, c->h_rprev, c->h_flags};
     sort_by_key();  // tracks by kept hits: lanes of a wave refit equally long tracks
-    k_refit_head<<<g64, 64, 0, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept,
-                                    c->f_perm, hd, c->d_par, c->d_st);
     // at most refit_waves one-wave workgroups per CU (160 KB of LDS shared):
     // the rest of each workgroup's share is reserved, not used
     const int rw = c->tune.refit_waves;
     const size_t lds_pad = rw ? (size_t)(160 << 10) / rw - sizeof(DevParams) - 256 : 0;
-    k_refit32<<<g64, 64, lds_pad, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->owner, c->nkept,
-                                 c->f_perm, hd, ro, c->fb_list, c->d_par, c->d_st);
+    k_refit<<<g64, 64, lds_pad, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->nkept, c->f_perm, ro,
+                                     c->d_par, c->d_st);
   }
   {
     StageTimer tm(c, 10);
@@ -695,11 +682,6 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->r_row = (uint8_t*)(base + pl.r_row);
   c->r_flags = (uint8_t*)(base + pl.r_flags);
   c->fb_list = (uint32_t*)(base + pl.fb_list);
-  c->h_state = (double*)(base + pl.h_state);
-  c->h_chi2 = (double*)(base + pl.h_chi2);
-  c->h_r = (int16_t*)(base + pl.h_r);
-  c->h_rprev = (int16_t*)(base + pl.h_rprev);
-  c->h_flags = (uint8_t*)(base + pl.h_flags);
   c->trk_index = (uint32_t*)(base + pl.trk_index);
   c->hit_off = (uint32_t*)(base + pl.hit_off);
   c->d_par = (DevParams*)(base + pl.par);
