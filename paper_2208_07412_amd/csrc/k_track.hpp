@@ -1030,9 +1030,10 @@ __device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, con
 // by kept hits): the circle seed and the first REFIT_HEAD updates in FP64,
 // where the broad prior's variances collapse by orders of magnitude, then the
 // rest in FP32 (Joseph form, y and sin phi carried with their rounding
-// errors).  Tracks that need more (low pT with a covariance that is not
-// positive definite, or an update that cancels most of a variance) are
-// flagged for the FP64 refit.
+// errors).  A track that needs more (low pT with a covariance that is not
+// positive definite, or an update that cancels most of a variance) is refit
+// again in FP64 from its seed by the same lane (TF_TO_FP64 marks it; the
+// mark is internal and counted by a scan).
 __global__ __launch_bounds__(64) void k_refit(ClusterView cl, const uint32_t* __restrict__ tl_start,
                                               FollowOut fo, const uint32_t* n_tl_dev,
                                               uint32_t tl_cap, const uint16_t* __restrict__ nkept,
@@ -1078,22 +1079,43 @@ __global__ __launch_bounds__(64) void k_refit(ClusterView cl, const uint32_t* __
       atomicAdd(&st->n_refit_fail, 1u);
       continue;
     }
+    if (P->force_fallback || guard || (!pd && lowpt)) {
+      // the whole refit again in FP64 (the FP32 result is discarded)
+      Trk<double> k2;
+      double c2 = 0;
+      int rp2 = refit_seed<double>(t, cl, anchor, fo, n, P, k2);
+      int r2 = n - 1;
+      bool pd2 = true;
+      const bool fail =
+          rp2 < 0 || refit_run<double>(t, cl, anchor, fo, P, k2, c2, rp2, r2, NROW, pd2) != 0;
+      if (fail || !pd2) {
+        ro.flags[t] = TF_TO_FP64 | (fail ? TF_REFIT_FAIL : TF_FP64_FAIL);
+        atomicAdd(fail ? &st->n_refit_fail : &st->n_fallback_fail, 1u);
+        continue;
+      }
+#pragma unroll
+      for (int i = 0; i < 5; ++i) ro.par[(size_t)t * 5 + i] = (float)k2.p[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) ro.cov[(size_t)t * 15 + i] = (float)k2.c[i];
+      ro.chi2[t] = (float)c2;
+      ro.row[t] = (uint8_t)rp2;
+      ro.flags[t] = TF_TO_FP64 | TF_FP64;
+      continue;
+    }
 #pragma unroll
     for (int i = 0; i < 5; ++i) ro.par[(size_t)t * 5 + i] = k.p[i];
 #pragma unroll
     for (int i = 0; i < 15; ++i) ro.cov[(size_t)t * 15 + i] = k.c[i];
     ro.chi2[t] = chi2s;
     ro.row[t] = (uint8_t)rprev;
-    if (P->force_fallback || guard || (!pd && lowpt)) {
-      ro.flags[t] = TF_TO_FP64;  // listed for the FP64 refit by a scan
-    } else if (!pd) {
+    if (!pd) {
       ro.flags[t] = TF_NOT_PD;
       atomicAdd(&st->n_not_pd, 1u);
     }
   }
 }
 
-// The tracks the FP32 refit hands to the FP64 one, in tracklet order.
+// The tracks refit in FP64, in tracklet order (counted for the status).
 struct GetToFp64 {
   const uint8_t* flags;
   __device__ uint32_t operator()(uint32_t t) const { return (flags[t] & TF_TO_FP64) ? 1u : 0u; }
@@ -1104,43 +1126,6 @@ struct EmitFbList {
     if (v) list[pos] = t;
   }
 };
-
-__global__ __launch_bounds__(64) void k_refit64(ClusterView cl, const uint32_t* __restrict__ tl_start,
-                                                FollowOut fo, uint32_t tl_cap,
-                                                const uint16_t* __restrict__ nkept,
-                                                RefitOut ro, const uint32_t* __restrict__ fb_list,
-                                                const DevParams* __restrict__ Pg, DevStatus* st) {
-  if (failed(st)) return;
-  __shared__ DevParams Ps;
-  const DevParams* P = params_to_lds(Pg, &Ps);
-  const uint32_t n = scan_count(&st->n_fb_list, tl_cap);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_fallback = n;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t t = fb_list[i];
-    Trk<double> k;
-    double chi2s = 0;
-    const int32_t anchor = tl_anchor(cl, tl_start, t);
-    const int n = nkept[t];
-    int rprev = refit_seed<double>(t, cl, anchor, fo, n, P, k);
-    int r = n - 1;
-    bool pd = true;
-    const int rc = rprev < 0 ? 1 : refit_run<double>(t, cl, anchor, fo, P, k, chi2s, rprev, r, NROW,
-                                                     pd);
-    if (rc || rprev < 0 || !pd) {
-      const bool fail = rc || rprev < 0;
-      ro.flags[t] = fail ? TF_REFIT_FAIL : TF_FP64_FAIL;
-      atomicAdd(fail ? &st->n_refit_fail : &st->n_fallback_fail, 1u);
-      continue;
-    }
-#pragma unroll
-    for (int j = 0; j < 5; ++j) ro.par[(size_t)t * 5 + j] = (float)k.p[j];
-#pragma unroll
-    for (int j = 0; j < 15; ++j) ro.cov[(size_t)t * 15 + j] = (float)k.c[j];
-    ro.chi2[t] = (float)chi2s;
-    ro.row[t] = (uint8_t)rprev;
-    ro.flags[t] = TF_FP64;
-  }
-}
 
 // final keep flag of a tracklet slot
 __device__ __forceinline__ bool final_kept(const uint16_t* nkept, const RefitOut& ro, uint32_t t) {
@@ -1186,6 +1171,7 @@ __global__ void k_track_totals(const unsigned long long* total, TrackOut to, uin
   const uint32_t nt = (uint32_t)(v >> 32), nh = (uint32_t)v;
   st->n_tracks = nt;
   st->n_hits = nh;
+  st->n_fallback = st->n_fb_list;
   if (n_tracks) *n_tracks = nt;
   if (n_hits) *n_hits = nh;
   if (nt > to.capacity) latch(st, TPC_ERR_CAPACITY, nt);
@@ -1213,7 +1199,7 @@ __global__ __launch_bounds__(256) void k_track_emit(
       to.chi2[j] = ro.chi2[t];
       to.ndf[j] = (uint16_t)(2 * nkept[t] - 5);
       to.row[j] = ro.row[t];
-      to.flags[j] = ro.flags[t];
+      to.flags[j] = ro.flags[t] & ~TF_TO_FP64;
       to.z_anchor[j] = cl.z_fx[tl_start[t]];
       to.hit_start[j] = o;
     }

@@ -547,10 +547,9 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 10);
+    // the tracks the refit redid in FP64 (listed, and counted for the status)
     run_scan<uint32_t>(c, GetToFp64{ro.flags}, EmitFbList{c->fb_list}, t->n_tracklets, tcap,
                        (uint32_t*)nullptr, &c->d_st->n_fb_list);
-    k_refit64<<<g64, 64, 0, s>>>(cv, t->start, fo, tcap, c->nkept, ro, c->fb_list, c->d_par,
-                                 c->d_st);
   }
   StageTimer tm(c, 11);
   run_scan<unsigned long long>(c, GetTrackPair{c->nkept, ro}, EmitTrackPair{c->trk_index, c->hit_off, c->f_perm, tcap},
