@@ -237,8 +237,9 @@ void* tpc_stream(tpc_ctx* ctx);
  * its kernel; 3: both.  Stages: 0 sample index, 1 cluster peaks
  * (peak finding and moments, one pass over the samples), 2 cluster scan,
  * 3 cluster output, 4 cluster grid, 5 neighbours, 6 tracklets (and their
- * seed points, timed inside the fit call), 7 following (one kernel),
- * 8 resolution, 9 refit FP32, 10 refit FP64, 11 track output. */
+ * seed points, timed inside the fit call), 7 following (sorts and passes),
+ * 8 resolution, 9 refit (FP64 head, FP32, FP64 redo), 10 listing of the FP64
+ * redos, 11 track output. */
 #define TPC_PROF_STAGES 12
 int tpc_profile_enable(tpc_ctx* ctx, int on);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, uint32_t* launches);

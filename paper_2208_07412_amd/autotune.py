@@ -18,7 +18,7 @@ FOLLOW_SHAPES: List[Tuple[int, int]] = [(fb, fm) for fm in (0, 1) for fb in (64,
 CLUSTER_STAGES = ("sample_index", "cluster_peaks", "cluster_scan", "cluster_output")
 FOLLOW_STAGES = ("following",)
 REFIT_WAVES: List[int] = [0, 4, 5, 6, 8]
-REFIT_STAGES = ("refit_fp32",)
+REFIT_STAGES = ("refit",)
 
 
 def _stage_ms(prof: Dict[str, tuple], names, runs: int) -> float:

@@ -468,23 +468,39 @@ __global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_
 // key is the most rows a following pass can take (rows above the start row
 // outward; the row of the outermost pass-A hit inward): the passes that can
 // run longest start first, and the lanes of a wave start on one row and step
-// through the same rows, reading the same parts of the hit grid.  Three steps: k_sort_work<false> counts each
-// block of SORT_BLOCK tracklets per key into bins[key' * nblk + block]
-// (key' = 255 - key); an exclusive scan of bins in place gives every
-// (key', block) its first position; k_sort_work<true> writes perm, ranking
-// the elements of one key in index order.  Tracklets of equal estimate keep
-// their order (unit, row, time), so neighbouring tracks share a wave.  Wave w of
-// a workgroup takes the elements [256 w, 256 w + 256) of its block.
+// through the same rows, reading the same parts of the hit grid.  The sort
+// can first split the tracklets into ngrp groups of consecutive blocks (so of
+// consecutive units) and sort each group on its own: the following gives group
+// g to the workgroups that the dispatcher places on XCD g, so each XCD's L2
+// holds the hit data of its own units only.  Three steps: k_sort_work<false>
+// counts each block of SORT_BLOCK tracklets per key into
+// bins[(g * 256 + key') * npg + block in group] (key' = 255 - key, npg blocks per
+// group); an exclusive scan of bins in place gives every (group, key', block)
+// its first position, and bins[g * 256 * npg] is where group g starts;
+// k_sort_work<true> writes perm, ranking the elements of one key in index
+// order.  Tracklets of equal estimate keep their order (unit, row, time), so
+// neighbouring tracks share a wave.  Wave w of a workgroup takes the elements
+// [256 w, 256 w + 256) of its block.  Launch at least
+// ceil(capacity / SORT_BLOCK) + ngrp - 1 workgroups, over as many times 256
+// bins.
 #define SORT_BLOCK 1024
+#define FOLLOW_GROUPS 8  // sort groups of the following: one per XCD
+__device__ __forceinline__ uint32_t sort_blocks_per_group(uint32_t n, uint32_t ngrp) {
+  return ((n + SORT_BLOCK - 1) / SORT_BLOCK + ngrp - 1) / ngrp;
+}
+
 template <bool SCATTER>
 __global__ __launch_bounds__(256) void k_sort_work(const uint8_t* __restrict__ key,
                                                    const uint32_t* n_tl_dev, uint32_t tl_cap,
-                                                   uint32_t nblk, uint32_t* __restrict__ bins,
+                                                   uint32_t ngrp, uint32_t* __restrict__ bins,
                                                    uint32_t* __restrict__ perm,
                                                    const DevStatus* st) {
   if (failed(st)) return;
   __shared__ uint32_t h[4][256];  // per wave: count per key, then next position per key
   const uint32_t n = scan_count(n_tl_dev, tl_cap);
+  const uint32_t npg = sort_blocks_per_group(n, ngrp);
+  if (blockIdx.x >= ngrp * npg) return;  // uniform per workgroup
+  const uint32_t grp = blockIdx.x / npg, lb = blockIdx.x - grp * npg;
   const uint32_t b0 = blockIdx.x * SORT_BLOCK;
   const uint32_t m = b0 < n ? min((uint32_t)SORT_BLOCK, n - b0) : 0u;
   if (SCATTER && m == 0) return;  // uniform per workgroup
@@ -502,11 +518,12 @@ __global__ __launch_bounds__(256) void k_sort_work(const uint8_t* __restrict__ k
   __syncthreads();
   const uint32_t k = threadIdx.x;
   const uint32_t c0 = h[0][k], c1 = h[1][k], c2 = h[2][k], c3 = h[3][k];
+  const size_t bi = (size_t)(grp * 256u + k) * npg + lb;
   if (!SCATTER) {
-    bins[(size_t)k * nblk + blockIdx.x] = c0 + c1 + c2 + c3;
+    bins[bi] = c0 + c1 + c2 + c3;
     return;
   }
-  const uint32_t base = bins[(size_t)k * nblk + blockIdx.x];
+  const uint32_t base = bins[bi];
   __syncthreads();
   h[0][k] = base;
   h[1][k] = base + c0;
@@ -733,6 +750,7 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
                                                const uint16_t* __restrict__ tl_len,
                                                const uint32_t* __restrict__ pts,
                                                const uint32_t* __restrict__ perm,
+                                               const uint32_t* __restrict__ bins, uint32_t ngrp,
                                                uint8_t* __restrict__ key,
                                                const uint32_t* n_tl_dev, uint32_t tl_cap,
                                                FollowOut fo, ulonglong4* __restrict__ work,
@@ -748,7 +766,19 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const float chi2max = pv.chi2_max();
   uint32_t w_steps = 0, w_cands = 0, w_upds = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tl; i += gridDim.x * blockDim.x) {
+  // sorted passes: workgroup b takes group b % ngrp of the sort (gridDim.x is
+  // a multiple of ngrp), in the group's order
+  uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x, i1 = n_tl, di = gridDim.x * blockDim.x;
+  if (PASS != FP_AB) {
+    const uint32_t g = blockIdx.x % ngrp, j = blockIdx.x / ngrp, per = gridDim.x / ngrp;
+    const uint32_t npg = sort_blocks_per_group(n_tl, ngrp);
+    const size_t gsz = (size_t)256 * npg;
+    const uint32_t gs = npg ? bins[g * gsz] : 0u;
+    i1 = npg == 0 ? 0u : g + 1 < ngrp ? bins[(g + 1) * gsz] : n_tl;
+    i0 = j < per ? gs + j * blockDim.x + threadIdx.x : i1;
+    di = per * blockDim.x;
+  }
+  for (uint32_t i = i0; i < i1; i += di) {
     const uint32_t t = PASS == FP_AB ? i : perm[i];
     FollowLane f;
     f.n_steps = f.n_cands = f.n_upds = 0;

@@ -123,8 +123,8 @@ Plan plan_for(const tpc_sizes& m) {
   uint64_t nscan = nur * p.nwin;
   if (m.max_clusters > nscan) nscan = m.max_clusters;
   if (m.max_tracklets > nscan) nscan = m.max_tracklets;
-  if (256ull * ceil_div(m.max_tracklets, SORT_BLOCK) > nscan)
-    nscan = 256ull * ceil_div(m.max_tracklets, SORT_BLOCK);
+  if (256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + FOLLOW_GROUPS - 1) > nscan)
+    nscan = 256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + FOLLOW_GROUPS - 1);
   p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
   const uint64_t mc = m.max_clusters > 0 ? m.max_clusters : 1;
   const uint64_t mt = m.max_tracklets > 0 ? m.max_tracklets : 1;
@@ -145,9 +145,9 @@ Plan plan_for(const tpc_sizes& m) {
   p.f_pts = L.add<uint32_t>(mt * 3);
   p.f_key = L.add<uint8_t>(mt);
   p.f_perm = L.add<uint32_t>(mt);
-  p.f_bins = L.add<uint32_t>(256 * ceil_div(mt, SORT_BLOCK));
+  p.f_bins = L.add<uint32_t>(256 * (ceil_div(mt, SORT_BLOCK) + FOLLOW_GROUPS - 1));
   p.f_krow = L.add<uint8_t>(mt * NROW);
-  p.f_work = L.add<ulonglong4>(2 * (mt / 64 + 8));  // two passes
+  p.f_work = L.add<ulonglong4>(2 * (mt / 64 + 4 * FOLLOW_GROUPS + 8));  // two passes
   p.pos = L.add<int2>(mc);
   p.owner = L.add<uint32_t>(mc);
   p.nkept = L.add<uint16_t>(mt);
@@ -469,13 +469,15 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   const uint32_t gw = grid_for(tcap, 32);
   // f_perm = the tracklets sorted by f_key, largest first (stable)
   const uint32_t nsb = ceil_div(tcap, SORT_BLOCK);
-  auto sort_by_key = [&]() {
-    k_sort_work<false><<<nsb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, nsb, c->f_bins,
-                                           c->f_perm, c->d_st);
-    run_scan<uint32_t>(c, GetU32{c->f_bins}, EmitU32{c->f_bins}, (const uint32_t*)nullptr,
-                       256 * nsb, (uint32_t*)nullptr, (uint32_t*)nullptr);
-    k_sort_work<true><<<nsb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, nsb, c->f_bins,
+  // ngrp groups sorted each on its own (the following: one group per XCD)
+  auto sort_by_key = [&](uint32_t ngrp) {
+    const uint32_t nb = nsb + ngrp - 1;
+    k_sort_work<false><<<nb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, ngrp, c->f_bins,
                                           c->f_perm, c->d_st);
+    run_scan<uint32_t>(c, GetU32{c->f_bins}, EmitU32{c->f_bins}, (const uint32_t*)nullptr,
+                       256 * nb, (uint32_t*)nullptr, (uint32_t*)nullptr);
+    k_sort_work<true><<<nb, 256, 0, s>>>(c->f_key, t->n_tracklets, tcap, ngrp, c->f_bins,
+                                         c->f_perm, c->d_st);
   };
   // per-call counters of the fit stage
   k_fill<uint32_t><<<1, 64, 0, s>>>(&c->d_st->n_fallback, 0u, 5);
@@ -488,7 +490,8 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   {
     StageTimer tm(c, 7);
     const int fb = c->tune.follow_block;
-    const uint32_t gf = grid_for(tcap, fb);
+    const uint32_t ng = FOLLOW_GROUPS;
+    const uint32_t gf = ceil_div(grid_for(tcap, fb), ng) * ng;
     const uint32_t nwf = gf * (uint32_t)(fb / 64);  // waves per following launch
     const bool split = c->tune.follow_mode == 0;
     auto launch = [&](auto Bc, auto Cc) {
@@ -498,20 +501,23 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
         // pass A, then pass B, each over the tracklets sorted by the most rows
         // the pass can take (the key k_tracklet_points, then pass A, leaves)
         for (int pass = 0; pass < 2; ++pass) {
-          sort_by_key();
+          sort_by_key(ng);
           if (pass == 0)
             k_follow<Bv, FP_A, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
-                                                     c->f_pts, c->f_perm, c->f_key, t->n_tracklets,
-                                                     tcap, fo, c->f_work, c->d_par, c->d_st);
+                                                     c->f_pts, c->f_perm, c->f_bins, ng, c->f_key,
+                                                     t->n_tracklets, tcap, fo, c->f_work, c->d_par,
+                                                     c->d_st);
           else
             k_follow<Bv, FP_B, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
-                                                     c->f_pts, c->f_perm, c->f_key, t->n_tracklets,
-                                                     tcap, fo, c->f_work + nwf, c->d_par, c->d_st);
+                                                     c->f_pts, c->f_perm, c->f_bins, ng, c->f_key,
+                                                     t->n_tracklets, tcap, fo, c->f_work + nwf,
+                                                     c->d_par, c->d_st);
         }
       } else {
         k_follow<Bv, FP_AB, Cv><<<gf, Bv, 0, s>>>(cv, c->cblk, nblk, l->upc, t->start, t->len,
-                                                  c->f_pts, nullptr, c->f_key, t->n_tracklets,
-                                                  tcap, fo, c->f_work, c->d_par, c->d_st);
+                                                  c->f_pts, nullptr, nullptr, 1u, c->f_key,
+                                                  t->n_tracklets, tcap, fo, c->f_work, c->d_par,
+                                                  c->d_st);
       }
     };
     using B64 = std::integral_constant<int, 64>;
@@ -537,7 +543,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 9);
-    sort_by_key();  // tracks by kept hits: lanes of a wave refit equally long tracks
+    sort_by_key(1);  // tracks by kept hits: lanes of a wave refit equally long tracks
     // at most refit_waves one-wave workgroups per CU (160 KB of LDS shared):
     // the rest of each workgroup's share is reserved, not used
     const int rw = c->tune.refit_waves;
@@ -822,7 +828,7 @@ int tpc_profile_read(tpc_ctx* c, double* ms, uint32_t* launches) {
 const char* tpc_profile_stage_name(int i) {
   static const char* names[TPC_PROF_STAGES] = {
       "sample_index", "cluster_peaks", "cluster_scan", "cluster_output", "cluster_grid",
-      "neighbours", "tracklets", "following", "resolution", "refit_fp32", "refit_fp64",
+      "neighbours", "tracklets", "following", "resolution", "refit", "refit_fp64_list",
       "track_output"};
   return (i >= 0 && i < TPC_PROF_STAGES) ? names[i] : "unknown";
 }
