@@ -79,6 +79,20 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
   return (bid & 7u) * per + (bid >> 3);
 }
 
+// One item per wave over n items, in rounds of the grid's waves (stride):
+// this wave's first item, with the workgroups that the dispatcher places on
+// one XCD (every eighth) taking consecutive items of each round (of all
+// items, when one round covers them).
+__device__ __forceinline__ uint32_t xcd_wave_item(uint32_t n, uint32_t& stride) {
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t nb = (n + wpb - 1) / wpb;
+  stride = gridDim.x * wpb;
+  uint32_t b = blockIdx.x;
+  if (nb > gridDim.x) b = xcd_remap(b, gridDim.x);
+  else if (b < nb) b = xcd_remap(b, nb);
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)(b * wpb + (threadIdx.x >> 6)));
+}
+
 // A value the whole wave holds alike, moved to a scalar register so that
 // the loop control and address arithmetic built on it stay scalar.
 __device__ __forceinline__ uint32_t uni(uint32_t v) {

@@ -879,9 +879,8 @@ __global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_t
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t i = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); i < n_tl;
-       i += nw) {
+  uint32_t nw;
+  for (uint32_t i = xcd_wave_item(n_tl, nw); i < n_tl; i += nw) {
     // the stores go in descending tracklet order, so that of two bidders with
     // equal hit counts the one that wins (the lower index) tends to store
     // last (a store order sorted by key wins more clusters at once but loses
@@ -913,9 +912,8 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t t = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); t < n_tl;
-       t += nw) {
+  uint32_t nw;
+  for (uint32_t t = xcd_wave_item(n_tl, nw); t < n_tl; t += nw) {
     uint32_t n = 0;
     if (fo.ok[t] && (int)fo.nhits[t] >= P->min_track_hits) {
       const uint32_t key = track_key(fo.nhits[t], t);
