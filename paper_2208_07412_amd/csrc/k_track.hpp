@@ -484,9 +484,24 @@ __global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_
 // ceil(capacity / SORT_BLOCK) + ngrp - 1 workgroups, over as many times 256
 // bins.
 #define SORT_BLOCK 1024
-#define FOLLOW_GROUPS 8  // sort groups of the following: one per XCD
+#define XCD_GROUPS 8  // sort groups of the following: one per XCD
 __device__ __forceinline__ uint32_t sort_blocks_per_group(uint32_t n, uint32_t ngrp) {
   return ((n + SORT_BLOCK - 1) / SORT_BLOCK + ngrp - 1) / ngrp;
+}
+
+// One item per thread over the sorted order of n items in ngrp groups:
+// workgroup b takes group b % ngrp (gridDim.x is a multiple of ngrp), in the
+// group's order; [i0, i1) with stride di are this thread's positions.
+__device__ __forceinline__ void sorted_items(const uint32_t* __restrict__ bins, uint32_t ngrp,
+                                             uint32_t n, uint32_t& i0, uint32_t& i1,
+                                             uint32_t& di) {
+  const uint32_t g = blockIdx.x % ngrp, j = blockIdx.x / ngrp, per = gridDim.x / ngrp;
+  const uint32_t npg = sort_blocks_per_group(n, ngrp);
+  const size_t gsz = (size_t)256 * npg;
+  const uint32_t gs = npg ? bins[g * gsz] : 0u;
+  i1 = npg == 0 ? 0u : g + 1 < ngrp ? bins[(g + 1) * gsz] : n;
+  i0 = j < per ? gs + j * blockDim.x + threadIdx.x : i1;
+  di = per * blockDim.x;
 }
 
 template <bool SCATTER>
@@ -766,18 +781,8 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const float chi2max = pv.chi2_max();
   uint32_t w_steps = 0, w_cands = 0, w_upds = 0;
-  // sorted passes: workgroup b takes group b % ngrp of the sort (gridDim.x is
-  // a multiple of ngrp), in the group's order
   uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x, i1 = n_tl, di = gridDim.x * blockDim.x;
-  if (PASS != FP_AB) {
-    const uint32_t g = blockIdx.x % ngrp, j = blockIdx.x / ngrp, per = gridDim.x / ngrp;
-    const uint32_t npg = sort_blocks_per_group(n_tl, ngrp);
-    const size_t gsz = (size_t)256 * npg;
-    const uint32_t gs = npg ? bins[g * gsz] : 0u;
-    i1 = npg == 0 ? 0u : g + 1 < ngrp ? bins[(g + 1) * gsz] : n_tl;
-    i0 = j < per ? gs + j * blockDim.x + threadIdx.x : i1;
-    di = per * blockDim.x;
-  }
+  if (PASS != FP_AB) sorted_items(bins, ngrp, n_tl, i0, i1, di);
   for (uint32_t i = i0; i < i1; i += di) {
     const uint32_t t = PASS == FP_AB ? i : perm[i];
     FollowLane f;
@@ -1065,13 +1070,17 @@ __device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, con
 __global__ __launch_bounds__(64) void k_refit(ClusterView cl, const uint32_t* __restrict__ tl_start,
                                               FollowOut fo, const uint32_t* n_tl_dev,
                                               uint32_t tl_cap, const uint16_t* __restrict__ nkept,
-                                              const uint32_t* __restrict__ perm, RefitOut ro,
+                                              const uint32_t* __restrict__ perm,
+                                              const uint32_t* __restrict__ bins, uint32_t ngrp,
+                                              RefitOut ro,
                                               const DevParams* __restrict__ Pg, DevStatus* st) {
   if (failed(st)) return;
   __shared__ DevParams Ps;
   const DevParams* P = params_to_lds(Pg, &Ps);
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_tl; j += gridDim.x * blockDim.x) {
+  uint32_t j0, j1, dj;
+  sorted_items(bins, ngrp, n_tl, j0, j1, dj);
+  for (uint32_t j = j0; j < j1; j += dj) {
     const uint32_t t = perm[j];
     ro.flags[t] = 0;
     const int n = nkept[t];

@@ -123,8 +123,8 @@ Plan plan_for(const tpc_sizes& m) {
   uint64_t nscan = nur * p.nwin;
   if (m.max_clusters > nscan) nscan = m.max_clusters;
   if (m.max_tracklets > nscan) nscan = m.max_tracklets;
-  if (256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + FOLLOW_GROUPS - 1) > nscan)
-    nscan = 256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + FOLLOW_GROUPS - 1);
+  if (256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + XCD_GROUPS - 1) > nscan)
+    nscan = 256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + XCD_GROUPS - 1);
   p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
   const uint64_t mc = m.max_clusters > 0 ? m.max_clusters : 1;
   const uint64_t mt = m.max_tracklets > 0 ? m.max_tracklets : 1;
@@ -145,9 +145,9 @@ Plan plan_for(const tpc_sizes& m) {
   p.f_pts = L.add<uint32_t>(mt * 3);
   p.f_key = L.add<uint8_t>(mt);
   p.f_perm = L.add<uint32_t>(mt);
-  p.f_bins = L.add<uint32_t>(256 * (ceil_div(mt, SORT_BLOCK) + FOLLOW_GROUPS - 1));
+  p.f_bins = L.add<uint32_t>(256 * (ceil_div(mt, SORT_BLOCK) + XCD_GROUPS - 1));
   p.f_krow = L.add<uint8_t>(mt * NROW);
-  p.f_work = L.add<ulonglong4>(2 * (mt / 64 + 4 * FOLLOW_GROUPS + 8));  // two passes
+  p.f_work = L.add<ulonglong4>(2 * (mt / 64 + 4 * XCD_GROUPS + 8));  // two passes
   p.pos = L.add<int2>(mc);
   p.owner = L.add<uint32_t>(mc);
   p.nkept = L.add<uint16_t>(mt);
@@ -490,7 +490,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   {
     StageTimer tm(c, 7);
     const int fb = c->tune.follow_block;
-    const uint32_t ng = FOLLOW_GROUPS;
+    const uint32_t ng = XCD_GROUPS;
     const uint32_t gf = ceil_div(grid_for(tcap, fb), ng) * ng;
     const uint32_t nwf = gf * (uint32_t)(fb / 64);  // waves per following launch
     const bool split = c->tune.follow_mode == 0;
@@ -543,13 +543,17 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 9);
-    sort_by_key(1);  // tracks by kept hits: lanes of a wave refit equally long tracks
+    // tracks by kept hits: lanes of a wave refit equally long tracks (one
+    // group: per-XCD groups made the refit slower, 1.04 -> 1.06 ms)
+    const uint32_t ng = 1;
+    sort_by_key(ng);
     // at most refit_waves one-wave workgroups per CU (160 KB of LDS shared):
     // the rest of each workgroup's share is reserved, not used
     const int rw = c->tune.refit_waves;
     const size_t lds_pad = rw ? (size_t)(160 << 10) / rw - sizeof(DevParams) - 256 : 0;
-    k_refit<<<g64, 64, lds_pad, s>>>(cv, t->start, fo, t->n_tracklets, tcap, c->nkept, c->f_perm, ro,
-                                     c->d_par, c->d_st);
+    k_refit<<<ceil_div(g64, ng) * ng, 64, lds_pad, s>>>(cv, t->start, fo, t->n_tracklets, tcap,
+                                                        c->nkept, c->f_perm, c->f_bins, ng, ro,
+                                                        c->d_par, c->d_st);
   }
   {
     StageTimer tm(c, 10);
