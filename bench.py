@@ -49,7 +49,7 @@ def log(*a):
 # Algorithmic bytes each stage must move, per unit of work:
 # samples are (pad, time, adc) u16; a cluster record is y_fx, z_fx (i32),
 # pad, time, s2pad, s2time (f32), qtot, qmax, ppad, ptime (u16), flags (u8).
-def stage_bytes(ns, nc, n_ur, T, W=16):
+def stage_bytes(ns, nc, n_ur, T, W=24):
     rec = 4 * 2 + 4 * 4 + 2 * 4 + 1
     raw = 24                 # raw record per cluster between the two clusterizer passes
     nblk_s = (T + 3) // 4   # sample index: one entry per 4 time bins

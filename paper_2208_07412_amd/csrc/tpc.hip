@@ -346,7 +346,7 @@ template <int W, int K>
 void launch_cluster(tpc_ctx* c, const ZsArgs& za, uint32_t nblk_s, uint32_t n_ur,
                     const ClusterOut& co, uint32_t* n_clusters, uint32_t capacity,
                     uint32_t* crow_start) {
-  constexpr int PRE = W == 8 ? 1 : (W == 16 ? 2 : 3);
+  constexpr int PRE = W == 8 ? 1 : (W <= 20 ? 2 : 3);
   hipStream_t s = c->stream;
   const uint32_t nwin = ceil_div(za.n_time_bins, W);
   const uint32_t nchunk = ceil_div(nwin, K);
@@ -404,6 +404,8 @@ int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
   else if (w == 16 && k == 4) run(I16{}, I4{});
   else if (w == 16 && k == 8) run(I16{}, I8{});
   else if (w == 16 && k == 16) run(I16{}, I16k{});
+  else if (w == 20 && k == 8) run(std::integral_constant<int, 20>{}, I8{});
+  else if (w == 24 && k == 8) run(std::integral_constant<int, 24>{}, I8{});
   else if (w == 32 && k == 4) run(I32{}, I4{});
   else if (w == 32 && k == 8) run(I32{}, I8{});
   else run(I32{}, I16k{});
@@ -839,7 +841,7 @@ const char* tpc_profile_stage_name(int i) {
 
 int tpc_tuning_default(tpc_tuning* t) {
   if (!t) return TPC_ERR_ARG;
-  t->cl_window = 16;
+  t->cl_window = 24;
   t->cl_chunk = 8;
   t->follow_block = 128;
   t->follow_mode = 0;
@@ -849,7 +851,10 @@ int tpc_tuning_default(tpc_tuning* t) {
 
 int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if (!c || !t) return TPC_ERR_ARG;
-  if (t->cl_window != 8 && t->cl_window != 16 && t->cl_window != 32) return TPC_ERR_ARG;
+  if (t->cl_window != 8 && t->cl_window != 16 && t->cl_window != 20 && t->cl_window != 24 &&
+      t->cl_window != 32)
+    return TPC_ERR_ARG;
+  if ((t->cl_window == 20 || t->cl_window == 24) && t->cl_chunk != 8) return TPC_ERR_ARG;
   if (t->cl_chunk != 4 && t->cl_chunk != 8 && t->cl_chunk != 16) return TPC_ERR_ARG;
   if (t->follow_block != 64 && t->follow_block != 128 && t->follow_block != 256) return TPC_ERR_ARG;
   if (t->follow_mode != 0 && t->follow_mode != 1) return TPC_ERR_ARG;

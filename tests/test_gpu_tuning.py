@@ -21,7 +21,8 @@ pytestmark = pytest.mark.gpu
 
 NPADS, _, _ = oracle.geometry()
 SHAPES = [(8, 8, 64, 0, 0), (8, 16, 128, 1, 4), (16, 4, 64, 0, 5), (16, 8, 128, 1, 6),
-          (16, 16, 256, 0, 8), (32, 4, 256, 1, 0), (32, 8, 64, 1, 5), (32, 16, 128, 0, 4)]
+          (16, 16, 256, 0, 8), (20, 8, 128, 0, 6), (24, 8, 256, 1, 5), (32, 4, 256, 1, 0),
+          (32, 8, 64, 1, 5), (32, 16, 128, 0, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -63,7 +64,7 @@ def _lattice_event(T, step_t, step_p, adc):
                           np.array(a, np.uint16), rs, 1, T, {}, {}, None)
 
 
-@pytest.mark.parametrize("w,k", [(8, 4), (16, 8), (32, 4)])
+@pytest.mark.parametrize("w,k", [(8, 4), (16, 8), (20, 8), (24, 8), (32, 4)])
 def test_most_peaks_per_window(w, k):
     # isolated samples on every other pad and bin: each one is a peak, so a
     # window holds far more peaks than one moment batch
@@ -74,7 +75,7 @@ def test_most_peaks_per_window(w, k):
     compare_clusters(g["clusters"], o["clusters"], labels=True)
 
 
-@pytest.mark.parametrize("w,k", [(8, 16), (16, 8), (32, 16)])
+@pytest.mark.parametrize("w,k", [(8, 16), (16, 8), (20, 8), (24, 8), (32, 16)])
 def test_fully_occupied_rows(w, k):
     # every (time, pad) present: the densest input a row can have
     ev = _lattice_event(120, 1, 1, lambda t, p: 3 + ((t * 131 + p * 71) * 2654435761 % 2**32) % 400)
@@ -107,8 +108,8 @@ def test_work_counting_variant_same_results(frame):
 def test_set_tuning_rejects_unknown_shapes():
     reco = tpc.Reco(1, 100, 1024, 64)
     before = reco.tuning()
-    for bad in (dict(cl_window=12), dict(cl_chunk=3), dict(follow_block=96), dict(follow_mode=2),
-                dict(refit_waves=3)):
+    for bad in (dict(cl_window=12), dict(cl_chunk=3), dict(cl_window=20, cl_chunk=4),
+                dict(follow_block=96), dict(follow_mode=2), dict(refit_waves=3)):
         with pytest.raises(tpc.TpcError):
             reco.set_tuning(**bad)
         assert reco.tuning() == before
