@@ -248,9 +248,9 @@ const char* tpc_profile_stage_name(int stage);
 const char* tpc_status_string(int status);
 
 /* Launch shapes (performance only: every choice gives the same results).
- * cl_window: clusterizer window in time bins, 8, 16, 20, 24 or 32; cl_chunk:
- * windows walked by one workgroup, 4, 8 or 16 (8 only for windows of 20 and
- * 24 bins); follow_block: threads per workgroup
+ * cl_window: clusterizer window in time bins, 8, 16, 20, 24 or 32;
+ * cl_chunk: windows walked by one workgroup, 4, 8 or 16 (8 only for windows
+ * of 20 and 24 bins); follow_block: threads per workgroup
  * of the following kernel, 64, 128 or 256; follow_mode: 0 one launch per
  * pass (outward, then inward), each over the tracklets sorted by the most
  * rows the pass can take, longest first; 1 one launch that runs both passes

@@ -346,7 +346,9 @@ template <int W, int K>
 void launch_cluster(tpc_ctx* c, const ZsArgs& za, uint32_t nblk_s, uint32_t n_ur,
                     const ClusterOut& co, uint32_t* n_clusters, uint32_t capacity,
                     uint32_t* crow_start) {
-  constexpr int PRE = W == 8 ? 1 : (W <= 20 ? 2 : 3);
+  // samples prefetched into registers: 64 per step (3 steps cover the larger
+  // windows of the denser rows)
+  constexpr int PRE = W == 8 ? 1 : 3;
   hipStream_t s = c->stream;
   const uint32_t nwin = ceil_div(za.n_time_bins, W);
   const uint32_t nchunk = ceil_div(nwin, K);

@@ -108,7 +108,7 @@ def test_work_counting_variant_same_results(frame):
 def test_set_tuning_rejects_unknown_shapes():
     reco = tpc.Reco(1, 100, 1024, 64)
     before = reco.tuning()
-    for bad in (dict(cl_window=12), dict(cl_chunk=3), dict(cl_window=20, cl_chunk=4),
+    for bad in (dict(cl_window=12), dict(cl_chunk=3), dict(cl_window=20, cl_chunk=4), dict(cl_window=28),
                 dict(follow_block=96), dict(follow_mode=2), dict(refit_waves=3)):
         with pytest.raises(tpc.TpcError):
             reco.set_tuning(**bad)
