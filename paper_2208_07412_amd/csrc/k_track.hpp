@@ -1216,7 +1216,13 @@ __global__ void k_track_totals(const unsigned long long* total, TrackOut to, uin
   if (nt <= to.capacity) to.hit_start[nt] = nh;
 }
 
-// One wave per track (the tracklets that became tracks, listed in order).
+// One wave per 64 consecutive tracks (the tracklets that became tracks,
+// listed in order), so that every output array is written in contiguous
+// runs: lane i writes the fields of track j0 + i, the wave writes the
+// parameters and covariances of its tracks as one run each, then the kept hits
+// of all its tracks (one output run, in track order, each track's hits in
+// ascending row order), lane e taking element e of the run: its track is the
+// last one whose first hit is at or before e.
 __global__ __launch_bounds__(256) void k_track_emit(
     ClusterView cl, const uint32_t* __restrict__ tl_start, FollowOut fo,
     const uint32_t* __restrict__ tlist, const uint16_t* __restrict__ nkept, RefitOut ro,
@@ -1225,27 +1231,55 @@ __global__ __launch_bounds__(256) void k_track_emit(
   const uint32_t n_trk = min(st->n_tracks, to.capacity);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t j = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); j < n_trk;
-       j += nw) {
-    const uint32_t t = uni(tlist[j]);
-    if (lane < 5) to.par[(size_t)j * 5 + lane] = ro.par[(size_t)t * 5 + lane];
-    if (lane < 15) to.cov[(size_t)j * 15 + lane] = ro.cov[(size_t)t * 15 + lane];
-    const uint32_t o = hit_off[t];
-    if (lane == 0) {
+  for (uint32_t w = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); w < (n_trk + 63) / 64;
+       w += nw) {
+    const uint32_t j0 = w * 64, m = min(64u, n_trk - j0);
+    const uint32_t j = j0 + lane;
+    uint32_t t = 0, o = 0, n = 0;
+    if (lane < m) {
+      t = tlist[j];
+      o = hit_off[t];
+      n = nkept[t];
       to.tracklet[j] = t;
       to.chi2[j] = ro.chi2[t];
-      to.ndf[j] = (uint16_t)(2 * nkept[t] - 5);
+      to.ndf[j] = (uint16_t)(2 * n - 5);
       to.row[j] = ro.row[t];
       to.flags[j] = ro.flags[t] & ~TF_TO_FP64;
       to.z_anchor[j] = cl.z_fx[tl_start[t]];
       to.hit_start[j] = o;
     }
-    // kept hits in ascending row order
-    const int32_t* H = fo.hits + (size_t)t * NROW;
-    const uint8_t* KR = fo.krow + (size_t)t * NROW;
-    const uint32_t n = nkept[t];
-    for (uint32_t i = lane; i < n; i += 64)
-      if (o + i < to.hit_capacity) to.hits[o + i] = (uint32_t)H[KR[i]];
+    // every lane takes part in each shuffle (the loops are uniform)
+    for (uint32_t e0 = 0; e0 < m * 5; e0 += 64) {
+      const uint32_t e = e0 + lane, k = min(e / 5, 63u);
+      const uint32_t tk = (uint32_t)__shfl((int)t, (int)k);
+      if (e < m * 5) to.par[(size_t)j0 * 5 + e] = ro.par[(size_t)tk * 5 + (e - k * 5)];
+    }
+    for (uint32_t e0 = 0; e0 < m * 15; e0 += 64) {
+      const uint32_t e = e0 + lane, k = min(e / 15, 63u);
+      const uint32_t tk = (uint32_t)__shfl((int)t, (int)k);
+      if (e < m * 15) to.cov[(size_t)j0 * 15 + e] = ro.cov[(size_t)tk * 15 + (e - k * 15)];
+    }
+    // the wave's hits: offsets relative to its first track's (lanes past the
+    // last track hold the end, so no element maps to them)
+    const uint32_t o0 = uni((uint32_t)__shfl((int)o, 0));
+    const uint32_t last = m - 1;
+    const uint32_t end = uni((uint32_t)__shfl((int)(o + n), (int)last)) - o0;
+    const uint32_t rel = lane < m ? o - o0 : end;
+    for (uint32_t e0 = 0; e0 < end; e0 += 64) {
+      const uint32_t e = e0 + lane;
+      uint32_t k = 0;
+#pragma unroll
+      for (uint32_t step = 32; step > 0; step >>= 1) {
+        const uint32_t rk = (uint32_t)__shfl((int)rel, (int)(k + step));
+        if (k + step < m && rk <= e) k += step;
+      }
+      const uint32_t tk = (uint32_t)__shfl((int)t, (int)k);
+      const uint32_t rk = (uint32_t)__shfl((int)rel, (int)k);
+      if (e < end && o0 + e < to.hit_capacity) {
+        const uint32_t i = e - rk;
+        to.hits[o0 + e] = (uint32_t)fo.hits[(size_t)tk * NROW + fo.krow[(size_t)tk * NROW + i]];
+      }
+    }
   }
 }
 

@@ -572,8 +572,8 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
               tr->row, tr->flags, tr->z_anchor, tr->hit_start, tr->hits, tr->cluster_track};
   k_track_totals<<<1, 1, 0, s>>>(c->tot64, to, tr->n_tracks, tr->n_hits, c->d_st);
   // tracklets of the tracks listed in f_perm (free after the refit)
-  k_track_emit<<<gw, 256, 0, s>>>(cv, t->start, fo, c->f_perm, c->nkept, ro, c->hit_off, to,
-                                  c->d_st);
+  k_track_emit<<<grid_for(tcap, 256), 256, 0, s>>>(cv, t->start, fo, c->f_perm, c->nkept, ro,
+                                                    c->hit_off, to, c->d_st);
   k_cluster_track<<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, c->trk_index, cl->n_clusters, ccap,
                                                       tcap, tr->cluster_track, c->d_st);
   if (tr->follow_hits)
