@@ -904,6 +904,8 @@ __global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_t
   }
 }
 
+#define KEEP_GROUP 16  // tracklets per wave of k_keep
+
 // Hits each track keeps after the claims; < min_track_hits drops the track.
 // The kept count is also the refit's sort key: the refit takes the tracks
 // sorted by it, so the lanes of a wave refit tracks of equal length.
@@ -918,29 +920,37 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const uint32_t lane = threadIdx.x & 63;
   uint32_t nw;
-  for (uint32_t t = xcd_wave_item(n_tl, nw); t < n_tl; t += nw) {
-    uint32_t n = 0;
-    if (fo.ok[t] && (int)fo.nhits[t] >= P->min_track_hits) {
-      const uint32_t key = track_key(fo.nhits[t], t);
-      const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
-      const int32_t* H = fo.hits + (size_t)t * NROW;
-      uint8_t* KR = fo.krow + (size_t)t * NROW;
-      for (int r0 = lo; r0 <= hi; r0 += 64) {
-        const int r = r0 + (int)lane;
-        bool kept = false;
-        if (r <= hi) {
-          const int32_t c = H[r];
-          kept = c >= 0 && (uint32_t)c < n_cl_cap && owner[c] == key;
+  // a wave takes KEEP_GROUP consecutive tracklets; lane k collects the count
+  // of the k-th, and the counts go out as one run per array
+  const uint32_t n_grp = (n_tl + KEEP_GROUP - 1) / KEEP_GROUP;
+  for (uint32_t g = xcd_wave_item(n_grp, nw); g < n_grp; g += nw) {
+    const uint32_t t0 = g * KEEP_GROUP, t1 = min(t0 + KEEP_GROUP, n_tl);
+    uint32_t mine = 0;
+    for (uint32_t t = t0; t < t1; ++t) {
+      uint32_t n = 0;
+      if (fo.ok[t] && (int)fo.nhits[t] >= P->min_track_hits) {
+        const uint32_t key = track_key(fo.nhits[t], t);
+        const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
+        const int32_t* H = fo.hits + (size_t)t * NROW;
+        uint8_t* KR = fo.krow + (size_t)t * NROW;
+        for (int r0 = lo; r0 <= hi; r0 += 64) {
+          const int r = r0 + (int)lane;
+          bool kept = false;
+          if (r <= hi) {
+            const int32_t c = H[r];
+            kept = c >= 0 && (uint32_t)c < n_cl_cap && owner[c] == key;
+          }
+          const uint64_t m = __ballot(kept);
+          if (kept) KR[n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)r;
+          n += (uint32_t)__popcll(m);
         }
-        const uint64_t m = __ballot(kept);
-        if (kept) KR[n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)r;
-        n += (uint32_t)__popcll(m);
+        if ((int)n < P->min_track_hits) n = 0;
       }
-      if ((int)n < P->min_track_hits) n = 0;
+      if (lane == t - t0) mine = n;
     }
-    if (lane == 0) {
-      nkept[t] = (uint16_t)n;
-      key[t] = (uint8_t)n;  // sort key of the refit (n <= NROW)
+    if (t0 + lane < t1) {
+      nkept[t0 + lane] = (uint16_t)mine;
+      key[t0 + lane] = (uint8_t)mine;  // sort key of the refit (n <= NROW)
     }
   }
 }
