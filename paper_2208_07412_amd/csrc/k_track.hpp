@@ -867,6 +867,20 @@ __device__ __forceinline__ uint32_t track_key(uint32_t nh, uint32_t t) {
 // of the tracklet's hit table (contiguous), so every table read is coalesced.
 // The tracklet index is made wave-uniform so its scalars load once.
 
+#define KEEP_GROUP 16  // consecutive tracklets per wave of the claim and keep kernels
+
+// Lane k of a wave loads what the claim and keep need of tracklet t0 + k
+// (t0 + k < t1): 1 | hit count << 8 | row range << 16 for a tracklet that bids
+// (followed, at least min_track_hits hits), else 0.  Read back per tracklet
+// with a lane read, so the fields come in one coalesced load per array.
+__device__ __forceinline__ uint32_t bid_info(const FollowOut& fo, uint32_t t0, uint32_t t1,
+                                             int min_hits) {
+  const uint32_t t = t0 + (threadIdx.x & 63);
+  if (t >= t1 || !fo.ok[t]) return 0u;
+  const uint32_t nh = fo.nhits[t];
+  return (int)nh >= min_hits ? 1u | (nh << 8) | ((uint32_t)fo.range[t] << 16) : 0u;
+}
+
 // Every followed tracklet with enough hits bids for its clusters: the owner
 // of a cluster is the largest key among its bidders.  Two launches instead of
 // one atomicMax per hit: FIX = false stores every bidder's key (one of them
@@ -884,27 +898,33 @@ __global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_t
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const uint32_t lane = threadIdx.x & 63;
+  const uint32_t n_grp = (n_tl + KEEP_GROUP - 1) / KEEP_GROUP;
   uint32_t nw;
-  for (uint32_t i = xcd_wave_item(n_tl, nw); i < n_tl; i += nw) {
+  for (uint32_t i = xcd_wave_item(n_grp, nw); i < n_grp; i += nw) {
     // the stores go in descending tracklet order, so that of two bidders with
     // equal hit counts the one that wins (the lower index) tends to store
     // last (a store order sorted by key wins more clusters at once but loses
     // the locality of neighbouring tracklets and costs more than it saves)
-    const uint32_t t = FIX ? i : n_tl - 1 - i;
-    if (!fo.ok[t] || (int)fo.nhits[t] < P->min_track_hits) continue;
-    const uint32_t key = track_key(fo.nhits[t], t);
-    const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
-    const int32_t* H = fo.hits + (size_t)t * NROW;
-    for (int r = lo + (int)lane; r <= hi; r += 64) {
-      const int32_t c = H[r];
-      if (c < 0 || (uint32_t)c >= n_cl_cap) continue;
-      if (!FIX) owner[c] = key;
-      else if (owner[c] < key) atomicMax(&owner[c], key);
+    const uint32_t g = FIX ? i : n_grp - 1 - i;
+    const uint32_t t0 = g * KEEP_GROUP, t1 = min(t0 + KEEP_GROUP, n_tl);
+    const uint32_t info = bid_info(fo, t0, t1, P->min_track_hits);
+    for (uint32_t k = 0; k < t1 - t0; ++k) {
+      const uint32_t kk = FIX ? k : t1 - t0 - 1 - k;
+      const uint32_t inf = (uint32_t)__builtin_amdgcn_readlane((int)info, (int)kk);
+      if (!inf) continue;
+      const uint32_t t = t0 + kk;
+      const uint32_t key = track_key((inf >> 8) & 255, t);
+      const int lo = (inf >> 16) & 255, hi = inf >> 24;
+      const int32_t* H = fo.hits + (size_t)t * NROW;
+      for (int r = lo + (int)lane; r <= hi; r += 64) {
+        const int32_t c = H[r];
+        if (c < 0 || (uint32_t)c >= n_cl_cap) continue;
+        if (!FIX) owner[c] = key;
+        else if (owner[c] < key) atomicMax(&owner[c], key);
+      }
     }
   }
 }
-
-#define KEEP_GROUP 16  // tracklets per wave of k_keep
 
 // Hits each track keeps after the claims; < min_track_hits drops the track.
 // The kept count is also the refit's sort key: the refit takes the tracks
@@ -926,11 +946,13 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
   for (uint32_t g = xcd_wave_item(n_grp, nw); g < n_grp; g += nw) {
     const uint32_t t0 = g * KEEP_GROUP, t1 = min(t0 + KEEP_GROUP, n_tl);
     uint32_t mine = 0;
+    const uint32_t info = bid_info(fo, t0, t1, P->min_track_hits);
     for (uint32_t t = t0; t < t1; ++t) {
       uint32_t n = 0;
-      if (fo.ok[t] && (int)fo.nhits[t] >= P->min_track_hits) {
-        const uint32_t key = track_key(fo.nhits[t], t);
-        const int lo = fo.range[t] & 255, hi = fo.range[t] >> 8;
+      const uint32_t inf = (uint32_t)__builtin_amdgcn_readlane((int)info, (int)(t - t0));
+      if (inf) {
+        const uint32_t key = track_key((inf >> 8) & 255, t);
+        const int lo = (inf >> 16) & 255, hi = inf >> 24;
         const int32_t* H = fo.hits + (size_t)t * NROW;
         uint8_t* KR = fo.krow + (size_t)t * NROW;
         for (int r0 = lo; r0 <= hi; r0 += 64) {
