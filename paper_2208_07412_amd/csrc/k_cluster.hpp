@@ -44,6 +44,11 @@ struct ClusterOut {
 // (unit,row); rows are time-sorted.  Each thread takes 8 consecutive keys
 // per step (one 16-byte load when the key array is 16-byte aligned; the
 // aligned block never crosses a page, and keys outside the row are masked).
+// A key writes the entries of the blocks between its predecessor's and its
+// own; with USE_LDS, when the row's table fits (BI_LDS entries), these writes
+// go to LDS and the table is copied out in one coalesced pass (worth it where
+// keys are sparse in time, as clusters are: ~9 entries per key, against
+// one per 16 keys for the samples).
 __device__ __forceinline__ void bi_sample(uint32_t s, uint32_t t, int32_t prev, uint32_t s1,
                                           uint32_t nblk, uint32_t bshift, uint32_t* b,
                                           DevStatus* st) {
@@ -56,6 +61,8 @@ __device__ __forceinline__ void bi_sample(uint32_t s, uint32_t t, int32_t prev, 
   if (cur < prev) latch(st, TPC_ERR_INPUT);
 }
 
+#define BI_LDS 6144
+template <bool USE_LDS>
 __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict__ tkey,
                                                      const uint16_t* __restrict__ pkey,
                                                      const uint32_t* __restrict__ rstart,
@@ -64,16 +71,27 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
                                                      uint32_t* __restrict__ blk,
                                                      const DevParams* __restrict__ P,
                                                      DevStatus* st, int check_input) {
+  __shared__ uint32_t lt[USE_LDS ? BI_LDS : 1];
   if (failed(st)) return;
   const bool vec = ((uintptr_t)tkey & 15) == 0 && (!check_input || ((uintptr_t)pkey & 15) == 0);
+  const bool staged = USE_LDS && nblk + 1 <= BI_LDS;
   for (uint32_t ur = blockIdx.x; ur < n_ur; ur += gridDim.x) {
     uint32_t s0 = rstart[ur], s1 = rstart[ur + 1];
     if (s1 > n_total) s1 = n_total;
     if (s0 > s1) s0 = s1;
-    uint32_t* b = blk + (size_t)ur * (nblk + 1);
+    uint32_t* const bg = blk + (size_t)ur * (nblk + 1);
     if (s0 == s1) {
-      for (uint32_t k = threadIdx.x; k <= nblk; k += blockDim.x) b[k] = s0;
+      for (uint32_t k = threadIdx.x; k <= nblk; k += blockDim.x) bg[k] = s0;
       continue;
+    }
+    // the row's table: in LDS (every entry preset to the row start, so an
+    // unsorted row, which is reported, leaves no stale entry) or in place
+    uint32_t* b = bg;
+    if (staged) {
+      __syncthreads();  // the previous row's copy-out has read lt
+      for (uint32_t k = threadIdx.x; k <= nblk; k += blockDim.x) lt[k] = s0;
+      __syncthreads();
+      b = lt;
     }
     const int np = P->np[ur % NROW];
     const bool validate = check_input && P->validate;
@@ -124,6 +142,10 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
           pp = p;
         }
       }
+    }
+    if (staged) {
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k <= nblk; k += blockDim.x) bg[k] = lt[k];
     }
   }
 }

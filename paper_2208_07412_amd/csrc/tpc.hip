@@ -381,9 +381,9 @@ int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
   hipStream_t s = c->stream;
   {
     StageTimer tm(c, 0);
-    k_block_index<<<n_ur, 256, 0, s>>>(in->time, in->pad, in->row_start, n_ur, nblk_s, CL_BSHIFT,
-                                       in->n_time_bins, in->n_samples, c->zblk, c->d_par, c->d_st,
-                                       1);
+    k_block_index<false><<<n_ur, 256, 0, s>>>(in->time, in->pad, in->row_start, n_ur, nblk_s,
+                                              CL_BSHIFT, in->n_time_bins, in->n_samples, c->zblk,
+                                              c->d_par, c->d_st, 1);
   }
   ClusterOut co{out->capacity, out->y_fx, out->z_fx, out->dpad, out->dtime, out->s2pad, out->s2time,
                 out->qtot, out->qmax, out->ppad, out->ptime, out->flags, out->sp, out->st,
@@ -421,7 +421,7 @@ int stage_grid(tpc_ctx* c, const tpc_clusters* cl) {
   const uint32_t n_ur = cl->n_units * NROW;
   const uint32_t nblk = ceil_div(cl->n_time_bins, 1u << CG_BSHIFT);
   StageTimer tm(c, 4);
-  k_block_index<<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk,
+  k_block_index<true><<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk,
                                              CG_BSHIFT,
                                              cl->n_time_bins, cl->capacity, c->cblk, c->d_par,
                                              c->d_st, 0);
