@@ -200,28 +200,30 @@ __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32
   }
 }
 
-// Reciprocal links.
+// Reciprocal links.  Also flags the start clusters of chains (no cleaned
+// down-link, a cleaned up-link) in a byte per cluster, which the scan that
+// lists them reads.
 __global__ void k_ca_clean(const int32_t* __restrict__ down, const int32_t* __restrict__ up,
                            int32_t* __restrict__ downc, int32_t* __restrict__ upc,
-                           const uint32_t* n_dev, uint32_t n_cap, const DevStatus* st) {
+                           uint8_t* __restrict__ start, const uint32_t* n_dev, uint32_t n_cap,
+                           const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n = scan_count(n_dev, n_cap);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int32_t u = up[i], d = down[i];
-    upc[i] = (u >= 0 && (uint32_t)u < n && down[u] == (int32_t)i) ? u : -1;
-    downc[i] = (d >= 0 && (uint32_t)d < n && up[d] == (int32_t)i) ? d : -1;
+    const int32_t uc = (u >= 0 && (uint32_t)u < n && down[u] == (int32_t)i) ? u : -1;
+    const int32_t dc = (d >= 0 && (uint32_t)d < n && up[d] == (int32_t)i) ? d : -1;
+    upc[i] = uc;
+    downc[i] = dc;
+    start[i] = (uint8_t)(dc == -1 && uc != -1);
   }
 }
 
-// Start clusters of chains (no cleaned down-link, a cleaned up-link), listed
-// in ascending order by a scan so that the chain walks below run one lane
-// per start on dense waves.
+// Start clusters of chains, listed in ascending order by a scan so that the
+// chain walks below run one lane per start on dense waves.
 struct GetStart {
-  const int32_t* downc;
-  const int32_t* upc;
-  __device__ uint32_t operator()(uint32_t i) const {
-    return (downc[i] == -1 && upc[i] != -1) ? 1u : 0u;
-  }
+  const uint8_t* start;
+  __device__ uint32_t operator()(uint32_t i) const { return start[i]; }
 };
 struct EmitStart {
   uint32_t* cand;

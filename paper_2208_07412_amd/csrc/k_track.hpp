@@ -412,12 +412,11 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
   return best;
 }
 
-// Middle and end cluster of every tracklet (walk of its cleaned up-links) and
-// the unit-row of its start; 0xFFFFFFFF marks a tracklet that cannot be
-// followed (broken chain or rows beyond the last).
-// Per tracklet: its middle and end clusters, its start unit-row, and the
-// sort key of the outward following pass: the rows above its start row (the
-// most rows that pass can take), 0 if it cannot be followed.
+// Per tracklet (a walk of its cleaned up-links): its middle and end clusters
+// (0xFFFFFFFF for a tracklet that cannot be followed: broken chain or rows
+// beyond the last), its start unit-row, and the sort key of the outward
+// following pass: the rows above its start row (the most rows that pass can
+// take), 0 if it cannot be followed.
 __global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_t n_ur,
                                                          const int32_t* __restrict__ upc,
                                                          const uint32_t* __restrict__ tl_start,
@@ -867,7 +866,7 @@ __device__ __forceinline__ uint32_t track_key(uint32_t nh, uint32_t t) {
 // of the tracklet's hit table (contiguous), so every table read is coalesced.
 // The tracklet index is made wave-uniform so its scalars load once.
 
-#define KEEP_GROUP 16  // consecutive tracklets per wave of the claim and keep kernels
+#define KEEP_GROUP 8  // consecutive tracklets per wave of the claim and keep kernels
 
 // Lane k of a wave loads what the claim and keep need of tracklet t0 + k
 // (t0 + k < t1): 1 | hit count << 8 | row range << 16 for a tracklet that bids

@@ -63,6 +63,7 @@ struct tpc_ctx {
   uint32_t* tot32 = nullptr;
   uint16_t* chain_len = nullptr;  // per listed chain start
   uint32_t* cand = nullptr;       // chain starts, ascending
+  uint8_t* start_flag = nullptr;  // 1 where a chain starts (per cluster)
   int32_t* f_hits = nullptr;
   float* f_state = nullptr;
   uint16_t* f_nhits = nullptr;
@@ -107,7 +108,7 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
+  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
   uint32_t nblk, nblk_s, nwin;
@@ -137,6 +138,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.tot32 = L.add<uint32_t>(2);
   p.chain_len = L.add<uint16_t>(mc / 2 + 1);
   p.cand = L.add<uint32_t>(mc / 2 + 1);
+  p.start_flag = L.add<uint8_t>(mc);
   p.f_hits = L.add<int32_t>(mt * NROW);
   p.f_state = L.add<float>(mt * 6);
   p.f_nhits = L.add<uint16_t>(mt);
@@ -444,11 +446,12 @@ int stage_tracklets(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l, tpc_trackl
   const uint32_t cap = cl->capacity;
   const uint32_t g = grid_for(cap, 256);
   StageTimer tm(c, 6);
-  k_ca_clean<<<g, 256, 0, s>>>(l->down, l->up, l->downc, l->upc, cl->n_clusters, cap, c->d_st);
+  k_ca_clean<<<g, 256, 0, s>>>(l->down, l->up, l->downc, l->upc, c->start_flag, cl->n_clusters, cap,
+                               c->d_st);
   // chain starts (at most one per two clusters: chains are disjoint and have
   // at least two), their chain lengths, then the tracklets in start order
   const uint32_t capc = cap / 2 + 1;
-  run_scan<uint32_t>(c, GetStart{l->downc, l->upc}, EmitStart{c->cand, capc}, cl->n_clusters, cap,
+  run_scan<uint32_t>(c, GetStart{c->start_flag}, EmitStart{c->cand, capc}, cl->n_clusters, cap,
                      (uint32_t*)nullptr, c->tot32);
   k_chain_len<<<grid_for(capc, 256), 256, 0, s>>>(c->cand, c->tot32, capc, l->upc, cl->n_clusters,
                                                   cap, c->chain_len, c->d_par, c->d_st);
@@ -675,6 +678,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->tot32 = (uint32_t*)(base + pl.tot32);
   c->chain_len = (uint16_t*)(base + pl.chain_len);
   c->cand = (uint32_t*)(base + pl.cand);
+  c->start_flag = (uint8_t*)(base + pl.start_flag);
   c->f_hits = (int32_t*)(base + pl.f_hits);
   c->f_state = (float*)(base + pl.f_state);
   c->f_nhits = (uint16_t*)(base + pl.f_nhits);
