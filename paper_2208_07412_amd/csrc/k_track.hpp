@@ -866,7 +866,7 @@ __device__ __forceinline__ uint32_t track_key(uint32_t nh, uint32_t t) {
 // of the tracklet's hit table (contiguous), so every table read is coalesced.
 // The tracklet index is made wave-uniform so its scalars load once.
 
-#define KEEP_GROUP 8  // consecutive tracklets per wave of the claim and keep kernels
+#define KEEP_GROUP 4  // consecutive tracklets per wave of the claim and keep kernels
 
 // Lane k of a wave loads what the claim and keep need of tracklet t0 + k
 // (t0 + k < t1): 1 | hit count << 8 | row range << 16 for a tracklet that bids
