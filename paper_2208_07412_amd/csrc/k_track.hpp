@@ -661,10 +661,11 @@ __device__ __forceinline__ bool follow_start_b(FollowLane& f, const ClusterView&
 }
 
 __device__ __forceinline__ void follow_finish(const FollowLane& f, FollowOut& fo) {
-  float* S = fo.state + (size_t)f.t * 6;
-#pragma unroll
-  for (int i = 0; i < 5; ++i) S[i] = f.sp[i];
-  S[5] = (float)f.rs;
+  // six floats per tracklet at 8-byte alignment: three 8-byte stores
+  float2* S = reinterpret_cast<float2*>(fo.state + (size_t)f.t * 6);
+  S[0] = make_float2(f.sp[0], f.sp[1]);
+  S[1] = make_float2(f.sp[2], f.sp[3]);
+  S[2] = make_float2(f.sp[4], (float)f.rs);
   fo.nhits[f.t] = (uint16_t)f.nh;
   fo.range[f.t] = (uint16_t)(f.lo | (f.hi << 8));
   fo.ok[f.t] = 1;
@@ -738,10 +739,14 @@ __device__ __forceinline__ void follow_resume(FollowLane& f, uint32_t t, const C
   f.ubase = urA - (uint32_t)f.r1;
   f.L = tl_len[t];
   f.anchor = cl.pos[tl_start[t]].y;
-  const float* S = fo.state + (size_t)t * 6;
-#pragma unroll
-  for (int i = 0; i < 5; ++i) f.sp[i] = S[i];
-  f.rs = (int)S[5];
+  const float2* S = reinterpret_cast<const float2*>(fo.state + (size_t)t * 6);
+  const float2 s01 = S[0], s23 = S[1], s4r = S[2];
+  f.sp[0] = s01.x;
+  f.sp[1] = s01.y;
+  f.sp[2] = s23.x;
+  f.sp[3] = s23.y;
+  f.sp[4] = s4r.x;
+  f.rs = (int)s4r.y;
   f.nh = fo.nhits[t];
   f.hi = fo.range[t] >> 8;
   f.ctl = -1;
