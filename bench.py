@@ -220,7 +220,7 @@ def stress_leg(torch, tpcsynth, tpc, stream, n_coll=20):
                 samples=ev.n_samples, clusters=c["n_clusters"], tracks=c["n_tracks"],
                 fp64_refits=c["n_fallback"], fp64_rate=c["n_fallback"] / max(c["n_tracks"], 1),
                 fp64_not_pd=c["n_fallback_fail"], flagged_not_pd=c["n_not_pd"],
-                refit_ms=ms["refit"], fp64_list_ms=ms["refit_fp64_list"],
+                refit_ms=ms["refit"], fp64_count_ms=ms["fp64_count"],
                 total_ms=sum(ms.values()))
 
 

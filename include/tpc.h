@@ -238,7 +238,7 @@ void* tpc_stream(tpc_ctx* ctx);
  * (peak finding and moments, one pass over the samples), 2 cluster scan,
  * 3 cluster output, 4 cluster grid, 5 neighbours, 6 tracklets (and their
  * seed points, timed inside the fit call), 7 following (sorts and passes),
- * 8 resolution, 9 refit (FP64 head, FP32, FP64 redo), 10 listing of the FP64
+ * 8 resolution, 9 refit (FP64 head, FP32, FP64 redo), 10 count of the FP64
  * redos, 11 track output. */
 #define TPC_PROF_STAGES 12
 int tpc_profile_enable(tpc_ctx* ctx, int on);

@@ -49,7 +49,7 @@ struct DevStatus {
   uint32_t required;
   uint32_t n_clusters, n_tracklets, n_tracks, n_hits;
   uint32_t n_fallback, n_fallback_fail, n_not_pd, n_refit_fail;
-  uint32_t n_fb_list;
+  uint32_t n_fp64_redo;
   uint32_t pad_[5];
   unsigned long long f_steps, f_cands, f_upds;  // following work (measurement)
 };

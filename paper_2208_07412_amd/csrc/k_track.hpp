@@ -1188,16 +1188,10 @@ __global__ __launch_bounds__(64) void k_refit(ClusterView cl, const uint32_t* __
   }
 }
 
-// The tracks refit in FP64, in tracklet order (counted for the status).
+// The tracks refit in FP64 (counted for the status).
 struct GetToFp64 {
   const uint8_t* flags;
   __device__ uint32_t operator()(uint32_t t) const { return (flags[t] & TF_TO_FP64) ? 1u : 0u; }
-};
-struct EmitFbList {
-  uint32_t* list;
-  __device__ void operator()(uint32_t t, uint32_t pos, uint32_t v) const {
-    if (v) list[pos] = t;
-  }
 };
 
 // final keep flag of a tracklet slot
@@ -1244,7 +1238,7 @@ __global__ void k_track_totals(const unsigned long long* total, TrackOut to, uin
   const uint32_t nt = (uint32_t)(v >> 32), nh = (uint32_t)v;
   st->n_tracks = nt;
   st->n_hits = nh;
-  st->n_fallback = st->n_fb_list;
+  st->n_fallback = st->n_fp64_redo;
   if (n_tracks) *n_tracks = nt;
   if (n_hits) *n_hits = nh;
   if (nt > to.capacity) latch(st, TPC_ERR_CAPACITY, nt);

@@ -80,7 +80,6 @@ struct tpc_ctx {
   uint16_t* nkept = nullptr;
   float *r_par = nullptr, *r_cov = nullptr, *r_chi2 = nullptr;
   uint8_t *r_row = nullptr, *r_flags = nullptr;
-  uint32_t* fb_list = nullptr;
   uint32_t* trk_index = nullptr;
   uint32_t* hit_off = nullptr;
   size_t bsum_cap = 0;
@@ -109,7 +108,7 @@ struct Layout {
 
 struct Plan {
   size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
-      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, fb_list, trk_index, hit_off, par, st, total;
+      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, hit_off, par, st, total;
   size_t bsum_cap;
   uint32_t nblk, nblk_s, nwin;
 };
@@ -158,7 +157,6 @@ Plan plan_for(const tpc_sizes& m) {
   p.r_chi2 = L.add<float>(mt);
   p.r_row = L.add<uint8_t>(mt);
   p.r_flags = L.add<uint8_t>(mt);
-  p.fb_list = L.add<uint32_t>(mt);
   p.trk_index = L.add<uint32_t>(mt);
   p.hit_off = L.add<uint32_t>(mt);
   p.par = L.add<DevParams>(1);
@@ -261,6 +259,16 @@ void run_scan(tpc_ctx* c, Get get, Emit emit, const uint32_t* n_dev, uint32_t n_
   k_scan_reduce<T, Get><<<nb, SCAN_BLOCK, 0, c->stream>>>(get, n_dev, n_cap, bs, c->d_st);
   k_scan_blocks<T><<<1, 1024, 0, c->stream>>>(bs, nb, total, total32, c->d_st);
   k_scan_down<T, Get, Emit><<<nb, SCAN_BLOCK, 0, c->stream>>>(get, emit, n_dev, n_cap, bs, c->d_st);
+}
+
+// The total alone (the reduce half of run_scan).
+template <typename T, typename Get>
+void run_count(tpc_ctx* c, Get get, const uint32_t* n_dev, uint32_t n_cap, uint32_t* total32) {
+  uint32_t nb = ceil_div(n_cap, SCAN_TILE);
+  if (nb < 1) nb = 1;
+  T* bs = reinterpret_cast<T*>(c->bsum);
+  k_scan_reduce<T, Get><<<nb, SCAN_BLOCK, 0, c->stream>>>(get, n_dev, n_cap, bs, c->d_st);
+  k_scan_blocks<T><<<1, 1024, 0, c->stream>>>(bs, nb, (T*)nullptr, total32, c->d_st);
 }
 
 struct GetU32 {
@@ -564,9 +572,9 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 10);
-    // the tracks the refit redid in FP64 (listed, and counted for the status)
-    run_scan<uint32_t>(c, GetToFp64{ro.flags}, EmitFbList{c->fb_list}, t->n_tracklets, tcap,
-                       (uint32_t*)nullptr, &c->d_st->n_fb_list);
+    // the tracks the refit redid in FP64, counted for the status (a reduction,
+    // not one same-address atomic per track)
+    run_count<uint32_t>(c, GetToFp64{ro.flags}, t->n_tracklets, tcap, &c->d_st->n_fp64_redo);
   }
   StageTimer tm(c, 11);
   run_scan<unsigned long long>(c, GetTrackPair{c->nkept, ro}, EmitTrackPair{c->trk_index, c->hit_off, c->f_perm, tcap},
@@ -698,7 +706,6 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->r_chi2 = (float*)(base + pl.r_chi2);
   c->r_row = (uint8_t*)(base + pl.r_row);
   c->r_flags = (uint8_t*)(base + pl.r_flags);
-  c->fb_list = (uint32_t*)(base + pl.fb_list);
   c->trk_index = (uint32_t*)(base + pl.trk_index);
   c->hit_off = (uint32_t*)(base + pl.hit_off);
   c->d_par = (DevParams*)(base + pl.par);
@@ -840,7 +847,7 @@ int tpc_profile_read(tpc_ctx* c, double* ms, uint32_t* launches) {
 const char* tpc_profile_stage_name(int i) {
   static const char* names[TPC_PROF_STAGES] = {
       "sample_index", "cluster_peaks", "cluster_scan", "cluster_output", "cluster_grid",
-      "neighbours", "tracklets", "following", "resolution", "refit", "refit_fp64_list",
+      "neighbours", "tracklets", "following", "resolution", "refit", "fp64_count",
       "track_output"};
   return (i >= 0 && i < TPC_PROF_STAGES) ? names[i] : "unknown";
 }
