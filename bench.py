@@ -46,7 +46,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes each stage must move, per unit of work (see DESIGN.md):
+# Algorithmic bytes each stage must move, per unit of work:
 # samples are (pad, time, adc) u16; a cluster record is y_fx, z_fx (i32),
 # pad, time, s2pad, s2time (f32), qtot, qmax, ppad, ptime (u16), flags (u8).
 def stage_bytes(ns, nc, n_ur, T, W=24):
@@ -246,7 +246,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} not supported; the reconstruction path runs on one "
-              "GPU (frames shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+              "GPU (time frames are independent and would shard across GPUs with no exchange)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

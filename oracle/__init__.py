@@ -1,8 +1,8 @@
 """CPU oracle of the TPC reconstruction chain -- TEST INFRASTRUCTURE ONLY.
 
 A plain, double-precision C implementation (``oracle/oracle.c``) of every
-step of the reconstruction path, written from the reading of the paper that
-the design doc records, plus this ctypes wrapper.  Only ``tests/``,
+step of the reconstruction path, written from the paper's description of it
+and the readings stated in ``oracle.c``'s header, plus this ctypes wrapper.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
 import it.  It shares no code with the GPU library
 (``paper_2208_07412_amd``), and the GPU library never calls it.

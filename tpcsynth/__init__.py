@@ -8,8 +8,8 @@ consume its arrays; it holds none of the reconstruction arithmetic
 The paper (Hardware and data flow; Software) says the TPC data of complete
 collisions is zero-suppressed on the readout FPGA and reconstructed on the
 EPN GPUs, but specifies no detector model or event shapes.  The model used
-here (geometry, drift, charge, noise, kinematics) is stated in DESIGN.md's
-input recipe and in ``tpcsynth/csrc/synth.c``.
+here (geometry, drift, charge, noise, kinematics) is stated in
+``tpcsynth/csrc/synth.c``.
 
 Layout of a generated ZS input (all numpy, host memory)::
 
