@@ -321,6 +321,27 @@ def main():
     stages = {k: v[0] / 3 for k, v in prof.items()}  # per reconstruction
     log("[bench] stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
 
+    # quality-control histograms of the slice's outputs (HIP events on the
+    # library's stream); algorithmic bytes: qtot, qmax (2 + 2) and
+    # cluster_track (4) per cluster, hit_start (4) per track
+    qc_hist = torch.empty(tpc.QC_BINS, dtype=torch.int32, device=dev)
+    with torch.cuda.stream(stream):
+        reco.qc_histograms(cl, tr, qc_hist)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            reco.qc_histograms(cl, tr, qc_hist)
+        e1.record(stream)
+    reco.sync()
+    qc_ms = e0.elapsed_time(e1) / 10
+    n_trk = int(tr["n_tracks"].item())
+    qc_bytes = 8 * nc + 4 * (n_trk + 1)
+    qc = dict(ms=qc_ms, bytes=qc_bytes, gb_per_s=qc_bytes / qc_ms / 1e6,
+              hbm_frac=qc_bytes / qc_ms / 1e6 / 8000.0,
+              clusters=int(qc_hist[tpc.QC_QTOT:tpc.QC_QTOT + 256].sum().item()),
+              tracks=int(qc_hist[tpc.QC_NHITS:tpc.QC_NHITS + 153].sum().item()))
+    log(f"[bench] qc histograms: {qc}")
+
     # the batched form: one context over the whole slice, or the slice's units
     # cut into n slices on n streams (pipeline.Pipeline), each captured as one
     # graph; the fastest form is the one timed
@@ -424,7 +445,7 @@ def main():
                            if graph is not None else "eager",
                            slices=n_slices, slice_start=start_pt, slice_ms=form_ms,
                            samples=ns, clusters=nc, tracks=counts["n_tracks"]),
-               roofline=roofline, roofline_2=roofline_2, stages_ms=stages)
+               roofline=roofline, roofline_2=roofline_2, stages_ms=stages, qc=qc)
     if tuning is not None:
         out["tuning"] = tuning["chosen"]
     del graph, forms

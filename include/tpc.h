@@ -11,6 +11,8 @@
  *   tpc_build_tracklets    links -> cleaned links + tracklets
  *   tpc_fit_tracks         tracklets -> followed, resolved, refitted tracks
  *   tpc_process_timeframe  all four in one launch sequence
+ * and, beside them, tpc_qc_histograms (quality-control histograms of the
+ * outputs).
  *
  * Conventions
  *   - Every array pointer inside the structs below is a DEVICE pointer,
@@ -219,6 +221,26 @@ int tpc_fit_tracks(tpc_ctx* ctx, const tpc_clusters* cl, const tpc_links* links,
 /* The four stages in one launch sequence on the context's stream. */
 int tpc_process_timeframe(tpc_ctx* ctx, const tpc_zs_input* in, tpc_clusters* cl,
                           tpc_links* links, tpc_tracklets* tl, tpc_tracks* tr);
+
+/* Quality-control histograms of a reconstruction's outputs (section
+ * "Software": the synchronous processing also validates the detector data in
+ * real time; the paper names no quantities, so these are chosen here).
+ * hist: DEVICE array of TPC_QC_BINS uint32 counts, caller-owned, overwritten:
+ *   [TPC_QC_QTOT,   +256)  clusters by total charge, bin min(qtot >> 3, 255)
+ *   [TPC_QC_QMAX,   +256)  clusters by peak charge, bin min(qmax >> 2, 255)
+ *   [TPC_QC_NHITS,  +153)  tracks by hit count (hit_start[j+1] - hit_start[j])
+ *   [TPC_QC_ATTACH, +2)    clusters with cluster_track -1 / >= 0
+ * Reads cl->qtot, cl->qmax, tr->cluster_track over *cl->n_clusters clusters
+ * and tr->hit_start over *tr->n_tracks tracks (device counts, limited to the
+ * capacities).  Enqueued on the context's stream behind the reconstruction;
+ * after a latched error every count is 0.  TPC_ERR_ARG for a missing
+ * pointer. */
+#define TPC_QC_QTOT 0
+#define TPC_QC_QMAX 256
+#define TPC_QC_NHITS 512
+#define TPC_QC_ATTACH 665
+#define TPC_QC_BINS 667
+int tpc_qc_histograms(tpc_ctx* ctx, const tpc_clusters* cl, const tpc_tracks* tr, uint32_t* hist);
 
 /* Wait for the stream, then report the first latched error and the counts.
  * Clears the status word for the next call. */

@@ -298,3 +298,28 @@ def is_pd(C) -> bool:
     lib = _load()
     c = np.ascontiguousarray(np.asarray(C, np.float64).reshape(25))
     return bool(lib.oracle_is_pd(_p(c)))
+
+
+# ---------------------------------------------------------------- QC
+QC_QTOT, QC_QMAX, QC_NHITS, QC_ATTACH, QC_BINS = 0, 256, 512, 665, 667
+
+
+def qc_histograms(qtot, qmax, cluster_track, hit_start) -> np.ndarray:
+    """Quality-control histograms of a reconstruction's outputs.  The paper
+    (section "Software") says the synchronous processing validates the
+    detector data in real time but names no quantities; these are chosen
+    here: clusters by total charge (bin min(qtot >> 3, 255)), by peak charge
+    (bin min(qmax >> 2, 255)), tracks by hit count (hit_start[j+1] -
+    hit_start[j], 0..152) and clusters off / on a track (cluster_track -1 /
+    >= 0), at the bin offsets QC_QTOT, QC_QMAX, QC_NHITS, QC_ATTACH."""
+    qtot = np.asarray(qtot, np.int64)
+    qmax = np.asarray(qmax, np.int64)
+    ct = np.asarray(cluster_track, np.int64)
+    hs = np.asarray(hit_start, np.int64)
+    h = np.zeros(QC_BINS, np.int64)
+    h[QC_QTOT:QC_QTOT + 256] = np.bincount(np.minimum(qtot >> 3, 255), minlength=256)
+    h[QC_QMAX:QC_QMAX + 256] = np.bincount(np.minimum(qmax >> 2, 255), minlength=256)
+    h[QC_NHITS:QC_NHITS + NROW + 1] = np.bincount(np.minimum(np.diff(hs), NROW),
+                                                  minlength=NROW + 1)
+    h[QC_ATTACH:QC_ATTACH + 2] = np.bincount((ct >= 0).astype(np.int64), minlength=2)
+    return h

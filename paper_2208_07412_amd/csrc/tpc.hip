@@ -17,6 +17,7 @@
 #include "k_cluster.hpp"
 #include "k_links.hpp"
 #include "k_track.hpp"
+#include "k_qc.hpp"
 
 namespace {
 
@@ -82,6 +83,7 @@ struct tpc_ctx {
   uint8_t *r_row = nullptr, *r_flags = nullptr;
   uint32_t* trk_index = nullptr;
   uint32_t* hit_off = nullptr;
+  uint32_t* qc_part = nullptr;   // per-workgroup QC histograms
   size_t bsum_cap = 0;
   tpc_tuning tune;
   // stage timing (measurement only)
@@ -108,7 +110,7 @@ struct Layout {
 
 struct Plan {
   size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
-      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, hit_off, par, st, total;
+      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, hit_off, par, st, total;
   size_t bsum_cap;
   uint32_t nblk, nblk_s, nwin;
 };
@@ -159,6 +161,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.r_flags = L.add<uint8_t>(mt);
   p.trk_index = L.add<uint32_t>(mt);
   p.hit_off = L.add<uint32_t>(mt);
+  p.qc_part = L.add<uint32_t>((uint64_t)QC_WG * QC_BINS);
   p.par = L.add<DevParams>(1);
   p.st = L.add<DevStatus>(1);
   p.total = (L.off + 255) & ~(size_t)255;
@@ -708,6 +711,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->r_flags = (uint8_t*)(base + pl.r_flags);
   c->trk_index = (uint32_t*)(base + pl.trk_index);
   c->hit_off = (uint32_t*)(base + pl.hit_off);
+  c->qc_part = (uint32_t*)(base + pl.qc_part);
   c->d_par = (DevParams*)(base + pl.par);
   c->d_st = (DevStatus*)(base + pl.st);
   c->bsum_cap = pl.bsum_cap;
@@ -765,6 +769,21 @@ int tpc_fit_tracks(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const
   int rc = stage_grid(c, cl);
   if (rc) return rc;
   return stage_fit(c, cl, l, t, tr);
+}
+
+static_assert(QC_BINS == TPC_QC_BINS && QC_QTOT == TPC_QC_QTOT && QC_QMAX == TPC_QC_QMAX &&
+                  QC_NHITS == TPC_QC_NHITS && QC_ATTACH == TPC_QC_ATTACH,
+              "QC histogram layout");
+
+int tpc_qc_histograms(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, uint32_t* hist) {
+  if (!c || !cl || !tr || !hist || !cl->n_clusters || !cl->qtot || !cl->qmax || !tr->n_tracks ||
+      !tr->hit_start || !tr->cluster_track)
+    return TPC_ERR_ARG;
+  k_qc_fill<<<QC_WG, 256, 0, c->stream>>>(cl->qtot, cl->qmax, tr->cluster_track, cl->n_clusters,
+                                          cl->capacity, tr->hit_start, tr->n_tracks,
+                                          tr->capacity, c->qc_part, c->d_st);
+  k_qc_sum<<<QC_BINS, 256, 0, c->stream>>>(c->qc_part, QC_WG, hist);
+  return launch_ok();
 }
 
 int tpc_process_timeframe(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* cl, tpc_links* l,

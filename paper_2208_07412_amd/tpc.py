@@ -88,8 +88,11 @@ EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_crea
            "tpc_destroy", "tpc_cluster", "tpc_find_neighbours", "tpc_build_tracklets",
            "tpc_fit_tracks", "tpc_process_timeframe", "tpc_sync", "tpc_stream",
            "tpc_status_string", "tpc_profile_enable", "tpc_profile_read",
-           "tpc_profile_stage_name", "tpc_tuning_default", "tpc_set_tuning", "tpc_get_tuning"]
+           "tpc_profile_stage_name", "tpc_tuning_default", "tpc_set_tuning", "tpc_get_tuning",
+           "tpc_qc_histograms"]
 PROF_STAGES = 12
+# quality-control histogram layout (bin offsets; see tpc_qc_histograms)
+QC_QTOT, QC_QMAX, QC_NHITS, QC_ATTACH, QC_BINS = 0, 256, 512, 665, 667
 
 
 def library_path() -> str:
@@ -116,6 +119,7 @@ def load():
     lib.tpc_build_tracklets.argtypes = [P, P, P, P]
     lib.tpc_fit_tracks.argtypes = [P, P, P, P, P]
     lib.tpc_process_timeframe.argtypes = [P, P, P, P, P, P]
+    lib.tpc_qc_histograms.argtypes = [P, P, P, P]
     lib.tpc_sync.argtypes = [P, P]
     lib.tpc_stream.argtypes = [P]
     lib.tpc_stream.restype = P
@@ -334,6 +338,19 @@ class Reco:
     def fit_tracks(self, cl: Buffers, links: Buffers, tl: Buffers, tr: Buffers):
         _check(self.lib.tpc_fit_tracks(self.ctx, ctypes.byref(cl.s), ctypes.byref(links.s),
                                        ctypes.byref(tl.s), ctypes.byref(tr.s)), "tpc_fit_tracks")
+
+    def qc_histograms(self, cl: Buffers, tr: Buffers, out=None):
+        """Quality-control histograms of a reconstruction's outputs (int32
+        device tensor of QC_BINS counts, laid out as QC_QTOT, QC_QMAX,
+        QC_NHITS, QC_ATTACH say), enqueued on the context's stream."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(QC_BINS, dtype=torch.int32, device=self.device)
+        if out.numel() < QC_BINS or out.dtype != torch.int32 or not out.is_cuda:
+            raise ValueError("qc_histograms: out must be an int32 device tensor of QC_BINS")
+        _check(self.lib.tpc_qc_histograms(self.ctx, ctypes.byref(cl.s), ctypes.byref(tr.s),
+                                          ctypes.c_void_p(out.data_ptr())), "tpc_qc_histograms")
+        return out
 
     def process(self, zs: dict, cl: Buffers, links: Buffers, tl: Buffers, tr: Buffers,
                 zs_s: Optional[TpcZsInput] = None):
