@@ -93,6 +93,18 @@ __device__ __forceinline__ uint32_t xcd_wave_item(uint32_t n, uint32_t& stride) 
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)(b * wpb + (threadIdx.x >> 6)));
 }
 
+// One item per thread over n items, in rounds of the grid's threads
+// (stride): this thread's first item, with the workgroups that the
+// dispatcher places on one XCD taking consecutive blocks of items.
+__device__ __forceinline__ uint32_t xcd_thread_item(uint32_t n, uint32_t& stride) {
+  const uint32_t nb = (n + blockDim.x - 1) / blockDim.x;
+  stride = gridDim.x * blockDim.x;
+  uint32_t b = blockIdx.x;
+  if (nb > gridDim.x) b = xcd_remap(b, gridDim.x);
+  else if (b < nb) b = xcd_remap(b, nb);
+  return b * blockDim.x + threadIdx.x;
+}
+
 // A value the whole wave holds alike, moved to a scalar register so that
 // the loop control and address arithmetic built on it stay scalar.
 __device__ __forceinline__ uint32_t uni(uint32_t v) {

@@ -244,7 +244,8 @@ __global__ void k_chain_len(const uint32_t* __restrict__ cand, const uint32_t* n
   if (failed(st)) return;
   const uint32_t n = scan_count(n_cand_dev, cand_cap);
   const uint32_t n_cl = scan_count(n_cl_dev, n_cl_cap);
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+  uint32_t dp;
+  for (uint32_t p = xcd_thread_item(n, dp); p < n; p += dp) {
     uint32_t L = 1;
     int32_t c = upc[cand[p]];
     while (c >= 0 && (uint32_t)c < n_cl && L < NROW) {

@@ -428,7 +428,8 @@ __global__ __launch_bounds__(256) void k_tracklet_points(ClusterView cl, uint32_
   if (failed(st)) return;
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const uint32_t n_cl = scan_count(cl.n_clusters, cl.capacity);
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tl; t += gridDim.x * blockDim.x) {
+  uint32_t dt;
+  for (uint32_t t = xcd_thread_item(n_tl, dt); t < n_tl; t += dt) {
     const uint32_t A = tl_start[t];
     const int L = tl_len[t];
     uint32_t M = 0xFFFFFFFFu, E = 0xFFFFFFFFu, urA = 0;
