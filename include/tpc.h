@@ -78,11 +78,9 @@ typedef struct {
   double c0r_y, c0r_z;    /* refit prior sigmas of y, z (5 cm: broad) */
   double c0r_snp, c0r_tgl, c0r_qpt; /* refit prior sigmas (0.5, 0.5, 10) */
   double refit_snp_max;   /* |sin phi| a refit step may not reach (0.999) */
-  double fp32_guard;      /* an FP32 refit update that leaves less than this
-                             fraction of a variance sends the track to the
-                             FP64 refit (0.1; 0 disables) */
   double sigma_y[TPC_NROW], sigma_z[TPC_NROW]; /* measurement errors [cm] */
-  int32_t validate;       /* 1: check input order and ranges on the device */
+  int32_t validate;       /* 1: check on the device that samples are sorted
+                             and that every ADC is in 1..1023 */
   int32_t force_fallback; /* 1: redo every refit in FP64 (test hook) */
 } tpc_params;
 
@@ -99,7 +97,10 @@ typedef struct {
 typedef struct {
   const uint16_t* pad;        /* [n_samples] pad index, < pads of the row */
   const uint16_t* time;       /* [n_samples] time bin, < n_time_bins */
-  const uint16_t* adc;        /* [n_samples] ADC value (10 bit) */
+  const uint16_t* adc;        /* [n_samples] ADC value, 1..1023 (10 bit; zero is
+                                 never stored).  Outside that range the result
+                                 is undefined unless params.validate is set,
+                                 which reports TPC_ERR_INPUT */
   const uint32_t* row_start;  /* [n_units*152 + 1] first sample of each (unit,row) */
   uint32_t n_samples;
   uint32_t n_units;
@@ -171,11 +172,21 @@ typedef struct {
   uint32_t n_fallback_fail;   /* FP64 refits still not PD (dropped) */
   uint32_t n_not_pd;          /* high-pT tracks flagged not PD */
   uint32_t n_refit_fail;      /* tracks dropped by a failed refit step */
-  uint32_t reserved;
+  uint32_t overflow;          /* TPC_ERR_CAPACITY: bit k set when capacity k
+                                 (TPC_OVF_*) was too small */
+  uint32_t required_by[4];    /* the count capacity k needed (0 if it fit) */
   /* work of the last following stage (measurement): helix steps with
      covariance transport, candidate chi2 evaluations, Kalman updates */
   uint64_t follow_steps, follow_candidates, follow_updates;
 } tpc_counts;
+
+/* Capacities named by tpc_counts.overflow / required_by: clusters
+ * (tpc_clusters.capacity), tracklets (tpc_tracklets.capacity), tracks
+ * (tpc_tracks.capacity) and track hits (tpc_tracks.hit_capacity). */
+#define TPC_OVF_CLUSTERS 0
+#define TPC_OVF_TRACKLETS 1
+#define TPC_OVF_TRACKS 2
+#define TPC_OVF_HITS 3
 
 typedef struct tpc_ctx tpc_ctx;
 

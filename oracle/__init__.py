@@ -63,7 +63,7 @@ class OClusters(ctypes.Structure):
 class OFit(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in (
         "hits", "near_tie", "follow_ok", "pb_state", "cluster_owner", "kept", "par", "cov",
-        "chi2", "row", "nhits", "flags")]
+        "chi2", "row", "nhits", "flags", "par_cond")]
 
 
 def default_params(noise_sigma: float = 1.0) -> dict:
@@ -213,8 +213,12 @@ def build_tracklets(down, up, params: Optional[dict] = None) -> dict:
 
 
 def fit_tracks(cl: dict, tl: dict, params: Optional[dict] = None, brute_force: bool = False,
-               n_threads: int = 1) -> dict:
-    """Following (pass A/B), conflict resolution and refit of all tracklets."""
+               n_threads: int = 1, cond: bool = False) -> dict:
+    """Following (pass A/B), conflict resolution and refit of all tracklets.
+
+    cond: also return par_cond, the refit from a start scaled by 1 + 2^-24
+    (one binary32 rounding unit): how far the FP64 result itself moves under a
+    perturbation of that size (NaN where that refit fails)."""
     lib = _load()
     op = make_params(params, brute_force=brute_force, n_threads=n_threads)
     nt = len(tl["tl_start"])
@@ -226,6 +230,8 @@ def fit_tracks(cl: dict, tl: dict, params: Optional[dict] = None, brute_force: b
                par=np.zeros(m * 5), cov=np.zeros(m * 15), chi2=np.zeros(m),
                row=np.full(m, -1, np.int32), nhits=np.zeros(m, np.int32),
                flags=np.zeros(m, np.int32))
+    if cond:
+        out["par_cond"] = np.zeros(m * 5)
     of = OFit(**{k: _p(v) for k, v in out.items()})
     y = np.ascontiguousarray(cl["y_fx"], np.int32)
     z = np.ascontiguousarray(cl["z_fx"], np.int32)
@@ -241,6 +247,8 @@ def fit_tracks(cl: dict, tl: dict, params: Optional[dict] = None, brute_force: b
     res["pb_state"] = out["pb_state"][: nt * 6].reshape(nt, 6)
     res["par"] = out["par"][: nt * 5].reshape(nt, 5)
     res["cov"] = out["cov"][: nt * 15].reshape(nt, 15)
+    if cond:
+        res["par_cond"] = out["par_cond"][: nt * 5].reshape(nt, 5)
     for k in ("near_tie", "follow_ok", "kept", "chi2", "row", "nhits", "flags"):
         res[k] = out[k][:nt]
     res["cluster_owner"] = out["cluster_owner"][:nc]
@@ -248,13 +256,14 @@ def fit_tracks(cl: dict, tl: dict, params: Optional[dict] = None, brute_force: b
 
 
 def process(pad, time, adc, row_start, n_units: int, n_time_bins: int,
-            params: Optional[dict] = None, n_threads: int = 1, labels: bool = False) -> dict:
-    """The whole chain: clusters, links, tracklets, tracks."""
+            params: Optional[dict] = None, n_threads: int = 1, labels: bool = False,
+            cond: bool = False) -> dict:
+    """The whole chain: clusters, links, tracklets, tracks (cond: see fit_tracks)."""
     cl = cluster(pad, time, adc, row_start, n_units, n_time_bins, params, labels=labels,
                  n_threads=n_threads)
     down, up = find_neighbours(cl, params, n_threads=n_threads)
     tl = build_tracklets(down, up, params)
-    fit = fit_tracks(cl, tl, params, n_threads=n_threads)
+    fit = fit_tracks(cl, tl, params, n_threads=n_threads, cond=cond)
     return dict(clusters=cl, down=down, up=up, tracklets=tl, fit=fit)
 
 

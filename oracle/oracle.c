@@ -272,7 +272,8 @@ static void clusterize_unit(void* ctx, int unit) {
 }
 
 /* Returns the number of clusters (written only if it fits cap), or -1 if the
-   input is not sorted or out of range. */
+   input is not sorted or out of range (pad beyond the row, time beyond the
+   frame, ADC 0 or above 10 bits). */
 int64_t oracle_cluster(const oparams* par, int32_t n_units, int32_t n_time_bins,
                        const uint16_t* pad, const uint16_t* time, const uint16_t* adc,
                        const uint32_t* row_start, int64_t cap, oclusters* out) {
@@ -284,6 +285,7 @@ int64_t oracle_cluster(const oparams* par, int32_t n_units, int32_t n_time_bins,
     if (row_start[ur + 1] < row_start[ur]) return -1;
     for (int64_t s = row_start[ur]; s < row_start[ur + 1]; ++s) {
       if (pad[s] >= np || time[s] >= n_time_bins) return -1;
+      if (adc[s] == 0 || adc[s] > 1023) return -1; /* 10-bit ADC, zero never stored */
       if (s > row_start[ur] &&
           (int64_t)time[s] * 256 + pad[s] <= (int64_t)time[s - 1] * 256 + pad[s - 1])
         return -1;
@@ -626,6 +628,7 @@ typedef struct {
   int32_t* out_row;       /* [Nt] innermost kept row */
   int32_t* out_nhits;     /* [Nt] */
   int32_t* out_flags;     /* [Nt] */
+  double* out_par_cond;   /* [Nt*5] refit from a perturbed start, or NULL */
   int64_t* pd_fail;       /* per unit counters */
 } fit_job;
 
@@ -859,16 +862,14 @@ enum { TFLAG_NOT_PD = 1, TFLAG_REFIT_FAIL = 2 };
    innermost, middle and outermost kept clusters, evaluated at the outermost
    one, with a broad covariance, so that the result depends on the kept hits
    alone; the Kalman filter then runs inward through every kept hit.  A step
-   fails only if the helix cannot reach the next hit's row. */
-static void refit_track(fit_job* J, int64_t t) {
+   fails only if the helix cannot reach the next hit's row.  rows[0..n) are
+   the kept rows, outermost first.  seed_scale multiplies every start
+   parameter (1 for the result itself).  Returns 1 if a step fails. */
+static int refit_from_seed(const fit_job* J, int64_t t, const int* rows, int n, double seed_scale,
+                           kstate* k, double* chi2_out, int* pd_ok, ktrace* tr) {
   const oparams* par = J->par;
   const int32_t* H = J->hits + t * NROW;
-  int rows[NROW], n = 0;
-  for (int r = NROW - 1; r >= 0; --r)
-    if (H[r] >= 0 && J->cluster_owner[H[r]] == t) rows[n++] = r;
   const int64_t anchor = J->z[J->tl_start[t]];
-  J->out_flags[t] = 0;
-  ktrace tr = {0, 0};
   /* circle through A (innermost), M (middle), E (outermost) kept clusters */
   const int rA = rows[n - 1], rM = rows[n - 1 - ((n + 1) / 2 - 1)], rE = rows[0];
   const int64_t cA = H[rA], cM = H[rM], cE = H[rE];
@@ -885,40 +886,53 @@ static void refit_track(fit_job* J, int64_t t) {
   if (sarg < -1.0) sarg = -1.0;
   const double h = dEA * fabs(C) / 2.0;
   const double arc = h > 0 ? dEA * asin(h > 1.0 ? 1.0 : h) / h : dEA;
-  kstate k;
-  k.x = G_X[rE];
-  k.p[0] = J->y[cE] / 65536.0;
-  k.p[1] = (J->z[cE] - anchor) / 65536.0;
-  k.p[2] = sin(atan2(ey, ex) + asin(sarg)); /* tangent at the far end of the chord */
-  k.p[3] = (double)(J->z[cE] - J->z[cA]) / 65536.0 / arc;
-  k.p[4] = qpt;
-  memset(k.C, 0, sizeof k.C);
-  k.C[0][0] = par->c0r_y * par->c0r_y;
-  k.C[1][1] = par->c0r_z * par->c0r_z;
-  k.C[2][2] = par->c0r_snp * par->c0r_snp;
-  k.C[3][3] = par->c0r_tgl * par->c0r_tgl;
-  k.C[4][4] = par->c0r_qpt * par->c0r_qpt;
+  k->x = G_X[rE];
+  k->p[0] = J->y[cE] / 65536.0;
+  k->p[1] = (J->z[cE] - anchor) / 65536.0;
+  k->p[2] = sin(atan2(ey, ex) + asin(sarg)); /* tangent at the far end of the chord */
+  k->p[3] = (double)(J->z[cE] - J->z[cA]) / 65536.0 / arc;
+  k->p[4] = qpt;
+  if (seed_scale != 1.0)
+    for (int i = 0; i < 5; ++i) k->p[i] *= seed_scale;
+  memset(k->C, 0, sizeof k->C);
+  k->C[0][0] = par->c0r_y * par->c0r_y;
+  k->C[1][1] = par->c0r_z * par->c0r_z;
+  k->C[2][2] = par->c0r_snp * par->c0r_snp;
+  k->C[3][3] = par->c0r_tgl * par->c0r_tgl;
+  k->C[4][4] = par->c0r_qpt * par->c0r_qpt;
   oparams rp = *par;
   rp.snp_max = par->refit_snp_max;
   double chi2sum = 0;
-  int pd_ok = 1;
+  *pd_ok = 1;
   for (int i = 0; i < n; ++i) {
     const int r = rows[i];
-    if (i > 0 && kstate_propagate(&rp, &k, G_X[r], &tr)) {
-      J->out_flags[t] |= TFLAG_REFIT_FAIL;
-      J->kept[t] = 0;
-      return;
-    }
+    if (i > 0 && kstate_propagate(&rp, k, G_X[r], tr)) return 1;
     double mmy, mmz, chi2;
     meas(J, H[r], anchor, &mmy, &mmz);
-    if (kstate_update(&k, mmy, mmz, par->sigma_y[r] * par->sigma_y[r],
-                      par->sigma_z[r] * par->sigma_z[r], &chi2, &tr)) {
-      J->out_flags[t] |= TFLAG_REFIT_FAIL;
-      J->kept[t] = 0;
-      return;
-    }
+    if (kstate_update(k, mmy, mmz, par->sigma_y[r] * par->sigma_y[r],
+                      par->sigma_z[r] * par->sigma_z[r], &chi2, tr))
+      return 1;
     chi2sum += chi2;
-    if (!is_pd(k.C)) pd_ok = 0;
+    if (!is_pd(k->C)) *pd_ok = 0;
+  }
+  *chi2_out = chi2sum;
+  return 0;
+}
+
+static void refit_track(fit_job* J, int64_t t) {
+  const int32_t* H = J->hits + t * NROW;
+  int rows[NROW], n = 0;
+  for (int r = NROW - 1; r >= 0; --r)
+    if (H[r] >= 0 && J->cluster_owner[H[r]] == t) rows[n++] = r;
+  J->out_flags[t] = 0;
+  ktrace tr = {0, 0};
+  kstate k;
+  double chi2sum;
+  int pd_ok;
+  if (refit_from_seed(J, t, rows, n, 1.0, &k, &chi2sum, &pd_ok, &tr)) {
+    J->out_flags[t] |= TFLAG_REFIT_FAIL;
+    J->kept[t] = 0;
+    return;
   }
   if (!pd_ok) J->out_flags[t] |= TFLAG_NOT_PD;
   for (int i = 0; i < 5; ++i) J->out_par[t * 5 + i] = k.p[i];
@@ -929,6 +943,16 @@ static void refit_track(fit_job* J, int64_t t) {
   J->out_row[t] = rows[n - 1];
   J->out_nhits[t] = n;
   J->near_tie[t] += tr.near_tie;
+  /* conditioning of the result: the same refit from a start perturbed by one
+     rounding unit of binary32 (2^-24), for comparisons made in that precision;
+     NaN if that refit fails */
+  if (J->out_par_cond) {
+    kstate kc;
+    double c2;
+    int pdc;
+    const int f = refit_from_seed(J, t, rows, n, 1.0 + 0x1p-24, &kc, &c2, &pdc, NULL);
+    for (int i = 0; i < 5; ++i) J->out_par_cond[t * 5 + i] = f ? NAN : kc.p[i];
+  }
 }
 
 static void refit_unit(void* ctx, int unit) {
@@ -954,6 +978,7 @@ typedef struct {
   int32_t* row;         /* [Nt] innermost kept row */
   int32_t* nhits;       /* [Nt] */
   int32_t* flags;       /* [Nt] */
+  double* par_cond;     /* [Nt*5] refit from the start scaled by 1 + 2^-24 (NULL: skipped) */
 } ofit;
 
 void oracle_fit_tracks(const oparams* par, int32_t n_units, const int32_t* y_fx,
@@ -995,6 +1020,7 @@ void oracle_fit_tracks(const oparams* par, int32_t n_units, const int32_t* y_fx,
   J.out_row = out->row;
   J.out_nhits = out->nhits;
   J.out_flags = out->flags;
+  J.out_par_cond = out->par_cond;
   for (int64_t i = 0; i < n_tracklets; ++i) {
     out->nhits[i] = 0;
     out->flags[i] = 0;

@@ -26,7 +26,6 @@ struct DevParams {
   double chi2_max_d, snp_max_d, bz_b_d, c0_snp2_d, c0_tgl2_d, c0_qpt2_d, qpt_clamp_d,
       edge_margin_d;
   float c0r2[5], refit_snp_max;  // refit prior variances (y, z, snp, tgl, q/pT)
-  float fp32_guard;
   double c0r2_d[5], refit_snp_max_d;
   int32_t validate, force_fallback;
 };
@@ -50,13 +49,22 @@ struct DevStatus {
   uint32_t n_clusters, n_tracklets, n_tracks, n_hits;
   uint32_t n_fallback, n_fallback_fail, n_not_pd, n_refit_fail;
   uint32_t n_fp64_redo;
-  uint32_t pad_[5];
+  uint32_t overflow;  // bit k set: capacity k (OVF_*) was too small
+  uint32_t req[4];    // count that capacity k needed
   unsigned long long f_steps, f_cands, f_upds;  // following work (measurement)
 };
 
 __device__ __forceinline__ void latch(DevStatus* st, int code, uint32_t required = 0) {
   atomicCAS(&st->status, 0, code);
   if (required) atomicMax(&st->required, required);
+}
+
+// Capacities whose overflow is reported, each with the count it needed.
+enum { OVF_CLUSTERS = 0, OVF_TRACKLETS = 1, OVF_TRACKS = 2, OVF_HITS = 3 };
+__device__ __forceinline__ void latch_capacity(DevStatus* st, int kind, uint32_t required) {
+  atomicOr(&st->overflow, 1u << kind);
+  atomicMax(&st->req[kind], required);
+  latch(st, TPC_ERR_CAPACITY, required);
 }
 
 __device__ __forceinline__ bool failed(const DevStatus* st) {

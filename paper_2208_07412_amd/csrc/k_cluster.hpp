@@ -65,6 +65,7 @@ __device__ __forceinline__ void bi_sample(uint32_t s, uint32_t t, int32_t prev, 
 template <bool USE_LDS>
 __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict__ tkey,
                                                      const uint16_t* __restrict__ pkey,
+                                                     const uint16_t* __restrict__ akey,
                                                      const uint32_t* __restrict__ rstart,
                                                      uint32_t n_ur, uint32_t nblk, uint32_t bshift,
                                                      uint32_t T, uint32_t n_total,
@@ -137,6 +138,11 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
             if ((int)p >= np) latch(st, TPC_ERR_INPUT);
             if (validate && s > s0 && ((traw << 8) | p) <= ((tp << 8) | pp))
               latch(st, TPC_ERR_INPUT);
+            // a zero-suppressed sample carries a 10-bit ADC above zero
+            if (validate && akey) {
+              const uint32_t a = akey[s];
+              if (a == 0 || a > 1023) latch(st, TPC_ERR_INPUT);
+            }
           }
           tp = t;
           pp = p;
@@ -613,13 +619,15 @@ __global__ __launch_bounds__(256) void k_cluster_output(const uint32_t* __restri
 __global__ void k_crow_start(const uint32_t* __restrict__ win_off, uint32_t nwin,
                              uint32_t n_ur, const uint32_t* __restrict__ n_clusters,
                              uint32_t capacity, uint32_t* __restrict__ crow, DevStatus* st) {
+  // after a latched error the scan that wrote *n_clusters did not run
+  if (failed(st)) return;
   const uint32_t n = *n_clusters;
   for (uint32_t ur = blockIdx.x * blockDim.x + threadIdx.x; ur <= n_ur;
        ur += gridDim.x * blockDim.x)
     crow[ur] = ur < n_ur ? win_off[(size_t)ur * nwin] : n;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->n_clusters = n;
-    if (n > capacity) latch(st, TPC_ERR_CAPACITY, n);
+    if (n > capacity) latch_capacity(st, OVF_CLUSTERS, n);
   }
 }
 

@@ -278,8 +278,10 @@ struct EmitTracklet {
 
 __global__ void k_tracklet_count(const uint32_t* n_tl, uint32_t capacity, uint32_t* out_n,
                                  DevStatus* st) {
+  // after a latched error the scan that wrote *n_tl did not run
+  if (failed(st)) return;
   const uint32_t n = *n_tl;
   st->n_tracklets = n;
   if (out_n) *out_n = n;
-  if (n > capacity) latch(st, TPC_ERR_CAPACITY, n);
+  if (n > capacity) latch_capacity(st, OVF_TRACKLETS, n);
 }

@@ -139,15 +139,22 @@ __device__ __forceinline__ float darc_dc<float>(float s1, float C, float dx) {
   return acc * dx * dx;
 }
 
-// Helix propagation over dx; with_cov also transports the covariance with
-// the analytic Jacobian.  Returns false (state untouched) if |sin phi| would
-// reach snp_max.
+// Off-diagonal elements of the helix Jacobian d(state after)/d(state before)
+// over one step.  Every other element is that of the identity: the Jacobian
+// is unit upper triangular in (y, z, sin phi, tan lambda, q/pT).
 template <typename T>
-__device__ __forceinline__ bool propagate(Trk<T>& k, T dx, const PV<T>& pv, bool with_cov,
-                                          T snp_lim, LoParts<T>* lo = nullptr) {
+struct HJac {
+  T j02, j04, j12, j13, j14, j24;
+};
+
+// Helix step of the state over dx; with J also the Jacobian.  Returns false
+// (state untouched) if |sin phi| would reach snp_lim.
+template <typename T>
+__device__ __forceinline__ bool helix_step(T p[5], T dx, const PV<T>& pv, T snp_lim,
+                                           LoParts<T>* lo, HJac<T>* J) {
   const T b = pv.b();
-  const T C = -b * k.p[4];
-  const T s1 = k.p[2];
+  const T C = -b * p[4];
+  const T s1 = p[2];
   T slo = lo ? lo->s : (T)0;
   const T s2 = lo ? two_sum_acc(s1, C * dx, &slo) : s1 + C * dx;
   if (!(fabs(s2) < snp_lim)) return false;
@@ -188,14 +195,36 @@ __device__ __forceinline__ bool propagate(Trk<T>& k, T dx, const PV<T>& pv, bool
   }
   const T D = c1 + c2;
   const T A = dx >= (T)0 ? L : -L;
-  if (with_cov) {
+  if (J) {
     const T iD2 = iD * iD;
-    const T j02 = dx * ((T)2 * D + N * (s1 * ic1 + s2 * ic2)) * iD2;
-    const T j04 = -b * dx * dx * (D + N * s2 * ic2) * iD2;
-    const T j12 = k.p[3] * dx * N * (ic1 * ic2 * iD);
-    const T j13 = A;
-    const T j14 = -b * k.p[3] * darc_dc(s1, C, dx);
-    const T j24 = -b * dx;
+    J->j02 = dx * ((T)2 * D + N * (s1 * ic1 + s2 * ic2)) * iD2;
+    J->j04 = -b * dx * dx * (D + N * s2 * ic2) * iD2;
+    J->j12 = p[3] * dx * N * (ic1 * ic2 * iD);
+    J->j13 = A;
+    J->j14 = -b * p[3] * darc_dc(s1, C, dx);
+    J->j24 = -b * dx;
+  }
+  if (lo) {
+    p[0] = two_sum_acc(p[0], dx * f, &lo->y);
+    lo->s = slo;
+  } else {
+    p[0] += dx * f;
+  }
+  p[1] += p[3] * A;
+  p[2] = s2;
+  return true;
+}
+
+// Helix propagation over dx; with_cov also transports the covariance,
+// C <- J C J^T.  Returns false (state untouched) if |sin phi| would reach
+// snp_lim.
+template <typename T>
+__device__ __forceinline__ bool propagate(Trk<T>& k, T dx, const PV<T>& pv, bool with_cov,
+                                          T snp_lim, LoParts<T>* lo = nullptr) {
+  HJac<T> J;
+  if (!helix_step(k.p, dx, pv, snp_lim, lo, with_cov ? &J : nullptr)) return false;
+  if (with_cov) {
+    const T j02 = J.j02, j04 = J.j04, j12 = J.j12, j13 = J.j13, j14 = J.j14, j24 = J.j24;
     T m[5][5];
 #pragma unroll
     for (int i = 0; i < 5; ++i)
@@ -219,14 +248,6 @@ __device__ __forceinline__ bool propagate(Trk<T>& k, T dx, const PV<T>& pv, bool
       for (int j = i; j < 5; ++j) k.c[PI(i, j)] = col[j];
     }
   }
-  if (lo) {
-    k.p[0] = two_sum_acc(k.p[0], dx * f, &lo->y);
-    lo->s = slo;
-  } else {
-    k.p[0] += dx * f;
-  }
-  k.p[1] += k.p[3] * A;
-  k.p[2] = s2;
   return true;
 }
 
@@ -272,78 +293,6 @@ __device__ __forceinline__ bool update(Trk<T>& k, T my, T mz, T vy, T vz, T* chi
   for (int i = 0; i < 5; ++i)
 #pragma unroll
     for (int j = i; j < 5; ++j) k.c[PI(i, j)] -= K0[i] * c0[j] + K1[i] * c1v[j];
-  return true;
-}
-
-// The same update with the covariance in Joseph form,
-// C' = (I - K H) C (I - K H)^T + K V K^T, which equals C - K H C in exact
-// arithmetic but keeps FP32 precision while the prior variance collapses by
-// many orders of magnitude over the first hits (used by the refit).
-template <typename T>
-__device__ __forceinline__ bool update_joseph(Trk<T>& k, T my, T mz, T vy, T vz, T* chi2,
-                                              LoParts<T>* lo = nullptr) {
-  const T r0 = my - k.p[0], r1 = mz - k.p[1];
-  const SInv<T> si = s_inverse(k, vy, vz);
-  const T I00 = si.i00, I01 = si.i01, I11 = si.i11;
-  if (chi2) *chi2 = r0 * r0 * I00 + (T)2 * r0 * r1 * I01 + r1 * r1 * I11;
-  T K0[5], K1[5], c0[5], c1v[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    c0[i] = cov(k.c, 0, i);
-    c1v[i] = cov(k.c, 1, i);
-    K0[i] = c0[i] * I00 + c1v[i] * I01;
-    K1[i] = c0[i] * I01 + c1v[i] * I11;
-  }
-  const T np2 = k.p[2] + K0[2] * r0 + K1[2] * r1;
-  if (!(fabs(np2) < (T)1)) return false;
-  if (lo) {
-    k.p[0] = two_sum_acc(k.p[0], K0[0] * r0 + K1[0] * r1, &lo->y);
-    k.p[2] = two_sum_acc(k.p[2], K0[2] * r0 + K1[2] * r1, &lo->s);
-#pragma unroll
-    for (int i = 0; i < 5; ++i)
-      if (i != 0 && i != 2) k.p[i] += K0[i] * r0 + K1[i] * r1;
-  } else {
-#pragma unroll
-    for (int i = 0; i < 5; ++i) k.p[i] += K0[i] * r0 + K1[i] * r1;
-  }
-  // columns 0 and 1 of M = (I - K H) C
-  T m0[5], m1[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    m0[i] = c0[i] - K0[i] * c0[0] - K1[i] * c1v[0];
-    m1[i] = c1v[i] - K0[i] * c0[1] - K1[i] * c1v[1];
-  }
-#pragma unroll
-  for (int i = 0; i < 5; ++i)
-#pragma unroll
-    for (int j = i; j < 5; ++j) {
-      const T mij = k.c[PI(i, j)] - K0[i] * c0[j] - K1[i] * c1v[j];
-      k.c[PI(i, j)] = mij - m0[i] * K0[j] - m1[i] * K1[j] + vy * K0[i] * K0[j] + vz * K1[i] * K1[j];
-    }
-  return true;
-}
-
-// positive definiteness by LDL^T: all pivots > 0
-template <typename T>
-__device__ __forceinline__ bool is_pd(const T* c) {
-  T L[5][5];
-  T D[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    T d = c[PI(j, j)];
-#pragma unroll
-    for (int m = 0; m < j; ++m) d -= L[j][m] * L[j][m] * D[m];
-    if (!(d > (T)0)) return false;
-    D[j] = d;
-    const T id = (T)1 / d;
-#pragma unroll
-    for (int i = j + 1; i < 5; ++i) {
-      T a = c[PI(j, i)];
-#pragma unroll
-      for (int m = 0; m < j; ++m) a -= L[i][m] * L[j][m] * D[m];
-      L[i][j] = a * id;
-    }
-  }
   return true;
 }
 
@@ -995,56 +944,166 @@ __device__ __forceinline__ int32_t tl_anchor(const ClusterView& cl, const uint32
   return cl.z_fx[tl_start[t]];
 }
 
-// Kept hits of the first refit updates, done in FP64: while the prior
-// variance collapses by orders of magnitude, FP32 cancellation in the
-// covariance update would bias the result; afterwards FP32 keeps up.
-#define REFIT_HEAD 5
+// ------------------------------------------------------------------ refit
+// The refit keeps its covariance as UD factors, C = U D U^T, with U unit
+// upper triangular (u[i][j] for j > i; the rest is implied) and D diagonal.
+// The helix Jacobian is unit upper triangular too and there is no process
+// noise, so a propagation is U <- J U with D unchanged.  A (y, z)
+// measurement with independent errors is two scalar updates in Bierman's
+// form: each pivot d_j becomes d_j alpha_(j-1) / alpha_j with alpha a running
+// sum of non-negative terms, so the covariance stays positive definite and
+// keeps FP32 precision while the broad start variances collapse by orders
+// of magnitude (the dense form loses it to cancellation there).
+template <typename T>
+struct UDCov {
+  T u[5][5];  // strictly upper part only
+  T d[5];
+};
 
-// Kalman steps of the refit: kept hits i, i-1, ... (rows descending), at
-// most max_hits of them; the state k sits at row r_state.  On return i is the
-// next kept hit to use.  Returns 1 if the helix cannot reach a hit's row or an
-// update fails; pd turns false if an update left the covariance not PD.
+__device__ __forceinline__ float rcp_of(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_of(double x) { return 1.0 / x; }
+
+// U <- J U (rows 0..2 change; row 2 is read before it is written)
+template <typename T>
+__device__ __forceinline__ void ud_propagate(UDCov<T>& c, const HJac<T>& J) {
+  const T u23 = c.u[2][3], u24 = c.u[2][4], u34 = c.u[3][4];
+  c.u[0][2] += J.j02;
+  c.u[0][3] += J.j02 * u23;
+  c.u[0][4] += J.j02 * u24 + J.j04;
+  c.u[1][2] += J.j12;
+  c.u[1][3] += J.j12 * u23 + J.j13;
+  c.u[1][4] += J.j12 * u24 + J.j13 * u34 + J.j14;
+  c.u[2][4] += J.j24;
+}
+
+// Scalar measurement of parameter M with variance r (Bierman): updates the
+// factors, writes the gain K and returns the residual variance alpha.
+template <int M, typename T>
+__device__ __forceinline__ T ud_update(UDCov<T>& c, T r, T K[5]) {
+  T f[5], v[5], b[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    f[j] = j < M ? (T)0 : (j == M ? (T)1 : c.u[M][j]);
+    v[j] = c.d[j] * f[j];
+    b[j] = 0;
+  }
+  T alpha = r, ia = rcp_of(r);
+#pragma unroll
+  for (int j = M; j < 5; ++j) {
+    const T ap = alpha, iap = ia;
+    alpha = ap + f[j] * v[j];
+    ia = rcp_of(alpha);
+    c.d[j] *= ap * ia;
+    const T lam = -f[j] * iap;
+#pragma unroll
+    for (int i = 0; i < j; ++i) {
+      const T uij = c.u[i][j];
+      c.u[i][j] = uij + b[i] * lam;
+      b[i] += uij * v[j];
+    }
+    b[j] = v[j];
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) K[i] = b[i] * ia;
+  return alpha;
+}
+
+// C = U D U^T, packed upper triangle
+template <typename T>
+__device__ __forceinline__ void ud_to_cov(const UDCov<T>& c, T* out) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      T a = 0;
+#pragma unroll
+      for (int k = j; k < 5; ++k) {
+        const T uik = k == i ? (T)1 : c.u[i][k];
+        const T ujk = k == j ? (T)1 : c.u[j][k];
+        a += uik * c.d[k] * ujk;
+      }
+      out[PI(i, j)] = a;
+    }
+}
+
+// positive definite: every pivot of the factorisation > 0 (NaN fails)
+template <typename T>
+__device__ __forceinline__ bool ud_pd(const UDCov<T>& c) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) ok = ok && c.d[j] > (T)0;
+  return ok;
+}
+
+// Kalman update of the refit with the (y, z) measurement, as a y update then
+// a z update; the y residual includes the low-order part of y.  Returns false
+// if |sin phi| >= 1 afterwards (the track then fails).
+template <typename T>
+__device__ __forceinline__ bool ud_measure(T p[5], UDCov<T>& c, LoParts<T>* lo, T my, T mz, T vy,
+                                           T vz, T* chi2) {
+  T K[5];
+  const T ry = lo ? (my - p[0]) - lo->y : my - p[0];
+  const T ay = ud_update<0>(c, vy, K);
+  if (lo) {
+    p[0] = two_sum_acc(p[0], K[0] * ry, &lo->y);
+    p[2] = two_sum_acc(p[2], K[2] * ry, &lo->s);
+  } else {
+    p[0] += K[0] * ry;
+    p[2] += K[2] * ry;
+  }
+  p[1] += K[1] * ry;
+  p[3] += K[3] * ry;
+  p[4] += K[4] * ry;
+  const T rz = mz - p[1];
+  const T az = ud_update<1>(c, vz, K);
+  if (lo) {
+    p[0] = two_sum_acc(p[0], K[0] * rz, &lo->y);
+    p[2] = two_sum_acc(p[2], K[2] * rz, &lo->s);
+  } else {
+    p[0] += K[0] * rz;
+    p[2] += K[2] * rz;
+  }
+  p[1] += K[1] * rz;
+  p[3] += K[3] * rz;
+  p[4] += K[4] * rz;
+  *chi2 = ry * ry * rcp_of(ay) + rz * rz * rcp_of(az);
+  return fabs(p[2]) < (T)1;
+}
+
+// Kalman steps of the refit over the kept hits i, i-1, ... (rows
+// descending); the state sits at row r_state.  On return i is the next kept
+// hit.  Returns 1 if the helix cannot reach a hit's row or an update fails;
+// pd turns false if an update left a pivot that is not positive.
 template <typename T>
 __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, const FollowOut& fo,
-                         const DevParams* P, Trk<T>& k, T& chi2s, int& r_state, int& i,
-                         int max_hits, bool& pd, bool* guard = nullptr,
-                         LoParts<T>* lp = nullptr) {
+                         const DevParams* P, T p[5], UDCov<T>& c, T& chi2s, int& r_state, int& i,
+                         bool& pd, LoParts<T>* lp) {
   const PV<T> pv{P};
   const int32_t* H = fo.hits + (size_t)t * NROW;
   const uint8_t* KR = fo.krow + (size_t)t * NROW;
-  int done = 0;
-  if (i < 0 || max_hits <= 0) return 0;
+  if (i < 0) return 0;
   // the row, cluster and position of the next hit are read a step ahead,
   // each behind a part of this step's arithmetic, so that their dependent
   // loads overlap it
   int r = KR[i];
   int2 q = cl.pos[H[r]];
-  for (; i >= 0 && done < max_hits; --i) {
-    const bool more = i > 0 && done + 1 < max_hits;
+  for (; i >= 0; --i) {
+    const bool more = i > 0;
     const int r_n = more ? (int)KR[i - 1] : r;
-    if (r != r_state &&
-        !propagate(k, row_dx<T>(P, r_state, r), pv, true, pv.refit_snp_max(), lp))
-      return 1;
+    if (r != r_state) {
+      HJac<T> J;
+      if (!helix_step(p, row_dx<T>(P, r_state, r), pv, pv.refit_snp_max(), lp, &J)) return 1;
+      ud_propagate(c, J);
+    }
     const int32_t c_n = more ? H[r_n] : 0;
     const T my = (T)q.x * (T)FX_SCALE;
     const T mz = (T)(q.y - anchor) * (T)FX_SCALE;
     T x2;
-    T d0[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) d0[i] = k.c[PI(i, i)];
-    if (!update_joseph(k, my, mz, pv.vy(r), pv.vz(r), &x2, lp)) return 1;
-    // cancellation guard: an update that removes more than (1 - fp32_guard)
-    // of a variance in one step loses FP32 precision in the covariance
-    if (guard) {
-#pragma unroll
-      for (int i = 0; i < 5; ++i)
-        if (k.c[PI(i, i)] < (T)P->fp32_guard * d0[i]) *guard = true;
-    }
+    if (!ud_measure(p, c, lp, my, mz, pv.vy(r), pv.vz(r), &x2)) return 1;
     const int2 q_n = more ? cl.pos[c_n] : q;
     chi2s += x2;
-    if (!is_pd(k.c)) pd = false;
+    if (!ud_pd(c)) pd = false;
     r_state = r;
-    ++done;
     r = r_n;
     q = q_n;
   }
@@ -1052,12 +1111,12 @@ __device__ int refit_run(uint32_t t, const ClusterView& cl, int32_t anchor, cons
 }
 
 // Start of the refit: the circle through the innermost, middle and outermost
-// kept clusters, evaluated at the outermost one, with the broad refit prior.
-// Fixed-point differences are exact integers.  Returns the outermost kept
-// row, or -1 if the track has fewer than 3 kept hits.
+// kept clusters, evaluated at the outermost one (fixed-point differences are
+// exact integers), and the broad refit prior as UD factors (U = I).  Returns
+// the outermost kept row, or -1 if the track has fewer than 3 kept hits.
 template <typename T>
 __device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, const FollowOut& fo,
-                          int n, const DevParams* P, Trk<T>& k) {
+                          int n, const DevParams* P, T p[5], UDCov<T>& c) {
   const PV<T> pv{P};
   if (n < 3) return -1;
   const int32_t* H = fo.hits + (size_t)t * NROW;
@@ -1081,29 +1140,27 @@ __device__ int refit_seed(uint32_t t, const ClusterView& cl, int32_t anchor, con
   const T sarg = fmin(fmax(dea * C * (T)0.5, (T)-1), (T)1);
   const T h = dea * fabs(C) * (T)0.5;
   const T arc = h > (T)0 ? dea * asin(fmin(h, (T)1)) / h : dea;
-  k.p[0] = (T)qE.x * S;
-  k.p[1] = (T)(qE.y - anchor) * S;
-  k.p[2] = sin(atan2((T)dye, (T)dxe) + asin(sarg));  // tangent at the far end of the chord
-  k.p[3] = (T)(qE.y - qA.y) * S / arc;
-  k.p[4] = qpt;
+  p[0] = (T)qE.x * S;
+  p[1] = (T)(qE.y - anchor) * S;
+  p[2] = sin(atan2((T)dye, (T)dxe) + asin(sarg));  // tangent at the far end of the chord
+  p[3] = (T)(qE.y - qA.y) * S / arc;
+  p[4] = qpt;
 #pragma unroll
-  for (int i = 0; i < 15; ++i) k.c[i] = 0;
-  k.c[PI(0, 0)] = pv.c0r(0);
-  k.c[PI(1, 1)] = pv.c0r(1);
-  k.c[PI(2, 2)] = pv.c0r(2);
-  k.c[PI(3, 3)] = pv.c0r(3);
-  k.c[PI(4, 4)] = pv.c0r(4);
+  for (int i = 0; i < 5; ++i) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) c.u[i][j] = 0;
+    c.d[i] = pv.c0r(i);
+  }
   return rE;
 }
 
 // The refit of each kept track, tracks taken in the order perm gives (sorted
-// by kept hits): the circle seed and the first REFIT_HEAD updates in FP64,
-// where the broad prior's variances collapse by orders of magnitude, then the
-// rest in FP32 (Joseph form, y and sin phi carried with their rounding
-// errors).  A track that needs more (low pT with a covariance that is not
-// positive definite, or an update that cancels most of a variance) is refit
-// again in FP64 from its seed by the same lane (TF_TO_FP64 marks it; the
-// mark is internal and counted by a scan).
+// by kept hits): in FP32 from the circle seed, with y and sin phi carried
+// with their rounding errors.  A low-pT track (|q/pT| >= lowpt_qpt at the
+// seed) whose FP32 covariance loses positive definiteness is refit again in
+// FP64 from its seed by the same lane (TF_TO_FP64 marks it; the mark is
+// internal and counted by a reduction); force_fallback sends every track
+// there (a test hook).
 __global__ __launch_bounds__(64) void k_refit(ClusterView cl, const uint32_t* __restrict__ tl_start,
                                               FollowOut fo, const uint32_t* n_tl_dev,
                                               uint32_t tl_cap, const uint16_t* __restrict__ nkept,
@@ -1123,69 +1180,61 @@ __global__ __launch_bounds__(64) void k_refit(ClusterView cl, const uint32_t* __
     const int n = nkept[t];
     if (n == 0) continue;
     const int32_t anchor = tl_anchor(cl, tl_start, t);
-    // FP64 head
-    Trk<double> kd;
-    double chi2d = 0;
-    int rprev = refit_seed<double>(t, cl, anchor, fo, n, P, kd);
-    int r = n - 1;
-    bool pd = true;
-    const bool lowpt = rprev >= 0 && fabs(kd.p[4]) >= (double)P->lowpt_qpt;
-    if (rprev < 0 || refit_run<double>(t, cl, anchor, fo, P, kd, chi2d, rprev, r, REFIT_HEAD, pd)) {
-      ro.flags[t] = TF_REFIT_FAIL;
-      atomicAdd(&st->n_refit_fail, 1u);
-      continue;
-    }
-    // FP32 from the head's state; y and sin phi handed over to twice FP32
-    // precision
-    Trk<float> k;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) k.p[i] = (float)kd.p[i];
-    LoParts<float> lo{(float)(kd.p[0] - (double)k.p[0]), (float)(kd.p[2] - (double)k.p[2])};
-#pragma unroll
-    for (int i = 0; i < 15; ++i) k.c[i] = (float)kd.c[i];
-    float chi2s = (float)chi2d;
-    bool guard = false;
-    const int rc = refit_run<float>(t, cl, anchor, fo, P, k, chi2s, rprev, r, NROW, pd, &guard, &lo);
-    k.p[0] += lo.y;
-    k.p[2] += lo.s;
-    if (rc) {
-      ro.flags[t] = TF_REFIT_FAIL;
-      atomicAdd(&st->n_refit_fail, 1u);
-      continue;
-    }
-    if (P->force_fallback || guard || (!pd && lowpt)) {
-      // the whole refit again in FP64 (the FP32 result is discarded)
-      Trk<double> k2;
-      double c2 = 0;
-      int rp2 = refit_seed<double>(t, cl, anchor, fo, n, P, k2);
-      int r2 = n - 1;
-      bool pd2 = true;
-      const bool fail =
-          rp2 < 0 || refit_run<double>(t, cl, anchor, fo, P, k2, c2, rp2, r2, NROW, pd2) != 0;
-      if (fail || !pd2) {
-        ro.flags[t] = TF_TO_FP64 | (fail ? TF_REFIT_FAIL : TF_FP64_FAIL);
-        atomicAdd(fail ? &st->n_refit_fail : &st->n_fallback_fail, 1u);
+    if (!P->force_fallback) {
+      float p[5];
+      UDCov<float> c;
+      int rs = refit_seed<float>(t, cl, anchor, fo, n, P, p, c);
+      const bool lowpt = rs >= 0 && fabsf(p[4]) >= (float)P->lowpt_qpt;
+      int r = n - 1;
+      bool pd = true;
+      float chi2s = 0.0f;
+      LoParts<float> lo{0.0f, 0.0f};
+      if (rs < 0 || refit_run<float>(t, cl, anchor, fo, P, p, c, chi2s, rs, r, pd, &lo)) {
+        ro.flags[t] = TF_REFIT_FAIL;
+        atomicAdd(&st->n_refit_fail, 1u);
         continue;
       }
+      if (pd || !lowpt) {
+        p[0] += lo.y;
+        p[2] += lo.s;
+        float cv[15];
+        ud_to_cov(c, cv);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) ro.par[(size_t)t * 5 + i] = (float)k2.p[i];
+        for (int i = 0; i < 5; ++i) ro.par[(size_t)t * 5 + i] = p[i];
 #pragma unroll
-      for (int i = 0; i < 15; ++i) ro.cov[(size_t)t * 15 + i] = (float)k2.c[i];
-      ro.chi2[t] = (float)c2;
-      ro.row[t] = (uint8_t)rp2;
-      ro.flags[t] = TF_TO_FP64 | TF_FP64;
+        for (int i = 0; i < 15; ++i) ro.cov[(size_t)t * 15 + i] = cv[i];
+        ro.chi2[t] = chi2s;
+        ro.row[t] = (uint8_t)rs;
+        if (!pd) {
+          ro.flags[t] = TF_NOT_PD;
+          atomicAdd(&st->n_not_pd, 1u);
+        }
+        continue;
+      }
+    }
+    // the whole refit again in FP64 (an FP32 result is discarded)
+    double p[5];
+    UDCov<double> c;
+    double c2 = 0;
+    int rs = refit_seed<double>(t, cl, anchor, fo, n, P, p, c);
+    int r = n - 1;
+    bool pd = true;
+    const bool fail = rs < 0 || refit_run<double>(t, cl, anchor, fo, P, p, c, c2, rs, r, pd,
+                                                  (LoParts<double>*)nullptr) != 0;
+    if (fail || !pd) {
+      ro.flags[t] = TF_TO_FP64 | (fail ? TF_REFIT_FAIL : TF_FP64_FAIL);
+      atomicAdd(fail ? &st->n_refit_fail : &st->n_fallback_fail, 1u);
       continue;
     }
+    double cv[15];
+    ud_to_cov(c, cv);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) ro.par[(size_t)t * 5 + i] = k.p[i];
+    for (int i = 0; i < 5; ++i) ro.par[(size_t)t * 5 + i] = (float)p[i];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) ro.cov[(size_t)t * 15 + i] = k.c[i];
-    ro.chi2[t] = chi2s;
-    ro.row[t] = (uint8_t)rprev;
-    if (!pd) {
-      ro.flags[t] = TF_NOT_PD;
-      atomicAdd(&st->n_not_pd, 1u);
-    }
+    for (int i = 0; i < 15; ++i) ro.cov[(size_t)t * 15 + i] = (float)cv[i];
+    ro.chi2[t] = (float)c2;
+    ro.row[t] = (uint8_t)rs;
+    ro.flags[t] = TF_TO_FP64 | TF_FP64;
   }
 }
 
@@ -1235,6 +1284,8 @@ struct TrackOut {
 
 __global__ void k_track_totals(const unsigned long long* total, TrackOut to, uint32_t* n_tracks,
                                uint32_t* n_hits, DevStatus* st) {
+  // after a latched error the scan that wrote *total did not run
+  if (failed(st)) return;
   const unsigned long long v = *total;
   const uint32_t nt = (uint32_t)(v >> 32), nh = (uint32_t)v;
   st->n_tracks = nt;
@@ -1242,8 +1293,8 @@ __global__ void k_track_totals(const unsigned long long* total, TrackOut to, uin
   st->n_fallback = st->n_fp64_redo;
   if (n_tracks) *n_tracks = nt;
   if (n_hits) *n_hits = nh;
-  if (nt > to.capacity) latch(st, TPC_ERR_CAPACITY, nt);
-  if (nh > to.hit_capacity) latch(st, TPC_ERR_CAPACITY, nh);
+  if (nt > to.capacity) latch_capacity(st, OVF_TRACKS, nt);
+  if (nh > to.hit_capacity) latch_capacity(st, OVF_HITS, nh);
   if (nt <= to.capacity) to.hit_start[nt] = nh;
 }
 

@@ -216,7 +216,6 @@ DevParams make_dev_params(const tpc_params& p) {
   }
   d.refit_snp_max_d = p.refit_snp_max;
   d.refit_snp_max = (float)p.refit_snp_max;
-  d.fp32_guard = (float)p.fp32_guard;
   d.validate = p.validate;
   d.force_fallback = p.force_fallback;
   return d;
@@ -394,7 +393,8 @@ int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
   hipStream_t s = c->stream;
   {
     StageTimer tm(c, 0);
-    k_block_index<false><<<n_ur, 256, 0, s>>>(in->time, in->pad, in->row_start, n_ur, nblk_s,
+    k_block_index<false><<<n_ur, 256, 0, s>>>(in->time, in->pad, in->adc, in->row_start, n_ur,
+                                              nblk_s,
                                               CL_BSHIFT, in->n_time_bins, in->n_samples, c->zblk,
                                               c->d_par, c->d_st, 1);
   }
@@ -434,7 +434,8 @@ int stage_grid(tpc_ctx* c, const tpc_clusters* cl) {
   const uint32_t n_ur = cl->n_units * NROW;
   const uint32_t nblk = ceil_div(cl->n_time_bins, 1u << CG_BSHIFT);
   StageTimer tm(c, 4);
-  k_block_index<true><<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, cl->crow_start, n_ur, nblk,
+  k_block_index<true><<<n_ur, 256, 0, c->stream>>>(cl->ptime, cl->ppad, nullptr, cl->crow_start,
+                                                   n_ur, nblk,
                                              CG_BSHIFT,
                                              cl->n_time_bins, cl->capacity, c->cblk, c->d_par,
                                              c->d_st, 0);
@@ -626,7 +627,6 @@ int tpc_params_default(tpc_params* p, double noise_sigma) {
   p->c0r_tgl = 0.5;
   p->c0r_qpt = 10.0;
   p->refit_snp_max = 0.999;
-  p->fp32_guard = 0.1;
   for (int r = 0; r < NROW; ++r) {
     p->sigma_y[r] = 0.06;
     p->sigma_z[r] = 0.05;
@@ -817,6 +817,8 @@ int tpc_sync(tpc_ctx* c, tpc_counts* counts) {
     counts->n_fallback_fail = ds.n_fallback_fail;
     counts->n_not_pd = ds.n_not_pd;
     counts->n_refit_fail = ds.n_refit_fail;
+    counts->overflow = ds.overflow;
+    for (int k = 0; k < 4; ++k) counts->required_by[k] = ds.req[k];
     counts->follow_steps = ds.f_steps;
     counts->follow_candidates = ds.f_cands;
     counts->follow_updates = ds.f_upds;

@@ -224,18 +224,22 @@ class GpuExecutor:
         c = self.recos[slot].sync(raise_on_error=False)
         job.counts = c
         if c["status"] == -2:  # capacity: rerun with what the device needed
-            need = int(c["required"])
-            if need > job.cl_cap:
-                if need > self.max_clusters:
-                    job.error = f"chunk needs {need} clusters, slots hold {self.max_clusters}"
-                    return False
-                job.cl_cap = need + need // 16
+            req = c["required_by"]
+            # track hits are bounded by the cluster capacity, tracks by the
+            # tracklet capacity (see _outputs)
+            need_cl = max(req.get("clusters", 0), req.get("hits", 0))
+            need_tl = max(req.get("tracklets", 0), req.get("tracks", 0))
+            if need_cl > self.max_clusters:
+                job.error = f"chunk needs {need_cl} clusters, slots hold {self.max_clusters}"
+                return False
+            if need_tl > self.max_tracklets:
+                job.error = f"chunk needs {need_tl} tracklets, slots hold {self.max_tracklets}"
+                return False
+            if need_cl:
+                job.cl_cap = need_cl + need_cl // 16
                 job.tl_cap = max(job.tl_cap, job.cl_cap // 8)
-            else:
-                if need > self.max_tracklets:
-                    job.error = f"chunk needs {need} tracklets, slots hold {self.max_tracklets}"
-                    return False
-                job.tl_cap = need + need // 16
+            if need_tl:
+                job.tl_cap = max(job.tl_cap, need_tl + need_tl // 16)
             return True
         if c["status"] != 0:
             job.error = tpc.load().tpc_status_string(c["status"]).decode()

@@ -32,7 +32,7 @@ class TpcParams(ctypes.Structure):
         ("lowpt_qpt", ctypes.c_double),
         ("c0r_y", ctypes.c_double), ("c0r_z", ctypes.c_double), ("c0r_snp", ctypes.c_double),
         ("c0r_tgl", ctypes.c_double), ("c0r_qpt", ctypes.c_double),
-        ("refit_snp_max", ctypes.c_double), ("fp32_guard", ctypes.c_double),
+        ("refit_snp_max", ctypes.c_double),
         ("sigma_y", ctypes.c_double * NROW), ("sigma_z", ctypes.c_double * NROW),
         ("validate", I32), ("force_fallback", I32),
     ]
@@ -71,11 +71,15 @@ class TpcTracks(ctypes.Structure):
                 ("cluster_track", P), ("follow_hits", P)]
 
 
+# capacities named by tpc_counts.overflow (bit k) and required_by[k]
+OVERFLOW_KINDS = ("clusters", "tracklets", "tracks", "hits")
+
+
 class TpcCounts(ctypes.Structure):
     _fields_ = [("status", I32), ("required", U32), ("n_samples", U32), ("n_clusters", U32),
                 ("n_tracklets", U32), ("n_tracks", U32), ("n_hits", U32), ("n_fallback", U32),
                 ("n_fallback_fail", U32), ("n_not_pd", U32), ("n_refit_fail", U32),
-                ("reserved", U32), ("follow_steps", ctypes.c_uint64),
+                ("overflow", U32), ("required_by", U32 * 4), ("follow_steps", ctypes.c_uint64),
                 ("follow_candidates", ctypes.c_uint64), ("follow_updates", ctypes.c_uint64)]
 
 
@@ -392,6 +396,8 @@ class Reco:
         c = TpcCounts()
         rc = self.lib.tpc_sync(self.ctx, ctypes.byref(c))
         out = {k: getattr(c, k) for k, _ in TpcCounts._fields_}
+        out["required_by"] = {name: int(c.required_by[i])
+                              for i, name in enumerate(OVERFLOW_KINDS) if c.overflow >> i & 1}
         if raise_on_error and rc != 0:
             raise TpcError(rc, f"tpc_sync (required {c.required})")
         return out

@@ -5,8 +5,14 @@ Rules (from the acceptance statement of the method):
 * integer outputs bit-exact: clusters (order, peaks, charges, moments, flags,
   fixed-point positions), links, tracklets, hit sets and cluster ownership;
 * centroids within 1e-4 pad / time bin;
-* track parameters within 1e-4 relative, with floors (y, z: 1 cm; sin phi,
-  tan lambda: 1; q/pT: 0.1 c/GeV) where a parameter is near zero;
+* track parameters within 1e-4 relative, with floors where a relative error
+  is undefined at zero (y, z: 1 cm; sin phi, tan lambda: 0.01; q/pT: 0.1
+  c/GeV, i.e. pT above 10 GeV/c);
+* a track whose FP64 oracle refit is not determined to that bar by inputs
+  known to binary32 precision -- its parameters move by more than 1% of the
+  bar when the refit restarts from a start scaled by 1 + 2^-24 -- is exempt
+  from the parameter comparison only (its hits and ownership are still
+  compared); their number is reported;
 * hit decisions that the oracle logs as near ties (chi2 against the cut or
   best against second best within 1e-3, |sin phi| against its limit within
   1e-5, |y| against the edge within 1e-4 cm) may differ between FP32 and
@@ -19,8 +25,10 @@ import oracle
 from paper_2208_07412_amd import tpc
 
 NROW = 152
-FLOORS = np.array([1.0, 1.0, 1.0, 1.0, 0.1])
+FLOORS = np.array([1.0, 1.0, 1e-2, 1e-2, 0.1])
 PAR_RTOL = 1e-4
+COND_LIMIT = 0.01  # fraction of the bar the oracle may move under one FP32 unit
+PAR_NAMES = ("y", "z", "snp", "tgl", "qpt")
 
 
 def run_gpu(ev, params=None, max_tracklets=None, labels=False, moments=True, follow=True,
@@ -51,7 +59,18 @@ def run_gpu(ev, params=None, max_tracklets=None, labels=False, moments=True, fol
 
 def run_oracle(ev, params=None, labels=False, n_threads=8):
     return oracle.process(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins,
-                          params=params, n_threads=n_threads, labels=labels)
+                          params=params, n_threads=n_threads, labels=labels, cond=True)
+
+
+def ill_conditioned(ofit, t):
+    """The FP64 refit of tracklet t moves by more than COND_LIMIT of the bar
+    (or fails) when restarted from a start perturbed by one FP32 unit."""
+    pc = ofit.get("par_cond")
+    if pc is None:
+        return False
+    op = ofit["par"][t]
+    d = np.abs(pc[t] - op) / (PAR_RTOL * np.maximum(np.abs(op), FLOORS))
+    return not np.all(d <= COND_LIMIT)
 
 
 def _diff_report(g, o, keys):
@@ -141,6 +160,8 @@ def compare_fit(g, o, check_params=True):
     gidx = {int(t): j for j, t in enumerate(gtr["tracklet"])}
     okept = set(np.nonzero(ofit["kept"])[0].tolist())
     worst = 0.0
+    n_ill = 0
+    rels = []
     for t in range(nt):
         if t in ex:
             continue
@@ -158,10 +179,14 @@ def compare_fit(g, o, check_params=True):
         if check_params:
             op = ofit["par"][t]
             gp = gtr["par"][j].astype(np.float64)
-            r = np.abs(gp - op) / (PAR_RTOL * np.maximum(np.abs(op), FLOORS))
-            worst = max(worst, float(r.max()))
-            if np.any(r > 1):
-                bad.append(("par", t, gp.tolist(), op.tolist(), r.round(3).tolist()))
+            if ill_conditioned(ofit, t):
+                n_ill += 1
+            else:
+                r = np.abs(gp - op) / (PAR_RTOL * np.maximum(np.abs(op), FLOORS))
+                rels.append(np.abs(gp - op) / np.maximum(np.abs(op), FLOORS))
+                worst = max(worst, float(r.max()))
+                if np.any(r > 1):
+                    bad.append(("par", t, gp.tolist(), op.tolist(), r.round(3).tolist()))
             if gtr["row"][j] != ofit["row"][t] or gtr["ndf"][j] != 2 * ofit["nhits"][t] - 5:
                 bad.append(("row/ndf", t))
     gct = gtr["cluster_track"]
@@ -177,8 +202,15 @@ def compare_fit(g, o, check_params=True):
             if n_own <= 5:
                 bad.append(("owner", c, ot, gt))
     print(f"fit parity: {nt} tracklets, {len(ex)} exempt, {len(gidx)} gpu tracks, "
+          f"{n_ill} ill-conditioned refits (parameters not compared), "
           f"worst parameter deviation {worst:.3f} of tolerance, {len(bad)} violations, "
           f"{n_own} ownership differences")
+    if rels:
+        R = np.array(rels)
+        q = np.percentile(R, [50, 99, 100], axis=0)
+        print("  relative error vs FP64 oracle (|gpu - oracle| / max(|oracle|, floor)):")
+        for i, name in enumerate(PAR_NAMES):
+            print(f"    {name:4s} median {q[0][i]:.2e}  p99 {q[1][i]:.2e}  max {q[2][i]:.2e}")
     for v in bad[:20]:
         print("  ", v)
     assert not bad

@@ -41,7 +41,6 @@ def test_library_exports_every_declared_symbol():
 def test_defaults_agree_with_oracle_readings():
     p = tpc.params()
     d = oracle.default_params()
-    assert p.fp32_guard == 0.1
     for k, v in d.items():
         if k in ("sigma_y", "sigma_z"):
             assert list(getattr(p, k)) == v
@@ -95,12 +94,30 @@ def test_status_strings():
     assert lib.tpc_status_string(99) == b"unknown status"
 
 
-def test_struct_layouts_match_header():
-    # field counts of the binding against the header's struct members
-    src = open(os.path.join(ROOT, "include", "tpc.h")).read()
-    assert ctypes.sizeof(tpc.TpcParams) == 4 * 4 + 3 * 8 + 16 * 8 + 2 * 152 * 8 + 2 * 4
-    assert ctypes.sizeof(tpc.TpcCounts) == 12 * 4 + 3 * 8
-    assert "uint32_t capacity;" in src
+def test_struct_layouts_match_header(tmp_path):
+    # every field offset and struct size of the binding against the header,
+    # as the C compiler lays them out
+    structs = {"tpc_params": tpc.TpcParams, "tpc_sizes": tpc.TpcSizes,
+               "tpc_zs_input": tpc.TpcZsInput, "tpc_clusters": tpc.TpcClusters,
+               "tpc_links": tpc.TpcLinks, "tpc_tracklets": tpc.TpcTracklets,
+               "tpc_tracks": tpc.TpcTracks, "tpc_counts": tpc.TpcCounts,
+               "tpc_tuning": tpc.TpcTuning}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "tpc.h"', "int main(void) {"]
+    expect = []
+    for cname, cls in structs.items():
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {fname}));')
+            expect.append(getattr(cls, fname).offset)
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert got == expect
 
 
 def test_tuning_defaults_and_validation():

@@ -230,6 +230,19 @@ def test_unsorted_input_rejected():
         oracle.cluster(pad, time, adc, rs, 1, 10)
 
 
+@pytest.mark.parametrize("bad_adc", [0, 1024, 4095])
+def test_adc_outside_ten_bits_rejected(bad_adc):
+    # a stored zero-suppressed sample has a 10-bit ADC above zero
+    pad = np.array([4, 5], np.uint16)
+    time = np.array([3, 3], np.uint16)
+    rs = np.zeros(153, np.uint32)
+    rs[1:] = 2
+    ok = oracle.cluster(pad, time, np.array([10, 1023], np.uint16), rs, 1, 10)
+    assert ok["qtot"].tolist() == [1033]
+    with pytest.raises(ValueError):
+        oracle.cluster(pad, time, np.array([10, bad_adc], np.uint16), rs, 1, 10)
+
+
 def test_empty_input():
     rs = np.zeros(153, np.uint32)
     e = np.zeros(0, np.uint16)
