@@ -253,6 +253,25 @@ int tpc_process_timeframe(tpc_ctx* ctx, const tpc_zs_input* in, tpc_clusters* cl
 #define TPC_QC_BINS 667
 int tpc_qc_histograms(tpc_ctx* ctx, const tpc_clusters* cl, const tpc_tracks* tr, uint32_t* hist);
 
+/* The same histograms without a context and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The per-workgroup
+ * partial histograms live in a fixed device array inside the library, one
+ * copy per GPU, resolved on the first call on each device and held until the
+ * process ends: one partial histogram per 65,536 entries of the larger of
+ * cl->capacity and tr->capacity, at most 1,024 of them (2.7 MB).  A larger
+ * capacity (above TPC_QC_NOALLOC_MAX) is rejected with TPC_ERR_CAPACITY and a
+ * message on stderr; missing pointers give TPC_ERR_ARG.  Enqueued on
+ * hip_stream (a hipStream_t; NULL = the null stream); no call here allocates
+ * or frees memory.  There is no status word: the caller passes the outputs of
+ * a reconstruction that completed without error.  Every call on one GPU uses
+ * that GPU's one array, so calls that overlap in time on the same GPU (on
+ * different streams, or from different threads) race and must be serialised
+ * by the caller.  Results equal tpc_qc_histograms on the same outputs. */
+#define TPC_QC_NOALLOC_MAX (1024ull * 65536ull)
+int tpc_qc_histograms_noalloc(const tpc_clusters* cl, const tpc_tracks* tr, uint32_t* hist,
+                              void* hip_stream);
+
 /* Wait for the stream, then report the first latched error and the counts.
  * Clears the status word for the next call. */
 int tpc_sync(tpc_ctx* ctx, tpc_counts* counts);

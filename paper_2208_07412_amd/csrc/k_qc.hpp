@@ -27,8 +27,9 @@ __global__ __launch_bounds__(256) void k_qc_fill(const uint16_t* __restrict__ qt
   const uint32_t w = threadIdx.x >> 6;
   for (uint32_t i = threadIdx.x; i < 4 * QC_BINS; i += blockDim.x) (&h[0][0])[i] = 0;
   __syncthreads();
-  // after a latched error the outputs are not valid: empty histograms
-  const bool ok = !failed(st);
+  // after a latched error the outputs are not valid: empty histograms (no
+  // status word, st == nullptr: the caller vouches for the outputs)
+  const bool ok = st == nullptr || !failed(st);
   const uint32_t n_cl = ok ? scan_count(n_cl_dev, cl_cap) : 0u;
   const uint32_t n_trk = ok ? scan_count(n_trk_dev, trk_cap) : 0u;
   const uint32_t stride = gridDim.x * blockDim.x;

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -783,6 +784,68 @@ int tpc_qc_histograms(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, 
                                           cl->capacity, tr->hit_start, tr->n_tracks,
                                           tr->capacity, c->qc_part, c->d_st);
   k_qc_sum<<<QC_BINS, 256, 0, c->stream>>>(c->qc_part, QC_WG, hist);
+  return launch_ok();
+}
+
+// Allocation-free QC histograms.  The per-workgroup partial histograms live in
+// a file-scope device array (one copy per GPU, held until the process ends)
+// instead of a context's scratch.  One partial histogram per QC_NA_ITEMS
+// entries of the larger capacity, at most QC_NA_WG of them.
+namespace {
+constexpr uint32_t QC_NA_WG = 1024;
+constexpr uint32_t QC_NA_ITEMS = 65536;
+constexpr int kMaxDevices = 64;
+static_assert(TPC_QC_NOALLOC_MAX == (uint64_t)QC_NA_WG * QC_NA_ITEMS, "no-alloc QC limit");
+}  // namespace
+
+static __device__ __align__(256) uint32_t scratch[(size_t)QC_NA_WG * QC_BINS];
+
+namespace {
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch`, resolved once per device
+// with that device current.  The array's name in host code is a host-side
+// stand-in, never a device address, so kernels only ever get this pointer.
+int noalloc_scratch(uint32_t** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TPC_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return TPC_ERR_STATE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TPC_ERR_HIP;
+    g_scratch_ptr[dev] = (uint32_t*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TPC_OK;
+}
+}  // namespace
+
+int tpc_qc_histograms_noalloc(const tpc_clusters* cl, const tpc_tracks* tr, uint32_t* hist,
+                              void* hip_stream) {
+  if (!cl || !tr || !hist || !cl->n_clusters || !cl->qtot || !cl->qmax || !tr->n_tracks ||
+      !tr->hit_start || !tr->cluster_track)
+    return TPC_ERR_ARG;
+  const uint64_t items = cl->capacity > tr->capacity ? cl->capacity : tr->capacity;
+  if (items > TPC_QC_NOALLOC_MAX) {
+    std::fprintf(stderr,
+                 "tpc_qc_histograms_noalloc: capacity %llu exceeds the limit of %llu entries "
+                 "(fixed scratch of %u partial histograms)\n",
+                 (unsigned long long)items, (unsigned long long)TPC_QC_NOALLOC_MAX, QC_NA_WG);
+    return TPC_ERR_CAPACITY;
+  }
+  uint32_t* part = nullptr;
+  const int rc = noalloc_scratch(&part);
+  if (rc) return rc;
+  uint32_t nwg = ceil_div(items, QC_NA_ITEMS);
+  if (nwg == 0) nwg = 1;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // every workgroup overwrites its whole partial histogram: nothing to clear
+  k_qc_fill<<<nwg, 256, 0, s>>>(cl->qtot, cl->qmax, tr->cluster_track, cl->n_clusters,
+                                cl->capacity, tr->hit_start, tr->n_tracks, tr->capacity, part,
+                                nullptr);
+  k_qc_sum<<<QC_BINS, 256, 0, s>>>(part, nwg, hist);
   return launch_ok();
 }
 

@@ -93,7 +93,7 @@ EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_crea
            "tpc_fit_tracks", "tpc_process_timeframe", "tpc_sync", "tpc_stream",
            "tpc_status_string", "tpc_profile_enable", "tpc_profile_read",
            "tpc_profile_stage_name", "tpc_tuning_default", "tpc_set_tuning", "tpc_get_tuning",
-           "tpc_qc_histograms"]
+           "tpc_qc_histograms", "tpc_qc_histograms_noalloc"]
 PROF_STAGES = 12
 # quality-control histogram layout (bin offsets; see tpc_qc_histograms)
 QC_QTOT, QC_QMAX, QC_NHITS, QC_ATTACH, QC_BINS = 0, 256, 512, 665, 667
@@ -124,6 +124,7 @@ def load():
     lib.tpc_fit_tracks.argtypes = [P, P, P, P, P]
     lib.tpc_process_timeframe.argtypes = [P, P, P, P, P, P]
     lib.tpc_qc_histograms.argtypes = [P, P, P, P]
+    lib.tpc_qc_histograms_noalloc.argtypes = [P, P, P, P]
     lib.tpc_sync.argtypes = [P, P]
     lib.tpc_stream.argtypes = [P]
     lib.tpc_stream.restype = P
@@ -356,6 +357,13 @@ class Reco:
                                           ctypes.c_void_p(out.data_ptr())), "tpc_qc_histograms")
         return out
 
+    def qc_histograms_noalloc(self, cl: Buffers, tr: Buffers, out, stream=None):
+        """tpc_qc_histograms_noalloc on the same outputs: no context and no
+        allocation inside the call (out: int32 device tensor of QC_BINS,
+        caller-allocated).  Enqueued on `stream` (a torch stream; default:
+        this context's stream)."""
+        return qc_histograms_noalloc(cl, tr, out, stream if stream is not None else self.stream)
+
     def process(self, zs: dict, cl: Buffers, links: Buffers, tl: Buffers, tr: Buffers,
                 zs_s: Optional[TpcZsInput] = None):
         s = zs_s if zs_s is not None else zs_struct(zs)
@@ -404,6 +412,26 @@ class Reco:
 
 
 # ---------------------------------------------------------------- host views
+QC_NOALLOC_MAX = 1024 * 65536
+
+
+def qc_histograms_noalloc(cl: Buffers, tr: Buffers, out, stream=None):
+    """Quality-control histograms through tpc_qc_histograms_noalloc: the
+    library's fixed per-GPU scratch, no context, nothing allocated.  `out` is
+    an int32 device tensor of QC_BINS counts; `stream` a torch stream (None:
+    torch's current stream)."""
+    torch = _torch()
+    lib = load()
+    if out.numel() < QC_BINS or out.dtype != torch.int32 or not out.is_cuda:
+        raise ValueError("qc_histograms_noalloc: out must be an int32 device tensor of QC_BINS")
+    s = stream if stream is not None else torch.cuda.current_stream(out.device)
+    _check(lib.tpc_qc_histograms_noalloc(ctypes.byref(cl.s), ctypes.byref(tr.s),
+                                         ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(s.cuda_stream)),
+           "tpc_qc_histograms_noalloc")
+    return out
+
+
 def _u(t, n, dt):
     a = t[:n].cpu().numpy()
     return a.view(dt) if a.dtype.itemsize == np.dtype(dt).itemsize else a.astype(dt)
