@@ -68,6 +68,8 @@ def _load():
                                    ctypes.c_double, P, ctypes.c_uint64, P]
     lib.synth_digitize.restype = ctypes.c_int64
     lib.synth_digitize_fetch.argtypes = [P, P, P]
+    lib.synth_pack_pages.argtypes = [ctypes.c_int32, P, P, P, P, P]
+    lib.synth_pack_pages.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -330,3 +332,54 @@ def stack(events: List[Event]) -> Event:
     n_units = sum(e.n_units for e in events)
     T = max(e.n_time_bins for e in events)
     return Event(events[0].config, pad, time, adc, row_start, n_units, T, {}, {}, None)
+
+
+def select_units(ev: Event, units: List[int]) -> Event:
+    """The given units of an event, as an event of their own (same time range).
+
+    Used to cut a bounded sample out of a large frame; units are independent,
+    so every unit reconstructs the same alone as inside its frame.
+    """
+    rs = ev.row_start.astype(np.int64)
+    parts, starts = [], [np.zeros(1, np.int64)]
+    off = 0
+    for u in units:
+        a, b = int(rs[u * NROW]), int(rs[(u + 1) * NROW])
+        parts.append((a, b))
+        starts.append(rs[u * NROW + 1:(u + 1) * NROW + 1] - a + off)
+        off += b - a
+    idx = np.concatenate([np.arange(a, b) for a, b in parts]) if parts else np.zeros(0, np.int64)
+    dep = {}
+    if ev.deposits:
+        # the deposits of the chosen units, renumbered to their new unit index
+        newu = np.full(int(ev.n_units), -1, np.int64)
+        newu[np.asarray(units, np.int64)] = np.arange(len(units))
+        m = newu[ev.deposits["unit"].astype(np.int64)] >= 0
+        dep = {k: v[m] for k, v in ev.deposits.items()}
+        dep["unit"] = newu[ev.deposits["unit"][m].astype(np.int64)].astype(
+            ev.deposits["unit"].dtype)
+        if "id" in dep:  # ids are positions; renumbering keeps their order
+            dep["id"] = np.arange(int(m.sum()), dtype=ev.deposits["id"].dtype)
+    return Event(ev.config, ev.pad[idx], ev.time[idx], ev.adc[idx],
+                 np.concatenate(starts).astype(np.uint32), len(units), ev.n_time_bins,
+                 ev.tracks, dep, None)
+
+
+PAGE_WORDS = 2048
+
+
+def zs_pages(ev: Event) -> np.ndarray:
+    """The event's samples packed into raw zero-suppressed pages (uint32
+    [n_pages, 2048]): the input format of the library's page decoder, as a
+    readout card would ship it.  One (unit, row) per page, runs of
+    consecutive pads per time bin, 10-bit ADC fields."""
+    lib = _load()
+    rs = np.ascontiguousarray(ev.row_start, np.uint32)
+    pad = np.ascontiguousarray(ev.pad, np.uint16)
+    time = np.ascontiguousarray(ev.time, np.uint16)
+    adc = np.ascontiguousarray(ev.adc, np.uint16)
+    n = lib.synth_pack_pages(ev.n_units, _ptr(rs), _ptr(pad), _ptr(time), _ptr(adc), None)
+    out = np.zeros((max(n, 0), PAGE_WORDS), np.uint32)
+    if n > 0:
+        lib.synth_pack_pages(ev.n_units, _ptr(rs), _ptr(pad), _ptr(time), _ptr(adc), _ptr(out))
+    return out

@@ -342,3 +342,64 @@ void synth_digitize_fetch(uint16_t* pad, uint16_t* time, uint16_t* adc) {
   g_rows = NULL;
   g_nrows = 0;
 }
+
+/* ------------------------------------------------------------ raw pages */
+/* Packs sorted zero-suppressed samples into the library's raw page format
+ * (8 KiB pages of 2048 little-endian words; header, run table, 10-bit ADC
+ * stream; the format is stated with tpc_decode_zs_pages).  One (unit,row)
+ * per page; a row continues on a new page when the next sample no longer
+ * fits.  Consecutive pads of one time bin form a run of up to 256 samples.
+ * out == NULL counts the pages only.  Returns the number of pages. */
+#define PG_WORDS 2048
+static void pg_flush(uint32_t* pg, int unit, int row, const uint32_t* runs, int nr,
+                     const uint16_t* adc, int ns) {
+  memset(pg, 0, PG_WORDS * sizeof(uint32_t));
+  pg[0] = 0x5A53u | (1u << 16);
+  pg[1] = (uint32_t)unit | ((uint32_t)row << 16);
+  pg[2] = (uint32_t)nr | ((uint32_t)ns << 16);
+  for (int i = 0; i < nr; ++i) pg[4 + i] = runs[i];
+  uint32_t* st = pg + 4 + nr;
+  for (int k = 0; k < ns; ++k) {
+    const uint64_t bit = (uint64_t)k * 10;
+    const uint64_t v = (uint64_t)(adc[k] & 0x3FF) << (bit & 31);
+    st[bit >> 5] |= (uint32_t)v;
+    if ((bit & 31) > 22) st[(bit >> 5) + 1] |= (uint32_t)(v >> 32);
+  }
+}
+
+int64_t synth_pack_pages(int32_t n_units, const uint32_t* row_start, const uint16_t* pad,
+                         const uint16_t* time, const uint16_t* adc, uint32_t* out) {
+  static uint32_t runs[PG_WORDS];
+  static uint16_t padc[PG_WORDS * 4];
+  int64_t np = 0;
+  for (int64_t ur = 0; ur < (int64_t)n_units * NROW; ++ur) {
+    const int unit = (int)(ur / NROW), row = (int)(ur % NROW);
+    int nr = 0, ns = 0;
+    int last_t = -1, last_p = -2, last_len = 0;
+    for (uint32_t s = row_start[ur]; s < row_start[ur + 1]; ++s) {
+      const int t = time[s], p = pad[s];
+      const int joins = nr > 0 && t == last_t && p == last_p + 1 && last_len < 256;
+      const int nr2 = nr + (joins ? 0 : 1);
+      if (4 + nr2 + (int)(((ns + 1) * 10 + 31) / 32) > PG_WORDS) {
+        if (out) pg_flush(out + np * PG_WORDS, unit, row, runs, nr, padc, ns);
+        ++np;
+        nr = ns = 0;
+      }
+      if (nr > 0 && t == last_t && p == last_p + 1 && last_len < 256) {
+        ++last_len;
+        runs[nr - 1] += 1u << 24;
+      } else {
+        runs[nr++] = (uint32_t)t | ((uint32_t)p << 16);
+        last_len = 1;
+      }
+      last_t = t;
+      last_p = p;
+      padc[ns++] = adc[s];
+    }
+    if (ns > 0) {
+      if (out) pg_flush(out + np * PG_WORDS, unit, row, runs, nr, padc, ns);
+      ++np;
+    }
+  }
+  return np;
+}

@@ -36,7 +36,6 @@ def cluster_labels(deposits: dict, clusters: dict, n_units: int) -> np.ndarray:
     labels = np.full(nc, -1, np.int64)
     if nc == 0 or len(deposits["mu_pad"]) == 0:
         return labels
-    best = np.full(nc, -np.inf)
     mu_p = deposits["mu_pad"]
     mu_t = deposits["mu_time"]
     pc = np.floor(mu_p + 0.5).astype(np.int64)
@@ -46,6 +45,7 @@ def cluster_labels(deposits: dict, clusters: dict, n_units: int) -> np.ndarray:
     did = deposits["id"].astype(np.int64)
     order = np.argsort(key_c)
     ks = key_c[order]
+    cs, vs, ds = [], [], []
     for dt in range(-2, 3):
         ft = _frac(mu_t, tc + dt)
         for dp in range(-2, 3):
@@ -56,14 +56,18 @@ def cluster_labels(deposits: dict, clusters: dict, n_units: int) -> np.ndarray:
             pos = np.searchsorted(ks, key)
             pos = np.minimum(pos, nc - 1)
             hit = ok & (ks[pos] == key)
-            ci = order[pos[hit]]
-            val = (q * _frac(mu_p, pp) * ft)[hit]
-            d = did[hit]
-            # process in deposit-id order so that ties keep the lower id
-            for c, v, dd in zip(ci, val, d):
-                if v > best[c] or (v == best[c] and dd < labels[c]):
-                    best[c] = v
-                    labels[c] = dd
+            cs.append(order[pos[hit]])
+            vs.append((q * _frac(mu_p, pp) * ft)[hit])
+            ds.append(did[hit])
+    c = np.concatenate(cs)
+    v = np.concatenate(vs)
+    d = np.concatenate(ds)
+    if len(c):
+        # per cluster: the largest expected charge, ties to the lower deposit id
+        srt = np.lexsort((d, -v, c))
+        first = np.ones(len(srt), bool)
+        first[1:] = c[srt][1:] != c[srt][:-1]
+        labels[c[srt][first]] = d[srt][first]
     return labels
 
 
@@ -85,23 +89,36 @@ def performance(deposits: dict, tracks: dict, clusters: dict, n_units: int,
     segs, counts = np.unique(seg_cl[seg_cl >= 0], return_counts=True)
     findable = set(segs[counts >= 20].tolist())
     matched = {}
-    n_fake = 0
-    for h in track_hits:
-        s = seg_cl[np.asarray(h, np.int64)]
-        s = s[s >= 0]
-        if len(s) == 0:
-            n_fake += 1
-            continue
-        vals, cnt = np.unique(s, return_counts=True)
-        j = np.argmax(cnt)
-        if cnt[j] >= 0.9 * len(h):
-            matched[vals[j]] = matched.get(vals[j], 0) + 1
-        else:
-            n_fake += 1
+    n_tr = len(track_hits)
+    lens = np.array([len(h) for h in track_hits], dtype=np.int64)
+    if n_tr and lens.sum():
+        hits = np.concatenate([np.asarray(h, np.int64) for h in track_hits])
+        tid = np.repeat(np.arange(n_tr, dtype=np.int64), lens)
+        sg = seg_cl[hits]
+        m = sg >= 0
+        tid, sg = tid[m], sg[m]
+        # per (track, segment) counts, then per track the largest count with
+        # ties to the smaller segment id
+        o = np.lexsort((sg, tid))
+        tid, sg = tid[o], sg[o]
+        new = np.ones(len(sg), bool)
+        new[1:] = (tid[1:] != tid[:-1]) | (sg[1:] != sg[:-1])
+        starts = np.nonzero(new)[0]
+        cnt = np.diff(np.append(starts, len(sg)))
+        t_run, s_run = tid[starts], sg[starts]
+        o2 = np.lexsort((s_run, -cnt, t_run))
+        first = np.ones(len(o2), bool)
+        first[1:] = t_run[o2][1:] != t_run[o2][:-1]
+        best_t, best_s, best_c = t_run[o2][first], s_run[o2][first], cnt[o2][first]
+        good = best_c >= 0.9 * lens[best_t]
+        gs, gc = np.unique(best_s[good], return_counts=True)
+        matched = dict(zip(gs.tolist(), gc.tolist()))
+        n_fake = n_tr - int(good.sum())
+    else:
+        n_fake = n_tr
     n_find = len(findable)
     n_match = sum(1 for s in findable if s in matched)
     clones = sum(max(0, matched[s] - 1) for s in findable if s in matched)
-    n_tr = len(track_hits)
     # split by primary/secondary and pT bin
     trk = np.array([s // 128 for s in findable], dtype=np.int64)
     ok = np.array([s in matched for s in findable], dtype=bool)
