@@ -111,27 +111,101 @@ def buffers(reco, ev, max_clusters, max_tracklets):
     return cl, links, tl, tr
 
 
-def cpu_baseline(ev, target_s=12.0):
-    """The oracle (full chain) on the whole slice, repeated until about
-    target_s seconds of host work, on the host's cores."""
-    import oracle
-
+def host_threads():
+    """Threads the oracle may use: the host's CPU share for one GPU.  The GPU
+    boxes give one GPU a share of 16 CPUs (whatever os.cpu_count() shows
+    there); a smaller affinity mask is honoured."""
     try:
         ncpu = len(os.sched_getaffinity(0))
     except AttributeError:
         ncpu = os.cpu_count() or 1
-    threads = max(1, min(16, ncpu))
+    return max(1, min(16, ncpu)), ncpu
+
+
+def _time_oracle(ev, threads, target_s, max_reps=50, noise=1.0):
+    """The oracle's full chain on ev, repeated until about target_s seconds."""
+    import oracle
+
+    params = oracle.default_params(noise)
     total_t, total_c, reps = 0.0, 0, 0
-    while total_t < target_s and reps < 50:
+    while (total_t < target_s or reps == 0) and reps < max_reps:
         t0 = time.perf_counter()
         res = oracle.process(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins,
-                             n_threads=threads)
+                             params=params, n_threads=threads)
         total_t += time.perf_counter() - t0
         total_c += len(res["clusters"]["y_fx"])
         reps += 1
-    return dict(value=total_c / total_t, unit="clusters/s", cores=threads, kind="oracle",
-                sample=f"full chain on the whole 2 ms slice (seed 303), {reps} repetition(s): "
-                       f"{total_c} clusters in {total_t:.1f} s")
+    return total_c / total_t, total_c, total_t, reps, res
+
+
+def stress_errors(gpu, res, floors=(1.0, 1.0, 1e-2, 1e-2, 0.1)):
+    """Per-parameter deviation of the GPU tracks from the FP64 oracle's, over
+    tracks of the same tracklet with the same kept hits: |gpu - oracle| /
+    max(|oracle|, floor), as median / p99 / max per parameter."""
+    fit = res["fit"]
+    kept = np.nonzero(fit["kept"])[0]
+    okept = set(kept.tolist())
+    owner = fit["cluster_owner"]
+    rels = []
+    same = 0
+    for j, t in enumerate(gpu["tracklet"]):
+        t = int(t)
+        if t not in okept:
+            continue
+        h = fit["hits"][t]
+        oh = h[h >= 0]
+        oh = np.sort(oh[owner[oh] == t])
+        gh = np.sort(gpu["hits"][gpu["hit_start"][j]:gpu["hit_start"][j + 1]])
+        if not np.array_equal(gh, oh):
+            continue
+        same += 1
+        op = fit["par"][t]
+        rels.append(np.abs(gpu["par"][j].astype(np.float64) - op) /
+                    np.maximum(np.abs(op), np.array(floors)))
+    out = dict(tracks_compared=same, gpu_tracks=len(gpu["tracklet"]), oracle_tracks=len(kept),
+               floors=list(floors))
+    if rels:
+        R = np.array(rels)
+        q = np.percentile(R, [50, 99, 100], axis=0)
+        for i, name in enumerate(("y", "z", "snp", "tgl", "qpt")):
+            out[name] = dict(median=float(q[0][i]), p99=float(q[1][i]), max=float(q[2][i]))
+    return out
+
+
+def cpu_baseline(ev, stress=None, target_s=10.0):
+    """The oracle as it stands, on the GPU machine's host cores: all threads of
+    one GPU's CPU share on the whole 2 ms slice (the reported value), one
+    thread on a bounded sample of its units, and both on one sector (C1) and
+    one central collision (C2).  With the precision-stress chunk's GPU tracks
+    (stress), the oracle also runs that chunk and the per-parameter deviation
+    of the FP32 GPU fit from its FP64 fit is reported beside the timing."""
+    import tpcsynth
+
+    threads, ncpu = host_threads()
+    v, nc, tt, reps, _ = _time_oracle(ev, threads, target_s)
+    out = dict(value=v, unit="clusters/s", cores=threads, kind="oracle",
+               sample=f"full chain on the whole 2 ms slice (seed 303), {reps} repetition(s): "
+                      f"{nc} clusters in {tt:.1f} s on {threads} threads "
+                      f"(host shows {ncpu} CPUs; one GPU's share is 16)")
+    sub = tpcsynth.select_units(ev, [0, 9, 18, 27])
+    v1, nc1, tt1, reps1, _ = _time_oracle(sub, 1, 0.0, max_reps=1)
+    out["single_thread"] = dict(value=v1, unit="clusters/s", cores=1,
+                                sample=f"4 of the slice's 36 sectors (0, 9, 18, 27), "
+                                       f"{nc1} clusters in {tt1:.1f} s")
+    for name, cfg, seed in (("c1", tpcsynth.config_c1(), 101), ("c2", tpcsynth.config_c2(), 202)):
+        e = tpcsynth.generate(cfg, seed)
+        va, nca, tta, ra, _ = _time_oracle(e, threads, 1.0)
+        vs, ncs, tts, rs_, _ = _time_oracle(e, 1, 1.0)
+        out[name] = dict(all_threads=va, single_thread=vs, unit="clusters/s",
+                         clusters=nca // ra, ms_all_threads=tta / ra * 1e3,
+                         ms_single_thread=tts / rs_ * 1e3)
+    if stress is not None:
+        sev, gpu = stress
+        vsx, ncx, ttx, rx, res = _time_oracle(sev, threads, 0.0, max_reps=1, noise=2.0)
+        out["precision_stress"] = dict(value=vsx, unit="clusters/s", cores=threads,
+                                       clusters=ncx, s=ttx,
+                                       error_vs_gpu=stress_errors(gpu, res))
+    return out
 
 
 def serve_leg(args, torch, tpcsynth, tuning):
@@ -184,13 +258,36 @@ def serve_leg(args, torch, tpcsynth, tuning):
     ncl = sum(j.counts["n_clusters"] for j in done)
     st = serve.latency_stats(done)
     ex.close()
+    # the plain per-chunk form on the same pool: one synchronous call per
+    # chunk, default launch shapes, no graph, one chunk on the GPU at a time
+    from paper_2208_07412_amd import tpc
+
+    ms_max = max(j.n_samples for j in pool)
+    reco = tpc.Reco(36, T, max_cl, max_tl, max_samples=ms_max)
+    bufs = (reco.alloc_clusters(36, T, max_cl), reco.alloc_links(max_cl),
+            reco.alloc_tracklets(max_tl), reco.alloc_tracks(max_tl, max_cl, max_cl))
+    plain_s, plain_c = 0.0, 0
+    for rep in range(2):
+        for j in pool:
+            bufs[0].s.n_time_bins = j.n_time_bins
+            t = time.perf_counter()
+            reco.process(j.zs, *bufs)
+            c = reco.sync()
+            if rep:
+                plain_s += time.perf_counter() - t
+                plain_c += c["n_clusters"]
+    reco.close()
     return dict(workload="Poisson stream of time-frame chunks, 10-200 minimum-bias collisions "
                          "each (100 n + 500 bins), seed 404", pool=len(pool), chunks=n,
                 slots=args.serve_slots, capacity_chunks_per_s=cap_chunks,
                 capacity_clusters_per_s=cap_clusters, rate_hz=rate, clusters_per_s=ncl / span,
                 p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], mean_ms=st["mean_ms"],
                 max_concurrent=sched.max_concurrent,
-                reruns=sum(j.retries for j in done))
+                reruns=sum(j.retries for j in done),
+                plain_chunks=dict(value=plain_c / plain_s, unit="clusters/s",
+                                  form="each pool chunk in one synchronous call, default "
+                                       "launch shapes, no graph"),
+                capacity_over_plain_chunks=cap_clusters / (plain_c / plain_s))
 
 
 def stress_leg(torch, tpcsynth, tpc, stream, n_coll=20):
@@ -207,6 +304,9 @@ def stress_leg(torch, tpcsynth, tpc, stream, n_coll=20):
     with torch.cuda.stream(stream):
         reco.process(zs, *b)
     c = reco.sync()
+    gtr = tpc.tracks_to_host(b[3], c["n_clusters"], 0)
+    gpu = dict(tracklet=gtr["tracklet"], par=gtr["par"], hits=gtr["hits"],
+               hit_start=gtr["hit_start"])
     reco.profile(True)
     with torch.cuda.stream(stream):
         for _ in range(3):
@@ -216,12 +316,73 @@ def stress_leg(torch, tpcsynth, tpc, stream, n_coll=20):
     reco.sync()
     reco.close()
     ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
-    return dict(workload=f"precision-stress chunk, {n_coll} collisions, seed 505",
-                samples=ev.n_samples, clusters=c["n_clusters"], tracks=c["n_tracks"],
-                fp64_refits=c["n_fallback"], fp64_rate=c["n_fallback"] / max(c["n_tracks"], 1),
-                fp64_not_pd=c["n_fallback_fail"], flagged_not_pd=c["n_not_pd"],
-                refit_ms=ms["refit"], fp64_count_ms=ms["fp64_count"],
-                total_ms=sum(ms.values()))
+    res = dict(workload=f"precision-stress chunk, {n_coll} collisions, seed 505",
+               samples=ev.n_samples, clusters=c["n_clusters"], tracks=c["n_tracks"],
+               fp64_refits=c["n_fallback"], fp64_rate=c["n_fallback"] / max(c["n_tracks"], 1),
+               fp64_not_pd=c["n_fallback_fail"], flagged_not_pd=c["n_not_pd"],
+               refit_ms=ms["refit"], fp64_count_ms=ms["fp64_count"],
+               total_ms=sum(ms.values()))
+    return res, (ev, gpu)
+
+
+def plain_sync(tpc, torch, reco, zs, b, stream, reps, warmup):
+    """Per-call wall latency of synchronous reconstructions (enqueue + sync)."""
+    lat = []
+    with torch.cuda.stream(stream):
+        for i in range(warmup + reps):
+            t = time.perf_counter()
+            reco.process(zs, *b)
+            c = reco.sync()
+            if i >= warmup:
+                lat.append(time.perf_counter() - t)
+    return np.array(lat), c
+
+
+def plain_latency(tpc, torch, tpcsynth, stream, dev, args, reps=50):
+    """One sector with 200 tracks (C1), one synchronous call at a time."""
+    ev = tpcsynth.generate(tpcsynth.config_c1(), 101)
+    mc = max(ev.n_samples // 4, 1 << 14)
+    mt = max(mc // 4, 1 << 12)
+    reco = make_reco(tpc, ev, stream, mc, mt, 1.0)
+    zs = tpc.to_device_zs(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins, dev)
+    b = buffers(reco, ev, mc, mt)
+    lat, c = plain_sync(tpc, torch, reco, zs, b, stream, reps, max(args.warmup, 2))
+    reco.close()
+    return dict(workload="one sector, 200 tracks (seed 101)", clusters=c["n_clusters"],
+                p50_ms=float(np.percentile(lat, 50) * 1e3),
+                p99_ms=float(np.percentile(lat, 99) * 1e3), calls=reps)
+
+
+def plain_collisions(tpc, torch, tpcsynth, stream, dev, cfg, seed=303):
+    """The plain form on the slice's work: each of its collisions (the same
+    multiplicities) as a frame of its own (500 bins, no pile-up), one
+    synchronous call each, default launch shapes, no graph."""
+    evs = []
+    for i, col in enumerate(cfg.collisions):
+        c1 = tpcsynth.EventConfig(f"C3-collision{i}", 500,
+                                  [tpcsynth.Collision(0.0, col.n_prim, col.n_sec)])
+        evs.append(tpcsynth.generate(c1, seed * 1000 + i))
+    ns_max = max(e.n_samples for e in evs)
+    mc = max(ns_max // 4, 1 << 16)
+    mt = max(mc // 4, 1 << 14)
+    reco = tpc.Reco(36, 500, mc, mt, stream=stream, max_samples=ns_max)
+    b = buffers(reco, evs[0], mc, mt)
+    zss = [tpc.to_device_zs(e.pad, e.time, e.adc, e.row_start, e.n_units, e.n_time_bins, dev)
+           for e in evs]
+    plain_sync(tpc, torch, reco, zss[0], b, stream, 0, 3)  # warm-up
+    total_s, total_c, lat = 0.0, 0, []
+    for zs in zss:
+        l, c = plain_sync(tpc, torch, reco, zs, b, stream, 1, 0)
+        total_s += float(l.sum())
+        total_c += c["n_clusters"]
+        lat.append(float(l[0]))
+    reco.close()
+    lat = np.array(lat)
+    return dict(workload="the 2 ms slice's 100 collisions, each alone in 500 bins "
+                         "(seed 303 multiplicities), one synchronous call each",
+                collisions=len(evs), clusters=total_c, value=total_c / total_s,
+                unit="clusters/s", s=total_s, p50_ms=float(np.percentile(lat, 50) * 1e3),
+                p99_ms=float(np.percentile(lat, 99) * 1e3))
 
 
 def main():
@@ -235,6 +396,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-form leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-stress", action="store_true", help="skip the precision-stress leg")
+    ap.add_argument("--no-h2d", action="store_true", help="skip the PCIe-inclusive figure")
     ap.add_argument("--collisions", type=int, default=100)
     ap.add_argument("--slices", type=int, nargs="*", default=[2, 3, 4],
                     help="unit slices on concurrent streams tried for the batched form")
@@ -411,12 +573,17 @@ def main():
     tn = tuning["chosen"] if tuning else {"cl_window": 16, "cl_chunk": 8}
     sb = stage_bytes(ns, nc, n_ur, ev.n_time_bins, tn["cl_window"])
     dom = max(stages, key=lambda k: stages[k])
-    ach = sb["cluster_peaks"] / (stages["cluster_peaks"] / 1e3) / 1e9
+    # algorithmic bytes of the clusterizer: the samples it reads (u16 pad,
+    # time, adc) and a 32-byte cluster record per cluster it produces
+    peak_bytes = 6 * ns + 32 * nc
+    ach = peak_bytes / (stages["cluster_peaks"] / 1e3) / 1e9
     kname = f"void k_cluster_peaks<{tn['cl_window']}, {tn['cl_chunk']},"
     roof_peaks = dict(bound="hbm", kernel="k_cluster_peaks", achieved=ach, peak=HBM_PEAK_GBS,
                       unit="GB/s", frac=ach / HBM_PEAK_GBS,
                       traffic=pmc_traffic(KERNEL_SOURCES["cluster_peaks"], "cluster_peaks", kname),
-                      bytes_per_launch=sb["cluster_peaks"], ms_per_launch=stages["cluster_peaks"])
+                      bytes_per_launch=peak_bytes, ms_per_launch=stages["cluster_peaks"],
+                      bytes_model="6 B per sample + 32 B per cluster",
+                      bytes_moved_by_design=sb["cluster_peaks"])
     flops = (FLOPS_STEP * fcounts["follow_steps"] + FLOPS_CAND * fcounts["follow_candidates"] +
              FLOPS_UPDATE * fcounts["follow_updates"])
     ach_f = flops / (stages["following"] / 1e3) / 1e12
@@ -448,6 +615,28 @@ def main():
                roofline=roofline, roofline_2=roofline_2, stages_ms=stages, qc=qc)
     if tuning is not None:
         out["tuning"] = tuning["chosen"]
+    # secondary throughput: the single-context graph preceded by the input's
+    # copy from pinned host memory on the same stream (PCIe included; not the
+    # metric, which takes the input resident in HBM)
+    if graph is not None and not args.no_h2d:
+        host = {k: zs[k].cpu().pin_memory() for k in ("pad", "time", "adc", "row_start")}
+        g_one = forms[1][1]
+
+        def with_h2d():
+            for k, v in host.items():
+                zs[k].copy_(v, non_blocking=True)
+            g_one()
+
+        h2d_ms, _ = time_steps(with_h2d, 3)
+        c3 = reco.sync()
+        assert c3["n_clusters"] == nc, "input copy changed the result"
+        h2d_bytes = sum(v.numel() * v.element_size() for v in host.values())
+        out["h2d_inclusive"] = dict(value=nc / (h2d_ms / 1e3), unit="clusters/s",
+                                    ms_per_step=h2d_ms, bytes_copied=h2d_bytes,
+                                    form="one context, one graph replay, input copied from "
+                                         "pinned host memory first")
+        log(f"[bench] h2d-inclusive: {out['h2d_inclusive']}")
+        del host
     del graph, forms
     if pl_best is not None:
         pl_best.close()
@@ -475,9 +664,14 @@ def main():
                             clusters=n2, value=n2 / lat.mean(), unit="clusters/s",
                             p50_ms=float(np.percentile(lat, 50) * 1e3),
                             p99_ms=float(np.percentile(lat, 99) * 1e3))
-        out["batched_over_plain"] = value / out["plain"]["value"]
         reco2.close()
         log(f"[bench] plain: {out['plain']}")
+        out["c1_latency"] = plain_latency(tpc, torch, tpcsynth, stream, dev, args)
+        log(f"[bench] c1 latency: {out['c1_latency']}")
+        out["plain_collisions"] = plain_collisions(tpc, torch, tpcsynth, stream, dev, cfg)
+        log(f"[bench] plain, the slice's collisions one call each: {out['plain_collisions']}")
+        out["batched_over_plain"] = value / out["plain_collisions"]["value"]
+        out["batched_over_plain_central"] = value / out["plain"]["value"]
     reco.close()
     del cl, links, tl, tr, zs
     torch.cuda.empty_cache()
@@ -486,13 +680,14 @@ def main():
         out["serving"] = serve_leg(args, torch, tpcsynth, tuning["chosen"] if tuning else None)
         log(f"[bench] serving: {out['serving']}")
 
+    stress = None
     if not args.no_stress:
-        out["precision_stress"] = stress_leg(torch, tpcsynth, tpc, stream)
+        out["precision_stress"], stress = stress_leg(torch, tpcsynth, tpc, stream)
         log(f"[bench] precision stress: {out['precision_stress']}")
 
     if not args.no_cpu:
         t = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(ev)
+        out["cpu_baseline"] = cpu_baseline(ev, stress)
         log(f"[bench] cpu baseline in {time.perf_counter() - t:.1f}s: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
