@@ -104,6 +104,9 @@ def _load():
     lib.oracle_seed.restype = ctypes.c_int
     lib.oracle_is_pd.argtypes = [P]
     lib.oracle_is_pd.restype = ctypes.c_int
+    lib.oracle_decode_zs_pages.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, P, P, P, P, ctypes.c_int64, P]
+    lib.oracle_decode_zs_pages.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -332,3 +335,27 @@ def qc_histograms(qtot, qmax, cluster_track, hit_start) -> np.ndarray:
                                                   minlength=NROW + 1)
     h[QC_ATTACH:QC_ATTACH + 2] = np.bincount((ct >= 0).astype(np.int64), minlength=2)
     return h
+
+
+ZS_PAGE_WORDS = 2048
+
+
+def decode_zs_pages(pages, n_units: int, n_time_bins: int, validate: bool = False,
+                    capacity: Optional[int] = None) -> dict:
+    """Raw zero-suppressed pages (uint32, n_pages x 2048 words) -> samples in
+    the clusterizer's input layout: pad, time, adc, row_start, and the status
+    (0; -3 malformed input; -2 more samples than `capacity`)."""
+    lib = _load()
+    pg = np.ascontiguousarray(pages, np.uint32).reshape(-1, ZS_PAGE_WORDS)
+    n_pages = pg.shape[0]
+    cap = int(n_pages * ZS_PAGE_WORDS * 32 // 10) if capacity is None else int(capacity)
+    pad = np.zeros(max(cap, 1), np.uint16)
+    time = np.zeros(max(cap, 1), np.uint16)
+    adc = np.zeros(max(cap, 1), np.uint16)
+    rs = np.zeros(n_units * NROW + 1, np.uint32)
+    n = ctypes.c_int64(0)
+    st = lib.oracle_decode_zs_pages(_p(pg), n_pages, n_units, n_time_bins, 1 if validate else 0,
+                                    _p(pad), _p(time), _p(adc), _p(rs), cap, ctypes.byref(n))
+    m = min(n.value, cap)
+    return dict(status=st, n_samples=n.value, pad=pad[:m].copy(), time=time[:m].copy(),
+                adc=adc[:m].copy(), row_start=rs)

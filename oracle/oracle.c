@@ -1096,3 +1096,74 @@ int oracle_is_pd(const double* C) {
     for (int j = 0; j < 5; ++j) M[i][j] = C[i * 5 + j];
   return is_pd(M);
 }
+
+/* ------------------------------------------------------- raw ZS pages */
+/* Decoder of the library's raw zero-suppressed page format (the paper,
+ * section "Hardware and data flow": zero suppression runs on the readout
+ * FPGA; the format itself is this project's): each 2048-word page holds a
+ * header (magic 0x5A53 | version 1 << 16; unit | row << 16; n_runs | n_samples
+ * << 16; 0), n_runs run words (time | first pad << 16 | (length - 1) << 24)
+ * and a stream of 10-bit ADC fields, sample k at bits [10k, 10k + 10).
+ * Samples are appended page by page, run by run, pad by pad.  Returns 0, -3
+ * for malformed input (header, pads beyond the row, time beyond the frame,
+ * run lengths not adding up, pages out of (unit,row) order; with validate
+ * also runs out of (time, pad) order and zero ADC values) or -2 when more
+ * than `capacity` samples result; *n_out is the sample count. */
+int oracle_decode_zs_pages(const uint32_t* pages, int64_t n_pages, int32_t n_units,
+                           int32_t n_time_bins, int32_t validate, uint16_t* pad, uint16_t* time,
+                           uint16_t* adc, uint32_t* row_start, int64_t capacity, int64_t* n_out) {
+  geometry_init();
+  int64_t n = 0, prev_ur = -1;
+  int64_t last_t = -1, last_end = 0; /* end pad (exclusive) of the last run of prev_ur */
+  int status = 0;
+  for (int64_t u = 0; u <= (int64_t)n_units * NROW; ++u) row_start[u] = 0;
+  for (int64_t p = 0; p < n_pages; ++p) {
+    const uint32_t* pg = pages + p * 2048;
+    const int64_t unit = pg[1] & 0xFFFF, row = (pg[1] >> 16) & 0xFF;
+    const int64_t nr = pg[2] & 0xFFFF, ns = pg[2] >> 16;
+    if (pg[0] != (0x5A53u | (1u << 16)) || (pg[1] >> 24) != 0 || pg[3] != 0 ||
+        unit >= n_units || row >= NROW || 4 + nr + (ns * 10 + 31) / 32 > 2048 ||
+        (nr > 0) != (ns > 0))
+      return -3;
+    const int64_t ur = unit * NROW + row;
+    if (ur < prev_ur) return -3;
+    if (ur != prev_ur) { /* rows between the previous page's and this one start here */
+      for (int64_t u = prev_ur + 1; u <= ur; ++u) row_start[u] = (uint32_t)n;
+      prev_ur = ur;
+      last_t = -1;
+      last_end = 0;
+    }
+    int64_t total = 0;
+    for (int64_t i = 0; i < nr; ++i) total += (pg[4 + i] >> 24) + 1;
+    if (total != ns) return -3;
+    const uint32_t* stream = pg + 4 + nr;
+    int64_t k = 0;
+    for (int64_t i = 0; i < nr; ++i) {
+      const uint32_t w = pg[4 + i];
+      const int64_t t = w & 0xFFFF, p0 = (w >> 16) & 0xFF, len = (w >> 24) + 1;
+      if (t >= n_time_bins || p0 + len > G_NP[row]) return -3;
+      if (validate && (t < last_t || (t == last_t && p0 < last_end))) return -3;
+      last_t = t;
+      last_end = p0 + len;
+      for (int64_t j = 0; j < len; ++j, ++k) {
+        /* bits [10k, 10k + 10) of the stream, least significant first */
+        uint32_t a = 0;
+        for (int b = 0; b < 10; ++b) {
+          const int64_t bit = 10 * k + b;
+          a |= ((stream[bit / 32] >> (bit % 32)) & 1u) << b;
+        }
+        if (validate && a == 0) return -3;
+        if (n < capacity) {
+          pad[n] = (uint16_t)(p0 + j);
+          time[n] = (uint16_t)t;
+          adc[n] = (uint16_t)a;
+        }
+        ++n;
+      }
+    }
+  }
+  for (int64_t u = prev_ur + 1; u <= (int64_t)n_units * NROW; ++u) row_start[u] = (uint32_t)n;
+  *n_out = n;
+  if (n > capacity) status = -2;
+  return status;
+}
