@@ -107,6 +107,39 @@ typedef struct {
   uint32_t n_time_bins;
 } tpc_zs_input;
 
+/* Raw zero-suppressed pages (section "Hardware and data flow": zero
+ * suppression runs in the user logic of the FPGA readout cards, and the EPNs
+ * receive the data of complete collisions).  The paper fixes no format; this
+ * one is the library's own.  A page is TPC_ZS_PAGE_WORDS little-endian 32-bit
+ * words (8 KiB) holding samples of one (unit, row):
+ *   word 0   0x5A53 | 1 << 16 (magic, version 1)
+ *   word 1   unit (bits 0-15) | row << 16 (bits 24-31 zero)
+ *   word 2   n_runs (bits 0-15) | n_samples << 16
+ *   word 3   0
+ *   words 4 .. 4 + n_runs - 1: runs, one word each:
+ *            time bin (bits 0-15) | first pad << 16 | (length - 1) << 24;
+ *            a run is `length` consecutive pads of one time bin
+ *   then the ADC values of the runs' samples in run order, as one stream of
+ *   10-bit fields: sample k occupies bits [10k, 10k + 10) of the stream (bit
+ *   b is bit b % 32 of the stream's word b / 32); the rest of the page is
+ *   padding.
+ * n_samples = sum of the run lengths, n_runs = 0 exactly when n_samples = 0,
+ * and 4 + n_runs + ceil(10 n_samples / 32) <= TPC_ZS_PAGE_WORDS.  Pages come
+ * in (unit, row) order, a (unit, row) may continue over several consecutive
+ * pages, and runs are in (time, pad) order without overlap; samples then come
+ * out sorted as tpc_zs_input requires.  ADC values are 1..1023. */
+#define TPC_ZS_PAGE_WORDS 2048
+
+/* Decoded samples: the layout of tpc_zs_input, written by the library. */
+typedef struct {
+  uint32_t capacity;          /* samples the three arrays hold */
+  uint32_t n_units;           /* units of the frame (set by the caller) */
+  uint32_t n_time_bins;       /* time bins of the frame (set by the caller) */
+  uint32_t* n_samples;        /* [1] device count written by the decoder */
+  uint16_t *pad, *time, *adc; /* [capacity] */
+  uint32_t* row_start;        /* [n_units*152 + 1] first sample of each (unit,row) */
+} tpc_zs_soa;
+
 /* Clusters in canonical order (unit, row, peak time, peak pad). */
 typedef struct {
   uint32_t capacity;          /* entries available in each per-cluster array */
@@ -205,31 +238,62 @@ int tpc_workspace_size(const tpc_sizes* max, size_t* bytes);
 int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* hip_stream);
 int tpc_destroy(tpc_ctx* ctx);
 
-/* Clusterizer: peaks are samples whose (adc, time, pad) key exceeds that of
+/* Decode n_pages raw pages (DEVICE pointer, n_pages * TPC_ZS_PAGE_WORDS
+ * words, caller-owned, read only) into out's arrays, in page order (section
+ * "Hardware and data flow": the readout cards zero-suppress, the EPNs
+ * reconstruct).  Writes *out->n_samples and row_start; the arrays then serve
+ * as a tpc_zs_input with n_samples = out->capacity (the device count bounds
+ * every row).  Always checked on the device (TPC_ERR_INPUT): the header of
+ * every page, runs inside the row's pads and the frame's time bins, run
+ * lengths adding up to the page's sample count, pages in (unit, row) order;
+ * with params.validate also the (time, pad) order of runs within and across
+ * pages and ADC values above zero.  A decoded count above out->capacity
+ * gives TPC_ERR_CAPACITY with the count needed in tpc_counts.required, and
+ * the pages that do not fit are not written.  Host errors (TPC_ERR_ARG):
+ * missing pointers, n_units or n_time_bins beyond the context's bounds,
+ * n_pages above max_samples / 16 + 152 * max_units. */
+int tpc_decode_zs_pages(tpc_ctx* ctx, const uint32_t* pages, uint32_t n_pages, tpc_zs_soa* out);
+
+/* Clusterizer.  Paper, section "Hardware and data flow": the EPNs run full
+ * online TPC track reconstruction on the data zero-suppressed in the readout
+ * FPGA; its first step turns the pad/time samples into clusters (the paper
+ * gives no algorithm; the rule below is the reading stated with the method).
+ * Peaks are samples whose (adc, time, pad) key exceeds that of
  * every present 8-neighbour and whose ADC reaches qmax_min; each sample joins
  * the peak it reaches in at most two uphill steps.  Writes n_clusters,
  * crow_start and every non-NULL per-cluster array.  in->n_samples must not
  * exceed the context's max_samples (TPC_ERR_ARG). */
 int tpc_cluster(tpc_ctx* ctx, const tpc_zs_input* in, tpc_clusters* out);
 
-/* For each cluster in rows 1..150: the pair (j in row r-1, k in row r+1)
+/* Cellular-automaton neighbour finding (same passage: the tracking step of
+ * the full reconstruction; the rule is this build's reading).
+ * For each cluster in rows 1..150: the pair (j in row r-1, k in row r+1)
  * inside the windows minimising (2y_i-y_j-y_k)^2 + (2z_i-z_j-z_k)^2 <= s_max,
  * ties to the smaller (j, k).  Writes down/up. */
 int tpc_find_neighbours(tpc_ctx* ctx, const tpc_clusters* cl, tpc_links* links);
 
-/* Keeps reciprocal links (downc/upc) and emits chains of at least
+/* Tracklet seeding (same passage; reading as above).
+ * Keeps reciprocal links (downc/upc) and emits chains of at least
  * min_tracklet clusters that start at a cluster without a cleaned down-link. */
 int tpc_build_tracklets(tpc_ctx* ctx, const tpc_clusters* cl, tpc_links* links,
                         tpc_tracklets* out);
 
-/* Kalman following (outward pass A, inward pass B), conflict resolution
+/* Track fit (same passage: the track reconstruction that TPC calibration
+ * and compression rely on; the Kalman filter of a helix in a uniform field is
+ * this build's reading).
+ * Kalman following (outward pass A, inward pass B), conflict resolution
  * (each cluster kept by the track with the most hits, then the lower
  * tracklet id) and the inward FP32 refit with FP64 fallback for low-pT
  * tracks whose covariance loses positive definiteness. */
 int tpc_fit_tracks(tpc_ctx* ctx, const tpc_clusters* cl, const tpc_links* links,
                    const tpc_tracklets* tl, tpc_tracks* out);
 
-/* The four stages in one launch sequence on the context's stream. */
+/* The four stages in one launch sequence on the context's stream (section
+ * "Hardware and data flow": the full TPC processing of complete collisions on
+ * the GPU; section "Software": intermediate results stay on the GPU, no
+ * transfer between steps).  Arguments, errors and ownership as for the four
+ * calls above; the input must satisfy tpc_cluster's contract and the outputs
+ * the capacities of each stage (TPC_ERR_ARG otherwise). */
 int tpc_process_timeframe(tpc_ctx* ctx, const tpc_zs_input* in, tpc_clusters* cl,
                           tpc_links* links, tpc_tracklets* tl, tpc_tracks* tr);
 
@@ -291,8 +355,8 @@ void* tpc_stream(tpc_ctx* ctx);
  * 3 cluster output, 4 cluster grid, 5 neighbours, 6 tracklets (and their
  * seed points, timed inside the fit call), 7 following (sorts and passes),
  * 8 resolution, 9 refit (FP64 head, FP32, FP64 redo), 10 count of the FP64
- * redos, 11 track output. */
-#define TPC_PROF_STAGES 12
+ * redos, 11 track output, 12 raw ZS page decoding (tpc_decode_zs_pages). */
+#define TPC_PROF_STAGES 13
 int tpc_profile_enable(tpc_ctx* ctx, int on);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, uint32_t* launches);
 const char* tpc_profile_stage_name(int stage);

@@ -19,6 +19,7 @@
 #include "k_links.hpp"
 #include "k_track.hpp"
 #include "k_qc.hpp"
+#include "k_zspage.hpp"
 
 namespace {
 
@@ -85,6 +86,7 @@ struct tpc_ctx {
   uint32_t* trk_index = nullptr;
   uint32_t* hit_off = nullptr;
   uint32_t* qc_part = nullptr;   // per-workgroup QC histograms
+  uint32_t* zp_off = nullptr;    // output offset of each raw ZS page
   size_t bsum_cap = 0;
   tpc_tuning tune;
   // stage timing (measurement only)
@@ -111,10 +113,16 @@ struct Layout {
 
 struct Plan {
   size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
-      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, hit_off, par, st, total;
+      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, hit_off, par, st, total;
   size_t bsum_cap;
   uint32_t nblk, nblk_s, nwin;
 };
+
+// Most raw ZS pages one call may decode: far more than any packing of
+// max_samples needs (a full page holds over 1,500 samples).
+uint64_t max_pages(const tpc_sizes& m) {
+  return (uint64_t)m.max_samples / 16 + (uint64_t)NROW * m.max_units;
+}
 
 Plan plan_for(const tpc_sizes& m) {
   Plan p;
@@ -126,6 +134,7 @@ Plan plan_for(const tpc_sizes& m) {
   uint64_t nscan = nur * p.nwin;
   if (m.max_clusters > nscan) nscan = m.max_clusters;
   if (m.max_tracklets > nscan) nscan = m.max_tracklets;
+  if (max_pages(m) > nscan) nscan = max_pages(m);
   if (256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + XCD_GROUPS - 1) > nscan)
     nscan = 256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + XCD_GROUPS - 1);
   p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
@@ -163,6 +172,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.trk_index = L.add<uint32_t>(mt);
   p.hit_off = L.add<uint32_t>(mt);
   p.qc_part = L.add<uint32_t>((uint64_t)QC_WG * QC_BINS);
+  p.zp_off = L.add<uint32_t>(max_pages(m) + 1);
   p.par = L.add<DevParams>(1);
   p.st = L.add<DevStatus>(1);
   p.total = (L.off + 255) & ~(size_t)255;
@@ -713,6 +723,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->trk_index = (uint32_t*)(base + pl.trk_index);
   c->hit_off = (uint32_t*)(base + pl.hit_off);
   c->qc_part = (uint32_t*)(base + pl.qc_part);
+  c->zp_off = (uint32_t*)(base + pl.zp_off);
   c->d_par = (DevParams*)(base + pl.par);
   c->d_st = (DevStatus*)(base + pl.st);
   c->bsum_cap = pl.bsum_cap;
@@ -741,6 +752,31 @@ int tpc_destroy(tpc_ctx* c) {
   (void)hipFree(c->zblk);
   delete c;
   return TPC_OK;
+}
+
+int tpc_decode_zs_pages(tpc_ctx* c, const uint32_t* pages, uint32_t n_pages, tpc_zs_soa* out) {
+  if (!c || !out || !out->n_samples || !out->row_start || (n_pages && !pages)) return TPC_ERR_ARG;
+  if (check_units(c, out->n_units, out->n_time_bins)) return TPC_ERR_ARG;
+  if (out->capacity && (!out->pad || !out->time || !out->adc)) return TPC_ERR_ARG;
+  if (n_pages > max_pages(c->max)) return TPC_ERR_ARG;
+  hipStream_t s = c->stream;
+  const uint32_t n_ur = out->n_units * NROW;
+  StageTimer tm(c, 12);
+  if (n_pages == 0) {
+    k_fill<uint32_t><<<grid_for(n_ur + 1, 256), 256, 0, s>>>(out->row_start, 0u, n_ur + 1);
+    k_fill<uint32_t><<<1, 64, 0, s>>>(out->n_samples, 0u, 1);
+    return launch_ok();
+  }
+  run_scan<uint32_t>(c, GetPageSamples{pages, out->n_units}, EmitPageOffset{c->zp_off}, nullptr,
+                     n_pages, (uint32_t*)nullptr, c->tot32);
+  const uint32_t g = n_pages < 4096 ? n_pages : 4096;
+  k_zs_decode<<<g, ZSP_BLOCK, 0, s>>>(pages, n_pages, out->n_units, out->n_time_bins, c->zp_off,
+                                      out->capacity, out->pad, out->time, out->adc, c->d_par,
+                                      c->d_st);
+  k_zs_rows<<<grid_for((uint64_t)n_pages + 1, 256), 256, 0, s>>>(
+      pages, n_pages, out->n_units, c->zp_off, c->tot32, out->capacity, out->row_start,
+      out->n_samples, c->d_st);
+  return launch_ok();
 }
 
 int tpc_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
@@ -932,7 +968,7 @@ const char* tpc_profile_stage_name(int i) {
   static const char* names[TPC_PROF_STAGES] = {
       "sample_index", "cluster_peaks", "cluster_scan", "cluster_output", "cluster_grid",
       "neighbours", "tracklets", "following", "resolution", "refit", "fp64_count",
-      "track_output"};
+      "track_output", "zs_decode"};
   return (i >= 0 && i < TPC_PROF_STAGES) ? names[i] : "unknown";
 }
 

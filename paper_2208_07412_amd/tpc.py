@@ -48,6 +48,11 @@ class TpcZsInput(ctypes.Structure):
                 ("n_units", U32), ("n_time_bins", U32)]
 
 
+class TpcZsSoa(ctypes.Structure):
+    _fields_ = [("capacity", U32), ("n_units", U32), ("n_time_bins", U32), ("n_samples", P),
+                ("pad", P), ("time", P), ("adc", P), ("row_start", P)]
+
+
 class TpcClusters(ctypes.Structure):
     _fields_ = [("capacity", U32), ("n_units", U32), ("n_time_bins", U32), ("n_clusters", P),
                 ("crow_start", P), ("y_fx", P), ("z_fx", P), ("dpad", P), ("dtime", P),
@@ -93,8 +98,8 @@ EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_crea
            "tpc_fit_tracks", "tpc_process_timeframe", "tpc_sync", "tpc_stream",
            "tpc_status_string", "tpc_profile_enable", "tpc_profile_read",
            "tpc_profile_stage_name", "tpc_tuning_default", "tpc_set_tuning", "tpc_get_tuning",
-           "tpc_qc_histograms", "tpc_qc_histograms_noalloc"]
-PROF_STAGES = 12
+           "tpc_qc_histograms", "tpc_qc_histograms_noalloc", "tpc_decode_zs_pages"]
+PROF_STAGES = 13
 # quality-control histogram layout (bin offsets; see tpc_qc_histograms)
 QC_QTOT, QC_QMAX, QC_NHITS, QC_ATTACH, QC_BINS = 0, 256, 512, 665, 667
 
@@ -125,6 +130,7 @@ def load():
     lib.tpc_process_timeframe.argtypes = [P, P, P, P, P, P]
     lib.tpc_qc_histograms.argtypes = [P, P, P, P]
     lib.tpc_qc_histograms_noalloc.argtypes = [P, P, P, P]
+    lib.tpc_decode_zs_pages.argtypes = [P, P, U32, P]
     lib.tpc_sync.argtypes = [P, P]
     lib.tpc_stream.argtypes = [P]
     lib.tpc_stream.restype = P
@@ -327,7 +333,30 @@ class Reco:
             "z_anchor", "hit_start", "hits", "cluster_track", "follow_hits")])
         return Buffers(t, s)
 
+    def alloc_zs_soa(self, n_units: int, n_time_bins: int, capacity: int) -> Buffers:
+        """Device arrays for decoded raw pages (tpc_zs_soa)."""
+        torch = _torch()
+        d = self.device
+        e = lambda n, dt: torch.empty(max(n, 1), dtype=dt, device=d)
+        t = dict(n_samples=torch.zeros(1, dtype=torch.int32, device=d),
+                 pad=e(capacity, torch.int16), time=e(capacity, torch.int16),
+                 adc=e(capacity, torch.int16), row_start=e(n_units * NROW + 1, torch.int32))
+        s = TpcZsSoa(int(capacity), n_units, n_time_bins,
+                     *[_dptr(t[k]) for k in ("n_samples", "pad", "time", "adc", "row_start")])
+        return Buffers(t, s)
+
     # ------------------------------------------------------------ calls
+    def decode_zs_pages(self, pages, out: Buffers, n_pages: Optional[int] = None):
+        """Raw zero-suppressed pages (device tensor of n_pages * 2048 32-bit
+        words) -> out's sample arrays and row offsets (tpc_decode_zs_pages)."""
+        if n_pages is None:
+            n_pages = pages.numel() // ZS_PAGE_WORDS
+        if pages.numel() < n_pages * ZS_PAGE_WORDS or pages.element_size() != 4 or not pages.is_cuda:
+            raise ValueError("decode_zs_pages: pages must be a device tensor of 32-bit words")
+        _check(self.lib.tpc_decode_zs_pages(self.ctx, ctypes.c_void_p(pages.data_ptr()),
+                                            int(n_pages), ctypes.byref(out.s)),
+               "tpc_decode_zs_pages")
+
     def cluster(self, zs: dict, out: Buffers):
         _check(self.lib.tpc_cluster(self.ctx, ctypes.byref(zs_struct(zs)), ctypes.byref(out.s)),
                "tpc_cluster")
@@ -412,6 +441,32 @@ class Reco:
 
 
 # ---------------------------------------------------------------- host views
+ZS_PAGE_WORDS = 2048
+
+
+def zs_from_soa(soa: Buffers) -> dict:
+    """Decoded pages as a clusterizer input: the arrays hold up to
+    `capacity` samples and the device row offsets bound every row."""
+    t, s = soa.t, soa.s
+    return dict(pad=t["pad"], time=t["time"], adc=t["adc"], row_start=t["row_start"],
+                n_samples=int(s.capacity), n_units=int(s.n_units), n_time_bins=int(s.n_time_bins))
+
+
+def pages_to_device(pages, device="cuda"):
+    """Host pages (uint32 [n_pages, 2048]) as a device tensor of 32-bit words."""
+    torch = _torch()
+    a = np.ascontiguousarray(pages, np.uint32).reshape(-1)
+    return torch.from_numpy(a.view(np.int32)).to(device)
+
+
+def zs_soa_to_host(b: Buffers) -> dict:
+    n = int(b["n_samples"].item())
+    m = min(n, int(b.s.capacity))
+    return dict(n_samples=n, pad=_u(b["pad"], m, np.uint16), time=_u(b["time"], m, np.uint16),
+                adc=_u(b["adc"], m, np.uint16),
+                row_start=_u(b["row_start"], int(b.s.n_units) * NROW + 1, np.uint32))
+
+
 QC_NOALLOC_MAX = 1024 * 65536
 
 

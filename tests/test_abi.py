@@ -98,7 +98,8 @@ def test_struct_layouts_match_header(tmp_path):
     # every field offset and struct size of the binding against the header,
     # as the C compiler lays them out
     structs = {"tpc_params": tpc.TpcParams, "tpc_sizes": tpc.TpcSizes,
-               "tpc_zs_input": tpc.TpcZsInput, "tpc_clusters": tpc.TpcClusters,
+               "tpc_zs_input": tpc.TpcZsInput, "tpc_zs_soa": tpc.TpcZsSoa,
+               "tpc_clusters": tpc.TpcClusters,
                "tpc_links": tpc.TpcLinks, "tpc_tracklets": tpc.TpcTracklets,
                "tpc_tracks": tpc.TpcTracks, "tpc_counts": tpc.TpcCounts,
                "tpc_tuning": tpc.TpcTuning}
