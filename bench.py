@@ -397,6 +397,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-stress", action="store_true", help="skip the precision-stress leg")
     ap.add_argument("--no-h2d", action="store_true", help="skip the PCIe-inclusive figure")
+    ap.add_argument("--no-pages", action="store_true", help="skip the raw-page decoding figure")
     ap.add_argument("--collisions", type=int, default=100)
     ap.add_argument("--slices", type=int, nargs="*", default=[2, 3, 4],
                     help="unit slices on concurrent streams tried for the batched form")
@@ -503,6 +504,37 @@ def main():
               clusters=int(qc_hist[tpc.QC_QTOT:tpc.QC_QTOT + 256].sum().item()),
               tracks=int(qc_hist[tpc.QC_NHITS:tpc.QC_NHITS + 153].sum().item()))
     log(f"[bench] qc histograms: {qc}")
+
+    # raw zero-suppressed pages of the slice decoded on the GPU (HIP events on
+    # the library's stream); algorithmic bytes: the pages read, 6 B written per
+    # sample, the row offsets written
+    if not args.no_pages:
+        t = time.perf_counter()
+        pages = tpcsynth.zs_pages(ev)
+        pg_dev = tpc.pages_to_device(pages, dev)
+        n_pages = pages.shape[0]
+        del pages
+        soa = reco.alloc_zs_soa(ev.n_units, ev.n_time_bins, ns)
+        with torch.cuda.stream(stream):
+            reco.decode_zs_pages(pg_dev, soa)
+        reco.sync()
+        reco.profile(True)
+        with torch.cuda.stream(stream):
+            for _ in range(5):
+                reco.decode_zs_pages(pg_dev, soa)
+        zprof = reco.profile_read()
+        reco.profile(False)
+        zc = reco.sync()
+        assert int(soa["n_samples"].item()) == ns
+        z_ms = zprof["zs_decode"][0] / max(zprof["zs_decode"][1], 1)
+        z_bytes = n_pages * 8192 + 6 * ns + 4 * (ev.n_units * 152 + 1)
+        out_pages = dict(pages=n_pages, page_bytes=n_pages * 8192, samples=ns, ms=z_ms,
+                         bytes=z_bytes, gb_per_s=z_bytes / z_ms / 1e6,
+                         hbm_frac=z_bytes / z_ms / 1e6 / HBM_PEAK_GBS)
+        log(f"[bench] zs page decode ({time.perf_counter() - t:.1f}s): {out_pages}")
+        del pg_dev, soa
+    else:
+        out_pages = None
 
     # the batched form: one context over the whole slice, or the slice's units
     # cut into n slices on n streams (pipeline.Pipeline), each captured as one
@@ -613,6 +645,8 @@ def main():
                            slices=n_slices, slice_start=start_pt, slice_ms=form_ms,
                            samples=ns, clusters=nc, tracks=counts["n_tracks"]),
                roofline=roofline, roofline_2=roofline_2, stages_ms=stages, qc=qc)
+    if out_pages is not None:
+        out["zs_pages"] = out_pages
     if tuning is not None:
         out["tuning"] = tuning["chosen"]
     # secondary throughput: the single-context graph preceded by the input's
