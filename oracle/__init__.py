@@ -107,6 +107,14 @@ def _load():
     lib.oracle_decode_zs_pages.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int32, P, P, P, P, ctypes.c_int64, P]
     lib.oracle_decode_zs_pages.restype = ctypes.c_int
+    lib.oracle_compress.argtypes = [P, ctypes.c_int32] + [P] * 6 + [ctypes.c_int64] + [P] * 6 + \
+        [P, ctypes.c_int64, P, P]
+    lib.oracle_compress.restype = ctypes.c_int
+    lib.oracle_decompress.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64] + [P] * 8
+    lib.oracle_decompress.restype = ctypes.c_int64
+    lib.oracle_track_model.argtypes = [P, P, ctypes.c_int32, ctypes.c_int, ctypes.c_int, P, P, P,
+                                       P]
+    lib.oracle_track_model.restype = None
     _lib = lib
     return lib
 
@@ -359,3 +367,101 @@ def decode_zs_pages(pages, n_units: int, n_time_bins: int, validate: bool = Fals
     m = min(n.value, cap)
     return dict(status=st, n_samples=n.value, pad=pad[:m].copy(), time=time[:m].copy(),
                 adc=adc[:m].copy(), row_start=rs)
+
+
+def tracks_from_fit(res: dict) -> dict:
+    """The oracle's kept tracks in the library's output layout: ascending
+    tracklet order, parameters rounded to float32, kept hits in ascending
+    row, z anchor (drift z of the tracklet start), and the cluster -> track
+    map."""
+    fit = res["fit"]
+    cl = res["clusters"]
+    ts = res["tracklets"]["tl_start"]
+    owner = fit["cluster_owner"]
+    kept = np.nonzero(fit["kept"])[0]
+    hs, hits = [0], []
+    for t in kept:
+        h = fit["hits"][t]
+        h = h[h >= 0]  # one per row, ascending row
+        h = h[owner[h] == t]
+        hits.append(h)
+        hs.append(hs[-1] + len(h))
+    idx = np.full(len(fit["kept"]), -1, np.int64)
+    idx[kept] = np.arange(len(kept))
+    ct = np.where(owner >= 0, idx[np.maximum(owner, 0)], -1).astype(np.int32)
+    return dict(tracklet=kept.astype(np.uint32), par=fit["par"][kept].astype(np.float32),
+                row=fit["row"][kept].astype(np.uint8),
+                z_anchor=cl["z_fx"][ts[kept]].astype(np.int32),
+                hit_start=np.array(hs, np.uint32),
+                hits=(np.concatenate(hits) if hits else np.zeros(0)).astype(np.uint32),
+                cluster_track=ct)
+
+
+def compress(clusters: dict, tracks: dict, n_units: int, params: Optional[dict] = None,
+             capacity_words: Optional[int] = None) -> dict:
+    """Track-model compression of a frame's clusters: the stream (uint32
+    words), its status (0; -2 capacity; -3 input the format cannot hold) and
+    the residual histograms (bins [0,128) y, [128,256) z)."""
+    lib = _load()
+    op = make_params(params)
+    crow = np.ascontiguousarray(clusters["crow_start"], np.uint32)
+    y = np.ascontiguousarray(clusters["y_fx"], np.int32)
+    z = np.ascontiguousarray(clusters["z_fx"], np.int32)
+    qt = np.ascontiguousarray(clusters["qtot"], np.uint16)
+    qm = np.ascontiguousarray(clusters["qmax"], np.uint16)
+    fl = np.ascontiguousarray(clusters["flags"], np.uint8)
+    n_tr = len(tracks["hit_start"]) - 1
+    par = np.ascontiguousarray(tracks["par"], np.float32).reshape(-1)
+    za = np.ascontiguousarray(tracks["z_anchor"], np.int32)
+    row = np.ascontiguousarray(tracks["row"], np.uint8)
+    hs = np.ascontiguousarray(tracks["hit_start"], np.uint32)
+    hits = np.ascontiguousarray(tracks["hits"], np.uint32)
+    ct = np.ascontiguousarray(tracks["cluster_track"], np.int32)
+    nc = len(y)
+    cap = capacity_words if capacity_words is not None else \
+        64 + (n_tr + 1) + n_units * NROW + 1 + (nc * 200 + n_tr * 200) // 32
+    out = np.zeros(max(cap, 1), np.uint32)
+    hist = np.zeros(256, np.int64)
+    nw = ctypes.c_int64(0)
+    st = lib.oracle_compress(ctypes.byref(op), n_units, _p(crow), _p(y), _p(z), _p(qt), _p(qm),
+                             _p(fl), n_tr, _p(par), _p(za), _p(row), _p(hs), _p(hits), _p(ct),
+                             _p(out), cap, ctypes.byref(nw), _p(hist))
+    return dict(status=st, words=out[:nw.value].copy() if st == 0 else None,
+                n_words=nw.value, hist=hist)
+
+
+def decompress(words, params: Optional[dict] = None, capacity: Optional[int] = None) -> dict:
+    """Decoded clusters in stream order (unit, row, quantised y_fx and z_fx,
+    qtot, qmax, flags, track index or -1); status = count, or -2 / -3."""
+    lib = _load()
+    op = make_params(params)
+    w = np.ascontiguousarray(words, np.uint32)
+    nc = int(w[4]) if len(w) > 4 else 0
+    cap = nc if capacity is None else capacity
+    m = max(cap, 1)
+    out = dict(unit=np.zeros(m, np.uint16), row=np.zeros(m, np.uint8),
+               y_fx=np.zeros(m, np.int32), z_fx=np.zeros(m, np.int32),
+               qtot=np.zeros(m, np.uint16), qmax=np.zeros(m, np.uint16),
+               flags=np.zeros(m, np.uint8), track=np.zeros(m, np.int32))
+    n = lib.oracle_decompress(ctypes.byref(op), _p(w), len(w), cap,
+                              *[_p(out[k]) for k in ("unit", "row", "y_fx", "z_fx", "qtot",
+                                                      "qmax", "flags", "track")])
+    res = {k: v[:max(n, 0)].copy() for k, v in out.items()}
+    res["status"] = int(n) if n < 0 else 0
+    return res
+
+
+def track_model(par, z_anchor: int, row0: int, rows, params: Optional[dict] = None):
+    """The codec's integer helix at the given rows (ascending): y, z in
+    2^-16 cm and whether the model had stopped (|sin phi| near 1)."""
+    lib = _load()
+    op = make_params(params)
+    p = np.ascontiguousarray(par, np.float32)
+    rows = np.ascontiguousarray(rows, np.int32)
+    n = len(rows)
+    y = np.zeros(n, np.int64)
+    z = np.zeros(n, np.int64)
+    fr = np.zeros(n, np.int32)
+    lib.oracle_track_model(ctypes.byref(op), _p(p), int(z_anchor), int(row0), n, _p(rows), _p(y),
+                           _p(z), _p(fr))
+    return y, z, fr

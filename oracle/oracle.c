@@ -1167,3 +1167,363 @@ int oracle_decode_zs_pages(const uint32_t* pages, int64_t n_pages, int32_t n_uni
   if (n > capacity) status = -2;
   return status;
 }
+
+/* ------------------------------------------- track-model cluster compression */
+/* The paper (section "Hardware and data flow") says data compression relies on
+ * the TPC tracking; it gives no codec.  Reading (the library's own format,
+ * stated with tpc_compress): cluster positions are quantised to 2^-7 cm; a
+ * cluster on a track is stored as its residual to the track model, an integer
+ * helix evaluated row by row from the fitted parameters; clusters on no track
+ * are stored per (unit,row) with the drift position relative to the previous
+ * one.  Every value is an Exp-Golomb code in an LSB-first bit stream, so the
+ * whole stream is integer arithmetic and decodes to the quantised clusters
+ * whatever the model predicts.  Returns -3 for input the format cannot hold
+ * (a track hit below the row of its parameters). */
+#define CM_MAGIC 0x54434D31u
+#define CM_HDR 8
+
+static int64_t cm_q(int64_t v) { return floor_div(v + 256, 512); } /* 2^-7 cm steps */
+
+static int64_t cm_isqrt(int64_t n) { /* floor(sqrt(n)), n >= 0 */
+  int64_t r = (int64_t)sqrt((double)n);
+  while (r > 0 && r * r > n) --r;
+  while ((r + 1) * (r + 1) <= n) ++r;
+  return r;
+}
+
+static uint64_t cm_zig(int64_t v) { return v >= 0 ? (uint64_t)v * 2 : (uint64_t)(-v) * 2 - 1; }
+static int64_t cm_unzig(uint64_t u) { return (u & 1) ? -(int64_t)((u + 1) / 2) : (int64_t)(u / 2); }
+
+/* Integer helix of one track: fixed-point state at the current row. */
+typedef struct {
+  int64_t Y, Z, S, T, C; /* y, z in 2^-16 cm; sin phi, tan lambda in 2^-30; C in 2^-46 / cm */
+  int row, frozen;
+} cm_model;
+
+/* The model's integers from the fitted float32 parameters: each value scaled
+ * by a power of two (exact) and rounded to the nearest integer, ties to even. */
+static void cm_model_init(cm_model* m, const oparams* par, const float p[5], int32_t z_anchor,
+                          int row, int64_t* Yo, int64_t* Zo, int64_t* So, int64_t* To,
+                          int64_t* Ko) {
+  int64_t S = (int64_t)rint((double)p[2] * 1073741824.0);
+  int64_t T = (int64_t)rint((double)p[3] * 1073741824.0);
+  int64_t K = (int64_t)rint((double)p[4] * 65536.0);
+  const int64_t lim = ((int64_t)1 << 30) - 1;
+  if (S > lim) S = lim;
+  if (S < -lim) S = -lim;
+  if (T > 4 * lim) T = 4 * lim;
+  if (T < -4 * lim) T = -4 * lim;
+  if (K > 20 * 65536) K = 20 * 65536;
+  if (K < -20 * 65536) K = -20 * 65536;
+  *Yo = (int64_t)rint((double)p[0] * 65536.0);
+  *Zo = (int64_t)rint((double)p[1] * 65536.0) + z_anchor;
+  *So = S;
+  *To = T;
+  *Ko = K;
+  m->Y = *Yo;
+  m->Z = *Zo;
+  m->S = S;
+  m->T = T;
+  m->C = -(int64_t)llrint(par->bz_b * 1073741824.0) * K;
+  m->row = row;
+  m->frozen = 0;
+}
+
+static void cm_model_from_ints(cm_model* m, const oparams* par, int64_t Y, int64_t Z, int64_t S,
+                               int64_t T, int64_t K, int row) {
+  m->Y = Y;
+  m->Z = Z;
+  m->S = S;
+  m->T = T;
+  m->C = -(int64_t)llrint(par->bz_b * 1073741824.0) * K;
+  m->row = row;
+  m->frozen = 0;
+}
+
+/* a / d rounded to the nearest integer, halves up (d > 0) */
+static int64_t cm_rdiv(int64_t a, int64_t d) { return floor_div(2 * a + d, 2 * d); }
+
+/* One row outward: exact helix step in fixed point (chord for the drift
+ * length), every quotient rounded to the nearest unit.  The model stops
+ * changing once |sin phi| would reach 1 - 2^-10. */
+static void cm_model_step(cm_model* m) {
+  const int a = m->row;
+  m->row = a + 1;
+  if (m->frozen || a + 1 >= NROW) return;
+  const int64_t D = G_XFX[a + 1] - G_XFX[a];
+  const int64_t S1 = m->S + cm_rdiv(m->C * D, (int64_t)1 << 32);
+  const int64_t smax = ((int64_t)1 << 30) - ((int64_t)1 << 20);
+  if (S1 >= smax || S1 <= -smax) {
+    m->frozen = 1;
+    return;
+  }
+  const int64_t one = (int64_t)1 << 60;
+  const int64_t c0 = cm_isqrt(one - m->S * m->S), c1 = cm_isqrt(one - S1 * S1);
+  const int64_t F = cm_rdiv((m->S + S1) * ((int64_t)1 << 24), c0 + c1);
+  m->Y += cm_rdiv(D * F, (int64_t)1 << 24);
+  const int64_t L = cm_rdiv(D * cm_isqrt(((int64_t)1 << 48) + F * F), (int64_t)1 << 24);
+  m->Z += cm_rdiv(m->T * L, (int64_t)1 << 30);
+  m->S = S1;
+}
+
+/* LSB-first bit stream: bit b is bit b % 32 of word b / 32. */
+typedef struct {
+  uint32_t* w;
+  int64_t cap_bits, pos;
+  int over;
+} cm_writer;
+
+static void cm_put(cm_writer* b, uint64_t v, int n) {
+  for (int i = 0; i < n; ++i, ++b->pos) {
+    if (b->pos >= b->cap_bits) {
+      b->over = 1;
+      continue;
+    }
+    if ((v >> i) & 1) b->w[b->pos / 32] |= 1u << (b->pos % 32);
+  }
+}
+
+/* Exp-Golomb code of order k: with q = (v >> k) + 1 and n = floor(log2 q),
+ * n zero bits, a one bit, the n low bits of q, then the k low bits of v. */
+static void cm_eg(cm_writer* b, uint64_t v, int k) {
+  const uint64_t q = (v >> k) + 1;
+  int n = 0;
+  while ((q >> (n + 1)) != 0) ++n;
+  cm_put(b, 0, n);
+  cm_put(b, 1, 1);
+  cm_put(b, q, n);
+  cm_put(b, v, k);
+}
+
+typedef struct {
+  const uint32_t* w;
+  int64_t n_bits, pos;
+  int bad;
+} cm_reader;
+
+static uint64_t cm_get(cm_reader* r, int n) {
+  uint64_t v = 0;
+  for (int i = 0; i < n; ++i, ++r->pos) {
+    if (r->pos >= r->n_bits) {
+      r->bad = 1;
+      continue;
+    }
+    v |= (uint64_t)((r->w[r->pos / 32] >> (r->pos % 32)) & 1u) << i;
+  }
+  return v;
+}
+
+static uint64_t cm_geteg(cm_reader* r, int k) {
+  int n = 0;
+  while (!r->bad && cm_get(r, 1) == 0) {
+    if (++n > 40) {
+      r->bad = 1;
+      return 0;
+    }
+  }
+  const uint64_t q = ((uint64_t)1 << n) | cm_get(r, n);
+  return ((q - 1) << k) | cm_get(r, k);
+}
+
+static void cm_cluster_fields(cm_writer* b, uint16_t qtot, uint16_t qmax, uint8_t flags) {
+  cm_eg(b, qtot, 6);
+  cm_eg(b, qmax, 5);
+  cm_put(b, flags & 3, 2);
+}
+
+/* Writes the stream into out (zeroed here, out_cap words) and, when hist is
+ * given, the residual histograms (bins [0,128) y, [128,256) z; residual d in
+ * 2^-7 cm at bin clamp(d, -64, 63) + 64).  Returns 0, or -2 when the stream
+ * needs more than out_cap words; *n_words is the size it needs. */
+int oracle_compress(const oparams* par, int32_t n_units, const uint32_t* crow_start,
+                    const int32_t* y_fx, const int32_t* z_fx, const uint16_t* qtot,
+                    const uint16_t* qmax, const uint8_t* flags, int64_t n_tracks,
+                    const float* tpar, const int32_t* z_anchor, const uint8_t* trow,
+                    const uint32_t* hit_start, const uint32_t* hits, const int32_t* cluster_track,
+                    uint32_t* out, int64_t out_cap, int64_t* n_words, int64_t* hist) {
+  geometry_init();
+  const int64_t n_ur = (int64_t)n_units * NROW;
+  const int64_t nc = crow_start[n_ur];
+  const int64_t dir = CM_HDR + (n_tracks + 1) + (n_ur + 1);
+  if (hist)
+    for (int i = 0; i < 256; ++i) hist[i] = 0;
+  /* pass 1 counts the bits, pass 2 writes them */
+  int64_t total_bits = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t need = dir + (total_bits + 31) / 32;
+    if (pass == 1) {
+      *n_words = need;
+      if (need > out_cap) return -2;
+      for (int64_t i = 0; i < need; ++i) out[i] = 0;
+      out[0] = CM_MAGIC;
+      out[1] = 1;
+      out[2] = (uint32_t)n_units;
+      out[3] = (uint32_t)n_tracks;
+      out[4] = (uint32_t)nc;
+      out[5] = n_tracks ? hit_start[n_tracks] : 0;
+      out[6] = (uint32_t)total_bits;
+      out[7] = 0;
+    }
+    uint32_t scratch = 0;
+    cm_writer b = {pass ? out + dir : &scratch, pass ? (need - dir) * 32 : 0, 0, 0};
+    for (int64_t j = 0; j < n_tracks; ++j) {
+      if (pass) out[CM_HDR + j] = (uint32_t)b.pos;
+      const uint32_t h0 = hit_start[j], h1 = hit_start[j + 1];
+      int64_t u = 0;
+      if (h1 > h0) { /* the unit of the first hit's (unit,row) */
+        int64_t lo = 0, hi = n_ur; /* crow_start[lo] <= c < crow_start[hi] */
+        const int64_t c = hits[h0];
+        while (hi - lo > 1) {
+          const int64_t mid = (lo + hi) / 2;
+          if ((int64_t)crow_start[mid] <= c) lo = mid;
+          else hi = mid;
+        }
+        u = lo / NROW;
+      }
+      cm_model m;
+      int64_t Y, Z, S, T, K;
+      cm_model_init(&m, par, tpar + 5 * j, z_anchor[j], trow[j], &Y, &Z, &S, &T, &K);
+      cm_put(&b, h1 - h0, 8);
+      cm_put(&b, (uint64_t)u, 16);
+      cm_put(&b, trow[j], 8);
+      cm_put(&b, (uint64_t)(uint32_t)(int32_t)Y, 32);
+      cm_put(&b, (uint64_t)(uint32_t)(int32_t)Z, 32);
+      cm_put(&b, (uint64_t)(uint32_t)(int32_t)S, 32);
+      cm_put(&b, (uint64_t)(uint32_t)(int32_t)T, 32);
+      cm_put(&b, (uint64_t)(uint32_t)(int32_t)K, 32);
+      int prev = trow[j];
+      for (uint32_t h = h0; h < h1; ++h) {
+        const int64_t c = hits[h];
+        int64_t lo = 0, hi = n_ur;
+        while (hi - lo > 1) {
+          const int64_t mid = (lo + hi) / 2;
+          if ((int64_t)crow_start[mid] <= c) lo = mid;
+          else hi = mid;
+        }
+        const int r = (int)(lo % NROW);
+        if (r - prev - (h > h0 ? 1 : 0) < 0) return -3; /* hits ascend from the model's row */
+        cm_eg(&b, (uint64_t)(r - prev - (h > h0 ? 1 : 0)), 0);
+        prev = r;
+        while (m.row < r) cm_model_step(&m);
+        const int64_t dy = cm_q(y_fx[c]) - cm_q(m.Y), dz = cm_q(z_fx[c]) - cm_q(m.Z);
+        cm_eg(&b, cm_zig(dy), 2);
+        cm_eg(&b, cm_zig(dz), 2);
+        cm_cluster_fields(&b, qtot[c], qmax[c], flags[c]);
+        if (hist && pass == 1) {
+          hist[(dy < -64 ? -64 : dy > 63 ? 63 : dy) + 64]++;
+          hist[128 + (dz < -64 ? -64 : dz > 63 ? 63 : dz) + 64]++;
+        }
+      }
+    }
+    if (pass) out[CM_HDR + n_tracks] = (uint32_t)b.pos;
+    for (int64_t ur = 0; ur < n_ur; ++ur) {
+      if (pass) out[CM_HDR + n_tracks + 1 + ur] = (uint32_t)b.pos;
+      int64_t n = 0;
+      for (int64_t c = crow_start[ur]; c < (int64_t)crow_start[ur + 1]; ++c) n += cluster_track[c] < 0;
+      cm_eg(&b, (uint64_t)n, 0);
+      int64_t zprev = 0, first = 1;
+      for (int64_t c = crow_start[ur]; c < (int64_t)crow_start[ur + 1]; ++c) {
+        if (cluster_track[c] >= 0) continue;
+        const int64_t zq = cm_q(z_fx[c]);
+        cm_eg(&b, cm_zig(cm_q(y_fx[c])), 10);
+        if (first) cm_eg(&b, cm_zig(zq), 12);
+        else cm_eg(&b, cm_zig(zq - zprev), 6);
+        first = 0;
+        zprev = zq;
+        cm_cluster_fields(&b, qtot[c], qmax[c], flags[c]);
+      }
+    }
+    if (pass) out[CM_HDR + n_tracks + 1 + n_ur] = (uint32_t)b.pos;
+    total_bits = b.pos;
+    if (total_bits > 0xFFFFFFFFll) return -2; /* offsets are 32-bit */
+  }
+  return 0;
+}
+
+/* Decodes a stream into clusters in stream order: the tracks' hits (track by
+ * track, ascending row), then the clusters on no track per (unit,row).
+ * Positions are the quantised ones (q * 512 in 2^-16 cm); track[i] is the
+ * track index or -1.  Returns the number of clusters, -3 for a malformed
+ * stream, -2 when more than cap clusters result. */
+int64_t oracle_decompress(const oparams* par, const uint32_t* in, int64_t n_words, int64_t cap,
+                          uint16_t* unit, uint8_t* row, int32_t* y_fx, int32_t* z_fx,
+                          uint16_t* qtot, uint16_t* qmax, uint8_t* flags, int32_t* track) {
+  geometry_init();
+  if (n_words < CM_HDR || in[0] != CM_MAGIC || in[1] != 1 || in[7] != 0) return -3;
+  const int64_t n_units = in[2], n_tracks = in[3], nc = in[4];
+  const int64_t n_ur = n_units * NROW;
+  const int64_t dir = CM_HDR + (n_tracks + 1) + (n_ur + 1);
+  if (dir > n_words || (int64_t)in[6] > (n_words - dir) * 32) return -3;
+  if (nc > cap) return -2;
+  cm_reader r = {in + dir, in[6], 0, 0};
+  int64_t k = 0;
+  for (int64_t j = 0; j < n_tracks; ++j) {
+    if (r.pos != in[CM_HDR + j]) return -3;
+    const int64_t nh = cm_get(&r, 8);
+    const int64_t u = cm_get(&r, 16);
+    const int r0 = (int)cm_get(&r, 8);
+    const int64_t Y = (int32_t)cm_get(&r, 32), Z = (int32_t)cm_get(&r, 32);
+    const int64_t S = (int32_t)cm_get(&r, 32), T = (int32_t)cm_get(&r, 32);
+    const int64_t K = (int32_t)cm_get(&r, 32);
+    if (u >= n_units || r0 >= NROW) return -3;
+    cm_model m;
+    cm_model_from_ints(&m, par, Y, Z, S, T, K, r0);
+    int prev = r0;
+    for (int64_t h = 0; h < nh; ++h) {
+      const int rr = prev + (int)cm_geteg(&r, 0) + (h > 0 ? 1 : 0);
+      if (rr >= NROW || k >= nc) return -3;
+      prev = rr;
+      while (m.row < rr) cm_model_step(&m);
+      const int64_t yq = cm_q(m.Y) + cm_unzig(cm_geteg(&r, 2));
+      const int64_t zq = cm_q(m.Z) + cm_unzig(cm_geteg(&r, 2));
+      unit[k] = (uint16_t)u;
+      row[k] = (uint8_t)rr;
+      y_fx[k] = (int32_t)(yq * 512);
+      z_fx[k] = (int32_t)(zq * 512);
+      qtot[k] = (uint16_t)cm_geteg(&r, 6);
+      qmax[k] = (uint16_t)cm_geteg(&r, 5);
+      flags[k] = (uint8_t)cm_get(&r, 2);
+      track[k] = (int32_t)j;
+      ++k;
+    }
+  }
+  for (int64_t ur = 0; ur < n_ur; ++ur) {
+    if (r.pos != in[CM_HDR + n_tracks + 1 + ur]) return -3;
+    if (ur == 0 && r.pos != in[CM_HDR + n_tracks]) return -3;
+    const int64_t n = cm_geteg(&r, 0);
+    int64_t zprev = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      if (k >= nc) return -3;
+      const int64_t yq = cm_unzig(cm_geteg(&r, 10));
+      const int64_t zq = i == 0 ? cm_unzig(cm_geteg(&r, 12)) : zprev + cm_unzig(cm_geteg(&r, 6));
+      zprev = zq;
+      unit[k] = (uint16_t)(ur / NROW);
+      row[k] = (uint8_t)(ur % NROW);
+      y_fx[k] = (int32_t)(yq * 512);
+      z_fx[k] = (int32_t)(zq * 512);
+      qtot[k] = (uint16_t)cm_geteg(&r, 6);
+      qmax[k] = (uint16_t)cm_geteg(&r, 5);
+      flags[k] = (uint8_t)cm_get(&r, 2);
+      track[k] = -1;
+      ++k;
+    }
+  }
+  if (r.bad || r.pos != (int64_t)in[6] || k != nc) return -3;
+  return k;
+}
+
+/* The integer track model at the rows of a list (for the pins): positions in
+ * 2^-16 cm after stepping from row0 to each row (rows ascending). */
+void oracle_track_model(const oparams* par, const float* p, int32_t z_anchor, int row0, int n,
+                        const int32_t* rows, int64_t* y, int64_t* z, int32_t* frozen) {
+  geometry_init();
+  cm_model m;
+  int64_t Y, Z, S, T, K;
+  cm_model_init(&m, par, p, z_anchor, row0, &Y, &Z, &S, &T, &K);
+  for (int i = 0; i < n; ++i) {
+    while (m.row < rows[i]) cm_model_step(&m);
+    y[i] = m.Y;
+    z[i] = m.Z;
+    frozen[i] = m.frozen;
+  }
+}
