@@ -505,6 +505,43 @@ def main():
               tracks=int(qc_hist[tpc.QC_NHITS:tpc.QC_NHITS + 153].sum().item()))
     log(f"[bench] qc histograms: {qc}")
 
+    # track-model compression of the slice's outputs and its decoding (HIP
+    # events on the library's stream).  Algorithmic bytes: per cluster y, z,
+    # qtot, qmax, flags and its track (17 B) read, per track its parameters,
+    # row, anchor and offsets (29 B) and 4 B per hit, the stream written;
+    # decoding reads the stream and writes 20 B per cluster.
+    comp = reco.alloc_compressed(max(nc, 1) * 2)
+    dec = reco.alloc_decoded(max(nc, 1))
+    with torch.cuda.stream(stream):
+        reco.compress(cl, tr, comp)
+        reco.decompress(comp["stream"], dec)
+    reco.sync()
+    reco.profile(True)
+    with torch.cuda.stream(stream):
+        for _ in range(5):
+            reco.compress(cl, tr, comp)
+            reco.decompress(comp["stream"], dec)
+    cprof = reco.profile_read()
+    reco.profile(False)
+    reco.sync()
+    n_words = int(comp["n_words"].item())
+    n_hits_c = int(tr["n_hits"].item())
+    c_ms = cprof["compress"][0] / max(cprof["compress"][1], 1)
+    d_ms = cprof["decompress"][0] / max(cprof["decompress"][1], 1)
+    c_bytes = 17 * nc + 29 * n_trk + 4 * n_hits_c + 4 * n_words
+    d_bytes = 4 * n_words + 20 * nc
+    out_comp = dict(stream_bytes=4 * n_words, bytes_per_cluster=4 * n_words / max(nc, 1),
+                    ratio_vs_cluster_arrays=33 * nc / (4 * n_words),
+                    ratio_vs_zs_samples=6 * ns / (4 * n_words),
+                    compress_ms=c_ms, compress_gb_per_s=c_bytes / c_ms / 1e6,
+                    compress_hbm_frac=c_bytes / c_ms / 1e6 / HBM_PEAK_GBS,
+                    decompress_ms=d_ms, decompress_gb_per_s=d_bytes / d_ms / 1e6,
+                    decompress_hbm_frac=d_bytes / d_ms / 1e6 / HBM_PEAK_GBS,
+                    residual_hist_y_within_8_steps=float(
+                        comp["res_hist"][56:72].sum().item() / max(n_hits_c, 1)))
+    log(f"[bench] compression: {out_comp}")
+    del comp, dec
+
     # raw zero-suppressed pages of the slice decoded on the GPU (HIP events on
     # the library's stream); algorithmic bytes: the pages read, 6 B written per
     # sample, the row offsets written
@@ -647,6 +684,7 @@ def main():
                roofline=roofline, roofline_2=roofline_2, stages_ms=stages, qc=qc)
     if out_pages is not None:
         out["zs_pages"] = out_pages
+    out["compression"] = out_comp
     if tuning is not None:
         out["tuning"] = tuning["chosen"]
     # secondary throughput: the single-context graph preceded by the input's

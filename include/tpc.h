@@ -336,6 +336,84 @@ int tpc_qc_histograms(tpc_ctx* ctx, const tpc_clusters* cl, const tpc_tracks* tr
 int tpc_qc_histograms_noalloc(const tpc_clusters* cl, const tpc_tracks* tr, uint32_t* hist,
                               void* hip_stream);
 
+/* Track-model cluster compression (section "Hardware and data flow": TPC
+ * data compression relies on the information from the TPC tracking).  The
+ * paper fixes no codec; this one is the library's own, all integer:
+ *   positions  q(v) = floor((v + 256) / 512): y_fx, z_fx in steps of 2^-7 cm
+ *   model      per track, from its float32 parameters p at row r0 = tr->row
+ *              and its z anchor A: Y = rne(p[0] 2^16), Z = rne(p[1] 2^16) + A,
+ *              S = rne(p[2] 2^30) (|S| <= 2^30 - 1), T = rne(p[3] 2^30)
+ *              (|T| <= 4 (2^30 - 1)), K = rne(p[4] 2^16) (|K| <= 20 * 2^16),
+ *              rne = to the nearest integer, ties to even; C = -rne(bz_b 2^30) K.
+ *              A step from row a to a + 1, with D = X_fx[a+1] - X_fx[a] and
+ *              [x / d] = floor((2x + d) / (2d)) (nearest, halves up):
+ *                S1 = S + [C D / 2^32]; if |S1| >= 2^30 - 2^20 the model stops
+ *                (no later step changes it); else c = isqrt(2^60 - S^2),
+ *                c1 = isqrt(2^60 - S1^2), F = [(S + S1) 2^24 / (c + c1)],
+ *                Y += [D F / 2^24], L = [D isqrt(2^48 + F^2) / 2^24],
+ *                Z += [T L / 2^30], S = S1 (isqrt = floor of the root).
+ *   codes      bit b of the stream is bit b % 32 of its word b / 32; an n-bit
+ *              field holds its value least significant bit first; EG(k) of v:
+ *              with q = (v >> k) + 1 and n = floor(log2 q): n zero bits, a one,
+ *              the n low bits of q, the k low bits of v; signed values are
+ *              zigzag-mapped (v >= 0: 2v, else -2v - 1).
+ *   stream     words 0-7: 0x54434D31, 1, n_units, n_tracks, n_clusters,
+ *              hits on tracks, payload bits, 0; then n_tracks + 1 bit offsets
+ *              of the track records (the last = end of the tracks), then
+ *              n_units * 152 + 1 bit offsets of the row blocks (the last = end
+ *              of the payload), then the payload words.
+ *   track      n_hits (8 bits), unit (16), r0 (8), Y, Z, S, T, K (32 each, two's
+ *              complement); per hit in ascending row: EG(0) of the row step
+ *              (r - r0 for the first hit, r - r_prev - 1 after), with the
+ *              model stepped to r: EG(2) of zig(q(y) - q(Y)), EG(2) of
+ *              zig(q(z) - q(Z)), then the cluster fields.
+ *   row block  per (unit, row): EG(0) of the number of clusters on no track,
+ *              then each in canonical order: EG(10) of zig(q(y)), EG(12) of
+ *              zig(q(z)) for the first, EG(6) of zig(q(z) - q(z_prev)) after,
+ *              then the cluster fields.
+ *   cluster    EG(6) of qtot, EG(5) of qmax, flags (2 bits).
+ * Decoding gives every cluster's quantised position (within 2^-8 cm of the
+ * original), its charges, flags and track, whatever the model predicts. */
+typedef struct {
+  uint32_t capacity;          /* words of stream[] */
+  uint32_t* stream;           /* [capacity] output */
+  uint32_t* n_words;          /* [1] device: words the stream needs (also on overflow) */
+  uint32_t* res_hist;         /* optional [256]: residuals of the clusters on
+                                 tracks, q(y) - q(Y) at bin clamp(d, -64, 63) + 64,
+                                 q(z) - q(Z) at 128 + the same (NULL to skip) */
+} tpc_compressed;
+
+/* Encode a reconstruction's clusters and tracks (the outputs of
+ * tpc_process_timeframe or equivalent; tracks in any order, each with its
+ * hits in ascending row from tr->row on).  Reads cl->y_fx, z_fx, qtot, qmax,
+ * flags, crow_start, n_clusters and tr->par, row, z_anchor, hit_start, hits,
+ * cluster_track, n_tracks.  Errors: TPC_ERR_ARG (missing pointers, a track
+ * capacity above the context's max_tracklets), TPC_ERR_CAPACITY (the stream
+ * needs more than out->capacity words, or more than 2^32 - 1 payload bits;
+ * *out->n_words and tpc_counts.required give the words needed),
+ * TPC_ERR_INPUT (a hit below its track's row). */
+int tpc_compress(tpc_ctx* ctx, const tpc_clusters* cl, const tpc_tracks* tr, tpc_compressed* out);
+
+/* Decoded clusters, in stream order: the tracks' hits (track by track,
+ * ascending row), then the clusters on no track per (unit, row). */
+typedef struct {
+  uint32_t capacity;
+  uint32_t* n_clusters;       /* [1] device count (the header's) */
+  uint16_t* unit;
+  uint8_t* row;
+  int32_t *y_fx, *z_fx;       /* quantised: q(v) * 512 */
+  uint16_t *qtot, *qmax;
+  uint8_t* flags;
+  int32_t* track;             /* track record index, -1 for none */
+} tpc_decoded_clusters;
+
+/* Decode a stream of stream_words words (DEVICE pointer).  TPC_ERR_INPUT for
+ * a malformed stream (header, directory, codes, a record not ending where the
+ * next begins, more units than max_units or tracks than max_tracklets),
+ * TPC_ERR_CAPACITY when it holds more than out->capacity clusters. */
+int tpc_decompress(tpc_ctx* ctx, const uint32_t* stream, uint32_t stream_words,
+                   tpc_decoded_clusters* out);
+
 /* Wait for the stream, then report the first latched error and the counts.
  * Clears the status word for the next call. */
 int tpc_sync(tpc_ctx* ctx, tpc_counts* counts);
@@ -355,8 +433,9 @@ void* tpc_stream(tpc_ctx* ctx);
  * 3 cluster output, 4 cluster grid, 5 neighbours, 6 tracklets (and their
  * seed points, timed inside the fit call), 7 following (sorts and passes),
  * 8 resolution, 9 refit (FP64 head, FP32, FP64 redo), 10 count of the FP64
- * redos, 11 track output, 12 raw ZS page decoding (tpc_decode_zs_pages). */
-#define TPC_PROF_STAGES 13
+ * redos, 11 track output, 12 raw ZS page decoding (tpc_decode_zs_pages),
+ * 13 compression (tpc_compress), 14 decompression (tpc_decompress). */
+#define TPC_PROF_STAGES 15
 int tpc_profile_enable(tpc_ctx* ctx, int on);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, uint32_t* launches);
 const char* tpc_profile_stage_name(int stage);

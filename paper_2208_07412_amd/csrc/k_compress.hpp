@@ -1,0 +1,674 @@
+// Track-model cluster compression (encoder and decoder) and the track-cluster
+// residual histograms.
+//
+// Format (stated field by field in include/tpc.h): a header, a directory of
+// bit offsets (one per track record, one per (unit,row) block of clusters on
+// no track) and an LSB-first bit stream of Exp-Golomb codes.  Positions are
+// quantised to 2^-7 cm; a cluster on a track is coded as its residual to an
+// integer helix evaluated row by row from the track's fitted parameters, so
+// every value in the stream is integer arithmetic and decoding gives the
+// quantised clusters whatever the model predicts.
+//
+// Encoder: one lane per track computes its record's length (and the residual
+// histograms); one wave per (unit,row) the lengths of its clusters on no
+// track; two device scans turn the lengths into the directory; a finishing
+// kernel writes the header and checks the capacity; the payload is cleared
+// and written again by the same lanes, each lane accumulating its bits and
+// storing whole words (atomic OR only because the first and last word of a
+// record may be shared with a neighbour).  Decoder: the record sizes come
+// from the directory and the fixed-width hit counts, a scan gives the output
+// offsets, and one lane per record decodes it.
+#pragma once
+
+#include "common.hpp"
+
+#define CM_MAGIC 0x54434D31u
+#define CM_HDR 8
+#define CM_QSHIFT 9  // positions quantised to 2^(9-16) cm
+
+// ---------------------------------------------------------------- arithmetic
+__device__ __forceinline__ int64_t cm_q(int64_t v) { return (v + 256) >> CM_QSHIFT; }
+
+// a / 2^k rounded to the nearest integer, halves up (arithmetic shift = floor)
+__device__ __forceinline__ int64_t cm_rshift(int64_t a, int k) {
+  return (a + ((int64_t)1 << (k - 1))) >> k;
+}
+// a / d rounded to the nearest integer, halves up (d > 0)
+__device__ __forceinline__ int64_t cm_rdiv(int64_t a, int64_t d) {
+  return floor_div64(2 * a + d, 2 * d);
+}
+// floor(sqrt(n)), n >= 0: the double square root, then exact corrections
+__device__ __forceinline__ int64_t cm_isqrt(int64_t n) {
+  int64_t r = (int64_t)sqrt((double)n);
+  while (r > 0 && r * r > n) --r;
+  while ((r + 1) * (r + 1) <= n) ++r;
+  return r;
+}
+__device__ __forceinline__ uint64_t cm_zig(int64_t v) {
+  return v >= 0 ? (uint64_t)v << 1 : ((uint64_t)(-v) << 1) - 1;
+}
+__device__ __forceinline__ int64_t cm_unzig(uint64_t u) {
+  return (u & 1) ? -(int64_t)((u + 1) >> 1) : (int64_t)(u >> 1);
+}
+// length of the order-k Exp-Golomb code of v
+__device__ __forceinline__ uint32_t cm_eg_len(uint64_t v, int k) {
+  const uint64_t q = (v >> k) + 1;
+  const uint32_t n = 63 - __builtin_clzll(q);
+  return 2 * n + 1 + k;
+}
+
+// Integer helix of one track (y, z in 2^-16 cm; sin phi, tan lambda in 2^-30;
+// C in 2^-46 per cm), stepped outward one row at a time.
+struct CmModel {
+  int64_t Y, Z, S, T, C;
+  int row;
+  bool frozen;
+};
+
+struct CmParams {  // the track's integers as stored in its record
+  int64_t Y, Z, S, T, K;
+};
+
+// From the float32 parameters: each scaled by a power of two (exact) and
+// rounded to the nearest integer, ties to even.
+__device__ __forceinline__ CmParams cm_params(const float* p, int32_t z_anchor) {
+  CmParams m;
+  const int64_t lim = ((int64_t)1 << 30) - 1;
+  int64_t S = (int64_t)rintf(p[2] * 1073741824.0f);
+  int64_t T = (int64_t)rintf(p[3] * 1073741824.0f);
+  int64_t K = (int64_t)rintf(p[4] * 65536.0f);
+  S = S > lim ? lim : (S < -lim ? -lim : S);
+  T = T > 4 * lim ? 4 * lim : (T < -4 * lim ? -4 * lim : T);
+  K = K > 20 * 65536 ? 20 * 65536 : (K < -20 * 65536 ? -20 * 65536 : K);
+  m.Y = (int64_t)rintf(p[0] * 65536.0f);
+  m.Z = (int64_t)rintf(p[1] * 65536.0f) + z_anchor;
+  m.S = S;
+  m.T = T;
+  m.K = K;
+  return m;
+}
+
+__device__ __forceinline__ CmModel cm_model(const CmParams& q, int64_t b30, int row) {
+  return CmModel{q.Y, q.Z, q.S, q.T, -b30 * q.K, row, false};
+}
+
+__device__ __forceinline__ void cm_step(CmModel& m, const int32_t* xfx) {
+  const int a = m.row;
+  m.row = a + 1;
+  if (m.frozen || a + 1 >= NROW) return;
+  const int64_t D = (int64_t)xfx[a + 1] - xfx[a];
+  const int64_t S1 = m.S + cm_rshift(m.C * D, 32);
+  const int64_t smax = ((int64_t)1 << 30) - ((int64_t)1 << 20);
+  if (S1 >= smax || S1 <= -smax) {
+    m.frozen = true;
+    return;
+  }
+  const int64_t one = (int64_t)1 << 60;
+  const int64_t c0 = cm_isqrt(one - m.S * m.S), c1 = cm_isqrt(one - S1 * S1);
+  const int64_t F = cm_rdiv((m.S + S1) * ((int64_t)1 << 24), c0 + c1);
+  m.Y += cm_rshift(D * F, 24);
+  const int64_t L = cm_rshift(D * cm_isqrt(((int64_t)1 << 48) + F * F), 24);
+  m.Z += cm_rshift(m.T * L, 30);
+  m.S = S1;
+}
+
+// (unit,row) of cluster c: the last entry of crow[0..n_ur) not above c
+__device__ __forceinline__ uint32_t cm_find_ur(const uint32_t* crow, uint32_t n_ur, uint32_t c) {
+  uint32_t lo = 0, hi = n_ur;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (crow[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------- bit writing
+// One lane's sequential writer over a contiguous bit range: completed words
+// are OR-ed into the (cleared) stream, the last partial word at the end.
+struct CmWriter {
+  uint32_t* w;
+  uint64_t limit;  // payload words (no store beyond them, whatever the lengths)
+  uint64_t pos;
+  uint64_t acc;   // pending bits, the lowest at stream position (pos & ~31)
+  uint32_t nacc;  // pending bit count = pos & 31 plus what was added
+  __device__ void init(uint32_t* words, uint64_t n_words, uint64_t bitpos) {
+    w = words;
+    limit = n_words;
+    pos = bitpos;
+    acc = 0;
+    nacc = (uint32_t)(bitpos & 31);
+  }
+  __device__ void store(uint64_t word, uint32_t v) {
+    if (word < limit && v) atomicOr(&w[word], v);
+  }
+  __device__ void put(uint64_t v, uint32_t n) {  // n <= 32
+    if (n == 0) return;
+    v &= (n == 64) ? ~0ull : ((1ull << n) - 1);
+    acc |= v << nacc;
+    nacc += n;
+    pos += n;
+    if (nacc >= 32) {
+      store((pos - nacc) >> 5, (uint32_t)acc);
+      acc >>= 32;
+      nacc -= 32;
+    }
+  }
+  __device__ void eg(uint64_t v, int k) {
+    const uint64_t q = (v >> k) + 1;
+    const uint32_t n = 63 - __builtin_clzll(q);
+    // n zeros, a one, the n low bits of q, the k low bits of v
+    for (uint32_t z = n; z > 0;) {
+      const uint32_t m = z > 32 ? 32 : z;
+      put(0, m);
+      z -= m;
+    }
+    put(1, 1);
+    put(q, n);
+    put(v, k);
+  }
+  __device__ void flush() {
+    if (nacc) store((pos - nacc) >> 5, (uint32_t)acc);
+    nacc = 0;
+    acc = 0;
+  }
+};
+
+// ------------------------------------------------------------- bit reading
+struct CmReader {
+  const uint32_t* w;
+  uint64_t pos, end;  // end = payload bits
+  bool bad;
+  __device__ uint64_t get(uint32_t n) {  // n <= 32
+    if (n == 0) return 0;
+    if (pos + n > end) {
+      bad = true;
+      pos = end;
+      return 0;
+    }
+    const uint64_t wi = pos >> 5;
+    const uint32_t sh = (uint32_t)(pos & 31);
+    uint64_t v = w[wi] >> sh;
+    if (sh + n > 32) v |= (uint64_t)w[wi + 1] << (32 - sh);
+    pos += n;
+    return v & ((1ull << n) - 1);
+  }
+  __device__ uint64_t eg(int k) {
+    uint32_t n = 0;
+    while (!bad && get(1) == 0) {
+      if (++n > 32) {
+        bad = true;
+        return 0;
+      }
+    }
+    const uint64_t q = (1ull << n) | get(n);
+    return ((q - 1) << k) | get(k);
+  }
+};
+
+// -------------------------------------------------------------- cluster view
+struct CmClusters {
+  const uint32_t* crow;
+  const int32_t *y, *z;
+  const uint16_t *qtot, *qmax;
+  const uint8_t* flags;
+  const uint32_t* n_dev;
+  uint32_t cap;
+  uint32_t n_ur;
+};
+
+struct CmTracks {
+  const float* par;
+  const uint8_t* row;
+  const int32_t* z_anchor;
+  const uint32_t* hit_start;
+  const uint32_t* hits;
+  const int32_t* cluster_track;
+  const uint32_t* n_dev;
+  uint32_t cap, hit_cap;
+};
+
+__device__ __forceinline__ uint32_t cm_cluster_len(uint16_t qt, uint16_t qm) {
+  return cm_eg_len(qt, 6) + cm_eg_len(qm, 5) + 2;
+}
+__device__ __forceinline__ void cm_cluster_put(CmWriter& b, uint16_t qt, uint16_t qm, uint8_t f) {
+  b.eg(qt, 6);
+  b.eg(qm, 5);
+  b.put(f & 3u, 2);
+}
+
+// One track record: its length (write = false) or its bits (write = true).
+// Returns false if a hit lies below the model's row (latched by the caller).
+template <bool WRITE>
+__device__ bool cm_track(const CmClusters& cl, const CmTracks& tr, uint32_t j, int64_t b30,
+                         const int32_t* xfx, uint64_t& bits, CmWriter* bw, uint32_t* hist) {
+  uint32_t h0 = tr.hit_start[j], h1 = tr.hit_start[j + 1];
+  if (h1 > tr.hit_cap) h1 = tr.hit_cap;
+  if (h0 > h1) h0 = h1;
+  const uint32_t n_cl = scan_count(cl.n_dev, cl.cap);
+  uint32_t ur = 0;
+  if (h1 > h0) {
+    const uint32_t c = tr.hits[h0];
+    ur = cm_find_ur(cl.crow, cl.n_ur, c < n_cl ? c : 0);
+  }
+  const uint32_t unit = ur / NROW;
+  const int r0 = tr.row[j];
+  const CmParams q = cm_params(tr.par + (size_t)j * 5, tr.z_anchor[j]);
+  CmModel m = cm_model(q, b30, r0);
+  uint64_t len = 8 + 16 + 8 + 5 * 32;
+  if (WRITE) {
+    bw->put(h1 - h0, 8);
+    bw->put(unit, 16);
+    bw->put((uint32_t)r0, 8);
+    bw->put((uint32_t)(int32_t)q.Y, 32);
+    bw->put((uint32_t)(int32_t)q.Z, 32);
+    bw->put((uint32_t)(int32_t)q.S, 32);
+    bw->put((uint32_t)(int32_t)q.T, 32);
+    bw->put((uint32_t)(int32_t)q.K, 32);
+  }
+  int prev = r0;
+  bool ok = true;
+  for (uint32_t h = h0; h < h1; ++h) {
+    uint32_t c = tr.hits[h];
+    if (c >= n_cl) {
+      ok = false;
+      c = 0;
+    }
+    while (ur + 1 < cl.n_ur && cl.crow[ur + 1] <= c) ++ur;
+    const int r = (int)(ur % NROW);
+    const int step = r - prev - (h > h0 ? 1 : 0);
+    if (step < 0) ok = false;
+    const uint64_t st = step < 0 ? 0 : (uint64_t)step;
+    prev = r;
+    while (m.row < r) cm_step(m, xfx);
+    const int64_t dy = cm_q(cl.y[c]) - cm_q(m.Y), dz = cm_q(cl.z[c]) - cm_q(m.Z);
+    const uint64_t zy = cm_zig(dy), zz = cm_zig(dz);
+    if (WRITE) {
+      bw->eg(st, 0);
+      bw->eg(zy, 2);
+      bw->eg(zz, 2);
+      cm_cluster_put(*bw, cl.qtot[c], cl.qmax[c], cl.flags[c]);
+    } else {
+      len += cm_eg_len(st, 0) + cm_eg_len(zy, 2) + cm_eg_len(zz, 2) +
+             cm_cluster_len(cl.qtot[c], cl.qmax[c]);
+      if (hist) {
+        atomicAdd(&hist[(dy < -64 ? -64 : dy > 63 ? 63 : dy) + 64], 1u);
+        atomicAdd(&hist[128 + (dz < -64 ? -64 : dz > 63 ? 63 : dz) + 64], 1u);
+      }
+    }
+  }
+  bits = len;
+  return ok;
+}
+
+// Per-track record lengths and the residual histograms (per workgroup in
+// LDS, then added to the caller's histogram).
+__global__ __launch_bounds__(256) void k_cm_track_bits(CmClusters cl, CmTracks tr, int64_t b30,
+                                                       const DevParams* __restrict__ P,
+                                                       uint32_t* __restrict__ tbits,
+                                                       uint32_t* __restrict__ hist_out,
+                                                       DevStatus* st) {
+  __shared__ uint32_t h[256];
+  if (failed(st)) return;
+  for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const uint32_t n = scan_count(tr.n_dev, tr.cap);
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    uint64_t bits = 0;
+    if (!cm_track<false>(cl, tr, j, b30, P->xfx, bits, nullptr, hist_out ? h : nullptr))
+      latch(st, TPC_ERR_INPUT);
+    tbits[j] = (uint32_t)(bits < 0xFFFFFFFFull ? bits : 0xFFFFFFFFull);
+  }
+  __syncthreads();
+  if (hist_out)
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x)
+      if (h[i]) atomicAdd(&hist_out[i], h[i]);
+}
+
+// Clusters on no track of one (unit,row), one wave: each lane's cluster code
+// length, with the drift position relative to the previous such cluster.
+// Calls fn(lane's cluster, its bit offset in the row block, yq zig, z code,
+// z order) for every such cluster; returns the block's length.
+template <class Fn>
+__device__ uint64_t cm_row(const CmClusters& cl, const int32_t* __restrict__ ct, uint32_t ur,
+                           uint64_t base, Fn fn) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t n_cl = scan_count(cl.n_dev, cl.cap);
+  uint32_t c0 = cl.crow[ur], c1 = cl.crow[ur + 1];
+  if (c1 > n_cl) c1 = n_cl;
+  if (c0 > c1) c0 = c1;
+  // the count first
+  uint32_t cnt = 0;
+  for (uint32_t b = c0; b < c1; b += 64) {
+    const uint32_t c = b + lane;
+    const bool un = c < c1 && ct[c] < 0;
+    cnt += (uint32_t)__popcll(__ballot(un));
+  }
+  uint64_t off = base;
+  const uint64_t cnt_len = cm_eg_len(cnt, 0);
+  fn.count(cnt, off);
+  off += cnt_len;
+  int64_t zprev = 0;
+  bool have_prev = false;
+  for (uint32_t b = c0; b < c1; b += 64) {
+    const uint32_t c = b + lane;
+    const bool un = c < c1 && ct[c] < 0;
+    const uint64_t mask = __ballot(un);
+    int64_t zq = 0, yq = 0;
+    uint32_t len = 0;
+    if (un) {
+      zq = cm_q(cl.z[c]);
+      yq = cm_q(cl.y[c]);
+    }
+    // the previous cluster on no track: the highest set lane below, else the
+    // carry from earlier chunks
+    const uint64_t below = mask & ((1ull << lane) - 1);
+    const int src = below ? 63 - __builtin_clzll(below) : (int)lane;
+    const int64_t zp_lane = __shfl(zq, src, 64);
+    const bool first = !below && !have_prev;
+    const int64_t zp = below ? zp_lane : zprev;
+    uint64_t zcode = 0;
+    int zk = 12;
+    if (un) {
+      if (first) {
+        zcode = cm_zig(zq);
+        zk = 12;
+      } else {
+        zcode = cm_zig(zq - zp);
+        zk = 6;
+      }
+      len = cm_eg_len(cm_zig(yq), 10) + cm_eg_len(zcode, zk) + cm_cluster_len(cl.qtot[c], cl.qmax[c]);
+    }
+    // exclusive prefix of the lengths in lane order
+    uint64_t incl = wave_incl_scan((uint64_t)len);
+    const uint64_t tot = __shfl(incl, 63, 64);
+    if (un) fn.cluster(c, off + incl - len, cm_zig(yq), zcode, zk);
+    off += tot;
+    if (mask) {  // uniform
+      const int last = 63 - __builtin_clzll(mask);
+      zprev = __shfl(zq, last, 64);
+      have_prev = true;
+    }
+  }
+  return off - base;
+}
+
+struct CmRowLen {
+  __device__ void count(uint32_t, uint64_t) const {}
+  __device__ void cluster(uint32_t, uint64_t, uint64_t, uint64_t, int) const {}
+};
+
+__global__ __launch_bounds__(256) void k_cm_row_bits(CmClusters cl, const int32_t* __restrict__ ct,
+                                                     uint32_t* __restrict__ rbits,
+                                                     const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t wpb = blockDim.x >> 6;
+  for (uint32_t ur = blockIdx.x * wpb + (threadIdx.x >> 6); ur < cl.n_ur;
+       ur += gridDim.x * wpb) {
+    const uint64_t len = cm_row(cl, ct, ur, 0, CmRowLen{});
+    if ((threadIdx.x & 63) == 0) rbits[ur] = (uint32_t)(len < 0xFFFFFFFFull ? len : 0xFFFFFFFFull);
+  }
+}
+
+// Directory entries from the scans: track j at stream[CM_HDR + j], row block
+// ur at stream[CM_HDR + n_tracks + 1 + ur] (after the tracks' total).
+struct CmEmitTrack {
+  uint32_t* s;
+  uint32_t cap;
+  __device__ void operator()(uint32_t j, unsigned long long pre, unsigned long long) const {
+    if (CM_HDR + (uint64_t)j < cap) s[CM_HDR + j] = (uint32_t)pre;
+  }
+};
+struct CmEmitRow {
+  uint32_t* s;
+  uint32_t cap;
+  const uint32_t* n_tracks_dev;
+  uint32_t tr_cap;
+  const unsigned long long* track_total;
+  __device__ void operator()(uint32_t ur, unsigned long long pre, unsigned long long) const {
+    const uint64_t i = CM_HDR + (uint64_t)scan_count(n_tracks_dev, tr_cap) + 1 + ur;
+    if (i < cap) s[i] = (uint32_t)(pre + *track_total);
+  }
+};
+struct CmEmitOff {
+  uint32_t* out;
+  __device__ void operator()(uint32_t i, unsigned long long pre, unsigned long long) const {
+    out[i] = (uint32_t)pre;
+  }
+};
+struct CmGetU32 {
+  const uint32_t* a;
+  __device__ unsigned long long operator()(uint32_t i) const { return a[i]; }
+};
+
+// Header, the closing directory entries, the size check.  tot[0] = tracks'
+// bits, tot[1] = rows' bits; info[0] = words needed (0 after an error).
+__global__ void k_cm_finish(uint32_t* __restrict__ s, uint32_t cap, uint32_t n_units,
+                            const uint32_t* n_tracks_dev, uint32_t tr_cap,
+                            const uint32_t* hit_start, const uint32_t* n_cl_dev, uint32_t cl_cap,
+                            const unsigned long long* tot, uint32_t* n_words_out,
+                            uint32_t* info, DevStatus* st) {
+  info[0] = 0;
+  if (failed(st)) return;
+  const uint32_t n_tr = scan_count(n_tracks_dev, tr_cap);
+  const uint32_t n_ur = n_units * NROW;
+  const unsigned long long bits = tot[0] + tot[1];
+  const uint64_t dir = CM_HDR + (uint64_t)n_tr + 1 + n_ur + 1;
+  const uint64_t need = dir + (bits + 31) / 32;
+  *n_words_out = (uint32_t)(need < 0xFFFFFFFFull ? need : 0xFFFFFFFFull);
+  if (bits > 0xFFFFFFFFull || need > cap) {
+    latch(st, TPC_ERR_CAPACITY, (uint32_t)(need < 0xFFFFFFFFull ? need : 0xFFFFFFFFull));
+    return;
+  }
+  s[0] = CM_MAGIC;
+  s[1] = 1;
+  s[2] = n_units;
+  s[3] = n_tr;
+  s[4] = scan_count(n_cl_dev, cl_cap);
+  s[5] = n_tr ? hit_start[n_tr] : 0;
+  s[6] = (uint32_t)bits;
+  s[7] = 0;
+  s[CM_HDR + n_tr] = (uint32_t)tot[0];
+  s[dir - 1] = (uint32_t)bits;
+  info[0] = (uint32_t)need;
+  info[1] = (uint32_t)dir;
+}
+
+// clear the payload words [dir, need)
+__global__ void k_cm_clear(uint32_t* __restrict__ s, const uint32_t* info, const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t need = info[0], dir = info[1];
+  for (uint32_t i = dir + blockIdx.x * blockDim.x + threadIdx.x; i < need;
+       i += gridDim.x * blockDim.x)
+    s[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_cm_track_write(CmClusters cl, CmTracks tr, int64_t b30,
+                                                        const DevParams* __restrict__ P,
+                                                        uint32_t* __restrict__ s,
+                                                        const uint32_t* info, DevStatus* st) {
+  if (failed(st) || info[0] == 0) return;
+  const uint32_t n = scan_count(tr.n_dev, tr.cap);
+  uint32_t* payload = s + info[1];
+  const uint64_t pw = info[0] - info[1];
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    CmWriter w;
+    w.init(payload, pw, s[CM_HDR + j]);
+    uint64_t bits = 0;
+    cm_track<true>(cl, tr, j, b30, P->xfx, bits, &w, nullptr);
+    w.flush();
+  }
+}
+
+struct CmRowPut {
+  const CmClusters* cl;
+  uint32_t* payload;
+  uint64_t pw;  // payload words
+  __device__ void count(uint32_t cnt, uint64_t off) const {
+    if ((threadIdx.x & 63) == 0) {
+      CmWriter w;
+      w.init(payload, pw, off);
+      w.eg(cnt, 0);
+      w.flush();
+    }
+  }
+  __device__ void cluster(uint32_t c, uint64_t off, uint64_t yz, uint64_t zcode, int zk) const {
+    CmWriter w;
+    w.init(payload, pw, off);
+    w.eg(yz, 10);
+    w.eg(zcode, zk);
+    cm_cluster_put(w, cl->qtot[c], cl->qmax[c], cl->flags[c]);
+    w.flush();
+  }
+};
+
+__global__ __launch_bounds__(256) void k_cm_row_write(CmClusters cl, const int32_t* __restrict__ ct,
+                                                      uint32_t* __restrict__ s,
+                                                      const uint32_t* n_tracks_dev, uint32_t tr_cap,
+                                                      const uint32_t* info, const DevStatus* st) {
+  if (failed(st) || info[0] == 0) return;
+  const uint32_t n_tr = scan_count(n_tracks_dev, tr_cap);
+  uint32_t* payload = s + info[1];
+  const uint32_t wpb = blockDim.x >> 6;
+  for (uint32_t ur = blockIdx.x * wpb + (threadIdx.x >> 6); ur < cl.n_ur;
+       ur += gridDim.x * wpb) {
+    const uint64_t base = s[CM_HDR + n_tr + 1 + ur];
+    cm_row(cl, ct, ur, base, CmRowPut{&cl, payload, (uint64_t)(info[0] - info[1])});
+  }
+}
+
+// ------------------------------------------------------------------ decoder
+struct CmDecOut {
+  uint32_t capacity;
+  uint16_t* unit;
+  uint8_t* row;
+  int32_t *y, *z;
+  uint16_t *qtot, *qmax;
+  uint8_t* flags;
+  int32_t* track;
+};
+
+// Header checks; info = {n_units, n_tracks, n_clusters, payload bits, dir
+// words, records (tracks + rows), ok}.
+__global__ void k_cm_dec_header(const uint32_t* __restrict__ s, uint32_t n_words, uint32_t max_units,
+                                uint32_t max_tracks, uint32_t out_cap, uint32_t* n_out,
+                                uint32_t* info, DevStatus* st) {
+  info[6] = 0;
+  if (failed(st)) return;
+  if (n_words < CM_HDR || s[0] != CM_MAGIC || s[1] != 1 || s[7] != 0) {
+    latch(st, TPC_ERR_INPUT);
+    return;
+  }
+  const uint32_t nu = s[2], nt = s[3], nc = s[4], bits = s[6];
+  const uint64_t dir = CM_HDR + (uint64_t)nt + 1 + (uint64_t)nu * NROW + 1;
+  if (nu > max_units || nt > max_tracks || dir > n_words || bits > (n_words - dir) * 32ull ||
+      s[CM_HDR + nt + 1 + (uint64_t)nu * NROW] != bits || s[CM_HDR] != 0) {
+    latch(st, TPC_ERR_INPUT);
+    return;
+  }
+  *n_out = nc;
+  if (nc > out_cap) {
+    latch(st, TPC_ERR_CAPACITY, nc);
+    return;
+  }
+  info[0] = nu;
+  info[1] = nt;
+  info[2] = nc;
+  info[3] = bits;
+  info[4] = (uint32_t)dir;
+  info[5] = nt + nu * NROW;
+  info[6] = 1;
+}
+
+// Clusters per record: a track's fixed-width hit count, a row's count code.
+__global__ void k_cm_dec_counts(const uint32_t* __restrict__ s, const uint32_t* info,
+                                uint32_t* __restrict__ cnt, DevStatus* st) {
+  if (failed(st) || !info[6]) return;
+  const uint32_t nt = info[1], nrec = info[5];
+  CmReader r{s + info[4], 0, info[3], false};
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nrec; i += gridDim.x * blockDim.x) {
+    r.pos = s[CM_HDR + (i < nt ? i : i + 1)];
+    r.bad = false;
+    cnt[i] = (uint32_t)(i < nt ? r.get(8) : r.eg(0));
+    if (r.bad || cnt[i] > 0xFFFFFFu) {
+      cnt[i] = 0;
+      latch(st, TPC_ERR_INPUT);
+    }
+  }
+}
+
+// One lane per record: decode it at its output offset and check that it ends
+// where the directory says the next one starts.
+__global__ __launch_bounds__(256) void k_cm_dec_records(const uint32_t* __restrict__ s,
+                                                        const uint32_t* info,
+                                                        const uint32_t* __restrict__ off,
+                                                        const unsigned long long* total,
+                                                        int64_t b30,
+                                                        const DevParams* __restrict__ P,
+                                                        CmDecOut o, DevStatus* st) {
+  if (failed(st) || !info[6]) return;
+  const uint32_t nu = info[0], nt = info[1], nc = info[2], nrec = info[5];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && *total != nc) latch(st, TPC_ERR_INPUT);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nrec; i += gridDim.x * blockDim.x) {
+    CmReader r{s + info[4], s[CM_HDR + (i < nt ? i : i + 1)], info[3], false};
+    const uint64_t end = s[CM_HDR + (i < nt ? i + 1 : i + 2)];
+    uint32_t k = off[i];
+    bool bad = false;
+    if (i < nt) {
+      const uint32_t nh = (uint32_t)r.get(8);
+      const uint32_t unit = (uint32_t)r.get(16);
+      const int r0 = (int)r.get(8);
+      CmParams q;
+      q.Y = (int32_t)r.get(32);
+      q.Z = (int32_t)r.get(32);
+      q.S = (int32_t)r.get(32);
+      q.T = (int32_t)r.get(32);
+      q.K = (int32_t)r.get(32);
+      if (unit >= nu || r0 >= NROW) bad = true;
+      CmModel m = cm_model(q, b30, r0);
+      int prev = r0;
+      for (uint32_t h = 0; h < nh && !bad && !r.bad; ++h, ++k) {
+        const uint64_t stp = r.eg(0);
+        const int rr = prev + (int)(stp > NROW ? NROW : stp) + (h > 0 ? 1 : 0);
+        if (rr >= NROW || k >= nc || k >= o.capacity) {
+          bad = true;
+          break;
+        }
+        prev = rr;
+        while (m.row < rr) cm_step(m, P->xfx);
+        const int64_t yq = cm_q(m.Y) + cm_unzig(r.eg(2));
+        const int64_t zq = cm_q(m.Z) + cm_unzig(r.eg(2));
+        o.unit[k] = (uint16_t)unit;
+        o.row[k] = (uint8_t)rr;
+        o.y[k] = (int32_t)(yq << CM_QSHIFT);
+        o.z[k] = (int32_t)(zq << CM_QSHIFT);
+        o.qtot[k] = (uint16_t)r.eg(6);
+        o.qmax[k] = (uint16_t)r.eg(5);
+        o.flags[k] = (uint8_t)r.get(2);
+        o.track[k] = (int32_t)i;
+      }
+    } else {
+      const uint32_t ur = i - nt;
+      const uint64_t n = r.eg(0);
+      int64_t zprev = 0;
+      for (uint64_t c = 0; c < n && !r.bad; ++c, ++k) {
+        if (k >= nc || k >= o.capacity) {
+          bad = true;
+          break;
+        }
+        const int64_t yq = cm_unzig(r.eg(10));
+        const int64_t zq = c == 0 ? cm_unzig(r.eg(12)) : zprev + cm_unzig(r.eg(6));
+        zprev = zq;
+        o.unit[k] = (uint16_t)(ur / NROW);
+        o.row[k] = (uint8_t)(ur % NROW);
+        o.y[k] = (int32_t)(yq << CM_QSHIFT);
+        o.z[k] = (int32_t)(zq << CM_QSHIFT);
+        o.qtot[k] = (uint16_t)r.eg(6);
+        o.qmax[k] = (uint16_t)r.eg(5);
+        o.flags[k] = (uint8_t)r.get(2);
+        o.track[k] = -1;
+      }
+    }
+    if (bad || r.bad || r.pos != end) latch(st, TPC_ERR_INPUT);
+  }
+}

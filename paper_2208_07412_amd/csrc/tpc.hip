@@ -20,6 +20,7 @@
 #include "k_track.hpp"
 #include "k_qc.hpp"
 #include "k_zspage.hpp"
+#include "k_compress.hpp"
 
 namespace {
 
@@ -87,6 +88,9 @@ struct tpc_ctx {
   uint32_t* hit_off = nullptr;
   uint32_t* qc_part = nullptr;   // per-workgroup QC histograms
   uint32_t* zp_off = nullptr;    // output offset of each raw ZS page
+  uint32_t *cm_a = nullptr, *cm_b = nullptr;  // compression: lengths / counts, offsets
+  unsigned long long* cm_tot = nullptr;       // compression: bit totals
+  uint32_t* cm_info = nullptr;                // compression: sizes of the stream
   size_t bsum_cap = 0;
   tpc_tuning tune;
   // stage timing (measurement only)
@@ -113,7 +117,7 @@ struct Layout {
 
 struct Plan {
   size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
-      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, hit_off, par, st, total;
+      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, cm_a, cm_b, cm_tot, cm_info, hit_off, par, st, total;
   size_t bsum_cap;
   uint32_t nblk, nblk_s, nwin;
 };
@@ -122,6 +126,11 @@ struct Plan {
 // max_samples needs (a full page holds over 1,500 samples).
 uint64_t max_pages(const tpc_sizes& m) {
   return (uint64_t)m.max_samples / 16 + (uint64_t)NROW * m.max_units;
+}
+
+// Records of a compressed stream: one per track, one per (unit,row).
+uint64_t cm_records(const tpc_sizes& m) {
+  return (uint64_t)m.max_tracklets + (uint64_t)NROW * m.max_units + 2;
 }
 
 Plan plan_for(const tpc_sizes& m) {
@@ -135,6 +144,7 @@ Plan plan_for(const tpc_sizes& m) {
   if (m.max_clusters > nscan) nscan = m.max_clusters;
   if (m.max_tracklets > nscan) nscan = m.max_tracklets;
   if (max_pages(m) > nscan) nscan = max_pages(m);
+  if (cm_records(m) > nscan) nscan = cm_records(m);
   if (256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + XCD_GROUPS - 1) > nscan)
     nscan = 256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + XCD_GROUPS - 1);
   p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
@@ -173,6 +183,10 @@ Plan plan_for(const tpc_sizes& m) {
   p.hit_off = L.add<uint32_t>(mt);
   p.qc_part = L.add<uint32_t>((uint64_t)QC_WG * QC_BINS);
   p.zp_off = L.add<uint32_t>(max_pages(m) + 1);
+  p.cm_a = L.add<uint32_t>(cm_records(m));
+  p.cm_b = L.add<uint32_t>(cm_records(m));
+  p.cm_tot = L.add<unsigned long long>(2);
+  p.cm_info = L.add<uint32_t>(8);
   p.par = L.add<DevParams>(1);
   p.st = L.add<DevStatus>(1);
   p.total = (L.off + 255) & ~(size_t)255;
@@ -724,6 +738,10 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->hit_off = (uint32_t*)(base + pl.hit_off);
   c->qc_part = (uint32_t*)(base + pl.qc_part);
   c->zp_off = (uint32_t*)(base + pl.zp_off);
+  c->cm_a = (uint32_t*)(base + pl.cm_a);
+  c->cm_b = (uint32_t*)(base + pl.cm_b);
+  c->cm_tot = (unsigned long long*)(base + pl.cm_tot);
+  c->cm_info = (uint32_t*)(base + pl.cm_info);
   c->d_par = (DevParams*)(base + pl.par);
   c->d_st = (DevStatus*)(base + pl.st);
   c->bsum_cap = pl.bsum_cap;
@@ -776,6 +794,67 @@ int tpc_decode_zs_pages(tpc_ctx* c, const uint32_t* pages, uint32_t n_pages, tpc
   k_zs_rows<<<grid_for((uint64_t)n_pages + 1, 256), 256, 0, s>>>(
       pages, n_pages, out->n_units, c->zp_off, c->tot32, out->capacity, out->row_start,
       out->n_samples, c->d_st);
+  return launch_ok();
+}
+
+namespace {
+int64_t cm_b30(const tpc_ctx* c) { return (int64_t)llrint(c->par.bz_b * 1073741824.0); }
+}  // namespace
+
+int tpc_compress(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, tpc_compressed* out) {
+  if (!c || check_clusters(c, cl, true) || !tr || !out || !out->stream || !out->n_words ||
+      out->capacity == 0)
+    return TPC_ERR_ARG;
+  if (!tr->par || !tr->row || !tr->z_anchor || !tr->hit_start || !tr->hits ||
+      !tr->cluster_track || !tr->n_tracks || tr->capacity > c->max.max_tracklets)
+    return TPC_ERR_ARG;
+  hipStream_t s = c->stream;
+  const uint32_t n_ur = cl->n_units * NROW;
+  StageTimer tm(c, 13);
+  const CmClusters cv{cl->crow_start, cl->y_fx, cl->z_fx, cl->qtot, cl->qmax, cl->flags,
+                      cl->n_clusters, cl->capacity, n_ur};
+  const CmTracks tv{tr->par, tr->row, tr->z_anchor, tr->hit_start, tr->hits, tr->cluster_track,
+                    tr->n_tracks, tr->capacity, tr->hit_capacity};
+  const int64_t b30 = cm_b30(c);
+  if (out->res_hist) k_fill<uint32_t><<<1, 256, 0, s>>>(out->res_hist, 0u, 256);
+  const uint32_t gt = grid_for(tr->capacity, 256, 4096);
+  k_cm_track_bits<<<gt, 256, 0, s>>>(cv, tv, b30, c->d_par, c->cm_a, out->res_hist, c->d_st);
+  k_cm_row_bits<<<grid_for(n_ur, 4, 4096), 256, 0, s>>>(cv, tr->cluster_track, c->cm_b, c->d_st);
+  run_scan<unsigned long long>(c, CmGetU32{c->cm_a}, CmEmitTrack{out->stream, out->capacity},
+                               tr->n_tracks, tr->capacity, c->cm_tot, (uint32_t*)nullptr);
+  run_scan<unsigned long long>(
+      c, CmGetU32{c->cm_b},
+      CmEmitRow{out->stream, out->capacity, tr->n_tracks, tr->capacity, c->cm_tot}, nullptr, n_ur,
+      c->cm_tot + 1, (uint32_t*)nullptr);
+  k_cm_finish<<<1, 1, 0, s>>>(out->stream, out->capacity, cl->n_units, tr->n_tracks, tr->capacity,
+                              tr->hit_start, cl->n_clusters, cl->capacity, c->cm_tot,
+                              out->n_words, c->cm_info, c->d_st);
+  k_cm_clear<<<grid_for(out->capacity, 256, 2048), 256, 0, s>>>(out->stream, c->cm_info, c->d_st);
+  k_cm_track_write<<<gt, 256, 0, s>>>(cv, tv, b30, c->d_par, out->stream, c->cm_info, c->d_st);
+  k_cm_row_write<<<grid_for(n_ur, 4, 4096), 256, 0, s>>>(cv, tr->cluster_track, out->stream,
+                                                         tr->n_tracks, tr->capacity, c->cm_info,
+                                                         c->d_st);
+  return launch_ok();
+}
+
+int tpc_decompress(tpc_ctx* c, const uint32_t* stream, uint32_t stream_words,
+                   tpc_decoded_clusters* out) {
+  if (!c || !stream || !out || !out->n_clusters || !out->unit || !out->row || !out->y_fx ||
+      !out->z_fx || !out->qtot || !out->qmax || !out->flags || !out->track)
+    return TPC_ERR_ARG;
+  hipStream_t s = c->stream;
+  StageTimer tm(c, 14);
+  const uint32_t max_rec = (uint32_t)cm_records(c->max);
+  k_cm_dec_header<<<1, 1, 0, s>>>(stream, stream_words, c->max.max_units, c->max.max_tracklets,
+                                  out->capacity, out->n_clusters, c->cm_info, c->d_st);
+  k_cm_dec_counts<<<grid_for(max_rec, 256, 4096), 256, 0, s>>>(stream, c->cm_info, c->cm_a,
+                                                               c->d_st);
+  run_scan<unsigned long long>(c, CmGetU32{c->cm_a}, CmEmitOff{c->cm_b}, c->cm_info + 5, max_rec,
+                               c->cm_tot, (uint32_t*)nullptr);
+  const CmDecOut o{out->capacity, out->unit, out->row, out->y_fx, out->z_fx,
+                   out->qtot, out->qmax, out->flags, out->track};
+  k_cm_dec_records<<<grid_for(max_rec, 256, 4096), 256, 0, s>>>(
+      stream, c->cm_info, c->cm_b, c->cm_tot, cm_b30(c), c->d_par, o, c->d_st);
   return launch_ok();
 }
 
@@ -968,7 +1047,7 @@ const char* tpc_profile_stage_name(int i) {
   static const char* names[TPC_PROF_STAGES] = {
       "sample_index", "cluster_peaks", "cluster_scan", "cluster_output", "cluster_grid",
       "neighbours", "tracklets", "following", "resolution", "refit", "fp64_count",
-      "track_output", "zs_decode"};
+      "track_output", "zs_decode", "compress", "decompress"};
   return (i >= 0 && i < TPC_PROF_STAGES) ? names[i] : "unknown";
 }
 

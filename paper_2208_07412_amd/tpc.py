@@ -53,6 +53,15 @@ class TpcZsSoa(ctypes.Structure):
                 ("pad", P), ("time", P), ("adc", P), ("row_start", P)]
 
 
+class TpcCompressed(ctypes.Structure):
+    _fields_ = [("capacity", U32), ("stream", P), ("n_words", P), ("res_hist", P)]
+
+
+class TpcDecoded(ctypes.Structure):
+    _fields_ = [("capacity", U32), ("n_clusters", P), ("unit", P), ("row", P), ("y_fx", P),
+                ("z_fx", P), ("qtot", P), ("qmax", P), ("flags", P), ("track", P)]
+
+
 class TpcClusters(ctypes.Structure):
     _fields_ = [("capacity", U32), ("n_units", U32), ("n_time_bins", U32), ("n_clusters", P),
                 ("crow_start", P), ("y_fx", P), ("z_fx", P), ("dpad", P), ("dtime", P),
@@ -98,8 +107,9 @@ EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_crea
            "tpc_fit_tracks", "tpc_process_timeframe", "tpc_sync", "tpc_stream",
            "tpc_status_string", "tpc_profile_enable", "tpc_profile_read",
            "tpc_profile_stage_name", "tpc_tuning_default", "tpc_set_tuning", "tpc_get_tuning",
-           "tpc_qc_histograms", "tpc_qc_histograms_noalloc", "tpc_decode_zs_pages"]
-PROF_STAGES = 13
+           "tpc_qc_histograms", "tpc_qc_histograms_noalloc", "tpc_decode_zs_pages",
+           "tpc_compress", "tpc_decompress"]
+PROF_STAGES = 15
 # quality-control histogram layout (bin offsets; see tpc_qc_histograms)
 QC_QTOT, QC_QMAX, QC_NHITS, QC_ATTACH, QC_BINS = 0, 256, 512, 665, 667
 
@@ -131,6 +141,8 @@ def load():
     lib.tpc_qc_histograms.argtypes = [P, P, P, P]
     lib.tpc_qc_histograms_noalloc.argtypes = [P, P, P, P]
     lib.tpc_decode_zs_pages.argtypes = [P, P, U32, P]
+    lib.tpc_compress.argtypes = [P, P, P, P]
+    lib.tpc_decompress.argtypes = [P, P, U32, P]
     lib.tpc_sync.argtypes = [P, P]
     lib.tpc_stream.argtypes = [P]
     lib.tpc_stream.restype = P
@@ -293,9 +305,59 @@ class Reco:
         if n:
             b.t["y_fx"][:n].copy_(dev(cl["y_fx"], np.int32, np.int32))
             b.t["z_fx"][:n].copy_(dev(cl["z_fx"], np.int32, np.int32))
-            b.t["ptime"][:n].copy_(dev(cl["ptime"], np.uint16, np.int16))
-            b.t["ppad"][:n].copy_(dev(cl["ppad"], np.uint16, np.int16))
+            for k in ("ptime", "ppad", "qtot", "qmax"):
+                if k in cl:
+                    b.t[k][:n].copy_(dev(cl[k], np.uint16, np.int16))
+            if "flags" in cl:
+                b.t["flags"][:n].copy_(dev(cl["flags"], np.uint8, np.uint8))
         return b
+
+    def tracks_from_host(self, tr: dict, cluster_capacity: int) -> Buffers:
+        """Device copy of a host track set (parameters, rows, anchors, hit
+        lists, cluster -> track map), e.g. the oracle's tracks."""
+        torch = _torch()
+        n = len(tr["hit_start"]) - 1
+        nh = int(tr["hit_start"][-1])
+        b = self.alloc_tracks(max(n, 1), max(nh, 1), cluster_capacity)
+        dev = lambda a, dt, vt: torch.from_numpy(np.ascontiguousarray(a, dt).view(vt)).to(self.device)
+        b.t["n_tracks"].copy_(torch.tensor([n], dtype=torch.int32))
+        b.t["n_hits"].copy_(torch.tensor([nh], dtype=torch.int32))
+        b.t["hit_start"][:n + 1].copy_(dev(tr["hit_start"], np.uint32, np.int32))
+        nc = len(tr["cluster_track"])
+        if nc:
+            b.t["cluster_track"][:nc].copy_(dev(tr["cluster_track"], np.int32, np.int32))
+        if n:
+            b.t["par"][:n * 5].copy_(dev(np.asarray(tr["par"]).reshape(-1), np.float32, np.float32))
+            b.t["row"][:n].copy_(dev(tr["row"], np.uint8, np.uint8))
+            b.t["z_anchor"][:n].copy_(dev(tr["z_anchor"], np.int32, np.int32))
+        if nh:
+            b.t["hits"][:nh].copy_(dev(tr["hits"], np.uint32, np.int32))
+        return b
+
+    def alloc_compressed(self, capacity_words: int, hist: bool = True) -> Buffers:
+        """Device buffer for a compressed stream (tpc_compressed)."""
+        torch = _torch()
+        d = self.device
+        t = dict(stream=torch.empty(max(int(capacity_words), 1), dtype=torch.int32, device=d),
+                 n_words=torch.zeros(1, dtype=torch.int32, device=d))
+        if hist:
+            t["res_hist"] = torch.zeros(256, dtype=torch.int32, device=d)
+        s = TpcCompressed(int(capacity_words), _dptr(t["stream"]), _dptr(t["n_words"]),
+                          _dptr(t.get("res_hist")))
+        return Buffers(t, s)
+
+    def alloc_decoded(self, capacity: int) -> Buffers:
+        """Device arrays for decompressed clusters (tpc_decoded_clusters)."""
+        torch = _torch()
+        d = self.device
+        e = lambda dt: torch.empty(max(int(capacity), 1), dtype=dt, device=d)
+        t = dict(n_clusters=torch.zeros(1, dtype=torch.int32, device=d), unit=e(torch.int16),
+                 row=e(torch.uint8), y_fx=e(torch.int32), z_fx=e(torch.int32),
+                 qtot=e(torch.int16), qmax=e(torch.int16), flags=e(torch.uint8),
+                 track=e(torch.int32))
+        s = TpcDecoded(int(capacity), *[_dptr(t[k]) for k in (
+            "n_clusters", "unit", "row", "y_fx", "z_fx", "qtot", "qmax", "flags", "track")])
+        return Buffers(t, s)
 
     def alloc_links(self, capacity: int) -> Buffers:
         torch = _torch()
@@ -356,6 +418,19 @@ class Reco:
         _check(self.lib.tpc_decode_zs_pages(self.ctx, ctypes.c_void_p(pages.data_ptr()),
                                             int(n_pages), ctypes.byref(out.s)),
                "tpc_decode_zs_pages")
+
+    def compress(self, cl: Buffers, tr: Buffers, out: Buffers):
+        """Track-model compression of a reconstruction's clusters (tpc_compress)."""
+        _check(self.lib.tpc_compress(self.ctx, ctypes.byref(cl.s), ctypes.byref(tr.s),
+                                     ctypes.byref(out.s)), "tpc_compress")
+
+    def decompress(self, stream, out: Buffers, stream_words: Optional[int] = None):
+        """Decode a stream (device tensor of 32-bit words) into out (tpc_decompress)."""
+        n = stream.numel() if stream_words is None else int(stream_words)
+        if stream.numel() < n or stream.element_size() != 4 or not stream.is_cuda:
+            raise ValueError("decompress: stream must be a device tensor of 32-bit words")
+        _check(self.lib.tpc_decompress(self.ctx, ctypes.c_void_p(stream.data_ptr()), n,
+                                       ctypes.byref(out.s)), "tpc_decompress")
 
     def cluster(self, zs: dict, out: Buffers):
         _check(self.lib.tpc_cluster(self.ctx, ctypes.byref(zs_struct(zs)), ctypes.byref(out.s)),
@@ -465,6 +540,23 @@ def zs_soa_to_host(b: Buffers) -> dict:
     return dict(n_samples=n, pad=_u(b["pad"], m, np.uint16), time=_u(b["time"], m, np.uint16),
                 adc=_u(b["adc"], m, np.uint16),
                 row_start=_u(b["row_start"], int(b.s.n_units) * NROW + 1, np.uint32))
+
+
+def compressed_to_host(b: Buffers) -> dict:
+    n = int(b["n_words"].item())
+    m = min(n, int(b.s.capacity))
+    out = dict(n_words=n, words=_u(b["stream"], m, np.uint32))
+    if "res_hist" in b.t:
+        out["hist"] = b["res_hist"].cpu().numpy().astype(np.int64)
+    return out
+
+
+def decoded_to_host(b: Buffers) -> dict:
+    n = min(int(b["n_clusters"].item()), int(b.s.capacity))
+    return dict(unit=_u(b["unit"], n, np.uint16), row=_u(b["row"], n, np.uint8),
+                y_fx=_u(b["y_fx"], n, np.int32), z_fx=_u(b["z_fx"], n, np.int32),
+                qtot=_u(b["qtot"], n, np.uint16), qmax=_u(b["qmax"], n, np.uint16),
+                flags=_u(b["flags"], n, np.uint8), track=_u(b["track"], n, np.int32))
 
 
 QC_NOALLOC_MAX = 1024 * 65536

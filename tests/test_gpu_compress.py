@@ -1,0 +1,160 @@
+"""GPU track-model compression against the oracle's codec (a byte stream:
+bit-exact), and the GPU decoder against the oracle's decoder.
+
+* Stage-isolated parity: both encoders take the same clusters and the same
+  tracks (the oracle's, parameters rounded to float32), so every word of the
+  two streams and the residual histograms must agree; the GPU decoder must
+  give the oracle decoder's clusters.  Cases: the hand-worked frame
+  (tests/golden), one sector, one central collision, a pile-up frame.
+* The full chain: the GPU's own reconstruction of the 2 ms slice is
+  compressed and decompressed on the GPU; the decoded clusters are the
+  quantised reconstruction outputs (a property at any size), and the oracle
+  decodes the GPU's stream to the same clusters.
+* Errors: a stream buffer too small (the words needed are reported), a
+  decoded-cluster buffer too small, malformed streams, repeated calls.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import tpcsynth
+from paper_2208_07412_amd import tpc
+
+from test_oracle_compress import _expected, load_example
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_codec(clusters, tracks, n_units, n_time_bins=500, cap_words=None, reco=None):
+    nc = len(clusters["y_fx"])
+    own = reco is None
+    if own:
+        nt = len(tracks["hit_start"]) - 1
+        reco = tpc.Reco(n_units, n_time_bins, max(nc, 1), max(nt, 1))
+    cl = reco.clusters_from_host(clusters, n_units, n_time_bins)
+    tr = reco.tracks_from_host(tracks, max(nc, 1))
+    cw = cap_words or (64 + len(tracks["hit_start"]) + n_units * 152 + (nc * 200) // 32 + 64)
+    comp = reco.alloc_compressed(cw)
+    reco.compress(cl, tr, comp)
+    c = reco.sync(raise_on_error=False)
+    out = dict(status=c["status"], required=c["required"], comp=tpc.compressed_to_host(comp))
+    if c["status"] == 0:
+        dec = reco.alloc_decoded(max(nc, 1))
+        reco.decompress(comp["stream"], dec, out["comp"]["n_words"])
+        c2 = reco.sync(raise_on_error=False)
+        out["dec_status"] = c2["status"]
+        out["dec"] = tpc.decoded_to_host(dec) if c2["status"] == 0 else None
+    if own:
+        reco.close()
+    return out
+
+
+def _same_decoded(a, b):
+    for k in ("unit", "row", "y_fx", "z_fx", "qtot", "qmax", "flags", "track"):
+        assert np.array_equal(np.asarray(a[k], np.int64), np.asarray(b[k], np.int64)), k
+
+
+def test_hand_worked_example():
+    clusters, tracks, bits, meta, cl = load_example()
+    o = oracle.compress(clusters, tracks, 1)
+    g = _gpu_codec(clusters, tracks, 1)
+    assert g["status"] == 0 and g["dec_status"] == 0
+    assert np.array_equal(g["comp"]["words"], o["words"])
+    assert np.array_equal(g["comp"]["hist"], o["hist"])
+    _same_decoded(g["dec"], oracle.decompress(o["words"]))
+
+
+@pytest.mark.parametrize("which", ["c1", "c2", "pileup"])
+def test_stage_parity_on_oracle_tracks(which):
+    cfg, seed = {"c1": (tpcsynth.config_c1(), 101), "c2": (tpcsynth.config_c2(), 202),
+                 "pileup": (tpcsynth.config_chunk(404, 1, n_coll=6), 4041)}[which]
+    ev = tpcsynth.generate(cfg, seed)
+    o = oracle.process(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins,
+                       n_threads=8)
+    tracks = oracle.tracks_from_fit(o)
+    oc = oracle.compress(o["clusters"], tracks, ev.n_units)
+    assert oc["status"] == 0
+    g = _gpu_codec(o["clusters"], tracks, ev.n_units, ev.n_time_bins)
+    assert g["status"] == 0 and g["dec_status"] == 0
+    gw, ow = g["comp"]["words"], oc["words"]
+    assert len(gw) == len(ow)
+    bad = np.nonzero(gw != ow)[0]
+    assert len(bad) == 0, f"{len(bad)} words differ, first {bad[:5]}"
+    assert np.array_equal(g["comp"]["hist"], oc["hist"])
+    _same_decoded(g["dec"], oracle.decompress(ow))
+    nc = len(o["clusters"]["y_fx"])
+    print(f"{which}: {nc} clusters -> {4 * len(ow)} bytes ({4 * len(ow) / nc:.2f} B/cluster)")
+
+
+def test_full_slice_round_trip():
+    ev = tpcsynth.generate(tpcsynth.config_c3(303, 100), 303)
+    ns = ev.n_samples
+    mc, mt = ns // 8, ns // 64
+    reco = tpc.Reco(ev.n_units, ev.n_time_bins, mc, mt, max_samples=ns)
+    try:
+        zs = tpc.to_device_zs(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins)
+        cl = reco.alloc_clusters(ev.n_units, ev.n_time_bins, mc)
+        links = reco.alloc_links(mc)
+        tl = reco.alloc_tracklets(mt)
+        tr = reco.alloc_tracks(mt, mc, mc)
+        reco.process(zs, cl, links, tl, tr)
+        counts = reco.sync()
+        del zs, links
+        comp = reco.alloc_compressed(mc * 2)
+        dec = reco.alloc_decoded(counts["n_clusters"])
+        for _ in range(2):  # a second call reuses (and clears) the stream
+            reco.compress(cl, tr, comp)
+            reco.decompress(comp["stream"], dec)
+            reco.sync()
+        ch = tpc.compressed_to_host(comp)
+        d = tpc.decoded_to_host(dec)
+        n = counts["n_clusters"]
+        hc = tpc.clusters_to_host(cl, ev.n_units)
+        ht = tpc.tracks_to_host(tr, n)
+        exp, idx = _expected(hc, ht, ev.n_units)
+        for k, v in exp.items():
+            assert np.array_equal(np.asarray(d[k], np.int64), np.asarray(v, np.int64)), k
+        assert np.abs(d["y_fx"] - hc["y_fx"][idx].astype(np.int64)).max() <= 256
+        assert ch["hist"][:128].sum() == counts["n_hits"] == ch["hist"][128:].sum()
+        od = oracle.decompress(ch["words"])
+        assert od["status"] == 0
+        _same_decoded(d, od)
+        core = ch["hist"][64 - 8:64 + 8].sum() / max(counts["n_hits"], 1)
+        print(f"slice: {n} clusters ({counts['n_hits']} on tracks) -> {4 * ch['n_words']} bytes "
+              f"({4 * ch['n_words'] / n:.2f} B/cluster); {core:.3f} of the y residuals "
+              f"within 8 steps (6.25e-2 cm)")
+    finally:
+        reco.close()
+
+
+def test_errors_and_capacity():
+    clusters, tracks, bits, meta, cl = load_example()
+    reco = tpc.Reco(1, 500, 16, 16)
+    try:
+        g = _gpu_codec(clusters, tracks, 1, cap_words=100, reco=reco)
+        assert g["status"] == -2 and g["required"] == 8 + 2 + 153 + 16
+        assert g["comp"]["n_words"] == 8 + 2 + 153 + 16
+        bad = dict(tracks, row=np.array([11], np.uint8))  # a hit below the model's row
+        assert _gpu_codec(clusters, bad, 1, reco=reco)["status"] == -3
+        w = oracle.compress(clusters, tracks, 1)["words"]
+        dec = reco.alloc_decoded(4)
+        for mutate in (lambda a: a.__setitem__(0, a[0] ^ 1),      # magic
+                       lambda a: a.__setitem__(9, a[9] + 1),      # directory
+                       lambda a: a.__setitem__(6, a[6] + 1)):     # payload size
+            a = w.copy()
+            mutate(a)
+            reco.decompress(torch.from_numpy(a.view(np.int32)).cuda(), dec)
+            assert reco.sync(raise_on_error=False)["status"] == -3
+        reco.decompress(torch.from_numpy(w[:-1].view(np.int32)).cuda(), dec)  # truncated
+        assert reco.sync(raise_on_error=False)["status"] == -3
+        small = reco.alloc_decoded(3)
+        reco.decompress(torch.from_numpy(w.view(np.int32)).cuda(), small)
+        c = reco.sync(raise_on_error=False)
+        assert c["status"] == -2 and c["required"] == 4
+        # and the context still works
+        reco.decompress(torch.from_numpy(w.view(np.int32)).cuda(), dec)
+        assert reco.sync(raise_on_error=False)["status"] == 0
+        _same_decoded(tpc.decoded_to_host(dec), oracle.decompress(w))
+    finally:
+        reco.close()
