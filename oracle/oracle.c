@@ -1316,7 +1316,7 @@ static uint64_t cm_get(cm_reader* r, int n) {
 static uint64_t cm_geteg(cm_reader* r, int k) {
   int n = 0;
   while (!r->bad && cm_get(r, 1) == 0) {
-    if (++n > 40) {
+    if (++n > 32) { /* no code of the format has a longer prefix */
       r->bad = 1;
       return 0;
     }
