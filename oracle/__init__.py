@@ -115,6 +115,9 @@ def _load():
     lib.oracle_track_model.argtypes = [P, P, ctypes.c_int32, ctypes.c_int, ctypes.c_int, P, P, P,
                                        P]
     lib.oracle_track_model.restype = None
+    lib.oracle_merge_tracks.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int64, P, P, P, P,
+                                        P, P, P]
+    lib.oracle_merge_tracks.restype = None
     _lib = lib
     return lib
 
@@ -465,3 +468,35 @@ def track_model(par, z_anchor: int, row0: int, rows, params: Optional[dict] = No
     lib.oracle_track_model(ctypes.byref(op), _p(p), int(z_anchor), int(row0), n, _p(rows), _p(y),
                            _p(z), _p(fr))
     return y, z, fr
+
+
+MERGE_FIT_FIELDS = ("n_segments", "n_hits", "xc", "yc", "radius", "dzdpsi", "zd_axis", "t0",
+                    "tgl", "flags", "turn")
+
+
+def merge_tracks(clusters: dict, tracks: dict, n_units: int,
+                 params: Optional[dict] = None) -> dict:
+    """Segments joined into tracks (cross-sector, looper legs), with the
+    merged helix fit and T0: label per segment (the component's smallest
+    segment index), near_tie per segment, and per component (at its label)
+    the fields of MERGE_FIT_FIELDS."""
+    lib = _load()
+    op = make_params(params)
+    crow = np.ascontiguousarray(clusters["crow_start"], np.uint32)
+    y = np.ascontiguousarray(clusters["y_fx"], np.int32)
+    z = np.ascontiguousarray(clusters["z_fx"], np.int32)
+    n = len(tracks["hit_start"]) - 1
+    par = np.ascontiguousarray(tracks["par"], np.float32).reshape(-1)
+    row = np.ascontiguousarray(tracks["row"], np.uint8)
+    hs = np.ascontiguousarray(tracks["hit_start"], np.uint32)
+    hits = np.ascontiguousarray(tracks["hits"], np.uint32)
+    label = np.zeros(max(n, 1), np.int64)
+    tie = np.zeros(max(n, 1), np.int32)
+    fit = np.zeros(max(n, 1) * 12)
+    lib.oracle_merge_tracks(ctypes.byref(op), n_units, _p(crow), _p(y), _p(z), n, _p(par), _p(row),
+                            _p(hs), _p(hits), _p(label), _p(tie), _p(fit))
+    f = fit[:n * 12].reshape(n, 12)
+    out = dict(label=label[:n].copy(), near_tie=tie[:n].astype(bool))
+    for i, k in enumerate(MERGE_FIT_FIELDS):
+        out[k] = f[:, i].copy()
+    return out

@@ -1527,3 +1527,305 @@ void oracle_track_model(const oparams* par, const float* p, int32_t z_anchor, in
     frozen[i] = m.frozen;
   }
 }
+
+/* ------------------------------------ segment merging and the T0 / z fit */
+/* The paper (section "Hardware and data flow") asks for full online TPC track
+ * reconstruction; the per-sector following leaves a particle that crosses a
+ * sector boundary, or loops back inside a sector, as several segments, and
+ * the drift coordinate of continuous readout is known only up to the
+ * collision's start time T0.  Reading: two segments of one frame and one
+ * side are joined when an end of one and an end of the other are within
+ * MG_DZMAX cm in drift and MG_GAP cm in the bending plane and each is reached
+ * from the other along the other segment's helix: within MG_PERP cm of its
+ * circle, an arc of at most MG_GAP cm, within MG_DZ (+ MG_DZ_ARC per cm of
+ * arc) cm of its dip line, with tangents that differ by |sin| <= MG_SIN
+ * there; and their curvatures differ by at most MG_DC_REL of the larger plus
+ * MG_DC_ABS.  A merged track is a
+ * connected component of that relation, named by its smallest segment index.
+ * Each merged track gets a helix fit of all its hits in global coordinates:
+ * an algebraic (Kasa) circle fit about the centroid, then a straight-line fit
+ * of the drift coordinate against the unwrapped azimuth about the centre.
+ * For a particle from z = 0, |z| grows along the path, so the drift
+ * coordinate grows towards the vertex: the helix is followed to the beam axis
+ * (the azimuth of the origin about the centre) in the direction in which the
+ * drift coordinate grows, to the first such azimuth beyond the hits; the
+ * drift coordinate there is 250 + T0/2 (T0 in time bins). */
+#define MG_GAP 30.0     /* cm: longest arc between two joined ends */
+#define MG_DZMAX 35.0   /* cm: largest drift distance between two joined ends */
+#define MG_PERP 0.5     /* cm off the other segment's circle */
+#define MG_DZ 1.0       /* cm off the other segment's dip line, plus MG_DZ_ARC per cm of arc */
+#define MG_DZ_ARC 0.02
+#define MG_SIN 0.1      /* |sin| of the angle between the tangents at the joined end */
+#define MG_DC_REL 0.2
+#define MG_DC_ABS 1e-3  /* 1/cm */
+#define MG_C_LINE 1e-4  /* 1/cm: below it a segment is followed as a straight line */
+#define MG_TIE 1e-9     /* relative margin at which a cut counts as a near tie */
+
+typedef struct {
+  double X, Y, z, tx, ty; /* global position, drift z, global tangent (outward fit sense) */
+} mg_end;
+
+typedef struct {
+  int64_t frame, side;
+  double C, tgl; /* signed curvature and dip (drift) of the outward fit */
+  mg_end e[2];   /* innermost, outermost hit */
+  int ok;
+} mg_seg;
+
+static int mg_row_of(const uint32_t* crow, int64_t n_ur, int64_t c, int64_t* ur) {
+  int64_t lo = 0, hi = n_ur;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) / 2;
+    if ((int64_t)crow[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  *ur = lo;
+  return (int)(lo % NROW);
+}
+
+static void mg_alpha(int64_t sector, double* ca, double* sa) {
+  const double a = ((double)(sector % 18) + 0.5) * 20.0 * PI_D / 180.0;
+  *ca = cos(a);
+  *sa = sin(a);
+}
+
+static double mg_wrap(double a) { /* into (-pi, pi] */
+  while (a > PI_D) a -= 2 * PI_D;
+  while (a <= -PI_D) a += 2 * PI_D;
+  return a;
+}
+
+/* one cut: passes when v <= cut; a value within the margin is a near tie */
+static int mg_cut(double v, double cut, int* tie) {
+  if (fabs(v - cut) <= MG_TIE * cut) *tie = 1;
+  return v <= cut;
+}
+
+/* End b seen from end a of segment A, following A's helix from a: the
+ * distance of b from A's circle, the signed arc to b's nearest point on it,
+ * the drift z that A's dip line gives there and the tangent there. */
+static int mg_follows(const mg_seg* A, const mg_end* a, const mg_end* b, int* tie) {
+  const double dx = b->X - a->X, dy = b->Y - a->Y;
+  double perp, arc, tx, ty;
+  if (fabs(A->C) >= MG_C_LINE) {
+    const double r = 1.0 / A->C; /* signed: the centre lies to the left when C > 0 */
+    const double cx = a->X - r * a->ty, cy = a->Y + r * a->tx;
+    const double ux = a->X - cx, uy = a->Y - cy, vx = b->X - cx, vy = b->Y - cy;
+    perp = fabs(sqrt(vx * vx + vy * vy) - fabs(r));
+    const double dpsi = atan2(ux * vy - uy * vx, ux * vx + uy * vy);
+    arc = dpsi / A->C;
+    const double turn = A->C * arc;
+    tx = a->tx * cos(turn) - a->ty * sin(turn);
+    ty = a->tx * sin(turn) + a->ty * cos(turn);
+  } else {
+    perp = fabs(a->tx * dy - a->ty * dx);
+    arc = a->tx * dx + a->ty * dy;
+    tx = a->tx;
+    ty = a->ty;
+  }
+  int ok = mg_cut(perp, MG_PERP, tie);
+  ok &= mg_cut(fabs(arc), MG_GAP, tie);
+  ok &= mg_cut(fabs(b->z - a->z - A->tgl * arc), MG_DZ + MG_DZ_ARC * fabs(arc), tie);
+  ok &= mg_cut(fabs(tx * b->ty - ty * b->tx), MG_SIN, tie);
+  return ok;
+}
+
+/* 1 joined, 0 not; *tie set when a cut is met within the near-tie margin */
+static int mg_compatible(const mg_seg* A, const mg_seg* B, int* tie) {
+  if (!A->ok || !B->ok || A->frame != B->frame || A->side != B->side) return 0;
+  const double ca = fabs(A->C), cb = fabs(B->C), cm = ca > cb ? ca : cb;
+  int found = 0;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const mg_end* a = &A->e[i];
+      const mg_end* b = &B->e[j];
+      /* two gates first: the ends near in drift and in the bending plane;
+         the other cuts (and their near ties) count only inside both.  Drift
+         positions are multiples of 2^-16 cm, so their difference is exact
+         and the first gate has no near tie. */
+      if (!(fabs(a->z - b->z) <= MG_DZMAX)) continue;
+      const double dxy = sqrt((a->X - b->X) * (a->X - b->X) + (a->Y - b->Y) * (a->Y - b->Y));
+      if (!mg_cut(dxy, MG_GAP, tie)) continue;
+      int ok = mg_cut(fabs(ca - cb), MG_DC_REL * cm + MG_DC_ABS, tie);
+      ok &= mg_follows(A, a, b, tie);
+      ok &= mg_follows(B, b, a, tie);
+      if (ok) found = 1;
+    }
+  return found;
+}
+
+static int64_t mg_find(int64_t* p, int64_t x) {
+  while (p[x] != x) x = p[x];
+  return x;
+}
+
+/* Inputs as for oracle_compress (tracks with their hits in ascending row).
+ * Outputs per track: label (component = smallest member), near_tie; per
+ * component, at its label: fit[12] = {n_segments, n_hits, xc, yc, radius,
+ * dz_d/dpsi, z_d at the axis, T0, |tan lambda|, flags, turning angle of the
+ * hits, 0} with flags 1 = circle fit, 2 = T0 estimated.  With T0 the global
+ * |z| of a point of drift coordinate z_d is 250 + T0/2 - z_d. */
+void oracle_merge_tracks(const oparams* par, int32_t n_units, const uint32_t* crow_start,
+                         const int32_t* y_fx, const int32_t* z_fx, int64_t n_tracks,
+                         const float* tpar, const uint8_t* trow, const uint32_t* hit_start,
+                         const uint32_t* hits, int64_t* label, int32_t* near_tie, double* fit) {
+  geometry_init();
+  const int64_t n_ur = (int64_t)n_units * NROW;
+  mg_seg* S = (mg_seg*)calloc(n_tracks > 0 ? n_tracks : 1, sizeof(mg_seg));
+  for (int64_t j = 0; j < n_tracks; ++j) {
+    const uint32_t h0 = hit_start[j], h1 = hit_start[j + 1];
+    mg_seg* s = &S[j];
+    s->ok = h1 > h0;
+    if (!s->ok) continue;
+    int64_t ur0, ur1;
+    const int r0 = mg_row_of(crow_start, n_ur, hits[h0], &ur0);
+    const int r1 = mg_row_of(crow_start, n_ur, hits[h1 - 1], &ur1);
+    const int64_t unit = ur0 / NROW, sector = unit % 36;
+    s->frame = unit / 36;
+    s->side = sector / 18;
+    s->C = -par->bz_b * (double)tpar[5 * j + 4];
+    s->tgl = (double)tpar[5 * j + 3];
+    double ca, sa;
+    mg_alpha(sector, &ca, &sa);
+    /* sin phi at the parameters' row, then at the two end rows (exact circle) */
+    const double xp = G_X[trow[j]];
+    const double sp = (double)tpar[5 * j + 2];
+    const int rows[2] = {r0, r1};
+    const int64_t cs[2] = {hits[h0], hits[h1 - 1]};
+    for (int e = 0; e < 2; ++e) {
+      const double x = G_X[rows[e]], y = y_fx[cs[e]] / 65536.0;
+      double snp = sp + s->C * (x - xp);
+      if (snp > 0.999999) snp = 0.999999;
+      if (snp < -0.999999) snp = -0.999999;
+      const double cp = sqrt(1.0 - snp * snp);
+      s->e[e].X = x * ca - y * sa;
+      s->e[e].Y = x * sa + y * ca;
+      s->e[e].z = z_fx[cs[e]] / 65536.0;
+      s->e[e].tx = cp * ca - snp * sa;
+      s->e[e].ty = cp * sa + snp * ca;
+    }
+  }
+  /* components of the pair relation (all pairs: plain, obviously complete) */
+  int64_t* p = (int64_t*)malloc((n_tracks > 0 ? n_tracks : 1) * sizeof(int64_t));
+  for (int64_t j = 0; j < n_tracks; ++j) {
+    p[j] = j;
+    near_tie[j] = 0;
+  }
+  for (int64_t a = 0; a < n_tracks; ++a)
+    for (int64_t b = a + 1; b < n_tracks; ++b) {
+      if (S[a].frame != S[b].frame || S[a].side != S[b].side) continue;
+      int tie = 0;
+      const int ok = mg_compatible(&S[a], &S[b], &tie);
+      if (tie) near_tie[a] = near_tie[b] = 1;
+      if (ok) {
+        const int64_t ra = mg_find(p, a), rb = mg_find(p, b);
+        if (ra < rb) p[rb] = ra;
+        else if (rb < ra) p[ra] = rb;
+      }
+    }
+  for (int64_t j = 0; j < n_tracks; ++j) label[j] = mg_find(p, j);
+  /* the fit of each component, members in ascending index, hits in order */
+  for (int64_t j = 0; j < 12 * n_tracks; ++j) fit[j] = 0;
+  for (int64_t root = 0; root < n_tracks; ++root) {
+    if (label[root] != root) continue;
+    double* f = fit + 12 * root;
+    double sx = 0, sy = 0;
+    int64_t n = 0, nseg = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      double mx = n ? sx / n : 0, my = n ? sy / n : 0;
+      double suu = 0, svv = 0, suv = 0, suuu = 0, svvv = 0, suvv = 0, svuu = 0;
+      for (int64_t j = root; j < n_tracks; ++j) {
+        if (label[j] != root) continue;
+        if (pass == 0) ++nseg;
+        for (uint32_t h = hit_start[j]; h < hit_start[j + 1]; ++h) {
+          int64_t ur;
+          const int r = mg_row_of(crow_start, n_ur, hits[h], &ur);
+          double ca, sa;
+          mg_alpha((ur / NROW) % 36, &ca, &sa);
+          const double x = G_X[r], y = y_fx[hits[h]] / 65536.0;
+          const double X = x * ca - y * sa, Y = x * sa + y * ca;
+          if (pass == 0) {
+            sx += X;
+            sy += Y;
+            ++n;
+          } else {
+            const double u = X - mx, v = Y - my;
+            suu += u * u;
+            svv += v * v;
+            suv += u * v;
+            suuu += u * u * u;
+            svvv += v * v * v;
+            suvv += u * v * v;
+            svuu += v * u * u;
+          }
+        }
+      }
+      if (pass == 1) {
+        f[0] = (double)nseg;
+        f[1] = (double)n;
+        const double det = suu * svv - suv * suv;
+        if (n < 3 || !(fabs(det) > 0)) break;
+        const double b1 = 0.5 * (suuu + suvv), b2 = 0.5 * (svvv + svuu);
+        const double uc = (b1 * svv - b2 * suv) / det, vc = (suu * b2 - suv * b1) / det;
+        f[2] = mx + uc;
+        f[3] = my + vc;
+        f[4] = sqrt(uc * uc + vc * vc + (suu + svv) / n);
+        f[9] = 1;
+      }
+    }
+    if (f[9] == 0) continue;
+    /* drift coordinate against the unwrapped azimuth about the centre */
+    const double xc = f[2], yc = f[3];
+    double psi_prev = 0, acc = 0, spsi = 0, spsi2 = 0, sz = 0, szp = 0;
+    double pmin = 0, pmax = 0;
+    int64_t k = 0;
+    for (int64_t j = root; j < n_tracks; ++j) {
+      if (label[j] != root) continue;
+      for (uint32_t h = hit_start[j]; h < hit_start[j + 1]; ++h) {
+        int64_t ur;
+        const int r = mg_row_of(crow_start, n_ur, hits[h], &ur);
+        double ca, sa;
+        mg_alpha((ur / NROW) % 36, &ca, &sa);
+        const double x = G_X[r], y = y_fx[hits[h]] / 65536.0;
+        const double X = x * ca - y * sa, Y = x * sa + y * ca;
+        const double psi = atan2(Y - yc, X - xc);
+        acc = k == 0 ? 0.0 : acc + mg_wrap(psi - psi_prev);
+        psi_prev = psi;
+        const double z = z_fx[hits[h]] / 65536.0;
+        spsi += acc;
+        spsi2 += acc * acc;
+        sz += z;
+        szp += z * acc;
+        if (k == 0 || acc < pmin) pmin = acc;
+        if (k == 0 || acc > pmax) pmax = acc;
+        ++k;
+      }
+    }
+    const double dd = k * spsi2 - spsi * spsi;
+    if (!(dd > 0)) continue;
+    const double slope = (k * szp - spsi * sz) / dd, icpt = (sz - slope * spsi) / k;
+    f[5] = slope;
+    f[8] = fabs(slope) / f[4]; /* |tan lambda| = |dz/ds| of the merged helix */
+    f[10] = pmax - pmin;
+    if (pmax - pmin < 2 * PI_D) {
+      /* the origin's azimuth about the centre, unwrapped next to the last
+         hit, then moved to the first value beyond the hits on the side where
+         the drift coordinate grows */
+      const double psi0 = atan2(-yc, -xc);
+      double a = acc + mg_wrap(psi0 - psi_prev);
+      if (slope >= 0) {
+        while (a < pmax) a += 2 * PI_D;
+        while (a - 2 * PI_D >= pmax) a -= 2 * PI_D;
+      } else {
+        while (a > pmin) a -= 2 * PI_D;
+        while (a + 2 * PI_D <= pmin) a += 2 * PI_D;
+      }
+      const double zd0 = icpt + slope * a;
+      f[6] = zd0;
+      f[7] = 2.0 * (zd0 - 250.0); /* T0 in time bins */
+      f[9] = 3;
+    }
+  }
+  free(p);
+  free(S);
+}
