@@ -542,6 +542,28 @@ def main():
     log(f"[bench] compression: {out_comp}")
     del comp, dec
 
+    # segment merging and the T0 / z fit of the slice's tracks (HIP events)
+    mg = reco.alloc_merged(max_tl)
+    with torch.cuda.stream(stream):
+        reco.merge_tracks(cl, tr, mg)
+    reco.sync()
+    reco.profile(True)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            reco.merge_tracks(cl, tr, mg)
+    mprof = reco.profile_read()
+    reco.profile(False)
+    reco.sync()
+    mh = tpc.merged_to_host(mg, n_trk)
+    roots = mh["label"] == np.arange(n_trk)
+    out_merge = dict(ms=mprof["merge"][0] / max(mprof["merge"][1], 1), segments=n_trk,
+                     merged_tracks=mh["n_merged"],
+                     multi_segment=int((np.bincount(mh["label"], minlength=n_trk) > 1).sum()),
+                     with_t0=int((roots & (mh["flags"] == 3)).sum()),
+                     near_ties=int(mh["near_tie"].sum()))
+    log(f"[bench] merging: {out_merge}")
+    del mg
+
     # raw zero-suppressed pages of the slice decoded on the GPU (HIP events on
     # the library's stream); algorithmic bytes: the pages read, 6 B written per
     # sample, the row offsets written
@@ -685,6 +707,7 @@ def main():
     if out_pages is not None:
         out["zs_pages"] = out_pages
     out["compression"] = out_comp
+    out["merging"] = out_merge
     if tuning is not None:
         out["tuning"] = tuning["chosen"]
     # secondary throughput: the single-context graph preceded by the input's

@@ -414,6 +414,56 @@ typedef struct {
 int tpc_decompress(tpc_ctx* ctx, const uint32_t* stream, uint32_t stream_words,
                    tpc_decoded_clusters* out);
 
+/* Merging of track segments and the continuous-readout T0 / z fit (section
+ * "Hardware and data flow": full online TPC track reconstruction).  The
+ * per-sector following leaves a particle that crosses sector boundaries or
+ * loops back as several segments, and continuous readout measures drift
+ * times only up to the collision's start time T0; the paper gives no rule,
+ * the reading is this library's:
+ *   joining  two segments of one frame (36 consecutive units) and one side
+ *            (units 0-17 / 18-35 of the frame) are joined when an end of one
+ *            (its innermost or outermost hit: global position, drift z, and
+ *            the tangent of its outward fit there) and an end of the other
+ *            are within 35 cm in drift and 30 cm in the bending plane, each
+ *            is reached from the other along the other's helix (off its circle
+ *            by at most 0.5 cm, an arc of at most 30 cm, on its dip line
+ *            within 1 cm + 0.02 x the arc, tangents within |sin| 0.1; helices
+ *            with |C| < 1e-4/cm are followed as lines), and their curvatures
+ *            differ by at most 0.2 x the larger + 1e-3/cm (C = -bz_b q/pT);
+ *   merged   a connected component of that relation, named by its smallest
+ *            track index;
+ *   fit      all hits of a merged track (tracks in ascending index, hits in
+ *            order) in global coordinates (sector s at azimuth
+ *            ((s mod 18) + 0.5) 20 deg): an algebraic circle fit about the
+ *            centroid, then a least-squares line of drift z against the
+ *            azimuth about the centre, unwrapped hit to hit; when the hits
+ *            turn less than a full turn, the helix is followed to the
+ *            azimuth of the beam axis, first reached beyond the hits in the
+ *            direction in which drift z grows (|z| grows away from a vertex at
+ *            z = 0); the drift z there is 250 cm + T0 / 2 (T0 in time bins),
+ *            and a point of drift z_d lies at |z| = 250 + T0 / 2 - z_d.
+ * Comparisons within 1e-9 (relative) of a cut are flagged as near ties. */
+#define TPC_MERGE_FIT 12
+typedef struct {
+  uint32_t capacity;          /* entries of label / near_tie, records of fit */
+  uint32_t* n_merged;         /* [1] device: number of merged tracks */
+  int32_t* label;             /* [capacity] merged track of each track: its smallest member */
+  uint8_t* near_tie;          /* [capacity] 1 where a joining decision was a near tie */
+  double* fit;                /* [capacity * TPC_MERGE_FIT], filled at each merged
+                                 track's label (zero elsewhere): n_segments, n_hits,
+                                 centre x, y, radius (cm), dz_drift / d azimuth
+                                 (cm/rad), drift z at the beam axis, T0 (bins),
+                                 |tan lambda|, flags (1 circle fitted, 3 and T0),
+                                 azimuth range of the hits (rad), 0 */
+} tpc_merged;
+
+/* Join the segments of a reconstruction and fit the merged tracks.  Reads
+ * cl->crow_start, y_fx, z_fx, n_clusters and tr->par, row, hit_start, hits,
+ * n_tracks (hits in ascending row).  TPC_ERR_ARG for missing pointers, a
+ * track capacity above max_tracklets or out->capacity below it. */
+int tpc_merge_tracks(tpc_ctx* ctx, const tpc_clusters* cl, const tpc_tracks* tr,
+                     tpc_merged* out);
+
 /* Wait for the stream, then report the first latched error and the counts.
  * Clears the status word for the next call. */
 int tpc_sync(tpc_ctx* ctx, tpc_counts* counts);
@@ -434,8 +484,9 @@ void* tpc_stream(tpc_ctx* ctx);
  * seed points, timed inside the fit call), 7 following (sorts and passes),
  * 8 resolution, 9 refit (FP64 head, FP32, FP64 redo), 10 count of the FP64
  * redos, 11 track output, 12 raw ZS page decoding (tpc_decode_zs_pages),
- * 13 compression (tpc_compress), 14 decompression (tpc_decompress). */
-#define TPC_PROF_STAGES 15
+ * 13 compression (tpc_compress), 14 decompression (tpc_decompress), 15 merging
+ * and the T0 fit (tpc_merge_tracks). */
+#define TPC_PROF_STAGES 16
 int tpc_profile_enable(tpc_ctx* ctx, int on);
 int tpc_profile_read(tpc_ctx* ctx, double* ms, uint32_t* launches);
 const char* tpc_profile_stage_name(int stage);

@@ -21,6 +21,7 @@
 #include "k_qc.hpp"
 #include "k_zspage.hpp"
 #include "k_compress.hpp"
+#include "k_merge.hpp"
 
 namespace {
 
@@ -91,6 +92,12 @@ struct tpc_ctx {
   uint32_t *cm_a = nullptr, *cm_b = nullptr;  // compression: lengths / counts, offsets
   unsigned long long* cm_tot = nullptr;       // compression: bit totals
   uint32_t* cm_info = nullptr;                // compression: sizes of the stream
+  // merging: per-segment ends, cells, union-find, member sort
+  uint32_t *mg_fs = nullptr, *mg_cell = nullptr, *mg_cnt = nullptr, *mg_off = nullptr,
+           *mg_cur = nullptr, *mg_ends = nullptr, *mg_parent = nullptr, *mg_key = nullptr,
+           *mg_idx = nullptr, *mg_skey = nullptr, *mg_sidx = nullptr;
+  uint8_t* mg_sector = nullptr;
+  double *mg_C = nullptr, *mg_tgl = nullptr, *mg_e = nullptr, *mg_cs18 = nullptr;
   size_t bsum_cap = 0;
   tpc_tuning tune;
   // stage timing (measurement only)
@@ -117,7 +124,9 @@ struct Layout {
 
 struct Plan {
   size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
-      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, cm_a, cm_b, cm_tot, cm_info, hit_off, par, st, total;
+      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, cm_a, cm_b, cm_tot, cm_info, mg_fs,
+      mg_cell, mg_cnt, mg_off, mg_cur, mg_ends, mg_parent, mg_key, mg_idx, mg_skey, mg_sidx,
+      mg_sector, mg_C, mg_tgl, mg_e, mg_cs18, hit_off, par, st, total;
   size_t bsum_cap;
   uint32_t nblk, nblk_s, nwin;
 };
@@ -133,6 +142,12 @@ uint64_t cm_records(const tpc_sizes& m) {
   return (uint64_t)m.max_tracklets + (uint64_t)NROW * m.max_units + 2;
 }
 
+// Drift cells of the merging grid per (frame-side, sector) and the cells.
+uint32_t mg_nzb(uint32_t n_time_bins) { return (uint32_t)((n_time_bins / 2.0 + 2.0) / MG_ZBIN) + 2; }
+uint64_t mg_cells(const tpc_sizes& m) {
+  return (uint64_t)((m.max_units + 35) / 36) * 2 * 18 * mg_nzb(m.max_time_bins) + 1;
+}
+
 Plan plan_for(const tpc_sizes& m) {
   Plan p;
   Layout L;
@@ -145,6 +160,7 @@ Plan plan_for(const tpc_sizes& m) {
   if (m.max_tracklets > nscan) nscan = m.max_tracklets;
   if (max_pages(m) > nscan) nscan = max_pages(m);
   if (cm_records(m) > nscan) nscan = cm_records(m);
+  if (mg_cells(m) > nscan) nscan = mg_cells(m);
   if (256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + XCD_GROUPS - 1) > nscan)
     nscan = 256ull * (ceil_div(m.max_tracklets, SORT_BLOCK) + XCD_GROUPS - 1);
   p.bsum_cap = ceil_div(nscan, SCAN_TILE) + 1;
@@ -187,6 +203,22 @@ Plan plan_for(const tpc_sizes& m) {
   p.cm_b = L.add<uint32_t>(cm_records(m));
   p.cm_tot = L.add<unsigned long long>(2);
   p.cm_info = L.add<uint32_t>(8);
+  p.mg_fs = L.add<uint32_t>(mt);
+  p.mg_cell = L.add<uint32_t>(2 * mt);
+  p.mg_cnt = L.add<uint32_t>(mg_cells(m));
+  p.mg_off = L.add<uint32_t>(mg_cells(m) + 1);
+  p.mg_cur = L.add<uint32_t>(mg_cells(m) + 1);
+  p.mg_ends = L.add<uint32_t>(2 * mt);
+  p.mg_parent = L.add<uint32_t>(mt);
+  p.mg_key = L.add<uint32_t>(mt);
+  p.mg_idx = L.add<uint32_t>(mt);
+  p.mg_skey = L.add<uint32_t>(mt);
+  p.mg_sidx = L.add<uint32_t>(mt);
+  p.mg_sector = L.add<uint8_t>(mt);
+  p.mg_C = L.add<double>(mt);
+  p.mg_tgl = L.add<double>(mt);
+  p.mg_e = L.add<double>(10 * mt);
+  p.mg_cs18 = L.add<double>(36);
   p.par = L.add<DevParams>(1);
   p.st = L.add<DevStatus>(1);
   p.total = (L.off + 255) & ~(size_t)255;
@@ -742,6 +774,22 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->cm_b = (uint32_t*)(base + pl.cm_b);
   c->cm_tot = (unsigned long long*)(base + pl.cm_tot);
   c->cm_info = (uint32_t*)(base + pl.cm_info);
+  c->mg_fs = (uint32_t*)(base + pl.mg_fs);
+  c->mg_cell = (uint32_t*)(base + pl.mg_cell);
+  c->mg_cnt = (uint32_t*)(base + pl.mg_cnt);
+  c->mg_off = (uint32_t*)(base + pl.mg_off);
+  c->mg_cur = (uint32_t*)(base + pl.mg_cur);
+  c->mg_ends = (uint32_t*)(base + pl.mg_ends);
+  c->mg_parent = (uint32_t*)(base + pl.mg_parent);
+  c->mg_key = (uint32_t*)(base + pl.mg_key);
+  c->mg_idx = (uint32_t*)(base + pl.mg_idx);
+  c->mg_skey = (uint32_t*)(base + pl.mg_skey);
+  c->mg_sidx = (uint32_t*)(base + pl.mg_sidx);
+  c->mg_sector = (uint8_t*)(base + pl.mg_sector);
+  c->mg_C = (double*)(base + pl.mg_C);
+  c->mg_tgl = (double*)(base + pl.mg_tgl);
+  c->mg_e = (double*)(base + pl.mg_e);
+  c->mg_cs18 = (double*)(base + pl.mg_cs18);
   c->d_par = (DevParams*)(base + pl.par);
   c->d_st = (DevStatus*)(base + pl.st);
   c->bsum_cap = pl.bsum_cap;
@@ -749,7 +797,15 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   const DevParams dp = make_dev_params(*p);
   DevStatus ds;
   std::memset(&ds, 0, sizeof ds);
-  if (hipMemcpy(c->d_par, &dp, sizeof dp, hipMemcpyHostToDevice) != hipSuccess ||
+  // sector azimuths ((s + 0.5) 20 deg) for the merging's global frame
+  double cs18[36];
+  for (int k = 0; k < 18; ++k) {
+    const double a = ((double)k + 0.5) * 20.0 * M_PI / 180.0;
+    cs18[2 * k] = std::cos(a);
+    cs18[2 * k + 1] = std::sin(a);
+  }
+  if (hipMemcpy(c->mg_cs18, cs18, sizeof cs18, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_par, &dp, sizeof dp, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_st, &ds, sizeof ds, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(base);
     delete c;
@@ -855,6 +911,74 @@ int tpc_decompress(tpc_ctx* c, const uint32_t* stream, uint32_t stream_words,
                    out->qtot, out->qmax, out->flags, out->track};
   k_cm_dec_records<<<grid_for(max_rec, 256, 4096), 256, 0, s>>>(
       stream, c->cm_info, c->cm_b, c->cm_tot, cm_b30(c), c->d_par, o, c->d_st);
+  return launch_ok();
+}
+
+struct MgEmitOff {
+  uint32_t *off, *cur;
+  __device__ void operator()(uint32_t i, uint32_t pre, uint32_t) const {
+    off[i] = pre;
+    cur[i] = pre;
+  }
+};
+
+int tpc_merge_tracks(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, tpc_merged* out) {
+  if (!c || check_clusters(c, cl, false) || !tr || !out || !out->n_merged || !out->label ||
+      !out->near_tie || !out->fit)
+    return TPC_ERR_ARG;
+  if (!tr->par || !tr->row || !tr->hit_start || !tr->hits || !tr->n_tracks ||
+      tr->capacity > c->max.max_tracklets || out->capacity < tr->capacity || tr->capacity == 0)
+    return TPC_ERR_ARG;
+  hipStream_t s = c->stream;
+  StageTimer tm(c, 15);
+  const uint32_t cap = tr->capacity, n_ur = cl->n_units * NROW;
+  const uint32_t nzb = mg_nzb(cl->n_time_bins);
+  const uint32_t n_cells = ((cl->n_units + 35) / 36) * 2 * 18 * nzb;
+  const MgSegs S{c->mg_fs, c->mg_sector, c->mg_C, c->mg_tgl, c->mg_e};
+  k_fill<uint32_t><<<grid_for(n_cells, 256, 4096), 256, 0, s>>>(c->mg_cnt, 0u, n_cells);
+  k_fill<double><<<grid_for((uint64_t)out->capacity * TPC_MERGE_FIT, 256, 4096), 256, 0, s>>>(
+      out->fit, 0.0, out->capacity * TPC_MERGE_FIT);
+  k_mg_init<<<grid_for(cap, 256, 4096), 256, 0, s>>>(c->mg_parent, out->near_tie, c->mg_idx, cap,
+                                                     c->d_st);
+  k_mg_segments<<<grid_for(cap, 256, 4096), 256, 0, s>>>(
+      cl->crow_start, n_ur, cl->y_fx, cl->z_fx, cl->n_clusters, cl->capacity, tr->par, tr->row,
+      tr->hit_start, tr->hits, tr->hit_capacity, tr->n_tracks, cap, c->mg_cs18, c->par.bz_b, nzb,
+      S, c->mg_cell, c->mg_cnt, c->d_par, c->d_st);
+  run_scan<uint32_t>(c, GetU32{c->mg_cnt}, MgEmitOff{c->mg_off, c->mg_cur}, nullptr, n_cells,
+                     (uint32_t*)nullptr, c->tot32);
+  k_mg_total<<<1, 1, 0, s>>>(c->mg_off, c->tot32, n_cells, c->d_st);
+  k_mg_fill_cells<<<grid_for(2 * (uint64_t)cap, 256, 4096), 256, 0, s>>>(
+      c->mg_cell, tr->n_tracks, cap, c->mg_cur, c->mg_ends, c->d_st);
+  k_mg_pairs<<<grid_for(2 * (uint64_t)cap, 256, 8192), 256, 0, s>>>(
+      S, tr->n_tracks, cap, nzb, c->mg_off, c->mg_ends, c->mg_cell, c->mg_parent, out->near_tie,
+      c->d_st);
+  k_mg_labels<<<grid_for(cap, 256, 4096), 256, 0, s>>>(c->mg_parent, tr->n_tracks, cap, out->label,
+                                                       c->mg_key, c->d_st);
+  // members grouped by component in ascending index: labels are below 2^24
+  {
+    const uint32_t nb = ceil_div(cap, MG_SORT_BLOCK);
+    uint32_t *ki = c->mg_key, *vi = c->mg_idx, *ko = c->mg_skey, *vo = c->mg_sidx;
+    for (int shift = 0; shift < 24; shift += 8) {
+      k_mg_rsort<false><<<nb, 256, 0, s>>>(ki, vi, tr->n_tracks, cap, shift, c->f_bins, ko, vo,
+                                           c->d_st);
+      run_scan<uint32_t>(c, GetU32{c->f_bins}, EmitU32{c->f_bins}, nullptr, 256 * nb,
+                         (uint32_t*)nullptr, c->tot32 + 1);
+      k_mg_rsort<true><<<nb, 256, 0, s>>>(ki, vi, tr->n_tracks, cap, shift, c->f_bins, ko, vo,
+                                          c->d_st);
+      uint32_t* t = ki;
+      ki = ko;
+      ko = t;
+      t = vi;
+      vi = vo;
+      vo = t;
+    }
+    // three passes: the result is in (mg_skey, mg_sidx)
+  }
+  k_mg_fit<<<grid_for(cap, 64, 16384), 64, 0, s>>>(c->mg_skey, c->mg_sidx, tr->n_tracks, cap,
+                                                   cl->crow_start, n_ur, cl->y_fx, cl->z_fx,
+                                                   tr->hit_start, tr->hits, tr->hit_capacity,
+                                                   c->mg_cs18, out->fit, c->d_par, c->d_st);
+  run_count<uint32_t>(c, MgIsRoot{out->label}, tr->n_tracks, cap, out->n_merged);
   return launch_ok();
 }
 
@@ -1047,7 +1171,7 @@ const char* tpc_profile_stage_name(int i) {
   static const char* names[TPC_PROF_STAGES] = {
       "sample_index", "cluster_peaks", "cluster_scan", "cluster_output", "cluster_grid",
       "neighbours", "tracklets", "following", "resolution", "refit", "fp64_count",
-      "track_output", "zs_decode", "compress", "decompress"};
+      "track_output", "zs_decode", "compress", "decompress", "merge"};
   return (i >= 0 && i < TPC_PROF_STAGES) ? names[i] : "unknown";
 }
 

@@ -62,6 +62,10 @@ class TpcDecoded(ctypes.Structure):
                 ("z_fx", P), ("qtot", P), ("qmax", P), ("flags", P), ("track", P)]
 
 
+class TpcMerged(ctypes.Structure):
+    _fields_ = [("capacity", U32), ("n_merged", P), ("label", P), ("near_tie", P), ("fit", P)]
+
+
 class TpcClusters(ctypes.Structure):
     _fields_ = [("capacity", U32), ("n_units", U32), ("n_time_bins", U32), ("n_clusters", P),
                 ("crow_start", P), ("y_fx", P), ("z_fx", P), ("dpad", P), ("dtime", P),
@@ -108,8 +112,8 @@ EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_crea
            "tpc_status_string", "tpc_profile_enable", "tpc_profile_read",
            "tpc_profile_stage_name", "tpc_tuning_default", "tpc_set_tuning", "tpc_get_tuning",
            "tpc_qc_histograms", "tpc_qc_histograms_noalloc", "tpc_decode_zs_pages",
-           "tpc_compress", "tpc_decompress"]
-PROF_STAGES = 15
+           "tpc_compress", "tpc_decompress", "tpc_merge_tracks"]
+PROF_STAGES = 16
 # quality-control histogram layout (bin offsets; see tpc_qc_histograms)
 QC_QTOT, QC_QMAX, QC_NHITS, QC_ATTACH, QC_BINS = 0, 256, 512, 665, 667
 
@@ -143,6 +147,7 @@ def load():
     lib.tpc_decode_zs_pages.argtypes = [P, P, U32, P]
     lib.tpc_compress.argtypes = [P, P, P, P]
     lib.tpc_decompress.argtypes = [P, P, U32, P]
+    lib.tpc_merge_tracks.argtypes = [P, P, P, P]
     lib.tpc_sync.argtypes = [P, P]
     lib.tpc_stream.argtypes = [P]
     lib.tpc_stream.restype = P
@@ -323,9 +328,11 @@ class Reco:
         b.t["n_tracks"].copy_(torch.tensor([n], dtype=torch.int32))
         b.t["n_hits"].copy_(torch.tensor([nh], dtype=torch.int32))
         b.t["hit_start"][:n + 1].copy_(dev(tr["hit_start"], np.uint32, np.int32))
-        nc = len(tr["cluster_track"])
-        if nc:
+        if "cluster_track" in tr and len(tr["cluster_track"]):
+            nc = len(tr["cluster_track"])
             b.t["cluster_track"][:nc].copy_(dev(tr["cluster_track"], np.int32, np.int32))
+        else:
+            b.t["cluster_track"].fill_(-1)
         if n:
             b.t["par"][:n * 5].copy_(dev(np.asarray(tr["par"]).reshape(-1), np.float32, np.float32))
             b.t["row"][:n].copy_(dev(tr["row"], np.uint8, np.uint8))
@@ -344,6 +351,18 @@ class Reco:
             t["res_hist"] = torch.zeros(256, dtype=torch.int32, device=d)
         s = TpcCompressed(int(capacity_words), _dptr(t["stream"]), _dptr(t["n_words"]),
                           _dptr(t.get("res_hist")))
+        return Buffers(t, s)
+
+    def alloc_merged(self, capacity: int) -> Buffers:
+        """Device arrays for merged tracks (tpc_merged)."""
+        torch = _torch()
+        d = self.device
+        cap = max(int(capacity), 1)
+        t = dict(n_merged=torch.zeros(1, dtype=torch.int32, device=d),
+                 label=torch.empty(cap, dtype=torch.int32, device=d),
+                 near_tie=torch.empty(cap, dtype=torch.uint8, device=d),
+                 fit=torch.empty(cap * MERGE_FIT, dtype=torch.float64, device=d))
+        s = TpcMerged(cap, *[_dptr(t[k]) for k in ("n_merged", "label", "near_tie", "fit")])
         return Buffers(t, s)
 
     def alloc_decoded(self, capacity: int) -> Buffers:
@@ -431,6 +450,11 @@ class Reco:
             raise ValueError("decompress: stream must be a device tensor of 32-bit words")
         _check(self.lib.tpc_decompress(self.ctx, ctypes.c_void_p(stream.data_ptr()), n,
                                        ctypes.byref(out.s)), "tpc_decompress")
+
+    def merge_tracks(self, cl: Buffers, tr: Buffers, out: Buffers):
+        """Join segments into tracks and fit them, with T0 (tpc_merge_tracks)."""
+        _check(self.lib.tpc_merge_tracks(self.ctx, ctypes.byref(cl.s), ctypes.byref(tr.s),
+                                         ctypes.byref(out.s)), "tpc_merge_tracks")
 
     def cluster(self, zs: dict, out: Buffers):
         _check(self.lib.tpc_cluster(self.ctx, ctypes.byref(zs_struct(zs)), ctypes.byref(out.s)),
@@ -540,6 +564,20 @@ def zs_soa_to_host(b: Buffers) -> dict:
     return dict(n_samples=n, pad=_u(b["pad"], m, np.uint16), time=_u(b["time"], m, np.uint16),
                 adc=_u(b["adc"], m, np.uint16),
                 row_start=_u(b["row_start"], int(b.s.n_units) * NROW + 1, np.uint32))
+
+
+MERGE_FIT = 12
+MERGE_FIT_FIELDS = ("n_segments", "n_hits", "xc", "yc", "radius", "dzdpsi", "zd_axis", "t0",
+                    "tgl", "flags", "turn")
+
+
+def merged_to_host(b: Buffers, n_tracks: int) -> dict:
+    f = b["fit"][: n_tracks * MERGE_FIT].cpu().numpy().reshape(n_tracks, MERGE_FIT)
+    out = dict(n_merged=int(b["n_merged"].item()), label=b["label"][:n_tracks].cpu().numpy(),
+               near_tie=b["near_tie"][:n_tracks].cpu().numpy().astype(bool))
+    for i, k in enumerate(MERGE_FIT_FIELDS):
+        out[k] = f[:, i].copy()
+    return out
 
 
 def compressed_to_host(b: Buffers) -> dict:

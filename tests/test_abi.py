@@ -100,6 +100,7 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"tpc_params": tpc.TpcParams, "tpc_sizes": tpc.TpcSizes,
                "tpc_zs_input": tpc.TpcZsInput, "tpc_zs_soa": tpc.TpcZsSoa,
                "tpc_compressed": tpc.TpcCompressed, "tpc_decoded_clusters": tpc.TpcDecoded,
+               "tpc_merged": tpc.TpcMerged,
                "tpc_clusters": tpc.TpcClusters,
                "tpc_links": tpc.TpcLinks, "tpc_tracklets": tpc.TpcTracklets,
                "tpc_tracks": tpc.TpcTracks, "tpc_counts": tpc.TpcCounts,
