@@ -1316,7 +1316,7 @@ static uint64_t cm_get(cm_reader* r, int n) {
 static uint64_t cm_geteg(cm_reader* r, int k) {
   int n = 0;
   while (!r->bad && cm_get(r, 1) == 0) {
-    if (++n > 32) { /* no code of the format has a longer prefix */
+    if (++n > 31) { /* no code of the format has a prefix of 32 zeros or more */
       r->bad = 1;
       return 0;
     }
@@ -1611,12 +1611,14 @@ static int mg_follows(const mg_seg* A, const mg_end* a, const mg_end* b, int* ti
     const double r = 1.0 / A->C; /* signed: the centre lies to the left when C > 0 */
     const double cx = a->X - r * a->ty, cy = a->Y + r * a->tx;
     const double ux = a->X - cx, uy = a->Y - cy, vx = b->X - cx, vy = b->Y - cy;
-    perp = fabs(sqrt(vx * vx + vy * vy) - fabs(r));
+    const double vr = sqrt(vx * vx + vy * vy);
+    perp = fabs(vr - fabs(r));
     const double dpsi = atan2(ux * vy - uy * vx, ux * vx + uy * vy);
     arc = dpsi / A->C;
-    const double turn = A->C * arc;
-    tx = a->tx * cos(turn) - a->ty * sin(turn);
-    ty = a->tx * sin(turn) + a->ty * cos(turn);
+    /* the tangent where b projects onto the circle: the radius vector turned
+       by a quarter turn in the sense of the motion */
+    tx = A->C > 0 ? -vy / vr : vy / vr;
+    ty = A->C > 0 ? vx / vr : -vx / vr;
   } else {
     perp = fabs(a->tx * dy - a->ty * dx);
     arc = a->tx * dx + a->ty * dy;

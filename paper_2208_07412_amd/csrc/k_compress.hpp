@@ -175,10 +175,13 @@ struct CmWriter {
 };
 
 // ------------------------------------------------------------- bit reading
+// Sequential reader of a bit range; w points at payload word woff (a staged
+// copy in LDS, or the payload itself with woff = 0).
 struct CmReader {
   const uint32_t* w;
   uint64_t pos, end;  // end = payload bits
   bool bad;
+  uint64_t woff;
   __device__ uint64_t get(uint32_t n) {  // n <= 32
     if (n == 0) return 0;
     if (pos + n > end) {
@@ -186,21 +189,34 @@ struct CmReader {
       pos = end;
       return 0;
     }
-    const uint64_t wi = pos >> 5;
+    const uint64_t wi = (pos >> 5) - woff;
     const uint32_t sh = (uint32_t)(pos & 31);
     uint64_t v = w[wi] >> sh;
     if (sh + n > 32) v |= (uint64_t)w[wi + 1] << (32 - sh);
     pos += n;
     return v & ((1ull << n) - 1);
   }
+  // up to 32 bits from pos on without advancing (bits past the end read 0)
+  __device__ uint32_t peek32() const {
+    if (pos >= end) return 0;
+    const uint64_t wi = (pos >> 5) - woff;
+    const uint32_t sh = (uint32_t)(pos & 31);
+    uint64_t v = w[wi] >> sh;
+    if (sh && pos + (32 - sh) < end) v |= (uint64_t)w[wi + 1] << (32 - sh);
+    const uint64_t avail = end - pos;
+    if (avail < 32) v &= (1ull << avail) - 1;
+    return (uint32_t)v;
+  }
   __device__ uint64_t eg(int k) {
-    uint32_t n = 0;
-    while (!bad && get(1) == 0) {
-      if (++n > 32) {
-        bad = true;
-        return 0;
-      }
+    // the zero prefix: the trailing zeros of the next 32 bits (LSB first)
+    const uint32_t v = peek32();
+    if (v == 0) {  // no one bit among the next 32: malformed
+      bad = true;
+      pos = end;
+      return 0;
     }
+    const uint32_t n = (uint32_t)__builtin_ctz(v);
+    pos += n + 1;
     const uint64_t q = (1ull << n) | get(n);
     return ((q - 1) << k) | get(k);
   }
@@ -585,7 +601,7 @@ __global__ void k_cm_dec_counts(const uint32_t* __restrict__ s, const uint32_t* 
                                 uint32_t* __restrict__ cnt, DevStatus* st) {
   if (failed(st) || !info[6]) return;
   const uint32_t nt = info[1], nrec = info[5];
-  CmReader r{s + info[4], 0, info[3], false};
+  CmReader r{s + info[4], 0, info[3], false, 0};
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nrec; i += gridDim.x * blockDim.x) {
     r.pos = s[CM_HDR + (i < nt ? i : i + 1)];
     r.bad = false;
@@ -597,78 +613,122 @@ __global__ void k_cm_dec_counts(const uint32_t* __restrict__ s, const uint32_t* 
   }
 }
 
-// One lane per record: decode it at its output offset and check that it ends
-// where the directory says the next one starts.
-__global__ __launch_bounds__(256) void k_cm_dec_records(const uint32_t* __restrict__ s,
-                                                        const uint32_t* info,
-                                                        const uint32_t* __restrict__ off,
-                                                        const unsigned long long* total,
-                                                        int64_t b30,
-                                                        const DevParams* __restrict__ P,
-                                                        CmDecOut o, DevStatus* st) {
+// Record i (a track for i < nt, else a row block) decoded from r at output
+// offset k; false if it is malformed or does not end at `end`.
+__device__ bool cm_decode_record(CmReader& r, uint32_t i, uint32_t nu, uint32_t nt, uint32_t nc,
+                                 uint32_t k, uint64_t end, int64_t b30, const int32_t* xfx,
+                                 const CmDecOut& o) {
+  bool bad = false;
+  if (i < nt) {
+    const uint32_t nh = (uint32_t)r.get(8);
+    const uint32_t unit = (uint32_t)r.get(16);
+    const int r0 = (int)r.get(8);
+    CmParams q;
+    q.Y = (int32_t)r.get(32);
+    q.Z = (int32_t)r.get(32);
+    q.S = (int32_t)r.get(32);
+    q.T = (int32_t)r.get(32);
+    q.K = (int32_t)r.get(32);
+    if (unit >= nu || r0 >= NROW) bad = true;
+    CmModel m = cm_model(q, b30, r0);
+    int prev = r0;
+    for (uint32_t h = 0; h < nh && !bad && !r.bad; ++h, ++k) {
+      const uint64_t stp = r.eg(0);
+      const int rr = prev + (int)(stp > NROW ? NROW : stp) + (h > 0 ? 1 : 0);
+      if (rr >= NROW || k >= nc || k >= o.capacity) {
+        bad = true;
+        break;
+      }
+      prev = rr;
+      while (m.row < rr) cm_step(m, xfx);
+      const int64_t yq = cm_q(m.Y) + cm_unzig(r.eg(2));
+      const int64_t zq = cm_q(m.Z) + cm_unzig(r.eg(2));
+      o.unit[k] = (uint16_t)unit;
+      o.row[k] = (uint8_t)rr;
+      o.y[k] = (int32_t)(yq << CM_QSHIFT);
+      o.z[k] = (int32_t)(zq << CM_QSHIFT);
+      o.qtot[k] = (uint16_t)r.eg(6);
+      o.qmax[k] = (uint16_t)r.eg(5);
+      o.flags[k] = (uint8_t)r.get(2);
+      o.track[k] = (int32_t)i;
+    }
+  } else {
+    const uint32_t ur = i - nt;
+    const uint64_t n = r.eg(0);
+    int64_t zprev = 0;
+    for (uint64_t c = 0; c < n && !r.bad; ++c, ++k) {
+      if (k >= nc || k >= o.capacity) {
+        bad = true;
+        break;
+      }
+      const int64_t yq = cm_unzig(r.eg(10));
+      const int64_t zq = c == 0 ? cm_unzig(r.eg(12)) : zprev + cm_unzig(r.eg(6));
+      zprev = zq;
+      o.unit[k] = (uint16_t)(ur / NROW);
+      o.row[k] = (uint8_t)(ur % NROW);
+      o.y[k] = (int32_t)(yq << CM_QSHIFT);
+      o.z[k] = (int32_t)(zq << CM_QSHIFT);
+      o.qtot[k] = (uint16_t)r.eg(6);
+      o.qmax[k] = (uint16_t)r.eg(5);
+      o.flags[k] = (uint8_t)r.get(2);
+      o.track[k] = -1;
+    }
+  }
+  return !(bad || r.bad || r.pos != end);
+}
+
+// Records decoded by waves: a wave takes `per_lane` = 1 record per lane (track
+// records) or one record per wave decoded by lane 0 (row blocks, which are
+// long); the records' bits are first copied into the wave's part of LDS when
+// they fit (a dependent chain of global reads is what bounds a sequential
+// decoder), else read from the payload.
+#define CM_STAGE_WORDS 3072
+template <bool TRACKS>
+__global__ __launch_bounds__(256) void k_cm_dec(const uint32_t* __restrict__ s,
+                                                const uint32_t* info,
+                                                const uint32_t* __restrict__ off,
+                                                const unsigned long long* total, int64_t b30,
+                                                const DevParams* __restrict__ P, CmDecOut o,
+                                                DevStatus* st) {
+  __shared__ uint32_t stage[4][CM_STAGE_WORDS];
   if (failed(st) || !info[6]) return;
   const uint32_t nu = info[0], nt = info[1], nc = info[2], nrec = info[5];
-  if (blockIdx.x == 0 && threadIdx.x == 0 && *total != nc) latch(st, TPC_ERR_INPUT);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nrec; i += gridDim.x * blockDim.x) {
-    CmReader r{s + info[4], s[CM_HDR + (i < nt ? i : i + 1)], info[3], false};
-    const uint64_t end = s[CM_HDR + (i < nt ? i + 1 : i + 2)];
-    uint32_t k = off[i];
-    bool bad = false;
-    if (i < nt) {
-      const uint32_t nh = (uint32_t)r.get(8);
-      const uint32_t unit = (uint32_t)r.get(16);
-      const int r0 = (int)r.get(8);
-      CmParams q;
-      q.Y = (int32_t)r.get(32);
-      q.Z = (int32_t)r.get(32);
-      q.S = (int32_t)r.get(32);
-      q.T = (int32_t)r.get(32);
-      q.K = (int32_t)r.get(32);
-      if (unit >= nu || r0 >= NROW) bad = true;
-      CmModel m = cm_model(q, b30, r0);
-      int prev = r0;
-      for (uint32_t h = 0; h < nh && !bad && !r.bad; ++h, ++k) {
-        const uint64_t stp = r.eg(0);
-        const int rr = prev + (int)(stp > NROW ? NROW : stp) + (h > 0 ? 1 : 0);
-        if (rr >= NROW || k >= nc || k >= o.capacity) {
-          bad = true;
-          break;
-        }
-        prev = rr;
-        while (m.row < rr) cm_step(m, P->xfx);
-        const int64_t yq = cm_q(m.Y) + cm_unzig(r.eg(2));
-        const int64_t zq = cm_q(m.Z) + cm_unzig(r.eg(2));
-        o.unit[k] = (uint16_t)unit;
-        o.row[k] = (uint8_t)rr;
-        o.y[k] = (int32_t)(yq << CM_QSHIFT);
-        o.z[k] = (int32_t)(zq << CM_QSHIFT);
-        o.qtot[k] = (uint16_t)r.eg(6);
-        o.qmax[k] = (uint16_t)r.eg(5);
-        o.flags[k] = (uint8_t)r.get(2);
-        o.track[k] = (int32_t)i;
-      }
-    } else {
-      const uint32_t ur = i - nt;
-      const uint64_t n = r.eg(0);
-      int64_t zprev = 0;
-      for (uint64_t c = 0; c < n && !r.bad; ++c, ++k) {
-        if (k >= nc || k >= o.capacity) {
-          bad = true;
-          break;
-        }
-        const int64_t yq = cm_unzig(r.eg(10));
-        const int64_t zq = c == 0 ? cm_unzig(r.eg(12)) : zprev + cm_unzig(r.eg(6));
-        zprev = zq;
-        o.unit[k] = (uint16_t)(ur / NROW);
-        o.row[k] = (uint8_t)(ur % NROW);
-        o.y[k] = (int32_t)(yq << CM_QSHIFT);
-        o.z[k] = (int32_t)(zq << CM_QSHIFT);
-        o.qtot[k] = (uint16_t)r.eg(6);
-        o.qmax[k] = (uint16_t)r.eg(5);
-        o.flags[k] = (uint8_t)r.get(2);
-        o.track[k] = -1;
-      }
+  const uint64_t bits = info[3];
+  const uint32_t* pay = s + info[4];
+  if (!TRACKS && blockIdx.x == 0 && threadIdx.x == 0 && *total != nc) latch(st, TPC_ERR_INPUT);
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t per = TRACKS ? 64 : 1;  // records per wave
+  const uint32_t first = TRACKS ? 0 : nt, last = TRACKS ? nt : nrec;
+  const uint32_t n_groups = (last - first + per - 1) / per;
+  for (uint32_t g = blockIdx.x * 4 + w; g < n_groups; g += gridDim.x * 4) {
+    const uint32_t i0 = first + g * per;
+    const uint32_t i1 = min(i0 + per, last);
+    // the wave's bit range: from the first record's start to the last one's end
+    uint64_t b0 = s[CM_HDR + i0 + (TRACKS ? 0 : 1)];
+    uint64_t b1 = s[CM_HDR + (i1 - 1) + (TRACKS ? 1 : 2)];
+    if (b0 > bits) b0 = bits;
+    if (b1 > bits) b1 = bits;
+    if (b1 < b0) b1 = b0;
+    const uint64_t w0 = b0 >> 5, w1 = (b1 + 31) >> 5;
+    const bool staged = w1 - w0 <= CM_STAGE_WORDS;
+    if (staged) {
+      for (uint64_t k = lane; k < w1 - w0; k += 64) stage[w][k] = pay[w0 + k];
     }
-    if (bad || r.bad || r.pos != end) latch(st, TPC_ERR_INPUT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t i = i0 + lane;
+    if (i < i1 && (TRACKS || lane == 0)) {
+      const uint64_t start = s[CM_HDR + i + (TRACKS ? 0 : 1)];
+      const uint64_t end = s[CM_HDR + i + (TRACKS ? 1 : 2)];
+      // from LDS when the record lies in the staged range (reads stop at its
+      // end), else (a malformed directory) from the payload
+      const bool in_lds = staged && start >= b0 && end <= b1;
+      CmReader r{in_lds ? stage[w] : pay, start, in_lds ? b1 : bits, false, in_lds ? w0 : 0};
+      if (!cm_decode_record(r, i, nu, nt, nc, off[i], end, b30, P->xfx, o))
+        latch(st, TPC_ERR_INPUT);
+    }
+    // the wave's LDS reads are done before the next group overwrites it
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }

@@ -172,12 +172,14 @@ __device__ __forceinline__ bool mg_follows(double C, double tgl, const double* a
     const double r = 1.0 / C;
     const double cx = a[0] - r * a[4], cy = a[1] + r * a[3];
     const double ux = a[0] - cx, uy = a[1] - cy, vx = b[0] - cx, vy = b[1] - cy;
-    perp = fabs(sqrt(vx * vx + vy * vy) - fabs(r));
+    const double vr = sqrt(vx * vx + vy * vy);
+    perp = fabs(vr - fabs(r));
     const double dpsi = atan2(ux * vy - uy * vx, ux * vx + uy * vy);
     arc = dpsi / C;
-    const double turn = C * arc;
-    tx = a[3] * cos(turn) - a[4] * sin(turn);
-    ty = a[3] * sin(turn) + a[4] * cos(turn);
+    // the tangent where b projects onto the circle (radius vector turned a
+    // quarter turn in the sense of the motion)
+    tx = C > 0 ? -vy / vr : vy / vr;
+    ty = C > 0 ? vx / vr : -vx / vr;
   } else {
     perp = fabs(a[3] * dy - a[4] * dx);
     arc = a[3] * dx + a[4] * dy;
@@ -191,53 +193,166 @@ __device__ __forceinline__ bool mg_follows(double C, double tgl, const double* a
   return ok;
 }
 
-// One lane per end of segment A: the ends of later segments in the cells
-// around it; joinable pairs are united, near ties flagged on both segments.
-__global__ __launch_bounds__(256) void k_mg_pairs(MgSegs S, const uint32_t* n_trk_dev,
-                                                  uint32_t trk_cap, uint32_t nzb,
+// The drift z and bending-plane position of every end, in cell order, so
+// that the candidate scans below read consecutive memory.
+__global__ void k_mg_pack(const uint32_t* __restrict__ cell_ends, const uint32_t* total_dev,
+                          const double* __restrict__ e_all, double* __restrict__ pk,
+                          const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t total = *total_dev;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+    const uint32_t e = cell_ends[k];
+    const double* E = e_all + (size_t)(e >> 1) * 10 + 5 * (e & 1);
+    pk[3 * (size_t)k] = E[2];
+    pk[3 * (size_t)k + 1] = E[0];
+    pk[3 * (size_t)k + 2] = E[1];
+  }
+}
+
+// The joining test of end t (cell order) against candidate end k: the
+// remaining gates and cuts, then the union; near ties flag both segments.
+__device__ __forceinline__ void mg_pair_check(const MgSegs& S, const uint32_t* cell_ends,
+                                              const double* pk, uint32_t t, uint32_t k,
+                                              uint32_t* parent, uint8_t* near_tie) {
+  const uint32_t e = cell_ends[t], f = cell_ends[k];
+  const uint32_t A = e >> 1, B = f >> 1;
+  const double* a = S.e + (size_t)A * 10 + 5 * (e & 1);
+  const double* b = S.e + (size_t)B * 10 + 5 * (f & 1);
+  const double ax = pk[3 * (size_t)t + 1], ay = pk[3 * (size_t)t + 2];
+  const double bx = pk[3 * (size_t)k + 1], by = pk[3 * (size_t)k + 2];
+  const double dxy = sqrt((ax - bx) * (ax - bx) + (ay - by) * (ay - by));
+  const double CA = S.C[A], CB = S.C[B], ca = fabs(CA), cb = fabs(CB), cm = ca > cb ? ca : cb;
+  bool tie = false;
+  bool ok = mg_cut(dxy, MG_GAP, tie);
+  if (ok) {
+    ok = mg_cut(fabs(ca - cb), MG_DC_REL * cm + MG_DC_ABS, tie);
+    ok &= mg_follows(CA, S.tgl[A], a, b, tie);
+    ok &= mg_follows(CB, S.tgl[B], b, a, tie);
+  }
+  if (tie) {
+    near_tie[A] = 1;
+    near_tie[B] = 1;
+  }
+  if (ok) mg_union(parent, A, B);
+}
+
+// One lane per end, ends taken in cell order (the lanes of a wave mostly
+// share their cell and so scan the same neighbour cells in step): the ends of
+// later segments in the 5 x 3 cells around it are gated on the packed drift z
+// and position; the pairs that pass go to the wave's queue in LDS, and every
+// 64 of them are tested by the 64 lanes together (the full test is long and
+// few lanes pass a gate at a time).
+#define MG_QCAP 128
+__global__ __launch_bounds__(256) void k_mg_pairs(MgSegs S, uint32_t nzb,
+                                                  const uint32_t* total_dev,
                                                   const uint32_t* __restrict__ cell_off,
                                                   const uint32_t* __restrict__ cell_ends,
                                                   const uint32_t* __restrict__ cell_of_end,
+                                                  const double* __restrict__ pk,
                                                   uint32_t* __restrict__ parent,
                                                   uint8_t* __restrict__ near_tie,
                                                   const DevStatus* st) {
+  __shared__ uint32_t qa[4][MG_QCAP], qb[4][MG_QCAP];
   if (failed(st)) return;
-  const uint32_t n = scan_count(n_trk_dev, trk_cap);
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * n; e += gridDim.x * blockDim.x) {
-    const uint32_t A = e >> 1;
-    const uint32_t cell = cell_of_end[e];
-    if (cell == 0xFFFFFFFFu) continue;
-    const uint32_t zb = cell % nzb, sec = (cell / nzb) % 18, fs = cell / nzb / 18;
-    const double* a = S.e + (size_t)A * 10 + 5 * (e & 1);
-    const double CA = S.C[A], ca = fabs(CA), tga = S.tgl[A];
-    for (int ds = -2; ds <= 2; ++ds) {
-      const uint32_t s2 = (sec + 18 + ds) % 18;
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int64_t z2 = (int64_t)zb + dz;
-        if (z2 < 0 || z2 >= (int64_t)nzb) continue;
-        const uint32_t c2 = (fs * 18 + s2) * nzb + (uint32_t)z2;
-        for (uint32_t k = cell_off[c2]; k < cell_off[c2 + 1]; ++k) {
-          const uint32_t f = cell_ends[k];
-          const uint32_t B = f >> 1;
-          if (B <= A) continue;
-          const double* b = S.e + (size_t)B * 10 + 5 * (f & 1);
-          if (!(fabs(a[2] - b[2]) <= MG_DZMAX)) continue;
-          bool tie = false;
-          const double dxy = sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]));
-          bool ok = mg_cut(dxy, MG_GAP, tie);
-          if (ok) {
-            const double CB = S.C[B], cb = fabs(CB), cm = ca > cb ? ca : cb;
-            ok = mg_cut(fabs(ca - cb), MG_DC_REL * cm + MG_DC_ABS, tie);
-            ok &= mg_follows(CA, tga, a, b, tie);
-            ok &= mg_follows(CB, S.tgl[B], b, a, tie);
+  const uint32_t total = *total_dev;
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (uint32_t t0 = blockIdx.x * blockDim.x + w * 64; t0 < total;
+       t0 += gridDim.x * blockDim.x) {  // uniform per wave
+    const uint32_t t = t0 + lane;
+    const bool have = t < total;
+    uint32_t A = 0, zb = 0, sec = 0, fs = 0;
+    double az = 0, ax = 0, ay = 0;
+    if (have) {
+      const uint32_t e = cell_ends[t];
+      A = e >> 1;
+      const uint32_t cell = cell_of_end[e];
+      zb = cell % nzb;
+      sec = (cell / nzb) % 18;
+      fs = cell / nzb / 18;
+      az = pk[3 * (size_t)t];
+      ax = pk[3 * (size_t)t + 1];
+      ay = pk[3 * (size_t)t + 2];
+    }
+    uint32_t qn = 0;  // queued pairs (the same in every lane)
+    for (int ci = 0; ci < 15; ++ci) {
+      const int ds = ci / 3 - 2, dz = ci % 3 - 1;
+      uint32_t k0 = 0, k1 = 0;
+      const int64_t z2 = (int64_t)zb + dz;
+      if (have && z2 >= 0 && z2 < (int64_t)nzb) {
+        const uint32_t c2 = (fs * 18 + (sec + 18 + ds) % 18) * nzb + (uint32_t)z2;
+        k0 = cell_off[c2];
+        k1 = cell_off[c2 + 1];
+      }
+      const uint32_t len = k1 - k0;
+      const uint32_t maxlen = (uint32_t)wave_max_i32((int32_t)len);
+      for (uint32_t it = 0; it < maxlen; ++it) {
+        bool pass = false;
+        const uint32_t k = k0 + it;
+        if (it < len) {
+          const double bz = pk[3 * (size_t)k];
+          if (fabs(az - bz) <= MG_DZMAX) {
+            const double bx = pk[3 * (size_t)k + 1], by = pk[3 * (size_t)k + 2];
+            const double dxy = sqrt((ax - bx) * (ax - bx) + (ay - by) * (ay - by));
+            // beyond the near-tie band of the gap cut nothing can pass or tie
+            pass = dxy <= MG_GAP * (1 + 2 * MG_TIE) && (cell_ends[k] >> 1) > A;
           }
-          if (tie) {
-            near_tie[A] = 1;
-            near_tie[B] = 1;
+        }
+        const uint64_t m = __ballot(pass);
+        if (m) {  // uniform
+          const uint32_t pos = qn + (uint32_t)__popcll(m & below);
+          if (pass) {
+            qa[w][pos] = t;
+            qb[w][pos] = k;
           }
-          if (ok) mg_union(parent, A, B);
+          qn += (uint32_t)__popcll(m);
+          if (qn >= 64) {  // uniform: the 64 newest pairs, one per lane
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t q = qn - 64 + lane;
+            mg_pair_check(S, cell_ends, pk, qa[w][q], qb[w][q], parent, near_tie);
+            qn -= 64;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+          }
         }
       }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane < qn) mg_pair_check(S, cell_ends, pk, qa[w][lane], qb[w][lane], parent, near_tie);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Global position of every hit of every track (the fit reads it three times):
+// one lane per track walks its hits, which ascend through the rows of one unit.
+__global__ void k_mg_hits(const uint32_t* __restrict__ crow, uint32_t n_ur,
+                          const int32_t* __restrict__ y_fx, const uint32_t* n_cl_dev,
+                          uint32_t cl_cap, const uint32_t* __restrict__ hit_start,
+                          const uint32_t* __restrict__ hits, uint32_t hit_cap,
+                          const uint32_t* n_trk_dev, uint32_t trk_cap,
+                          const double* __restrict__ cs18, double* __restrict__ hxy,
+                          const DevParams* __restrict__ P, const DevStatus* st) {
+  if (failed(st)) return;
+  const uint32_t n = scan_count(n_trk_dev, trk_cap);
+  const uint32_t n_cl = scan_count(n_cl_dev, cl_cap);
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    uint32_t h0 = hit_start[j], h1 = hit_start[j + 1];
+    if (h1 > hit_cap) h1 = hit_cap;
+    if (h0 >= h1) continue;
+    uint32_t ur = mg_ur_of(crow, n_ur, hits[h0] < n_cl ? hits[h0] : 0);
+    for (uint32_t h = h0; h < h1; ++h) {
+      const uint32_t c = hits[h] < n_cl ? hits[h] : 0;
+      // ascending rows: walk forward; anything else falls back to the search
+      while (ur + 1 < n_ur && crow[ur + 1] <= c) ++ur;
+      if (c < crow[ur]) ur = mg_ur_of(crow, n_ur, c);
+      const uint32_t s18 = (ur / NROW) % 36 % 18;
+      const double ca = cs18[2 * s18], sa = cs18[2 * s18 + 1];
+      const double x = P->xd[ur % NROW], y = y_fx[c] / 65536.0;
+      hxy[2 * (size_t)h] = x * ca - y * sa;
+      hxy[2 * (size_t)h + 1] = x * sa + y * ca;
     }
   }
 }
@@ -274,15 +389,11 @@ __global__ void k_mg_labels(const uint32_t* __restrict__ parent, const uint32_t*
 __global__ __launch_bounds__(64) void k_mg_fit(const uint32_t* __restrict__ skey,
                                                const uint32_t* __restrict__ sidx,
                                                const uint32_t* n_trk_dev, uint32_t trk_cap,
-                                               const uint32_t* __restrict__ crow, uint32_t n_ur,
-                                               const int32_t* __restrict__ y_fx,
                                                const int32_t* __restrict__ z_fx,
                                                const uint32_t* __restrict__ hit_start,
                                                const uint32_t* __restrict__ hits,
-                                               uint32_t hit_cap, const double* __restrict__ cs18,
-                                               double* __restrict__ fit,
-                                               const DevParams* __restrict__ P,
-                                               const DevStatus* st) {
+                                               uint32_t hit_cap, const double* __restrict__ hxy,
+                                               double* __restrict__ fit, const DevStatus* st) {
   if (failed(st)) return;
   const uint32_t n = scan_count(n_trk_dev, trk_cap);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -292,14 +403,10 @@ __global__ __launch_bounds__(64) void k_mg_fit(const uint32_t* __restrict__ skey
     while (end < n && skey[end] == root) ++end;
     double* f = fit + (size_t)root * MG_FIT;
     for (int k = 0; k < MG_FIT; ++k) f[k] = 0;
-    // global position of hit h
-    auto hit_xy = [&](uint32_t c, double& X, double& Y) {
-      const uint32_t ur = mg_ur_of(crow, n_ur, c);
-      const uint32_t s18 = (ur / NROW) % 36 % 18;
-      const double ca = cs18[2 * s18], sa = cs18[2 * s18 + 1];
-      const double x = P->xd[ur % NROW], y = y_fx[c] / 65536.0;
-      X = x * ca - y * sa;
-      Y = x * sa + y * ca;
+    // global position of hit h (computed by k_mg_hits)
+    auto hit_xy = [&](uint32_t h, double& X, double& Y) {
+      X = hxy[2 * (size_t)h];
+      Y = hxy[2 * (size_t)h + 1];
     };
     auto hit_range = [&](uint32_t j, uint32_t& h0, uint32_t& h1) {
       h0 = hit_start[j];
@@ -314,7 +421,7 @@ __global__ __launch_bounds__(64) void k_mg_fit(const uint32_t* __restrict__ skey
       hit_range(sidx[m], h0, h1);
       for (uint32_t h = h0; h < h1; ++h) {
         double X, Y;
-        hit_xy(hits[h], X, Y);
+        hit_xy(h, X, Y);
         sx += X;
         sy += Y;
         ++nh;
@@ -329,7 +436,7 @@ __global__ __launch_bounds__(64) void k_mg_fit(const uint32_t* __restrict__ skey
       hit_range(sidx[m], h0, h1);
       for (uint32_t h = h0; h < h1; ++h) {
         double X, Y;
-        hit_xy(hits[h], X, Y);
+        hit_xy(h, X, Y);
         const double u = X - mx, v = Y - my;
         suu += u * u;
         svv += v * v;
@@ -356,7 +463,7 @@ __global__ __launch_bounds__(64) void k_mg_fit(const uint32_t* __restrict__ skey
       hit_range(sidx[m], h0, h1);
       for (uint32_t h = h0; h < h1; ++h) {
         double X, Y;
-        hit_xy(hits[h], X, Y);
+        hit_xy(h, X, Y);
         const double psi = atan2(Y - yc, X - xc);
         acc = k == 0 ? 0.0 : acc + mg_wrap(psi - psi_prev);
         psi_prev = psi;

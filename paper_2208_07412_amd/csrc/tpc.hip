@@ -98,6 +98,7 @@ struct tpc_ctx {
            *mg_idx = nullptr, *mg_skey = nullptr, *mg_sidx = nullptr;
   uint8_t* mg_sector = nullptr;
   double *mg_C = nullptr, *mg_tgl = nullptr, *mg_e = nullptr, *mg_cs18 = nullptr;
+  double *mg_pk = nullptr, *mg_hxy = nullptr;  // ends' gate data in cell order; hit positions
   size_t bsum_cap = 0;
   tpc_tuning tune;
   // stage timing (measurement only)
@@ -126,7 +127,7 @@ struct Plan {
   size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, cm_a, cm_b, cm_tot, cm_info, mg_fs,
       mg_cell, mg_cnt, mg_off, mg_cur, mg_ends, mg_parent, mg_key, mg_idx, mg_skey, mg_sidx,
-      mg_sector, mg_C, mg_tgl, mg_e, mg_cs18, hit_off, par, st, total;
+      mg_sector, mg_C, mg_tgl, mg_e, mg_cs18, mg_pk, mg_hxy, hit_off, par, st, total;
   size_t bsum_cap;
   uint32_t nblk, nblk_s, nwin;
 };
@@ -219,6 +220,8 @@ Plan plan_for(const tpc_sizes& m) {
   p.mg_tgl = L.add<double>(mt);
   p.mg_e = L.add<double>(10 * mt);
   p.mg_cs18 = L.add<double>(36);
+  p.mg_pk = L.add<double>(6 * mt);
+  p.mg_hxy = L.add<double>(2 * mc);
   p.par = L.add<DevParams>(1);
   p.st = L.add<DevStatus>(1);
   p.total = (L.off + 255) & ~(size_t)255;
@@ -790,6 +793,8 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->mg_tgl = (double*)(base + pl.mg_tgl);
   c->mg_e = (double*)(base + pl.mg_e);
   c->mg_cs18 = (double*)(base + pl.mg_cs18);
+  c->mg_pk = (double*)(base + pl.mg_pk);
+  c->mg_hxy = (double*)(base + pl.mg_hxy);
   c->d_par = (DevParams*)(base + pl.par);
   c->d_st = (DevStatus*)(base + pl.st);
   c->bsum_cap = pl.bsum_cap;
@@ -909,7 +914,9 @@ int tpc_decompress(tpc_ctx* c, const uint32_t* stream, uint32_t stream_words,
                                c->cm_tot, (uint32_t*)nullptr);
   const CmDecOut o{out->capacity, out->unit, out->row, out->y_fx, out->z_fx,
                    out->qtot, out->qmax, out->flags, out->track};
-  k_cm_dec_records<<<grid_for(max_rec, 256, 4096), 256, 0, s>>>(
+  k_cm_dec<true><<<grid_for(c->max.max_tracklets, 256, 4096), 256, 0, s>>>(
+      stream, c->cm_info, c->cm_b, c->cm_tot, cm_b30(c), c->d_par, o, c->d_st);
+  k_cm_dec<false><<<grid_for((uint64_t)c->max.max_units * NROW, 4, 4096), 256, 0, s>>>(
       stream, c->cm_info, c->cm_b, c->cm_tot, cm_b30(c), c->d_par, o, c->d_st);
   return launch_ok();
 }
@@ -932,6 +939,10 @@ int tpc_merge_tracks(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, t
   hipStream_t s = c->stream;
   StageTimer tm(c, 15);
   const uint32_t cap = tr->capacity, n_ur = cl->n_units * NROW;
+  // hit positions are kept for at most max_clusters hits (a track set holds
+  // each cluster at most once)
+  const uint32_t hit_bound =
+      tr->hit_capacity < c->max.max_clusters ? tr->hit_capacity : c->max.max_clusters;
   const uint32_t nzb = mg_nzb(cl->n_time_bins);
   const uint32_t n_cells = ((cl->n_units + 35) / 36) * 2 * 18 * nzb;
   const MgSegs S{c->mg_fs, c->mg_sector, c->mg_C, c->mg_tgl, c->mg_e};
@@ -949,9 +960,14 @@ int tpc_merge_tracks(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, t
   k_mg_total<<<1, 1, 0, s>>>(c->mg_off, c->tot32, n_cells, c->d_st);
   k_mg_fill_cells<<<grid_for(2 * (uint64_t)cap, 256, 4096), 256, 0, s>>>(
       c->mg_cell, tr->n_tracks, cap, c->mg_cur, c->mg_ends, c->d_st);
+  k_mg_pack<<<grid_for(2 * (uint64_t)cap, 256, 4096), 256, 0, s>>>(c->mg_ends, c->tot32, c->mg_e,
+                                                                   c->mg_pk, c->d_st);
   k_mg_pairs<<<grid_for(2 * (uint64_t)cap, 256, 8192), 256, 0, s>>>(
-      S, tr->n_tracks, cap, nzb, c->mg_off, c->mg_ends, c->mg_cell, c->mg_parent, out->near_tie,
+      S, nzb, c->tot32, c->mg_off, c->mg_ends, c->mg_cell, c->mg_pk, c->mg_parent, out->near_tie,
       c->d_st);
+  k_mg_hits<<<grid_for(cap, 256, 4096), 256, 0, s>>>(
+      cl->crow_start, n_ur, cl->y_fx, cl->n_clusters, cl->capacity, tr->hit_start, tr->hits,
+      hit_bound, tr->n_tracks, cap, c->mg_cs18, c->mg_hxy, c->d_par, c->d_st);
   k_mg_labels<<<grid_for(cap, 256, 4096), 256, 0, s>>>(c->mg_parent, tr->n_tracks, cap, out->label,
                                                        c->mg_key, c->d_st);
   // members grouped by component in ascending index: labels are below 2^24
@@ -975,9 +991,8 @@ int tpc_merge_tracks(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, t
     // three passes: the result is in (mg_skey, mg_sidx)
   }
   k_mg_fit<<<grid_for(cap, 64, 16384), 64, 0, s>>>(c->mg_skey, c->mg_sidx, tr->n_tracks, cap,
-                                                   cl->crow_start, n_ur, cl->y_fx, cl->z_fx,
-                                                   tr->hit_start, tr->hits, tr->hit_capacity,
-                                                   c->mg_cs18, out->fit, c->d_par, c->d_st);
+                                                   cl->z_fx, tr->hit_start, tr->hits, hit_bound,
+                                                   c->mg_hxy, out->fit, c->d_st);
   run_count<uint32_t>(c, MgIsRoot{out->label}, tr->n_tracks, cap, out->n_merged);
   return launch_ok();
 }
