@@ -685,7 +685,9 @@ def main():
                                            "void k_follow<"),
                        flops_per_launch=flops, ms_per_launch=stages["following"],
                        steps=fcounts["follow_steps"], candidates=fcounts["follow_candidates"],
-                       updates=fcounts["follow_updates"])
+                       updates=fcounts["follow_updates"],
+                       lane_slots=fcounts["follow_lane_slots"],
+                       lane_use=fcounts["follow_steps"] / max(fcounts["follow_lane_slots"], 1))
     if stages["cluster_peaks"] >= stages["following"]:
         roofline, roofline_2 = roof_peaks, roof_follow
     else:

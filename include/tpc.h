@@ -209,8 +209,11 @@ typedef struct {
                                  (TPC_OVF_*) was too small */
   uint32_t required_by[4];    /* the count capacity k needed (0 if it fit) */
   /* work of the last following stage (measurement): helix steps with
-     covariance transport, candidate chi2 evaluations, Kalman updates */
-  uint64_t follow_steps, follow_candidates, follow_updates;
+     covariance transport, candidate chi2 evaluations, Kalman updates; and
+     the lane slots its waves held: 64 x the most steps of any lane, summed
+     over the waves (follow_steps / follow_lane_slots is the share of lanes
+     that did a step while their wave ran) */
+  uint64_t follow_steps, follow_candidates, follow_updates, follow_lane_slots;
 } tpc_counts;
 
 /* Capacities named by tpc_counts.overflow / required_by: clusters
@@ -500,8 +503,10 @@ const char* tpc_status_string(int status);
  * of the following kernel, 64, 128 or 256; follow_mode: 0 one launch per
  * pass (outward, then inward), each over the tracklets sorted by the most
  * rows the pass can take, longest first; 1 one launch that runs both passes
- * of a tracklet per lane, in tracklet order.  One tracklet per lane in both
- * modes.  refit_waves: most waves of the FP32 refit resident per compute
+ * of a tracklet per lane, in tracklet order; 2 as 0, but a lane whose
+ * tracklet has ended takes the next one in the sorted order (lane refill,
+ * in batches of 32 free lanes per wave, on a grid of the resident waves).
+ * One tracklet per lane at a time in every mode.  refit_waves: most waves of the FP32 refit resident per compute
  * unit, 0 (no limit), 4, 5, 6 or 8; the refit lasts as long as its longest
  * tracks' serial chains, which run faster with fewer waves sharing a SIMD
  * (the limit is a reservation of LDS per workgroup).  tpc_set_tuning rejects

@@ -14,7 +14,7 @@ from typing import Dict, List, Tuple
 
 CLUSTER_SHAPES: List[Tuple[int, int]] = [(8, 4), (8, 8), (8, 16), (16, 4), (16, 8), (16, 16), (20, 8), (24, 8),
                                          (32, 4), (32, 8), (32, 16)]
-FOLLOW_SHAPES: List[Tuple[int, int]] = [(fb, fm) for fm in (0, 1) for fb in (64, 128, 256)]
+FOLLOW_SHAPES: List[Tuple[int, int]] = [(fb, fm) for fm in (0, 1, 2) for fb in (64, 128, 256)]
 CLUSTER_STAGES = ("sample_index", "cluster_peaks", "cluster_scan", "cluster_output")
 FOLLOW_STAGES = ("following",)
 REFIT_WAVES: List[int] = [0, 4, 5, 6, 8]

@@ -51,7 +51,7 @@ struct DevStatus {
   uint32_t n_fp64_redo;
   uint32_t overflow;  // bit k set: capacity k (OVF_*) was too small
   uint32_t req[4];    // count that capacity k needed
-  unsigned long long f_steps, f_cands, f_upds;  // following work (measurement)
+  unsigned long long f_steps, f_cands, f_upds, f_slots;  // following work (measurement)
 };
 
 __device__ __forceinline__ void latch(DevStatus* st, int code, uint32_t required = 0) {

@@ -37,7 +37,9 @@ __global__ void k_pack_pos(const int32_t* __restrict__ y, const int32_t* __restr
 
 // The cluster grid (block index over peak times) has one entry per
 // 2^CG_BSHIFT time bins.
+#ifndef CG_BSHIFT
 #define CG_BSHIFT 1
+#endif
 
 // Candidate cluster range of row ur for a drift position z (fixed point):
 // |z_c - z| <= win_z and the centroid lies within 2 bins of the peak time.

@@ -327,11 +327,15 @@ struct FollowOut {
   uint8_t* krow;      // [cap*152]: rows of the kept hits, ascending (after resolution)
 };
 
-// best candidate of row r: smallest (chi2, id) with chi2 <= chi2_max
+#define SEARCH_UNROLL 2
+// Best candidate of row ur for the track state k: the cluster with the least
+// chi2 within the cut, the lower index on ties (-1 if none).  Only the grid
+// blocks within the z residual bound that chi2 alone sets (plus a margin) are
+// scanned; bq receives the chosen cluster's position.
 __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint32_t* cblk,
                                               uint32_t nblk, uint32_t ur, const Trk<float>& k,
                                               int32_t anchor, float vy, float vz, float chi2max,
-                                              uint32_t& n_cand) {
+                                              uint32_t& n_cand, int2& bq) {
   const float w = sqrtf(chi2max * (k.c[5] + vz));
   const float zabs = k.p[1] + (float)anchor * (float)FX_SCALE;
   const float flo = floorf(2.0f * (zabs - w)) - 3.0f, fhi = ceilf(2.0f * (zabs + w)) + 3.0f;
@@ -348,14 +352,23 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
   float bchi = 0.0f;
   const SInv<float> si = s_inverse(k, vy, vz);
   n_cand += b - a;
-  for (uint32_t c = a; c < b; ++c) {
-    const int2 q = cl.pos[c];
-    const float my = (float)q.x * (float)FX_SCALE;
-    const float mz = (float)(q.y - anchor) * (float)FX_SCALE;
-    const float x2 = chi2_of(k, my, mz, si);
-    if (x2 <= chi2max && (best < 0 || x2 < bchi)) {
-      best = (int32_t)c;
-      bchi = x2;
+  // candidates in index order, their positions loaded SEARCH_UNROLL at a
+  // time so that the loads of one group are in flight together
+  for (uint32_t c0 = a; c0 < b; c0 += SEARCH_UNROLL) {
+    int2 q[SEARCH_UNROLL];
+#pragma unroll
+    for (int j = 0; j < SEARCH_UNROLL; ++j) q[j] = c0 + j < b ? cl.pos[c0 + j] : make_int2(0, 0);
+#pragma unroll
+    for (int j = 0; j < SEARCH_UNROLL; ++j) {
+      if (c0 + j >= b) break;
+      const float my = (float)q[j].x * (float)FX_SCALE;
+      const float mz = (float)(q[j].y - anchor) * (float)FX_SCALE;
+      const float x2 = chi2_of(k, my, mz, si);
+      if (x2 <= chi2max && (best < 0 || x2 < bchi)) {
+        best = (int32_t)(c0 + j);
+        bchi = x2;
+        bq = q[j];
+      }
     }
   }
   return best;
@@ -520,7 +533,8 @@ struct FollowLane {
   Trk<float> k;   // state at row r
   float sp[5];    // state after the last update (pass A, then pass B)
   uint32_t t;
-  int32_t anchor, ctl;
+  int32_t anchor;
+  int32_t pre;    // candidate of the next row known before its helix step, or -1
   uint32_t ubase;
   int r, r1, L, nmiss, nh, hi, lo, rs;  // rs: row of sp
   uint32_t n_steps, n_cands, n_upds;      // work done (measurement)
@@ -529,7 +543,7 @@ struct FollowLane {
 // Seed and first update of tracklet t; false if it cannot be followed.
 __device__ __forceinline__ bool follow_init(FollowLane& f, uint32_t t, const ClusterView& cl,
                                             const uint32_t* tl_start, const uint16_t* tl_len,
-                                            const uint32_t* pts, FollowOut& fo,
+                                            const int32_t* upc, const uint32_t* pts, FollowOut& fo,
                                             const DevParams* P, const PV<float>& pv) {
   fo.ok[t] = 0;
   fo.nhits[t] = 0;
@@ -583,7 +597,7 @@ __device__ __forceinline__ bool follow_init(FollowLane& f, uint32_t t, const Clu
   f.rs = r1;
   f.nmiss = 0;
   f.hi = r1;
-  f.ctl = (int32_t)A;
+  f.pre = L > 1 ? upc[A] : -1;  // the next row is on the tracklet's own chain
   f.r = r1;
   return true;
 }
@@ -607,6 +621,7 @@ __device__ __forceinline__ bool follow_start_b(FollowLane& f, const ClusterView&
   for (int i = 0; i < 5; ++i) f.sp[i] = k.p[i];
   f.nmiss = 0;
   f.r = f.rs;
+  f.pre = f.rs - 1 >= f.r1 ? fo.hits[(size_t)f.t * NROW + f.rs - 1] : -1;
   return true;
 }
 
@@ -631,24 +646,30 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
   constexpr bool pa = PA == 1;
   const int rn = f.r + (pa ? 1 : -1);
   if (rn >= NROW || rn < 0) return true;
+  int32_t* H = fo.hits + (size_t)f.t * NROW;
+  // Rows whose candidate is known before the helix step: the tracklet's own
+  // chain (pass A) and the rows pass A covered (pass B: its hit, or -1 for a
+  // row it missed, which is searched).  The candidate's position and the
+  // next row's known candidate are loaded before the step, so their latency
+  // overlaps its arithmetic.
+  const bool known = pa ? rn < f.r1 + f.L : rn >= f.r1;
+  int32_t cand = known ? f.pre : -1;
+  int2 q = make_int2(0, 0);
+  if (cand >= 0) q = cl.pos[cand];
+  const int rn2 = rn + (pa ? 1 : -1);
+  int32_t pre2 = -1;
+  if (pa ? (rn2 < f.r1 + f.L && cand >= 0) : (rn2 >= f.r1 && rn2 >= 0)) pre2 = pa ? upc[cand] : H[rn2];
   Trk<float>& k = f.k;
   if (!propagate(k, row_dx<float>(P, f.r, rn), pv, true, pv.snp_max())) return true;
   ++f.n_steps;
-  int32_t* H = fo.hits + (size_t)f.t * NROW;
-  int32_t cand = -1;
   bool fresh = false;
-  if (pa && rn < f.r1 + f.L) {
-    f.ctl = upc[f.ctl];
-    cand = f.ctl;
-  } else {
-    if (!pa && rn >= f.r1) cand = H[rn];
-    if (cand < 0) {
-      if (fabsf(k.p[0]) > pv.hw(rn) + pv.edge_margin()) return true;
-      cand = search_row(cl, cblk, nblk, f.ubase + rn, k, f.anchor, pv.vy(rn), pv.vz(rn), chi2max,
-                        f.n_cands);
-      fresh = true;
-    }
+  if (!known || (!pa && cand < 0)) {
+    if (fabsf(k.p[0]) > pv.hw(rn) + pv.edge_margin()) return true;
+    cand = search_row(cl, cblk, nblk, f.ubase + rn, k, f.anchor, pv.vy(rn), pv.vz(rn), chi2max,
+                      f.n_cands, q);
+    fresh = true;
   }
+  f.pre = pre2;
   f.r = rn;
   // a row this pass visits first gets exactly one store: its hit, or -1
   const bool first = pa || (fresh && rn < f.lo);
@@ -659,7 +680,6 @@ __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl
     if ((pa || rn < f.r1) && ++f.nmiss >= P->max_miss) return true;
     return false;
   }
-  const int2 q = cl.pos[cand];
   const float my = (float)q.x * (float)FX_SCALE;
   const float mz = (float)(q.y - f.anchor) * (float)FX_SCALE;
   ++f.n_upds;
@@ -699,7 +719,7 @@ __device__ __forceinline__ void follow_resume(FollowLane& f, uint32_t t, const C
   f.rs = (int)s4r.y;
   f.nh = fo.nhits[t];
   f.hi = fo.range[t] >> 8;
-  f.ctl = -1;
+  f.pre = -1;
 }
 
 enum { FP_A = 0, FP_B = 1, FP_AB = 2 };
@@ -744,7 +764,7 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
     if (PASS == FP_B) {
       if (!fo.ok[t]) continue;
       follow_resume(f, t, cl, tl_start, tl_len, pts, fo);
-    } else if (!follow_init(f, t, cl, tl_start, tl_len, pts, fo, P, pv)) {
+    } else if (!follow_init(f, t, cl, tl_start, tl_len, upc, pts, fo, P, pv)) {
       if (PASS == FP_A) key[t] = 0;
       if (COUNT) w_upds += f.n_upds;
       continue;
@@ -775,39 +795,145 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
   // from every wave on one address would serialise at the end of the kernel)
   const unsigned long long s0 = wave_sum_u64(w_steps), s1 = wave_sum_u64(w_cands),
                            s2 = wave_sum_u64(w_upds);
-  if ((threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(s0, s1, s2, 0);
+  // lane slots: the wave runs as long as its busiest lane (exact when each
+  // lane takes at most one tracklet, as with a grid that covers the capacity)
+  const uint32_t mx = (uint32_t)wave_max_i32((int32_t)w_steps);
+  if ((threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(s0, s1, s2, 64ull * mx);
+}
+
+// Following with lane refill, one pass (FP_A or FP_B) over the tracklets in
+// sorted order.  A lane holds one tracklet; when at least FOLLOW_REFILL lanes
+// of a wave are free (or none is busy), the wave takes that many next
+// tracklets of its workgroup's sort group with one atomic on the group's
+// counter (refill = FOLLOW_REFILL), so the wave no longer runs as long as its longest tracklet with
+// the other lanes idle.  Every tracklet is followed by exactly one lane, with
+// the same arithmetic as k_follow, so the results do not depend on which lane
+// or wave takes it.  The grid is sized to the resident waves (more would find
+// the queues empty); qnext holds ngrp zeroed counters.
+#define FOLLOW_REFILL 32
+template <int B, int PASS, bool COUNT>
+__global__ __launch_bounds__(B) void k_follow_q(ClusterView cl, const uint32_t* __restrict__ cblk,
+                                                 uint32_t nblk, const int32_t* __restrict__ upc,
+                                                 const uint32_t* __restrict__ tl_start,
+                                                 const uint16_t* __restrict__ tl_len,
+                                                 const uint32_t* __restrict__ pts,
+                                                 const uint32_t* __restrict__ perm,
+                                                 const uint32_t* __restrict__ bins, uint32_t ngrp,
+                                                 uint32_t* __restrict__ qnext,
+                                                 uint32_t refill,
+                                                 uint8_t* __restrict__ key,
+                                                 const uint32_t* n_tl_dev, uint32_t tl_cap,
+                                                 FollowOut fo, ulonglong4* __restrict__ work,
+                                                 const DevParams* __restrict__ Pg, DevStatus* st) {
+  static_assert(PASS == FP_A || PASS == FP_B, "one pass per launch");
+  const uint32_t wave = blockIdx.x * (B / 64) + (threadIdx.x >> 6);
+  if (failed(st)) {
+    if (COUNT && (threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(0, 0, 0, 0);
+    return;
+  }
+  __shared__ DevParams Ps;
+  const DevParams* P = params_to_lds(Pg, &Ps);
+  const PV<float> pv{P};
+  const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
+  const float chi2max = pv.chi2_max();
+  // this workgroup's sort group: positions [gs, ge) of perm
+  const uint32_t g = blockIdx.x % ngrp;
+  const uint32_t npg = sort_blocks_per_group(n_tl, ngrp);
+  const size_t gsz = (size_t)256 * npg;
+  const uint32_t gs = npg ? bins[g * gsz] : 0u;
+  const uint32_t ge = npg == 0 ? 0u : g + 1 < ngrp ? bins[(g + 1) * gsz] : n_tl;
+  const uint64_t below = (1ull << (threadIdx.x & 63)) - 1ull;
+  uint32_t w_steps = 0, w_cands = 0, w_upds = 0, w_iter = 0;
+  FollowLane f;
+  bool busy = false, retired = false;
+  for (;;) {
+    const uint64_t want = __ballot(!busy && !retired);
+    const uint32_t nwant = (uint32_t)__popcll(want);
+    const bool any_busy = __ballot(busy) != 0ull;
+    if (!any_busy && nwant == 0) break;
+    if (nwant >= refill || (!any_busy && nwant > 0)) {
+      const int lead = __ffsll((long long)want) - 1;
+      uint32_t base = 0;
+      if ((int)(threadIdx.x & 63) == lead) base = atomicAdd(&qnext[g], nwant);
+      base = (uint32_t)__shfl((int)base, lead, 64);
+      if (!busy && !retired) {
+        const uint32_t i = gs + base + (uint32_t)__popcll(want & below);
+        if (i >= ge) {
+          retired = true;
+        } else {
+          const uint32_t t = perm[i];
+          f.n_steps = f.n_cands = f.n_upds = 0;
+          if (PASS == FP_B) {
+            if (fo.ok[t]) {
+              follow_resume(f, t, cl, tl_start, tl_len, pts, fo);
+              busy = follow_start_b(f, cl, fo, pv);
+            }
+          } else {
+            busy = follow_init(f, t, cl, tl_start, tl_len, upc, pts, fo, P, pv);
+            if (!busy) key[t] = 0;
+          }
+          if (COUNT && !busy) w_upds += f.n_upds;
+        }
+      }
+    }
+    if (COUNT) ++w_iter;
+    if (busy && follow_step<PASS == FP_A ? 1 : 0>(f, cl, cblk, nblk, upc, fo, P, pv, chi2max)) {
+      busy = false;
+      if (PASS == FP_A) {
+        f.lo = f.r1;
+        follow_finish(f, fo);
+        key[f.t] = (uint8_t)f.rs;
+      } else {
+        follow_finish(f, fo);
+      }
+      if (COUNT) {
+        w_steps += f.n_steps;
+        w_cands += f.n_cands;
+        w_upds += f.n_upds;
+      }
+    }
+  }
+  if (!COUNT) return;
+  const unsigned long long s0 = wave_sum_u64(w_steps), s1 = wave_sum_u64(w_cands),
+                           s2 = wave_sum_u64(w_upds);
+  // lane slots: 64 per loop round of the wave
+  if ((threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(s0, s1, s2, 64ull * w_iter);
 }
 
 // Sum of the following's per-wave work counters into the status block.
 __global__ __launch_bounds__(1024) void k_work_sum(const ulonglong4* __restrict__ work,
                                                    uint32_t n, DevStatus* st) {
-  __shared__ unsigned long long part[3][16];
-  unsigned long long a = 0, b = 0, c = 0;
+  __shared__ unsigned long long part[4][16];
+  unsigned long long a = 0, b = 0, c = 0, e = 0;
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
     const ulonglong4 v = work[i];
     a += v.x;
     b += v.y;
     c += v.z;
+    e += v.w;
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     a += __shfl_xor(a, d, 64);
     b += __shfl_xor(b, d, 64);
     c += __shfl_xor(c, d, 64);
+    e += __shfl_xor(e, d, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     part[0][threadIdx.x >> 6] = a;
     part[1][threadIdx.x >> 6] = b;
     part[2][threadIdx.x >> 6] = c;
+    part[3][threadIdx.x >> 6] = e;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long s[3] = {0, 0, 0};
-    for (int k = 0; k < 3; ++k)
+    unsigned long long s[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k)
       for (uint32_t w = 0; w < blockDim.x / 64; ++w) s[k] += part[k][w];
     st->f_steps = s[0];
     st->f_cands = s[1];
     st->f_upds = s[2];
+    st->f_slots = s[3];
   }
 }
 

@@ -80,6 +80,8 @@ struct tpc_ctx {
   uint32_t* f_bins = nullptr;  // counts, then first positions, per (work estimate, block)
   uint8_t* f_krow = nullptr;
   ulonglong4* f_work = nullptr;  // per-wave work counters of the following
+  uint32_t* f_qnext = nullptr;   // per-group queue counters of the following's refill mode
+  int n_cu = 0;                  // compute units of the device
   int2* pos = nullptr;           // packed cluster positions
   uint32_t* owner = nullptr;
   uint16_t* nkept = nullptr;
@@ -124,7 +126,7 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, pos,
+  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, f_qnext, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, cm_a, cm_b, cm_tot, cm_info, mg_fs,
       mg_cell, mg_cnt, mg_off, mg_cur, mg_ends, mg_parent, mg_key, mg_idx, mg_skey, mg_sidx,
       mg_sector, mg_C, mg_tgl, mg_e, mg_cs18, mg_pk, mg_hxy, hit_off, par, st, total;
@@ -188,6 +190,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.f_bins = L.add<uint32_t>(256 * (ceil_div(mt, SORT_BLOCK) + XCD_GROUPS - 1));
   p.f_krow = L.add<uint8_t>(mt * NROW);
   p.f_work = L.add<ulonglong4>(2 * (mt / 64 + 4 * XCD_GROUPS + 8));  // two passes
+  p.f_qnext = L.add<uint32_t>(2 * XCD_GROUPS);  // queue counters of the refill mode
   p.pos = L.add<int2>(mc);
   p.owner = L.add<uint32_t>(mc);
   p.nkept = L.add<uint16_t>(mt);
@@ -572,10 +575,45 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
     const uint32_t ng = XCD_GROUPS;
     const uint32_t gf = ceil_div(grid_for(tcap, fb), ng) * ng;
     const uint32_t nwf = gf * (uint32_t)(fb / 64);  // waves per following launch
-    const bool split = c->tune.follow_mode == 0;
+    const bool split = c->tune.follow_mode != 1;
     auto launch = [&](auto Bc, auto Cc) {
       constexpr int Bv = decltype(Bc)::value;
       constexpr bool Cv = decltype(Cc)::value;
+      if (c->tune.follow_mode == 2) {
+        // lane refill: a grid of the resident workgroups (a multiple of ng),
+        // each pass over the tracklets sorted by the most rows it can take
+        k_fill<uint32_t><<<1, 64, 0, s>>>(c->f_qnext, 0u, 2 * ng);
+        // waves beyond the resident grid leave their work counters untouched
+        if (Cv)
+          k_fill<unsigned long long><<<grid_for(8 * nwf, 256), 256, 0, s>>>(
+              reinterpret_cast<unsigned long long*>(c->f_work), 0ull, 8 * nwf);
+        // resident workgroups per compute unit of each pass kernel, queried
+        // once per process (a property of the kernel, not of the call)
+        auto occupancy = [](const void* fn) {
+          int per_cu = 0;
+          if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, Bv, 0) != hipSuccess ||
+              per_cu < 1)
+            per_cu = 1;
+          return per_cu;
+        };
+        static const int occ_a = occupancy((const void*)k_follow_q<Bv, FP_A, Cv>);
+        static const int occ_b = occupancy((const void*)k_follow_q<Bv, FP_B, Cv>);
+        auto grid_q = [&](int per_cu) {
+          const uint32_t gq = ceil_div((uint32_t)(per_cu * c->n_cu), ng) * ng;
+          return gq < gf ? gq : gf;
+        };
+        const uint32_t refill = FOLLOW_REFILL;
+        sort_by_key(ng);
+        k_follow_q<Bv, FP_A, Cv><<<grid_q(occ_a), Bv, 0, s>>>(
+            cv, c->cblk, nblk, l->upc, t->start, t->len, c->f_pts, c->f_perm, c->f_bins, ng,
+            c->f_qnext, refill, c->f_key, t->n_tracklets, tcap, fo, c->f_work, c->d_par, c->d_st);
+        sort_by_key(ng);
+        k_follow_q<Bv, FP_B, Cv><<<grid_q(occ_b), Bv, 0, s>>>(
+            cv, c->cblk, nblk, l->upc, t->start, t->len, c->f_pts, c->f_perm, c->f_bins, ng,
+            c->f_qnext + ng, refill, c->f_key, t->n_tracklets, tcap, fo, c->f_work + nwf, c->d_par,
+            c->d_st);
+        return;
+      }
       if (split) {
         // pass A, then pass B, each over the tracklets sorted by the most rows
         // the pass can take (the key k_tracklet_points, then pass A, leaves)
@@ -730,7 +768,9 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->stream = (hipStream_t)hip_stream;
   c->par = *p;
   c->max = *max;
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+          hipSuccess) {
     delete c;
     return TPC_ERR_HIP;
   }
@@ -761,6 +801,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->f_bins = (uint32_t*)(base + pl.f_bins);
   c->f_krow = (uint8_t*)(base + pl.f_krow);
   c->f_work = (ulonglong4*)(base + pl.f_work);
+  c->f_qnext = (uint32_t*)(base + pl.f_qnext);
   c->pos = (int2*)(base + pl.pos);
   c->owner = (uint32_t*)(base + pl.owner);
   c->nkept = (uint16_t*)(base + pl.nkept);
@@ -1139,6 +1180,7 @@ int tpc_sync(tpc_ctx* c, tpc_counts* counts) {
     counts->follow_steps = ds.f_steps;
     counts->follow_candidates = ds.f_cands;
     counts->follow_updates = ds.f_upds;
+    counts->follow_lane_slots = ds.f_slots;
   }
   DevStatus zero;
   std::memset(&zero, 0, sizeof zero);
@@ -1194,8 +1236,8 @@ int tpc_tuning_default(tpc_tuning* t) {
   if (!t) return TPC_ERR_ARG;
   t->cl_window = 24;
   t->cl_chunk = 8;
-  t->follow_block = 128;
-  t->follow_mode = 0;
+  t->follow_block = 64;
+  t->follow_mode = 2;
   t->refit_waves = 6;
   return TPC_OK;
 }
@@ -1208,7 +1250,7 @@ int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if ((t->cl_window == 20 || t->cl_window == 24) && t->cl_chunk != 8) return TPC_ERR_ARG;
   if (t->cl_chunk != 4 && t->cl_chunk != 8 && t->cl_chunk != 16) return TPC_ERR_ARG;
   if (t->follow_block != 64 && t->follow_block != 128 && t->follow_block != 256) return TPC_ERR_ARG;
-  if (t->follow_mode != 0 && t->follow_mode != 1) return TPC_ERR_ARG;
+  if (t->follow_mode < 0 || t->follow_mode > 2) return TPC_ERR_ARG;
   if (t->refit_waves != 0 && t->refit_waves != 4 && t->refit_waves != 5 && t->refit_waves != 6 &&
       t->refit_waves != 8)
     return TPC_ERR_ARG;

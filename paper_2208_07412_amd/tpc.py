@@ -98,7 +98,8 @@ class TpcCounts(ctypes.Structure):
                 ("n_tracklets", U32), ("n_tracks", U32), ("n_hits", U32), ("n_fallback", U32),
                 ("n_fallback_fail", U32), ("n_not_pd", U32), ("n_refit_fail", U32),
                 ("overflow", U32), ("required_by", U32 * 4), ("follow_steps", ctypes.c_uint64),
-                ("follow_candidates", ctypes.c_uint64), ("follow_updates", ctypes.c_uint64)]
+                ("follow_candidates", ctypes.c_uint64), ("follow_updates", ctypes.c_uint64),
+                ("follow_lane_slots", ctypes.c_uint64)]
 
 
 class TpcTuning(ctypes.Structure):

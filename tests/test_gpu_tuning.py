@@ -20,9 +20,9 @@ from _parity import compare_clusters, compare_fit, run_gpu, run_oracle
 pytestmark = pytest.mark.gpu
 
 NPADS, _, _ = oracle.geometry()
-SHAPES = [(8, 8, 64, 0, 0), (8, 16, 128, 1, 4), (16, 4, 64, 0, 5), (16, 8, 128, 1, 6),
+SHAPES = [(8, 8, 64, 0, 0), (8, 16, 128, 1, 4), (16, 4, 64, 2, 5), (16, 8, 128, 1, 6),
           (16, 16, 256, 0, 8), (20, 8, 128, 0, 6), (24, 8, 256, 1, 5), (32, 4, 256, 1, 0),
-          (32, 8, 64, 1, 5), (32, 16, 128, 0, 4)]
+          (32, 8, 64, 1, 5), (32, 16, 128, 0, 4), (24, 8, 128, 2, 0), (8, 4, 256, 2, 6)]
 
 
 @pytest.fixture(scope="module")
@@ -84,7 +84,8 @@ def test_fully_occupied_rows(w, k):
     compare_clusters(g["clusters"], o["clusters"], labels=True)
 
 
-def test_work_counting_variant_same_results(frame):
+@pytest.mark.parametrize("fm", [0, 2])
+def test_work_counting_variant_same_results(frame, fm):
     # the measurement variant of the following kernel counts its work and
     # must leave every output unchanged
     ev, o = frame
@@ -92,11 +93,15 @@ def test_work_counting_variant_same_results(frame):
 
     ns = ev.n_samples
     reco = tpc.Reco(ev.n_units, ev.n_time_bins, ns, ns // 8)
+    reco.set_tuning(follow_mode=fm)
     reco.profile(False, count_work=True)
     g1 = run_gpu(ev, reco=reco, max_tracklets=ns // 8)
     c = g1["counts"]
     assert c["follow_steps"] > 0 and c["follow_updates"] > 0 and c["follow_candidates"] > 0
     assert c["follow_updates"] <= c["follow_steps"] + 2 * c["n_tracklets"]
+    # a lane slot per lane and wave round: at least one per step
+    assert c["follow_lane_slots"] >= c["follow_steps"]
+    print(f"follow_mode {fm}: lane use {c['follow_steps'] / c['follow_lane_slots']:.3f}")
     reco.profile(False)
     g2 = run_gpu(ev, reco=reco, max_tracklets=ns // 8)
     assert g2["counts"]["follow_steps"] == 0
@@ -109,7 +114,7 @@ def test_set_tuning_rejects_unknown_shapes():
     reco = tpc.Reco(1, 100, 1024, 64)
     before = reco.tuning()
     for bad in (dict(cl_window=12), dict(cl_chunk=3), dict(cl_window=20, cl_chunk=4), dict(cl_window=28),
-                dict(follow_block=96), dict(follow_mode=2), dict(refit_waves=3)):
+                dict(follow_block=96), dict(follow_mode=3), dict(refit_waves=3)):
         with pytest.raises(tpc.TpcError):
             reco.set_tuning(**bad)
         assert reco.tuning() == before
