@@ -661,15 +661,17 @@ def main():
     # their sorts; FP32 operations).  `roofline` is the one whose launch time
     # is the larger, i.e. the dominant kernel.
     n_ur = ev.n_units * 152
-    tn = tuning["chosen"] if tuning else {"cl_window": 16, "cl_chunk": 8}
+    tn = reco.tuning()  # the launch shapes the timed steps ran with
     sb = stage_bytes(ns, nc, n_ur, ev.n_time_bins, tn["cl_window"])
     dom = max(stages, key=lambda k: stages[k])
     # algorithmic bytes of the clusterizer: the samples it reads (u16 pad,
     # time, adc) and a 32-byte cluster record per cluster it produces
     peak_bytes = 6 * ns + 32 * nc
     ach = peak_bytes / (stages["cluster_peaks"] / 1e3) / 1e9
-    kname = f"void k_cluster_peaks<{tn['cl_window']}, {tn['cl_chunk']},"
-    roof_peaks = dict(bound="hbm", kernel="k_cluster_peaks", achieved=ach, peak=HBM_PEAK_GBS,
+    kname = (f"void k_cluster_stream<{tn['cl_window']}, {tn['cl_chunk']}>" if tn["cl_mode"] == 1 else
+             f"void k_cluster_peaks<{tn['cl_window']}, {tn['cl_chunk']},")
+    roof_peaks = dict(bound="hbm", kernel="k_cluster_stream" if tn["cl_mode"] == 1 else "k_cluster_peaks",
+                      achieved=ach, peak=HBM_PEAK_GBS,
                       unit="GB/s", frac=ach / HBM_PEAK_GBS,
                       traffic=pmc_traffic(KERNEL_SOURCES["cluster_peaks"], "cluster_peaks", kname),
                       bytes_per_launch=peak_bytes, ms_per_launch=stages["cluster_peaks"],
@@ -678,11 +680,14 @@ def main():
     flops = (FLOPS_STEP * fcounts["follow_steps"] + FLOPS_CAND * fcounts["follow_candidates"] +
              FLOPS_UPDATE * fcounts["follow_updates"])
     ach_f = flops / (stages["following"] / 1e3) / 1e12
-    roof_follow = dict(bound="alu", kernel="following (k_follow pass A + pass B, with their sorts)",
+    fb, fm = tn["follow_block"], tn["follow_mode"]
+    fkern = (f"void k_follow<{fb}, 2, false>" if fm == 1 else
+             " + ".join(f"void {'k_follow_q' if fm == 2 else 'k_follow'}<{fb}, {p}, false>"
+                        for p in (0, 1)))
+    roof_follow = dict(bound="alu", kernel=f"following ({fkern}, with the sorts)",
                        achieved=ach_f, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                        frac=ach_f / FP32_PEAK_TFLOPS,
-                       traffic=pmc_traffic(KERNEL_SOURCES["following"], "following",
-                                           "void k_follow<"),
+                       traffic=pmc_traffic(KERNEL_SOURCES["following"], "following", fkern),
                        flops_per_launch=flops, ms_per_launch=stages["following"],
                        steps=fcounts["follow_steps"], candidates=fcounts["follow_candidates"],
                        updates=fcounts["follow_updates"],

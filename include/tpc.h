@@ -509,7 +509,11 @@ const char* tpc_status_string(int status);
  * One tracklet per lane at a time in every mode.  refit_waves: most waves of the FP32 refit resident per compute
  * unit, 0 (no limit), 4, 5, 6 or 8; the refit lasts as long as its longest
  * tracks' serial chains, which run faster with fewer waves sharing a SIMD
- * (the limit is a reservation of LDS per workgroup).  tpc_set_tuning rejects
+ * (the limit is a reservation of LDS per workgroup).  cl_mode: 0 the
+ * clusterizer's peak pass per window (each window with its own halo of time
+ * bins), 1 per chunk of cl_chunk windows as one stream of samples through a
+ * ring of 32 time bins, handing chunks whose live peaks exceed its 31 moment
+ * slots to the per-window pass.  tpc_set_tuning rejects
  * other values with TPC_ERR_ARG and leaves
  * the context unchanged; it takes effect at the next call (a captured graph
  * keeps the shapes it was captured with). */
@@ -519,6 +523,7 @@ typedef struct {
   int32_t follow_block;
   int32_t follow_mode;
   int32_t refit_waves;
+  int32_t cl_mode;
 } tpc_tuning;
 int tpc_tuning_default(tpc_tuning* t);
 int tpc_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

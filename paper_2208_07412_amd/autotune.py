@@ -1,7 +1,7 @@
 """Launch-shape autotuner.
 
-Every launch shape the library offers (clusterizer window and windows per
-workgroup; workgroup size and mode of the following; resident waves of the
+Every launch shape the library offers (clusterizer window, windows per
+workgroup and per-window or streamed peak pass; workgroup size and mode of the following; resident waves of the
 FP32 refit) gives identical results, so
 the choice is made by timing alone: each candidate runs the full launch
 sequence on the caller's resident workload, the library's stage timers (HIP
@@ -12,8 +12,10 @@ from __future__ import annotations
 
 from typing import Dict, List, Tuple
 
-CLUSTER_SHAPES: List[Tuple[int, int]] = [(8, 4), (8, 8), (8, 16), (16, 4), (16, 8), (16, 16), (20, 8), (24, 8),
-                                         (32, 4), (32, 8), (32, 16)]
+# (window, windows per workgroup, mode): mode 0 per window, 1 streamed per chunk
+CLUSTER_SHAPES: List[Tuple[int, int, int]] = [
+    (8, 4, 0), (8, 8, 0), (8, 16, 0), (16, 4, 0), (16, 8, 0), (16, 16, 0), (20, 8, 0), (24, 8, 0),
+    (32, 4, 0), (32, 8, 0), (32, 16, 0), (16, 16, 1), (24, 8, 1), (32, 16, 1)]
 FOLLOW_SHAPES: List[Tuple[int, int]] = [(fb, fm) for fm in (0, 1, 2) for fb in (64, 128, 256)]
 CLUSTER_STAGES = ("sample_index", "cluster_peaks", "cluster_scan", "cluster_output")
 FOLLOW_STAGES = ("following",)
@@ -51,12 +53,13 @@ def autotune(reco, run, reps: int = 3, margin: float = 0.02) -> dict:
     fastest shapes set on reco and returns them with every timing (ms)."""
     start = reco.tuning()
     res = {"cluster": {}, "follow": {}}
-    for w, k in CLUSTER_SHAPES:
-        reco.set_tuning(cl_window=w, cl_chunk=k)
-        res["cluster"][f"{w}x{k}"] = _time(reco, run, CLUSTER_STAGES, reps)
-    best_c = _pick(res["cluster"], f"{start['cl_window']}x{start['cl_chunk']}", margin)
-    w, k = (int(x) for x in best_c.split("x"))
-    reco.set_tuning(cl_window=w, cl_chunk=k)
+    for w, k, m in CLUSTER_SHAPES:
+        reco.set_tuning(cl_window=w, cl_chunk=k, cl_mode=m)
+        res["cluster"][f"{w}x{k}x{m}"] = _time(reco, run, CLUSTER_STAGES, reps)
+    best_c = _pick(res["cluster"], f"{start['cl_window']}x{start['cl_chunk']}x{start['cl_mode']}",
+                   margin)
+    w, k, m = (int(x) for x in best_c.split("x"))
+    reco.set_tuning(cl_window=w, cl_chunk=k, cl_mode=m)
     for fb, fm in FOLLOW_SHAPES:
         reco.set_tuning(follow_block=fb, follow_mode=fm)
         res["follow"][f"{fb}x{fm}"] = _time(reco, run, FOLLOW_STAGES, reps)

@@ -359,21 +359,26 @@ struct ClusterRec {
 // finds the up codes and peaks, accumulates each peak's moments in LDS
 // (batches of CL_SLOTS peaks), writes one raw record per peak and the
 // window's peak count.
+template <int W>
+struct PeaksLds {
+  __attribute__((aligned(16))) uint16_t tile[(W + 2 * CL_HALO) * CL_TP];
+  uint16_t pk_cell[CL_SLOTS + 1];
+  unsigned long long acc0[CL_SLOTS + 1], acc1[CL_SLOTS + 1];
+};
+
 template <int W, int K, int PRE>
-__global__ __launch_bounds__(64) void k_cluster_peaks(ZsArgs in, const uint32_t* __restrict__ zblk,
-                                                      uint32_t nblk, uint32_t nwin,
-                                                      uint32_t nchunk, uint32_t n_ur,
-                                                      uint32_t* __restrict__ win_cnt,
-                                                      ClusterRec* __restrict__ rec,
-                                                      int32_t* __restrict__ sample_label,
-                                                      const DevParams* __restrict__ P,
-                                                      const DevStatus* st) {
+__device__ __forceinline__ void peaks_chunk(const ZsArgs& in, const uint32_t* __restrict__ zblk,
+                                            uint32_t nblk, uint32_t nwin, uint32_t nchunk,
+                                            uint32_t n_ur, uint32_t* __restrict__ win_cnt,
+                                            ClusterRec* __restrict__ rec,
+                                            int32_t* __restrict__ sample_label,
+                                            const DevParams* __restrict__ P, uint32_t logical,
+                                            PeaksLds<W>& L) {
   constexpr int ROWS = W + 2 * CL_HALO;
-  __shared__ __attribute__((aligned(16))) uint16_t tile[ROWS * CL_TP];
-  __shared__ uint16_t pk_cell[CL_SLOTS + 1];
-  __shared__ unsigned long long acc0[CL_SLOTS + 1], acc1[CL_SLOTS + 1];
-  if (failed(st)) return;
-  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
+  uint16_t* tile = L.tile;
+  uint16_t* pk_cell = L.pk_cell;
+  unsigned long long* acc0 = L.acc0;
+  unsigned long long* acc1 = L.acc1;
   const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
   if (ur >= n_ur) return;
   const int np = uni(P->np[ur % NROW]), qmin = uni(P->qmax_min);
@@ -526,6 +531,336 @@ __global__ __launch_bounds__(64) void k_cluster_peaks(ZsArgs in, const uint32_t*
     R = Rn;
     cur = nxt;
   }
+}
+
+template <int W, int K, int PRE>
+__global__ __launch_bounds__(64) void k_cluster_peaks(ZsArgs in, const uint32_t* __restrict__ zblk,
+                                                      uint32_t nblk, uint32_t nwin,
+                                                      uint32_t nchunk, uint32_t n_ur,
+                                                      uint32_t* __restrict__ win_cnt,
+                                                      ClusterRec* __restrict__ rec,
+                                                      int32_t* __restrict__ sample_label,
+                                                      const DevParams* __restrict__ P,
+                                                      const DevStatus* st) {
+  __shared__ PeaksLds<W> L;
+  if (failed(st)) return;
+  peaks_chunk<W, K, PRE>(in, zblk, nblk, nwin, nchunk, n_ur, win_cnt, rec, sample_label, P,
+                         xcd_remap(blockIdx.x, gridDim.x), L);
+}
+
+// The windowed pass over the chunks that the streaming pass handed back:
+// list[0] is their count, list[1 + i] the chunks (any order).
+template <int W, int K, int PRE>
+__global__ __launch_bounds__(64) void k_cluster_peaks_list(ZsArgs in,
+                                                           const uint32_t* __restrict__ zblk,
+                                                           uint32_t nblk, uint32_t nwin,
+                                                           uint32_t nchunk, uint32_t n_ur,
+                                                           uint32_t* __restrict__ win_cnt,
+                                                           ClusterRec* __restrict__ rec,
+                                                           int32_t* __restrict__ sample_label,
+                                                           const uint32_t* __restrict__ list,
+                                                           const DevParams* __restrict__ P,
+                                                           const DevStatus* st) {
+  __shared__ PeaksLds<W> L;
+  if (failed(st)) return;
+  const uint32_t n = uni(list[0]);
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    peaks_chunk<W, K, PRE>(in, zblk, nblk, nwin, nchunk, n_ur, win_cnt, rec, sample_label, P,
+                           uni(list[1 + i]), L);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ streaming pass
+// Same records, window counts and labels as the windowed pass, without its
+// per-window halo work and partly filled 64-sample steps.  One wave walks the
+// chunk's samples (time, pad order) through a ring tile of CS_RB time bins
+// (time t in ring row t mod CS_RB) with four cursors, each taking up to 64
+// samples per round:
+//   place:  the ADC of samples in [T0-3, T1+3) into the ring;
+//   code:   up code and peak flag of samples in [T0-2, T1+2), once every
+//           sample up to t+1 is placed; core peaks get a moment slot and a
+//           record index (window start + rank in the window);
+//   gather: each sample in [T0-2, T1+2) adds itself to the core peak it
+//           reaches in two uphill steps (and labels itself, for core
+//           samples), once every code up to t+2 is written;
+//   clear:  zeroes the cells of samples below the rows the gather still
+//           reads, so the ring rows can take later times.
+// The ring holds the times [R, R + CS_RB), R the lowest row still read: a
+// time is placed, and a row read, only inside that range, so a row with no
+// sample reads as empty rather than as the cells of a time CS_RB apart.
+// A peak's record is written once the gather has passed its time + 2.  Slots
+// are reused in rank order (CL_SLOTS live at most); a chunk that would need
+// more, or that stops making progress (input not sorted), is appended to a
+// list for the windowed pass.
+#define CS_RB 32
+
+struct SCur {
+  uint32_t x;         // first sample not taken (uniform)
+  uint32_t tp0, tp1;  // samples x + lane and x + 64 + lane: time << 16 | pad, or ~0u
+};
+
+__device__ __forceinline__ uint32_t cs_tp(const ZsArgs& in, uint32_t s, uint32_t s_hi) {
+  return s < s_hi ? (((uint32_t)in.time[s] << 16) | in.pad[s]) : 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ void cs_init(SCur& c, const ZsArgs& in, uint32_t x, uint32_t s_hi) {
+  c.x = x;
+  c.tp0 = cs_tp(in, x + threadIdx.x, s_hi);
+  c.tp1 = cs_tp(in, x + 64 + threadIdx.x, s_hi);
+}
+
+// the lane's value of lane (lane + n) of the pair (v0, v1), n in [1, 64]
+__device__ __forceinline__ uint32_t cs_shift(uint32_t v0, uint32_t v1, uint32_t n) {
+  const uint32_t src = threadIdx.x + n;
+  const int addr = (int)((src & 63u) << 2);
+  const uint32_t a = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v0);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v1);
+  return src < 64 ? a : b;
+}
+
+// take n (uniform, 0..64) samples; the next 64 are loaded for the round after
+__device__ __forceinline__ void cs_take(SCur& c, uint32_t n, const ZsArgs& in, uint32_t s_hi) {
+  if (n == 0) return;
+  c.tp0 = cs_shift(c.tp0, c.tp1, n);
+  c.x += n;
+  c.tp1 = cs_tp(in, c.x + 64 + threadIdx.x, s_hi);
+}
+
+// time of the first sample not taken, CS_END when none is left
+#define CS_END (1 << 20)
+__device__ __forceinline__ int cs_front(const SCur& c) {
+  const uint32_t v = __builtin_amdgcn_readfirstlane(c.tp0);
+  return v == 0xFFFFFFFFu ? CS_END : (int)(v >> 16);
+}
+
+// number of leading lanes (a prefix, as times are sorted) with ok set
+__device__ __forceinline__ uint32_t cs_count(bool ok) {
+  const uint64_t m = __ballot(ok);
+  return m == ~0ull ? 64u : (uint32_t)__builtin_ctzll(~m);
+}
+
+__device__ __forceinline__ int cs_cell(int t, int p) {
+  return (int)__umul24((uint32_t)t & (CS_RB - 1), CL_TP) + p + 2;
+}
+
+template <int W, int K>
+__global__ __launch_bounds__(64) void k_cluster_stream(ZsArgs in, const uint32_t* __restrict__ zblk,
+                                                       uint32_t nblk, uint32_t nwin,
+                                                       uint32_t nchunk, uint32_t n_ur,
+                                                       uint32_t* __restrict__ win_cnt,
+                                                       ClusterRec* __restrict__ rec,
+                                                       int32_t* __restrict__ sample_label,
+                                                       uint32_t* __restrict__ list,
+                                                       const DevParams* __restrict__ P,
+                                                       const DevStatus* st) {
+  static_assert(K <= 64, "one lane per window");
+  __shared__ __attribute__((aligned(16))) uint16_t tile[CS_RB * CL_TP];
+  __shared__ unsigned long long acc0[CL_SLOTS], acc1[CL_SLOTS], meta[CL_SLOTS];
+  __shared__ uint32_t ridx[CL_SLOTS];
+  __shared__ uint32_t clo[K], wfirst[K], wcnt[K];
+  if (failed(st)) return;
+  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
+  if (ur >= n_ur) return;
+  const uint32_t lane = threadIdx.x;
+  const int np = uni(P->np[ur % NROW]), qmin = uni(P->qmax_min);
+  const uint32_t* zb = zblk + (size_t)ur * (nblk + 1);
+  uint32_t rs0 = uni(zb[0]), rs1 = uni(zb[nblk]);
+  if (rs1 > in.n_samples) rs1 = in.n_samples;
+  if (rs0 > rs1) rs0 = rs1;
+  constexpr int BW = W >> CL_BSHIFT;
+  const int w0 = (int)(chunk * K);
+  const int nw = min((int)nwin - w0, K);
+  const int T0 = w0 * W, T1 = (w0 + nw) * W;
+  uint32_t s_lo, s_hi;
+  row_range(zb, nblk, w0 * BW - 1, (w0 + nw) * BW + 1, rs0, rs1, s_lo, s_hi);
+  s_lo = uni(s_lo);
+  s_hi = uni(s_hi);
+  if ((int)lane < nw) {
+    uint32_t a, b;
+    row_range(zb, nblk, (w0 + (int)lane) * BW, (w0 + (int)lane + 1) * BW, rs0, rs1, a, b);
+    clo[lane] = a;
+    wfirst[lane] = 0xFFFFFFFFu;
+    wcnt[lane] = 0;
+  }
+  {
+    uint4* t4 = reinterpret_cast<uint4*>(tile);
+    constexpr int N4 = CS_RB * CL_TP * 2 / 16;
+    for (int i = lane; i < N4; i += 64) t4[i] = make_uint4(0, 0, 0, 0);
+  }
+  SCur cp, cq, cg, cc;  // place, code, gather, clear
+  cs_init(cp, in, s_lo, s_hi);
+  uint32_t a0 = cp.tp0 != 0xFFFFFFFFu ? in.adc[s_lo + lane] : 0u;
+  uint32_t a1 = cp.tp1 != 0xFFFFFFFFu ? in.adc[s_lo + 64 + lane] : 0u;
+  cq = cp;
+  cg = cp;
+  cc = cp;
+  uint32_t nrank = 0, drank = 0;  // core peaks ranked / whose records are written
+  bool handed_back = false;
+  __syncthreads();
+  for (;;) {
+    // the ring holds the times [R, R + CS_RB): R is the lowest row still read
+    // (the gather reads two bins below its front, rows below an uncleared
+    // sample keep their data), even where no sample falls in it
+    const int R = min(cs_front(cc), cs_front(cg) - 2);
+    // ---- place
+    uint32_t n_p;
+    {
+      const int t = (int)(cp.tp0 >> 16), p = (int)(cp.tp0 & 0xFFFF);
+      const bool ok = cp.tp0 != 0xFFFFFFFFu && t < R + CS_RB;
+      n_p = cs_count(ok);
+      if (lane < n_p && t >= T0 - 3 && t < T1 + 3 && p < np)
+        tile[cs_cell(t, p)] = (uint16_t)(a0 & 0x3FF);
+      if (n_p) {
+        a0 = cs_shift(a0, a1, n_p);
+        cs_take(cp, n_p, in, s_hi);
+        a1 = cp.tp1 != 0xFFFFFFFFu ? in.adc[cp.x + 64 + lane] : 0u;
+      }
+    }
+    // rows at or above R + CS_RB are not in the ring yet: a read there would
+    // see an older time's cells
+    const int Fp = min(cs_front(cp), R + CS_RB);
+    __syncthreads();
+    // ---- code
+    uint32_t n_q;
+    {
+      const int t = (int)(cq.tp0 >> 16), p = (int)(cq.tp0 & 0xFFFF);
+      const bool ok = cq.tp0 != 0xFFFFFFFFu && t + 2 <= Fp;
+      const bool live = ok && t >= T0 - 2 && t < T1 + 2 && p < np;
+      int code = 0, a = 0, c = 0;
+      if (live) {
+        c = cs_cell(t, p);
+        const int bu = (int)__umul24((uint32_t)(t - 1) & (CS_RB - 1), CL_TP);
+        const int bm = (int)__umul24((uint32_t)t & (CS_RB - 1), CL_TP);
+        const int bd = (int)__umul24((uint32_t)(t + 1) & (CS_RB - 1), CL_TP);
+        const Row3 u = row3(tile, bu + p + 2), m = row3(tile, bm + p + 2),
+                   d = row3(tile, bd + p + 2);
+        a = m.m;
+        int best = (a << 4) | 5;
+        best = max(best, max(u.l << 4, (u.m << 4) | 1));
+        best = max(best, max((u.r << 4) | 2, (m.l << 4) | 4));
+        best = max(best, max((m.r << 4) | 6, (d.l << 4) | 8));
+        best = max(best, max((d.m << 4) | 9, (d.r << 4) | 10));
+        code = best >= 16 ? (best & 15) : 5;
+        code |= (code == 5 && a >= qmin) ? 16 : 0;
+      }
+      const bool pk = live && (code & 16) && t >= T0 && t < T1;
+      // a core peak needs a free slot: take the samples before the first
+      // peak that would overflow the slots
+      const uint64_t pm = __ballot(pk);
+      const uint32_t below = (uint32_t)__popcll(pm & ((1ull << lane) - 1ull));
+      const uint32_t room = CL_SLOTS - (nrank - drank);
+      const uint64_t over = __ballot(pk && below >= room);
+      n_q = cs_count(ok);
+      if (over) n_q = min(n_q, (uint32_t)__builtin_ctzll(over));
+      const bool take = lane < n_q;
+      const uint32_t rank = nrank + below;
+      const uint32_t slot = rank % CL_SLOTS;
+      int wi = 0;
+      if (take && pk) {
+        wi = (t - T0) / W;
+        atomicMin(&wfirst[wi], rank);
+        acc0[slot] = 0;
+        acc1[slot] = 0;
+        meta[slot] = (uint64_t)(uint32_t)p | ((uint64_t)(uint32_t)t << 8) | ((uint64_t)(uint32_t)a << 32);
+      }
+      if (take && live)
+        tile[c] = (uint16_t)((code & 16) ? (a | CL_PEAK | (pk ? slot_bits((int)slot) : CL_NOSLOT))
+                                         : (a | ((code & 15) << 10)));
+      __syncthreads();
+      if (take && pk) {
+        const uint32_t r = rank - wfirst[wi];
+        ridx[slot] = clo[wi] + r;
+        atomicMax(&wcnt[wi], r + 1);
+      }
+      nrank += (uint32_t)__popcll(pm & (n_q >= 64 ? ~0ull : ((1ull << n_q) - 1ull)));
+      cs_take(cq, n_q, in, s_hi);
+    }
+    const int Fq = min(cs_front(cq), R + CS_RB);
+    __syncthreads();
+    // ---- gather
+    uint32_t n_g;
+    {
+      const int t = (int)(cg.tp0 >> 16), p = (int)(cg.tp0 & 0xFFFF);
+      const bool ok = cg.tp0 != 0xFFFFFFFFu && t + 3 <= Fq;
+      n_g = cs_count(ok);
+      int32_t lab = -1;
+      if (lane < n_g && t >= T0 - 2 && t < T1 + 2 && p < np) {
+        const int tx = tile[cs_cell(t, p)];
+        const int cx = chase_code(tx);
+        const int yt = t + (cx >> 2) - 1, yp = p + (cx & 3) - 1;
+        if (yt >= T0 - 2 && yt < T1 + 2) {
+          const int ty = tile[cs_cell(yt, yp)];
+          const int cy = chase_code(ty);
+          const int zt = yt + (cy >> 2) - 1, zp = yp + (cy & 3) - 1;
+          const int tz = tile[cs_cell(zt, zp)];
+          if (tz & CL_PEAK) lab = (zt << 8) | zp;
+          const int slot = slot_of(tz);
+          if ((tz & CL_PEAK) && slot != CL_SLOTS && zt >= T0 && zt < T1) {
+            const uint32_t av = tx & 0x3FF;
+            const uint32_t dt2 = 4 - (cx >> 2) - (cy >> 2);  // dt + 2, dt = sample - peak
+            const uint32_t dp2 = 4 - (cx & 3) - (cy & 3);
+            const int dt = (int)dt2 - 2, dp = (int)dp2 - 2;
+            const uint32_t dtt = (uint32_t)__mul24(dt, dt), dpp = (uint32_t)__mul24(dp, dp);
+            const uint32_t ap = __umul24(av, dp2), at = __umul24(av, dt2);
+            const uint32_t lo0 = av | (1u << 15) | ((uint32_t)(av >= 1023) << 20) | (ap << 25);
+            uint32_t adpp;
+            asm("v_mul_u32_u24 %0, %1, %2" : "=v"(adpp) : "v"(av), "v"(dpp));
+            const uint32_t hi0 = (ap >> 7) | (adpp << 10);
+            const uint64_t v0 = ((uint64_t)hi0 << 32) | lo0;
+            const uint64_t v1 = ((uint64_t)__umul24(av, dtt) << 32) | at;
+            atomicAdd(&acc0[slot], (unsigned long long)v0);
+            atomicAdd(&acc1[slot], (unsigned long long)v1);
+          }
+        }
+      }
+      if (sample_label && lane < n_g && t >= T0 && t < T1) sample_label[cg.x + lane] = lab;
+      cs_take(cg, n_g, in, s_hi);
+    }
+    const int Fg = cs_front(cg);
+    __syncthreads();
+    // ---- records of the peaks the gather has passed (ranks are in time order)
+    uint32_t n_r;
+    {
+      const uint32_t r = drank + lane;
+      bool ok = false;
+      uint32_t slot = 0;
+      if (r < nrank) {
+        slot = r % CL_SLOTS;
+        ok = (int)((meta[slot] >> 8) & 0xFFFF) + 3 <= Fg;
+      }
+      n_r = cs_count(ok);
+      if (lane < n_r) {
+        ClusterRec rr;
+        rr.m0 = acc0[slot];
+        rr.m1 = acc1[slot];
+        rr.m2 = meta[slot];
+        rec[ridx[slot]] = rr;
+      }
+      drank += n_r;
+    }
+    // ---- clear the cells of samples below the rows still read
+    uint32_t n_c;
+    {
+      const int t = (int)(cc.tp0 >> 16), p = (int)(cc.tp0 & 0xFFFF);
+      const bool ok = cc.tp0 != 0xFFFFFFFFu && t + 3 <= Fg;
+      n_c = cs_count(ok);
+      if (lane < n_c && t >= T0 - 3 && t < T1 + 3 && p < np) tile[cs_cell(t, p)] = 0;
+      cs_take(cc, n_c, in, s_hi);
+    }
+    __syncthreads();
+    if (cg.x >= s_hi && drank == nrank) break;
+    if (n_p + n_q + n_g + n_r + n_c == 0) {  // no progress: not sorted
+      handed_back = true;
+      break;
+    }
+  }
+  if (handed_back) {
+    if (lane == 0) list[1 + atomicAdd(&list[0], 1u)] = logical;
+    return;
+  }
+  if ((int)lane < nw) win_cnt[(size_t)ur * nwin + w0 + lane] = wcnt[lane];
 }
 
 // Output pass: clusters from the raw records, one thread per cluster.  A

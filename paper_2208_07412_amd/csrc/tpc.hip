@@ -62,6 +62,7 @@ struct tpc_ctx {
   uint32_t* zblk = nullptr;   // sample block index
   uint32_t* cblk = nullptr;   // cluster block index (hit grid)
   uint32_t* win = nullptr;    // clusterizer window counts / offsets
+  uint32_t* cl_list = nullptr;  // chunks the streaming peak pass handed back
   ClusterRec* crec = nullptr;  // raw cluster records, indexed like the samples
   void* bsum = nullptr;       // scan block sums (u64)
   unsigned long long* tot64 = nullptr;
@@ -126,7 +127,7 @@ struct Layout {
 };
 
 struct Plan {
-  size_t zblk, cblk, win, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, f_qnext, pos,
+  size_t zblk, cblk, win, cl_list, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, f_qnext, pos,
       owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, cm_a, cm_b, cm_tot, cm_info, mg_fs,
       mg_cell, mg_cnt, mg_off, mg_cur, mg_ends, mg_parent, mg_key, mg_idx, mg_skey, mg_sidx,
       mg_sector, mg_C, mg_tgl, mg_e, mg_cs18, mg_pk, mg_hxy, hit_off, par, st, total;
@@ -172,6 +173,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.zblk = L.add<uint32_t>(nur * (p.nblk_s + 1));
   p.cblk = L.add<uint32_t>(nur * (p.nblk + 1));
   p.win = L.add<uint32_t>(nur * p.nwin);
+  p.cl_list = L.add<uint32_t>(1 + nur * (p.nwin / 4 + 1));  // chunks handed back
   p.crec = L.add<ClusterRec>(m.max_samples > 0 ? m.max_samples : 1);
   p.bsum = L.add<unsigned long long>(p.bsum_cap);
   p.tot64 = L.add<unsigned long long>(1);
@@ -431,9 +433,20 @@ void launch_cluster(tpc_ctx* c, const ZsArgs& za, uint32_t nblk_s, uint32_t n_ur
   const uint32_t nwt = n_ur * nwin;
   {
     StageTimer tm(c, 1);
-    k_cluster_peaks<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur,
-                                                     c->win, c->crec, co.sample_label, c->d_par,
-                                                     c->d_st);
+    if (c->tune.cl_mode == 1) {
+      // streaming pass, then the windowed pass over the chunks it handed back
+      k_fill<uint32_t><<<1, 64, 0, s>>>(c->cl_list, 0u, 1);
+      k_cluster_stream<W, K><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur, c->win,
+                                                  c->crec, co.sample_label, c->cl_list, c->d_par,
+                                                  c->d_st);
+      k_cluster_peaks_list<W, K, PRE><<<ngrid < 2048 ? ngrid : 2048, 64, 0, s>>>(
+          za, c->zblk, nblk_s, nwin, nchunk, n_ur, c->win, c->crec, co.sample_label, c->cl_list,
+          c->d_par, c->d_st);
+    } else {
+      k_cluster_peaks<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur,
+                                                       c->win, c->crec, co.sample_label, c->d_par,
+                                                       c->d_st);
+    }
   }
   {
     StageTimer tm(c, 2);
@@ -783,6 +796,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->zblk = (uint32_t*)(base + pl.zblk);
   c->cblk = (uint32_t*)(base + pl.cblk);
   c->win = (uint32_t*)(base + pl.win);
+  c->cl_list = (uint32_t*)(base + pl.cl_list);
   c->crec = (ClusterRec*)(base + pl.crec);
   c->bsum = base + pl.bsum;
   c->tot64 = (unsigned long long*)(base + pl.tot64);
@@ -1239,6 +1253,7 @@ int tpc_tuning_default(tpc_tuning* t) {
   t->follow_block = 64;
   t->follow_mode = 2;
   t->refit_waves = 6;
+  t->cl_mode = 0;
   return TPC_OK;
 }
 
@@ -1251,6 +1266,7 @@ int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
   if (t->cl_chunk != 4 && t->cl_chunk != 8 && t->cl_chunk != 16) return TPC_ERR_ARG;
   if (t->follow_block != 64 && t->follow_block != 128 && t->follow_block != 256) return TPC_ERR_ARG;
   if (t->follow_mode < 0 || t->follow_mode > 2) return TPC_ERR_ARG;
+  if (t->cl_mode != 0 && t->cl_mode != 1) return TPC_ERR_ARG;
   if (t->refit_waves != 0 && t->refit_waves != 4 && t->refit_waves != 5 && t->refit_waves != 6 &&
       t->refit_waves != 8)
     return TPC_ERR_ARG;

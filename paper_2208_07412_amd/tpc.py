@@ -104,7 +104,7 @@ class TpcCounts(ctypes.Structure):
 
 class TpcTuning(ctypes.Structure):
     _fields_ = [("cl_window", I32), ("cl_chunk", I32), ("follow_block", I32), ("follow_mode", I32),
-                ("refit_waves", I32)]
+                ("refit_waves", I32), ("cl_mode", I32)]
 
 
 EXPORTS = ["tpc_params_default", "tpc_geometry", "tpc_workspace_size", "tpc_create",
@@ -506,11 +506,13 @@ class Reco:
         return {k: getattr(t, k) for k, _ in TpcTuning._fields_}
 
     def set_tuning(self, **kw):
-        """Change launch shapes (cl_window, cl_chunk, follow_block, follow_mode, refit_waves)."""
+        """Change launch shapes (cl_window, cl_chunk, follow_block, follow_mode, refit_waves,
+        cl_mode)."""
         t = TpcTuning()
         _check(self.lib.tpc_get_tuning(self.ctx, ctypes.byref(t)), "tpc_get_tuning")
         for k, v in kw.items():
-            if k not in ("cl_window", "cl_chunk", "follow_block", "follow_mode", "refit_waves"):
+            if k not in ("cl_window", "cl_chunk", "follow_block", "follow_mode", "refit_waves",
+                         "cl_mode"):
                 raise KeyError(k)
             setattr(t, k, int(v))
         _check(self.lib.tpc_set_tuning(self.ctx, ctypes.byref(t)), "tpc_set_tuning")

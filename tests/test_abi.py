@@ -127,9 +127,9 @@ def test_tuning_defaults_and_validation():
     lib = tpc.load()
     t = tpc.TpcTuning()
     assert lib.tpc_tuning_default(ctypes.byref(t)) == 0
-    assert (t.cl_window, t.cl_chunk, t.follow_block, t.follow_mode, t.refit_waves) == \
-        (24, 8, 64, 2, 6)
+    assert (t.cl_window, t.cl_chunk, t.follow_block, t.follow_mode, t.refit_waves, t.cl_mode) == \
+        (24, 8, 64, 2, 6, 0)
     assert lib.tpc_set_tuning(None, ctypes.byref(t)) == -1
     assert lib.tpc_get_tuning(None, ctypes.byref(t)) == -1
     assert lib.tpc_tuning_default(None) == -1
-    assert ctypes.sizeof(tpc.TpcTuning) == 20
+    assert ctypes.sizeof(tpc.TpcTuning) == 24

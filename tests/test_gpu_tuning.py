@@ -33,11 +33,12 @@ def frame():
     return ev, run_oracle(ev, labels=True)
 
 
+@pytest.mark.parametrize("cm", [0, 1])
 @pytest.mark.parametrize("w,k,fb,fm,rw", SHAPES)
-def test_shape_parity(frame, w, k, fb, fm, rw):
+def test_shape_parity(frame, w, k, fb, fm, rw, cm):
     ev, o = frame
     g = run_gpu(ev, labels=True, tuning=dict(cl_window=w, cl_chunk=k, follow_block=fb,
-                                              follow_mode=fm, refit_waves=rw))
+                                              follow_mode=fm, refit_waves=rw, cl_mode=cm))
     compare_clusters(g["clusters"], o["clusters"], labels=True)
     assert np.array_equal(g["links"]["down"], o["down"])
     assert np.array_equal(g["links"]["up"], o["up"])
@@ -64,22 +65,25 @@ def _lattice_event(T, step_t, step_p, adc):
                           np.array(a, np.uint16), rs, 1, T, {}, {}, None)
 
 
+@pytest.mark.parametrize("cm", [0, 1])
 @pytest.mark.parametrize("w,k", [(8, 4), (16, 8), (20, 8), (24, 8), (32, 4)])
-def test_most_peaks_per_window(w, k):
+def test_most_peaks_per_window(w, k, cm):
     # isolated samples on every other pad and bin: each one is a peak, so a
-    # window holds far more peaks than one moment batch
+    # window holds far more peaks than one moment batch (and the streaming
+    # pass hands its chunks to the per-window pass)
     ev = _lattice_event(100, 2, 2, lambda t, p: 5 + (t * 7 + p * 3) % 900)
-    g = run_gpu(ev, labels=True, max_tracklets=64, tuning=dict(cl_window=w, cl_chunk=k))
+    g = run_gpu(ev, labels=True, max_tracklets=64, tuning=dict(cl_window=w, cl_chunk=k, cl_mode=cm))
     o = run_oracle(ev, labels=True)
     assert len(o["clusters"]["y_fx"]) == ev.n_samples
     compare_clusters(g["clusters"], o["clusters"], labels=True)
 
 
+@pytest.mark.parametrize("cm", [0, 1])
 @pytest.mark.parametrize("w,k", [(8, 16), (16, 8), (20, 8), (24, 8), (32, 16)])
-def test_fully_occupied_rows(w, k):
+def test_fully_occupied_rows(w, k, cm):
     # every (time, pad) present: the densest input a row can have
     ev = _lattice_event(120, 1, 1, lambda t, p: 3 + ((t * 131 + p * 71) * 2654435761 % 2**32) % 400)
-    g = run_gpu(ev, labels=True, max_tracklets=64, tuning=dict(cl_window=w, cl_chunk=k))
+    g = run_gpu(ev, labels=True, max_tracklets=64, tuning=dict(cl_window=w, cl_chunk=k, cl_mode=cm))
     o = run_oracle(ev, labels=True)
     compare_clusters(g["clusters"], o["clusters"], labels=True)
 
@@ -114,7 +118,7 @@ def test_set_tuning_rejects_unknown_shapes():
     reco = tpc.Reco(1, 100, 1024, 64)
     before = reco.tuning()
     for bad in (dict(cl_window=12), dict(cl_chunk=3), dict(cl_window=20, cl_chunk=4), dict(cl_window=28),
-                dict(follow_block=96), dict(follow_mode=3), dict(refit_waves=3)):
+                dict(follow_block=96), dict(follow_mode=3), dict(refit_waves=3), dict(cl_mode=2)):
         with pytest.raises(tpc.TpcError):
             reco.set_tuning(**bad)
         assert reco.tuning() == before
