@@ -233,7 +233,11 @@ int tpc_params_default(tpc_params* p, double noise_sigma);
 /* Library-side geometry: pads per row and fixed-point row radius / pitch. */
 int tpc_geometry(int32_t* npads, int32_t* x_fx, int32_t* pitch_fx);
 
-/* Bytes of device scratch a context with these bounds allocates. */
+/* Bytes of device scratch a context with these bounds allocates.  Bounds
+ * beyond what a context supports give TPC_ERR_ARG here and in tpc_create:
+ * max_time_bins above 65000, max_tracklets above 2^24, max_clusters * 8
+ * bytes or the cluster grid (max_units * 152 * (max_time_bins / 2 + 1)
+ * entries of 4 bytes) at 4 GiB or more. */
 int tpc_workspace_size(const tpc_sizes* max, size_t* bytes);
 
 /* Create a context on the current device bound to hip_stream (a

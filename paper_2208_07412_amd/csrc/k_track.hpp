@@ -327,7 +327,16 @@ struct FollowOut {
   uint8_t* krow;      // [cap*152]: rows of the kept hits, ascending (after resolution)
 };
 
-#define SEARCH_UNROLL 2
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Raw buffer resource over a device array (uniform base, no range limit:
+// callers read inside the array; word 3 = 32-bit data format).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)0xFFFFFFFF,
+                                           0x00020000);
+}
+
 // Best candidate of row ur for the track state k: the cluster with the least
 // chi2 within the cut, the lower index on ties (-1 if none).  Only the grid
 // blocks within the z residual bound that chi2 alone sets (plus a margin) are
@@ -345,21 +354,50 @@ __device__ __forceinline__ int32_t search_row(const ClusterView& cl, const uint3
   if (!(fhi >= 0.0f) || !(flo == flo)) bhi = -1;
   if (blo > (int32_t)nblk - 1) blo = nblk - 1;
   if (bhi > (int32_t)nblk - 1) bhi = nblk - 1;
+  // Every load below is a cache line of its own per lane, and the following
+  // is bound by their number: the row bounds come in one 8-byte load, the two
+  // grid entries in one 16-byte load when the range spans at most 3 blocks,
+  // the candidates two per 16-byte load.  Same clamps as row_range.
+  // (buffer loads: the compiler keeps them whole; every read lies inside the
+  // arrays, the row's own table included)
+  const u32x2 rb = __builtin_amdgcn_raw_buffer_load_b64(buffer_of(cl.crow), (int)(ur * 4u), 0, 0);
+  const uint32_t cap = cl.capacity;
+  const uint32_t s0 = rb.x < cap ? rb.x : cap, s1 = rb.y < cap ? rb.y : cap;
+  int32_t ilo = blo < 0 ? 0 : blo, ihi = bhi + 1 > (int32_t)nblk ? (int32_t)nblk : bhi + 1;
+  if (ihi < ilo) ihi = ilo;
+  const size_t rowe = (size_t)ur * (nblk + 1);
   uint32_t a, b;
-  row_range(cblk + (size_t)ur * (nblk + 1), nblk, blo, bhi + 1, cl.row_start(ur),
-            cl.row_start(ur + 1), a, b);
+  if (ihi - ilo <= 3 && ilo + 3 <= (int32_t)nblk) {
+    const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(buffer_of(cblk), (int)((rowe + ilo) * 4u),
+                                                          0, 0);
+    const int d = ihi - ilo;
+    a = e.x;
+    b = d == 0 ? e.x : d == 1 ? e.y : d == 2 ? e.z : e.w;
+  } else {
+    a = cblk[rowe + ilo];
+    b = cblk[rowe + ihi];
+  }
+  if (a < s0) a = s0;
+  if (a > s1) a = s1;
+  if (b < a) b = a;
+  if (b > s1) b = s1;
   int32_t best = -1;
   float bchi = 0.0f;
   const SInv<float> si = s_inverse(k, vy, vz);
   n_cand += b - a;
-  // candidates in index order, their positions loaded SEARCH_UNROLL at a
-  // time so that the loads of one group are in flight together
-  for (uint32_t c0 = a; c0 < b; c0 += SEARCH_UNROLL) {
-    int2 q[SEARCH_UNROLL];
+  // candidates in index order, two at a time (both loads of a pair in flight)
+  for (uint32_t c0 = a; c0 < b; c0 += 2) {
+    int2 q[2];
+    if (c0 + 1 < b) {
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(buffer_of(cl.pos), (int)(c0 * 8u), 0, 0);
+      q[0] = make_int2((int)v.x, (int)v.y);
+      q[1] = make_int2((int)v.z, (int)v.w);
+    } else {
+      q[0] = cl.pos[c0];
+      q[1] = make_int2(0, 0);
+    }
 #pragma unroll
-    for (int j = 0; j < SEARCH_UNROLL; ++j) q[j] = c0 + j < b ? cl.pos[c0 + j] : make_int2(0, 0);
-#pragma unroll
-    for (int j = 0; j < SEARCH_UNROLL; ++j) {
+    for (int j = 0; j < 2; ++j) {
       if (c0 + j >= b) break;
       const float my = (float)q[j].x * (float)FX_SCALE;
       const float mz = (float)(q[j].y - anchor) * (float)FX_SCALE;

@@ -755,11 +755,20 @@ int tpc_geometry(int32_t* npads, int32_t* x_fx, int32_t* pitch_fx) {
   return TPC_OK;
 }
 
+// Bounds a context supports: time bins within 16 bits, tracklet ids within
+// 24 bits, and the cluster positions and the cluster grid within the 32-bit
+// byte offsets of the following's buffer loads.
+bool sizes_ok(const tpc_sizes& m) {
+  if (m.max_units == 0 || m.max_time_bins == 0 || m.max_time_bins > 65000 ||
+      m.max_tracklets > (1u << 24))
+    return false;
+  const uint64_t grid = (uint64_t)m.max_units * NROW * (ceil_div(m.max_time_bins, 1u << CG_BSHIFT) + 1);
+  return (uint64_t)m.max_clusters * 8 < (1ull << 32) && grid * 4 < (1ull << 32);
+}
+
 int tpc_workspace_size(const tpc_sizes* max, size_t* bytes) {
   if (!max || !bytes) return TPC_ERR_ARG;
-  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65000 ||
-      max->max_tracklets > (1u << 24))
-    return TPC_ERR_ARG;
+  if (!sizes_ok(*max)) return TPC_ERR_ARG;
   *bytes = plan_for(*max).total;
   return TPC_OK;
 }
@@ -767,9 +776,7 @@ int tpc_workspace_size(const tpc_sizes* max, size_t* bytes) {
 int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* hip_stream) {
   if (!out || !p || !max) return TPC_ERR_ARG;
   *out = nullptr;
-  if (max->max_units == 0 || max->max_time_bins == 0 || max->max_time_bins > 65000 ||
-      max->max_tracklets > (1u << 24))
-    return TPC_ERR_ARG;
+  if (!sizes_ok(*max)) return TPC_ERR_ARG;
   if (p->min_tracklet < 3 || p->min_tracklet > NROW || p->min_track_hits < 3 || p->max_miss < 1 ||
       p->qmax_min < 1 || !(p->chi2_max > 0) || !(p->snp_max > 0 && p->snp_max < 1) ||
       p->win_y < 0 || p->win_z < 0 || p->s_max < 0)
