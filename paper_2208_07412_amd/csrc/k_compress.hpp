@@ -177,50 +177,91 @@ struct CmWriter {
 // ------------------------------------------------------------- bit reading
 // Sequential reader of a bit range; w points at payload word woff (a staged
 // copy in LDS, or the payload itself with woff = 0).
-struct CmReader {
-  const uint32_t* w;
-  uint64_t pos, end;  // end = payload bits
+// LSB-first reader over payload words w (w[0] is payload word woff) with a
+// 64-bit bit buffer: one word read per 32 bits consumed.  Bits at or past
+// `end` read as zero; a read that would pass `end` (or a zero prefix longer
+// than 31) marks the reader bad and moves it to `end`.  P is the word
+// pointer: global, or LDS for a staged record (an LDS pointer keeps the
+// reads off the counter that the decoder's global stores also raise, so a
+// read does not wait for the stores before it).
+typedef const __attribute__((address_space(3))) uint32_t lds_u32;
+template <typename P>
+struct CmReaderT {
+  P w;
+  uint64_t pos, end;  // next bit, end of the readable bits (payload bits)
   bool bad;
   uint64_t woff;
+  uint64_t buf;    // bits from pos on; nbuf of them loaded, zeros above
+  uint32_t nbuf;
+  uint64_t wnext;  // payload index of the next word to load
+  __device__ CmReaderT(P w_, uint64_t pos_, uint64_t end_, bool bad_, uint64_t woff_)
+      : w(w_), pos(0), end(end_), bad(bad_), woff(woff_), buf(0), nbuf(0), wnext(0) {
+    seek(pos_);
+  }
+  __device__ void seek(uint64_t p) {
+    pos = p;
+    buf = 0;
+    nbuf = 0;
+    wnext = p >> 5;
+    if (p < end) {
+      buf = (uint64_t)(w[wnext - woff] >> (uint32_t)(p & 31));
+      nbuf = 32 - (uint32_t)(p & 31);
+      ++wnext;
+    }
+  }
+  // at least 32 loaded bits, or every word up to the one holding end - 1
+  __device__ void fill() {
+    if (nbuf < 32 && (wnext << 5) < end) {
+      buf |= (uint64_t)w[wnext - woff] << nbuf;
+      nbuf += 32;
+      ++wnext;
+    }
+  }
+  __device__ void skip(uint32_t n) {
+    buf >>= n;
+    nbuf -= n;
+    pos += n;
+  }
+  __device__ void fail() {
+    bad = true;
+    pos = end;
+    buf = 0;
+    nbuf = 0;
+  }
   __device__ uint64_t get(uint32_t n) {  // n <= 32
     if (n == 0) return 0;
     if (pos + n > end) {
-      bad = true;
-      pos = end;
+      fail();
       return 0;
     }
-    const uint64_t wi = (pos >> 5) - woff;
-    const uint32_t sh = (uint32_t)(pos & 31);
-    uint64_t v = w[wi] >> sh;
-    if (sh + n > 32) v |= (uint64_t)w[wi + 1] << (32 - sh);
-    pos += n;
-    return v & ((1ull << n) - 1);
+    fill();
+    const uint64_t v = buf & ((1ull << n) - 1);
+    skip(n);
+    return v;
   }
   // up to 32 bits from pos on without advancing (bits past the end read 0)
-  __device__ uint32_t peek32() const {
+  __device__ uint32_t peek32() {
     if (pos >= end) return 0;
-    const uint64_t wi = (pos >> 5) - woff;
-    const uint32_t sh = (uint32_t)(pos & 31);
-    uint64_t v = w[wi] >> sh;
-    if (sh && pos + (32 - sh) < end) v |= (uint64_t)w[wi + 1] << (32 - sh);
+    fill();
+    uint32_t v = (uint32_t)buf;
     const uint64_t avail = end - pos;
-    if (avail < 32) v &= (1ull << avail) - 1;
-    return (uint32_t)v;
+    if (avail < 32) v &= (1u << (uint32_t)avail) - 1u;
+    return v;
   }
   __device__ uint64_t eg(int k) {
     // the zero prefix: the trailing zeros of the next 32 bits (LSB first)
     const uint32_t v = peek32();
     if (v == 0) {  // no one bit among the next 32: malformed
-      bad = true;
-      pos = end;
+      fail();
       return 0;
     }
     const uint32_t n = (uint32_t)__builtin_ctz(v);
-    pos += n + 1;
+    skip(n + 1);
     const uint64_t q = (1ull << n) | get(n);
     return ((q - 1) << k) | get(k);
   }
 };
+typedef CmReaderT<const uint32_t*> CmReader;
 
 // -------------------------------------------------------------- cluster view
 struct CmClusters {
@@ -603,8 +644,8 @@ __global__ void k_cm_dec_counts(const uint32_t* __restrict__ s, const uint32_t* 
   const uint32_t nt = info[1], nrec = info[5];
   CmReader r{s + info[4], 0, info[3], false, 0};
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nrec; i += gridDim.x * blockDim.x) {
-    r.pos = s[CM_HDR + (i < nt ? i : i + 1)];
     r.bad = false;
+    r.seek(s[CM_HDR + (i < nt ? i : i + 1)]);
     cnt[i] = (uint32_t)(i < nt ? r.get(8) : r.eg(0));
     if (r.bad || cnt[i] > 0xFFFFFFu) {
       cnt[i] = 0;
@@ -615,7 +656,8 @@ __global__ void k_cm_dec_counts(const uint32_t* __restrict__ s, const uint32_t* 
 
 // Record i (a track for i < nt, else a row block) decoded from r at output
 // offset k; false if it is malformed or does not end at `end`.
-__device__ bool cm_decode_record(CmReader& r, uint32_t i, uint32_t nu, uint32_t nt, uint32_t nc,
+template <typename Reader>
+__device__ bool cm_decode_record(Reader& r, uint32_t i, uint32_t nu, uint32_t nt, uint32_t nc,
                                  uint32_t k, uint64_t end, int64_t b30, const int32_t* xfx,
                                  const CmDecOut& o) {
   bool bad = false;
@@ -723,9 +765,15 @@ __global__ __launch_bounds__(256) void k_cm_dec(const uint32_t* __restrict__ s,
       // from LDS when the record lies in the staged range (reads stop at its
       // end), else (a malformed directory) from the payload
       const bool in_lds = staged && start >= b0 && end <= b1;
-      CmReader r{in_lds ? stage[w] : pay, start, in_lds ? b1 : bits, false, in_lds ? w0 : 0};
-      if (!cm_decode_record(r, i, nu, nt, nc, off[i], end, b30, P->xfx, o))
-        latch(st, TPC_ERR_INPUT);
+      bool ok;
+      if (in_lds) {
+        CmReaderT<lds_u32*> r((lds_u32*)stage[w], start, b1, false, w0);
+        ok = cm_decode_record(r, i, nu, nt, nc, off[i], end, b30, P->xfx, o);
+      } else {
+        CmReader r(pay, start, bits, false, 0);
+        ok = cm_decode_record(r, i, nu, nt, nc, off[i], end, b30, P->xfx, o);
+      }
+      if (!ok) latch(st, TPC_ERR_INPUT);
     }
     // the wave's LDS reads are done before the next group overwrites it
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
