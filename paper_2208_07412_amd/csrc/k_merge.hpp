@@ -3,10 +3,11 @@
 //
 // A segment's two ends (innermost and outermost hit) carry their global
 // position, drift z and the tangent of the segment's outward fit there.  Ends
-// are binned by (frame, side, sector, 36 cm of drift); one lane per end tests
-// the ends of later segments in the 5 sectors x 3 drift bins around it with
-// the joining rule (every joinable pair has ends within 35 cm in drift and
-// 30 cm in the bending plane, so the cells hold all candidates), and joins
+// are binned by (frame, side, 30.5 cm squares of the bending plane, 36 cm of
+// drift); one lane per end tests the ends of later segments in the 3 x 3 x 3
+// cells around it with the joining rule (every joinable pair has ends within
+// 35 cm in drift and 30 cm in the bending plane, so the cells hold all
+// candidates), and joins
 // segments by a lock-free union-find that always hangs the larger root under
 // the smaller, so the final root of a component is its smallest segment
 // whatever the order of the unions.  The members of each component are then
@@ -30,6 +31,9 @@
 #define MG_C_LINE 1e-4
 #define MG_TIE 1e-9
 #define MG_ZBIN 36.0  // drift cell (cm), above MG_DZMAX
+#define MG_XYBIN 30.5  // bending-plane cell (cm), above MG_GAP with its tie band
+#define MG_XY0 260.0   // the cells cover [-MG_XY0, MG_XY0) in x and y (outer radius ~247 cm)
+#define MG_NXY 18      // cells per axis: ceil(2 MG_XY0 / MG_XYBIN)
 #define MG_FIT 12     // doubles per merged-track fit record
 
 struct MgSegs {  // per segment (track), device SoA
@@ -58,6 +62,15 @@ __device__ __forceinline__ double mg_wrap(double a) {
 __device__ __forceinline__ bool mg_cut(double v, double cut, bool& tie) {
   if (fabs(v - cut) <= MG_TIE * cut) tie = true;
   return v <= cut;
+}
+
+// Bending-plane cell index of a coordinate (clamped: a pair within MG_GAP
+// still falls in neighbouring cells).
+__device__ __forceinline__ uint32_t mg_xy_bin(double v) {
+  double b = floor((v + MG_XY0) / MG_XYBIN);
+  if (!(b >= 0.0)) b = 0.0;
+  if (b > MG_NXY - 1) b = MG_NXY - 1;
+  return (uint32_t)b;
 }
 
 // Per segment: frame-side, curvature, dip and the two ends; per end its cell.
@@ -118,7 +131,8 @@ __global__ void k_mg_segments(const uint32_t* __restrict__ crow, uint32_t n_ur,
       int64_t zb = (int64_t)floor((E[2] + 1.0) / MG_ZBIN);
       if (zb < 0) zb = 0;
       if (zb >= (int64_t)nzb) zb = nzb - 1;
-      const uint32_t cell = (fs * 18 + sector % 18) * nzb + (uint32_t)zb;
+      const uint32_t cell = ((fs * MG_NXY + mg_xy_bin(E[1])) * MG_NXY + mg_xy_bin(E[0])) * nzb +
+                            (uint32_t)zb;
       cell_of_end[2 * j + e] = cell;
       atomicAdd(&cell_cnt[cell], 1u);
     }
@@ -237,8 +251,8 @@ __device__ __forceinline__ void mg_pair_check(const MgSegs& S, const uint32_t* c
 }
 
 // One lane per end, ends taken in cell order (the lanes of a wave mostly
-// share their cell and so scan the same neighbour cells in step): the ends of
-// later segments in the 5 x 3 cells around it are gated on the packed drift z
+// share their cells and so scan the same neighbour cells in step): the ends of
+// later segments in the 3 x 3 x 3 cells around it are gated on the packed drift z
 // and position; the pairs that pass go to the wave's queue in LDS, and every
 // 64 of them are tested by the 64 lanes together (the full test is long and
 // few lanes pass a gate at a time).
@@ -261,26 +275,27 @@ __global__ __launch_bounds__(256) void k_mg_pairs(MgSegs S, uint32_t nzb,
        t0 += gridDim.x * blockDim.x) {  // uniform per wave
     const uint32_t t = t0 + lane;
     const bool have = t < total;
-    uint32_t A = 0, zb = 0, sec = 0, fs = 0;
+    uint32_t A = 0, zb = 0, ix = 0, iy = 0, fs = 0;
     double az = 0, ax = 0, ay = 0;
     if (have) {
       const uint32_t e = cell_ends[t];
       A = e >> 1;
       const uint32_t cell = cell_of_end[e];
       zb = cell % nzb;
-      sec = (cell / nzb) % 18;
-      fs = cell / nzb / 18;
+      ix = (cell / nzb) % MG_NXY;
+      iy = (cell / nzb / MG_NXY) % MG_NXY;
+      fs = cell / nzb / MG_NXY / MG_NXY;
       az = pk[3 * (size_t)t];
       ax = pk[3 * (size_t)t + 1];
       ay = pk[3 * (size_t)t + 2];
     }
     uint32_t qn = 0;  // queued pairs (the same in every lane)
-    for (int ci = 0; ci < 15; ++ci) {
-      const int ds = ci / 3 - 2, dz = ci % 3 - 1;
+    for (int ci = 0; ci < 27; ++ci) {
+      const int dy = ci / 9 - 1, dx = (ci / 3) % 3 - 1, dz = ci % 3 - 1;
       uint32_t k0 = 0, k1 = 0;
-      const int64_t z2 = (int64_t)zb + dz;
-      if (have && z2 >= 0 && z2 < (int64_t)nzb) {
-        const uint32_t c2 = (fs * 18 + (sec + 18 + ds) % 18) * nzb + (uint32_t)z2;
+      const int z2 = (int)zb + dz, x2 = (int)ix + dx, y2 = (int)iy + dy;
+      if (have && z2 >= 0 && z2 < (int)nzb && x2 >= 0 && x2 < MG_NXY && y2 >= 0 && y2 < MG_NXY) {
+        const uint32_t c2 = ((fs * MG_NXY + (uint32_t)y2) * MG_NXY + (uint32_t)x2) * nzb + (uint32_t)z2;
         k0 = cell_off[c2];
         k1 = cell_off[c2 + 1];
       }

@@ -149,7 +149,7 @@ uint64_t cm_records(const tpc_sizes& m) {
 // Drift cells of the merging grid per (frame-side, sector) and the cells.
 uint32_t mg_nzb(uint32_t n_time_bins) { return (uint32_t)((n_time_bins / 2.0 + 2.0) / MG_ZBIN) + 2; }
 uint64_t mg_cells(const tpc_sizes& m) {
-  return (uint64_t)((m.max_units + 35) / 36) * 2 * 18 * mg_nzb(m.max_time_bins) + 1;
+  return (uint64_t)((m.max_units + 35) / 36) * 2 * MG_NXY * MG_NXY * mg_nzb(m.max_time_bins) + 1;
 }
 
 Plan plan_for(const tpc_sizes& m) {
@@ -1006,7 +1006,7 @@ int tpc_merge_tracks(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, t
   const uint32_t hit_bound =
       tr->hit_capacity < c->max.max_clusters ? tr->hit_capacity : c->max.max_clusters;
   const uint32_t nzb = mg_nzb(cl->n_time_bins);
-  const uint32_t n_cells = ((cl->n_units + 35) / 36) * 2 * 18 * nzb;
+  const uint32_t n_cells = ((cl->n_units + 35) / 36) * 2 * MG_NXY * MG_NXY * nzb;
   const MgSegs S{c->mg_fs, c->mg_sector, c->mg_C, c->mg_tgl, c->mg_e};
   k_fill<uint32_t><<<grid_for(n_cells, 256, 4096), 256, 0, s>>>(c->mg_cnt, 0u, n_cells);
   k_fill<double><<<grid_for((uint64_t)out->capacity * TPC_MERGE_FIT, 256, 4096), 256, 0, s>>>(
