@@ -296,9 +296,13 @@ __device__ __forceinline__ void cm_cluster_put(CmWriter& b, uint16_t qt, uint16_
 
 // One track record: its length (write = false) or its bits (write = true).
 // Returns false if a hit lies below the model's row (latched by the caller).
+// res (optional, res_cap hits): the hits' two zigzag residuals, stored by the
+// sizing pass (WRITE false) and read back by the writing pass, which then
+// does not step the model again (the same values either way).
 template <bool WRITE>
 __device__ bool cm_track(const CmClusters& cl, const CmTracks& tr, uint32_t j, int64_t b30,
-                         const int32_t* xfx, uint64_t& bits, CmWriter* bw, uint32_t* hist) {
+                         const int32_t* xfx, uint64_t& bits, CmWriter* bw, uint32_t* hist,
+                         uint64_t* res, uint32_t res_cap) {
   uint32_t h0 = tr.hit_start[j], h1 = tr.hit_start[j + 1];
   if (h1 > tr.hit_cap) h1 = tr.hit_cap;
   if (h0 > h1) h0 = h1;
@@ -325,6 +329,7 @@ __device__ bool cm_track(const CmClusters& cl, const CmTracks& tr, uint32_t j, i
   }
   int prev = r0;
   bool ok = true;
+  const bool cached = res != nullptr && h1 <= res_cap;
   for (uint32_t h = h0; h < h1; ++h) {
     uint32_t c = tr.hits[h];
     if (c >= n_cl) {
@@ -337,9 +342,22 @@ __device__ bool cm_track(const CmClusters& cl, const CmTracks& tr, uint32_t j, i
     if (step < 0) ok = false;
     const uint64_t st = step < 0 ? 0 : (uint64_t)step;
     prev = r;
-    while (m.row < r) cm_step(m, xfx);
-    const int64_t dy = cm_q(cl.y[c]) - cm_q(m.Y), dz = cm_q(cl.z[c]) - cm_q(m.Z);
-    const uint64_t zy = cm_zig(dy), zz = cm_zig(dz);
+    int64_t dy = 0, dz = 0;
+    uint64_t zy, zz;
+    if (WRITE && cached) {
+      zy = res[2 * (size_t)h];
+      zz = res[2 * (size_t)h + 1];
+    } else {
+      while (m.row < r) cm_step(m, xfx);
+      dy = cm_q(cl.y[c]) - cm_q(m.Y);
+      dz = cm_q(cl.z[c]) - cm_q(m.Z);
+      zy = cm_zig(dy);
+      zz = cm_zig(dz);
+      if (!WRITE && cached) {
+        res[2 * (size_t)h] = zy;
+        res[2 * (size_t)h + 1] = zz;
+      }
+    }
     if (WRITE) {
       bw->eg(st, 0);
       bw->eg(zy, 2);
@@ -364,6 +382,7 @@ __global__ __launch_bounds__(256) void k_cm_track_bits(CmClusters cl, CmTracks t
                                                        const DevParams* __restrict__ P,
                                                        uint32_t* __restrict__ tbits,
                                                        uint32_t* __restrict__ hist_out,
+                                                       uint64_t* __restrict__ res, uint32_t res_cap,
                                                        DevStatus* st) {
   __shared__ uint32_t h[256];
   if (failed(st)) return;
@@ -372,7 +391,8 @@ __global__ __launch_bounds__(256) void k_cm_track_bits(CmClusters cl, CmTracks t
   const uint32_t n = scan_count(tr.n_dev, tr.cap);
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     uint64_t bits = 0;
-    if (!cm_track<false>(cl, tr, j, b30, P->xfx, bits, nullptr, hist_out ? h : nullptr))
+    if (!cm_track<false>(cl, tr, j, b30, P->xfx, bits, nullptr, hist_out ? h : nullptr, res,
+                         res_cap))
       latch(st, TPC_ERR_INPUT);
     tbits[j] = (uint32_t)(bits < 0xFFFFFFFFull ? bits : 0xFFFFFFFFull);
   }
@@ -543,7 +563,9 @@ __global__ void k_cm_clear(uint32_t* __restrict__ s, const uint32_t* info, const
 __global__ __launch_bounds__(256) void k_cm_track_write(CmClusters cl, CmTracks tr, int64_t b30,
                                                         const DevParams* __restrict__ P,
                                                         uint32_t* __restrict__ s,
-                                                        const uint32_t* info, DevStatus* st) {
+                                                        const uint32_t* info,
+                                                        const uint64_t* __restrict__ res,
+                                                        uint32_t res_cap, DevStatus* st) {
   if (failed(st) || info[0] == 0) return;
   const uint32_t n = scan_count(tr.n_dev, tr.cap);
   uint32_t* payload = s + info[1];
@@ -552,7 +574,7 @@ __global__ __launch_bounds__(256) void k_cm_track_write(CmClusters cl, CmTracks 
     CmWriter w;
     w.init(payload, pw, s[CM_HDR + j]);
     uint64_t bits = 0;
-    cm_track<true>(cl, tr, j, b30, P->xfx, bits, &w, nullptr);
+    cm_track<true>(cl, tr, j, b30, P->xfx, bits, &w, nullptr, const_cast<uint64_t*>(res), res_cap);
     w.flush();
   }
 }

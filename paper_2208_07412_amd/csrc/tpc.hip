@@ -93,6 +93,7 @@ struct tpc_ctx {
   uint32_t* qc_part = nullptr;   // per-workgroup QC histograms
   uint32_t* zp_off = nullptr;    // output offset of each raw ZS page
   uint32_t *cm_a = nullptr, *cm_b = nullptr;  // compression: lengths / counts, offsets
+  uint64_t* cm_res = nullptr;  // compression: the hits' residual codes
   unsigned long long* cm_tot = nullptr;       // compression: bit totals
   uint32_t* cm_info = nullptr;                // compression: sizes of the stream
   // merging: per-segment ends, cells, union-find, member sort
@@ -128,7 +129,7 @@ struct Layout {
 
 struct Plan {
   size_t zblk, cblk, win, cl_list, crec, bsum, tot64, tot32, chain_len, cand, start_flag, f_hits, f_state, f_nhits, f_range, f_ok, f_pts, f_key, f_perm, f_bins, f_krow, f_work, f_qnext, pos,
-      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, cm_a, cm_b, cm_tot, cm_info, mg_fs,
+      owner, nkept, r_par, r_cov, r_chi2, r_row, r_flags, trk_index, qc_part, zp_off, cm_a, cm_b, cm_res, cm_tot, cm_info, mg_fs,
       mg_cell, mg_cnt, mg_off, mg_cur, mg_ends, mg_parent, mg_key, mg_idx, mg_skey, mg_sidx,
       mg_sector, mg_C, mg_tgl, mg_e, mg_cs18, mg_pk, mg_hxy, hit_off, par, st, total;
   size_t bsum_cap;
@@ -207,6 +208,7 @@ Plan plan_for(const tpc_sizes& m) {
   p.zp_off = L.add<uint32_t>(max_pages(m) + 1);
   p.cm_a = L.add<uint32_t>(cm_records(m));
   p.cm_b = L.add<uint32_t>(cm_records(m));
+  p.cm_res = L.add<unsigned long long>(2 * mc);  // two residual codes per hit
   p.cm_tot = L.add<unsigned long long>(2);
   p.cm_info = L.add<uint32_t>(8);
   p.mg_fs = L.add<uint32_t>(mt);
@@ -837,6 +839,7 @@ int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* h
   c->zp_off = (uint32_t*)(base + pl.zp_off);
   c->cm_a = (uint32_t*)(base + pl.cm_a);
   c->cm_b = (uint32_t*)(base + pl.cm_b);
+  c->cm_res = (uint64_t*)(base + pl.cm_res);
   c->cm_tot = (unsigned long long*)(base + pl.cm_tot);
   c->cm_info = (uint32_t*)(base + pl.cm_info);
   c->mg_fs = (uint32_t*)(base + pl.mg_fs);
@@ -941,7 +944,10 @@ int tpc_compress(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, tpc_c
   const int64_t b30 = cm_b30(c);
   if (out->res_hist) k_fill<uint32_t><<<1, 256, 0, s>>>(out->res_hist, 0u, 256);
   const uint32_t gt = grid_for(tr->capacity, 256, 4096);
-  k_cm_track_bits<<<gt, 256, 0, s>>>(cv, tv, b30, c->d_par, c->cm_a, out->res_hist, c->d_st);
+  // the hits' residual codes, cached between the two track passes
+  const uint32_t res_cap = (uint32_t)c->max.max_clusters;
+  k_cm_track_bits<<<gt, 256, 0, s>>>(cv, tv, b30, c->d_par, c->cm_a, out->res_hist, c->cm_res,
+                                     res_cap, c->d_st);
   k_cm_row_bits<<<grid_for(n_ur, 4, 4096), 256, 0, s>>>(cv, tr->cluster_track, c->cm_b, c->d_st);
   run_scan<unsigned long long>(c, CmGetU32{c->cm_a}, CmEmitTrack{out->stream, out->capacity},
                                tr->n_tracks, tr->capacity, c->cm_tot, (uint32_t*)nullptr);
@@ -953,7 +959,8 @@ int tpc_compress(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, tpc_c
                               tr->hit_start, cl->n_clusters, cl->capacity, c->cm_tot,
                               out->n_words, c->cm_info, c->d_st);
   k_cm_clear<<<grid_for(out->capacity, 256, 2048), 256, 0, s>>>(out->stream, c->cm_info, c->d_st);
-  k_cm_track_write<<<gt, 256, 0, s>>>(cv, tv, b30, c->d_par, out->stream, c->cm_info, c->d_st);
+  k_cm_track_write<<<gt, 256, 0, s>>>(cv, tv, b30, c->d_par, out->stream, c->cm_info, c->cm_res,
+                                      res_cap, c->d_st);
   k_cm_row_write<<<grid_for(n_ur, 4, 4096), 256, 0, s>>>(cv, tr->cluster_track, out->stream,
                                                          tr->n_tracks, tr->capacity, c->cm_info,
                                                          c->d_st);
