@@ -359,6 +359,14 @@ struct ClusterRec {
 // finds the up codes and peaks, accumulates each peak's moments in LDS
 // (batches of CL_SLOTS peaks), writes one raw record per peak and the
 // window's peak count.
+// The peak passes run one wave per workgroup: the LDS operations of a wave
+// complete in order, so ordering them needs only a compiler fence, not a
+// workgroup barrier (which would also wait for every outstanding LDS access).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int W>
 struct PeaksLds {
   __attribute__((aligned(16))) uint16_t tile[(W + 2 * CL_HALO) * CL_TP];
@@ -392,7 +400,7 @@ __device__ __forceinline__ void peaks_chunk(const ZsArgs& in, const uint32_t* __
   WinRange R = window_range<W>(zb, nblk, w0, rs0, rs1);
   SampleRegs<PRE> cur, nxt;
   prefetch(in, R, cur);
-  __syncthreads();
+  wave_sync();
   for (int w = w0; w < w1; ++w) {
     const int tile_t0 = w * W - CL_HALO;
     scatter<ROWS>(tile, in, R, cur, tile_t0, np, true);
@@ -401,7 +409,7 @@ __device__ __forceinline__ void peaks_chunk(const ZsArgs& in, const uint32_t* __
       Rn = window_range<W>(zb, nblk, w + 1, rs0, rs1);
       prefetch(in, Rn, nxt);
     }
-    __syncthreads();
+    wave_sync();
     // Up codes of the samples within 3 bins of the core, written in place;
     // core peaks are ranked in sample order and the first CL_SLOTS get slots.
     uint32_t total = 0;
@@ -436,7 +444,7 @@ __device__ __forceinline__ void peaks_chunk(const ZsArgs& in, const uint32_t* __
         acc0[threadIdx.x] = 0;
         acc1[threadIdx.x] = 0;
       }
-      __syncthreads();
+      wave_sync();
       // every sample within two bins of the core adds itself to its peak;
       // the offset to the peak is the sum of the two chase steps
       for (uint32_t s0 = R.s_lo; s0 < R.s_hi; s0 += 64) {
@@ -472,7 +480,7 @@ __device__ __forceinline__ void peaks_chunk(const ZsArgs& in, const uint32_t* __
         atomicAdd(&acc0[slot], (unsigned long long)v0);
         atomicAdd(&acc1[slot], (unsigned long long)v1);
       }
-      __syncthreads();
+      wave_sync();
       if (threadIdx.x < nb) {
         // the batch's records; the peak leaves the batch
         const int c = pk_cell[threadIdx.x];
@@ -491,7 +499,7 @@ __device__ __forceinline__ void peaks_chunk(const ZsArgs& in, const uint32_t* __
       done += nb;
       nb = min(total - done, (uint32_t)CL_SLOTS);
       if (nb == 0) break;
-      __syncthreads();
+      wave_sync();
       // slots for the next batch of core peaks, in sample order
       uint32_t rank = 0;
       for (uint32_t s0 = R.s_lo; s0 < R.c_hi; s0 += 64) {
@@ -511,7 +519,7 @@ __device__ __forceinline__ void peaks_chunk(const ZsArgs& in, const uint32_t* __
     }
     if (threadIdx.x == 0) win_cnt[(size_t)ur * nwin + w] = total;
     if (sample_label) {
-      __syncthreads();
+      wave_sync();
       for (uint32_t s = R.c_lo + threadIdx.x; s < R.c_hi; s += 64) {
         const uint32_t tp = ((uint32_t)in.time[s] << 16) | in.pad[s];
         const int lt = (int)(tp >> 16) - tile_t0;
@@ -525,9 +533,9 @@ __device__ __forceinline__ void peaks_chunk(const ZsArgs& in, const uint32_t* __
         sample_label[s] = lab;
       }
     }
-    __syncthreads();
+    wave_sync();
     scatter<ROWS>(tile, in, R, cur, tile_t0, np, false);
-    __syncthreads();
+    wave_sync();
     R = Rn;
     cur = nxt;
   }
@@ -567,7 +575,7 @@ __global__ __launch_bounds__(64) void k_cluster_peaks_list(ZsArgs in,
   for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
     peaks_chunk<W, K, PRE>(in, zblk, nblk, nwin, nchunk, n_ur, win_cnt, rec, sample_label, P,
                            uni(list[1 + i]), L);
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -698,7 +706,7 @@ __global__ __launch_bounds__(64) void k_cluster_stream(ZsArgs in, const uint32_t
   cc = cp;
   uint32_t nrank = 0, drank = 0;  // core peaks ranked / whose records are written
   bool handed_back = false;
-  __syncthreads();
+  wave_sync();
   for (;;) {
     // the ring holds the times [R, R + CS_RB): R is the lowest row still read
     // (the gather reads two bins below its front, rows below an uncleared
@@ -721,7 +729,7 @@ __global__ __launch_bounds__(64) void k_cluster_stream(ZsArgs in, const uint32_t
     // rows at or above R + CS_RB are not in the ring yet: a read there would
     // see an older time's cells
     const int Fp = min(cs_front(cp), R + CS_RB);
-    __syncthreads();
+    wave_sync();
     // ---- code
     uint32_t n_q;
     {
@@ -768,7 +776,7 @@ __global__ __launch_bounds__(64) void k_cluster_stream(ZsArgs in, const uint32_t
       if (take && live)
         tile[c] = (uint16_t)((code & 16) ? (a | CL_PEAK | (pk ? slot_bits((int)slot) : CL_NOSLOT))
                                          : (a | ((code & 15) << 10)));
-      __syncthreads();
+      wave_sync();
       if (take && pk) {
         const uint32_t r = rank - wfirst[wi];
         ridx[slot] = clo[wi] + r;
@@ -778,7 +786,7 @@ __global__ __launch_bounds__(64) void k_cluster_stream(ZsArgs in, const uint32_t
       cs_take(cq, n_q, in, s_hi);
     }
     const int Fq = min(cs_front(cq), R + CS_RB);
-    __syncthreads();
+    wave_sync();
     // ---- gather
     uint32_t n_g;
     {
@@ -819,7 +827,7 @@ __global__ __launch_bounds__(64) void k_cluster_stream(ZsArgs in, const uint32_t
       cs_take(cg, n_g, in, s_hi);
     }
     const int Fg = cs_front(cg);
-    __syncthreads();
+    wave_sync();
     // ---- records of the peaks the gather has passed (ranks are in time order)
     uint32_t n_r;
     {
@@ -849,7 +857,7 @@ __global__ __launch_bounds__(64) void k_cluster_stream(ZsArgs in, const uint32_t
       if (lane < n_c && t >= T0 - 3 && t < T1 + 3 && p < np) tile[cs_cell(t, p)] = 0;
       cs_take(cc, n_c, in, s_hi);
     }
-    __syncthreads();
+    wave_sync();
     if (cg.x >= s_hi && drank == nrank) break;
     if (n_p + n_q + n_g + n_r + n_c == 0) {  // no progress: not sorted
       handed_back = true;
