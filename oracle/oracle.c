@@ -1180,6 +1180,8 @@ int oracle_decode_zs_pages(const uint32_t* pages, int64_t n_pages, int32_t n_uni
  * whatever the model predicts.  Returns -3 for input the format cannot hold
  * (a track hit below the row of its parameters). */
 #define CM_MAGIC 0x54434D31u
+#define CM_VERSION 2u
+#define CM_CHUNK 64 /* clusters on no track per independently decodable chunk of a row */
 #define CM_HDR 8
 
 static int64_t cm_q(int64_t v) { return floor_div(v + 256, 512); } /* 2^-7 cm steps */
@@ -1356,7 +1358,7 @@ int oracle_compress(const oparams* par, int32_t n_units, const uint32_t* crow_st
       if (need > out_cap) return -2;
       for (int64_t i = 0; i < need; ++i) out[i] = 0;
       out[0] = CM_MAGIC;
-      out[1] = 1;
+      out[1] = CM_VERSION;
       out[2] = (uint32_t)n_units;
       out[3] = (uint32_t)n_tracks;
       out[4] = (uint32_t)nc;
@@ -1421,15 +1423,27 @@ int oracle_compress(const oparams* par, int32_t n_units, const uint32_t* crow_st
       int64_t n = 0;
       for (int64_t c = crow_start[ur]; c < (int64_t)crow_start[ur + 1]; ++c) n += cluster_track[c] < 0;
       cm_eg(&b, (uint64_t)n, 0);
-      int64_t zprev = 0, first = 1;
+      /* the row's clusters in chunks of CM_CHUNK; chunks 1.. start where the
+         32-bit fields after the count say (bit offsets from the end of the
+         fields), each with its z coded whole */
+      const int64_t n_chunks = (n + CM_CHUNK - 1) / CM_CHUNK;
+      const int64_t fields = b.pos;
+      for (int64_t k = 1; k < n_chunks; ++k) cm_put(&b, 0, 32);
+      const int64_t chunk0 = b.pos;
+      int64_t zprev = 0, i = 0;
       for (int64_t c = crow_start[ur]; c < (int64_t)crow_start[ur + 1]; ++c) {
         if (cluster_track[c] >= 0) continue;
+        if (i > 0 && i % CM_CHUNK == 0 && pass) { /* this chunk's offset field */
+          cm_writer f = b;
+          f.pos = fields + 32 * (i / CM_CHUNK - 1);
+          cm_put(&f, (uint64_t)(b.pos - chunk0), 32);
+        }
         const int64_t zq = cm_q(z_fx[c]);
         cm_eg(&b, cm_zig(cm_q(y_fx[c])), 10);
-        if (first) cm_eg(&b, cm_zig(zq), 12);
+        if (i % CM_CHUNK == 0) cm_eg(&b, cm_zig(zq), 12);
         else cm_eg(&b, cm_zig(zq - zprev), 6);
-        first = 0;
         zprev = zq;
+        ++i;
         cm_cluster_fields(&b, qtot[c], qmax[c], flags[c]);
       }
     }
@@ -1449,7 +1463,7 @@ int64_t oracle_decompress(const oparams* par, const uint32_t* in, int64_t n_word
                           uint16_t* unit, uint8_t* row, int32_t* y_fx, int32_t* z_fx,
                           uint16_t* qtot, uint16_t* qmax, uint8_t* flags, int32_t* track) {
   geometry_init();
-  if (n_words < CM_HDR || in[0] != CM_MAGIC || in[1] != 1 || in[7] != 0) return -3;
+  if (n_words < CM_HDR || in[0] != CM_MAGIC || in[1] != CM_VERSION || in[7] != 0) return -3;
   const int64_t n_units = in[2], n_tracks = in[3], nc = in[4];
   const int64_t n_ur = n_units * NROW;
   const int64_t dir = CM_HDR + (n_tracks + 1) + (n_ur + 1);
@@ -1491,11 +1505,20 @@ int64_t oracle_decompress(const oparams* par, const uint32_t* in, int64_t n_word
     if (r.pos != in[CM_HDR + n_tracks + 1 + ur]) return -3;
     if (ur == 0 && r.pos != in[CM_HDR + n_tracks]) return -3;
     const int64_t n = cm_geteg(&r, 0);
+    const int64_t n_chunks = (n + CM_CHUNK - 1) / CM_CHUNK;
+    const int64_t fields = r.pos;
+    r.pos += 32 * (n_chunks > 1 ? n_chunks - 1 : 0);
+    const int64_t chunk0 = r.pos;
     int64_t zprev = 0;
     for (int64_t i = 0; i < n; ++i) {
       if (k >= nc) return -3;
+      if (i > 0 && i % CM_CHUNK == 0) { /* a chunk starts where its field says */
+        cm_reader f = r;
+        f.pos = fields + 32 * (i / CM_CHUNK - 1);
+        if (chunk0 + (int64_t)cm_get(&f, 32) != r.pos || f.bad) return -3;
+      }
       const int64_t yq = cm_unzig(cm_geteg(&r, 10));
-      const int64_t zq = i == 0 ? cm_unzig(cm_geteg(&r, 12)) : zprev + cm_unzig(cm_geteg(&r, 6));
+      const int64_t zq = i % CM_CHUNK == 0 ? cm_unzig(cm_geteg(&r, 12)) : zprev + cm_unzig(cm_geteg(&r, 6));
       zprev = zq;
       unit[k] = (uint16_t)(ur / NROW);
       row[k] = (uint8_t)(ur % NROW);

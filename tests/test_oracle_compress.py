@@ -12,6 +12,9 @@ tpc_compress).  The oracle's encoder and decoder are pinned by
 * the integer helix model against the exact FP64 helix (circle in the
   bending plane, drift length summed over the row chords) for pT from 0.1 to
   10 GeV/c, both charges and both drift directions;
+* a row of 150 clusters on no track read with an independent bit reader:
+  its chunk offset fields, each chunk starting with its z coded whole, and a
+  corrupted field rejected;
 * the error rules (stream too large for its buffer, a hit below the model's
   row, malformed streams).
 """
@@ -139,6 +142,90 @@ def test_round_trip_generated(which):
     assert c["hist"][:128].sum() == n_hits == c["hist"][128:].sum()
     print(f"{which}: {nc} clusters ({n_hits} on tracks) in {4 * c['n_words']} bytes: "
           f"{4 * c['n_words'] / nc:.2f} B/cluster")
+
+
+class _Bits:
+    """Independent LSB-first reader of a stream's payload (for the pins)."""
+
+    def __init__(self, words, pos):
+        self.w, self.pos = [int(x) for x in words], pos
+
+    def get(self, n):
+        v = 0
+        for i in range(n):
+            v |= ((self.w[self.pos // 32] >> (self.pos % 32)) & 1) << i
+            self.pos += 1
+        return v
+
+    def eg(self, k):
+        n = 0
+        while self.get(1) == 0:
+            n += 1
+        qv = (1 << n) | self.get(n)
+        return ((qv - 1) << k) | self.get(k)
+
+
+def _unzig(v):
+    return v >> 1 if v % 2 == 0 else -((v + 1) >> 1)
+
+
+def test_row_chunks():
+    # One row with 150 clusters on no track: the count, then two 32-bit
+    # fields with the offsets of chunks 1 and 2 (clusters 64 and 128) from the
+    # end of the fields, and every chunk starts with its z coded whole
+    # (EG(12)), so each chunk decodes on its own.  Read with a reader of its
+    # own, not the oracle's.
+    n, r = 150, 7
+    rng = np.random.default_rng(5)
+    t = np.sort(rng.integers(0, 200, n))
+    cl_y = rng.integers(-2_000_000, 2_000_000, n).astype(np.int32)
+    cl_z = (t * 32768 + rng.integers(0, 32768, n)).astype(np.int32)
+    crow = np.zeros(NROW + 1, np.uint32)
+    crow[r + 1:] = n
+    clusters = dict(crow_start=crow, y_fx=cl_y, z_fx=cl_z,
+                    qtot=rng.integers(1, 3000, n).astype(np.uint16),
+                    qmax=rng.integers(1, 1023, n).astype(np.uint16),
+                    flags=rng.integers(0, 4, n).astype(np.uint8))
+    tracks = dict(par=np.zeros((0, 5), np.float32), row=np.zeros(0, np.uint8),
+                  z_anchor=np.zeros(0, np.int32), hit_start=np.zeros(1, np.uint32),
+                  hits=np.zeros(0, np.uint32), cluster_track=np.full(n, -1, np.int32))
+    c = oracle.compress(clusters, tracks, 1)
+    assert c["status"] == 0
+    w = c["words"]
+    assert w[1] == 2  # the format with row chunks
+    dir0 = 8 + 1  # no tracks: one closing track offset
+    payload = 8 + 1 + NROW + 1
+    start = int(w[dir0 + r])
+    b = _Bits(w[payload:], start)
+    assert b.eg(0) == n
+    offs = [b.get(32), b.get(32)]
+    chunk0 = b.pos
+    # sequential decode of the whole row
+    seq = []
+    zprev = 0
+    for i in range(n):
+        if i % 64 == 0:
+            assert i == 0 or b.pos == chunk0 + offs[i // 64 - 1]
+        yq = _unzig(b.eg(10))
+        zq = _unzig(b.eg(12)) if i % 64 == 0 else zprev + _unzig(b.eg(6))
+        zprev = zq
+        seq.append((yq, zq, b.eg(6), b.eg(5), b.get(2)))
+    assert b.pos == int(w[dir0 + r + 1])
+    assert [s[0] for s in seq] == q(cl_y).tolist() and [s[1] for s in seq] == q(cl_z).tolist()
+    assert [s[2] for s in seq] == clusters["qtot"].tolist()
+    # each chunk on its own from its field
+    for k in (1, 2):
+        bk = _Bits(w[payload:], chunk0 + offs[k - 1])
+        assert _unzig(bk.eg(10)) == q(cl_y[64 * k])
+        assert _unzig(bk.eg(12)) == q(cl_z[64 * k])
+    d = oracle.decompress(w)
+    assert d["status"] == 0 and len(d["y_fx"]) == n
+    assert np.array_equal(d["y_fx"], q(cl_y) * 512) and np.array_equal(d["z_fx"], q(cl_z) * 512)
+    # a wrong offset field is a malformed stream
+    bad = w.copy()
+    pos = payload * 32 + start + 1 + 2 * 8 + 1  # inside the first field (EG(0) of 150 is 15 bits)
+    bad[pos // 32] ^= 1 << (pos % 32)
+    assert oracle.decompress(bad)["status"] == -3
 
 
 def _exact_model(par, z_anchor, row0, rows, xr):
