@@ -364,20 +364,25 @@ int tpc_qc_histograms_noalloc(const tpc_clusters* cl, const tpc_tracks* tr, uint
  *              with q = (v >> k) + 1 and n = floor(log2 q): n zero bits, a one,
  *              the n low bits of q, the k low bits of v; signed values are
  *              zigzag-mapped (v >= 0: 2v, else -2v - 1).
- *   stream     words 0-7: 0x54434D31, 1, n_units, n_tracks, n_clusters,
+ *   stream     words 0-7: 0x54434D31, 2 (format), n_units, n_tracks, n_clusters,
  *              hits on tracks, payload bits, 0; then n_tracks + 1 bit offsets
- *              of the track records (the last = end of the tracks), then
- *              n_units * 152 + 1 bit offsets of the row blocks (the last = end
- *              of the payload), then the payload words.
+ *              of the track records (the last = end of the tracks, equal
+ *              to the first row block's), then n_units * 152 + 1 bit offsets
+ *              of the row blocks (the last = end of the payload), then the
+ *              payload words.
  *   track      n_hits (8 bits), unit (16), r0 (8), Y, Z, S, T, K (32 each, two's
  *              complement); per hit in ascending row: EG(0) of the row step
  *              (r - r0 for the first hit, r - r_prev - 1 after), with the
  *              model stepped to r: EG(2) of zig(q(y) - q(Y)), EG(2) of
  *              zig(q(z) - q(Z)), then the cluster fields.
- *   row block  per (unit, row): EG(0) of the number of clusters on no track,
- *              then each in canonical order: EG(10) of zig(q(y)), EG(12) of
- *              zig(q(z)) for the first, EG(6) of zig(q(z) - q(z_prev)) after,
- *              then the cluster fields.
+ *   row block  per (unit, row): EG(0) of the number n of clusters on no
+ *              track; they form m = ceil(n / 64) chunks of 64 (the last
+ *              shorter); m - 1 fields of 32 bits give the bit offsets of
+ *              chunks 1..m-1 from the end of these fields (where chunk 0
+ *              starts); then the clusters in canonical order: EG(10) of
+ *              zig(q(y)), EG(12) of zig(q(z)) for the first of a chunk, EG(6)
+ *              of zig(q(z) - q(z_prev)) after, then the cluster fields.  Each
+ *              chunk decodes on its own; a row of at most 64 has no field.
  *   cluster    EG(6) of qtot, EG(5) of qmax, flags (2 bits).
  * Decoding gives every cluster's quantised position (within 2^-8 cm of the
  * original), its charges, flags and track, whatever the model predicts. */

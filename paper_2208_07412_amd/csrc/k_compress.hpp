@@ -24,6 +24,9 @@
 
 #define CM_MAGIC 0x54434D31u
 #define CM_HDR 8
+#define CM_VERSION 2u
+#define CM_CHUNK 64  // clusters on no track per independently decodable chunk of a row
+#define CM_STAGE_WORDS 3072  // LDS words per wave for staging a record
 #define CM_QSHIFT 9  // positions quantised to 2^(9-16) cm
 
 // ---------------------------------------------------------------- arithmetic
@@ -424,9 +427,14 @@ __device__ uint64_t cm_row(const CmClusters& cl, const int32_t* __restrict__ ct,
   uint64_t off = base;
   const uint64_t cnt_len = cm_eg_len(cnt, 0);
   fn.count(cnt, off);
-  off += cnt_len;
+  // chunks of CM_CHUNK clusters: a 32-bit field per chunk after the first
+  // (its bit offset from the end of the fields), each chunk's first z whole
+  const uint32_t n_chunks = (cnt + CM_CHUNK - 1) / CM_CHUNK;
+  const uint64_t fields = off + cnt_len;
+  off = fields + 32ull * (n_chunks > 1 ? n_chunks - 1 : 0);
+  const uint64_t chunk0 = off;
   int64_t zprev = 0;
-  bool have_prev = false;
+  uint32_t rank0 = 0;  // clusters on no track in earlier batches
   for (uint32_t b = c0; b < c1; b += 64) {
     const uint32_t c = b + lane;
     const bool un = c < c1 && ct[c] < 0;
@@ -438,11 +446,12 @@ __device__ uint64_t cm_row(const CmClusters& cl, const int32_t* __restrict__ ct,
       yq = cm_q(cl.y[c]);
     }
     // the previous cluster on no track: the highest set lane below, else the
-    // carry from earlier chunks
+    // carry from earlier batches
     const uint64_t below = mask & ((1ull << lane) - 1);
+    const uint32_t rank = rank0 + (uint32_t)__popcll(below);
     const int src = below ? 63 - __builtin_clzll(below) : (int)lane;
     const int64_t zp_lane = __shfl(zq, src, 64);
-    const bool first = !below && !have_prev;
+    const bool first = rank % CM_CHUNK == 0;
     const int64_t zp = below ? zp_lane : zprev;
     uint64_t zcode = 0;
     int zk = 12;
@@ -459,12 +468,16 @@ __device__ uint64_t cm_row(const CmClusters& cl, const int32_t* __restrict__ ct,
     // exclusive prefix of the lengths in lane order
     uint64_t incl = wave_incl_scan((uint64_t)len);
     const uint64_t tot = __shfl(incl, 63, 64);
-    if (un) fn.cluster(c, off + incl - len, cm_zig(yq), zcode, zk);
+    if (un) {
+      const uint64_t at = off + incl - len;
+      if (first && rank > 0) fn.field(at - chunk0, fields + 32ull * (rank / CM_CHUNK - 1));
+      fn.cluster(c, at, cm_zig(yq), zcode, zk);
+    }
     off += tot;
     if (mask) {  // uniform
       const int last = 63 - __builtin_clzll(mask);
       zprev = __shfl(zq, last, 64);
-      have_prev = true;
+      rank0 += (uint32_t)__popcll(mask);
     }
   }
   return off - base;
@@ -472,6 +485,7 @@ __device__ uint64_t cm_row(const CmClusters& cl, const int32_t* __restrict__ ct,
 
 struct CmRowLen {
   __device__ void count(uint32_t, uint64_t) const {}
+  __device__ void field(uint64_t, uint64_t) const {}
   __device__ void cluster(uint32_t, uint64_t, uint64_t, uint64_t, int) const {}
 };
 
@@ -538,7 +552,7 @@ __global__ void k_cm_finish(uint32_t* __restrict__ s, uint32_t cap, uint32_t n_u
     return;
   }
   s[0] = CM_MAGIC;
-  s[1] = 1;
+  s[1] = CM_VERSION;
   s[2] = n_units;
   s[3] = n_tr;
   s[4] = scan_count(n_cl_dev, cl_cap);
@@ -591,6 +605,13 @@ struct CmRowPut {
       w.flush();
     }
   }
+  // a chunk's 32-bit offset field (its value < 2^32: payload offsets are)
+  __device__ void field(uint64_t v, uint64_t off) const {
+    CmWriter w;
+    w.init(payload, pw, off);
+    w.put((uint32_t)v, 32);
+    w.flush();
+  }
   __device__ void cluster(uint32_t c, uint64_t off, uint64_t yz, uint64_t zcode, int zk) const {
     CmWriter w;
     w.init(payload, pw, off);
@@ -634,14 +655,15 @@ __global__ void k_cm_dec_header(const uint32_t* __restrict__ s, uint32_t n_words
                                 uint32_t* info, DevStatus* st) {
   info[6] = 0;
   if (failed(st)) return;
-  if (n_words < CM_HDR || s[0] != CM_MAGIC || s[1] != 1 || s[7] != 0) {
+  if (n_words < CM_HDR || s[0] != CM_MAGIC || s[1] != CM_VERSION || s[7] != 0) {
     latch(st, TPC_ERR_INPUT);
     return;
   }
   const uint32_t nu = s[2], nt = s[3], nc = s[4], bits = s[6];
   const uint64_t dir = CM_HDR + (uint64_t)nt + 1 + (uint64_t)nu * NROW + 1;
   if (nu > max_units || nt > max_tracks || dir > n_words || bits > (n_words - dir) * 32ull ||
-      s[CM_HDR + nt + 1 + (uint64_t)nu * NROW] != bits || s[CM_HDR] != 0) {
+      s[CM_HDR + nt + 1 + (uint64_t)nu * NROW] != bits || s[CM_HDR] != 0 ||
+      s[CM_HDR + nt] != s[CM_HDR + nt + 1]) {  // the rows begin where the tracks end
     latch(st, TPC_ERR_INPUT);
     return;
   }
@@ -676,8 +698,8 @@ __global__ void k_cm_dec_counts(const uint32_t* __restrict__ s, const uint32_t* 
   }
 }
 
-// Record i (a track for i < nt, else a row block) decoded from r at output
-// offset k; false if it is malformed or does not end at `end`.
+// Track record i decoded from r at output offset k; false if it is malformed
+// or does not end at `end`.
 template <typename Reader>
 __device__ bool cm_decode_record(Reader& r, uint32_t i, uint32_t nu, uint32_t nt, uint32_t nc,
                                  uint32_t k, uint64_t end, int64_t b30, const int32_t* xfx,
@@ -716,60 +738,141 @@ __device__ bool cm_decode_record(Reader& r, uint32_t i, uint32_t nu, uint32_t nt
       o.flags[k] = (uint8_t)r.get(2);
       o.track[k] = (int32_t)i;
     }
-  } else {
-    const uint32_t ur = i - nt;
-    const uint64_t n = r.eg(0);
-    int64_t zprev = 0;
-    for (uint64_t c = 0; c < n && !r.bad; ++c, ++k) {
-      if (k >= nc || k >= o.capacity) {
-        bad = true;
-        break;
-      }
-      const int64_t yq = cm_unzig(r.eg(10));
-      const int64_t zq = c == 0 ? cm_unzig(r.eg(12)) : zprev + cm_unzig(r.eg(6));
-      zprev = zq;
-      o.unit[k] = (uint16_t)(ur / NROW);
-      o.row[k] = (uint8_t)(ur % NROW);
-      o.y[k] = (int32_t)(yq << CM_QSHIFT);
-      o.z[k] = (int32_t)(zq << CM_QSHIFT);
-      o.qtot[k] = (uint16_t)r.eg(6);
-      o.qmax[k] = (uint16_t)r.eg(5);
-      o.flags[k] = (uint8_t)r.get(2);
-      o.track[k] = -1;
-    }
   }
   return !(bad || r.bad || r.pos != end);
 }
 
-// Records decoded by waves: a wave takes `per_lane` = 1 record per lane (track
-// records) or one record per wave decoded by lane 0 (row blocks, which are
-// long); the records' bits are first copied into the wave's part of LDS when
-// they fit (a dependent chain of global reads is what bounds a sequential
-// decoder), else read from the payload.
-#define CM_STAGE_WORDS 3072
-template <bool TRACKS>
-__global__ __launch_bounds__(256) void k_cm_dec(const uint32_t* __restrict__ s,
-                                                const uint32_t* info,
-                                                const uint32_t* __restrict__ off,
-                                                const unsigned long long* total, int64_t b30,
-                                                const DevParams* __restrict__ P, CmDecOut o,
-                                                DevStatus* st) {
+// One chunk of row record ur (k-th, `count` clusters) from r, written at
+// output index k0 on; false if malformed or not ending at `end`.
+template <typename Reader>
+__device__ bool cm_decode_chunk(Reader& r, uint32_t ur, uint32_t count, uint32_t k0, uint32_t nc,
+                                uint64_t end, const CmDecOut& o) {
+  int64_t zprev = 0;
+  uint32_t k = k0;
+  for (uint32_t c = 0; c < count && !r.bad; ++c, ++k) {
+    if (k >= nc || k >= o.capacity) return false;
+    const int64_t yq = cm_unzig(r.eg(10));
+    const int64_t zq = c == 0 ? cm_unzig(r.eg(12)) : zprev + cm_unzig(r.eg(6));
+    zprev = zq;
+    o.unit[k] = (uint16_t)(ur / NROW);
+    o.row[k] = (uint8_t)(ur % NROW);
+    o.y[k] = (int32_t)(yq << CM_QSHIFT);
+    o.z[k] = (int32_t)(zq << CM_QSHIFT);
+    o.qtot[k] = (uint16_t)r.eg(6);
+    o.qmax[k] = (uint16_t)r.eg(5);
+    o.flags[k] = (uint8_t)r.get(2);
+    o.track[k] = -1;
+  }
+  return !(r.bad || r.pos != end);
+}
+
+// Row record ur at bits [b0, b1): the count and the chunk fields, then lane
+// l decodes chunks l, l + 64, ...; every chunk must end where the next one
+// (or the record) ends.  Reader: the row's bits (staged in LDS, or global).
+template <typename Reader>
+__device__ void cm_decode_row(Reader r, uint32_t ur, uint32_t k_row, uint32_t nc, uint64_t b0,
+                              uint64_t b1, const CmDecOut& o, DevStatus* st) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t n = r.eg(0);
+  if (r.bad || n > 0xFFFFFFu) {
+    if (lane == 0) latch(st, TPC_ERR_INPUT);
+    return;
+  }
+  const uint32_t m = ((uint32_t)n + CM_CHUNK - 1) / CM_CHUNK;
+  const uint64_t fields = r.pos;
+  const uint64_t chunk0 = fields + 32ull * (m > 1 ? m - 1 : 0);
+  if (m == 0) {
+    if (lane == 0 && r.pos != b1) latch(st, TPC_ERR_INPUT);
+    return;
+  }
+  if (chunk0 > b1) {
+    if (lane == 0) latch(st, TPC_ERR_INPUT);
+    return;
+  }
+  for (uint32_t k = lane; k < m; k += 64) {
+    uint64_t cs = chunk0, ce = b1;
+    if (k > 0) {
+      r.seek(fields + 32ull * (k - 1));
+      cs = chunk0 + r.get(32);
+    }
+    if (k + 1 < m) {
+      r.seek(fields + 32ull * k);
+      ce = chunk0 + r.get(32);
+    }
+    bool ok = !r.bad && cs <= ce && ce <= b1;
+    if (ok) {
+      const uint64_t end_save = r.end;
+      r.end = ce;  // reads stop at the chunk's end
+      r.seek(cs);
+      const uint32_t count = min((uint32_t)n - CM_CHUNK * k, (uint32_t)CM_CHUNK);
+      ok = cm_decode_chunk(r, ur, count, k_row + CM_CHUNK * k, nc, ce, o);
+      r.end = end_save;
+      r.bad = false;
+    }
+    if (!ok) latch(st, TPC_ERR_INPUT);
+  }
+}
+
+// Row records: one wave per record, its bits first copied into the wave's
+// part of LDS when they fit, one lane per chunk.
+__global__ __launch_bounds__(256) void k_cm_dec_rows(const uint32_t* __restrict__ s,
+                                                     const uint32_t* info,
+                                                     const uint32_t* __restrict__ off,
+                                                     const unsigned long long* total,
+                                                     CmDecOut o, DevStatus* st) {
   __shared__ uint32_t stage[4][CM_STAGE_WORDS];
   if (failed(st) || !info[6]) return;
-  const uint32_t nu = info[0], nt = info[1], nc = info[2], nrec = info[5];
+  const uint32_t nt = info[1], nc = info[2], nrec = info[5];
   const uint64_t bits = info[3];
   const uint32_t* pay = s + info[4];
-  if (!TRACKS && blockIdx.x == 0 && threadIdx.x == 0 && *total != nc) latch(st, TPC_ERR_INPUT);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && *total != nc) latch(st, TPC_ERR_INPUT);
   const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const uint32_t per = TRACKS ? 64 : 1;  // records per wave
-  const uint32_t first = TRACKS ? 0 : nt, last = TRACKS ? nt : nrec;
-  const uint32_t n_groups = (last - first + per - 1) / per;
+  for (uint32_t i = nt + blockIdx.x * 4 + w; i < nrec; i += gridDim.x * 4) {
+    uint64_t b0 = s[CM_HDR + i + 1], b1 = s[CM_HDR + i + 2];
+    if (b0 > bits) b0 = bits;
+    if (b1 > bits) b1 = bits;
+    if (b1 < b0) b1 = b0;
+    const uint64_t w0 = b0 >> 5, w1 = (b1 + 31) >> 5;
+    const bool staged = w1 - w0 <= CM_STAGE_WORDS;
+    if (staged) {
+      for (uint64_t k = lane; k < w1 - w0; k += 64) stage[w][k] = pay[w0 + k];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (staged) {
+      cm_decode_row(CmReaderT<lds_u32*>((lds_u32*)stage[w], b0, b1, false, w0), i - nt, off[i], nc,
+                    b0, b1, o, st);
+    } else {
+      cm_decode_row(CmReader(pay, b0, b1, false, 0), i - nt, off[i], nc, b0, b1, o, st);
+    }
+    // the wave's LDS reads are done before the next record overwrites it
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Track records: 64 per wave, one per lane; the wave's records' bits are
+// first copied into its part of LDS when they fit (a dependent chain of
+// global reads is what bounds a sequential decoder), else read from the
+// payload.
+__global__ __launch_bounds__(256) void k_cm_dec_tracks(const uint32_t* __restrict__ s,
+                                                       const uint32_t* info,
+                                                       const uint32_t* __restrict__ off,
+                                                       int64_t b30, const DevParams* __restrict__ P,
+                                                       CmDecOut o, DevStatus* st) {
+  __shared__ uint32_t stage[4][CM_STAGE_WORDS];
+  if (failed(st) || !info[6]) return;
+  const uint32_t nu = info[0], nt = info[1], nc = info[2];
+  const uint64_t bits = info[3];
+  const uint32_t* pay = s + info[4];
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t n_groups = (nt + 63) / 64;
   for (uint32_t g = blockIdx.x * 4 + w; g < n_groups; g += gridDim.x * 4) {
-    const uint32_t i0 = first + g * per;
-    const uint32_t i1 = min(i0 + per, last);
+    const uint32_t i0 = g * 64;
+    const uint32_t i1 = min(i0 + 64, nt);
     // the wave's bit range: from the first record's start to the last one's end
-    uint64_t b0 = s[CM_HDR + i0 + (TRACKS ? 0 : 1)];
-    uint64_t b1 = s[CM_HDR + (i1 - 1) + (TRACKS ? 1 : 2)];
+    uint64_t b0 = s[CM_HDR + i0];
+    uint64_t b1 = s[CM_HDR + i1];
     if (b0 > bits) b0 = bits;
     if (b1 > bits) b1 = bits;
     if (b1 < b0) b1 = b0;
@@ -781,9 +884,9 @@ __global__ __launch_bounds__(256) void k_cm_dec(const uint32_t* __restrict__ s,
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const uint32_t i = i0 + lane;
-    if (i < i1 && (TRACKS || lane == 0)) {
-      const uint64_t start = s[CM_HDR + i + (TRACKS ? 0 : 1)];
-      const uint64_t end = s[CM_HDR + i + (TRACKS ? 1 : 2)];
+    if (i < i1) {
+      const uint64_t start = s[CM_HDR + i];
+      const uint64_t end = s[CM_HDR + i + 1];
       // from LDS when the record lies in the staged range (reads stop at its
       // end), else (a malformed directory) from the payload
       const bool in_lds = staged && start >= b0 && end <= b1;

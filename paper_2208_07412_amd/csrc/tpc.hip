@@ -983,10 +983,10 @@ int tpc_decompress(tpc_ctx* c, const uint32_t* stream, uint32_t stream_words,
                                c->cm_tot, (uint32_t*)nullptr);
   const CmDecOut o{out->capacity, out->unit, out->row, out->y_fx, out->z_fx,
                    out->qtot, out->qmax, out->flags, out->track};
-  k_cm_dec<true><<<grid_for(c->max.max_tracklets, 256, 4096), 256, 0, s>>>(
-      stream, c->cm_info, c->cm_b, c->cm_tot, cm_b30(c), c->d_par, o, c->d_st);
-  k_cm_dec<false><<<grid_for((uint64_t)c->max.max_units * NROW, 4, 4096), 256, 0, s>>>(
-      stream, c->cm_info, c->cm_b, c->cm_tot, cm_b30(c), c->d_par, o, c->d_st);
+  k_cm_dec_tracks<<<grid_for(c->max.max_tracklets, 256, 4096), 256, 0, s>>>(
+      stream, c->cm_info, c->cm_b, cm_b30(c), c->d_par, o, c->d_st);
+  k_cm_dec_rows<<<grid_for((uint64_t)c->max.max_units * NROW, 4, 4096), 256, 0, s>>>(
+      stream, c->cm_info, c->cm_b, c->cm_tot, o, c->d_st);
   return launch_ok();
 }
 

@@ -21,7 +21,7 @@ import oracle
 import tpcsynth
 from paper_2208_07412_amd import tpc
 
-from test_oracle_compress import _expected, load_example
+from test_oracle_compress import NROW, _expected, chunk_frame, load_example
 
 pytestmark = pytest.mark.gpu
 
@@ -124,6 +124,33 @@ def test_full_slice_round_trip():
         print(f"slice: {n} clusters ({counts['n_hits']} on tracks) -> {4 * ch['n_words']} bytes "
               f"({4 * ch['n_words'] / n:.2f} B/cluster); {core:.3f} of the y residuals "
               f"within 8 steps (6.25e-2 cm)")
+    finally:
+        reco.close()
+
+
+@pytest.mark.parametrize("n", [64, 65, 150, 4200])
+def test_row_chunks(n):
+    # rows of one and of several chunks of 64 clusters on no track (4200:
+    # more chunks than a wave has lanes): the same stream as the oracle's,
+    # decoded chunk by chunk; a corrupted chunk offset is rejected
+    n, r, clusters, tracks = chunk_frame(n=n)
+    o = oracle.compress(clusters, tracks, 1)
+    assert o["status"] == 0
+    reco = tpc.Reco(1, 500, n, 16)
+    try:
+        g = _gpu_codec(clusters, tracks, 1, reco=reco)
+        assert g["status"] == 0 and g["dec_status"] == 0
+        assert np.array_equal(g["comp"]["words"], o["words"])
+        _same_decoded(g["dec"], oracle.decompress(o["words"]))
+        if n > 64:
+            bad = o["words"].copy()
+            eg_len = 2 * int(np.log2(n + 1)) + 1  # EG(0) of the count
+            pos = (8 + 1 + NROW + 1) * 32 + int(bad[8 + 1 + r]) + eg_len + 3  # in the first field
+            bad[pos // 32] ^= 1 << (pos % 32)
+            assert oracle.decompress(bad)["status"] == -3
+            dec = reco.alloc_decoded(n)
+            reco.decompress(torch.from_numpy(bad.view(np.int32)).cuda(), dec)
+            assert reco.sync(raise_on_error=False)["status"] == -3
     finally:
         reco.close()
 

@@ -169,26 +169,32 @@ def _unzig(v):
     return v >> 1 if v % 2 == 0 else -((v + 1) >> 1)
 
 
-def test_row_chunks():
-    # One row with 150 clusters on no track: the count, then two 32-bit
-    # fields with the offsets of chunks 1 and 2 (clusters 64 and 128) from the
-    # end of the fields, and every chunk starts with its z coded whole
-    # (EG(12)), so each chunk decodes on its own.  Read with a reader of its
-    # own, not the oracle's.
-    n, r = 150, 7
-    rng = np.random.default_rng(5)
+def chunk_frame(n=150, r=7, seed=5):
+    """One unit, n clusters on no track in row r (no tracks): a row of
+    several chunks."""
+    rng = np.random.default_rng(seed)
     t = np.sort(rng.integers(0, 200, n))
-    cl_y = rng.integers(-2_000_000, 2_000_000, n).astype(np.int32)
-    cl_z = (t * 32768 + rng.integers(0, 32768, n)).astype(np.int32)
     crow = np.zeros(NROW + 1, np.uint32)
     crow[r + 1:] = n
-    clusters = dict(crow_start=crow, y_fx=cl_y, z_fx=cl_z,
+    clusters = dict(crow_start=crow, y_fx=rng.integers(-2_000_000, 2_000_000, n).astype(np.int32),
+                    z_fx=(t * 32768 + rng.integers(0, 32768, n)).astype(np.int32),
                     qtot=rng.integers(1, 3000, n).astype(np.uint16),
                     qmax=rng.integers(1, 1023, n).astype(np.uint16),
                     flags=rng.integers(0, 4, n).astype(np.uint8))
     tracks = dict(par=np.zeros((0, 5), np.float32), row=np.zeros(0, np.uint8),
                   z_anchor=np.zeros(0, np.int32), hit_start=np.zeros(1, np.uint32),
                   hits=np.zeros(0, np.uint32), cluster_track=np.full(n, -1, np.int32))
+    return n, r, clusters, tracks
+
+
+def test_row_chunks():
+    # One row with 150 clusters on no track: the count, then two 32-bit
+    # fields with the offsets of chunks 1 and 2 (clusters 64 and 128) from the
+    # end of the fields, and every chunk starts with its z coded whole
+    # (EG(12)), so each chunk decodes on its own.  Read with a reader of its
+    # own, not the oracle's.
+    n, r, clusters, tracks = chunk_frame()
+    cl_y, cl_z = clusters["y_fx"], clusters["z_fx"]
     c = oracle.compress(clusters, tracks, 1)
     assert c["status"] == 0
     w = c["words"]
