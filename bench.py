@@ -668,9 +668,10 @@ def main():
     # time, adc) and a 32-byte cluster record per cluster it produces
     peak_bytes = 6 * ns + 32 * nc
     ach = peak_bytes / (stages["cluster_peaks"] / 1e3) / 1e9
+    kbase = {0: "k_cluster_peaks", 1: "k_cluster_stream", 2: "k_cluster_peaks_mw"}[tn["cl_mode"]]
     kname = (f"void k_cluster_stream<{tn['cl_window']}, {tn['cl_chunk']}>" if tn["cl_mode"] == 1 else
-             f"void k_cluster_peaks<{tn['cl_window']}, {tn['cl_chunk']},")
-    roof_peaks = dict(bound="hbm", kernel="k_cluster_stream" if tn["cl_mode"] == 1 else "k_cluster_peaks",
+             f"void {kbase}<{tn['cl_window']}, {tn['cl_chunk']},")
+    roof_peaks = dict(bound="hbm", kernel=kbase,
                       achieved=ach, peak=HBM_PEAK_GBS,
                       unit="GB/s", frac=ach / HBM_PEAK_GBS,
                       traffic=pmc_traffic(KERNEL_SOURCES["cluster_peaks"], "cluster_peaks", kname),

@@ -506,7 +506,8 @@ const char* tpc_profile_stage_name(int stage);
 const char* tpc_status_string(int status);
 
 /* Launch shapes (performance only: every choice gives the same results).
- * cl_window: clusterizer window in time bins, 8, 16, 20, 24 or 32;
+ * cl_window: clusterizer window in time bins, 8, 16, 20, 24 or 32 (24 or
+ * 32 in cl_mode 2);
  * cl_chunk: windows walked by one workgroup, 4, 8 or 16 (8 only for windows
  * of 20 and 24 bins); follow_block: threads per workgroup
  * of the following kernel, 64, 128 or 256; follow_mode: 0 one launch per
@@ -522,7 +523,9 @@ const char* tpc_status_string(int status);
  * clusterizer's peak pass per window (each window with its own halo of time
  * bins), 1 per chunk of cl_chunk windows as one stream of samples through a
  * ring of 32 time bins, handing chunks whose live peaks exceed its 31 moment
- * slots to the per-window pass.  tpc_set_tuning rejects
+ * slots to the per-window pass; 2 per window as 0, with two waves sharing
+ * each window's tile (twice the waves per compute unit for the same LDS,
+ * at the cost of a workgroup barrier per phase).  tpc_set_tuning rejects
  * other values with TPC_ERR_ARG and leaves
  * the context unchanged; it takes effect at the next call (a captured graph
  * keeps the shapes it was captured with). */

@@ -15,7 +15,8 @@ from typing import Dict, List, Tuple
 # (window, windows per workgroup, mode): mode 0 per window, 1 streamed per chunk
 CLUSTER_SHAPES: List[Tuple[int, int, int]] = [
     (8, 4, 0), (8, 8, 0), (8, 16, 0), (16, 4, 0), (16, 8, 0), (16, 16, 0), (20, 8, 0), (24, 8, 0),
-    (32, 4, 0), (32, 8, 0), (32, 16, 0), (16, 16, 1), (24, 8, 1), (32, 16, 1)]
+    (32, 4, 0), (32, 8, 0), (32, 16, 0), (16, 16, 1), (24, 8, 1), (32, 16, 1),
+    (24, 8, 2), (32, 4, 2), (32, 8, 2), (32, 16, 2)]
 FOLLOW_SHAPES: List[Tuple[int, int]] = [(fb, fm) for fm in (0, 1, 2) for fb in (64, 128, 256)]
 CLUSTER_STAGES = ("sample_index", "cluster_peaks", "cluster_scan", "cluster_output")
 FOLLOW_STAGES = ("following",)

@@ -16,6 +16,10 @@
 #include "common.hpp"
 
 #define CL_HALO 4    // time bins loaded on each side of a window
+// time bins kept in the shared-window tile on each side of a window: a
+// sample reaches a core peak in two uphill steps only from within 2 bins of
+// the core, so up codes are needed there and ADCs one bin further out
+#define CL_TH 3
 #define CL_BSHIFT 2  // the sample index has one entry per 4 time bins
 #define CL_TP 142    // tile row stride: pad p is stored in column p + 2
 
@@ -577,6 +581,301 @@ __global__ __launch_bounds__(64) void k_cluster_peaks_list(ZsArgs in,
                            uni(list[1 + i]), L);
     wave_sync();
   }
+}
+
+// ------------------------------------------------------------ shared-tile pass
+// The per-window pass is bound by the latency of its dependent LDS and memory
+// steps rather than by issue: its time follows the number of windows in
+// flight per compute unit, which the tile's LDS limits (one tile per wave).
+// Here NW waves (the library launches two) share the tile of one window of W
+// bins: each wave takes every NW-th 64-sample step of the window, so a
+// compute unit holds NW times as many waves for the same tile, and longer
+// windows recompute less halo per core sample.  The phases of a window are
+// ordered by workgroup barriers (four per window when one moment batch
+// suffices), whose waits take back most of what the extra waves gain.  The
+// results are those of the per-window pass.
+//
+// Tile cell: ADC in bits 0-9; v = bits 10-15 is a non-peak's up code
+// (v <= 10) or, for a peak, MW_V0 + its moment slot (v <= 61); v = MW_PEND
+// marks a core peak still waiting for a slot, v = MW_NONE a peak with no
+// record to write here (outside the core, or already written).  Each wave
+// owns MW_SW(NW) slots and hands them out in its own sample order, so no slot
+// counter is shared.
+#define MW_V0 11
+#define MW_PEND 62
+#define MW_NONE 63
+#define MW_SW(NW) (51 / (NW))  // slots per wave (NW * MW_SW <= 51)
+// 64-sample steps of a window (core and halo) that a valid input can fill:
+// at most one sample per cell, at most 138 pads
+#define MW_GROUPS(W) ((((W) + 2 * CL_HALO) * (CL_TP - 4) + 63) / 64)
+
+__device__ __forceinline__ int mw_code(int cell) {
+  const int v = cell >> 10;
+  return v <= 10 ? v : 5;
+}
+__device__ __forceinline__ int mw_cell(int a, int v) { return a | (v << 10); }
+
+template <int W, int NW>
+struct PeaksLdsMw {
+  __attribute__((aligned(16))) uint16_t tile[(W + 2 * CL_TH) * CL_TP];
+  unsigned long long acc0[NW * MW_SW(NW)], acc1[NW * MW_SW(NW)];
+  uint32_t grp[MW_GROUPS(W) + 1];  // core peaks per step, then their exclusive prefix
+  uint16_t pk_cell[NW * MW_SW(NW)];
+  uint16_t pk_gi[NW * MW_SW(NW)];  // step << 6 | rank within the step
+  uint16_t pk_a[NW * MW_SW(NW)];   // the peak's ADC
+  uint32_t wcnt[NW];               // slots used by each wave in the batch
+  uint32_t total;
+};
+
+template <int PRE, int NT>
+__device__ __forceinline__ void prefetch_mw(const ZsArgs& in, const WinRange& R,
+                                            SampleRegs<PRE>& S) {
+#pragma unroll
+  for (int j = 0; j < PRE; ++j) {
+    const uint32_t s = R.s_lo + threadIdx.x + j * NT;
+    if (s < R.s_hi) {
+      S.tp[j] = ((uint32_t)in.time[s] << 16) | in.pad[s];
+      S.a[j] = in.adc[s];
+    } else {
+      S.tp[j] = 0xFFFFFFFFu;
+      S.a[j] = 0;
+    }
+  }
+}
+
+template <int ROWS, int PRE, int NT>
+__device__ __forceinline__ void scatter_mw(uint16_t* tile, const ZsArgs& in, const WinRange& R,
+                                           const SampleRegs<PRE>& S, int tile_t0, int np,
+                                           bool place) {
+#pragma unroll
+  for (int j = 0; j < PRE; ++j) {
+    const int c = cell_of<ROWS>(S.tp[j], tile_t0, np);
+    if (c >= 0) tile[c] = place ? (uint16_t)(S.a[j] & 0x3FF) : 0;
+  }
+  for (uint32_t s = R.s_lo + PRE * NT + threadIdx.x; s < R.s_hi; s += NT) {
+    const uint32_t tp = ((uint32_t)in.time[s] << 16) | in.pad[s];
+    const int c = cell_of<ROWS>(tp, tile_t0, np);
+    if (c >= 0) tile[c] = place ? (uint16_t)(in.adc[s] & 0x3FF) : 0;
+  }
+}
+
+template <int W, int K, int NW, int PRE>
+__device__ __forceinline__ void peaks_chunk_mw(const ZsArgs& in, const uint32_t* __restrict__ zblk,
+                                               uint32_t nblk, uint32_t nwin, uint32_t nchunk,
+                                               uint32_t n_ur, uint32_t* __restrict__ win_cnt,
+                                               ClusterRec* __restrict__ rec,
+                                               int32_t* __restrict__ sample_label,
+                                               const DevParams* __restrict__ P, DevStatus* st,
+                                               uint32_t logical, PeaksLdsMw<W, NW>& L) {
+  constexpr int ROWS = W + 2 * CL_TH, NT = 64 * NW, SW = MW_SW(NW);
+  uint16_t* tile = L.tile;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint32_t ur = logical / nchunk, chunk = logical % nchunk;
+  if (ur >= n_ur) return;
+  const int np = uni(P->np[ur % NROW]), qmin = uni(P->qmax_min);
+  const uint32_t* zb = zblk + (size_t)ur * (nblk + 1);
+  uint32_t rs0 = uni(zb[0]), rs1 = uni(zb[nblk]);
+  if (rs1 > in.n_samples) rs1 = in.n_samples;
+  if (rs0 > rs1) rs0 = rs1;
+  const int w0 = chunk * K;
+  const int w1 = min((int)nwin, w0 + K);
+  for (int i = threadIdx.x; i < ROWS * CL_TP / 8; i += NT)
+    reinterpret_cast<uint4*>(tile)[i] = make_uint4(0, 0, 0, 0);
+  for (int i = ROWS * CL_TP / 8 * 8 + threadIdx.x; i < ROWS * CL_TP; i += NT) tile[i] = 0;
+  if (threadIdx.x < NW * SW) {
+    L.acc0[threadIdx.x] = 0;
+    L.acc1[threadIdx.x] = 0;
+  }
+  WinRange R = window_range<W>(zb, nblk, w0, rs0, rs1);
+  SampleRegs<PRE> cur, nxt;
+  prefetch_mw<PRE, NT>(in, R, cur);
+  __syncthreads();
+  for (int w = w0; w < w1; ++w) {
+    const int tile_t0 = w * W - CL_TH;
+    scatter_mw<ROWS, PRE, NT>(tile, in, R, cur, tile_t0, np, true);
+    WinRange Rn = R;
+    if (w + 1 < w1) {
+      Rn = window_range<W>(zb, nblk, w + 1, rs0, rs1);
+      prefetch_mw<PRE, NT>(in, Rn, nxt);
+    }
+    __syncthreads();
+    // more samples than cells: not a valid input (uniform over the workgroup)
+    const bool fits = R.s_hi - R.s_lo <= (uint32_t)MW_GROUPS(W) * 64u;
+    if (!fits && threadIdx.x == 0) latch(st, TPC_ERR_INPUT);
+    uint32_t total = 0;
+    if (fits) {
+      // up codes of the samples within 2 bins of the core, in place; each
+      // wave gives its core peaks its own slots in sample order
+      uint32_t used = 0;
+      uint32_t j = 0;
+      for (uint32_t s0 = R.s_lo + wave * 64; s0 < R.s_hi; s0 += NT, ++j) {
+        const uint32_t s = s0 + lane;
+        int c = -1, lt = -1;
+        if (s < R.s_hi) {
+          const uint32_t tp = sample_tp(in, cur, j, s);
+          c = cell_of<ROWS>(tp, tile_t0, np);
+          lt = (int)(tp >> 16) - tile_t0;
+        }
+        const bool live = c >= 0 && lt >= CL_TH - 2 && lt < CL_TH + W + 2;
+        int a = 0;
+        const int code = live ? up_code_of(tile, c, qmin, a) : 0;
+        const bool pk = live && (code & 16) && lt >= CL_TH && lt < CL_TH + W;
+        const uint64_t m = __ballot(pk);
+        const uint32_t idx = (uint32_t)__popcll(m & below);
+        const uint32_t k = used + idx;
+        const bool pslot = pk && k < (uint32_t)SW;
+        const uint32_t slot = wave * SW + k;
+        const int v = (code & 16) ? (pk ? (pslot ? MW_V0 + (int)slot : MW_PEND) : MW_NONE)
+                                  : (code & 15);
+        if (live) tile[c] = (uint16_t)mw_cell(a, v);
+        const uint32_t g = (s0 - R.s_lo) >> 6;
+        if (pslot) {
+          L.pk_cell[slot] = (uint16_t)c;
+          L.pk_a[slot] = (uint16_t)a;
+          L.pk_gi[slot] = (uint16_t)((g << 6) | idx);
+        }
+        if (lane == 0) L.grp[g] = (uint32_t)__popcll(m);
+        used += (uint32_t)__popcll(m);
+      }
+      if (lane == 0) L.wcnt[wave] = min(used, (uint32_t)SW);
+      __syncthreads();
+      const uint32_t ng = (R.s_hi - R.s_lo + 63) >> 6;
+      for (uint32_t g = 0; g < ng; ++g) total += L.grp[g];
+      ClusterRec* wrec = rec + R.c_lo;
+      uint32_t nb = 0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) nb += L.wcnt[q];
+      uint32_t done = 0;
+      // the moment sums start at zero: cleared at the start and by each record
+      while (nb > 0) {
+        // every sample within two bins of the core adds itself to the core
+        // peak that two uphill steps reach
+        j = 0;
+        for (uint32_t s0 = R.s_lo + wave * 64; s0 < R.s_hi; s0 += NT, ++j) {
+          const uint32_t s = s0 + lane;
+          if (s >= R.s_hi) continue;
+          const uint32_t tp = sample_tp(in, cur, j, s);
+          const int x = cell_of<ROWS>(tp, tile_t0, np);
+          const int lt = (int)(tp >> 16) - tile_t0;
+          if (x < 0 || lt < CL_TH - 2 || lt >= CL_TH + W + 2) continue;
+          const int tx = tile[x];
+          const int cx = mw_code(tx);
+          const int ly = lt + (cx >> 2) - 1;
+          if (ly < CL_TH - 1 || ly >= CL_TH + W + 1) continue;
+          const int y = x + code_offset(cx);
+          const int cy = mw_code(tile[y]);
+          const int vz = tile[y + code_offset(cy)] >> 10;
+          if (vz < MW_V0 || vz >= MW_V0 + NW * SW) continue;
+          const int slot = vz - MW_V0;
+          const uint32_t a = tx & 0x3FF;
+          const uint32_t dt2 = 4 - (cx >> 2) - (cy >> 2);  // dt + 2, dt = sample - peak
+          const uint32_t dp2 = 4 - (cx & 3) - (cy & 3);
+          const int dt = (int)dt2 - 2, dp = (int)dp2 - 2;
+          const uint32_t dtt = (uint32_t)__mul24(dt, dt), dpp = (uint32_t)__mul24(dp, dp);
+          const uint32_t ap = __umul24(a, dp2), at = __umul24(a, dt2);
+          const uint32_t lo0 = a | (1u << 15) | ((uint32_t)(a >= 1023) << 20) | (ap << 25);
+          uint32_t adpp;
+          asm("v_mul_u32_u24 %0, %1, %2" : "=v"(adpp) : "v"(a), "v"(dpp));
+          const uint32_t hi0 = (ap >> 7) | (adpp << 10);
+          const uint64_t v0 = ((uint64_t)hi0 << 32) | lo0;
+          const uint64_t v1 = ((uint64_t)__umul24(a, dtt) << 32) | at;
+          atomicAdd(&L.acc0[slot], (unsigned long long)v0);
+          atomicAdd(&L.acc1[slot], (unsigned long long)v1);
+        }
+        __syncthreads();
+        // the batch's records, at the peak's rank in the window; the tile
+        // is read again only if another batch follows
+        const bool more = done + nb < total;
+        if (threadIdx.x < NW * SW && threadIdx.x % SW < L.wcnt[threadIdx.x / SW]) {
+          const int c = L.pk_cell[threadIdx.x];
+          const uint32_t gi = L.pk_gi[threadIdx.x];
+          uint32_t rank = gi & 63;
+          for (uint32_t g = 0; g < (gi >> 6); ++g) rank += L.grp[g];
+          const int lt = c / CL_TP;
+          const uint64_t meta = (uint64_t)(uint32_t)(c - lt * CL_TP - 2) |
+                                ((uint64_t)(uint32_t)(lt + tile_t0) << 8) |
+                                ((uint64_t)L.pk_a[threadIdx.x] << 32);
+          ClusterRec rr;
+          rr.m0 = L.acc0[threadIdx.x];
+          rr.m1 = L.acc1[threadIdx.x];
+          rr.m2 = meta;
+          wrec[rank] = rr;
+          L.acc0[threadIdx.x] = 0;
+          L.acc1[threadIdx.x] = 0;
+          if (more) tile[c] = (uint16_t)mw_cell(L.pk_a[threadIdx.x], MW_NONE);
+        }
+        done += nb;
+        if (!more) break;
+        __syncthreads();
+        // slots for the core peaks still waiting, each wave in its sample order
+        used = 0;
+        j = 0;
+        for (uint32_t s0 = R.s_lo + wave * 64; s0 < R.c_hi; s0 += NT, ++j) {
+          const uint32_t s = s0 + lane;
+          int c = -1;
+          if (s >= R.c_lo && s < R.c_hi) c = cell_of<ROWS>(sample_tp(in, cur, j, s), tile_t0, np);
+          const int cell = c >= 0 ? tile[c] : 0;
+          const int v = cell >> 10;
+          const bool pk = v >= MW_V0;  // a peak in the core
+          const bool pend = v == MW_PEND;
+          const uint64_t m = __ballot(pk), mp = __ballot(pend);
+          const uint32_t k = used + (uint32_t)__popcll(mp & below);
+          if (pend && k < (uint32_t)SW) {
+            const uint32_t slot = wave * SW + k;
+            tile[c] = (uint16_t)mw_cell(cell & 0x3FF, MW_V0 + (int)slot);
+            L.pk_cell[slot] = (uint16_t)c;
+            L.pk_a[slot] = (uint16_t)(cell & 0x3FF);
+            L.pk_gi[slot] = (uint16_t)((((s0 - R.s_lo) >> 6) << 6) | (uint32_t)__popcll(m & below));
+          }
+          used += (uint32_t)__popcll(mp);
+        }
+        if (lane == 0) L.wcnt[wave] = min(used, (uint32_t)SW);
+        __syncthreads();
+        nb = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) nb += L.wcnt[q];
+      }
+    }
+    if (threadIdx.x == 0) win_cnt[(size_t)ur * nwin + w] = total;
+    if (sample_label && fits) {
+      // the tile is final: the last batch wrote none of it
+      for (uint32_t s = R.c_lo + threadIdx.x; s < R.c_hi; s += NT) {
+        const uint32_t tp = ((uint32_t)in.time[s] << 16) | in.pad[s];
+        const int lt = (int)(tp >> 16) - tile_t0;
+        const int x = cell_of<ROWS>(tp, tile_t0, np);
+        int32_t lab = -1;
+        if (x >= 0 && lt >= CL_TH && lt < CL_TH + W) {
+          const int y = x + code_offset(mw_code(tile[x]));
+          const int z = y + code_offset(mw_code(tile[y]));
+          if ((tile[z] >> 10) >= MW_V0) lab = ((z / CL_TP + tile_t0) << 8) | (z % CL_TP - 2);
+        }
+        sample_label[s] = lab;
+      }
+      __syncthreads();
+    }
+    // the clear writes only cells that no wave reads any more
+    scatter_mw<ROWS, PRE, NT>(tile, in, R, cur, tile_t0, np, false);
+    __syncthreads();
+    R = Rn;
+    cur = nxt;
+  }
+}
+
+template <int W, int K, int NW, int PRE>
+__global__ __launch_bounds__(64 * NW) void k_cluster_peaks_mw(ZsArgs in,
+                                                             const uint32_t* __restrict__ zblk,
+                                                             uint32_t nblk, uint32_t nwin,
+                                                             uint32_t nchunk, uint32_t n_ur,
+                                                             uint32_t* __restrict__ win_cnt,
+                                                             ClusterRec* __restrict__ rec,
+                                                             int32_t* __restrict__ sample_label,
+                                                             const DevParams* __restrict__ P,
+                                                             DevStatus* st) {
+  __shared__ PeaksLdsMw<W, NW> L;
+  if (failed(st)) return;
+  peaks_chunk_mw<W, K, NW, PRE>(in, zblk, nblk, nwin, nchunk, n_ur, win_cnt, rec, sample_label, P,
+                                st, xcd_remap(blockIdx.x, gridDim.x), L);
 }
 
 // ------------------------------------------------------------ streaming pass

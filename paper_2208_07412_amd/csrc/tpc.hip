@@ -435,19 +435,27 @@ void launch_cluster(tpc_ctx* c, const ZsArgs& za, uint32_t nblk_s, uint32_t n_ur
   const uint32_t nwt = n_ur * nwin;
   {
     StageTimer tm(c, 1);
-    if (c->tune.cl_mode == 1) {
-      // streaming pass, then the windowed pass over the chunks it handed back
-      k_fill<uint32_t><<<1, 64, 0, s>>>(c->cl_list, 0u, 1);
-      k_cluster_stream<W, K><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur, c->win,
-                                                  c->crec, co.sample_label, c->cl_list, c->d_par,
-                                                  c->d_st);
-      k_cluster_peaks_list<W, K, PRE><<<ngrid < 2048 ? ngrid : 2048, 64, 0, s>>>(
-          za, c->zblk, nblk_s, nwin, nchunk, n_ur, c->win, c->crec, co.sample_label, c->cl_list,
-          c->d_par, c->d_st);
+    if (c->tune.cl_mode == 2) {
+      // windows shared by two waves (W >= 24, checked by tpc_set_tuning)
+      if constexpr (W >= 24)
+        k_cluster_peaks_mw<W, K, 2, 2><<<ngrid, 128, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk,
+                                                             n_ur, c->win, c->crec,
+                                                             co.sample_label, c->d_par, c->d_st);
     } else {
-      k_cluster_peaks<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur,
-                                                       c->win, c->crec, co.sample_label, c->d_par,
-                                                       c->d_st);
+      if (c->tune.cl_mode == 1) {
+        // streaming pass, then the windowed pass over the chunks it handed back
+        k_fill<uint32_t><<<1, 64, 0, s>>>(c->cl_list, 0u, 1);
+        k_cluster_stream<W, K><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur,
+                                                    c->win, c->crec, co.sample_label, c->cl_list,
+                                                    c->d_par, c->d_st);
+        k_cluster_peaks_list<W, K, PRE><<<ngrid < 2048 ? ngrid : 2048, 64, 0, s>>>(
+            za, c->zblk, nblk_s, nwin, nchunk, n_ur, c->win, c->crec, co.sample_label,
+            c->cl_list, c->d_par, c->d_st);
+      } else {
+        k_cluster_peaks<W, K, PRE><<<ngrid, 64, 0, s>>>(za, c->zblk, nblk_s, nwin, nchunk, n_ur,
+                                                         c->win, c->crec, co.sample_label,
+                                                         c->d_par, c->d_st);
+      }
     }
   }
   {
@@ -1262,12 +1270,12 @@ const char* tpc_profile_stage_name(int i) {
 
 int tpc_tuning_default(tpc_tuning* t) {
   if (!t) return TPC_ERR_ARG;
-  t->cl_window = 24;
+  t->cl_window = 32;
   t->cl_chunk = 8;
   t->follow_block = 64;
   t->follow_mode = 2;
   t->refit_waves = 6;
-  t->cl_mode = 0;
+  t->cl_mode = 2;
   return TPC_OK;
 }
 
@@ -1278,9 +1286,11 @@ int tpc_set_tuning(tpc_ctx* c, const tpc_tuning* t) {
     return TPC_ERR_ARG;
   if ((t->cl_window == 20 || t->cl_window == 24) && t->cl_chunk != 8) return TPC_ERR_ARG;
   if (t->cl_chunk != 4 && t->cl_chunk != 8 && t->cl_chunk != 16) return TPC_ERR_ARG;
+  // shared windows (mode 2) of 24 or 32 bins
+  if (t->cl_mode < 0 || t->cl_mode > 2) return TPC_ERR_ARG;
+  if (t->cl_mode == 2 && t->cl_window < 24) return TPC_ERR_ARG;
   if (t->follow_block != 64 && t->follow_block != 128 && t->follow_block != 256) return TPC_ERR_ARG;
   if (t->follow_mode < 0 || t->follow_mode > 2) return TPC_ERR_ARG;
-  if (t->cl_mode != 0 && t->cl_mode != 1) return TPC_ERR_ARG;
   if (t->refit_waves != 0 && t->refit_waves != 4 && t->refit_waves != 5 && t->refit_waves != 6 &&
       t->refit_waves != 8)
     return TPC_ERR_ARG;

@@ -128,7 +128,7 @@ def test_tuning_defaults_and_validation():
     t = tpc.TpcTuning()
     assert lib.tpc_tuning_default(ctypes.byref(t)) == 0
     assert (t.cl_window, t.cl_chunk, t.follow_block, t.follow_mode, t.refit_waves, t.cl_mode) == \
-        (24, 8, 64, 2, 6, 0)
+        (32, 8, 64, 2, 6, 2)
     assert lib.tpc_set_tuning(None, ctypes.byref(t)) == -1
     assert lib.tpc_get_tuning(None, ctypes.byref(t)) == -1
     assert lib.tpc_tuning_default(None) == -1

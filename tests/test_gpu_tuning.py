@@ -6,7 +6,8 @@ over the GPU, so each
 one is held to the same parity rules as the default: clusters, links,
 tracklets and hit sets bit-exact, parameters within tolerance.  The
 dense-lattice frame gives windows with hundreds of peaks, more than one
-moment batch.
+moment batch.  The shared-window mode (two waves on one window's tile) is
+held to the same rules in each of its shapes.
 """
 import numpy as np
 import pytest
@@ -23,6 +24,10 @@ NPADS, _, _ = oracle.geometry()
 SHAPES = [(8, 8, 64, 0, 0), (8, 16, 128, 1, 4), (16, 4, 64, 2, 5), (16, 8, 128, 1, 6),
           (16, 16, 256, 0, 8), (20, 8, 128, 0, 6), (24, 8, 256, 1, 5), (32, 4, 256, 1, 0),
           (32, 8, 64, 1, 5), (32, 16, 128, 0, 4), (24, 8, 128, 2, 0), (8, 4, 256, 2, 6)]
+
+
+# (window, windows per workgroup, mode) of the shared-window passes
+SHARED = [(24, 8, 2), (32, 4, 2), (32, 8, 2), (32, 16, 2)]
 
 
 @pytest.fixture(scope="module")
@@ -46,6 +51,15 @@ def test_shape_parity(frame, w, k, fb, fm, rw, cm):
     compare_fit(g, o)
 
 
+@pytest.mark.parametrize("w,k,cm", SHARED)
+def test_shared_window_parity(frame, w, k, cm):
+    ev, o = frame
+    g = run_gpu(ev, labels=True, tuning=dict(cl_window=w, cl_chunk=k, cl_mode=cm))
+    compare_clusters(g["clusters"], o["clusters"], labels=True)
+    assert np.array_equal(g["links"]["down"], o["down"])
+    assert np.array_equal(g["tracklets"]["tl_start"], o["tracklets"]["tl_start"])
+
+
 def _lattice_event(T, step_t, step_p, adc):
     pad, time, a = [], [], []
     rows = (0, 40, 151)
@@ -65,8 +79,9 @@ def _lattice_event(T, step_t, step_p, adc):
                           np.array(a, np.uint16), rs, 1, T, {}, {}, None)
 
 
-@pytest.mark.parametrize("cm", [0, 1])
-@pytest.mark.parametrize("w,k", [(8, 4), (16, 8), (20, 8), (24, 8), (32, 4)])
+@pytest.mark.parametrize("w,k,cm", [(w, k, cm) for cm in (0, 1)
+                                    for w, k in ((8, 4), (16, 8), (20, 8), (24, 8), (32, 4))] +
+                         [(24, 8, 2), (32, 8, 2), (32, 16, 2)])
 def test_most_peaks_per_window(w, k, cm):
     # isolated samples on every other pad and bin: each one is a peak, so a
     # window holds far more peaks than one moment batch (and the streaming
@@ -78,8 +93,9 @@ def test_most_peaks_per_window(w, k, cm):
     compare_clusters(g["clusters"], o["clusters"], labels=True)
 
 
-@pytest.mark.parametrize("cm", [0, 1])
-@pytest.mark.parametrize("w,k", [(8, 16), (16, 8), (20, 8), (24, 8), (32, 16)])
+@pytest.mark.parametrize("w,k,cm", [(w, k, cm) for cm in (0, 1)
+                                    for w, k in ((8, 16), (16, 8), (20, 8), (24, 8), (32, 16))] +
+                         [(24, 8, 2), (32, 4, 2)])
 def test_fully_occupied_rows(w, k, cm):
     # every (time, pad) present: the densest input a row can have
     ev = _lattice_event(120, 1, 1, lambda t, p: 3 + ((t * 131 + p * 71) * 2654435761 % 2**32) % 400)
@@ -118,7 +134,8 @@ def test_set_tuning_rejects_unknown_shapes():
     reco = tpc.Reco(1, 100, 1024, 64)
     before = reco.tuning()
     for bad in (dict(cl_window=12), dict(cl_chunk=3), dict(cl_window=20, cl_chunk=4), dict(cl_window=28),
-                dict(follow_block=96), dict(follow_mode=3), dict(refit_waves=3), dict(cl_mode=2)):
+                dict(follow_block=96), dict(follow_mode=3), dict(refit_waves=3), dict(cl_mode=3),
+                dict(cl_window=48), dict(cl_window=16, cl_mode=2), dict(cl_window=20, cl_mode=2)):
         with pytest.raises(tpc.TpcError):
             reco.set_tuning(**bad)
         assert reco.tuning() == before
