@@ -14,30 +14,36 @@
 #define SCAN_TILE (SCAN_BLOCK * SCAN_ITEMS)
 
 // Parameters and row tables, resident in device memory for one context.
-struct DevParams {
+// DevParams32 holds everything but the FP64 copies, which only the refit's
+// FP64 path reads: kernels that compute in FP32 copy just this part into LDS.
+struct DevParams32 {
   int32_t np[NROW];   // pads per row
   int32_t xfx[NROW];  // row radius, 2^-16 cm
   int32_t pfx[NROW];  // pad pitch, 2^-16 cm
   float x[NROW], hw[NROW], vy[NROW], vz[NROW];
-  double xd[NROW], hwd[NROW], vyd[NROW], vzd[NROW];
   int32_t qmax_min, min_tracklet, max_miss, min_track_hits;
   int64_t win_y, win_z, s_max;
   float chi2_max, snp_max, bz_b, c0_snp2, c0_tgl2, c0_qpt2, qpt_clamp, edge_margin, lowpt_qpt;
-  double chi2_max_d, snp_max_d, bz_b_d, c0_snp2_d, c0_tgl2_d, c0_qpt2_d, qpt_clamp_d,
-      edge_margin_d;
   float c0r2[5], refit_snp_max;  // refit prior variances (y, z, snp, tgl, q/pT)
-  double c0r2_d[5], refit_snp_max_d;
   int32_t validate, force_fallback;
 };
+struct DevParams : DevParams32 {
+  double xd[NROW], hwd[NROW], vyd[NROW], vzd[NROW];
+  double chi2_max_d, snp_max_d, bz_b_d, c0_snp2_d, c0_tgl2_d, c0_qpt2_d, qpt_clamp_d,
+      edge_margin_d;
+  double c0r2_d[5], refit_snp_max_d;
+};
 
-// The parameters and row tables copied into LDS by the whole workgroup (a
-// barrier follows): per-lane row lookups in long serial loops then cost an
-// LDS read instead of a round trip to the caches.
-__device__ __forceinline__ const DevParams* params_to_lds(const DevParams* P, DevParams* lds) {
-  static_assert(sizeof(DevParams) % 8 == 0, "copied in 8-byte words");
-  const uint2* src = reinterpret_cast<const uint2*>(P);
+// The parameters and row tables (all of them, or the FP32 part: PD is
+// DevParams or DevParams32, the first part of a DevParams) copied into LDS by
+// the whole workgroup (a barrier follows): per-lane row lookups in long
+// serial loops then cost an LDS read instead of a round trip to the caches.
+template <typename PD>
+__device__ __forceinline__ const PD* params_to_lds(const DevParams* P, PD* lds) {
+  static_assert(sizeof(PD) % 8 == 0, "copied in 8-byte words");
+  const uint2* src = reinterpret_cast<const uint2*>(static_cast<const PD*>(P));
   uint2* dst = reinterpret_cast<uint2*>(lds);
-  for (uint32_t i = threadIdx.x; i < sizeof(DevParams) / 8; i += blockDim.x) dst[i] = src[i];
+  for (uint32_t i = threadIdx.x; i < sizeof(PD) / 8; i += blockDim.x) dst[i] = src[i];
   __syncthreads();
   return lds;
 }

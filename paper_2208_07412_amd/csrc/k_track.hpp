@@ -37,7 +37,7 @@ template <typename T>
 struct PV;
 template <>
 struct PV<float> {
-  const DevParams* P;
+  const DevParams32* P;
   __device__ float x(int r) const { return P->x[r]; }
   __device__ float hw(int r) const { return P->hw[r]; }
   __device__ float vy(int r) const { return P->vy[r]; }
@@ -94,7 +94,7 @@ __device__ __forceinline__ T two_sum_acc(T a, T b, T* acc) {
 
 // exact row-to-row distance from the integer radii
 template <typename T>
-__device__ __forceinline__ T row_dx(const DevParams* P, int r1, int r2) {
+__device__ __forceinline__ T row_dx(const DevParams32* P, int r1, int r2) {
   return (T)(P->xfx[r2] - P->xfx[r1]) * (T)FX_SCALE;
 }
 
@@ -582,7 +582,7 @@ struct FollowLane {
 __device__ __forceinline__ bool follow_init(FollowLane& f, uint32_t t, const ClusterView& cl,
                                             const uint32_t* tl_start, const uint16_t* tl_len,
                                             const int32_t* upc, const uint32_t* pts, FollowOut& fo,
-                                            const DevParams* P, const PV<float>& pv) {
+                                            const DevParams32* P, const PV<float>& pv) {
   fo.ok[t] = 0;
   fo.nhits[t] = 0;
   fo.range[t] = 0;
@@ -679,7 +679,7 @@ __device__ __forceinline__ void follow_finish(const FollowLane& f, FollowOut& fo
 template <int PA>
 __device__ __forceinline__ bool follow_step(FollowLane& f, const ClusterView& cl,
                                             const uint32_t* cblk, uint32_t nblk,
-                                            const int32_t* upc, FollowOut& fo, const DevParams* P,
+                                            const int32_t* upc, FollowOut& fo, const DevParams32* P,
                                             const PV<float>& pv, float chi2max) {
   constexpr bool pa = PA == 1;
   const int rn = f.r + (pa ? 1 : -1);
@@ -787,8 +787,9 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
     if (COUNT && (threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(0, 0, 0, 0);
     return;
   }
-  __shared__ DevParams Ps;
-  const DevParams* P = params_to_lds(Pg, &Ps);
+  // FP32 only: the parameter block without its FP64 copies
+  __shared__ DevParams32 Ps;
+  const DevParams32* P = params_to_lds(Pg, &Ps);
   const PV<float> pv{P};
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const float chi2max = pv.chi2_max();
@@ -846,9 +847,15 @@ __global__ __launch_bounds__(B) void k_follow(ClusterView cl, const uint32_t* __
 // counter (refill = FOLLOW_REFILL), so the wave no longer runs as long as its longest tracklet with
 // the other lanes idle.  Every tracklet is followed by exactly one lane, with
 // the same arithmetic as k_follow, so the results do not depend on which lane
-// or wave takes it.  The grid is sized to the resident waves (more would find
-// the queues empty); qnext holds ngrp zeroed counters.
+// or wave takes it.  The grid is sized to the resident waves, at most
+// FOLLOW_Q_WAVES_PER_CU per compute unit (more would find the queues empty);
+// qnext holds ngrp zeroed counters.
 #define FOLLOW_REFILL 32
+// Waves of the lane-refill grid per compute unit.  Each lane gathers lines of
+// its own (hit grid, positions, hit table) that the L2 holds only while few
+// lanes compete for it: on a 2 ms Pb-Pb slice the two passes took 3.02, 2.53,
+// 2.41, 2.53 and 2.63 ms with 8, 12, 16, 20 and 24 waves per compute unit.
+#define FOLLOW_Q_WAVES_PER_CU 16
 template <int B, int PASS, bool COUNT>
 __global__ __launch_bounds__(B) void k_follow_q(ClusterView cl, const uint32_t* __restrict__ cblk,
                                                  uint32_t nblk, const int32_t* __restrict__ upc,
@@ -869,8 +876,9 @@ __global__ __launch_bounds__(B) void k_follow_q(ClusterView cl, const uint32_t* 
     if (COUNT && (threadIdx.x & 63) == 0) work[wave] = make_ulonglong4(0, 0, 0, 0);
     return;
   }
-  __shared__ DevParams Ps;
-  const DevParams* P = params_to_lds(Pg, &Ps);
+  // FP32 only: the parameter block without its FP64 copies
+  __shared__ DevParams32 Ps;
+  const DevParams32* P = params_to_lds(Pg, &Ps);
   const PV<float> pv{P};
   const uint32_t n_tl = scan_count(n_tl_dev, tl_cap);
   const float chi2max = pv.chi2_max();

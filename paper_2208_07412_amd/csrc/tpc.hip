@@ -611,7 +611,8 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
           k_fill<unsigned long long><<<grid_for(8 * nwf, 256), 256, 0, s>>>(
               reinterpret_cast<unsigned long long*>(c->f_work), 0ull, 8 * nwf);
         // resident workgroups per compute unit of each pass kernel, queried
-        // once per process (a property of the kernel, not of the call)
+        // once per process (a property of the kernel, not of the call), at
+        // most FOLLOW_Q_WAVES_PER_CU waves
         auto occupancy = [](const void* fn) {
           int per_cu = 0;
           if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, Bv, 0) != hipSuccess ||
@@ -622,6 +623,8 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
         static const int occ_a = occupancy((const void*)k_follow_q<Bv, FP_A, Cv>);
         static const int occ_b = occupancy((const void*)k_follow_q<Bv, FP_B, Cv>);
         auto grid_q = [&](int per_cu) {
+          const int cap = FOLLOW_Q_WAVES_PER_CU / (Bv / 64);
+          if (per_cu > cap) per_cu = cap;
           const uint32_t gq = ceil_div((uint32_t)(per_cu * c->n_cu), ng) * ng;
           return gq < gf ? gq : gf;
         };
