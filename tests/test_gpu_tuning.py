@@ -104,6 +104,29 @@ def test_fully_occupied_rows(w, k, cm):
     compare_clusters(g["clusters"], o["clusters"], labels=True)
 
 
+def test_shared_window_reports_overfull_window():
+    # every (time, pad) of the widest row three times over: duplicates pass the
+    # sample index when validation is off, and a window then holds more
+    # samples than cells, which the shared-window pass reports (and skips)
+    T, r = 40, 151
+    npads = int(NPADS[r])
+    time = np.repeat(np.arange(T), npads * 3).astype(np.uint16)
+    pad = np.tile(np.repeat(np.arange(npads), 3), T).astype(np.uint16)
+    adc = np.full(len(pad), 7, np.uint16)
+    rs = np.zeros(153, np.uint32)
+    rs[r + 1:] = len(pad)
+    reco = tpc.Reco(1, T, len(pad), 64)
+    reco.set_tuning(cl_window=32, cl_chunk=8, cl_mode=2)
+    zs = tpc.to_device_zs(pad, time, adc, rs, 1, T)
+    reco.cluster(zs, reco.alloc_clusters(1, T, len(pad)))
+    assert reco.sync(raise_on_error=False)["status"] == -3
+    # the context serves the next (valid) call
+    ev = _lattice_event(T, 2, 2, lambda t, p: 5 + (t * 7 + p * 3) % 900)
+    g = run_gpu(ev, reco=reco, labels=True, max_tracklets=64)
+    compare_clusters(g["clusters"], run_oracle(ev, labels=True)["clusters"], labels=True)
+    reco.close()
+
+
 @pytest.mark.parametrize("fm", [0, 2])
 def test_work_counting_variant_same_results(frame, fm):
     # the measurement variant of the following kernel counts its work and
