@@ -302,6 +302,19 @@ uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 1u << 20) {
   return (uint32_t)g;
 }
 
+// Grid caps of the grid-stride kernels of the track stages, whose grids are
+// sized by buffer capacity (the counts are known only on the device): a
+// workgroup with nothing to do still costs its dispatch, and in the refit its
+// copy of the parameter block into LDS.  Measured on a 2 ms Pb-Pb slice
+// (buffers for 2.2x its clusters and 6.6x its tracklets), uncapped against
+// capped: hit grid + tracklets + track output 0.77 -> 0.70 ms at 16384
+// workgroups; claim and keep (a wave per 4 tracklets) 0.88 -> 0.78 ms at
+// 65536 (1.02 at 16384, 1.10 at 32768: they want a wave per group); refit
+// (one-wave workgroups) 0.71 -> 0.60 ms at 4096.
+constexpr uint32_t kCapStream = 16384;
+constexpr uint32_t kCapClaim = 65536;
+constexpr uint32_t kCapRefit = 4096;
+
 // Records a pair of events around one stage when stage timing is on.
 struct StageTimer {
   tpc_ctx* c;
@@ -525,7 +538,7 @@ int stage_grid(tpc_ctx* c, const tpc_clusters* cl) {
                                              CG_BSHIFT,
                                              cl->n_time_bins, cl->capacity, c->cblk, c->d_par,
                                              c->d_st, 0);
-  k_pack_pos<<<grid_for(cl->capacity, 256), 256, 0, c->stream>>>(cl->y_fx, cl->z_fx, cl->n_clusters,
+  k_pack_pos<<<grid_for(cl->capacity, 256, kCapStream), 256, 0, c->stream>>>(cl->y_fx, cl->z_fx, cl->n_clusters,
                                                                  cl->capacity, c->pos, c->d_st);
   return launch_ok();
 }
@@ -542,7 +555,7 @@ int stage_neighbours(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l) {
 int stage_tracklets(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l, tpc_tracklets* t) {
   hipStream_t s = c->stream;
   const uint32_t cap = cl->capacity;
-  const uint32_t g = grid_for(cap, 256);
+  const uint32_t g = grid_for(cap, 256, kCapStream);
   StageTimer tm(c, 6);
   k_ca_clean<<<g, 256, 0, s>>>(l->down, l->up, l->downc, l->upc, c->start_flag, cl->n_clusters, cap,
                                c->d_st);
@@ -551,7 +564,7 @@ int stage_tracklets(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l, tpc_trackl
   const uint32_t capc = cap / 2 + 1;
   run_scan<uint32_t>(c, GetStart{c->start_flag}, EmitStart{c->cand, capc}, cl->n_clusters, cap,
                      (uint32_t*)nullptr, c->tot32);
-  k_chain_len<<<grid_for(capc, 256), 256, 0, s>>>(c->cand, c->tot32, capc, l->upc, cl->n_clusters,
+  k_chain_len<<<grid_for(capc, 256, kCapStream), 256, 0, s>>>(c->cand, c->tot32, capc, l->upc, cl->n_clusters,
                                                   cap, c->chain_len, c->d_par, c->d_st);
   run_scan<uint32_t>(c, GetKeepLen{c->chain_len},
                      EmitTracklet{c->cand, c->chain_len, t->start, t->len, t->capacity}, c->tot32,
@@ -570,8 +583,8 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   const ClusterView cv = cluster_view(c, cl);
   const FollowOut fo = follow_out(c);
   const RefitOut ro = refit_out(c);
-  const uint32_t g64 = grid_for(tcap, 64);
-  const uint32_t gw = grid_for(tcap, 32);
+  const uint32_t g64 = grid_for(tcap, 64, kCapRefit);
+  const uint32_t gw = grid_for(tcap, 32, kCapClaim);
   // f_perm = the tracklets sorted by f_key, largest first (stable)
   const uint32_t nsb = ceil_div(tcap, SORT_BLOCK);
   // ngrp groups sorted each on its own (the following: one group per XCD)
@@ -588,7 +601,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   k_fill<uint32_t><<<1, 64, 0, s>>>(&c->d_st->n_fallback, 0u, 5);
   {
     StageTimer tm(c, 6);  // the tracklets' seed points belong to tracklet building
-    k_tracklet_points<<<grid_for(tcap, 256), 256, 0, s>>>(cv, n_ur, l->upc, t->start, t->len,
+    k_tracklet_points<<<grid_for(tcap, 256, kCapStream), 256, 0, s>>>(cv, n_ur, l->upc, t->start, t->len,
                                                            t->n_tracklets, tcap, c->f_pts,
                                                            c->f_key, c->d_st);
   }
@@ -676,7 +689,7 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
   }
   {
     StageTimer tm(c, 8);
-    k_fill_dev<uint32_t><<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, 0u,
+    k_fill_dev<uint32_t><<<grid_for(ccap, 256, kCapStream), 256, 0, s>>>(c->owner, 0u,
                                                                         cl->n_clusters, ccap);
     // one wave per tracklet, about 8 tracklets per wave
     k_claim<false><<<gw, 256, 0, s>>>(fo, t->n_tracklets, tcap, c->owner, ccap, c->d_par, c->d_st);
@@ -711,9 +724,9 @@ int stage_fit(tpc_ctx* c, const tpc_clusters* cl, const tpc_links* l, const tpc_
               tr->row, tr->flags, tr->z_anchor, tr->hit_start, tr->hits, tr->cluster_track};
   k_track_totals<<<1, 1, 0, s>>>(c->tot64, to, tr->n_tracks, tr->n_hits, c->d_st);
   // tracklets of the tracks listed in f_perm (free after the refit)
-  k_track_emit<<<grid_for(tcap, 256), 256, 0, s>>>(cv, t->start, fo, c->f_perm, c->nkept, ro,
+  k_track_emit<<<grid_for(tcap, 256, kCapStream), 256, 0, s>>>(cv, t->start, fo, c->f_perm, c->nkept, ro,
                                                     c->hit_off, to, c->d_st);
-  k_cluster_track<<<grid_for(ccap, 256), 256, 0, s>>>(c->owner, c->trk_index, cl->n_clusters, ccap,
+  k_cluster_track<<<grid_for(ccap, 256, kCapStream), 256, 0, s>>>(c->owner, c->trk_index, cl->n_clusters, ccap,
                                                       tcap, tr->cluster_track, c->d_st);
   if (tr->follow_hits)
     k_follow_export<<<grid_for((uint64_t)tcap * NROW, 256), 256, 0, s>>>(fo, t->n_tracklets, tcap,
