@@ -122,6 +122,26 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
           pv[e] = (check_input && s >= s0 && s < s1) ? pkey[s] : 0;
         }
       }
+      if (vec && check_input && !validate && base >= s0 && base + 8 < s1) {
+        // a group inside the row, not holding its last key: the checks of
+        // the general path below, without its per-key range tests, and one
+        // report per group
+        uint32_t tq0 = (base > s0) ? (uint32_t)tkey[base - 1] : 0;
+        int32_t prev = base > s0 ? (int32_t)((tq0 < T ? tq0 : T - 1) >> bshift) : -1;
+        bool bad = false;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          uint32_t t = tv[e];
+          bad |= t >= T || (int)pv[e] >= np;
+          if (t >= T) t = T - 1;
+          const int32_t cur = (int32_t)(t >> bshift);
+          for (int32_t k = prev + 1; k <= cur; ++k) b[k] = base + e;
+          bad |= cur < prev;
+          prev = cur;
+        }
+        if (bad) latch(st, TPC_ERR_INPUT);
+        continue;
+      }
       // key before this group (inside the row)
       uint32_t tp = (base > s0) ? (uint32_t)tkey[base - 1] : 0;
       uint32_t pp = (validate && base > s0) ? (uint32_t)pkey[base - 1] : 0;
