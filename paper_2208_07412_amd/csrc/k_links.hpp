@@ -58,8 +58,10 @@ __device__ __forceinline__ void nb_candidates(const ClusterView& cl, const uint3
 
 // Best (j, k) pair for cluster i among the candidates [ja, jb) in row r-1
 // and [ka, kb) in row r+1 (positions pos[]).  The k candidates inside the
-// window are listed once in registers (up to NB_KLIST; beyond that the whole
-// range is scanned per j).  Positions are below 2^30 in magnitude and
+// window are marked once in a 64-bit mask when the range has at most 64
+// (most of a time window's candidates lie outside the y window), else listed
+// in registers (up to NB_KLIST; beyond that the whole range is scanned per
+// j).  Positions are below 2^30 in magnitude and
 // windows are capped at 2^30 (far beyond any row), so every difference fits
 // 32 bits and a score (sum of two squares) fits 64 bits unsigned; the
 // decision is the exact integer one.
@@ -72,6 +74,34 @@ template <class PJ, class PK>
 __device__ __forceinline__ void nb_best(PJ J, PK K, int32_t yi, int32_t zi, int32_t wy,
                                         int32_t wz, uint64_t smax, uint32_t ja, uint32_t jb,
                                         uint32_t ka, uint32_t kb, int32_t& bd, int32_t& bu) {
+  if (kb - ka <= 64) {
+    // the in-window k candidates as a bit mask, walked in ascending order
+    uint64_t km = 0;
+    for (uint32_t k = ka; k < kb; ++k) {
+      const int2 pk = K(k);
+      if (nb_in(pk.x, yi, wy) && nb_in(pk.y, zi, wz)) km |= 1ull << (k - ka);
+    }
+    if (km == 0) return;
+    uint64_t best = ~0ull;
+    for (uint32_t j = ja; j < jb; ++j) {
+      const int2 pj = J(j);
+      if (!nb_in(pj.x, yi, wy) || !nb_in(pj.y, zi, wz)) continue;
+      const int32_t ay = yi - pj.x, az = zi - pj.y;
+      for (uint64_t m = km; m != 0; m &= m - 1) {
+        const uint32_t k = ka + (uint32_t)__builtin_ctzll(m);
+        const int2 pk = K(k);
+        const int32_t dy = ay + (yi - pk.x), dz = az + (zi - pk.y);
+        const uint64_t sc = (uint64_t)((int64_t)dy * dy) + (uint64_t)((int64_t)dz * dz);
+        // j and k ascend, so a strict "<" keeps the smallest (j, k) on ties
+        if (sc <= smax && sc < best) {
+          best = sc;
+          bd = (int32_t)j;
+          bu = (int32_t)k;
+        }
+      }
+    }
+    return;
+  }
   uint32_t kl[NB_KLIST];
   int nk = 0;
   bool over = false;
