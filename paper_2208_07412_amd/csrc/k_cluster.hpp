@@ -44,8 +44,11 @@ struct ClusterOut {
 
 // Offsets of the samples (or clusters) of each (unit,row) per block of
 // 2^bshift time bins: blk[ur*(nblk+1) + b] = first index with key time >=
-// b << bshift; the entry at nblk is the row end.  One workgroup per
-// (unit,row); rows are time-sorted.  Each thread takes 8 consecutive keys
+// b << bshift; the entry at nblk is the row end.  Rows are time-sorted.  A
+// key needs only the key before it (read from memory), so without LDS
+// staging a row is split into BI_PARTS workgroups, each taking a contiguous
+// part of its keys (the last part writes the row end); with staging, one
+// workgroup per (unit,row).  Each thread takes 8 consecutive keys
 // per step (one 16-byte load when the key array is 16-byte aligned; the
 // aligned block never crosses a page, and keys outside the row are masked).
 // A key writes the entries of the blocks between its predecessor's and its
@@ -66,6 +69,9 @@ __device__ __forceinline__ void bi_sample(uint32_t s, uint32_t t, int32_t prev, 
 }
 
 #define BI_LDS 6144
+// parts per row of the unstaged index (a 2 ms Pb-Pb slice: 0.256, 0.233, 0.244
+// and 0.275 ms with 1, 4, 8 and 16 parts)
+#define BI_PARTS 4
 template <bool USE_LDS>
 __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict__ tkey,
                                                      const uint16_t* __restrict__ pkey,
@@ -80,15 +86,22 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
   if (failed(st)) return;
   const bool vec = ((uintptr_t)tkey & 15) == 0 && (!check_input || ((uintptr_t)pkey & 15) == 0);
   const bool staged = USE_LDS && nblk + 1 <= BI_LDS;
-  for (uint32_t ur = blockIdx.x; ur < n_ur; ur += gridDim.x) {
+  constexpr uint32_t parts = USE_LDS ? 1 : BI_PARTS;
+  for (uint32_t item = blockIdx.x; item < n_ur * parts; item += gridDim.x) {
+    const uint32_t ur = item / parts, part = item % parts;
     uint32_t s0 = rstart[ur], s1 = rstart[ur + 1];
     if (s1 > n_total) s1 = n_total;
     if (s0 > s1) s0 = s1;
     uint32_t* const bg = blk + (size_t)ur * (nblk + 1);
     if (s0 == s1) {
-      for (uint32_t k = threadIdx.x; k <= nblk; k += blockDim.x) bg[k] = s0;
+      if (part == 0)
+        for (uint32_t k = threadIdx.x; k <= nblk; k += blockDim.x) bg[k] = s0;
       continue;
     }
+    // this part's 8-key groups
+    const uint32_t glo = s0 >> 3, ng = ((s1 + 7) >> 3) - glo;
+    const uint32_t g0 = glo + (uint32_t)((uint64_t)ng * part / parts);
+    const uint32_t g1 = glo + (uint32_t)((uint64_t)ng * (part + 1) / parts);
     // the row's table: in LDS (every entry preset to the row start, so an
     // unsorted row, which is reported, leaves no stale entry) or in place
     uint32_t* b = bg;
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(256) void k_block_index(const uint16_t* __restrict_
     }
     const int np = P->np[ur % NROW];
     const bool validate = check_input && P->validate;
-    for (uint32_t g = (s0 >> 3) + threadIdx.x; g < ((s1 + 7) >> 3); g += blockDim.x) {
+    for (uint32_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
       const uint32_t base = g << 3;
       uint16_t tv[8], pv[8];
       if (vec) {

@@ -492,7 +492,8 @@ int stage_cluster(tpc_ctx* c, const tpc_zs_input* in, tpc_clusters* out) {
   hipStream_t s = c->stream;
   {
     StageTimer tm(c, 0);
-    k_block_index<false><<<n_ur, 256, 0, s>>>(in->time, in->pad, in->adc, in->row_start, n_ur,
+    k_block_index<false><<<n_ur * BI_PARTS, 256, 0, s>>>(in->time, in->pad, in->adc, in->row_start,
+                                                         n_ur,
                                               nblk_s,
                                               CL_BSHIFT, in->n_time_bins, in->n_samples, c->zblk,
                                               c->d_par, c->d_st, 1);
