@@ -150,8 +150,8 @@ __device__ __forceinline__ void nb_best(PJ J, PK K, int32_t yi, int32_t zi, int3
   }
 }
 
-// One lane per cluster, one workgroup per (unit,row), the row's clusters in
-// batches of 64 per wave.  Each wave copies the union of its lanes'
+// One lane per cluster, NB_PARTS workgroups per (unit,row), each part's
+// clusters in batches of 64 per wave.  Each wave copies the union of its lanes'
 // candidate ranges in rows r-1 and r+1 (contiguous: rows are time-sorted)
 // into its own LDS slice when it fits and scores from there; no workgroup
 // barrier is involved (a wave reads back its own LDS writes in order), so
@@ -159,6 +159,10 @@ __device__ __forceinline__ void nb_best(PJ J, PK K, int32_t yi, int32_t zi, int3
 // workgroup batch of 256 behind barriers serialised each workgroup's batches:
 // 1.40 ms for the slice; reading every candidate through the caches: 1.13 ms.)
 #define NB_WSTAGE 256
+// parts of a row, each a workgroup taking a contiguous run of its 64-cluster
+// batches (fewer idle compute units in the last round of rows; a 2 ms Pb-Pb
+// slice: 0.645, 0.615, 0.625 and 0.631 ms with 1, 2, 4 and 8 parts)
+#define NB_PARTS 2
 __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32_t* __restrict__ cblk,
                                                     uint32_t nblk, uint32_t n_ur,
                                                     int32_t* __restrict__ down,
@@ -174,12 +178,17 @@ __global__ __launch_bounds__(256) void k_neighbours(ClusterView cl, const uint32
   const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int2* sj = sp[w][0];
   int2* sk = sp[w][1];
-  for (uint32_t b = blockIdx.x; b < n_ur; b += gridDim.x) {
+  const uint32_t n_items = n_ur * NB_PARTS;
+  for (uint32_t b = blockIdx.x; b < n_items; b += gridDim.x) {
     // consecutive rows of a sector share an XCD (and its L2) when the grid
     // covers every row
-    const uint32_t ur = gridDim.x == n_ur ? xcd_remap(b, n_ur) : b;
+    const uint32_t item = gridDim.x == n_items ? xcd_remap(b, n_items) : b;
+    const uint32_t ur = item / NB_PARTS, part = item % NB_PARTS;
     const int r = ur % NROW;
-    const uint32_t c0 = cl.row_start(ur), c1 = cl.row_start(ur + 1);
+    const uint32_t r0 = cl.row_start(ur), r1 = cl.row_start(ur + 1);
+    const uint32_t nbat = (r1 - r0 + 63) / 64;
+    const uint32_t c0 = r0 + 64 * (nbat * part / NB_PARTS);
+    const uint32_t c1 = min(r1, r0 + 64 * (nbat * (part + 1) / NB_PARTS));
     if (r < 1 || r > NROW - 2) {
       for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
         down[i] = -1;

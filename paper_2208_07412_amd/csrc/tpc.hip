@@ -548,7 +548,7 @@ int stage_neighbours(tpc_ctx* c, const tpc_clusters* cl, tpc_links* l) {
   const uint32_t n_ur = cl->n_units * NROW;
   const uint32_t nblk = ceil_div(cl->n_time_bins, 1u << CG_BSHIFT);
   StageTimer tm(c, 5);
-  k_neighbours<<<n_ur, 256, 0, c->stream>>>(cluster_view(c, cl), c->cblk, nblk, n_ur, l->down, l->up,
+  k_neighbours<<<n_ur * NB_PARTS, 256, 0, c->stream>>>(cluster_view(c, cl), c->cblk, nblk, n_ur, l->down, l->up,
                                             c->d_par, c->d_st);
   return launch_ok();
 }
