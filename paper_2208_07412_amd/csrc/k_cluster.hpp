@@ -339,19 +339,40 @@ __device__ __forceinline__ Row3 row3(const uint16_t* tile, int c) {
 // up code (bits 0-3) and peak flag (bit 4) of the sample in cell c: the
 // argmax of the key (adc, time, pad) over the cell and its present neighbours;
 // a = the cell's ADC
+//
+// key = adc * 16 + code: the codes order the nine cells by (time, pad), so
+// the largest key is the argmax of (adc, time, pad) and its low bits are the
+// up code.  An empty cell (adc 0) has a key below 16 and never beats a
+// present cell; if nothing present is left (an ADC-0 sample alone), the
+// sample keeps its own code.  Keys fit 14 bits, so the two cells of a 32-bit
+// word are keyed and compared as a pair (packed 16-bit max).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_max_u16(uint32_t x, uint32_t y) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, x),
+                                                                __builtin_bit_cast(u16x2, y)));
+}
+// keys of the cells c-1 and c (lo) and c+1 (hi, upper half 0) of one tile
+// row, with the codes of those cells in lo_code (c-1 low, c high) and hi_code
+__device__ __forceinline__ void row_keys(const uint16_t* tile, int c, uint32_t lo_code,
+                                         uint32_t hi_code, uint32_t& lo, uint32_t& hi) {
+  const uint32_t* t32 = reinterpret_cast<const uint32_t*>(tile);
+  const int w = (c - 1) >> 1;
+  const uint32_t w0 = t32[w], w1 = t32[w + 1];
+  const uint32_t sh = ((c - 1) & 1) * 16;
+  lo = __builtin_amdgcn_alignbit(w1, w0, sh);  // cells c-1, c
+  hi = w1 >> sh;                               // cell c+1 (and c+2 or nothing)
+  lo = ((lo & 0x03FF03FFu) << 4) | lo_code;
+  hi = ((hi & 0x3FFu) << 4) | hi_code;
+}
 __device__ __forceinline__ int up_code_of(const uint16_t* tile, int c, int qmin, int& a) {
-  const Row3 u = row3(tile, c - CL_TP), m = row3(tile, c), d = row3(tile, c + CL_TP);
-  a = m.m;
-  // key = adc * 16 + code: the codes order the nine cells by (time, pad), so
-  // the largest key is the argmax of (adc, time, pad) and its low bits are the
-  // up code.  An empty cell (adc 0) has a key below 16 and never beats a
-  // present cell; if nothing present is left (an ADC-0 sample alone), the
-  // sample keeps its own code.
-  int best = (a << 4) | 5;
-  best = max(best, max(u.l << 4, (u.m << 4) | 1));
-  best = max(best, max((u.r << 4) | 2, (m.l << 4) | 4));
-  best = max(best, max((m.r << 4) | 6, (d.l << 4) | 8));
-  best = max(best, max((d.m << 4) | 9, (d.r << 4) | 10));
+  uint32_t ul, uh, ml, mh, dl, dh;
+  row_keys(tile, c - CL_TP, 0x00010000u, 2u, ul, uh);
+  row_keys(tile, c, 0x00050004u, 6u, ml, mh);
+  row_keys(tile, c + CL_TP, 0x00090008u, 10u, dl, dh);
+  a = (int)(ml >> 20);  // the cell's own key is its ADC * 16 + 5
+  const uint32_t m2 = pk_max_u16(pk_max_u16(pk_max_u16(ul, ml), pk_max_u16(dl, uh)),
+                                 pk_max_u16(mh, dh));
+  const int best = (int)max(m2 & 0xFFFFu, m2 >> 16);
   const int code = best >= 16 ? (best & 15) : 5;
   return code | ((code == 5 && a >= qmin) ? 16 : 0);
 }
