@@ -712,6 +712,11 @@ def main():
                            slices=n_slices, slice_start=start_pt, slice_ms=form_ms,
                            samples=ns, clusters=nc, tracks=counts["n_tracks"]),
                roofline=roofline, roofline_2=roofline_2, stages_ms=stages, qc=qc)
+    # real-time factor: the slice's collisions per second of one GPU against
+    # the 50 kHz interaction rate the slice is drawn at
+    coll_per_s = len(cfg.collisions) / (ms_step / 1e3)
+    out["realtime"] = dict(collisions=len(cfg.collisions), collisions_per_s=coll_per_s,
+                           rate_hz=50e3, factor=coll_per_s / 50e3)
     if out_pages is not None:
         out["zs_pages"] = out_pages
     out["compression"] = out_comp
