@@ -308,9 +308,11 @@ __global__ __launch_bounds__(256) void k_mg_pairs(MgSegs S, uint32_t nzb,
           const double bz = pk[3 * (size_t)k];
           if (fabs(az - bz) <= MG_DZMAX) {
             const double bx = pk[3 * (size_t)k + 1], by = pk[3 * (size_t)k + 2];
-            const double dxy = sqrt((ax - bx) * (ax - bx) + (ay - by) * (ay - by));
+            const double d2 = (ax - bx) * (ax - bx) + (ay - by) * (ay - by);
             // beyond the near-tie band of the gap cut nothing can pass or tie
-            pass = dxy <= MG_GAP * (1 + 2 * MG_TIE) && (cell_ends[k] >> 1) > A;
+            // (squared distances: the band's margin of 2e-9 dwarfs the rounding)
+            constexpr double g = MG_GAP * (1 + 2 * MG_TIE);
+            pass = d2 <= g * g && (cell_ends[k] >> 1) > A;
           }
         }
         const uint64_t m = __ballot(pass);
