@@ -938,7 +938,9 @@ int tpc_decode_zs_pages(tpc_ctx* c, const uint32_t* pages, uint32_t n_pages, tpc
   }
   run_scan<uint32_t>(c, GetPageSamples{pages, out->n_units}, EmitPageOffset{c->zp_off}, nullptr,
                      n_pages, (uint32_t*)nullptr, c->tot32);
-  const uint32_t g = n_pages < 4096 ? n_pages : 4096;
+  // pages per workgroup in turn (a 2 ms Pb-Pb slice's 86,836 pages: 1.18 ms
+  // with 4096 workgroups, 1.11 with 16384, 1.13 with one per page)
+  const uint32_t g = n_pages < 16384 ? n_pages : 16384;
   k_zs_decode<<<g, ZSP_BLOCK, 0, s>>>(pages, n_pages, out->n_units, out->n_time_bins, c->zp_off,
                                       out->capacity, out->pad, out->time, out->adc, c->d_par,
                                       c->d_st);
