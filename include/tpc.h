@@ -245,8 +245,9 @@ int tpc_workspace_size(const tpc_sizes* max, size_t* bytes);
 int tpc_create(tpc_ctx** out, const tpc_params* p, const tpc_sizes* max, void* hip_stream);
 int tpc_destroy(tpc_ctx* ctx);
 
-/* Decode n_pages raw pages (DEVICE pointer, n_pages * TPC_ZS_PAGE_WORDS
- * words, caller-owned, read only) into out's arrays, in page order (section
+/* Decode n_pages raw pages (DEVICE pointer, 16-byte aligned, n_pages *
+ * TPC_ZS_PAGE_WORDS words, caller-owned, read only) into out's arrays, in
+ * page order (section
  * "Hardware and data flow": the readout cards zero-suppress, the EPNs
  * reconstruct).  Writes *out->n_samples and row_start; the arrays then serve
  * as a tpc_zs_input with n_samples = out->capacity (the device count bounds
@@ -257,8 +258,9 @@ int tpc_destroy(tpc_ctx* ctx);
  * pages and ADC values above zero.  A decoded count above out->capacity
  * gives TPC_ERR_CAPACITY with the count needed in tpc_counts.required, and
  * the pages that do not fit are not written.  Host errors (TPC_ERR_ARG):
- * missing pointers, n_units or n_time_bins beyond the context's bounds,
- * n_pages above max_samples / 16 + 152 * max_units. */
+ * missing pointers, a pages pointer not 16-byte aligned, n_units or
+ * n_time_bins beyond the context's bounds, n_pages above max_samples / 16 +
+ * 152 * max_units. */
 int tpc_decode_zs_pages(tpc_ctx* ctx, const uint32_t* pages, uint32_t n_pages, tpc_zs_soa* out);
 
 /* Clusterizer.  Paper, section "Hardware and data flow": the EPNs run full

@@ -9,7 +9,7 @@
 // set of consecutive pads of one time bin.
 //
 // Work: a device scan of the pages' sample counts gives each page its output
-// offset; one workgroup per page then loads the run table into LDS, scans the
+// offset; a workgroup per page in turn then loads the page into LDS, scans the
 // run lengths, expands them into a per-sample run index and writes every
 // sample at its final index (stores of consecutive samples are consecutive).
 // Bound: HBM (each page is read once, 6 bytes written per sample).
@@ -31,11 +31,10 @@ struct ZsPageHdr {
   bool ok;         // header well formed and the page's fields fit it
 };
 
-// Header of page p.  A page whose header is malformed counts no samples.
-__device__ __forceinline__ ZsPageHdr zsp_header(const uint32_t* __restrict__ pages, uint32_t p,
-                                                uint32_t n_units) {
-  const uint32_t* pg = pages + (size_t)p * ZSP_WORDS;
-  const uint32_t w0 = pg[0], w1 = pg[1], w2 = pg[2], w3 = pg[3];
+// Header of a page from its first four words.  A page whose header is
+// malformed counts no samples.
+__device__ __forceinline__ ZsPageHdr zsp_header_of(uint32_t w0, uint32_t w1, uint32_t w2,
+                                                   uint32_t w3, uint32_t n_units) {
   ZsPageHdr h;
   const uint32_t unit = w1 & 0xFFFFu, row = (w1 >> 16) & 0xFFu;
   h.nruns = w2 & 0xFFFFu;
@@ -47,6 +46,12 @@ __device__ __forceinline__ ZsPageHdr zsp_header(const uint32_t* __restrict__ pag
          (h.nruns > 0) == (h.nsamp > 0);
   if (!h.ok) h.nsamp = 0;
   return h;
+}
+// Header of page p.
+__device__ __forceinline__ ZsPageHdr zsp_header(const uint32_t* __restrict__ pages, uint32_t p,
+                                                uint32_t n_units) {
+  const uint32_t* pg = pages + (size_t)p * ZSP_WORDS;
+  return zsp_header_of(pg[0], pg[1], pg[2], pg[3], n_units);
 }
 
 struct GetPageSamples {
@@ -61,7 +66,12 @@ struct EmitPageOffset {
 
 // Samples of one page at their final indices; also checks every field that
 // the writes depend on (always) and the order and ADC range (validate mode).
+// The page (8 KiB: 8 words per thread) is loaded whole into LDS with one
+// coalesced load per thread, and the next page's load is issued before the
+// current one is decoded, so the run table and the bit stream are read from
+// LDS and only one memory round trip per page is exposed.
 #define ZSP_BLOCK 256
+static_assert(ZSP_WORDS == ZSP_BLOCK * 8, "a page is 8 words per thread");
 __global__ __launch_bounds__(ZSP_BLOCK) void k_zs_decode(const uint32_t* __restrict__ pages,
                                                          uint32_t n_pages, uint32_t n_units,
                                                          uint32_t n_time_bins,
@@ -72,38 +82,50 @@ __global__ __launch_bounds__(ZSP_BLOCK) void k_zs_decode(const uint32_t* __restr
                                                          uint16_t* __restrict__ adc,
                                                          const DevParams* __restrict__ P,
                                                          DevStatus* st) {
-  __shared__ uint32_t runs[ZSP_WORDS];
+  __shared__ __attribute__((aligned(16))) uint32_t pg[ZSP_WORDS];
   __shared__ uint16_t first[ZSP_WORDS];
   __shared__ uint16_t run_of[ZSP_MAX_SAMPLES];
   __shared__ uint32_t lds_scan[ZSP_BLOCK / 64 + 1];
   __shared__ int bad;
   if (failed(st)) return;
   const bool validate = P->validate != 0;
-  for (uint32_t p = blockIdx.x; p < n_pages; p += gridDim.x) {
-    const ZsPageHdr h = zsp_header(pages, p, n_units);
+  const uint4* src = reinterpret_cast<const uint4*>(pages);
+  uint32_t p = blockIdx.x;
+  uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
+  if (p < n_pages) {
+    q0 = src[(size_t)p * (ZSP_WORDS / 4) + threadIdx.x * 2];
+    q1 = src[(size_t)p * (ZSP_WORDS / 4) + threadIdx.x * 2 + 1];
+  }
+  for (; p < n_pages; p += gridDim.x) {
+    __syncthreads();  // the previous page's LDS reads are done
+    reinterpret_cast<uint4*>(pg)[threadIdx.x * 2] = q0;
+    reinterpret_cast<uint4*>(pg)[threadIdx.x * 2 + 1] = q1;
+    const uint32_t pn = p + gridDim.x;
+    if (pn < n_pages) {  // the next page's words, in flight while this one is decoded
+      q0 = src[(size_t)pn * (ZSP_WORDS / 4) + threadIdx.x * 2];
+      q1 = src[(size_t)pn * (ZSP_WORDS / 4) + threadIdx.x * 2 + 1];
+    }
+    const uint32_t o = off[p];
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const ZsPageHdr h = zsp_header_of(pg[0], pg[1], pg[2], pg[3], n_units);
     if (!h.ok) {  // uniform: every thread read the same header
       if (threadIdx.x == 0) latch(st, TPC_ERR_INPUT);
       continue;
     }
-    const uint32_t o = off[p];
     if (h.nsamp == 0) continue;
     if ((uint64_t)o + h.nsamp > capacity) continue;  // overflow, latched by the row kernel
-    const uint32_t* pg = pages + (size_t)p * ZSP_WORDS;
-    const uint32_t* stream = pg + ZSP_HDR + h.nruns;
+    const uint32_t* runs = pg + ZSP_HDR;
+    const uint32_t* stream = runs + h.nruns;
     const int np = P->np[h.ur % NROW];
-    __syncthreads();  // the previous page's LDS reads are done
-    if (threadIdx.x == 0) bad = 0;
-    // the run table, and each thread's 8 consecutive run lengths
+    // each thread's 8 consecutive run lengths
     const uint32_t r0 = threadIdx.x * 8;
     uint32_t len[8];
     uint32_t acc = 0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const uint32_t r = r0 + e;
-      uint32_t w = 0;
-      if (r < h.nruns) w = pg[ZSP_HDR + r];
-      runs[r] = w;
-      len[e] = r < h.nruns ? (w >> 24) + 1 : 0;
+      len[e] = r < h.nruns ? (runs[r] >> 24) + 1 : 0;
       acc += len[e];
     }
     uint32_t sum;

@@ -925,6 +925,7 @@ int tpc_destroy(tpc_ctx* c) {
 
 int tpc_decode_zs_pages(tpc_ctx* c, const uint32_t* pages, uint32_t n_pages, tpc_zs_soa* out) {
   if (!c || !out || !out->n_samples || !out->row_start || (n_pages && !pages)) return TPC_ERR_ARG;
+  if ((uintptr_t)pages & 15) return TPC_ERR_ARG;  // each page is loaded in 16-byte words
   if (check_units(c, out->n_units, out->n_time_bins)) return TPC_ERR_ARG;
   if (out->capacity && (!out->pad || !out->time || !out->adc)) return TPC_ERR_ARG;
   if (n_pages > max_pages(c->max)) return TPC_ERR_ARG;

@@ -151,6 +151,17 @@ def test_malformed_pages_reported():
         reco_v.close()
 
 
+def test_misaligned_pages_rejected():
+    # pages are loaded in 16-byte words: a pointer off that alignment is an
+    # argument error, raised before anything is launched
+    reco = tpc.Reco(1, 500, 4096, 64)
+    words = torch.zeros(2 * tpc.ZS_PAGE_WORDS + 1, dtype=torch.int32, device="cuda")
+    soa = reco.alloc_zs_soa(1, 500, 4096)
+    with pytest.raises(tpc.TpcError):
+        reco.decode_zs_pages(words[1:], soa, n_pages=2)
+    reco.close()
+
+
 def test_capacity_overflow_reported():
     pages, nu, T, exp = load_example()
     c, _, _ = _decode(pages, nu, T, capacity=5)
