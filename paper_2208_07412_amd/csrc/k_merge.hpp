@@ -344,7 +344,9 @@ __global__ __launch_bounds__(256) void k_mg_pairs(MgSegs S, uint32_t nzb,
 }
 
 // Global position of every hit of every track (the fit reads it three times):
-// one lane per track walks its hits, which ascend through the rows of one unit.
+// one thread per hit, its cluster's (unit,row) found by a binary search of the
+// row starts (one lane per track walking its hits took 0.68 ms on a 2 ms
+// Pb-Pb slice, the longest tracks setting the pace; per hit: 0.21 ms).
 __global__ void k_mg_hits(const uint32_t* __restrict__ crow, uint32_t n_ur,
                           const int32_t* __restrict__ y_fx, const uint32_t* n_cl_dev,
                           uint32_t cl_cap, const uint32_t* __restrict__ hit_start,
@@ -355,22 +357,16 @@ __global__ void k_mg_hits(const uint32_t* __restrict__ crow, uint32_t n_ur,
   if (failed(st)) return;
   const uint32_t n = scan_count(n_trk_dev, trk_cap);
   const uint32_t n_cl = scan_count(n_cl_dev, cl_cap);
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    uint32_t h0 = hit_start[j], h1 = hit_start[j + 1];
-    if (h1 > hit_cap) h1 = hit_cap;
-    if (h0 >= h1) continue;
-    uint32_t ur = mg_ur_of(crow, n_ur, hits[h0] < n_cl ? hits[h0] : 0);
-    for (uint32_t h = h0; h < h1; ++h) {
-      const uint32_t c = hits[h] < n_cl ? hits[h] : 0;
-      // ascending rows: walk forward; anything else falls back to the search
-      while (ur + 1 < n_ur && crow[ur + 1] <= c) ++ur;
-      if (c < crow[ur]) ur = mg_ur_of(crow, n_ur, c);
-      const uint32_t s18 = (ur / NROW) % 36 % 18;
-      const double ca = cs18[2 * s18], sa = cs18[2 * s18 + 1];
-      const double x = P->xd[ur % NROW], y = y_fx[c] / 65536.0;
-      hxy[2 * (size_t)h] = x * ca - y * sa;
-      hxy[2 * (size_t)h + 1] = x * sa + y * ca;
-    }
+  uint32_t nh = n ? hit_start[n] : 0;  // the tracks' hits are [0, hit_start[n])
+  if (nh > hit_cap) nh = hit_cap;
+  for (uint32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
+    const uint32_t c = hits[h] < n_cl ? hits[h] : 0;
+    const uint32_t ur = mg_ur_of(crow, n_ur, c);
+    const uint32_t s18 = (ur / NROW) % 36 % 18;
+    const double ca = cs18[2 * s18], sa = cs18[2 * s18 + 1];
+    const double x = P->xd[ur % NROW], y = y_fx[c] / 65536.0;
+    hxy[2 * (size_t)h] = x * ca - y * sa;
+    hxy[2 * (size_t)h + 1] = x * sa + y * ca;
   }
 }
 

@@ -1062,7 +1062,7 @@ int tpc_merge_tracks(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, t
   k_mg_pairs<<<grid_for(2 * (uint64_t)cap, 256, 8192), 256, 0, s>>>(
       S, nzb, c->tot32, c->mg_off, c->mg_ends, c->mg_cell, c->mg_pk, c->mg_parent, out->near_tie,
       c->d_st);
-  k_mg_hits<<<grid_for(cap, 256, 4096), 256, 0, s>>>(
+  k_mg_hits<<<grid_for(hit_bound, 256, 16384), 256, 0, s>>>(
       cl->crow_start, n_ur, cl->y_fx, cl->n_clusters, cl->capacity, tr->hit_start, tr->hits,
       hit_bound, tr->n_tracks, cap, c->mg_cs18, c->mg_hxy, c->d_par, c->d_st);
   k_mg_labels<<<grid_for(cap, 256, 4096), 256, 0, s>>>(c->mg_parent, tr->n_tracks, cap, out->label,
