@@ -301,16 +301,24 @@ __global__ __launch_bounds__(256) void k_mg_pairs(MgSegs S, uint32_t nzb,
       }
       const uint32_t len = k1 - k0;
       const uint32_t maxlen = (uint32_t)wave_max_i32((int32_t)len);
-      // each candidate's drift z is loaded one candidate ahead of its test
-      double bz_next = len > 0 ? pk[3 * (size_t)k0] : 0.0;
+      // each candidate's gate data is loaded one candidate ahead of its test
+      double bz_next = 0.0, bx_next = 0.0, by_next = 0.0;
+      if (len > 0) {
+        bz_next = pk[3 * (size_t)k0];
+        bx_next = pk[3 * (size_t)k0 + 1];
+        by_next = pk[3 * (size_t)k0 + 2];
+      }
       for (uint32_t it = 0; it < maxlen; ++it) {
         bool pass = false;
         const uint32_t k = k0 + it;
-        const double bz = bz_next;
-        if (it + 1 < len) bz_next = pk[3 * (size_t)(k + 1)];
+        const double bz = bz_next, bx = bx_next, by = by_next;
+        if (it + 1 < len) {
+          bz_next = pk[3 * (size_t)(k + 1)];
+          bx_next = pk[3 * (size_t)(k + 1) + 1];
+          by_next = pk[3 * (size_t)(k + 1) + 2];
+        }
         if (it < len) {
           if (fabs(az - bz) <= MG_DZMAX) {
-            const double bx = pk[3 * (size_t)k + 1], by = pk[3 * (size_t)k + 2];
             const double d2 = (ax - bx) * (ax - bx) + (ay - by) * (ay - by);
             // beyond the near-tie band of the gap cut nothing can pass or tie
             // (squared distances: the band's margin of 2e-9 dwarfs the rounding)
