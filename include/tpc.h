@@ -11,8 +11,10 @@
  *   tpc_build_tracklets    links -> cleaned links + tracklets
  *   tpc_fit_tracks         tracklets -> followed, resolved, refitted tracks
  *   tpc_process_timeframe  all four in one launch sequence
- * and, beside them, tpc_qc_histograms (quality-control histograms of the
- * outputs).
+ * and, beside them, tpc_decode_zs_pages (raw zero-suppressed pages -> the
+ * samples), tpc_compress / tpc_decompress (track-model cluster compression),
+ * tpc_merge_tracks (segment merging and the T0 / z fit) and
+ * tpc_qc_histograms (quality-control histograms of the outputs).
  *
  * Conventions
  *   - Every array pointer inside the structs below is a DEVICE pointer,
@@ -201,7 +203,8 @@ typedef struct {
   int32_t status;             /* first latched error (tpc_status) */
   uint32_t required;          /* capacity that an overflow needed */
   uint32_t n_samples, n_clusters, n_tracklets, n_tracks, n_hits;
-  uint32_t n_fallback;        /* refits redone in FP64 (PD check or cancellation guard) */
+  uint32_t n_fallback;        /* refits redone in FP64 (low-pT tracks whose FP32
+                                 pivots failed, or every track under force_fallback) */
   uint32_t n_fallback_fail;   /* FP64 refits still not PD (dropped) */
   uint32_t n_not_pd;          /* high-pT tracks flagged not PD */
   uint32_t n_refit_fail;      /* tracks dropped by a failed refit step */
@@ -496,7 +499,7 @@ void* tpc_stream(tpc_ctx* ctx);
  * (peak finding and moments, one pass over the samples), 2 cluster scan,
  * 3 cluster output, 4 cluster grid, 5 neighbours, 6 tracklets (and their
  * seed points, timed inside the fit call), 7 following (sorts and passes),
- * 8 resolution, 9 refit (FP64 head, FP32, FP64 redo), 10 count of the FP64
+ * 8 resolution, 9 refit (FP32, FP64 redo of failing low-pT tracks), 10 count of the FP64
  * redos, 11 track output, 12 raw ZS page decoding (tpc_decode_zs_pages),
  * 13 compression (tpc_compress), 14 decompression (tpc_decompress), 15 merging
  * and the T0 fit (tpc_merge_tracks). */
