@@ -438,14 +438,18 @@ __global__ __launch_bounds__(64) void k_mg_fit(const uint32_t* __restrict__ skey
       if (h1 > hit_cap) h1 = hit_cap;
       if (h0 > h1) h0 = h1;
     };
+    // every pass loads the next hit's data one hit ahead of its use (same
+    // order of the sums)
     double sx = 0, sy = 0;
     int64_t nh = 0;
     for (uint32_t m = i; m < end; ++m) {
       uint32_t h0, h1;
       hit_range(sidx[m], h0, h1);
+      double Xn = 0, Yn = 0;
+      if (h0 < h1) hit_xy(h0, Xn, Yn);
       for (uint32_t h = h0; h < h1; ++h) {
-        double X, Y;
-        hit_xy(h, X, Y);
+        const double X = Xn, Y = Yn;
+        if (h + 1 < h1) hit_xy(h + 1, Xn, Yn);
         sx += X;
         sy += Y;
         ++nh;
@@ -458,9 +462,11 @@ __global__ __launch_bounds__(64) void k_mg_fit(const uint32_t* __restrict__ skey
     for (uint32_t m = i; m < end; ++m) {
       uint32_t h0, h1;
       hit_range(sidx[m], h0, h1);
+      double Xn = 0, Yn = 0;
+      if (h0 < h1) hit_xy(h0, Xn, Yn);
       for (uint32_t h = h0; h < h1; ++h) {
-        double X, Y;
-        hit_xy(h, X, Y);
+        const double X = Xn, Y = Yn;
+        if (h + 1 < h1) hit_xy(h + 1, Xn, Yn);
         const double u = X - mx, v = Y - my;
         suu += u * u;
         svv += v * v;
@@ -485,13 +491,23 @@ __global__ __launch_bounds__(64) void k_mg_fit(const uint32_t* __restrict__ skey
     for (uint32_t m = i; m < end; ++m) {
       uint32_t h0, h1;
       hit_range(sidx[m], h0, h1);
+      double Xn = 0, Yn = 0;
+      int32_t zn = 0;
+      if (h0 < h1) {
+        hit_xy(h0, Xn, Yn);
+        zn = z_fx[hits[h0]];
+      }
       for (uint32_t h = h0; h < h1; ++h) {
-        double X, Y;
-        hit_xy(h, X, Y);
+        const double X = Xn, Y = Yn;
+        const int32_t zq = zn;
+        if (h + 1 < h1) {
+          hit_xy(h + 1, Xn, Yn);
+          zn = z_fx[hits[h + 1]];
+        }
         const double psi = atan2(Y - yc, X - xc);
         acc = k == 0 ? 0.0 : acc + mg_wrap(psi - psi_prev);
         psi_prev = psi;
-        const double z = z_fx[hits[h]] / 65536.0;
+        const double z = zq / 65536.0;
         sp += acc;
         sp2 += acc * acc;
         sz += z;
