@@ -1007,6 +1007,21 @@ __device__ __forceinline__ uint32_t bid_info(const FollowOut& fo, uint32_t t0, u
   return (int)nh >= min_hits ? 1u | (nh << 8) | ((uint32_t)fo.range[t] << 16) : 0u;
 }
 
+// The hit-table entries of the first 64 rows of each bidding tracklet of a
+// group (lane l: row lo + l, or -1), loaded together so that their latencies
+// overlap instead of coming one tracklet after the other.
+__device__ __forceinline__ void first_rows(const FollowOut& fo, uint32_t t0, uint32_t info,
+                                           int32_t (&first)[KEEP_GROUP]) {
+  const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+  for (int kk = 0; kk < KEEP_GROUP; ++kk) {
+    const uint32_t inf = (uint32_t)__builtin_amdgcn_readlane((int)info, kk);
+    const int lo = (inf >> 16) & 255, hi = inf >> 24;
+    const int r = lo + lane;
+    first[kk] = inf && r <= hi ? fo.hits[(size_t)(t0 + kk) * NROW + r] : -1;
+  }
+}
+
 // Every followed tracklet with enough hits bids for its clusters: the owner
 // of a cluster is the largest key among its bidders.  Two launches instead of
 // one atomicMax per hit: FIX = false stores every bidder's key (one of them
@@ -1034,16 +1049,20 @@ __global__ __launch_bounds__(256) void k_claim(FollowOut fo, const uint32_t* n_t
     const uint32_t g = FIX ? i : n_grp - 1 - i;
     const uint32_t t0 = g * KEEP_GROUP, t1 = min(t0 + KEEP_GROUP, n_tl);
     const uint32_t info = bid_info(fo, t0, t1, P->min_track_hits);
-    for (uint32_t k = 0; k < t1 - t0; ++k) {
-      const uint32_t kk = FIX ? k : t1 - t0 - 1 - k;
-      const uint32_t inf = (uint32_t)__builtin_amdgcn_readlane((int)info, (int)kk);
+    int32_t first[KEEP_GROUP];
+    first_rows(fo, t0, info, first);
+#pragma unroll
+    for (int k = 0; k < KEEP_GROUP; ++k) {
+      const int kk = FIX ? k : KEEP_GROUP - 1 - k;
+      if (kk >= (int)(t1 - t0)) continue;
+      const uint32_t inf = (uint32_t)__builtin_amdgcn_readlane((int)info, kk);
       if (!inf) continue;
       const uint32_t t = t0 + kk;
       const uint32_t key = track_key((inf >> 8) & 255, t);
       const int lo = (inf >> 16) & 255, hi = inf >> 24;
       const int32_t* H = fo.hits + (size_t)t * NROW;
       for (int r = lo + (int)lane; r <= hi; r += 64) {
-        const int32_t c = H[r];
+        const int32_t c = r < lo + 64 ? first[kk] : H[r];
         if (c < 0 || (uint32_t)c >= n_cl_cap) continue;
         if (!FIX) owner[c] = key;
         else if (owner[c] < key) atomicMax(&owner[c], key);
@@ -1073,9 +1092,14 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
     const uint32_t t0 = g * KEEP_GROUP, t1 = min(t0 + KEEP_GROUP, n_tl);
     uint32_t mine = 0;
     const uint32_t info = bid_info(fo, t0, t1, P->min_track_hits);
-    for (uint32_t t = t0; t < t1; ++t) {
+    int32_t first[KEEP_GROUP];
+    first_rows(fo, t0, info, first);
+#pragma unroll
+    for (int kk = 0; kk < KEEP_GROUP; ++kk) {
+      const uint32_t t = t0 + kk;
+      if (t >= t1) continue;
       uint32_t n = 0;
-      const uint32_t inf = (uint32_t)__builtin_amdgcn_readlane((int)info, (int)(t - t0));
+      const uint32_t inf = (uint32_t)__builtin_amdgcn_readlane((int)info, kk);
       if (inf) {
         const uint32_t key = track_key((inf >> 8) & 255, t);
         const int lo = (inf >> 16) & 255, hi = inf >> 24;
@@ -1085,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
           const int r = r0 + (int)lane;
           bool kept = false;
           if (r <= hi) {
-            const int32_t c = H[r];
+            const int32_t c = r0 == lo ? first[kk] : H[r];
             kept = c >= 0 && (uint32_t)c < n_cl_cap && owner[c] == key;
           }
           const uint64_t m = __ballot(kept);
@@ -1094,7 +1118,7 @@ __global__ __launch_bounds__(256) void k_keep(FollowOut fo, const uint32_t* n_tl
         }
         if ((int)n < P->min_track_hits) n = 0;
       }
-      if (lane == t - t0) mine = n;
+      if (lane == (uint32_t)kk) mine = n;
     }
     if (t0 + lane < t1) {
       nkept[t0 + lane] = (uint16_t)mine;
