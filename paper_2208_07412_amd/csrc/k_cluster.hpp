@@ -673,12 +673,11 @@ template <int W, int NW>
 struct PeaksLdsMw {
   __attribute__((aligned(16))) uint16_t tile[(W + 2 * CL_TH) * CL_TP];
   unsigned long long acc0[NW * MW_SW(NW)], acc1[NW * MW_SW(NW)];
-  uint32_t grp[MW_GROUPS(W) + 1];  // core peaks per step, then their exclusive prefix
+  uint32_t grp[MW_GROUPS(W) + 1];  // core peaks per 64-sample step (ranks sum them)
   uint16_t pk_cell[NW * MW_SW(NW)];
   uint16_t pk_gi[NW * MW_SW(NW)];  // step << 6 | rank within the step
   uint16_t pk_a[NW * MW_SW(NW)];   // the peak's ADC
   uint32_t wcnt[NW];               // slots used by each wave in the batch
-  uint32_t total;
 };
 
 template <int PRE, int NT>
