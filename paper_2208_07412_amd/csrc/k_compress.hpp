@@ -36,12 +36,24 @@ __device__ __forceinline__ int64_t cm_q(int64_t v) { return (v + 256) >> CM_QSHI
 __device__ __forceinline__ int64_t cm_rshift(int64_t a, int k) {
   return (a + ((int64_t)1 << (k - 1))) >> k;
 }
-// a / d rounded to the nearest integer, halves up (d > 0)
+// a / d rounded to the nearest integer, halves up: floor((2a + d) / 2d).  In
+// the helix step 2^25 < d <= 2^31 and |a| < 2^56, so the quotient is below
+// 2^31 and the double quotient (two roundings, relative error <= 2^-52) is
+// within 2^-21 of it: its floor is off by at most one, which the exact
+// remainder repairs.  (A 64-bit integer division is a long software sequence
+// on the GPU.)
 __device__ __forceinline__ int64_t cm_rdiv(int64_t a, int64_t d) {
-  return floor_div64(2 * a + d, 2 * d);
+  const int64_t n = 2 * a + d, m = 2 * d;
+  int64_t q = (int64_t)floor((double)n / (double)m);
+  const int64_t r = n - q * m;
+  if (r < 0) --q;
+  else if (r >= m) ++q;
+  return q;
 }
 // floor(sqrt(n)), n >= 0: the double square root, then exact corrections
+// (0 for n <= 0, which only a malformed record reaches)
 __device__ __forceinline__ int64_t cm_isqrt(int64_t n) {
+  if (n <= 0) return 0;
   int64_t r = (int64_t)sqrt((double)n);
   while (r > 0 && r * r > n) --r;
   while ((r + 1) * (r + 1) <= n) ++r;
@@ -61,9 +73,11 @@ __device__ __forceinline__ uint32_t cm_eg_len(uint64_t v, int k) {
 }
 
 // Integer helix of one track (y, z in 2^-16 cm; sin phi, tan lambda in 2^-30;
-// C in 2^-46 per cm), stepped outward one row at a time.
+// C in 2^-46 per cm), stepped outward one row at a time.  Sc is
+// floor(sqrt(2^60 - S^2)) of the current S, kept so that a step computes one
+// such root for its new S instead of two.
 struct CmModel {
-  int64_t Y, Z, S, T, C;
+  int64_t Y, Z, S, T, C, Sc;
   int row;
   bool frozen;
 };
@@ -92,7 +106,8 @@ __device__ __forceinline__ CmParams cm_params(const float* p, int32_t z_anchor) 
 }
 
 __device__ __forceinline__ CmModel cm_model(const CmParams& q, int64_t b30, int row) {
-  return CmModel{q.Y, q.Z, q.S, q.T, -b30 * q.K, row, false};
+  return CmModel{q.Y, q.Z, q.S, q.T, -b30 * q.K, cm_isqrt(((int64_t)1 << 60) - q.S * q.S), row,
+                 false};
 }
 
 __device__ __forceinline__ void cm_step(CmModel& m, const int32_t* xfx) {
@@ -107,12 +122,13 @@ __device__ __forceinline__ void cm_step(CmModel& m, const int32_t* xfx) {
     return;
   }
   const int64_t one = (int64_t)1 << 60;
-  const int64_t c0 = cm_isqrt(one - m.S * m.S), c1 = cm_isqrt(one - S1 * S1);
-  const int64_t F = cm_rdiv((m.S + S1) * ((int64_t)1 << 24), c0 + c1);
+  const int64_t c1 = cm_isqrt(one - S1 * S1);
+  const int64_t F = cm_rdiv((m.S + S1) * ((int64_t)1 << 24), m.Sc + c1);
   m.Y += cm_rshift(D * F, 24);
   const int64_t L = cm_rshift(D * cm_isqrt(((int64_t)1 << 48) + F * F), 24);
   m.Z += cm_rshift(m.T * L, 30);
   m.S = S1;
+  m.Sc = c1;
 }
 
 // (unit,row) of cluster c: the last entry of crow[0..n_ur) not above c
@@ -388,13 +404,15 @@ __global__ __launch_bounds__(256) void k_cm_track_bits(CmClusters cl, CmTracks t
                                                        uint64_t* __restrict__ res, uint32_t res_cap,
                                                        DevStatus* st) {
   __shared__ uint32_t h[256];
+  __shared__ int32_t xs[NROW];  // row radii: the helix steps read them per lane
   if (failed(st)) return;
   for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+  for (uint32_t i = threadIdx.x; i < NROW; i += blockDim.x) xs[i] = P->xfx[i];
   __syncthreads();
   const uint32_t n = scan_count(tr.n_dev, tr.cap);
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     uint64_t bits = 0;
-    if (!cm_track<false>(cl, tr, j, b30, P->xfx, bits, nullptr, hist_out ? h : nullptr, res,
+    if (!cm_track<false>(cl, tr, j, b30, xs, bits, nullptr, hist_out ? h : nullptr, res,
                          res_cap))
       latch(st, TPC_ERR_INPUT);
     tbits[j] = (uint32_t)(bits < 0xFFFFFFFFull ? bits : 0xFFFFFFFFull);
@@ -580,7 +598,10 @@ __global__ __launch_bounds__(256) void k_cm_track_write(CmClusters cl, CmTracks 
                                                         const uint32_t* info,
                                                         const uint64_t* __restrict__ res,
                                                         uint32_t res_cap, DevStatus* st) {
+  __shared__ int32_t xs[NROW];  // row radii, for tracks whose residuals were not kept
   if (failed(st) || info[0] == 0) return;
+  for (uint32_t i = threadIdx.x; i < NROW; i += blockDim.x) xs[i] = P->xfx[i];
+  __syncthreads();
   const uint32_t n = scan_count(tr.n_dev, tr.cap);
   uint32_t* payload = s + info[1];
   const uint64_t pw = info[0] - info[1];
@@ -588,7 +609,7 @@ __global__ __launch_bounds__(256) void k_cm_track_write(CmClusters cl, CmTracks 
     CmWriter w;
     w.init(payload, pw, s[CM_HDR + j]);
     uint64_t bits = 0;
-    cm_track<true>(cl, tr, j, b30, P->xfx, bits, &w, nullptr, const_cast<uint64_t*>(res), res_cap);
+    cm_track<true>(cl, tr, j, b30, xs, bits, &w, nullptr, const_cast<uint64_t*>(res), res_cap);
     w.flush();
   }
 }
@@ -861,7 +882,10 @@ __global__ __launch_bounds__(256) void k_cm_dec_tracks(const uint32_t* __restric
                                                        int64_t b30, const DevParams* __restrict__ P,
                                                        CmDecOut o, DevStatus* st) {
   __shared__ uint32_t stage[4][CM_STAGE_WORDS];
+  __shared__ int32_t xs[NROW];  // row radii: the helix steps read them per lane
   if (failed(st) || !info[6]) return;
+  for (uint32_t i = threadIdx.x; i < NROW; i += blockDim.x) xs[i] = P->xfx[i];
+  __syncthreads();
   const uint32_t nu = info[0], nt = info[1], nc = info[2];
   const uint64_t bits = info[3];
   const uint32_t* pay = s + info[4];
@@ -893,10 +917,10 @@ __global__ __launch_bounds__(256) void k_cm_dec_tracks(const uint32_t* __restric
       bool ok;
       if (in_lds) {
         CmReaderT<lds_u32*> r((lds_u32*)stage[w], start, b1, false, w0);
-        ok = cm_decode_record(r, i, nu, nt, nc, off[i], end, b30, P->xfx, o);
+        ok = cm_decode_record(r, i, nu, nt, nc, off[i], end, b30, xs, o);
       } else {
         CmReader r(pay, start, bits, false, 0);
-        ok = cm_decode_record(r, i, nu, nt, nc, off[i], end, b30, P->xfx, o);
+        ok = cm_decode_record(r, i, nu, nt, nc, off[i], end, b30, xs, o);
       }
       if (!ok) latch(st, TPC_ERR_INPUT);
     }
