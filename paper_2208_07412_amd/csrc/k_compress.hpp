@@ -349,13 +349,25 @@ __device__ bool cm_track(const CmClusters& cl, const CmTracks& tr, uint32_t j, i
   int prev = r0;
   bool ok = true;
   const bool cached = res != nullptr && h1 <= res_cap;
+  // the next hit's cluster index is loaded one hit ahead
+  uint32_t c_next = h1 > h0 ? tr.hits[h0] : 0;
   for (uint32_t h = h0; h < h1; ++h) {
-    uint32_t c = tr.hits[h];
+    uint32_t c = c_next;
+    if (h + 1 < h1) c_next = tr.hits[h + 1];
     if (c >= n_cl) {
       ok = false;
       c = 0;
     }
-    while (ur + 1 < cl.n_ur && cl.crow[ur + 1] <= c) ++ur;
+    // the hit's (unit,row): the last row start not above c.  A track's rows
+    // mostly step out by one, so each probe reads the next two row starts at
+    // once (one memory round trip where one at a time takes two).
+    for (;;) {
+      const uint32_t a = ur + 1 < cl.n_ur ? cl.crow[ur + 1] : 0xFFFFFFFFu;
+      const uint32_t b = ur + 2 < cl.n_ur ? cl.crow[ur + 2] : 0xFFFFFFFFu;
+      const uint32_t adv = (uint32_t)(a <= c) + (uint32_t)(a <= c && b <= c);
+      ur += adv;
+      if (adv < 2) break;
+    }
     const int r = (int)(ur % NROW);
     const int step = r - prev - (h > h0 ? 1 : 0);
     if (step < 0) ok = false;
