@@ -252,8 +252,9 @@ __device__ __forceinline__ void mg_pair_check(const MgSegs& S, const uint32_t* c
 
 // One lane per end, ends taken in cell order (the lanes of a wave mostly
 // share their cells and so scan the same neighbour cells in step): the ends of
-// later segments in the 3 x 3 x 3 cells around it are gated on the packed drift z
-// and position; the pairs that pass go to the wave's queue in LDS, and every
+// later segments in the 3 x 3 x 3 cells around it (nine runs of three
+// consecutive drift cells) are gated on the packed drift z and position; the
+// pairs that pass go to the wave's queue in LDS, and every
 // 64 of them are tested by the 64 lanes together (the full test is long and
 // few lanes pass a gate at a time).
 #define MG_QCAP 128
@@ -290,14 +291,18 @@ __global__ __launch_bounds__(256) void k_mg_pairs(MgSegs S, uint32_t nzb,
       ay = pk[3 * (size_t)t + 2];
     }
     uint32_t qn = 0;  // queued pairs (the same in every lane)
-    for (int ci = 0; ci < 27; ++ci) {
-      const int dy = ci / 9 - 1, dx = (ci / 3) % 3 - 1, dz = ci % 3 - 1;
+    for (int ci = 0; ci < 9; ++ci) {
+      const int dy = ci / 3 - 1, dx = ci % 3 - 1;
       uint32_t k0 = 0, k1 = 0;
-      const int z2 = (int)zb + dz, x2 = (int)ix + dx, y2 = (int)iy + dy;
-      if (have && z2 >= 0 && z2 < (int)nzb && x2 >= 0 && x2 < MG_NXY && y2 >= 0 && y2 < MG_NXY) {
-        const uint32_t c2 = ((fs * MG_NXY + (uint32_t)y2) * MG_NXY + (uint32_t)x2) * nzb + (uint32_t)z2;
-        k0 = cell_off[c2];
-        k1 = cell_off[c2 + 1];
+      const int x2 = (int)ix + dx, y2 = (int)iy + dy;
+      if (have && x2 >= 0 && x2 < MG_NXY && y2 >= 0 && y2 < MG_NXY) {
+        // the drift cells zb - 1, zb, zb + 1 (those that exist) of a
+        // neighbouring (x, y) cell are consecutive cells: their ends form one
+        // run, taken in the same order as cell by cell
+        const uint32_t cb = ((fs * MG_NXY + (uint32_t)y2) * MG_NXY + (uint32_t)x2) * nzb;
+        const uint32_t zlo = zb > 0 ? zb - 1 : 0, zhi = zb + 1 < nzb ? zb + 1 : nzb - 1;
+        k0 = cell_off[cb + zlo];
+        k1 = cell_off[cb + zhi + 1];
       }
       const uint32_t len = k1 - k0;
       const uint32_t maxlen = (uint32_t)wave_max_i32((int32_t)len);
