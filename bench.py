@@ -173,7 +173,7 @@ def stress_errors(gpu, res, floors=(1.0, 1.0, 1e-2, 1e-2, 0.1)):
 
 
 def cpu_baseline(ev, stress=None, target_s=10.0):
-    """The oracle as it stands, on the GPU machine's host cores: all threads of
+    """The oracle as it stands, on this machine's host cores: all threads of
     one GPU's CPU share on the whole 2 ms slice (the reported value), one
     thread on a bounded sample of its units, and both on one sector (C1) and
     one central collision (C2).  With the precision-stress chunk's GPU tracks

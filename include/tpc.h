@@ -278,7 +278,8 @@ int tpc_decode_zs_pages(tpc_ctx* ctx, const uint32_t* pages, uint32_t n_pages, t
 int tpc_cluster(tpc_ctx* ctx, const tpc_zs_input* in, tpc_clusters* out);
 
 /* Cellular-automaton neighbour finding (same passage: the tracking step of
- * the full reconstruction; the rule is this build's reading).
+ * the full reconstruction; the paper gives no rule, this is the library's
+ * reading).
  * For each cluster in rows 1..150: the pair (j in row r-1, k in row r+1)
  * inside the windows minimising (2y_i-y_j-y_k)^2 + (2z_i-z_j-z_k)^2 <= s_max,
  * ties to the smaller (j, k).  Writes down/up. */
@@ -292,7 +293,7 @@ int tpc_build_tracklets(tpc_ctx* ctx, const tpc_clusters* cl, tpc_links* links,
 
 /* Track fit (same passage: the track reconstruction that TPC calibration
  * and compression rely on; the Kalman filter of a helix in a uniform field is
- * this build's reading).
+ * the library's reading).
  * Kalman following (outward pass A, inward pass B), conflict resolution
  * (each cluster kept by the track with the most hits, then the lower
  * tracklet id) and the inward FP32 refit with FP64 fallback for low-pT

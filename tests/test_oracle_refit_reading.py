@@ -2,19 +2,19 @@
 
 Two readings of "refit the kept hits" were considered:
 
-* survey reading: take the pass-B state at its innermost row, propagate it
+* pass-B reading: take the pass-B state at its innermost row, propagate it
   out to the outermost kept row, reset the covariance to the seed covariance
   (sigma_y, sigma_z of one measurement, 0.1, 0.1, 10) and filter inward;
 * chosen reading (the oracle's): start from the circle through the
   innermost, middle and outermost kept clusters at the outermost one, with a
   broad prior (5 cm, 5 cm, 0.5, 0.5, 10), and filter inward.
 
-The survey reading treats the propagated pass-B state as a measurement of y
+The pass-B reading treats the propagated pass-B state as a measurement of y
 and z at the outermost row with the error of one cluster, although it comes
 from a propagation over up to 150 rows.  Against generator truth this shows
 as wider q/pT pulls and more outliers; the chosen reading's result depends on
 the kept clusters alone.  This test computes both readings on the same kept
-hit sets (the survey reading from the oracle's pass-B state with its exposed
+hit sets (the pass-B reading from the oracle's pass-B state with its exposed
 propagation and Kalman primitives) and compares their q/pT pulls.
 """
 import numpy as np
@@ -32,7 +32,7 @@ def _pulls(seeds):
     rp = dict(PAR, snp_max=PAR["refit_snp_max"])
     C0 = np.diag([PAR["sigma_y"][0] ** 2, PAR["sigma_z"][0] ** 2, PAR["c0_snp"] ** 2,
                   PAR["c0_tgl"] ** 2, PAR["c0_qpt"] ** 2])
-    chosen, survey, survey_fail = [], [], 0
+    chosen, passb, passb_fail = [], [], 0
     for seed in seeds:
         ev = tpcsynth.generate(tpcsynth.config_small(1500, sector_mode=0), seed)
         res = oracle.process(ev.pad, ev.time, ev.adc, ev.row_start, ev.n_units, ev.n_time_bins,
@@ -60,8 +60,8 @@ def _pulls(seeds):
             rd, cd = rows[order], c[order]
             rc, p = oracle.helix_propagate(pb[:5], X[int(pb[5])], X[rd[0]], rp)
             if rc:
-                survey_fail += 1
-                survey.append(np.inf)
+                passb_fail += 1
+                passb.append(np.inf)
                 continue
             anchor = int(cl["z_fx"][tl["tl_start"][t]])
             my = cl["y_fx"][cd] / 65536.0
@@ -70,22 +70,22 @@ def _pulls(seeds):
             vz = [PAR["sigma_z"][r] ** 2 for r in rd]
             rc, p2, C2, _ = oracle.kalman_fit(rd, my, mz, vy, vz, p, C0, params=rp)
             if rc in (1, 2):
-                survey_fail += 1
-                survey.append(np.inf)
+                passb_fail += 1
+                passb.append(np.inf)
                 continue
-            survey.append((p2[4] - q_true) / np.sqrt(C2[4, 4]))
-    return np.abs(np.array(chosen)), np.abs(np.array(survey)), survey_fail
+            passb.append((p2[4] - q_true) / np.sqrt(C2[4, 4]))
+    return np.abs(np.array(chosen)), np.abs(np.array(passb)), passb_fail
 
 
 def test_chosen_refit_start_gives_narrower_pulls_than_the_pass_b_start():
-    chosen, survey, survey_fail = _pulls([1000, 1001])
+    chosen, passb, passb_fail = _pulls([1000, 1001])
     n = len(chosen)
     assert n > 5000
-    q68_c, q68_s = np.percentile(chosen, 68.27), np.percentile(survey, 68.27)
-    out_c, out_s = np.mean(chosen > 5), np.mean(survey > 5)
+    q68_c, q68_s = np.percentile(chosen, 68.27), np.percentile(passb, 68.27)
+    out_c, out_s = np.mean(chosen > 5), np.mean(passb > 5)
     print(f"q/pT pulls on {n} tracks: 68% quantile of |pull| chosen {q68_c:.3f}, "
-          f"survey reading {q68_s:.3f}; |pull| > 5: {out_c:.4f} vs {out_s:.4f} "
-          f"(survey reading failures {survey_fail})")
+          f"pass-B reading {q68_s:.3f}; |pull| > 5: {out_c:.4f} vs {out_s:.4f} "
+          f"(pass-B reading failures {passb_fail})")
     assert q68_c < q68_s - 0.04
     assert out_c < out_s
     assert np.all(np.isfinite(chosen))
