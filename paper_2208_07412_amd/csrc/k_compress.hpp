@@ -407,8 +407,96 @@ __device__ bool cm_track(const CmClusters& cl, const CmTracks& tr, uint32_t j, i
   return ok;
 }
 
-// Per-track record lengths and the residual histograms (per workgroup in
-// LDS, then added to the caller's histogram).
+// (unit,row) of cluster c found by a whole wave (every lane gets it): the
+// last entry of crow[0..n_ur) not above c, as cm_find_ur; each round probes
+// 64 evenly spaced entries, so 5,472 rows take three dependent loads.
+__device__ __forceinline__ uint32_t cm_find_ur_wave(const uint32_t* crow, uint32_t n_ur,
+                                                    uint32_t c) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t lo = 0, hi = n_ur;
+  while (hi - lo > 1) {  // uniform
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t p = lo + lane * step;
+    // the probes not above c are a prefix of the lanes (crow does not decrease)
+    const uint64_t b = __ballot(p < hi && crow[p] <= c);
+    lo += (b ? 63u - (uint32_t)__builtin_clzll(b) : 0u) * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t cm_wave_incl_max(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, 64);
+    if ((int)(threadIdx.x & 63) >= d) v = max(v, o);
+  }
+  return v;
+}
+
+// The helix m at every row from m.row (< NROW) to the last, one wave: q(y)
+// and q(z) at row r in ty[r] and tz[r].  Along a track C is constant, so the
+// S after each step is S0 plus a prefix sum of per-step increments, and a
+// step's changes of y and z depend only on the S before and after it: wave
+// prefix sums give the same integers as cm_step row after row.  The first
+// step whose S leaves the range freezes that step and all after it.  Ends
+// with the table visible to the whole wave.
+__device__ void cm_helix_rows(const CmModel& m, const int32_t* xs, int64_t* ty, int64_t* tz) {
+  const uint32_t lane = threadIdx.x & 63;
+  const int64_t one = (int64_t)1 << 60;
+  const int64_t smax = ((int64_t)1 << 30) - ((int64_t)1 << 20);
+  int64_t S = m.S, Sc = m.Sc, Y = m.Y, Z = m.Z;
+  bool frozen = false;
+  if (lane == 0) {
+    ty[m.row] = cm_q(Y);
+    tz[m.row] = cm_q(Z);
+  }
+  for (int base = m.row; base + 1 < NROW; base += 64) {  // uniform
+    const int a = base + (int)lane;  // this lane's step: row a to row a + 1
+    const bool valid = a + 1 < NROW;
+    const int64_t D = valid ? (int64_t)xs[a + 1] - xs[a] : 0;
+    const int64_t inc = valid ? cm_rshift(m.C * D, 32) : 0;
+    const int64_t S1 = S + (int64_t)wave_incl_scan((uint64_t)inc);
+    const int64_t S0 = S1 - inc;
+    const uint64_t out = __ballot(valid && (S1 >= smax || S1 <= -smax));
+    const uint32_t first_out = out ? (uint32_t)__builtin_ctzll(out) : 64u;
+    const bool live = valid && !frozen && lane < first_out;  // a prefix of the lanes
+    const int64_t c1 = live ? cm_isqrt(one - S1 * S1) : 0;
+    const int64_t c_up = __shfl_up(c1, 1, 64);
+    const int64_t c0 = lane == 0 ? Sc : c_up;
+    int64_t dY = 0, dZ = 0;
+    if (live) {
+      const int64_t F = cm_rdiv((S0 + S1) * ((int64_t)1 << 24), c0 + c1);
+      dY = cm_rshift(D * F, 24);
+      const int64_t L = cm_rshift(D * cm_isqrt(((int64_t)1 << 48) + F * F), 24);
+      dZ = cm_rshift(m.T * L, 30);
+    }
+    const int64_t Y1 = Y + (int64_t)wave_incl_scan((uint64_t)dY);
+    const int64_t Z1 = Z + (int64_t)wave_incl_scan((uint64_t)dZ);
+    if (valid) {
+      ty[a + 1] = cm_q(Y1);
+      tz[a + 1] = cm_q(Z1);
+    }
+    // the state after the last of these 64 steps (S and its root matter only
+    // while nothing is frozen)
+    Y = __shfl(Y1, 63, 64);
+    Z = __shfl(Z1, 63, 64);
+    S = __shfl(S1, 63, 64);
+    Sc = __shfl(c1, 63, 64);
+    if (out) frozen = true;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Per-track record lengths, the hits' residual codes (kept for the writing
+// pass) and the residual histograms (per workgroup in LDS, then added to the
+// caller's): one wave per track, its hits 64 at a time.  The same lengths
+// and codes as stepping the track hit by hit (cm_track): a hit's (unit,row)
+// is the largest reached so far (rows are searched forward only), the helix
+// is taken at the highest row reached so far (it is never stepped back), from
+// a table of all rows (cm_helix_rows); the rows are found in the first hit's
+// unit's row starts staged in LDS, or in all of them for a hit outside it.
 __global__ __launch_bounds__(256) void k_cm_track_bits(CmClusters cl, CmTracks tr, int64_t b30,
                                                        const DevParams* __restrict__ P,
                                                        uint32_t* __restrict__ tbits,
@@ -416,18 +504,100 @@ __global__ __launch_bounds__(256) void k_cm_track_bits(CmClusters cl, CmTracks t
                                                        uint64_t* __restrict__ res, uint32_t res_cap,
                                                        DevStatus* st) {
   __shared__ uint32_t h[256];
-  __shared__ int32_t xs[NROW];  // row radii: the helix steps read them per lane
+  __shared__ int32_t xs[NROW];
+  __shared__ int64_t tab[4][2][NROW];  // per wave: q(y), q(z) of the helix per row
+  __shared__ uint32_t rs[4][NROW + 1];  // per wave: row starts of the track's unit
   if (failed(st)) return;
   for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
   for (uint32_t i = threadIdx.x; i < NROW; i += blockDim.x) xs[i] = P->xfx[i];
   __syncthreads();
   const uint32_t n = scan_count(tr.n_dev, tr.cap);
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    uint64_t bits = 0;
-    if (!cm_track<false>(cl, tr, j, b30, xs, bits, nullptr, hist_out ? h : nullptr, res,
-                         res_cap))
-      latch(st, TPC_ERR_INPUT);
-    tbits[j] = (uint32_t)(bits < 0xFFFFFFFFull ? bits : 0xFFFFFFFFull);
+  const uint32_t n_cl = scan_count(cl.n_dev, cl.cap);
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t* ty = tab[w][0];
+  int64_t* tz = tab[w][1];
+  uint32_t* rw = rs[w];
+  const bool staged = cl.n_ur >= NROW;
+  for (uint32_t j = blockIdx.x * 4 + w; j < n; j += gridDim.x * 4) {  // uniform per wave
+    uint32_t h0 = tr.hit_start[j], h1 = tr.hit_start[j + 1];
+    if (h1 > tr.hit_cap) h1 = tr.hit_cap;
+    if (h0 > h1) h0 = h1;
+    uint32_t ur0 = 0;
+    if (h1 > h0) {
+      const uint32_t c = tr.hits[h0];
+      ur0 = cm_find_ur_wave(cl.crow, cl.n_ur, c < n_cl ? c : 0);
+    }
+    const uint32_t ub = ur0 / NROW * NROW;  // ub + NROW <= n_ur: n_ur is a multiple of NROW
+    const int r0 = tr.row[j];
+    const int rt = r0 < NROW ? r0 : NROW - 1;  // a helix at a row past the last is never stepped
+    const CmParams q = cm_params(tr.par + (size_t)j * 5, tr.z_anchor[j]);
+    if (staged)
+      for (uint32_t k = lane; k <= NROW; k += 64) rw[k] = cl.crow[ub + k];
+    cm_helix_rows(cm_model(q, b30, rt), xs, ty, tz);  // also makes rw visible
+    const bool cached = res != nullptr && h1 <= res_cap;
+    uint64_t len = 0;
+    bool bad = false;
+    uint32_t ur_c = ur0;  // the (unit,row) reached so far
+    int prev_c = r0;      // the previous hit's row (the track's row before the first)
+    int mrow_c = rt;      // the helix's row so far
+    for (uint32_t base = h0; base < h1; base += 64) {  // uniform
+      const uint32_t hh = base + lane;
+      const bool act = hh < h1;
+      uint32_t c = act ? tr.hits[hh] : 0u;
+      if (c >= n_cl) {
+        bad = bad || act;
+        c = 0;
+      }
+      uint32_t f;
+      if (staged && c >= rw[0] && c < rw[NROW]) {
+        uint32_t lo = 0, hi = NROW;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (rw[mid] <= c) lo = mid;
+          else hi = mid;
+        }
+        f = ub + lo;
+      } else {
+        f = cm_find_ur(cl.crow, cl.n_ur, c);
+      }
+      const uint32_t u = cm_wave_incl_max(act ? max(f, ur_c) : ur_c);
+      const int r = (int)(u % NROW);
+      const int r_up = __shfl_up(r, 1, 64);
+      const int prev = lane == 0 ? prev_c : r_up;
+      const int step = r - prev - (hh > h0 ? 1 : 0);
+      if (act && step < 0) bad = true;
+      const uint64_t stp = step < 0 ? 0 : (uint64_t)step;
+      const int mr = (int)cm_wave_incl_max((uint32_t)(act ? max(r, mrow_c) : mrow_c));
+      if (act) {
+        const int64_t dy = cm_q(cl.y[c]) - ty[mr];
+        const int64_t dz = cm_q(cl.z[c]) - tz[mr];
+        const uint64_t zy = cm_zig(dy), zz = cm_zig(dz);
+        if (cached) {
+          res[2 * (size_t)hh] = zy;
+          res[2 * (size_t)hh + 1] = zz;
+        }
+        len += cm_eg_len(stp, 0) + cm_eg_len(zy, 2) + cm_eg_len(zz, 2) +
+               cm_cluster_len(cl.qtot[c], cl.qmax[c]);
+        if (hist_out) {
+          atomicAdd(&h[(dy < -64 ? -64 : dy > 63 ? 63 : dy) + 64], 1u);
+          atomicAdd(&h[128 + (dz < -64 ? -64 : dz > 63 ? 63 : dz) + 64], 1u);
+        }
+      }
+      // the carries: the last hit of these 64
+      const int last = (int)min(63u, h1 - 1 - base);
+      ur_c = __shfl(u, last, 64);
+      prev_c = __shfl(r, last, 64);
+      mrow_c = __shfl(mr, last, 64);
+    }
+    const uint64_t tot = 8 + 16 + 8 + 5 * 32 + __shfl(wave_incl_scan(len), 63, 64);
+    const bool any_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+      if (any_bad) latch(st, TPC_ERR_INPUT);
+      tbits[j] = (uint32_t)(tot < 0xFFFFFFFFull ? tot : 0xFFFFFFFFull);
+    }
+    // the wave's LDS reads are done before the next track overwrites them
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   if (hist_out)

@@ -974,8 +974,8 @@ int tpc_compress(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, tpc_c
   const uint32_t gt = grid_for(tr->capacity, 256, 4096);
   // the hits' residual codes, cached between the two track passes
   const uint32_t res_cap = (uint32_t)c->max.max_clusters;
-  k_cm_track_bits<<<gt, 256, 0, s>>>(cv, tv, b30, c->d_par, c->cm_a, out->res_hist, c->cm_res,
-                                     res_cap, c->d_st);
+  k_cm_track_bits<<<grid_for(tr->capacity, 4, kCapStream), 256, 0, s>>>(
+      cv, tv, b30, c->d_par, c->cm_a, out->res_hist, c->cm_res, res_cap, c->d_st);
   k_cm_row_bits<<<grid_for(n_ur, 4, 4096), 256, 0, s>>>(cv, tr->cluster_track, c->cm_b, c->d_st);
   run_scan<unsigned long long>(c, CmGetU32{c->cm_a}, CmEmitTrack{out->stream, out->capacity},
                                tr->n_tracks, tr->capacity, c->cm_tot, (uint32_t*)nullptr);
