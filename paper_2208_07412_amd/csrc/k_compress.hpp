@@ -9,13 +9,14 @@
 // every value in the stream is integer arithmetic and decoding gives the
 // quantised clusters whatever the model predicts.
 //
-// Encoder: one lane per track computes its record's length (and the residual
-// histograms); one wave per (unit,row) the lengths of its clusters on no
-// track; two device scans turn the lengths into the directory; a finishing
-// kernel writes the header and checks the capacity; the payload is cleared
-// and written again by the same lanes, each lane accumulating its bits and
-// storing whole words (atomic OR only because the first and last word of a
-// record may be shared with a neighbour).  Decoder: the record sizes come
+// Encoder: one wave per track computes its record's length (and the residual
+// histograms), its hits 64 at a time on a table of the helix at every row;
+// one wave per (unit,row) the lengths of its clusters on no track; two device
+// scans turn the lengths into the directory; a finishing kernel writes the
+// header and checks the capacity; the payload is cleared and written by the
+// same waves, each lane accumulating its codes' bits and storing whole words
+// (atomic OR because a code's first and last word may be shared with a
+// neighbour).  Decoder: the record sizes come
 // from the directory and the fixed-width hit counts, a scan gives the output
 // offsets, and one lane per record decodes it.
 #pragma once
@@ -313,100 +314,6 @@ __device__ __forceinline__ void cm_cluster_put(CmWriter& b, uint16_t qt, uint16_
   b.put(f & 3u, 2);
 }
 
-// One track record: its length (write = false) or its bits (write = true).
-// Returns false if a hit lies below the model's row (latched by the caller).
-// res (optional, res_cap hits): the hits' two zigzag residuals, stored by the
-// sizing pass (WRITE false) and read back by the writing pass, which then
-// does not step the model again (the same values either way).
-template <bool WRITE>
-__device__ bool cm_track(const CmClusters& cl, const CmTracks& tr, uint32_t j, int64_t b30,
-                         const int32_t* xfx, uint64_t& bits, CmWriter* bw, uint32_t* hist,
-                         uint64_t* res, uint32_t res_cap) {
-  uint32_t h0 = tr.hit_start[j], h1 = tr.hit_start[j + 1];
-  if (h1 > tr.hit_cap) h1 = tr.hit_cap;
-  if (h0 > h1) h0 = h1;
-  const uint32_t n_cl = scan_count(cl.n_dev, cl.cap);
-  uint32_t ur = 0;
-  if (h1 > h0) {
-    const uint32_t c = tr.hits[h0];
-    ur = cm_find_ur(cl.crow, cl.n_ur, c < n_cl ? c : 0);
-  }
-  const uint32_t unit = ur / NROW;
-  const int r0 = tr.row[j];
-  const CmParams q = cm_params(tr.par + (size_t)j * 5, tr.z_anchor[j]);
-  CmModel m = cm_model(q, b30, r0);
-  uint64_t len = 8 + 16 + 8 + 5 * 32;
-  if (WRITE) {
-    bw->put(h1 - h0, 8);
-    bw->put(unit, 16);
-    bw->put((uint32_t)r0, 8);
-    bw->put((uint32_t)(int32_t)q.Y, 32);
-    bw->put((uint32_t)(int32_t)q.Z, 32);
-    bw->put((uint32_t)(int32_t)q.S, 32);
-    bw->put((uint32_t)(int32_t)q.T, 32);
-    bw->put((uint32_t)(int32_t)q.K, 32);
-  }
-  int prev = r0;
-  bool ok = true;
-  const bool cached = res != nullptr && h1 <= res_cap;
-  // the next hit's cluster index is loaded one hit ahead
-  uint32_t c_next = h1 > h0 ? tr.hits[h0] : 0;
-  for (uint32_t h = h0; h < h1; ++h) {
-    uint32_t c = c_next;
-    if (h + 1 < h1) c_next = tr.hits[h + 1];
-    if (c >= n_cl) {
-      ok = false;
-      c = 0;
-    }
-    // the hit's (unit,row): the last row start not above c.  A track's rows
-    // mostly step out by one, so each probe reads the next two row starts at
-    // once (one memory round trip where one at a time takes two).
-    for (;;) {
-      const uint32_t a = ur + 1 < cl.n_ur ? cl.crow[ur + 1] : 0xFFFFFFFFu;
-      const uint32_t b = ur + 2 < cl.n_ur ? cl.crow[ur + 2] : 0xFFFFFFFFu;
-      const uint32_t adv = (uint32_t)(a <= c) + (uint32_t)(a <= c && b <= c);
-      ur += adv;
-      if (adv < 2) break;
-    }
-    const int r = (int)(ur % NROW);
-    const int step = r - prev - (h > h0 ? 1 : 0);
-    if (step < 0) ok = false;
-    const uint64_t st = step < 0 ? 0 : (uint64_t)step;
-    prev = r;
-    int64_t dy = 0, dz = 0;
-    uint64_t zy, zz;
-    if (WRITE && cached) {
-      zy = res[2 * (size_t)h];
-      zz = res[2 * (size_t)h + 1];
-    } else {
-      while (m.row < r) cm_step(m, xfx);
-      dy = cm_q(cl.y[c]) - cm_q(m.Y);
-      dz = cm_q(cl.z[c]) - cm_q(m.Z);
-      zy = cm_zig(dy);
-      zz = cm_zig(dz);
-      if (!WRITE && cached) {
-        res[2 * (size_t)h] = zy;
-        res[2 * (size_t)h + 1] = zz;
-      }
-    }
-    if (WRITE) {
-      bw->eg(st, 0);
-      bw->eg(zy, 2);
-      bw->eg(zz, 2);
-      cm_cluster_put(*bw, cl.qtot[c], cl.qmax[c], cl.flags[c]);
-    } else {
-      len += cm_eg_len(st, 0) + cm_eg_len(zy, 2) + cm_eg_len(zz, 2) +
-             cm_cluster_len(cl.qtot[c], cl.qmax[c]);
-      if (hist) {
-        atomicAdd(&hist[(dy < -64 ? -64 : dy > 63 ? 63 : dy) + 64], 1u);
-        atomicAdd(&hist[128 + (dz < -64 ? -64 : dz > 63 ? 63 : dz) + 64], 1u);
-      }
-    }
-  }
-  bits = len;
-  return ok;
-}
-
 // (unit,row) of cluster c found by a whole wave (every lane gets it): the
 // last entry of crow[0..n_ur) not above c, as cm_find_ur; each round probes
 // 64 evenly spaced entries, so 5,472 rows take three dependent loads.
@@ -492,7 +399,7 @@ __device__ void cm_helix_rows(const CmModel& m, const int32_t* xs, int64_t* ty, 
 // Per-track record lengths, the hits' residual codes (kept for the writing
 // pass) and the residual histograms (per workgroup in LDS, then added to the
 // caller's): one wave per track, its hits 64 at a time.  The same lengths
-// and codes as stepping the track hit by hit (cm_track): a hit's (unit,row)
+// and codes as stepping the helix hit by hit with cm_step: a hit's (unit,row)
 // is the largest reached so far (rows are searched forward only), the helix
 // is taken at the highest row reached so far (it is never stepped back), from
 // a table of all rows (cm_helix_rows); the rows are found in the first hit's
@@ -774,25 +681,133 @@ __global__ void k_cm_clear(uint32_t* __restrict__ s, const uint32_t* info, const
     s[i] = 0;
 }
 
+// The track records' bits at their directory offsets, one wave per track:
+// lane 0 writes the record's fixed fields, and each hit's lane its codes at
+// the record's start + 192 bits + the lengths of the hits before it (a wave
+// prefix sum), each lane with its own writer (atomic OR: a word may be shared
+// with a neighbouring hit or record).  The residuals come from the sizing
+// pass's cache, else from the helix table, as in k_cm_track_bits.
 __global__ __launch_bounds__(256) void k_cm_track_write(CmClusters cl, CmTracks tr, int64_t b30,
                                                         const DevParams* __restrict__ P,
                                                         uint32_t* __restrict__ s,
                                                         const uint32_t* info,
                                                         const uint64_t* __restrict__ res,
                                                         uint32_t res_cap, DevStatus* st) {
-  __shared__ int32_t xs[NROW];  // row radii, for tracks whose residuals were not kept
+  __shared__ int32_t xs[NROW];
+  __shared__ int64_t tab[4][2][NROW];
+  __shared__ uint32_t rs[4][NROW + 1];
   if (failed(st) || info[0] == 0) return;
   for (uint32_t i = threadIdx.x; i < NROW; i += blockDim.x) xs[i] = P->xfx[i];
   __syncthreads();
   const uint32_t n = scan_count(tr.n_dev, tr.cap);
+  const uint32_t n_cl = scan_count(cl.n_dev, cl.cap);
   uint32_t* payload = s + info[1];
   const uint64_t pw = info[0] - info[1];
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    CmWriter w;
-    w.init(payload, pw, s[CM_HDR + j]);
-    uint64_t bits = 0;
-    cm_track<true>(cl, tr, j, b30, xs, bits, &w, nullptr, const_cast<uint64_t*>(res), res_cap);
-    w.flush();
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t* ty = tab[w][0];
+  int64_t* tz = tab[w][1];
+  uint32_t* rw = rs[w];
+  const bool staged = cl.n_ur >= NROW;
+  for (uint32_t j = blockIdx.x * 4 + w; j < n; j += gridDim.x * 4) {  // uniform per wave
+    uint32_t h0 = tr.hit_start[j], h1 = tr.hit_start[j + 1];
+    if (h1 > tr.hit_cap) h1 = tr.hit_cap;
+    if (h0 > h1) h0 = h1;
+    uint32_t ur0 = 0;
+    if (h1 > h0) {
+      const uint32_t c = tr.hits[h0];
+      ur0 = cm_find_ur_wave(cl.crow, cl.n_ur, c < n_cl ? c : 0);
+    }
+    const uint32_t ub = ur0 / NROW * NROW;
+    const int r0 = tr.row[j];
+    const int rt = r0 < NROW ? r0 : NROW - 1;
+    const CmParams q = cm_params(tr.par + (size_t)j * 5, tr.z_anchor[j]);
+    const uint64_t start = s[CM_HDR + j];
+    const bool cached = res != nullptr && h1 <= res_cap;  // uniform
+    if (staged)
+      for (uint32_t k = lane; k <= NROW; k += 64) rw[k] = cl.crow[ub + k];
+    if (!cached) {
+      cm_helix_rows(cm_model(q, b30, rt), xs, ty, tz);  // also makes rw visible
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+      CmWriter wr;
+      wr.init(payload, pw, start);
+      wr.put(h1 - h0, 8);
+      wr.put(ur0 / NROW, 16);
+      wr.put((uint32_t)r0, 8);
+      wr.put((uint32_t)(int32_t)q.Y, 32);
+      wr.put((uint32_t)(int32_t)q.Z, 32);
+      wr.put((uint32_t)(int32_t)q.S, 32);
+      wr.put((uint32_t)(int32_t)q.T, 32);
+      wr.put((uint32_t)(int32_t)q.K, 32);
+      wr.flush();
+    }
+    uint64_t off = start + 8 + 16 + 8 + 5 * 32;
+    uint32_t ur_c = ur0;
+    int prev_c = r0;
+    int mrow_c = rt;
+    for (uint32_t base = h0; base < h1; base += 64) {  // uniform
+      const uint32_t hh = base + lane;
+      const bool act = hh < h1;
+      uint32_t c = act ? tr.hits[hh] : 0u;
+      if (c >= n_cl) c = 0;
+      uint32_t f;
+      if (staged && c >= rw[0] && c < rw[NROW]) {
+        uint32_t lo = 0, hi = NROW;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (rw[mid] <= c) lo = mid;
+          else hi = mid;
+        }
+        f = ub + lo;
+      } else {
+        f = cm_find_ur(cl.crow, cl.n_ur, c);
+      }
+      const uint32_t u = cm_wave_incl_max(act ? max(f, ur_c) : ur_c);
+      const int r = (int)(u % NROW);
+      const int r_up = __shfl_up(r, 1, 64);
+      const int prev = lane == 0 ? prev_c : r_up;
+      const int step = r - prev - (hh > h0 ? 1 : 0);
+      const uint64_t stp = step < 0 ? 0 : (uint64_t)step;
+      const int mr = (int)cm_wave_incl_max((uint32_t)(act ? max(r, mrow_c) : mrow_c));
+      uint64_t zy = 0, zz = 0;
+      uint16_t qt = 0, qm = 0;
+      uint8_t fl = 0;
+      uint64_t hl = 0;
+      if (act) {
+        if (cached) {
+          zy = res[2 * (size_t)hh];
+          zz = res[2 * (size_t)hh + 1];
+        } else {
+          zy = cm_zig(cm_q(cl.y[c]) - ty[mr]);
+          zz = cm_zig(cm_q(cl.z[c]) - tz[mr]);
+        }
+        qt = cl.qtot[c];
+        qm = cl.qmax[c];
+        fl = cl.flags[c];
+        hl = cm_eg_len(stp, 0) + cm_eg_len(zy, 2) + cm_eg_len(zz, 2) + cm_cluster_len(qt, qm);
+      }
+      const uint64_t incl = wave_incl_scan(hl);
+      if (act) {
+        CmWriter wr;
+        wr.init(payload, pw, off + incl - hl);
+        wr.eg(stp, 0);
+        wr.eg(zy, 2);
+        wr.eg(zz, 2);
+        cm_cluster_put(wr, qt, qm, fl);
+        wr.flush();
+      }
+      off += __shfl(incl, 63, 64);
+      const int last = (int)min(63u, h1 - 1 - base);
+      ur_c = __shfl(u, last, 64);
+      prev_c = __shfl(r, last, 64);
+      mrow_c = __shfl(mr, last, 64);
+    }
+    // the wave's LDS reads are done before the next track overwrites them
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 

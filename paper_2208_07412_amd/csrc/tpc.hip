@@ -971,7 +971,6 @@ int tpc_compress(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, tpc_c
                     tr->n_tracks, tr->capacity, tr->hit_capacity};
   const int64_t b30 = cm_b30(c);
   if (out->res_hist) k_fill<uint32_t><<<1, 256, 0, s>>>(out->res_hist, 0u, 256);
-  const uint32_t gt = grid_for(tr->capacity, 256, 4096);
   // the hits' residual codes, cached between the two track passes
   const uint32_t res_cap = (uint32_t)c->max.max_clusters;
   k_cm_track_bits<<<grid_for(tr->capacity, 4, kCapStream), 256, 0, s>>>(
@@ -987,8 +986,8 @@ int tpc_compress(tpc_ctx* c, const tpc_clusters* cl, const tpc_tracks* tr, tpc_c
                               tr->hit_start, cl->n_clusters, cl->capacity, c->cm_tot,
                               out->n_words, c->cm_info, c->d_st);
   k_cm_clear<<<grid_for(out->capacity, 256, 2048), 256, 0, s>>>(out->stream, c->cm_info, c->d_st);
-  k_cm_track_write<<<gt, 256, 0, s>>>(cv, tv, b30, c->d_par, out->stream, c->cm_info, c->cm_res,
-                                      res_cap, c->d_st);
+  k_cm_track_write<<<grid_for(tr->capacity, 4, kCapStream), 256, 0, s>>>(
+      cv, tv, b30, c->d_par, out->stream, c->cm_info, c->cm_res, res_cap, c->d_st);
   k_cm_row_write<<<grid_for(n_ur, 4, 4096), 256, 0, s>>>(cv, tr->cluster_track, out->stream,
                                                          tr->n_tracks, tr->capacity, c->cm_info,
                                                          c->d_st);
