@@ -404,7 +404,10 @@ __device__ void cm_helix_rows(const CmModel& m, const int32_t* xs, int64_t* ty, 
 // is taken at the highest row reached so far (it is never stepped back), from
 // a table of all rows (cm_helix_rows); the rows are found in the first hit's
 // unit's row starts staged in LDS, or in all of them for a hit outside it.
-__global__ __launch_bounds__(256) void k_cm_track_bits(CmClusters cl, CmTracks tr, int64_t b30,
+// Seven waves per SIMD (71 VGPRs, no spill) where the compiler would allow
+// six: a track's wave mostly waits on memory, and more waves hide more of it
+// (1.00 -> 0.96 ms on the 2 ms slice).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_cm_track_bits(CmClusters cl, CmTracks tr, int64_t b30,
                                                        const DevParams* __restrict__ P,
                                                        uint32_t* __restrict__ tbits,
                                                        uint32_t* __restrict__ hist_out,
@@ -687,7 +690,9 @@ __global__ void k_cm_clear(uint32_t* __restrict__ s, const uint32_t* info, const
 // prefix sum), each lane with its own writer (atomic OR: a word may be shared
 // with a neighbouring hit or record).  The residuals come from the sizing
 // pass's cache, else from the helix table, as in k_cm_track_bits.
-__global__ __launch_bounds__(256) void k_cm_track_write(CmClusters cl, CmTracks tr, int64_t b30,
+// Six waves per SIMD (80 VGPRs, no spill; seven would spill) where the
+// compiler would allow five (1.17 -> 1.06 ms on the 2 ms slice).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_cm_track_write(CmClusters cl, CmTracks tr, int64_t b30,
                                                         const DevParams* __restrict__ P,
                                                         uint32_t* __restrict__ s,
                                                         const uint32_t* info,
